@@ -1,0 +1,304 @@
+"""FP64 CPU oracle for Selective Extrapolation (SE) and Fast SE (FaSE).
+
+TEST INFRASTRUCTURE ONLY.  This module is the plain, slow, obviously correct
+statement of what the HIP path computes.  Only the test suite, the smoke check
+and the CPU-baseline leg of the benchmark may import it; the library never
+does, and it shares no code with the library (it reads only the seeded inputs
+of ``paper_2204_14194_amd.synth``).
+
+Everything is real-valued float64.  The paper states the method for complex
+basis functions; for real signals and atoms the conjugations drop out
+(Section III, opening paragraph), which is the reading used throughout.
+
+Contents, in the paper's notation:
+  * ``area_weights``      -- weighting function w = rho on A, 0 on B (eq. 4)
+                             with the isotropic decay rho (eq. 5)
+  * ``se_original``       -- Algorithm 1: every iteration recomputes the
+                             weighted projection of the residual onto every
+                             atom (eq. 3), selects by eq. 7, estimates the
+                             coefficient by eq. 8, updates by eq. 9-10
+  * ``table_generation``  -- Algorithm 2: C (eq. 16) and D (eq. 17)
+  * ``fase``              -- Algorithm 3: R^(0) once (eq. 12), then
+                             selection by eq. 18, coefficient by eq. 19 and
+                             the recursive update eq. 20
+  * ``conceal``           -- the whole task for a list of lost blocks of an
+                             image: weights, SE (or FaSE), and the
+                             replacement of the loss area by the model
+                             (last step of Algorithms 1 and 3)
+  * ``duplicate_classes`` -- atoms that are parallel over the whole area
+  * ``operation_counts``  -- Table I
+
+Readings where the paper is silent (each is listed in the design notes):
+  * exact ties in the selection go to the lowest atom index (np.argmax);
+  * an atom with a zero weighted norm (sum phi w phi = 0, i.e. the atom
+    vanishes on the whole support) gets p_k = 0 and D_k = 0 and is never
+    selected; if every score is zero the lowest index is "selected" with a
+    zero coefficient, which changes nothing;
+  * pixels outside the image or inside any lost block are not support:
+    their weight is 0 and their sample value is taken as 0;
+  * the model is cut into the image as clip(round-half-even(g), 0, 255).
+"""
+from __future__ import annotations
+
+import dataclasses
+from fractions import Fraction
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "area_weights", "area_signal", "se_original", "table_generation", "fase",
+    "conceal", "duplicate_classes", "quantise", "operation_counts",
+    "SEResult",
+]
+
+
+# ----------------------------------------------------------------------------
+# weighting function (eq. 4, eq. 5)
+# ----------------------------------------------------------------------------
+def area_weights(M: int, N: int, rho_hat: float, support: np.ndarray) -> np.ndarray:
+    """w[m, n] = rho_hat ** sqrt((m - (M-1)/2)^2 + (n - (N-1)/2)^2) on the
+    support area A (``support`` True), 0 elsewhere.  Returns a flat (M*N,)
+    float64 vector, pixel (m, n) at m*N + n."""
+    m = np.arange(M, dtype=np.float64)[:, None]
+    n = np.arange(N, dtype=np.float64)[None, :]
+    dist = np.sqrt((m - (M - 1) / 2.0) ** 2 + (n - (N - 1) / 2.0) ** 2)
+    rho = float(rho_hat) ** dist
+    w = np.where(np.asarray(support, dtype=bool).reshape(M, N), rho, 0.0)
+    return w.reshape(M * N)
+
+
+def area_signal(image: np.ndarray, lost: np.ndarray, y0: int, x0: int,
+                M: int, N: int):
+    """Cut the M x N area with top-left (y0, x0) out of ``image``.
+    Returns (s, support): s as float64 (M*N,), 0 where the pixel is outside
+    the image or lost; support True exactly where the pixel is available."""
+    H, W = image.shape
+    s = np.zeros((M, N))
+    support = np.zeros((M, N), dtype=bool)
+    for m in range(M):
+        y = y0 + m
+        if y < 0 or y >= H:
+            continue
+        for n in range(N):
+            x = x0 + n
+            if x < 0 or x >= W or lost[y, x]:
+                continue
+            s[m, n] = float(image[y, x])
+            support[m, n] = True
+    return s.reshape(M * N), support
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 1: original SE
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class SEResult:
+    sel: np.ndarray          # (I,) selected atom index per iteration
+    coef: np.ndarray         # (I,) estimated coefficient c-hat per iteration
+    g: np.ndarray            # (M*N,) final model over the whole area
+    best: np.ndarray         # (I,) winning score per iteration
+    second: np.ndarray       # (I,) best score outside the winner's class
+    energy: np.ndarray       # (I+1,) weighted residual energy sum w r^2
+    R_history: Optional[List[np.ndarray]] = None
+
+
+def _second_best(score: np.ndarray, u: int, classes: Optional[np.ndarray]) -> float:
+    if classes is None:
+        mask = np.ones(score.shape, dtype=bool)
+        mask[u] = False
+    else:
+        mask = classes != classes[u]
+    return float(score[mask].max()) if mask.any() else 0.0
+
+
+def se_original(s: np.ndarray, w: np.ndarray, phi: np.ndarray, gamma: float,
+                iters: int, classes: Optional[np.ndarray] = None) -> SEResult:
+    """Algorithm 1, literally: for every iteration the weighted projection
+    p_k (eq. 3) of the residual onto every atom is recomputed from scratch,
+    numerator and denominator, the atom maximising |p_k|^2 sum(phi_k w phi_k)
+    (eq. 7) is selected, c-hat = gamma p_u (eq. 8), and model and residual are
+    updated (eq. 9, eq. 10).
+
+    Each scalar product is a plain row-wise sum of elementwise products, so
+    bit-identical atoms get bit-identical scores and the lowest index wins.
+    """
+    s = np.asarray(s, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    phi = np.asarray(phi, dtype=np.float64)
+    r = s.copy()                         # r^(0) = s  (eq. 2)
+    g = np.zeros_like(s)                 # g^(0) = 0
+    sel = np.zeros(iters, dtype=np.int64)
+    coef = np.zeros(iters)
+    best = np.zeros(iters)
+    second = np.zeros(iters)
+    energy = np.zeros(iters + 1)
+    energy[0] = float(np.sum(w * r * r))
+    for nu in range(iters):
+        num = np.sum(phi * (r * w)[None, :], axis=1)        # sum r phi_k w
+        den = np.sum(phi * w[None, :] * phi, axis=1)         # sum phi_k w phi_k
+        safe = den > 0.0
+        p = np.zeros_like(num)
+        p[safe] = num[safe] / den[safe]                      # eq. 3
+        score = np.where(safe, p * p * den, 0.0)             # eq. 7
+        u = int(np.argmax(score))
+        c = gamma * p[u]                                     # eq. 8
+        g = g + c * phi[u]                                   # eq. 9
+        r = r - c * phi[u]                                   # eq. 10
+        sel[nu] = u
+        coef[nu] = c
+        best[nu] = score[u]
+        second[nu] = _second_best(score, u, classes)
+        energy[nu + 1] = float(np.sum(w * r * r))
+    return SEResult(sel, coef, g, best, second, energy)
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 2: table generation
+# ----------------------------------------------------------------------------
+def table_generation(phi: np.ndarray, w: np.ndarray):
+    """C_(k,l) = sum phi_k w phi_l (eq. 16) for l >= k, mirrored to l < k as
+    Algorithm 2 does; D_k = 1/sqrt(C_(k,k)) (eq. 17), 0 for an atom with a
+    zero weighted norm.  One matrix product serves as the summation step."""
+    phi = np.asarray(phi, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    full = (phi * w[None, :]) @ phi.T
+    upper = np.triu(full)
+    C = upper + np.triu(full, 1).T
+    diag = np.diag(C).copy()
+    D = np.zeros_like(diag)
+    pos = diag > 0.0
+    D[pos] = 1.0 / np.sqrt(diag[pos])
+    return C, D
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 3: FaSE
+# ----------------------------------------------------------------------------
+def fase(s: np.ndarray, w: np.ndarray, phi: np.ndarray, C: np.ndarray,
+         D: np.ndarray, gamma: float, iters: int,
+         classes: Optional[np.ndarray] = None,
+         keep_R: bool = False) -> SEResult:
+    """Algorithm 3: R_k = sum s phi_k w once (eq. 12); per iteration
+    u = argmax |R_k| D_k (eq. 18), c-hat = gamma R_u D_u^2 (eq. 19),
+    g += c-hat phi_u (eq. 9), R_k -= c-hat C_(k,u) (eq. 20)."""
+    s = np.asarray(s, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    phi = np.asarray(phi, dtype=np.float64)
+    R = np.sum(phi * (s * w)[None, :], axis=1)
+    g = np.zeros_like(s)
+    r = s.copy()                          # tracked only for the energy report
+    sel = np.zeros(iters, dtype=np.int64)
+    coef = np.zeros(iters)
+    best = np.zeros(iters)
+    second = np.zeros(iters)
+    energy = np.zeros(iters + 1)
+    energy[0] = float(np.sum(w * r * r))
+    hist = [R.copy()] if keep_R else None
+    for nu in range(iters):
+        score = np.abs(R) * D
+        u = int(np.argmax(score))
+        c = gamma * R[u] * D[u] * D[u]
+        g = g + c * phi[u]
+        R = R - c * C[:, u]
+        r = r - c * phi[u]
+        sel[nu] = u
+        coef[nu] = c
+        # report the score in the eq. 7 form (|R|^2 D^2) so it compares
+        # directly with se_original's
+        best[nu] = score[u] ** 2
+        second[nu] = _second_best(score, u, classes) ** 2
+        energy[nu + 1] = float(np.sum(w * r * r))
+        if keep_R:
+            hist.append(R.copy())
+    return SEResult(sel, coef, g, best, second, energy, hist)
+
+
+# ----------------------------------------------------------------------------
+# whole task: conceal lost blocks of an image
+# ----------------------------------------------------------------------------
+def quantise(g: np.ndarray) -> np.ndarray:
+    """clip(round-half-even(g), 0, 255) as uint8."""
+    return np.clip(np.rint(g), 0.0, 255.0).astype(np.uint8)
+
+
+def conceal(image: np.ndarray, lost: np.ndarray, blocks: Sequence, phi: np.ndarray,
+            M: int, N: int, rho_hat: float, gamma: float, iters: int,
+            method: str = "fase", classes: Optional[np.ndarray] = None,
+            table_cache: Optional[Dict] = None):
+    """Conceal every block of ``blocks`` (objects with y0, x0, ly, lx, lh,
+    lw) in ``image`` (uint8 H x W, not modified).  ``lost`` marks every lost
+    pixel of the image (1 = lost); no lost pixel is ever used as support, so
+    the result does not depend on the order of the blocks.
+
+    Returns (out, per_block) where ``out`` is the concealed uint8 image and
+    per_block[i] = (SEResult, g over the loss rectangle as float64 lh x lw).
+    """
+    out = image.copy()
+    per_block = []
+    for b in blocks:
+        s, support = area_signal(image, lost, b.y0, b.x0, M, N)
+        w = area_weights(M, N, rho_hat, support)
+        if method == "se":
+            res = se_original(s, w, phi, gamma, iters, classes)
+        elif method == "fase":
+            key = w.tobytes()
+            if table_cache is not None and key in table_cache:
+                C, D = table_cache[key]
+            else:
+                C, D = table_generation(phi, w)
+                if table_cache is not None:
+                    table_cache[key] = (C, D)
+            res = fase(s, w, phi, C, D, gamma, iters, classes)
+        else:
+            raise ValueError(method)
+        g = res.g.reshape(M, N)[b.ly:b.ly + b.lh, b.lx:b.lx + b.lw]
+        H, W = image.shape
+        for i in range(b.lh):
+            for j in range(b.lw):
+                y, x = b.y0 + b.ly + i, b.x0 + b.lx + j
+                if 0 <= y < H and 0 <= x < W:
+                    out[y, x] = quantise(g[i, j])
+        per_block.append((res, g.copy()))
+    return out, per_block
+
+
+# ----------------------------------------------------------------------------
+# duplicate atoms
+# ----------------------------------------------------------------------------
+def duplicate_classes(phi: np.ndarray, rtol: float = 1e-12) -> np.ndarray:
+    """Class id per atom: atoms k, l share a class when they are parallel over
+    the whole area, |<phi_k, phi_l>| >= (1 - rtol) |phi_k| |phi_l|.  The id is
+    the lowest index in the class.  Parallel atoms always tie in the selection
+    and give the same model, so selections are compared modulo these classes."""
+    phi = np.asarray(phi, dtype=np.float64)
+    norms = np.linalg.norm(phi, axis=1)
+    gram = phi @ phi.T
+    lim = (1.0 - rtol) * np.outer(norms, norms)
+    par = (np.abs(gram) >= lim) & (np.outer(norms, norms) > 0)
+    K = phi.shape[0]
+    cls = np.arange(K)
+    for k in range(K):
+        js = np.nonzero(par[k])[0]
+        cls[k] = int(js.min()) if js.size else k
+    return cls
+
+
+# ----------------------------------------------------------------------------
+# Table I
+# ----------------------------------------------------------------------------
+def operation_counts(M: int, N: int, K: int, I: int) -> Dict[str, Dict[str, int]]:
+    """Table I: MUL, ADD and OTHER operations of SE, FaSE (per block) and of
+    the FaSE table generation, for area M x N, |D| = K atoms, I iterations."""
+    MN = M * N
+    return {
+        "se": {"mul": I * (6 * MN * K + K + 2 * MN + 1),
+               "add": I * (3 * MN * K + 2 * MN),
+               "other": 3 * I * K},
+        "fase": {"mul": 2 * MN * K + I * (2 * K + MN + 1),
+                 "add": MN * K + I * (K + MN),
+                 "other": 2 * I * K},
+        "tables": {"mul": (K * K + K) * MN,
+                   "add": Fraction((K * K + K) * MN, 2),
+                   "other": Fraction((K * K + K) * MN, 2) + K},
+    }

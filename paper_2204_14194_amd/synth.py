@@ -1,0 +1,253 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module produces *inputs only*: 8-bit test images, loss layouts (which
+pixels are lost and which extrapolation area belongs to each lost block) and
+dictionaries of basis functions.  It contains no step of the extrapolation
+itself: no weighting function, no scalar products, no selection.  Both the
+FP64 oracle and the HIP path consume what it returns.
+
+The paper measures on natural 8-bit images with 16x16 lost blocks
+(Section "Results for Arbitrary Basis Functions", Table II); the generators
+below are seeded stand-ins with smooth oscillating texture plus sharp edges.
+
+Dictionary conventions (the paper allows arbitrary, even only numerically
+defined, basis functions, Section II):
+  * an atom is a length M*N vector over the extrapolation area, pixel (m, n)
+    at index m*N + n; a dictionary is a (K, M*N) float64 array;
+  * 2-D transform atoms are separable, index k = k1*N + k2 with k1 the
+    vertical frequency;
+  * DCT-II rows are orthonormal; Walsh-Hadamard rows are in natural
+    (Sylvester) order with entries +-1/sqrt(M);
+  * the DCT-II rows 0 and M/2 take exactly the values +-1/sqrt(M) in exact
+    arithmetic, the same as two Walsh-Hadamard rows.  Both dictionaries use
+    the identical float64 constant for those entries and the same outer
+    product, so the resulting parallel atoms in DCT u WHT unions are
+    bit-identical ("twins").
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Sequence
+
+import numpy as np
+
+__all__ = [
+    "synth_image", "dct_rows", "wht_rows", "separable_atoms", "dct2_atoms",
+    "wht2_atoms", "gaussian_atoms", "dictionary", "Block", "grid_layout",
+    "parity_lattice_layout", "lost_mask", "round_to_f32", "cfg0_inputs",
+    "cfg1_inputs", "cfg3_inputs",
+]
+
+
+# ----------------------------------------------------------------------------
+# images
+# ----------------------------------------------------------------------------
+def synth_image(H: int, W: int, seed: int, n_cos: int = 20, n_rect: int = 6,
+                amp_max: float = 40.0, step_max: float = 80.0,
+                f_max: float = 1.0 / 8.0) -> np.ndarray:
+    """Seeded uint8 image: 128 + sum of ``n_cos`` random 2-D cosines
+    (amplitude U[0, amp_max], frequency U[-f_max, f_max] cycles/px per axis,
+    phase U[0, 2 pi)) + ``n_rect`` axis-aligned rectangles with value steps
+    U[-step_max, step_max]; clipped to [0, 255] and rounded half-to-even.
+
+    Draw order (fixed): amplitudes, vertical freqs, horizontal freqs, phases,
+    then per rectangle: height, width, top, left, step.
+    """
+    rng = np.random.default_rng(seed)
+    amp = rng.uniform(0.0, amp_max, n_cos)
+    fy = rng.uniform(-f_max, f_max, n_cos)
+    fx = rng.uniform(-f_max, f_max, n_cos)
+    ph = rng.uniform(0.0, 2.0 * np.pi, n_cos)
+    y = np.arange(H, dtype=np.float64)[:, None]
+    x = np.arange(W, dtype=np.float64)[None, :]
+    img = np.full((H, W), 128.0)
+    for a, v, u, p in zip(amp, fy, fx, ph):
+        img += a * np.cos(2.0 * np.pi * (v * y + u * x) + p)
+    for _ in range(n_rect):
+        h = rng.uniform(H / 16.0, H / 2.0)
+        w = rng.uniform(W / 16.0, W / 2.0)
+        top = rng.uniform(0.0, H - h)
+        left = rng.uniform(0.0, W - w)
+        step = rng.uniform(-step_max, step_max)
+        y0, y1 = int(round(top)), int(round(top + h))
+        x0, x1 = int(round(left)), int(round(left + w))
+        img[y0:y1, x0:x1] += step
+    return np.rint(np.clip(img, 0.0, 255.0)).astype(np.uint8)
+
+
+# ----------------------------------------------------------------------------
+# dictionaries
+# ----------------------------------------------------------------------------
+def _inv_sqrt(M: int) -> float:
+    return 1.0 / np.sqrt(float(M))
+
+
+def dct_rows(M: int) -> np.ndarray:
+    """(M, M) orthonormal 1-D DCT-II rows, row k = alpha_k cos(pi (2m+1) k / 2M).
+    Rows 0 and M/2 are set to +-1/sqrt(M) exactly (their exact values)."""
+    m = np.arange(M, dtype=np.float64)
+    k = np.arange(M, dtype=np.float64)[:, None]
+    rows = np.sqrt(2.0 / M) * np.cos(np.pi * (2.0 * m + 1.0) * k / (2.0 * M))
+    c = _inv_sqrt(M)
+    rows[0, :] = c
+    if M % 2 == 0:
+        # cos(pi (2m+1)/4) is +sqrt(2)/2 for m = 0, 3 (mod 4), -sqrt(2)/2 else
+        sign = np.where(np.isin(np.arange(M) % 4, (0, 3)), 1.0, -1.0)
+        rows[M // 2, :] = sign * c
+    return rows
+
+
+def wht_rows(M: int) -> np.ndarray:
+    """(M, M) Walsh-Hadamard rows in natural (Sylvester) order:
+    row k, entry m = (-1)^popcount(m & k) / sqrt(M).  M must be a power of 2."""
+    if M <= 0 or (M & (M - 1)) != 0:
+        raise ValueError("Walsh-Hadamard rows need a power-of-two length")
+    m = np.arange(M)
+    k = np.arange(M)[:, None]
+    parity = np.vectorize(lambda v: bin(int(v)).count("1") & 1)(m & k)
+    return np.where(parity == 0, 1.0, -1.0) * _inv_sqrt(M)
+
+
+def separable_atoms(rows_v: np.ndarray, rows_h: np.ndarray) -> np.ndarray:
+    """2-D atoms phi_{k1*N+k2}[m*N+n] = rows_v[k1, m] * rows_h[k2, n]."""
+    Kv, M = rows_v.shape
+    Kh, N = rows_h.shape
+    out = rows_v[:, None, :, None] * rows_h[None, :, None, :]
+    return np.ascontiguousarray(out.reshape(Kv * Kh, M * N))
+
+
+def dct2_atoms(M: int, N: int) -> np.ndarray:
+    return separable_atoms(dct_rows(M), dct_rows(N))
+
+
+def wht2_atoms(M: int, N: int) -> np.ndarray:
+    return separable_atoms(wht_rows(M), wht_rows(N))
+
+
+def gaussian_atoms(M: int, N: int, count: int, seed: int) -> np.ndarray:
+    """``count`` numerically defined atoms: i.i.d. N(0,1) samples, each row
+    scaled to unit L2 norm over the M x N area."""
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((count, M * N))
+    return a / np.linalg.norm(a, axis=1, keepdims=True)
+
+
+def dictionary(M: int, N: int, parts: Sequence[str], seed: int = 101,
+               n_gauss: int = 0) -> np.ndarray:
+    """Union of sub-dictionaries, in the order given: 'dct', 'wht', 'gauss'."""
+    blocks = []
+    for p in parts:
+        if p == "dct":
+            blocks.append(dct2_atoms(M, N))
+        elif p == "wht":
+            blocks.append(wht2_atoms(M, N))
+        elif p == "gauss":
+            blocks.append(gaussian_atoms(M, N, n_gauss, seed))
+        else:
+            raise ValueError(p)
+    return np.ascontiguousarray(np.concatenate(blocks, axis=0))
+
+
+def round_to_f32(a: np.ndarray) -> np.ndarray:
+    """Round to the nearest float32 and return float64: the exact values a
+    float32 device buffer holds, so both sides start from identical inputs."""
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+# ----------------------------------------------------------------------------
+# loss layouts
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass(frozen=True)
+class Block:
+    """One lost block and its extrapolation area.
+
+    img      : index of the image the block lies in
+    y0, x0   : top-left corner of the M x N extrapolation area (image coords,
+               may lie partly outside the image)
+    ly, lx   : top-left corner of the loss rectangle, relative to the area
+    lh, lw   : loss rectangle size
+    """
+    img: int
+    y0: int
+    x0: int
+    ly: int
+    lx: int
+    lh: int
+    lw: int
+
+
+def grid_layout(H: int, W: int, cell: int, loss: int, n_img: int = 1) -> List[Block]:
+    """One centred ``loss`` x ``loss`` block in every ``cell`` x ``cell`` cell of
+    each H x W image; the area is the cell itself."""
+    off = (cell - loss) // 2
+    out = []
+    for i in range(n_img):
+        for cy in range(H // cell):
+            for cx in range(W // cell):
+                out.append(Block(i, cy * cell, cx * cell, off, off, loss, loss))
+    return out
+
+
+def parity_lattice_layout(H: int, W: int, loss: int, area: int, seed: int,
+                          margin: int, n_img: int = 1) -> List[Block]:
+    """One loss per 2x2 group of the ``loss``-pixel block grid, all on one seeded
+    parity lattice, so no area holds a second loss.  Coordinates are in a
+    canvas that extends the H x W image by ``margin`` pixels on every side."""
+    rng = np.random.default_rng(seed)
+    py, px = (int(v) for v in rng.integers(0, 2, size=2))
+    off = (area - loss) // 2
+    out = []
+    for i in range(n_img):
+        for by in range(py, H // loss, 2):
+            for bx in range(px, W // loss, 2):
+                y = margin + by * loss
+                x = margin + bx * loss
+                out.append(Block(i, y - off, x - off, off, off, loss, loss))
+    return out
+
+
+def lost_mask(H: int, W: int, blocks: Sequence[Block], img: int = 0) -> np.ndarray:
+    """uint8 mask, 1 where a pixel of image ``img`` is lost."""
+    mask = np.zeros((H, W), dtype=np.uint8)
+    for b in blocks:
+        if b.img != img:
+            continue
+        y, x = b.y0 + b.ly, b.x0 + b.lx
+        mask[max(y, 0):max(y + b.lh, 0), max(x, 0):max(x + b.lw, 0)] = 1
+    return mask
+
+
+# ----------------------------------------------------------------------------
+# the workloads (one geometry each)
+# ----------------------------------------------------------------------------
+def cfg0_inputs(n_img: int = 1, seed0: int = 0):
+    """128x128 images (seeds seed0..), 4x4 grid of 32x32 areas with centred
+    8x8 losses (support width 12); K = 2048 (DCT-II 32^2 u WHT 32^2);
+    rho_hat = 0.8, gamma = 0.5, I = 100."""
+    imgs = np.stack([synth_image(128, 128, seed0 + i) for i in range(n_img)])
+    blocks = grid_layout(128, 128, 32, 8, n_img)
+    phi = dictionary(32, 32, ("dct", "wht"))
+    return dict(images=imgs, blocks=blocks, phi=phi, M=32, N=32,
+                rho_hat=0.8, gamma=0.5, iters=100)
+
+
+def cfg1_inputs(n_img: int = 1, seed0: int = 1, layout_seed: int = 7):
+    """512x512 image generated on a 544x544 canvas (areas read from the
+    canvas); 256 isolated 16x16 losses on one parity lattice of the 16-px
+    grid; area 48x48; K = 4096 (DCT 48^2 u 1792 seeded Gaussian atoms);
+    rho_hat = 0.8, gamma = 0.5, I = 200."""
+    imgs = np.stack([synth_image(544, 544, seed0 + i) for i in range(n_img)])
+    blocks = parity_lattice_layout(512, 512, 16, 48, layout_seed, 16, n_img)
+    phi = dictionary(48, 48, ("dct", "gauss"), seed=101, n_gauss=1792)
+    return dict(images=imgs, blocks=blocks, phi=phi, M=48, N=48,
+                rho_hat=0.8, gamma=0.5, iters=200)
+
+
+def cfg3_inputs(n_img: int = 1, seed0: int = 300):
+    """2048x2048 image, 1024 64x64 areas with centred 16x16 losses;
+    K = 8192 (DCT 64^2 u WHT 64^2); rho_hat = 0.8, gamma = 0.5, I = 300."""
+    imgs = np.stack([synth_image(2048, 2048, seed0 + i) for i in range(n_img)])
+    blocks = grid_layout(2048, 2048, 64, 16, n_img)
+    phi = dictionary(64, 64, ("dct", "wht"))
+    return dict(images=imgs, blocks=blocks, phi=phi, M=64, N=64,
+                rho_hat=0.8, gamma=0.5, iters=300)
