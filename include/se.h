@@ -1,0 +1,225 @@
+/*
+ * se.h -- C ABI of libsefase: Fast Selective Extrapolation (FaSE) on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The calls follow the paper's statement of the problem (J. Seiler and
+ * A. Kaup, "A Fast Algorithm for Selective Signal Extrapolation with
+ * Arbitrary Basis Functions"):
+ *
+ *   se_area_weights        -- the weighting function w (eq. 4) with the
+ *                             isotropic decay rho (eq. 5), per block
+ *   se_weighted_gram       -- table generation, Algorithm 2 (eq. 16, 17)
+ *   se_extrapolate_batch   -- model generation, Algorithm 3 (eq. 12, 18-20,
+ *                             model update eq. 9, replacement of the loss
+ *                             area), batched over many blocks that share one
+ *                             set of tables
+ *   se_extrapolate_plain   -- the same result, one block at a time
+ *                             (three launches per block); the baseline form
+ *
+ * Conventions shared by every call
+ *   * Real-valued signals and atoms (Section III: for real data the
+ *     conjugations drop out).  Arithmetic is float32 unless a precision
+ *     argument says otherwise.
+ *   * An atom is a vector over the M x N extrapolation area, pixel (m, n) at
+ *     index m*N + n.  A dictionary is K atoms, row-major K x (M*N).
+ *   * Pointers documented "device" point to GPU memory the CALLER allocates
+ *     and owns (e.g. torch tensors); pointers documented "host" point to
+ *     host memory read during the call only.  The library never frees
+ *     caller memory and never keeps a pointer after a call returns.
+ *   * Every call is asynchronous on `stream` (a hipStream_t passed as void*,
+ *     NULL = the null stream) unless it says otherwise.  Argument errors are
+ *     detected on the host before anything is launched and return SE_EINVAL
+ *     synchronously; a failed launch returns SE_EHIP.  In both cases
+ *     se_last_error() describes the problem.
+ *   * Scratch memory ("ws") is device memory supplied by the caller; the
+ *     matching *_ws_bytes() call gives the size needed.  No call allocates
+ *     device memory.
+ */
+#ifndef SEFASE_SE_H
+#define SEFASE_SE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t se_status;
+#define SE_OK 0
+#define SE_EINVAL (-1)    /* invalid argument (host-side check)            */
+#define SE_ENOMEM (-2)    /* workspace or budget too small                 */
+#define SE_EHIP (-3)      /* a HIP runtime call or kernel launch failed    */
+#define SE_EAGAIN (-4)    /* result not ready yet (serving)                */
+#define SE_EBUSY (-5)     /* queue full (serving)                          */
+#define SE_ENUMERIC (-6)  /* numerically degenerate input                  */
+#define SE_ECANCELED (-7) /* request cancelled / server shut down         */
+
+typedef enum { SE_FP32 = 0, SE_BF16X3 = 1 } se_precision;
+
+/* Diagonal flags of se_weighted_gram (how C_(k,k) of eq. 16 is summed). */
+#define SE_DIAG_AUTO 0u        /* FP64 if precision is BF16X3 or the area is
+                                  ill-conditioned (min/max C_kk < 1e-3 over
+                                  atoms with C_kk > 0), else FP32          */
+#define SE_DIAG_FP64 1u        /* always FP64                              */
+#define SE_DIAG_FP32 2u        /* always FP32                              */
+
+/* A dictionary (Section II: phi_k[m, n], k in the dictionary D).
+ * phi: device, K x (M*N) float32, row-major. */
+typedef struct {
+  int32_t M, N, K;
+  const float* phi;
+} se_basis;
+
+/* One lost block and its extrapolation area L = A u B (Section II, Fig. 2).
+ * img      : index of the image in the batch of images
+ * y0, x0   : top-left corner of the M x N area in image coordinates; the
+ *            area may extend past the image border (those pixels are not
+ *            support: weight 0)
+ * ly, lx   : top-left corner of the loss rectangle B relative to the area
+ * lh, lw   : loss rectangle size; B must lie inside the area
+ * geom     : caller's tag of the weight pattern (not interpreted by the
+ *            batch calls, which take one table set for all blocks)       */
+typedef struct {
+  int32_t img, y0, x0, ly, lx, lh, lw, geom;
+} se_block;
+
+/* Tables for one weight pattern (Algorithm 2), as written by
+ * se_weighted_gram.  All pointers device, allocated by the caller:
+ *   G    : K x ldG float32, ldG >= K rounded up to a multiple of 4.
+ *          G[k][l] = D_k C_(k,l) D_l, the weighted Gram of eq. 16 expressed
+ *          for the atoms scaled to unit weighted norm (so G[k][k] = 1 for
+ *          every atom with C_kk > 0).  Exactly symmetric.  Columns >= K
+ *          are never read.
+ *   D    : K float32, D_k = 1/sqrt(C_(k,k)) (eq. 17); 0 for an atom whose
+ *          weighted norm is 0 (it can never be selected).
+ *   Y    : K x (M*N) float32, Y[k][p] = D_k sqrt(w[p]) phi_k[p]; the
+ *          initial projections of eq. 12 are Y (sqrt(w) s), in units of
+ *          D_k.
+ *   sqrtw: M*N float32, sqrt(w).
+ *   phi  : the dictionary itself (read by the model update).
+ *   info : optional (may be NULL) device int32: 1 if the diagonal was
+ *          summed in FP64, 0 if in FP32.                                  */
+typedef struct {
+  int32_t M, N, K, ldG;
+  float* G;
+  float* D;
+  float* Y;
+  float* sqrtw;
+  const float* phi;
+  int32_t* info;
+} se_tables;
+
+/* Model-generation parameters: gamma of eq. 8 (0 < gamma <= 1) and the
+ * iteration count I. */
+typedef struct {
+  float gamma;
+  int32_t iters;
+  uint32_t flags; /* reserved, must be 0 */
+} se_params;
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics                                                              */
+/* ------------------------------------------------------------------------ */
+
+/* Text of the last error on the calling thread ("" if none). */
+const char* se_last_error(void);
+/* Library version as 10000*major + 100*minor + patch. */
+int32_t se_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Weighting function: eq. 4 and eq. 5                                      */
+/* ------------------------------------------------------------------------ */
+
+/* w_b[m*N+n] = rho_hat ^ sqrt((m-(M-1)/2)^2 + (n-(N-1)/2)^2) for every
+ * pixel of block b's area that lies inside the image and is not lost, and
+ * 0 elsewhere (eq. 4: the loss and every unavailable pixel are masked).
+ *   lost    : device uint8, n_img images of H x W (row pitch W, image
+ *             stride H*W); nonzero = lost pixel
+ *   blocks  : host, n_blk descriptors (only img, y0, x0 are read)
+ *   w       : device, n_blk x (M*N) float32 output
+ *   ws      : device scratch of se_area_weights_ws_bytes(n_blk) bytes
+ * Errors: SE_EINVAL for M, N < 1, rho_hat outside (0, 1], img out of range,
+ * ws too small. */
+size_t se_area_weights_ws_bytes(int32_t n_blk);
+se_status se_area_weights(int32_t M, int32_t N, float rho_hat,
+                          const uint8_t* lost, int32_t n_img, int32_t H,
+                          int32_t W, const se_block* blocks, int32_t n_blk,
+                          float* w, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Table generation: Algorithm 2, eq. 16, eq. 17                            */
+/* ------------------------------------------------------------------------ */
+
+/* Builds the tables of one weight pattern w (device, M*N float32, w >= 0)
+ * for dictionary b into *t (whose buffers and ldG the caller has set; M, N,
+ * K and phi are filled in from b).  The diagonal C_kk is summed first (FP32
+ * or FP64 per `flags`), then D, then Y, then the lower triangle of
+ * G = Y Y^T on the matrix cores (FP32 MFMA for SE_FP32; three BF16 products
+ * hi*hi + hi*lo + lo*hi with FP32 accumulation for SE_BF16X3), mirrored to
+ * the upper triangle -- Algorithm 2 computes (|D|^2 + |D|)/2 products and
+ * mirrors the rest.
+ * ws: device scratch of se_weighted_gram_ws_bytes(b, prec) bytes.
+ * Errors: SE_EINVAL for a NULL pointer, K < 1, ldG < K or not a multiple
+ * of 4, an unknown precision or flag, ws too small. */
+size_t se_weighted_gram_ws_bytes(const se_basis* b, se_precision prec);
+se_status se_weighted_gram(const se_basis* b, const float* w,
+                           se_precision prec, uint32_t flags, se_tables* t,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Model generation: Algorithm 3                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Conceals n_blk lost blocks that share the tables t (one weight pattern:
+ * the caller guarantees every block's available pixels match the w the
+ * tables were built from).  Per block:
+ *   R^(0) = initial weighted projections (eq. 12), for all blocks at once as
+ *           one matrix product on the matrix cores;
+ *   I times: u = argmax_k |R_k| D_k (eq. 18; exact ties go to the lowest
+ *           k), c = gamma R_u D_u^2 (eq. 19), g += c phi_u over the loss
+ *           (eq. 9), R_k -= c C_(k,u) for all k (eq. 20);
+ *   the loss rectangle of `images` is replaced by clip(rint(g), 0, 255)
+ *           (round half to even).
+ * Arguments:
+ *   images  : device uint8, n_img images H x W (row pitch W, image stride
+ *             H*W); read on the support, written on each loss (in place)
+ *   blocks  : host, n_blk descriptors; every loss rectangle must lie inside
+ *             its area and hold at most 4*64*waves pixels (waves = the
+ *             workgroup size the library picks for K: 1 for K <= 2048,
+ *             2 for K <= 4096, 4 for K <= 8192, 8 for K <= 16384; so >= 256
+ *             pixels always); losses of different blocks must not overlap
+ *   sel     : optional device int32 n_blk x iters, selected atom per
+ *             iteration (NULL to skip)
+ *   coef    : optional device float32 n_blk x iters, coefficient c per
+ *             iteration (NULL to skip)
+ *   g_loss  : optional device float32 n_blk x g_loss_ld, the model over the
+ *             loss before rounding, row-major lh x lw (NULL to skip)
+ *   ws      : device scratch of se_extrapolate_batch_ws_bytes() bytes
+ * Errors: SE_EINVAL for bad descriptors or parameters (nothing launched),
+ * SE_ENOMEM for ws too small, SE_EHIP for launch failures. */
+size_t se_extrapolate_batch_ws_bytes(const se_tables* t, int32_t n_blk);
+se_status se_extrapolate_batch(const se_tables* t, uint8_t* images,
+                               int32_t n_img, int32_t H, int32_t W,
+                               const se_block* blocks, int32_t n_blk,
+                               se_params prm, int32_t* sel, float* coef,
+                               float* g_loss, int32_t g_loss_ld, void* ws,
+                               size_t ws_bytes, void* stream);
+
+/* Same contract and results as se_extrapolate_batch, executed one block at
+ * a time: per block one gather launch, one matrix-vector launch for R^(0)
+ * and one single-workgroup launch of the iteration loop.  This is the
+ * "plain per-block" baseline the batched form is measured against.  The
+ * workspace is se_extrapolate_batch_ws_bytes(t, n_blk) (only part of it is
+ * used). */
+se_status se_extrapolate_plain(const se_tables* t, uint8_t* images,
+                               int32_t n_img, int32_t H, int32_t W,
+                               const se_block* blocks, int32_t n_blk,
+                               se_params prm, int32_t* sel, float* coef,
+                               float* g_loss, int32_t g_loss_ld, void* ws,
+                               size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEFASE_SE_H */

@@ -1,0 +1,245 @@
+"""ctypes binding of libsefase (include/se.h).
+
+Argument marshalling only: torch tensors provide device memory and the HIP
+stream; every step of the method runs in the library's HIP kernels.  There is
+no fallback: if the library is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsefase.so")
+
+SE_OK, SE_EINVAL, SE_ENOMEM, SE_EHIP, SE_EAGAIN, SE_EBUSY, SE_ENUMERIC, SE_ECANCELED = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+SE_FP32, SE_BF16X3 = 0, 1
+SE_DIAG_AUTO, SE_DIAG_FP64, SE_DIAG_FP32 = 0, 1, 2
+
+# every symbol include/se.h declares
+EXPORTED = (
+    "se_last_error", "se_version", "se_area_weights_ws_bytes", "se_area_weights",
+    "se_weighted_gram_ws_bytes", "se_weighted_gram", "se_extrapolate_batch_ws_bytes",
+    "se_extrapolate_batch", "se_extrapolate_plain",
+)
+
+
+class SEError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libsefase error {code}: {msg}")
+        self.code = code
+
+
+class se_basis(C.Structure):
+    _fields_ = [("M", C.c_int32), ("N", C.c_int32), ("K", C.c_int32), ("phi", C.c_void_p)]
+
+
+class se_block(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("img", "y0", "x0", "ly", "lx", "lh", "lw", "geom")]
+
+
+class se_tables(C.Structure):
+    _fields_ = [("M", C.c_int32), ("N", C.c_int32), ("K", C.c_int32), ("ldG", C.c_int32),
+                ("G", C.c_void_p), ("D", C.c_void_p), ("Y", C.c_void_p),
+                ("sqrtw", C.c_void_p), ("phi", C.c_void_p), ("info", C.c_void_p)]
+
+
+class se_params(C.Structure):
+    _fields_ = [("gamma", C.c_float), ("iters", C.c_int32), ("flags", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Open libsefase.so (once).  Raises if it is missing: there is no other
+    implementation to fall back to."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing; build it with "
+                           "`python -m paper_2204_14194_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, f32, sz = C.c_void_p, C.c_int32, C.c_float, C.c_size_t
+    L.se_last_error.restype = C.c_char_p
+    L.se_version.restype = i32
+    L.se_area_weights_ws_bytes.restype = sz
+    L.se_area_weights_ws_bytes.argtypes = [i32]
+    L.se_area_weights.restype = i32
+    L.se_area_weights.argtypes = [i32, i32, f32, vp, i32, i32, i32, vp, i32, vp, vp, sz, vp]
+    L.se_weighted_gram_ws_bytes.restype = sz
+    L.se_weighted_gram_ws_bytes.argtypes = [C.POINTER(se_basis), i32]
+    L.se_weighted_gram.restype = i32
+    L.se_weighted_gram.argtypes = [C.POINTER(se_basis), vp, i32, C.c_uint32,
+                                   C.POINTER(se_tables), vp, sz, vp]
+    L.se_extrapolate_batch_ws_bytes.restype = sz
+    L.se_extrapolate_batch_ws_bytes.argtypes = [C.POINTER(se_tables), i32]
+    for name in ("se_extrapolate_batch", "se_extrapolate_plain"):
+        f = getattr(L, name)
+        f.restype = i32
+        f.argtypes = [C.POINTER(se_tables), vp, i32, i32, i32, vp, i32, se_params, vp, vp, vp,
+                      i32, vp, sz, vp]
+    _lib = L
+    return L
+
+
+def _check(code: int):
+    if code != SE_OK:
+        raise SEError(code, lib().se_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_f32(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    return t
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def blocks_array(blocks: Sequence) -> C.Array:
+    """Host array of se_block from objects with img, y0, x0, ly, lx, lh, lw
+    (and optionally geom)."""
+    arr = (se_block * max(len(blocks), 1))()
+    for i, b in enumerate(blocks):
+        arr[i] = se_block(b.img, b.y0, b.x0, b.ly, b.lx, b.lh, b.lw, getattr(b, "geom", 0))
+    return arr
+
+
+def version() -> int:
+    return int(lib().se_version())
+
+
+# ---------------------------------------------------------------------------
+def area_weights(M: int, N: int, rho_hat: float, lost: torch.Tensor, blocks: Sequence,
+                 stream=None) -> torch.Tensor:
+    """se_area_weights: per-block weights (n_blk, M*N) float32 on the device."""
+    L = lib()
+    if not (lost.is_cuda and lost.dtype == torch.uint8 and lost.dim() == 3 and lost.is_contiguous()):
+        raise ValueError("lost must be a contiguous (n_img, H, W) uint8 CUDA tensor")
+    n_img, H, W = lost.shape
+    n = len(blocks)
+    w = torch.empty((n, M * N), dtype=torch.float32, device=lost.device)
+    nb = L.se_area_weights_ws_bytes(n)
+    ws = _workspace(nb, lost.device)
+    arr = blocks_array(blocks)
+    _check(L.se_area_weights(M, N, float(rho_hat), _ptr(lost), n_img, H, W, arr, n, _ptr(w),
+                             _ptr(ws), nb, _stream(stream)))
+    return w
+
+
+@dataclass
+class Tables:
+    """Device tables of one weight pattern and the ctypes struct describing them."""
+    M: int
+    N: int
+    K: int
+    ldG: int
+    G: torch.Tensor
+    D: torch.Tensor
+    Y: torch.Tensor
+    sqrtw: torch.Tensor
+    phi: torch.Tensor
+    info: torch.Tensor
+    precision: int
+
+    def struct(self) -> se_tables:
+        return se_tables(self.M, self.N, self.K, self.ldG, self.G.data_ptr(), self.D.data_ptr(),
+                         self.Y.data_ptr(), self.sqrtw.data_ptr(), self.phi.data_ptr(),
+                         self.info.data_ptr())
+
+    def nbytes(self) -> int:
+        return sum(t.numel() * t.element_size() for t in (self.G, self.D, self.Y, self.sqrtw))
+
+
+def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
+                  precision: int = SE_FP32, flags: int = SE_DIAG_AUTO, stream=None) -> Tables:
+    """se_weighted_gram (Algorithm 2) for dictionary ``phi`` (K, M*N) and weight
+    pattern ``w`` (M*N,)."""
+    L = lib()
+    _dev_f32(phi, "phi")
+    _dev_f32(w, "w")
+    K = phi.shape[0]
+    if phi.shape[1] != M * N or w.numel() != M * N:
+        raise ValueError("phi must be (K, M*N) and w (M*N,)")
+    ldG = (K + 3) // 4 * 4
+    dev = phi.device
+    t = Tables(M, N, K, ldG,
+               torch.empty((K, ldG), dtype=torch.float32, device=dev),
+               torch.empty(K, dtype=torch.float32, device=dev),
+               torch.empty((K, M * N), dtype=torch.float32, device=dev),
+               torch.empty(M * N, dtype=torch.float32, device=dev),
+               phi, torch.zeros(1, dtype=torch.int32, device=dev), int(precision))
+    b = se_basis(M, N, K, phi.data_ptr())
+    nb = L.se_weighted_gram_ws_bytes(C.byref(b), int(precision))
+    ws = _workspace(nb, dev)
+    st = t.struct()
+    _check(L.se_weighted_gram(C.byref(b), _ptr(w), int(precision), int(flags), C.byref(st),
+                              _ptr(ws), nb, _stream(stream)))
+    return t
+
+
+def extrapolate_batch_ws_bytes(t: Tables, n_blk: int) -> int:
+    st = t.struct()
+    return int(lib().se_extrapolate_batch_ws_bytes(C.byref(st), n_blk))
+
+
+def _extrapolate(name: str, t: Tables, images: torch.Tensor, blocks: Sequence, gamma: float,
+                 iters: int, want_sel: bool, want_coef: bool, want_g: bool,
+                 ws: Optional[torch.Tensor], stream, blocks_arr=None):
+    L = lib()
+    if not (images.is_cuda and images.dtype == torch.uint8 and images.dim() == 3
+            and images.is_contiguous()):
+        raise ValueError("images must be a contiguous (n_img, H, W) uint8 CUDA tensor")
+    n_img, H, W = images.shape
+    n = len(blocks)
+    dev = images.device
+    sel = torch.empty((n, iters), dtype=torch.int32, device=dev) if want_sel else None
+    coef = torch.empty((n, iters), dtype=torch.float32, device=dev) if want_coef else None
+    gld = max([b.lh * b.lw for b in blocks] + [1])
+    g = torch.zeros((n, gld), dtype=torch.float32, device=dev) if want_g else None
+    st = t.struct()
+    nb = L.se_extrapolate_batch_ws_bytes(C.byref(st), n)
+    if ws is None:
+        ws = _workspace(nb, dev)
+    elif ws.numel() < nb:
+        raise ValueError(f"workspace of {ws.numel()} bytes < {nb}")
+    arr = blocks_arr if blocks_arr is not None else blocks_array(blocks)
+    prm = se_params(float(gamma), int(iters), 0)
+    _check(getattr(L, name)(C.byref(st), _ptr(images), n_img, H, W, arr, n, prm, _ptr(sel),
+                            _ptr(coef), _ptr(g), gld, _ptr(ws), ws.numel(), _stream(stream)))
+    return sel, coef, g
+
+
+def extrapolate_batch(t: Tables, images: torch.Tensor, blocks: Sequence, gamma: float,
+                      iters: int, want_sel=True, want_coef=True, want_g=True, ws=None,
+                      stream=None, blocks_arr=None):
+    """se_extrapolate_batch (Algorithm 3, batched).  ``images`` is modified in
+    place (each loss replaced).  Returns (sel, coef, g_loss) device tensors
+    (None where not requested)."""
+    return _extrapolate("se_extrapolate_batch", t, images, blocks, gamma, iters, want_sel,
+                        want_coef, want_g, ws, stream, blocks_arr)
+
+
+def extrapolate_plain(t: Tables, images: torch.Tensor, blocks: Sequence, gamma: float,
+                      iters: int, want_sel=True, want_coef=True, want_g=True, ws=None,
+                      stream=None, blocks_arr=None):
+    """se_extrapolate_plain: same results, one block at a time."""
+    return _extrapolate("se_extrapolate_plain", t, images, blocks, gamma, iters, want_sel,
+                        want_coef, want_g, ws, stream, blocks_arr)

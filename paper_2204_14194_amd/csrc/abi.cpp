@@ -1,0 +1,270 @@
+// Host side of the C ABI declared in include/se.h: argument validation,
+// workspace carving and kernel sequencing.  Nothing here computes any part
+// of the method; every step runs in the HIP kernels of this directory.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "se_internal.h"
+
+namespace sefase {
+
+static thread_local char g_err[512] = "";
+
+se_status fail(se_status code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+se_status check_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SE_EHIP, "%s: %s", what, hipGetErrorString(e));
+  return SE_OK;
+}
+
+static inline int round4(int v) { return (v + 3) & ~3; }
+
+// Carves aligned sub-buffers out of the caller's workspace.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* p) : base(static_cast<char*>(p)) {}
+  template <class T>
+  T* take(size_t count) {
+    off = align_up(off, 256);
+    T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+static se_status upload_blocks(const se_block* blocks, int n_blk, DevBlock* dst,
+                               hipStream_t s) {
+  std::vector<DevBlock> tmp((size_t)n_blk);
+  for (int i = 0; i < n_blk; ++i) {
+    const se_block& b = blocks[i];
+    tmp[(size_t)i] = DevBlock{b.img, b.y0, b.x0, b.ly, b.lx, b.lh, b.lw, 0};
+  }
+  // pageable source: the call returns once the data has been staged
+  const hipError_t e = hipMemcpyAsync(dst, tmp.data(), tmp.size() * sizeof(DevBlock),
+                                      hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return fail(SE_EHIP, "block upload: %s", hipGetErrorString(e));
+  return SE_OK;
+}
+
+static se_status check_tables(const se_tables* t) {
+  if (!t) return fail(SE_EINVAL, "tables is NULL");
+  if (t->M < 1 || t->N < 1 || t->K < 1) return fail(SE_EINVAL, "bad table shape M=%d N=%d K=%d", t->M, t->N, t->K);
+  if ((long long)t->M * t->N > (1 << 24)) return fail(SE_EINVAL, "area too large");
+  if (t->ldG < t->K || (t->ldG & 3)) return fail(SE_EINVAL, "ldG=%d must be >= K=%d and a multiple of 4", t->ldG, t->K);
+  if (!t->G || !t->D || !t->Y || !t->sqrtw || !t->phi) return fail(SE_EINVAL, "a table pointer is NULL");
+  if (reinterpret_cast<uintptr_t>(t->G) % 16) return fail(SE_EINVAL, "G must be 16-byte aligned");
+  if (greedy_waves_for(t->K) == 0) return fail(SE_EINVAL, "K=%d exceeds 16384", t->K);
+  return SE_OK;
+}
+
+static se_status check_blocks(const se_tables* t, int n_img, int H, int W, const se_block* blocks,
+                              int n_blk, int g_loss_ld, const float* g_loss) {
+  if (n_blk < 0) return fail(SE_EINVAL, "n_blk < 0");
+  if (n_blk > 0 && !blocks) return fail(SE_EINVAL, "blocks is NULL");
+  if (n_img < 1 || H < 1 || W < 1) return fail(SE_EINVAL, "bad image batch %d x %d x %d", n_img, H, W);
+  const int T = 64 * greedy_waves_for(t->K);
+  for (int i = 0; i < n_blk; ++i) {
+    const se_block& b = blocks[i];
+    if (b.img < 0 || b.img >= n_img) return fail(SE_EINVAL, "block %d: img %d out of range", i, b.img);
+    if (b.lh < 1 || b.lw < 1 || b.ly < 0 || b.lx < 0 || b.ly + b.lh > t->M || b.lx + b.lw > t->N)
+      return fail(SE_EINVAL, "block %d: loss rectangle not inside the %dx%d area", i, t->M, t->N);
+    if (b.lh * b.lw > 4 * T)
+      return fail(SE_EINVAL, "block %d: loss of %d pixels exceeds %d", i, b.lh * b.lw, 4 * T);
+    if (g_loss && b.lh * b.lw > g_loss_ld)
+      return fail(SE_EINVAL, "block %d: g_loss_ld=%d < loss size %d", i, g_loss_ld, b.lh * b.lw);
+  }
+  return SE_OK;
+}
+
+}  // namespace sefase
+
+using namespace sefase;
+
+extern "C" {
+
+const char* se_last_error(void) { return g_err; }
+int32_t se_version(void) { return 100; }
+
+// ---------------------------------------------------------------------------
+size_t se_area_weights_ws_bytes(int32_t n_blk) {
+  return align_up((size_t)(n_blk > 0 ? n_blk : 0) * sizeof(DevBlock), 256) + 256;
+}
+
+se_status se_area_weights(int32_t M, int32_t N, float rho_hat, const uint8_t* lost, int32_t n_img,
+                          int32_t H, int32_t W, const se_block* blocks, int32_t n_blk, float* w,
+                          void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  if (M < 1 || N < 1) return fail(SE_EINVAL, "bad area %dx%d", M, N);
+  if (!(rho_hat > 0.0f && rho_hat <= 1.0f)) return fail(SE_EINVAL, "rho_hat must lie in (0, 1]");
+  if (!lost || !w || (n_blk > 0 && !blocks)) return fail(SE_EINVAL, "NULL pointer");
+  if (n_img < 1 || H < 1 || W < 1) return fail(SE_EINVAL, "bad image batch");
+  if (n_blk < 0) return fail(SE_EINVAL, "n_blk < 0");
+  for (int i = 0; i < n_blk; ++i)
+    if (blocks[i].img < 0 || blocks[i].img >= n_img)
+      return fail(SE_EINVAL, "block %d: img out of range", i);
+  if (n_blk == 0) return SE_OK;
+  if (!ws || ws_bytes < se_area_weights_ws_bytes(n_blk)) return fail(SE_ENOMEM, "workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Carver cv(ws);
+  DevBlock* dblk = cv.take<DevBlock>((size_t)n_blk);
+  se_status st = upload_blocks(blocks, n_blk, dblk, s);
+  if (st) return st;
+  launch_area_weights(M, N, rho_hat, lost, H, W, dblk, n_blk, w, s);
+  return check_launch("area_weights");
+}
+
+// ---------------------------------------------------------------------------
+size_t se_weighted_gram_ws_bytes(const se_basis* b, se_precision prec) {
+  if (!b || b->K < 1 || b->M < 1 || b->N < 1) return 0;
+  Carver cv(nullptr);
+  const size_t K = (size_t)b->K, P = (size_t)b->M * b->N;
+  cv.take<float>(K);
+  cv.take<double>(K);
+  if (prec == SE_BF16X3) {
+    cv.take<uint16_t>(K * P);
+    cv.take<uint16_t>(K * P);
+  }
+  return cv.off + 256;
+}
+
+se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec, uint32_t flags,
+                           se_tables* t, void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  if (!b || !w || !t) return fail(SE_EINVAL, "NULL argument");
+  if (!b->phi) return fail(SE_EINVAL, "basis phi is NULL");
+  if (b->M < 1 || b->N < 1 || b->K < 1) return fail(SE_EINVAL, "bad basis shape");
+  if (prec != SE_FP32 && prec != SE_BF16X3) return fail(SE_EINVAL, "unknown precision %d", (int)prec);
+  if (flags > SE_DIAG_FP32) return fail(SE_EINVAL, "unknown flags 0x%x", flags);
+  t->M = b->M;
+  t->N = b->N;
+  t->K = b->K;
+  t->phi = b->phi;
+  se_status st = check_tables(t);
+  if (st) return st;
+  if (!ws || ws_bytes < se_weighted_gram_ws_bytes(b, prec)) return fail(SE_ENOMEM, "workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int K = b->K, P = b->M * b->N;
+  Carver cv(ws);
+  float* diag32 = cv.take<float>((size_t)K);
+  double* diag64 = cv.take<double>((size_t)K);
+  launch_diag(b->phi, w, K, P, diag32, diag64, s);
+  if ((st = check_launch("diag"))) return st;
+  launch_finalize_d(diag32, diag64, w, K, P, (int)flags, prec == SE_BF16X3 ? 1 : 0, t->D, t->sqrtw,
+                    t->info, s);
+  if ((st = check_launch("finalize_d"))) return st;
+  launch_scale_y(b->phi, t->D, t->sqrtw, K, P, t->Y, s);
+  if ((st = check_launch("scale_y"))) return st;
+  if (prec == SE_FP32) {
+    return gemm_nt_f32(t->Y, P, t->Y, P, t->G, t->ldG, K, K, K, P, true, 0, s);
+  }
+  uint16_t* yhi = cv.take<uint16_t>((size_t)K * P);
+  uint16_t* ylo = cv.take<uint16_t>((size_t)K * P);
+  launch_split_bf16(t->Y, (size_t)K * P, yhi, ylo, s);
+  if ((st = check_launch("split_bf16"))) return st;
+  return gemm_nt_bf16x3(yhi, ylo, P, yhi, ylo, P, t->G, t->ldG, K, K, K, P, true, s);
+}
+
+// ---------------------------------------------------------------------------
+size_t se_extrapolate_batch_ws_bytes(const se_tables* t, int32_t n_blk) {
+  if (!t || t->K < 1 || t->M < 1 || t->N < 1 || n_blk < 0) return 0;
+  Carver cv(nullptr);
+  const size_t P = (size_t)t->M * t->N;
+  cv.take<DevBlock>((size_t)n_blk);
+  cv.take<float>((size_t)n_blk * round4((int)P));
+  cv.take<float>((size_t)n_blk * round4(t->K));
+  return cv.off + 256;
+}
+
+static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, int32_t n_img,
+                             int32_t H, int32_t W, const se_block* blocks, int32_t n_blk,
+                             se_params prm, int32_t* sel, float* coef, float* g_loss,
+                             int32_t g_loss_ld, void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  se_status st = check_tables(t);
+  if (st) return st;
+  if (!images) return fail(SE_EINVAL, "images is NULL");
+  if (!(prm.gamma > 0.0f && prm.gamma <= 1.0f)) return fail(SE_EINVAL, "gamma must lie in (0, 1]");
+  if (prm.iters < 0) return fail(SE_EINVAL, "iters < 0");
+  if (prm.flags != 0) return fail(SE_EINVAL, "unknown flags 0x%x", prm.flags);
+  if ((st = check_blocks(t, n_img, H, W, blocks, n_blk, g_loss_ld, g_loss))) return st;
+  if (n_blk == 0) return SE_OK;
+  // the plain form uploads every descriptor but needs only one X/R row
+  const int nws = plain ? 1 : n_blk;
+  Carver cv(ws);
+  const int P = t->M * t->N, ldX = round4(P), ldR = round4(t->K);
+  DevBlock* dblk = cv.take<DevBlock>((size_t)n_blk);
+  float* X = cv.take<float>((size_t)nws * ldX);
+  float* R = cv.take<float>((size_t)nws * ldR);
+  if (!ws || cv.off + 256 > ws_bytes)
+    return fail(SE_ENOMEM, "workspace too small: need %zu bytes", cv.off + 256);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = upload_blocks(blocks, n_blk, dblk, s))) return st;
+
+  GreedyArgs ga;
+  ga.R0 = R;
+  ga.ldR = ldR;
+  ga.G = t->G;
+  ga.ldG = t->ldG;
+  ga.D = t->D;
+  ga.phi = t->phi;
+  ga.K = t->K;
+  ga.M = t->M;
+  ga.N = t->N;
+  ga.blk = dblk;
+  ga.n_blk = n_blk;
+  ga.blk0 = 0;
+  ga.images = images;
+  ga.H = H;
+  ga.W = W;
+  ga.gamma = prm.gamma;
+  ga.iters = prm.iters;
+  ga.sel = sel;
+  ga.coef = coef;
+  ga.g_loss = g_loss;
+  ga.g_loss_ld = g_loss_ld;
+
+  if (!plain) {
+    launch_gather(images, H, W, dblk, n_blk, t->M, t->N, t->sqrtw, X, ldX, s);
+    if ((st = check_launch("gather"))) return st;
+    if ((st = gemm_nt_f32(X, ldX, t->Y, P, R, ldR, n_blk, t->K, ldR, P, false, 0, s))) return st;
+    return launch_greedy(ga, n_blk, s);
+  }
+  for (int i = 0; i < n_blk; ++i) {
+    launch_gather(images, H, W, dblk + i, 1, t->M, t->N, t->sqrtw, X, ldX, s);
+    if ((st = check_launch("gather"))) return st;
+    launch_gemv(t->Y, t->K, P, X, R, s);
+    if ((st = check_launch("gemv"))) return st;
+    ga.blk0 = i;
+    if ((st = launch_greedy(ga, 1, s))) return st;
+  }
+  return SE_OK;
+}
+
+se_status se_extrapolate_batch(const se_tables* t, uint8_t* images, int32_t n_img, int32_t H,
+                               int32_t W, const se_block* blocks, int32_t n_blk, se_params prm,
+                               int32_t* sel, float* coef, float* g_loss, int32_t g_loss_ld,
+                               void* ws, size_t ws_bytes, void* stream) {
+  return extrapolate(false, t, images, n_img, H, W, blocks, n_blk, prm, sel, coef, g_loss,
+                     g_loss_ld, ws, ws_bytes, stream);
+}
+
+se_status se_extrapolate_plain(const se_tables* t, uint8_t* images, int32_t n_img, int32_t H,
+                               int32_t W, const se_block* blocks, int32_t n_blk, se_params prm,
+                               int32_t* sel, float* coef, float* g_loss, int32_t g_loss_ld,
+                               void* ws, size_t ws_bytes, void* stream) {
+  return extrapolate(true, t, images, n_img, H, W, blocks, n_blk, prm, sel, coef, g_loss,
+                     g_loss_ld, ws, ws_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// Internal declarations shared by the HIP translation units of libsefase.
+// Device code targets gfx950 (CDNA4) only: 64-lane wavefronts, MFMA matrix
+// cores, 160 KiB of LDS per compute unit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/se.h"
+
+namespace sefase {
+
+// ---------------------------------------------------------------------------
+// error reporting (thread-local message, see se_last_error)
+// ---------------------------------------------------------------------------
+se_status fail(se_status code, const char* fmt, ...);
+se_status check_launch(const char* what);
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Device copy of one block descriptor, validated on the host.
+struct DevBlock {
+  int32_t img, y0, x0, ly, lx, lh, lw, pad;
+};
+
+// ---------------------------------------------------------------------------
+// kernel launchers (defined in the .hip files)
+// ---------------------------------------------------------------------------
+
+// weights.hip -- eq. 4 / eq. 5 per block
+void launch_area_weights(int M, int N, float rho_hat, const uint8_t* lost,
+                         int H, int W, const DevBlock* blk, int n_blk,
+                         float* w, hipStream_t s);
+
+// gram.hip -- Algorithm 2 support kernels
+// diag32/diag64: C_kk summed in fp32 and fp64 with one fixed order.
+void launch_diag(const float* phi, const float* w, int K, int P,
+                 float* diag32, double* diag64, hipStream_t s);
+// D_k from the diagonal (mode 0 auto, 1 fp64, 2 fp32), sqrt(w), info word.
+void launch_finalize_d(const float* diag32, const double* diag64,
+                       const float* w, int K, int P, int mode, int force64,
+                       float* D, float* sqrtw, int32_t* info, hipStream_t s);
+// Y[k][p] = D_k sqrt(w_p) phi[k][p]
+void launch_scale_y(const float* phi, const float* D, const float* sqrtw,
+                    int K, int P, float* Y, hipStream_t s);
+// split x = hi + lo into two bf16 arrays (precision path)
+void launch_split_bf16(const float* x, size_t n, uint16_t* hi, uint16_t* lo,
+                       hipStream_t s);
+
+// gemm.hip -- C[r][c] = sum_p A[r][p] B[c][p] (both operands row-major with
+// the contraction index contiguous).  syrk: A == B, only tiles on or below
+// the diagonal are computed and each is also stored transposed.
+// Rows r < Mr, columns c < Nc are computed; columns Nc <= c < Nst are
+// stored as 0 (padding of the output rows).
+se_status gemm_nt_f32(const float* A, int lda, const float* B, int ldb,
+                      float* C, int ldc, int Mr, int Nc, int Nst, int P,
+                      bool syrk, int tile, hipStream_t s);
+se_status gemm_nt_bf16x3(const uint16_t* Ahi, const uint16_t* Alo, int lda,
+                         const uint16_t* Bhi, const uint16_t* Blo, int ldb,
+                         float* C, int ldc, int Mr, int Nc, int Nst, int P,
+                         bool syrk, hipStream_t s);
+
+// project.hip -- X[b][p] = sqrt(w_p) s_b[p] and the per-block GEMV
+void launch_gather(const uint8_t* images, int H, int W, const DevBlock* blk,
+                   int n_blk, int M, int N, const float* sqrtw, float* X,
+                   int ldX, hipStream_t s);
+void launch_gemv(const float* Y, int K, int P, const float* x, float* r,
+                 hipStream_t s);
+
+// greedy.hip -- the iteration loop of Algorithm 3
+struct GreedyArgs {
+  const float* R0;     // n_blk x ldR initial projections (units of D_k)
+  int ldR;
+  const float* G;      // K x ldG unit-diagonal Gram
+  int ldG;
+  const float* D;      // K
+  const float* phi;    // K x M*N
+  int K, M, N;
+  const DevBlock* blk; // n_blk
+  int n_blk;
+  int blk0;            // index of the first block (plain form: one launch per block)
+  uint8_t* images;
+  int H, W;
+  float gamma;
+  int iters;
+  int32_t* sel;        // optional
+  float* coef;         // optional
+  float* g_loss;       // optional
+  int g_loss_ld;
+};
+int greedy_waves_for(int K);   // 0 if K is too large
+se_status launch_greedy(const GreedyArgs& a, int grid, hipStream_t s);
+
+}  // namespace sefase

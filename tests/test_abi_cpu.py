@@ -1,0 +1,98 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects invalid arguments on the host before touching
+a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2204_14194_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_symbols():
+    text = open(os.path.join(ROOT, "include", "se.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(se_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_what_binding_lists():
+    assert _header_symbols() == sorted(B.EXPORTED)
+
+
+def test_library_exports_every_symbol():
+    L = B.lib()
+    for name in _header_symbols():
+        assert hasattr(L, name), name
+    assert B.version() == 100
+
+
+def test_no_gpu_code_in_python_fallback():
+    src = open(os.path.join(ROOT, "paper_2204_14194_amd", "binding.py")).read()
+    assert "import oracle" not in src and "from oracle" not in src
+
+
+def _tables_struct(K=64, M=8, N=8, ldG=64, fake=0x1000):
+    return B.se_tables(M, N, K, ldG, fake, fake, fake, fake, fake, 0)
+
+
+def test_rejects_bad_arguments_on_host():
+    L = B.lib()
+    t = _tables_struct()
+    blk = (B.se_block * 1)(B.se_block(0, 0, 0, 6, 6, 4, 4, 0))   # loss leaves the area
+    fake = C.c_void_p(0x1000)
+    prm = B.se_params(0.5, 10, 0)
+    r = L.se_extrapolate_batch(C.byref(t), fake, 1, 32, 32, blk, 1, prm, None, None, None, 0,
+                               fake, 1 << 20, None)
+    assert r == B.SE_EINVAL
+    assert b"loss rectangle" in L.se_last_error()
+    # gamma outside (0, 1]
+    blk[0] = B.se_block(0, 0, 0, 2, 2, 4, 4, 0)
+    r = L.se_extrapolate_batch(C.byref(t), fake, 1, 32, 32, blk, 1, B.se_params(1.5, 10, 0),
+                               None, None, None, 0, fake, 1 << 20, None)
+    assert r == B.SE_EINVAL
+    # ldG not a multiple of 4
+    t2 = _tables_struct(K=63, ldG=63)
+    r = L.se_extrapolate_batch(C.byref(t2), fake, 1, 32, 32, blk, 1, prm, None, None, None, 0,
+                               fake, 1 << 20, None)
+    assert r == B.SE_EINVAL
+    # image index out of range
+    blk[0] = B.se_block(3, 0, 0, 2, 2, 4, 4, 0)
+    r = L.se_extrapolate_batch(C.byref(t), fake, 1, 32, 32, blk, 1, prm, None, None, None, 0,
+                               fake, 1 << 20, None)
+    assert r == B.SE_EINVAL
+    # loss larger than the per-lane capacity of the loop (K <= 2048: 256 px)
+    tb = _tables_struct(K=64, M=32, N=32)
+    blk[0] = B.se_block(0, 0, 0, 0, 0, 17, 16, 0)
+    r = L.se_extrapolate_batch(C.byref(tb), fake, 1, 64, 64, blk, 1, prm, None, None, None, 0,
+                               fake, 1 << 20, None)
+    assert r == B.SE_EINVAL
+    # workspace too small
+    blk[0] = B.se_block(0, 0, 0, 2, 2, 4, 4, 0)
+    r = L.se_extrapolate_batch(C.byref(t), fake, 1, 32, 32, blk, 1, prm, None, None, None, 0,
+                               fake, 16, None)
+    assert r == B.SE_ENOMEM
+    # weights: rho_hat outside (0, 1]
+    r = L.se_area_weights(8, 8, 1.5, fake, 1, 32, 32, blk, 1, fake, fake, 1 << 20, None)
+    assert r == B.SE_EINVAL
+    # table generation: unknown precision, NULL basis
+    bas = B.se_basis(8, 8, 64, 0x1000)
+    r = L.se_weighted_gram(C.byref(bas), fake, 7, 0, C.byref(t), fake, 1 << 20, None)
+    assert r == B.SE_EINVAL
+    bas0 = B.se_basis(8, 8, 64, 0)
+    r = L.se_weighted_gram(C.byref(bas0), fake, 0, 0, C.byref(t), fake, 1 << 20, None)
+    assert r == B.SE_EINVAL
+
+
+def test_workspace_sizes_grow_with_work():
+    L = B.lib()
+    t = _tables_struct(K=2048, M=32, N=32, ldG=2048)
+    a = L.se_extrapolate_batch_ws_bytes(C.byref(t), 16)
+    b = L.se_extrapolate_batch_ws_bytes(C.byref(t), 4096)
+    assert 0 < a < b
+    assert b >= 4096 * (2048 + 1024) * 4
+    bas = B.se_basis(32, 32, 2048, 0x1000)
+    assert L.se_weighted_gram_ws_bytes(C.byref(bas), B.SE_BF16X3) > \
+        L.se_weighted_gram_ws_bytes(C.byref(bas), B.SE_FP32)

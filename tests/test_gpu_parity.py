@@ -1,0 +1,233 @@
+"""GPU parity of the HIP path against the FP64 oracle.
+
+Each test prints the case it runs before touching the GPU.  Tolerances (on
+the 0..255 scale, model g over the loss before rounding): 1e-3 for the FP32
+path; selections identical modulo classes of parallel atoms.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2204_14194_amd import binding as B
+from paper_2204_14194_amd import synth
+
+from helpers import classes_of, compare_selections, min_margin, oracle_blocks
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP32 = 1e-3
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def upload_phi(phi):
+    return torch.from_numpy(np.asarray(phi, dtype=np.float32)).to(dev())
+
+
+def shared_tables(images, blocks, phi32, M, N, rho_hat, precision=B.SE_FP32, flags=0,
+                  ref_block=0):
+    """Weights of block ``ref_block`` computed on the device, then the tables."""
+    n_img, H, W = images.shape
+    lost = np.stack([synth.lost_mask(H, W, blocks, i) for i in range(n_img)])
+    lost_d = torch.from_numpy(lost).to(dev())
+    w = B.area_weights(M, N, rho_hat, lost_d, [blocks[ref_block]])
+    t = B.weighted_gram(phi32, w[0].contiguous(), M, N, precision, flags)
+    return t, w[0], lost
+
+
+def run_batch(t, images, blocks, gamma, iters, plain=False):
+    img_d = torch.from_numpy(images).to(dev())
+    f = B.extrapolate_plain if plain else B.extrapolate_batch
+    sel, coef, g = f(t, img_d, blocks, gamma, iters)
+    torch.cuda.synchronize()
+    return (sel.cpu().numpy(), coef.cpu().numpy(), g.cpu().numpy(), img_d.cpu().numpy())
+
+
+def check_against_oracle(images, blocks, phi, M, N, rho_hat, gamma, iters, sel, coef, g, out,
+                         sample=None, tol=TOL_FP32):
+    cls = classes_of(phi)
+    idx = list(range(len(blocks))) if sample is None else list(sample)
+    ref = oracle_blocks(images, blocks, phi, M, N, rho_hat, gamma, iters, sample=idx)
+    worst, margin = 0.0, np.inf
+    for i, (res, gref) in zip(idx, ref):
+        b = blocks[i]
+        n = b.lh * b.lw
+        assert compare_selections(sel[i], res.sel, cls), f"block {i}: selections differ"
+        err = np.abs(g[i, :n].astype(np.float64) - gref).max()
+        worst = max(worst, err)
+        margin = min(margin, min_margin(res))
+        # the pasted pixels are the rounded model (round half to even), except
+        # where the oracle's value sits within the tolerance of a .5 boundary
+        q_ref = np.clip(np.rint(gref), 0, 255)
+        near = np.abs(np.abs(gref - np.floor(gref)) - 0.5) < tol
+        y, x = b.y0 + b.ly, b.x0 + b.lx
+        got = out[b.img, y:y + b.lh, x:x + b.lw].reshape(-1).astype(np.float64)
+        ok = (got == q_ref) | near
+        assert ok.all(), f"block {i}: pasted pixels differ from the rounded model"
+    assert worst <= tol, f"max |g - g_oracle| = {worst}"
+    return worst, margin
+
+
+# ---------------------------------------------------------------------------
+def test_area_weights_match_oracle():
+    say("area_weights: 3 blocks of a 40x44 image, one crossing the border")
+    H, W = 40, 44
+    blocks = [synth.Block(0, -5, 3, 7, 7, 6, 5), synth.Block(0, 10, 20, 4, 4, 8, 8),
+              synth.Block(0, 20, 30, 2, 2, 4, 4)]
+    lost = synth.lost_mask(H, W, blocks)[None]
+    w = B.area_weights(20, 18, 0.8, torch.from_numpy(lost).to(dev()), blocks).cpu().numpy()
+    for i, b in enumerate(blocks):
+        _, sup = oracle.area_signal(np.zeros((H, W), np.uint8), lost[0], b.y0, b.x0, 20, 18)
+        ref = oracle.area_weights(20, 18, 0.8, sup)
+        np.testing.assert_array_equal(w[i] == 0, ref == 0)
+        np.testing.assert_allclose(w[i], ref, rtol=2e-6, atol=0)
+
+
+@pytest.mark.parametrize("M,N,K,kind", [(32, 32, 2048, "dctwht"), (5, 7, 37, "gauss"),
+                                        (12, 12, 300, "gauss")])
+def test_gram_matches_oracle(M, N, K, kind):
+    say(f"weighted_gram M={M} N={N} K={K} {kind}")
+    if kind == "dctwht":
+        phi = synth.round_to_f32(synth.dictionary(M, N, ("dct", "wht")))
+    else:
+        phi = synth.round_to_f32(synth.gaussian_atoms(M, N, K, seed=5))
+    sup = np.ones((M, N), bool)
+    sup[M // 3:M // 3 + 2, N // 3:N // 3 + 3] = False
+    w_ref = oracle.area_weights(M, N, 0.8, sup)
+    w_d = torch.from_numpy(w_ref.astype(np.float32)).to(dev())
+    t = B.weighted_gram(upload_phi(phi), w_d, M, N)
+    torch.cuda.synchronize()
+    G = t.G.cpu().numpy()[:, :K].astype(np.float64)
+    D = t.D.cpu().numpy().astype(np.float64)
+    C_ref, D_ref = oracle.table_generation(phi, w_ref.astype(np.float32).astype(np.float64))
+    np.testing.assert_allclose(D, D_ref, rtol=2e-6)
+    G_ref = D_ref[:, None] * C_ref * D_ref[None, :]
+    assert np.abs(G - G_ref).max() < 2e-5
+    np.testing.assert_array_equal(G, G.T)                      # exactly symmetric
+    if kind == "dctwht":                                       # twins: identical rows
+        cls = classes_of(phi)
+        for k in np.nonzero(cls != np.arange(K))[0]:
+            np.testing.assert_array_equal(G[k], G[cls[k]])
+            assert D[k] == D[cls[k]]
+
+
+def test_cfg0_batch_parity():
+    d = synth.cfg0_inputs(1)
+    say("cfg0 batched: 1 image 128x128, 16 blocks, K=2048, I=100")
+    phi = synth.round_to_f32(d["phi"])
+    t, _, _ = shared_tables(d["images"], d["blocks"], upload_phi(phi), 32, 32, 0.8)
+    sel, coef, g, out = run_batch(t, d["images"], d["blocks"], 0.5, 100)
+    worst, margin = check_against_oracle(d["images"], d["blocks"], phi, 32, 32, 0.8, 0.5, 100,
+                                         sel, coef, g, out)
+    print(f"cfg0 batched: max|dg|={worst:.3g} min tie margin={margin:.3g}")
+    # the higher-indexed twin is never selected (exact ties go to the lowest k)
+    assert not set(np.unique(sel)) & {1024, 1027, 1120, 1123}
+    # nothing outside the losses changed
+    mask = np.ones_like(out, bool)
+    for b in d["blocks"]:
+        mask[b.img, b.y0 + b.ly:b.y0 + b.ly + b.lh, b.x0 + b.lx:b.x0 + b.lx + b.lw] = False
+    np.testing.assert_array_equal(out[mask], d["images"][mask])
+
+
+def test_cfg0_plain_parity_and_agreement_with_batch():
+    d = synth.cfg0_inputs(1)
+    say("cfg0 plain (per-block launches): 16 blocks, K=2048, I=100")
+    phi = synth.round_to_f32(d["phi"])
+    t, _, _ = shared_tables(d["images"], d["blocks"], upload_phi(phi), 32, 32, 0.8)
+    sel_p, coef_p, g_p, out_p = run_batch(t, d["images"], d["blocks"], 0.5, 100, plain=True)
+    check_against_oracle(d["images"], d["blocks"], phi, 32, 32, 0.8, 0.5, 100, sel_p, coef_p,
+                         g_p, out_p)
+    sel_b, coef_b, g_b, out_b = run_batch(t, d["images"], d["blocks"], 0.5, 100)
+    np.testing.assert_array_equal(sel_p, sel_b)
+    assert np.abs(g_p - g_b).max() <= TOL_FP32
+
+
+def test_cfg0_se_original_anchor():
+    """Two blocks against Algorithm 1 itself (not only its fast form)."""
+    d = synth.cfg0_inputs(1)
+    say("cfg0 vs original SE (Algorithm 1): blocks 3 and 12")
+    phi = synth.round_to_f32(d["phi"])
+    t, _, _ = shared_tables(d["images"], d["blocks"], upload_phi(phi), 32, 32, 0.8)
+    sel, coef, g, out = run_batch(t, d["images"], d["blocks"], 0.5, 100)
+    cls = classes_of(phi)
+    ref = oracle_blocks(d["images"], d["blocks"], phi, 32, 32, 0.8, 0.5, 100, method="se",
+                        sample=[3, 12])
+    for i, (res, gref) in zip([3, 12], ref):
+        assert compare_selections(sel[i], res.sel, cls)
+        assert np.abs(g[i] - gref).max() <= TOL_FP32
+        np.testing.assert_allclose(coef[i], res.coef, rtol=1e-3, atol=1e-3)
+
+
+@pytest.mark.parametrize("K,M,N,iters", [(512, 16, 16, 60), (1000, 20, 20, 60),
+                                         (3000, 24, 24, 50), (4096, 16, 16, 40),
+                                         (6000, 16, 16, 30)])
+def test_loop_variants_ragged(K, M, N, iters):
+    """Every workgroup shape of the loop (1, 2 and 4 waves), K not a multiple
+    of the tile, areas crossing the image border handled with one table set
+    per block."""
+    say(f"loop variant K={K} area {M}x{N} I={iters}")
+    rng = np.random.default_rng(K)
+    base = synth.dictionary(M, N, ("dct",))
+    phi = synth.round_to_f32(np.concatenate(
+        [base, synth.gaussian_atoms(M, N, K - base.shape[0], seed=K)]))
+    H, W = 3 * M, 3 * N
+    img = synth.synth_image(H, W, seed=K)[None]
+    lh, lw = M // 3, N // 4 + 1
+    blocks = [synth.Block(0, M, N, (M - lh) // 2, (N - lw) // 2, lh, lw),
+              synth.Block(0, 2 * M + 2, -3, (M - lh) // 2, (N - lw) // 2 + 2, lh, lw)]
+    phi_d = upload_phi(phi)
+    out = img.copy()
+    for i, b in enumerate(blocks):
+        t, _, _ = shared_tables(img, blocks, phi_d, M, N, 0.8, ref_block=i)
+        sel, coef, g, o = run_batch(t, out, [b], 0.5, iters)
+        check_against_oracle(img, [b], phi, M, N, 0.8, 0.5, iters, sel, coef, g, o)
+        out = o
+
+
+def test_degenerate_atom_and_zero_signal():
+    M = N = 12
+    say("degenerate atom (lives on the loss only) and an all-zero image")
+    phi = synth.round_to_f32(synth.dictionary(M, N, ("dct",)))
+    spike = np.zeros((1, M * N))
+    spike[0, 5 * N + 5] = 1.0
+    phi = np.concatenate([phi, spike])
+    blocks = [synth.Block(0, 0, 0, 4, 4, 4, 4)]
+    img = synth.synth_image(M, N, seed=3)[None]
+    t, _, _ = shared_tables(img, blocks, upload_phi(phi), M, N, 0.8)
+    assert t.D.cpu().numpy()[-1] == 0.0
+    sel, coef, g, out = run_batch(t, img, blocks, 0.5, 30)
+    assert M * N not in set(sel[0])
+    assert np.isfinite(g).all()
+    check_against_oracle(img, blocks, phi, M, N, 0.8, 0.5, 30, sel, coef, g, out)
+    zero = np.zeros_like(img)
+    sel0, coef0, g0, out0 = run_batch(t, zero, blocks, 0.5, 10)
+    np.testing.assert_array_equal(sel0, 0)
+    np.testing.assert_array_equal(coef0, 0.0)
+    np.testing.assert_array_equal(g0, 0.0)
+
+
+def test_cfg0_bench_scale_sampled():
+    """The launch configuration the benchmark times: 256 images x 16 blocks."""
+    d = synth.cfg0_inputs(256)
+    say("cfg0 at benchmark scale: 256 images, 4096 blocks, sampled oracle check")
+    phi = synth.round_to_f32(d["phi"])
+    t, _, _ = shared_tables(d["images"], d["blocks"], upload_phi(phi), 32, 32, 0.8)
+    sel, coef, g, out = run_batch(t, d["images"], d["blocks"], 0.5, 100)
+    sample = np.random.default_rng(0).choice(len(d["blocks"]), 24, replace=False)
+    check_against_oracle(d["images"], d["blocks"], phi, 32, 32, 0.8, 0.5, 100, sel, coef, g,
+                         out, sample=sample)
+    # every block: the pasted pixels are the rounded model
+    for i, b in enumerate(d["blocks"]):
+        y, x = b.y0 + b.ly, b.x0 + b.lx
+        q = np.clip(np.rint(g[i, :64]), 0, 255).reshape(8, 8)
+        np.testing.assert_array_equal(out[b.img, y:y + 8, x:x + 8], q)
