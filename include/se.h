@@ -86,11 +86,12 @@ typedef struct {
 
 /* Tables for one weight pattern (Algorithm 2), as written by
  * se_weighted_gram.  All pointers device, allocated by the caller:
- *   G    : K x ldG float32, ldG >= K rounded up to a multiple of 4.
- *          G[k][l] = D_k C_(k,l) D_l, the weighted Gram of eq. 16 expressed
- *          for the atoms scaled to unit weighted norm (so G[k][k] = 1 for
- *          every atom with C_kk > 0).  Exactly symmetric.  Columns >= K
- *          are never read.
+ *   G    : K x ldG float32, ldG >= se_table_ld(K), a multiple of 4,
+ *          16-byte aligned.  G[k][l] = D_k C_(k,l) D_l, the weighted Gram of
+ *          eq. 16 expressed for the atoms scaled to unit weighted norm (so
+ *          G[k][k] = 1 for every atom with C_kk > 0).  Exactly symmetric.
+ *          Columns K .. ldG-1 are written as 0 (the loop streams padded
+ *          rows).
  *   D    : K float32, D_k = 1/sqrt(C_(k,k)) (eq. 17); 0 for an atom whose
  *          weighted norm is 0 (it can never be selected).
  *   Y    : K x (M*N) float32, Y[k][p] = D_k sqrt(w[p]) phi_k[p]; the
@@ -126,6 +127,11 @@ typedef struct {
 const char* se_last_error(void);
 /* Library version as 10000*major + 100*minor + patch. */
 int32_t se_version(void);
+/* Minimum row stride (in floats) of the table G and of projection buffers
+ * for a dictionary of K atoms: K rounded up to the padded row length of the
+ * iteration loop's workgroup shape (64 * waves * values per lane).  0 if K
+ * is below 1 or above 32768, the largest supported dictionary. */
+int32_t se_table_ld(int32_t K);
 
 /* ------------------------------------------------------------------------ */
 /* Weighting function: eq. 4 and eq. 5                                      */
@@ -185,10 +191,11 @@ se_status se_weighted_gram(const se_basis* b, const float* w,
  *   images  : device uint8, n_img images H x W (row pitch W, image stride
  *             H*W); read on the support, written on each loss (in place)
  *   blocks  : host, n_blk descriptors; every loss rectangle must lie inside
- *             its area and hold at most 4*64*waves pixels (waves = the
- *             workgroup size the library picks for K: 1 for K <= 2048,
- *             2 for K <= 4096, 4 for K <= 8192, 8 for K <= 16384; so >= 256
- *             pixels always); losses of different blocks must not overlap
+ *             its area and hold at most 256*waves pixels (waves = the
+ *             workgroup size of the loop for K: 1 for K <= 2048, 2 for
+ *             K <= 4096, 4 for K <= 8192, 8 for K <= 16384, 16 above; so 256
+ *             pixels are always accepted); losses of different blocks must
+ *             not overlap
  *   sel     : optional device int32 n_blk x iters, selected atom per
  *             iteration (NULL to skip)
  *   coef    : optional device float32 n_blk x iters, coefficient c per
@@ -205,6 +212,39 @@ se_status se_extrapolate_batch(const se_tables* t, uint8_t* images,
                                se_params prm, int32_t* sel, float* coef,
                                float* g_loss, int32_t g_loss_ld, void* ws,
                                size_t ws_bytes, void* stream);
+
+/* The two stages of se_extrapolate_batch, for callers that keep block
+ * descriptors on the device (graph capture, serving) or time the stages.
+ *
+ * se_blocks_upload: validates n_blk host descriptors exactly as
+ *   se_extrapolate_batch does and copies them to dev_blocks (device, n_blk
+ *   se_block, caller-owned) on `stream`; *max_loss (host, may be NULL)
+ *   receives the largest loss size in pixels.  The other two calls accept
+ *   only descriptors that went through this validation.
+ * se_project: the initial weighted scalar products of eq. 12 for every
+ *   block, R[b][k] = D_k R_k^(0) (device float32, n_blk rows of stride ldR,
+ *   a multiple of 4, 16-byte aligned), as one matrix product on
+ *   the matrix cores; columns K .. ldR-1 are written as 0.  ldR >=
+ *   se_table_ld(K).  ws: se_project_ws_bytes(t, n_blk) bytes.
+ * se_iterate: the iteration loop (eq. 18, 19, 9, 20) from R and the
+ *   replacement of every loss in `images`; R is read only.  Outputs as for
+ *   se_extrapolate_batch; g_loss rows hold g_loss_ld values (a longer loss
+ *   is truncated in g_loss, never in the image).
+ * se_extrapolate_batch(...) == se_blocks_upload + se_project + se_iterate. */
+se_status se_blocks_upload(const se_tables* t, int32_t n_img, int32_t H,
+                           int32_t W, const se_block* blocks, int32_t n_blk,
+                           se_block* dev_blocks, int32_t* max_loss,
+                           void* stream);
+size_t se_project_ws_bytes(const se_tables* t, int32_t n_blk);
+se_status se_project(const se_tables* t, const uint8_t* images, int32_t n_img,
+                     int32_t H, int32_t W, const se_block* dev_blocks,
+                     int32_t n_blk, float* R, int32_t ldR, void* ws,
+                     size_t ws_bytes, void* stream);
+se_status se_iterate(const se_tables* t, const float* R, int32_t ldR,
+                     uint8_t* images, int32_t n_img, int32_t H, int32_t W,
+                     const se_block* dev_blocks, int32_t n_blk, se_params prm,
+                     int32_t* sel, float* coef, float* g_loss,
+                     int32_t g_loss_ld, void* stream);
 
 /* Same contract and results as se_extrapolate_batch, executed one block at
  * a time: per block one gather launch, one matrix-vector launch for R^(0)

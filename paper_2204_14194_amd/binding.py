@@ -25,7 +25,8 @@ SE_DIAG_AUTO, SE_DIAG_FP64, SE_DIAG_FP32 = 0, 1, 2
 EXPORTED = (
     "se_last_error", "se_version", "se_area_weights_ws_bytes", "se_area_weights",
     "se_weighted_gram_ws_bytes", "se_weighted_gram", "se_extrapolate_batch_ws_bytes",
-    "se_extrapolate_batch", "se_extrapolate_plain",
+    "se_extrapolate_batch", "se_extrapolate_plain", "se_blocks_upload", "se_project_ws_bytes",
+    "se_project", "se_iterate", "se_table_ld",
 )
 
 
@@ -69,6 +70,8 @@ def lib():
     vp, i32, f32, sz = C.c_void_p, C.c_int32, C.c_float, C.c_size_t
     L.se_last_error.restype = C.c_char_p
     L.se_version.restype = i32
+    L.se_table_ld.restype = i32
+    L.se_table_ld.argtypes = [i32]
     L.se_area_weights_ws_bytes.restype = sz
     L.se_area_weights_ws_bytes.argtypes = [i32]
     L.se_area_weights.restype = i32
@@ -85,6 +88,17 @@ def lib():
         f.restype = i32
         f.argtypes = [C.POINTER(se_tables), vp, i32, i32, i32, vp, i32, se_params, vp, vp, vp,
                       i32, vp, sz, vp]
+    L.se_blocks_upload.restype = i32
+    L.se_blocks_upload.argtypes = [C.POINTER(se_tables), i32, i32, i32, vp, i32, vp,
+                                   C.POINTER(C.c_int32), vp]
+    L.se_project_ws_bytes.restype = sz
+    L.se_project_ws_bytes.argtypes = [C.POINTER(se_tables), i32]
+    L.se_project.restype = i32
+    L.se_project.argtypes = [C.POINTER(se_tables), vp, i32, i32, i32, vp, i32, vp, i32, vp, sz,
+                             vp]
+    L.se_iterate.restype = i32
+    L.se_iterate.argtypes = [C.POINTER(se_tables), vp, i32, vp, i32, i32, i32, vp, i32,
+                             se_params, vp, vp, vp, i32, vp]
     _lib = L
     return L
 
@@ -124,6 +138,14 @@ def blocks_array(blocks: Sequence) -> C.Array:
 
 def version() -> int:
     return int(lib().se_version())
+
+
+def table_ld(K: int) -> int:
+    """se_table_ld: row stride of the table and of projection buffers."""
+    ld = int(lib().se_table_ld(int(K)))
+    if ld <= 0:
+        raise ValueError(f"unsupported dictionary size K={K}")
+    return ld
 
 
 # ---------------------------------------------------------------------------
@@ -178,7 +200,7 @@ def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
     K = phi.shape[0]
     if phi.shape[1] != M * N or w.numel() != M * N:
         raise ValueError("phi must be (K, M*N) and w (M*N,)")
-    ldG = (K + 3) // 4 * 4
+    ldG = table_ld(K)
     dev = phi.device
     t = Tables(M, N, K, ldG,
                torch.empty((K, ldG), dtype=torch.float32, device=dev),
@@ -243,3 +265,48 @@ def extrapolate_plain(t: Tables, images: torch.Tensor, blocks: Sequence, gamma: 
     """se_extrapolate_plain: same results, one block at a time."""
     return _extrapolate("se_extrapolate_plain", t, images, blocks, gamma, iters, want_sel,
                         want_coef, want_g, ws, stream, blocks_arr)
+
+
+# ---------------------------------------------------------------------------
+# stage calls
+# ---------------------------------------------------------------------------
+class DeviceBlocks:
+    """Validated block descriptors resident on the device (se_blocks_upload)."""
+
+    def __init__(self, t: Tables, images: torch.Tensor, blocks: Sequence, stream=None):
+        L = lib()
+        n_img, H, W = images.shape
+        self.n = len(blocks)
+        self.buf = torch.empty((max(self.n, 1), 8), dtype=torch.int32, device=images.device)
+        mx = C.c_int32(0)
+        st = t.struct()
+        _check(L.se_blocks_upload(C.byref(st), n_img, H, W, blocks_array(blocks), self.n,
+                                  _ptr(self.buf), C.byref(mx), _stream(stream)))
+        self.max_loss = int(mx.value)
+
+
+def project(t: Tables, images: torch.Tensor, dblocks: DeviceBlocks, R: torch.Tensor,
+            ws: torch.Tensor, stream=None):
+    """se_project: R[b, k] = D_k R_k^(0) for every block (eq. 12)."""
+    L = lib()
+    n_img, H, W = images.shape
+    st = t.struct()
+    _check(L.se_project(C.byref(st), _ptr(images), n_img, H, W, _ptr(dblocks.buf), dblocks.n,
+                        _ptr(R), R.shape[1], _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def project_ws_bytes(t: Tables, n_blk: int) -> int:
+    st = t.struct()
+    return int(lib().se_project_ws_bytes(C.byref(st), n_blk))
+
+
+def iterate(t: Tables, R: torch.Tensor, images: torch.Tensor, dblocks: DeviceBlocks,
+            gamma: float, iters: int, sel=None, coef=None, g_loss=None, stream=None):
+    """se_iterate: the iteration loop and the paste, from R."""
+    L = lib()
+    n_img, H, W = images.shape
+    st = t.struct()
+    gld = g_loss.shape[1] if g_loss is not None else 0
+    _check(L.se_iterate(C.byref(st), _ptr(R), R.shape[1], _ptr(images), n_img, H, W,
+                        _ptr(dblocks.buf), dblocks.n, se_params(float(gamma), int(iters), 0),
+                        _ptr(sel), _ptr(coef), _ptr(g_loss), gld, _stream(stream)))

@@ -61,10 +61,12 @@ static se_status check_tables(const se_tables* t) {
   if (!t) return fail(SE_EINVAL, "tables is NULL");
   if (t->M < 1 || t->N < 1 || t->K < 1) return fail(SE_EINVAL, "bad table shape M=%d N=%d K=%d", t->M, t->N, t->K);
   if ((long long)t->M * t->N > (1 << 24)) return fail(SE_EINVAL, "area too large");
-  if (t->ldG < t->K || (t->ldG & 3)) return fail(SE_EINVAL, "ldG=%d must be >= K=%d and a multiple of 4", t->ldG, t->K);
+  if (greedy_waves_for(t->K) == 0) return fail(SE_EINVAL, "K=%d exceeds %d", t->K, 32768);
+  if (t->ldG < greedy_row_len(t->K) || (t->ldG & 3))
+    return fail(SE_EINVAL, "ldG=%d must be >= se_table_ld(K)=%d and a multiple of 4", t->ldG,
+                greedy_row_len(t->K));
   if (!t->G || !t->D || !t->Y || !t->sqrtw || !t->phi) return fail(SE_EINVAL, "a table pointer is NULL");
   if (reinterpret_cast<uintptr_t>(t->G) % 16) return fail(SE_EINVAL, "G must be 16-byte aligned");
-  if (greedy_waves_for(t->K) == 0) return fail(SE_EINVAL, "K=%d exceeds 16384", t->K);
   return SE_OK;
 }
 
@@ -95,6 +97,7 @@ extern "C" {
 
 const char* se_last_error(void) { return g_err; }
 int32_t se_version(void) { return 100; }
+int32_t se_table_ld(int32_t K) { return K >= 1 && greedy_waves_for(K) ? greedy_row_len(K) : 0; }
 
 // ---------------------------------------------------------------------------
 size_t se_area_weights_ws_bytes(int32_t n_blk) {
@@ -165,6 +168,8 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
   if ((st = check_launch("finalize_d"))) return st;
   launch_scale_y(b->phi, t->D, t->sqrtw, K, P, t->Y, s);
   if ((st = check_launch("scale_y"))) return st;
+  launch_zero_cols(t->G, K, K, t->ldG, s);
+  if ((st = check_launch("zero_cols"))) return st;
   if (prec == SE_FP32) {
     return gemm_nt_f32(t->Y, P, t->Y, P, t->G, t->ldG, K, K, K, P, true, 0, s);
   }
@@ -176,13 +181,114 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
 }
 
 // ---------------------------------------------------------------------------
+se_status se_blocks_upload(const se_tables* t, int32_t n_img, int32_t H, int32_t W,
+                           const se_block* blocks, int32_t n_blk, se_block* dev_blocks,
+                           int32_t* max_loss, void* stream) {
+  g_err[0] = 0;
+  se_status st = check_tables(t);
+  if (st) return st;
+  if ((st = check_blocks(t, n_img, H, W, blocks, n_blk, 0, nullptr))) return st;
+  int mx = 0;
+  for (int i = 0; i < n_blk; ++i) mx = blocks[i].lh * blocks[i].lw > mx ? blocks[i].lh * blocks[i].lw : mx;
+  if (max_loss) *max_loss = mx;
+  if (n_blk == 0) return SE_OK;
+  if (!dev_blocks) return fail(SE_EINVAL, "dev_blocks is NULL");
+  return upload_blocks(blocks, n_blk, dev_blocks, static_cast<hipStream_t>(stream));
+}
+
+size_t se_project_ws_bytes(const se_tables* t, int32_t n_blk) {
+  if (!t || t->K < 1 || t->M < 1 || t->N < 1 || n_blk < 0) return 0;
+  return align_up((size_t)n_blk * round4(t->M * t->N) * sizeof(float), 256) + 256;
+}
+
+static se_status check_common(const se_tables* t, int n_img, int H, int W, int n_blk,
+                              const void* images, const void* dev_blocks) {
+  se_status st = check_tables(t);
+  if (st) return st;
+  if (n_img < 1 || H < 1 || W < 1) return fail(SE_EINVAL, "bad image batch %d x %d x %d", n_img, H, W);
+  if (n_blk < 0) return fail(SE_EINVAL, "n_blk < 0");
+  if (n_blk > 0 && (!images || !dev_blocks)) return fail(SE_EINVAL, "NULL pointer");
+  return SE_OK;
+}
+
+se_status se_project(const se_tables* t, const uint8_t* images, int32_t n_img, int32_t H, int32_t W,
+                     const se_block* dev_blocks, int32_t n_blk, float* R, int32_t ldR, void* ws,
+                     size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  se_status st = check_common(t, n_img, H, W, n_blk, images, dev_blocks);
+  if (st) return st;
+  if (n_blk == 0) return SE_OK;
+  if (!R || ldR < greedy_row_len(t->K) || (ldR & 3) || reinterpret_cast<uintptr_t>(R) % 16)
+    return fail(SE_EINVAL, "R must be 16-byte aligned with ldR >= se_table_ld(K)=%d, a multiple of 4",
+                greedy_row_len(t->K));
+  if (!ws || ws_bytes < se_project_ws_bytes(t, n_blk)) return fail(SE_ENOMEM, "workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int P = t->M * t->N, ldX = round4(P);
+  Carver cv(ws);
+  float* X = cv.take<float>((size_t)n_blk * ldX);
+  launch_gather(images, H, W, dev_blocks, n_blk, t->M, t->N, t->sqrtw, X, ldX, s);
+  if ((st = check_launch("gather"))) return st;
+  return gemm_nt_f32(X, ldX, t->Y, P, R, ldR, n_blk, t->K, ldR, P, false, 0, s);
+}
+
+static GreedyArgs greedy_args(const se_tables* t, const float* R, int ldR, uint8_t* images, int H,
+                              int W, const se_block* dev_blocks, int n_blk, se_params prm,
+                              int32_t* sel, float* coef, float* g_loss, int g_loss_ld) {
+  GreedyArgs ga;
+  ga.R0 = R;
+  ga.ldR = ldR;
+  ga.G = t->G;
+  ga.ldG = t->ldG;
+  ga.D = t->D;
+  ga.phi = t->phi;
+  ga.K = t->K;
+  ga.M = t->M;
+  ga.N = t->N;
+  ga.blk = dev_blocks;
+  ga.n_blk = n_blk;
+  ga.blk0 = 0;
+  ga.images = images;
+  ga.H = H;
+  ga.W = W;
+  ga.gamma = prm.gamma;
+  ga.iters = prm.iters;
+  ga.sel = sel;
+  ga.coef = coef;
+  ga.g_loss = g_loss;
+  ga.g_loss_ld = g_loss ? g_loss_ld : 0;
+  return ga;
+}
+
+static se_status check_params(se_params prm, const float* g_loss, int g_loss_ld) {
+  if (!(prm.gamma > 0.0f && prm.gamma <= 1.0f)) return fail(SE_EINVAL, "gamma must lie in (0, 1]");
+  if (prm.iters < 0) return fail(SE_EINVAL, "iters < 0");
+  if (prm.flags != 0) return fail(SE_EINVAL, "unknown flags 0x%x", prm.flags);
+  if (g_loss && g_loss_ld < 1) return fail(SE_EINVAL, "g_loss_ld < 1");
+  return SE_OK;
+}
+
+se_status se_iterate(const se_tables* t, const float* R, int32_t ldR, uint8_t* images, int32_t n_img,
+                     int32_t H, int32_t W, const se_block* dev_blocks, int32_t n_blk, se_params prm,
+                     int32_t* sel, float* coef, float* g_loss, int32_t g_loss_ld, void* stream) {
+  g_err[0] = 0;
+  se_status st = check_common(t, n_img, H, W, n_blk, images, dev_blocks);
+  if (st) return st;
+  if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
+  if (n_blk == 0) return SE_OK;
+  if (!R || ldR < greedy_row_len(t->K) || (ldR & 3) || reinterpret_cast<uintptr_t>(R) % 16)
+    return fail(SE_EINVAL, "R must be 16-byte aligned with ldR >= se_table_ld(K)=%d, a multiple of 4",
+                greedy_row_len(t->K));
+  GreedyArgs ga = greedy_args(t, R, ldR, images, H, W, dev_blocks, n_blk, prm, sel, coef, g_loss,
+                              g_loss_ld);
+  return launch_greedy(ga, n_blk, static_cast<hipStream_t>(stream));
+}
+
 size_t se_extrapolate_batch_ws_bytes(const se_tables* t, int32_t n_blk) {
   if (!t || t->K < 1 || t->M < 1 || t->N < 1 || n_blk < 0) return 0;
   Carver cv(nullptr);
-  const size_t P = (size_t)t->M * t->N;
-  cv.take<DevBlock>((size_t)n_blk);
-  cv.take<float>((size_t)n_blk * round4((int)P));
-  cv.take<float>((size_t)n_blk * round4(t->K));
+  cv.take<se_block>((size_t)n_blk);
+  cv.take<float>((size_t)n_blk * round4(t->M * t->N));
+  cv.take<float>((size_t)n_blk * greedy_row_len(t->K));
   return cv.off + 256;
 }
 
@@ -194,52 +300,27 @@ static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, in
   se_status st = check_tables(t);
   if (st) return st;
   if (!images) return fail(SE_EINVAL, "images is NULL");
-  if (!(prm.gamma > 0.0f && prm.gamma <= 1.0f)) return fail(SE_EINVAL, "gamma must lie in (0, 1]");
-  if (prm.iters < 0) return fail(SE_EINVAL, "iters < 0");
-  if (prm.flags != 0) return fail(SE_EINVAL, "unknown flags 0x%x", prm.flags);
+  if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
   if ((st = check_blocks(t, n_img, H, W, blocks, n_blk, g_loss_ld, g_loss))) return st;
   if (n_blk == 0) return SE_OK;
-  // the plain form uploads every descriptor but needs only one X/R row
-  const int nws = plain ? 1 : n_blk;
-  Carver cv(ws);
-  const int P = t->M * t->N, ldX = round4(P), ldR = round4(t->K);
-  DevBlock* dblk = cv.take<DevBlock>((size_t)n_blk);
-  float* X = cv.take<float>((size_t)nws * ldX);
-  float* R = cv.take<float>((size_t)nws * ldR);
-  if (!ws || cv.off + 256 > ws_bytes)
-    return fail(SE_ENOMEM, "workspace too small: need %zu bytes", cv.off + 256);
+  const size_t need = se_extrapolate_batch_ws_bytes(t, n_blk);
+  if (!ws || ws_bytes < need) return fail(SE_ENOMEM, "workspace too small: need %zu bytes", need);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const int P = t->M * t->N, ldX = round4(P), ldR = greedy_row_len(t->K);
+  Carver cv(ws);
+  se_block* dblk = cv.take<se_block>((size_t)n_blk);
+  float* X = cv.take<float>((size_t)n_blk * ldX);
+  float* R = cv.take<float>((size_t)n_blk * ldR);
   if ((st = upload_blocks(blocks, n_blk, dblk, s))) return st;
-
-  GreedyArgs ga;
-  ga.R0 = R;
-  ga.ldR = ldR;
-  ga.G = t->G;
-  ga.ldG = t->ldG;
-  ga.D = t->D;
-  ga.phi = t->phi;
-  ga.K = t->K;
-  ga.M = t->M;
-  ga.N = t->N;
-  ga.blk = dblk;
-  ga.n_blk = n_blk;
-  ga.blk0 = 0;
-  ga.images = images;
-  ga.H = H;
-  ga.W = W;
-  ga.gamma = prm.gamma;
-  ga.iters = prm.iters;
-  ga.sel = sel;
-  ga.coef = coef;
-  ga.g_loss = g_loss;
-  ga.g_loss_ld = g_loss_ld;
-
+  GreedyArgs ga = greedy_args(t, R, ldR, images, H, W, dblk, n_blk, prm, sel, coef, g_loss,
+                              g_loss_ld);
   if (!plain) {
     launch_gather(images, H, W, dblk, n_blk, t->M, t->N, t->sqrtw, X, ldX, s);
     if ((st = check_launch("gather"))) return st;
     if ((st = gemm_nt_f32(X, ldX, t->Y, P, R, ldR, n_blk, t->K, ldR, P, false, 0, s))) return st;
     return launch_greedy(ga, n_blk, s);
   }
+  // one block at a time: gather, matrix-vector product, single-workgroup loop
   for (int i = 0; i < n_blk; ++i) {
     launch_gather(images, H, W, dblk + i, 1, t->M, t->N, t->sqrtw, X, ldX, s);
     if ((st = check_launch("gather"))) return st;

@@ -115,6 +115,21 @@ __global__ void k_split_bf16(const float* __restrict__ x, size_t n, uint16_t* __
   lo[i] = f32_to_bf16_rne(v - bf16_to_f32(h));
 }
 
+__global__ void k_zero_cols(float* __restrict__ A, int rows, int c0, int ld) {
+  const int w = ld - c0;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)rows * w) return;
+  const int r = (int)(i / w);
+  A[(size_t)r * ld + c0 + (int)(i - (long long)r * w)] = 0.0f;
+}
+
+void launch_zero_cols(float* A, int rows, int c0, int ld, hipStream_t s) {
+  const long long total = (long long)rows * (ld - c0);
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_zero_cols, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, A, rows,
+                     c0, ld);
+}
+
 void launch_diag(const float* phi, const float* w, int K, int P, float* diag32, double* diag64,
                  hipStream_t s) {
   hipLaunchKernelGGL(k_diag, dim3((K + 3) / 4), dim3(256), 0, s, phi, w, K, P, diag32, diag64);

@@ -14,21 +14,61 @@
 //
 // Atom ownership: lane t of the workgroup (T = 64 * WAVES lanes) holds atoms
 // 4 (j T + t) + e, j < VPL/4, e < 4, so every row load is a coalesced float4
-// sweep and a lane's atoms increase with (j, e).  Ties: the scan keeps the
-// first maximum of a lane, the cross-lane reduction prefers the lower index,
-// so exact ties go to the lowest atom index.
+// sweep.  Rows of G and of R are padded with zeros to T * VPL columns (the
+// table row stride), so no load needs a bounds check; padded atoms hold 0
+// and are never candidates.
+//
+// Selection: a lane scans its atoms in increasing index order keeping the
+// first strict maximum of |R~| (the position is tracked as a compile-time
+// code), then the wave reduces 64-bit keys
+//     |R~| bits << 32  |  (0xFFFF - k) << 16  |  sign << 15
+// with DPP lane permutations; the maximum key is the largest |R~| and, among
+// exact ties, the lowest index k.  Workgroups of several waves combine the
+// wave winners through LDS.
 #include "se_internal.h"
 
 namespace sefase {
 
 constexpr int kQPL = 4;   // loss pixels per lane (the loss may hold <= 4 T pixels)
 
-__device__ inline void better(float& bv, int& bi, float ov, int oi) {
-  const float a = fabsf(ov), c = fabsf(bv);
-  if (a > c || (a == c && oi < bi)) {
-    bv = ov;
-    bi = oi;
+// DPP controls (gfx9 encoding)
+constexpr int kQuadXor1 = 0xB1;       // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;       // quad_perm [2,3,0,1]
+constexpr int kRowHalfMirror = 0x141;
+constexpr int kRowMirror = 0x140;
+constexpr int kRowBcast15 = 0x142;
+constexpr int kRowBcast31 = 0x143;
+
+template <int CTRL, int ROWMASK>
+__device__ inline void key_step(uint32_t& hi, uint32_t& lo) {
+  const uint32_t ohi = (uint32_t)__builtin_amdgcn_update_dpp((int)hi, (int)hi, CTRL, ROWMASK, 0xF, false);
+  const uint32_t olo = (uint32_t)__builtin_amdgcn_update_dpp((int)lo, (int)lo, CTRL, ROWMASK, 0xF, false);
+  const uint64_t a = ((uint64_t)ohi << 32) | olo;
+  const uint64_t b = ((uint64_t)hi << 32) | lo;
+  if (a > b) {
+    hi = ohi;
+    lo = olo;
   }
+}
+
+// Maximum 64-bit key over the wave, returned wave-uniform.
+__device__ inline uint64_t wave_max_key(uint32_t hi, uint32_t lo) {
+  key_step<kQuadXor1, 0xF>(hi, lo);
+  key_step<kQuadXor2, 0xF>(hi, lo);
+  key_step<kRowHalfMirror, 0xF>(hi, lo);
+  key_step<kRowMirror, 0xF>(hi, lo);          // every row of 16 lanes now uniform
+  key_step<kRowBcast15, 0xA>(hi, lo);         // rows 1, 3 take rows 0, 2
+  key_step<kRowBcast31, 0xC>(hi, lo);         // rows 2, 3 take row 1 -> lane 63 holds the max
+  const uint32_t h = (uint32_t)__builtin_amdgcn_readlane((int)hi, 63);
+  const uint32_t l = (uint32_t)__builtin_amdgcn_readlane((int)lo, 63);
+  return ((uint64_t)h << 32) | l;
+}
+
+__device__ inline uint64_t make_key(float v, int idx) {
+  const uint32_t bits = __float_as_uint(v);
+  const uint32_t hi = bits & 0x7FFFFFFFu;
+  const uint32_t lo = ((uint32_t)(0xFFFF - idx) << 16) | ((bits >> 31) << 15);
+  return ((uint64_t)hi << 32) | lo;
 }
 
 template <int WAVES, int VPL>
@@ -41,78 +81,68 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy(GreedyArgs a) {
   const DevBlock d = a.blk[b];
   const int K = a.K, P = a.M * a.N;
 
-  // ---- load R~^(0) --------------------------------------------------------
+  // ---- load R~^(0) (rows padded with zeros to T * VPL) -------------------
   float R[NJ][4];
   {
     const float* src = a.R0 + (size_t)blockIdx.x * a.ldR;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      const int idx = 4 * (j * T + t);
-      if (idx + 3 < K) {
-        const float4 v = *reinterpret_cast<const float4*>(src + idx);
-        R[j][0] = v.x; R[j][1] = v.y; R[j][2] = v.z; R[j][3] = v.w;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) R[j][e] = (idx + e < K) ? src[idx + e] : 0.0f;
-      }
+      const float4 v = *reinterpret_cast<const float4*>(src + 4 * (j * T + t));
+      R[j][0] = v.x; R[j][1] = v.y; R[j][2] = v.z; R[j][3] = v.w;
     }
   }
 
   // ---- loss pixels owned by this lane ----------------------------------
+  // Lanes past the end of the loss repeat its last pixel (a valid address);
+  // their sums are never written.
   const int nloss = d.lh * d.lw;
+  const int nq = (nloss + T - 1) / T;          // uniform
   int poff[kQPL];
   float g[kQPL];
 #pragma unroll
   for (int q = 0; q < kQPL; ++q) {
-    const int i = t + q * T;
+    int i = t + q * T;
+    i = i < nloss ? i : nloss - 1;
+    const int my = i / d.lw, mx = i - my * d.lw;
+    poff[q] = (d.ly + my) * a.N + d.lx + mx;
     g[q] = 0.0f;
-    poff[q] = -1;
-    if (i < nloss) {
-      const int my = i / d.lw, mx = i - my * d.lw;
-      poff[q] = (d.ly + my) * a.N + d.lx + mx;
-    }
   }
 
-  __shared__ float s_val[2][WAVES];
-  __shared__ int s_idx[2][WAVES];
+  __shared__ uint64_t s_key[2][WAVES];
   int par = 0;
-
-  // local candidate of the initial state
-  float bv = 0.0f;
-  int bi = 0x7fffffff;
-#pragma unroll
-  for (int j = 0; j < NJ; ++j)
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (fabsf(R[j][e]) > fabsf(bv)) {
-        bv = R[j][e];
-        bi = 4 * (j * T + t) + e;
-      }
-
   const float gamma = a.gamma;
+
   for (int it = 0; it < a.iters; ++it) {
-    // ---- argmax over the workgroup --------------------------------------
+    // ---- local candidate: first strict maximum of |R~| ------------------
+    float bv = 0.0f;
+    int code = 0;
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const float ov = __shfl_xor(bv, off);
-      const int oi = __shfl_xor(bi, off);
-      better(bv, bi, ov, oi);
-    }
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (fabsf(R[j][e]) > fabsf(bv)) {
+          bv = R[j][e];
+          code = 4 * j + e;
+        }
+    const int idx = 4 * ((code >> 2) * T + t) + (code & 3);
+    const uint64_t mine = make_key(bv, idx);
+    uint64_t key = wave_max_key((uint32_t)(mine >> 32), (uint32_t)mine);
     if (WAVES > 1) {
-      if (lane == 0) {
-        s_val[par][wave] = bv;
-        s_idx[par][wave] = bi;
-      }
+      if (lane == 0) s_key[par][wave] = key;
       __syncthreads();
-      bv = s_val[par][0];
-      bi = s_idx[par][0];
+      key = s_key[par][0];
 #pragma unroll
-      for (int w = 1; w < WAVES; ++w) better(bv, bi, s_val[par][w], s_idx[par][w]);
+      for (int w = 1; w < WAVES; ++w) {
+        const uint64_t o = s_key[par][w];
+        key = o > key ? o : key;
+      }
       par ^= 1;
     }
-    int u = bi;
-    float rv = bv;
-    if (u == 0x7fffffff) {   // every score is zero: a no-op iteration on atom 0
+    // ---- decode the winner (wave-uniform) -------------------------------
+    const uint32_t khi = (uint32_t)(key >> 32), klo = (uint32_t)key;
+    int u = 0xFFFF - (int)(klo >> 16);
+    float rv = __uint_as_float(khi | ((klo & 0x8000u) << 16));
+    if (khi == 0u || u < 0 || u >= K) {   // every score is zero: no-op on atom 0
       u = 0;
       rv = 0.0f;
     }
@@ -125,36 +155,22 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy(GreedyArgs a) {
 
     // ---- stream row u of the table and the atom over the loss -------------
     const float* grow = a.G + (size_t)u * a.ldG;
-    float row[NJ][4];
+    float4 row[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int idx = 4 * (j * T + t);
-      if (idx + 3 < K) {
-        const float4 v = *reinterpret_cast<const float4*>(grow + idx);
-        row[j][0] = v.x; row[j][1] = v.y; row[j][2] = v.z; row[j][3] = v.w;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) row[j][e] = (idx + e < K) ? grow[idx + e] : 0.0f;
-      }
-    }
+    for (int j = 0; j < NJ; ++j) row[j] = *reinterpret_cast<const float4*>(grow + 4 * (j * T + t));
     const float* prow = a.phi + (size_t)u * P;
 #pragma unroll
     for (int q = 0; q < kQPL; ++q)
-      if (poff[q] >= 0) g[q] = fmaf(c, prow[poff[q]], g[q]);   // eq. 9
+      if (q < nq) g[q] = fmaf(c, prow[poff[q]], g[q]);   // eq. 9
 
-    // ---- eq. 20 and the next local candidate -----------------------------
-    bv = 0.0f;
-    bi = 0x7fffffff;
+    // ---- eq. 20 ---------------------------------------------------------
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        R[j][e] = fmaf(-tc, row[j][e], R[j][e]);
-        if (fabsf(R[j][e]) > fabsf(bv)) {
-          bv = R[j][e];
-          bi = 4 * (j * T + t) + e;
-        }
-      }
+    for (int j = 0; j < NJ; ++j) {
+      R[j][0] = fmaf(-tc, row[j].x, R[j][0]);
+      R[j][1] = fmaf(-tc, row[j].y, R[j][1]);
+      R[j][2] = fmaf(-tc, row[j].z, R[j][2]);
+      R[j][3] = fmaf(-tc, row[j].w, R[j][3]);
+    }
   }
 
   // ---- replace the loss area by the model ----------------------------------
@@ -162,7 +178,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy(GreedyArgs a) {
   for (int q = 0; q < kQPL; ++q) {
     const int i = t + q * T;
     if (i >= nloss) continue;
-    if (a.g_loss) a.g_loss[(size_t)b * a.g_loss_ld + i] = g[q];
+    if (a.g_loss && i < a.g_loss_ld) a.g_loss[(size_t)b * a.g_loss_ld + i] = g[q];
     const int my = i / d.lw, mx = i - my * d.lw;
     const int y = d.y0 + d.ly + my, x = d.x0 + d.lx + mx;
     if (y >= 0 && y < a.H && x >= 0 && x < a.W) {
@@ -172,31 +188,64 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy(GreedyArgs a) {
   }
 }
 
-int greedy_waves_for(int K) {
-  if (K <= 2048) return 1;
-  if (K <= 4096) return 2;
-  if (K <= 8192) return 4;
-  if (K <= 16384) return 8;
-  return 0;
+// Workgroup shapes: (waves, values per lane).  The capacity 64 * waves * vpl
+// is the padded row length.
+struct LoopShape {
+  int waves, vpl;
+};
+static const LoopShape kShapes[] = {
+    {1, 8}, {1, 16}, {1, 24}, {1, 32}, {2, 24}, {2, 32}, {4, 24}, {4, 32},
+    {8, 24}, {8, 32}, {16, 24}, {16, 32},
+};
+
+static LoopShape shape_for(int K) {
+  LoopShape best{0, 0};
+  long long cap_best = 1LL << 40;
+  for (const LoopShape& s : kShapes) {
+    const long long cap = 64LL * s.waves * s.vpl;
+    if (cap >= K && (cap < cap_best || (cap == cap_best && s.waves < best.waves))) {
+      best = s;
+      cap_best = cap;
+    }
+  }
+  return best;
+}
+
+int greedy_waves_for(int K) { return shape_for(K).waves; }
+
+int greedy_row_len(int K) {
+  const LoopShape s = shape_for(K);
+  return 64 * s.waves * s.vpl;
+}
+
+template <int W, int V>
+static void launch_shape(const GreedyArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_greedy<W, V>), dim3(grid), dim3(64 * W), 0, s, a);
 }
 
 se_status launch_greedy(const GreedyArgs& a, int grid, hipStream_t s) {
   if (grid <= 0) return SE_OK;
-  const int K = a.K;
-  if (K <= 512)
-    hipLaunchKernelGGL((k_greedy<1, 8>), dim3(grid), dim3(64), 0, s, a);
-  else if (K <= 1024)
-    hipLaunchKernelGGL((k_greedy<1, 16>), dim3(grid), dim3(64), 0, s, a);
-  else if (K <= 2048)
-    hipLaunchKernelGGL((k_greedy<1, 32>), dim3(grid), dim3(64), 0, s, a);
-  else if (K <= 4096)
-    hipLaunchKernelGGL((k_greedy<2, 32>), dim3(grid), dim3(128), 0, s, a);
-  else if (K <= 8192)
-    hipLaunchKernelGGL((k_greedy<4, 32>), dim3(grid), dim3(256), 0, s, a);
-  else if (K <= 16384)
-    hipLaunchKernelGGL((k_greedy<8, 32>), dim3(grid), dim3(512), 0, s, a);
-  else
-    return fail(SE_EINVAL, "K=%d exceeds the largest loop configuration (16384)", K);
+  const LoopShape sh = shape_for(a.K);
+  const int cap = 64 * sh.waves * sh.vpl;
+  if (sh.waves == 0) return fail(SE_EINVAL, "K=%d exceeds the largest loop configuration", a.K);
+  if (a.ldG < cap || a.ldR < cap)
+    return fail(SE_EINVAL, "row strides (ldG=%d, ldR=%d) below the padded length %d", a.ldG,
+                a.ldR, cap);
+  switch (sh.waves * 100 + sh.vpl) {
+    case 108: launch_shape<1, 8>(a, grid, s); break;
+    case 116: launch_shape<1, 16>(a, grid, s); break;
+    case 124: launch_shape<1, 24>(a, grid, s); break;
+    case 132: launch_shape<1, 32>(a, grid, s); break;
+    case 224: launch_shape<2, 24>(a, grid, s); break;
+    case 232: launch_shape<2, 32>(a, grid, s); break;
+    case 424: launch_shape<4, 24>(a, grid, s); break;
+    case 432: launch_shape<4, 32>(a, grid, s); break;
+    case 824: launch_shape<8, 24>(a, grid, s); break;
+    case 832: launch_shape<8, 32>(a, grid, s); break;
+    case 1624: launch_shape<16, 24>(a, grid, s); break;
+    case 1632: launch_shape<16, 32>(a, grid, s); break;
+    default: return fail(SE_EINVAL, "no loop shape for K=%d", a.K);
+  }
   return check_launch("greedy");
 }
 

@@ -19,10 +19,9 @@ se_status check_launch(const char* what);
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Device copy of one block descriptor, validated on the host.
-struct DevBlock {
-  int32_t img, y0, x0, ly, lx, lh, lw, pad;
-};
+// Device copy of one block descriptor (same layout as se_block), validated
+// on the host by se_blocks_upload.
+using DevBlock = se_block;
 
 // ---------------------------------------------------------------------------
 // kernel launchers (defined in the .hip files)
@@ -44,6 +43,8 @@ void launch_finalize_d(const float* diag32, const double* diag64,
 // Y[k][p] = D_k sqrt(w_p) phi[k][p]
 void launch_scale_y(const float* phi, const float* D, const float* sqrtw,
                     int K, int P, float* Y, hipStream_t s);
+// zero columns [c0, ld) of a rows x ld matrix
+void launch_zero_cols(float* A, int rows, int c0, int ld, hipStream_t s);
 // split x = hi + lo into two bf16 arrays (precision path)
 void launch_split_bf16(const float* x, size_t n, uint16_t* hi, uint16_t* lo,
                        hipStream_t s);
@@ -90,6 +91,7 @@ struct GreedyArgs {
   int g_loss_ld;
 };
 int greedy_waves_for(int K);   // 0 if K is too large
+int greedy_row_len(int K);     // padded row length (table row stride minimum)
 se_status launch_greedy(const GreedyArgs& a, int grid, hipStream_t s);
 
 }  // namespace sefase

@@ -34,7 +34,8 @@ def test_no_gpu_code_in_python_fallback():
     assert "import oracle" not in src and "from oracle" not in src
 
 
-def _tables_struct(K=64, M=8, N=8, ldG=64, fake=0x1000):
+def _tables_struct(K=64, M=8, N=8, ldG=None, fake=0x1000):
+    ldG = B.table_ld(K) if ldG is None else ldG
     return B.se_tables(M, N, K, ldG, fake, fake, fake, fake, fake, 0)
 
 
@@ -53,8 +54,8 @@ def test_rejects_bad_arguments_on_host():
     r = L.se_extrapolate_batch(C.byref(t), fake, 1, 32, 32, blk, 1, B.se_params(1.5, 10, 0),
                                None, None, None, 0, fake, 1 << 20, None)
     assert r == B.SE_EINVAL
-    # ldG not a multiple of 4
-    t2 = _tables_struct(K=63, ldG=63)
+    # ldG below the padded row length
+    t2 = _tables_struct(K=63, ldG=64)
     r = L.se_extrapolate_batch(C.byref(t2), fake, 1, 32, 32, blk, 1, prm, None, None, None, 0,
                                fake, 1 << 20, None)
     assert r == B.SE_EINVAL
@@ -86,9 +87,22 @@ def test_rejects_bad_arguments_on_host():
     assert r == B.SE_EINVAL
 
 
+def test_table_ld_is_padded_row_length():
+    assert B.table_ld(2048) == 2048
+    assert B.table_ld(2000) == 2048
+    assert B.table_ld(4096) == 4096
+    assert B.table_ld(8192) == 8192
+    assert B.table_ld(4608) == 6144
+    assert B.table_ld(1) == 512
+    assert B.lib().se_table_ld(0) == 0 and B.lib().se_table_ld(40000) == 0
+    for K in (1, 100, 513, 1025, 3000, 12000, 32768):
+        ld = B.table_ld(K)
+        assert ld >= K and ld % 64 == 0
+
+
 def test_workspace_sizes_grow_with_work():
     L = B.lib()
-    t = _tables_struct(K=2048, M=32, N=32, ldG=2048)
+    t = _tables_struct(K=2048, M=32, N=32)
     a = L.se_extrapolate_batch_ws_bytes(C.byref(t), 16)
     b = L.se_extrapolate_batch_ws_bytes(C.byref(t), 4096)
     assert 0 < a < b
