@@ -100,7 +100,12 @@ typedef struct {
  *   sqrtw: M*N float32, sqrt(w).
  *   phi  : the dictionary itself (read by the model update).
  *   info : optional (may be NULL) device int32: 1 if the diagonal was
- *          summed in FP64, 0 if in FP32.                                  */
+ *          summed in FP64, 0 if in FP32.
+ *   precision : set by se_weighted_gram; the initial projections of blocks
+ *          using these tables are computed in the same precision.
+ *   Yhi, Ylo : K x (M*N) bfloat16 bit patterns, Y = Yhi + Ylo (hi = bf16(Y),
+ *          lo = bf16(Y - hi)); required (non-NULL) for SE_BF16X3, unused
+ *          for SE_FP32.                                                   */
 typedef struct {
   int32_t M, N, K, ldG;
   float* G;
@@ -109,6 +114,9 @@ typedef struct {
   float* sqrtw;
   const float* phi;
   int32_t* info;
+  int32_t precision;
+  uint16_t* Yhi;
+  uint16_t* Ylo;
 } se_tables;
 
 /* Model-generation parameters: gamma of eq. 8 (0 < gamma <= 1) and the
@@ -159,12 +167,13 @@ se_status se_area_weights(int32_t M, int32_t N, float rho_hat,
 
 /* Builds the tables of one weight pattern w (device, M*N float32, w >= 0)
  * for dictionary b into *t (whose buffers and ldG the caller has set; M, N,
- * K and phi are filled in from b).  The diagonal C_kk is summed first (FP32
- * or FP64 per `flags`), then D, then Y, then the lower triangle of
- * G = Y Y^T on the matrix cores (FP32 MFMA for SE_FP32; three BF16 products
- * hi*hi + hi*lo + lo*hi with FP32 accumulation for SE_BF16X3), mirrored to
- * the upper triangle -- Algorithm 2 computes (|D|^2 + |D|)/2 products and
- * mirrors the rest.
+ * K, phi and precision are filled in).  The diagonal C_kk is summed first
+ * (FP32 or FP64 per `flags`), then D, then Y, then the lower triangle of
+ * G = Y Y^T on the matrix cores (FP32 MFMA for SE_FP32; for SE_BF16X3, Y is
+ * split into t->Yhi + t->Ylo and the products hi*hi + hi*lo + lo*hi are
+ * accumulated in FP32 on the BF16 matrix cores), mirrored to the upper
+ * triangle -- Algorithm 2 computes (|D|^2 + |D|)/2 products and mirrors the
+ * rest.
  * ws: device scratch of se_weighted_gram_ws_bytes(b, prec) bytes.
  * Errors: SE_EINVAL for a NULL pointer, K < 1, ldG < K or not a multiple
  * of 4, an unknown precision or flag, ws too small. */
@@ -224,7 +233,8 @@ se_status se_extrapolate_batch(const se_tables* t, uint8_t* images,
  * se_project: the initial weighted scalar products of eq. 12 for every
  *   block, R[b][k] = D_k R_k^(0) (device float32, n_blk rows of stride ldR,
  *   a multiple of 4, 16-byte aligned), as one matrix product on
- *   the matrix cores; columns K .. ldR-1 are written as 0.  ldR >=
+ *   the matrix cores (FP32, or split BF16 when t->precision is SE_BF16X3);
+ *   columns K .. ldR-1 are written as 0.  ldR >=
  *   se_table_ld(K).  ws: se_project_ws_bytes(t, n_blk) bytes.
  * se_iterate: the iteration loop (eq. 18, 19, 9, 20) from R and the
  *   replacement of every loss in `images`; R is read only.  Outputs as for

@@ -101,6 +101,7 @@ class SEResult:
     second: np.ndarray       # (I,) best score outside the winner's class
     energy: np.ndarray       # (I+1,) weighted residual energy sum w r^2
     R_history: Optional[List[np.ndarray]] = None
+    picked: Optional[np.ndarray] = None   # (I,) score of the atom actually taken
 
 
 def _second_best(score: np.ndarray, u: int, classes: Optional[np.ndarray]) -> float:
@@ -113,7 +114,8 @@ def _second_best(score: np.ndarray, u: int, classes: Optional[np.ndarray]) -> fl
 
 
 def se_original(s: np.ndarray, w: np.ndarray, phi: np.ndarray, gamma: float,
-                iters: int, classes: Optional[np.ndarray] = None) -> SEResult:
+                iters: int, classes: Optional[np.ndarray] = None,
+                forced: Optional[Sequence[int]] = None) -> SEResult:
     """Algorithm 1, literally: for every iteration the weighted projection
     p_k (eq. 3) of the residual onto every atom is recomputed from scratch,
     numerator and denominator, the atom maximising |p_k|^2 sum(phi_k w phi_k)
@@ -122,6 +124,12 @@ def se_original(s: np.ndarray, w: np.ndarray, phi: np.ndarray, gamma: float,
 
     Each scalar product is a plain row-wise sum of elementwise products, so
     bit-identical atoms get bit-identical scores and the lowest index wins.
+
+    ``forced``: if given, iteration nu takes atom forced[nu] instead of the
+    maximiser (everything else unchanged); ``picked`` then records that
+    atom's score beside the maximal score in ``best``.  This evaluates the
+    algorithm along a selection sequence that another implementation chose
+    at a near-tie.
     """
     s = np.asarray(s, dtype=np.float64)
     w = np.asarray(w, dtype=np.float64)
@@ -132,6 +140,7 @@ def se_original(s: np.ndarray, w: np.ndarray, phi: np.ndarray, gamma: float,
     coef = np.zeros(iters)
     best = np.zeros(iters)
     second = np.zeros(iters)
+    picked = np.zeros(iters)
     energy = np.zeros(iters + 1)
     energy[0] = float(np.sum(w * r * r))
     for nu in range(iters):
@@ -141,16 +150,18 @@ def se_original(s: np.ndarray, w: np.ndarray, phi: np.ndarray, gamma: float,
         p = np.zeros_like(num)
         p[safe] = num[safe] / den[safe]                      # eq. 3
         score = np.where(safe, p * p * den, 0.0)             # eq. 7
-        u = int(np.argmax(score))
+        top = int(np.argmax(score))
+        u = top if forced is None else int(forced[nu])
         c = gamma * p[u]                                     # eq. 8
         g = g + c * phi[u]                                   # eq. 9
         r = r - c * phi[u]                                   # eq. 10
         sel[nu] = u
         coef[nu] = c
-        best[nu] = score[u]
-        second[nu] = _second_best(score, u, classes)
+        best[nu] = score[top]
+        picked[nu] = score[u]
+        second[nu] = _second_best(score, top, classes)
         energy[nu + 1] = float(np.sum(w * r * r))
-    return SEResult(sel, coef, g, best, second, energy)
+    return SEResult(sel, coef, g, best, second, energy, picked=picked)
 
 
 # ----------------------------------------------------------------------------
@@ -178,10 +189,11 @@ def table_generation(phi: np.ndarray, w: np.ndarray):
 def fase(s: np.ndarray, w: np.ndarray, phi: np.ndarray, C: np.ndarray,
          D: np.ndarray, gamma: float, iters: int,
          classes: Optional[np.ndarray] = None,
-         keep_R: bool = False) -> SEResult:
+         keep_R: bool = False, forced: Optional[Sequence[int]] = None) -> SEResult:
     """Algorithm 3: R_k = sum s phi_k w once (eq. 12); per iteration
     u = argmax |R_k| D_k (eq. 18), c-hat = gamma R_u D_u^2 (eq. 19),
-    g += c-hat phi_u (eq. 9), R_k -= c-hat C_(k,u) (eq. 20)."""
+    g += c-hat phi_u (eq. 9), R_k -= c-hat C_(k,u) (eq. 20).
+    ``forced`` as in se_original."""
     s = np.asarray(s, dtype=np.float64)
     w = np.asarray(w, dtype=np.float64)
     phi = np.asarray(phi, dtype=np.float64)
@@ -192,12 +204,14 @@ def fase(s: np.ndarray, w: np.ndarray, phi: np.ndarray, C: np.ndarray,
     coef = np.zeros(iters)
     best = np.zeros(iters)
     second = np.zeros(iters)
+    picked = np.zeros(iters)
     energy = np.zeros(iters + 1)
     energy[0] = float(np.sum(w * r * r))
     hist = [R.copy()] if keep_R else None
     for nu in range(iters):
         score = np.abs(R) * D
-        u = int(np.argmax(score))
+        top = int(np.argmax(score))
+        u = top if forced is None else int(forced[nu])
         c = gamma * R[u] * D[u] * D[u]
         g = g + c * phi[u]
         R = R - c * C[:, u]
@@ -206,12 +220,13 @@ def fase(s: np.ndarray, w: np.ndarray, phi: np.ndarray, C: np.ndarray,
         coef[nu] = c
         # report the score in the eq. 7 form (|R|^2 D^2) so it compares
         # directly with se_original's
-        best[nu] = score[u] ** 2
-        second[nu] = _second_best(score, u, classes) ** 2
+        best[nu] = score[top] ** 2
+        picked[nu] = score[u] ** 2
+        second[nu] = _second_best(score, top, classes) ** 2
         energy[nu + 1] = float(np.sum(w * r * r))
         if keep_R:
             hist.append(R.copy())
-    return SEResult(sel, coef, g, best, second, energy, hist)
+    return SEResult(sel, coef, g, best, second, energy, hist, picked)
 
 
 # ----------------------------------------------------------------------------

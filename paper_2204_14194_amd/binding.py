@@ -47,7 +47,8 @@ class se_block(C.Structure):
 class se_tables(C.Structure):
     _fields_ = [("M", C.c_int32), ("N", C.c_int32), ("K", C.c_int32), ("ldG", C.c_int32),
                 ("G", C.c_void_p), ("D", C.c_void_p), ("Y", C.c_void_p),
-                ("sqrtw", C.c_void_p), ("phi", C.c_void_p), ("info", C.c_void_p)]
+                ("sqrtw", C.c_void_p), ("phi", C.c_void_p), ("info", C.c_void_p),
+                ("precision", C.c_int32), ("Yhi", C.c_void_p), ("Ylo", C.c_void_p)]
 
 
 class se_params(C.Structure):
@@ -180,14 +181,20 @@ class Tables:
     phi: torch.Tensor
     info: torch.Tensor
     precision: int
+    Yhi: Optional[torch.Tensor] = None
+    Ylo: Optional[torch.Tensor] = None
 
     def struct(self) -> se_tables:
         return se_tables(self.M, self.N, self.K, self.ldG, self.G.data_ptr(), self.D.data_ptr(),
                          self.Y.data_ptr(), self.sqrtw.data_ptr(), self.phi.data_ptr(),
-                         self.info.data_ptr())
+                         self.info.data_ptr(), self.precision,
+                         self.Yhi.data_ptr() if self.Yhi is not None else None,
+                         self.Ylo.data_ptr() if self.Ylo is not None else None)
 
     def nbytes(self) -> int:
-        return sum(t.numel() * t.element_size() for t in (self.G, self.D, self.Y, self.sqrtw))
+        parts = [self.G, self.D, self.Y, self.sqrtw]
+        parts += [x for x in (self.Yhi, self.Ylo) if x is not None]
+        return sum(t.numel() * t.element_size() for t in parts)
 
 
 def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
@@ -208,6 +215,9 @@ def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
                torch.empty((K, M * N), dtype=torch.float32, device=dev),
                torch.empty(M * N, dtype=torch.float32, device=dev),
                phi, torch.zeros(1, dtype=torch.int32, device=dev), int(precision))
+    if precision == SE_BF16X3:
+        t.Yhi = torch.empty((K, M * N), dtype=torch.int16, device=dev)
+        t.Ylo = torch.empty((K, M * N), dtype=torch.int16, device=dev)
     b = se_basis(M, N, K, phi.data_ptr())
     nb = L.se_weighted_gram_ws_bytes(C.byref(b), int(precision))
     ws = _workspace(nb, dev)

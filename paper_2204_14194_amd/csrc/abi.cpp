@@ -67,7 +67,48 @@ static se_status check_tables(const se_tables* t) {
                 greedy_row_len(t->K));
   if (!t->G || !t->D || !t->Y || !t->sqrtw || !t->phi) return fail(SE_EINVAL, "a table pointer is NULL");
   if (reinterpret_cast<uintptr_t>(t->G) % 16) return fail(SE_EINVAL, "G must be 16-byte aligned");
+  if (t->precision != SE_FP32 && t->precision != SE_BF16X3)
+    return fail(SE_EINVAL, "unknown table precision %d", t->precision);
+  if (t->precision == SE_BF16X3 && (!t->Yhi || !t->Ylo))
+    return fail(SE_EINVAL, "BF16X3 tables need Yhi and Ylo");
   return SE_OK;
+}
+
+static inline int round8(int v) { return (v + 7) & ~7; }
+
+// Workspace of the projection stage: X as float32, or as split bf16 pairs.
+static size_t project_ws(const se_tables* t, int n_blk) {
+  Carver cv(nullptr);
+  const int P = t->M * t->N;
+  if (t->precision == SE_BF16X3) {
+    cv.take<uint16_t>((size_t)n_blk * round8(P));
+    cv.take<uint16_t>((size_t)n_blk * round8(P));
+  } else {
+    cv.take<float>((size_t)n_blk * round4(P));
+  }
+  return cv.off + 256;
+}
+
+// gather + projection GEMM in the tables' precision; ws holds project_ws().
+static se_status project_into(const se_tables* t, const uint8_t* images, int H, int W,
+                              const se_block* dblk, int n_blk, float* R, int ldR, void* ws,
+                              hipStream_t s) {
+  se_status st;
+  const int P = t->M * t->N;
+  Carver cv(ws);
+  if (t->precision == SE_BF16X3) {
+    const int ldX = round8(P);
+    uint16_t* xh = cv.take<uint16_t>((size_t)n_blk * ldX);
+    uint16_t* xl = cv.take<uint16_t>((size_t)n_blk * ldX);
+    launch_gather_split(images, H, W, dblk, n_blk, t->M, t->N, t->sqrtw, xh, xl, ldX, s);
+    if ((st = check_launch("gather_split"))) return st;
+    return gemm_project_bf16x3(t->Yhi, t->Ylo, P, t->K, xh, xl, ldX, n_blk, P, R, ldR, s);
+  }
+  const int ldX = round4(P);
+  float* X = cv.take<float>((size_t)n_blk * ldX);
+  launch_gather(images, H, W, dblk, n_blk, t->M, t->N, t->sqrtw, X, ldX, s);
+  if ((st = check_launch("gather"))) return st;
+  return gemm_project_f32(t->Y, P, t->K, X, ldX, n_blk, P, R, ldR, 0, s);
 }
 
 static se_status check_blocks(const se_tables* t, int n_img, int H, int W, const se_block* blocks,
@@ -129,15 +170,12 @@ se_status se_area_weights(int32_t M, int32_t N, float rho_hat, const uint8_t* lo
 
 // ---------------------------------------------------------------------------
 size_t se_weighted_gram_ws_bytes(const se_basis* b, se_precision prec) {
+  (void)prec;
   if (!b || b->K < 1 || b->M < 1 || b->N < 1) return 0;
   Carver cv(nullptr);
-  const size_t K = (size_t)b->K, P = (size_t)b->M * b->N;
+  const size_t K = (size_t)b->K;
   cv.take<float>(K);
   cv.take<double>(K);
-  if (prec == SE_BF16X3) {
-    cv.take<uint16_t>(K * P);
-    cv.take<uint16_t>(K * P);
-  }
   return cv.off + 256;
 }
 
@@ -153,6 +191,7 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
   t->N = b->N;
   t->K = b->K;
   t->phi = b->phi;
+  t->precision = (int32_t)prec;
   se_status st = check_tables(t);
   if (st) return st;
   if (!ws || ws_bytes < se_weighted_gram_ws_bytes(b, prec)) return fail(SE_ENOMEM, "workspace too small");
@@ -170,14 +209,10 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
   if ((st = check_launch("scale_y"))) return st;
   launch_zero_cols(t->G, K, K, t->ldG, s);
   if ((st = check_launch("zero_cols"))) return st;
-  if (prec == SE_FP32) {
-    return gemm_nt_f32(t->Y, P, t->Y, P, t->G, t->ldG, K, K, K, P, true, 0, s);
-  }
-  uint16_t* yhi = cv.take<uint16_t>((size_t)K * P);
-  uint16_t* ylo = cv.take<uint16_t>((size_t)K * P);
-  launch_split_bf16(t->Y, (size_t)K * P, yhi, ylo, s);
+  if (prec == SE_FP32) return gemm_syrk_f32(t->Y, P, K, P, t->G, t->ldG, s);
+  launch_split_bf16(t->Y, (size_t)K * P, t->Yhi, t->Ylo, s);
   if ((st = check_launch("split_bf16"))) return st;
-  return gemm_nt_bf16x3(yhi, ylo, P, yhi, ylo, P, t->G, t->ldG, K, K, K, P, true, s);
+  return gemm_syrk_bf16x3(t->Yhi, t->Ylo, P, K, P, t->G, t->ldG, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -198,7 +233,7 @@ se_status se_blocks_upload(const se_tables* t, int32_t n_img, int32_t H, int32_t
 
 size_t se_project_ws_bytes(const se_tables* t, int32_t n_blk) {
   if (!t || t->K < 1 || t->M < 1 || t->N < 1 || n_blk < 0) return 0;
-  return align_up((size_t)n_blk * round4(t->M * t->N) * sizeof(float), 256) + 256;
+  return project_ws(t, n_blk);
 }
 
 static se_status check_common(const se_tables* t, int n_img, int H, int W, int n_blk,
@@ -222,13 +257,8 @@ se_status se_project(const se_tables* t, const uint8_t* images, int32_t n_img, i
     return fail(SE_EINVAL, "R must be 16-byte aligned with ldR >= se_table_ld(K)=%d, a multiple of 4",
                 greedy_row_len(t->K));
   if (!ws || ws_bytes < se_project_ws_bytes(t, n_blk)) return fail(SE_ENOMEM, "workspace too small");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const int P = t->M * t->N, ldX = round4(P);
-  Carver cv(ws);
-  float* X = cv.take<float>((size_t)n_blk * ldX);
-  launch_gather(images, H, W, dev_blocks, n_blk, t->M, t->N, t->sqrtw, X, ldX, s);
-  if ((st = check_launch("gather"))) return st;
-  return gemm_nt_f32(X, ldX, t->Y, P, R, ldR, n_blk, t->K, ldR, P, false, 0, s);
+  return project_into(t, images, H, W, dev_blocks, n_blk, R, ldR, ws,
+                      static_cast<hipStream_t>(stream));
 }
 
 static GreedyArgs greedy_args(const se_tables* t, const float* R, int ldR, uint8_t* images, int H,
@@ -246,7 +276,7 @@ static GreedyArgs greedy_args(const se_tables* t, const float* R, int ldR, uint8
   ga.N = t->N;
   ga.blk = dev_blocks;
   ga.n_blk = n_blk;
-  ga.blk0 = 0;
+  ga.blk0 = -1;   // batched: block = workgroup index
   ga.images = images;
   ga.H = H;
   ga.W = W;
@@ -287,8 +317,8 @@ size_t se_extrapolate_batch_ws_bytes(const se_tables* t, int32_t n_blk) {
   if (!t || t->K < 1 || t->M < 1 || t->N < 1 || n_blk < 0) return 0;
   Carver cv(nullptr);
   cv.take<se_block>((size_t)n_blk);
-  cv.take<float>((size_t)n_blk * round4(t->M * t->N));
   cv.take<float>((size_t)n_blk * greedy_row_len(t->K));
+  cv.take<char>(project_ws(t, n_blk > 0 ? n_blk : 0));
   return cv.off + 256;
 }
 
@@ -306,23 +336,22 @@ static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, in
   const size_t need = se_extrapolate_batch_ws_bytes(t, n_blk);
   if (!ws || ws_bytes < need) return fail(SE_ENOMEM, "workspace too small: need %zu bytes", need);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int P = t->M * t->N, ldX = round4(P), ldR = greedy_row_len(t->K);
+  const int P = t->M * t->N, ldR = greedy_row_len(t->K);
   Carver cv(ws);
   se_block* dblk = cv.take<se_block>((size_t)n_blk);
-  float* X = cv.take<float>((size_t)n_blk * ldX);
   float* R = cv.take<float>((size_t)n_blk * ldR);
+  char* pws = cv.take<char>(project_ws(t, n_blk));
   if ((st = upload_blocks(blocks, n_blk, dblk, s))) return st;
   GreedyArgs ga = greedy_args(t, R, ldR, images, H, W, dblk, n_blk, prm, sel, coef, g_loss,
                               g_loss_ld);
   if (!plain) {
-    launch_gather(images, H, W, dblk, n_blk, t->M, t->N, t->sqrtw, X, ldX, s);
-    if ((st = check_launch("gather"))) return st;
-    if ((st = gemm_nt_f32(X, ldX, t->Y, P, R, ldR, n_blk, t->K, ldR, P, false, 0, s))) return st;
+    if ((st = project_into(t, images, H, W, dblk, n_blk, R, ldR, pws, s))) return st;
     return launch_greedy(ga, n_blk, s);
   }
-  // one block at a time: gather, matrix-vector product, single-workgroup loop
+  // one block at a time: gather, matrix-vector product (FP32), single-workgroup loop
+  float* X = reinterpret_cast<float*>(pws);
   for (int i = 0; i < n_blk; ++i) {
-    launch_gather(images, H, W, dblk + i, 1, t->M, t->N, t->sqrtw, X, ldX, s);
+    launch_gather(images, H, W, dblk + i, 1, t->M, t->N, t->sqrtw, X, round4(P), s);
     if ((st = check_launch("gather"))) return st;
     launch_gemv(t->Y, t->K, P, X, R, s);
     if ((st = check_launch("gemv"))) return st;

@@ -2,16 +2,20 @@
 //   * table generation (Algorithm 2, eq. 16): G = Y Y^T over the area pixels,
 //     lower-triangle tiles only, each stored twice (G is symmetric, so only
 //     (|D|^2 + |D|)/2 scalar products are needed);
-//   * initial projections (eq. 12) of a batch of blocks: R = X Y^T.
-// C[r][c] = sum_p A[r][p] B[c][p]; both operands row-major with the
+//   * initial projections (eq. 12) of a batch of blocks: R = X Y^T, computed
+//     as Y X^T and stored transposed so every lane writes float4 rows.
+// S[r][c] = sum_p A[r][p] B[c][p]; both operands row-major with the
 // contraction index p contiguous ("NT").
 //
 // FP32 path: v_mfma_f32_16x16x4_f32.  A 256-thread workgroup (4 waves, 2x2)
-// owns a BM x BN output tile; each wave a (BM/2) x (BN/2) sub-tile made of
+// owns a BM x BN tile of S; each wave a (BM/2) x (BN/2) sub-tile made of
 // 16x16 MFMA tiles.  Operand tiles of BK = 32 contraction steps are staged
 // through LDS, double-buffered (one barrier per step).  A lane feeds the MFMA
-// a float4 along p: four consecutive MFMAs consume its x, y, z, w components,
-// which only permutes the order of the contraction, identically for A and B.
+// a float4 along p: four consecutive MFMA rounds consume its x, y, z, w
+// components, which only permutes the order of the contraction, identically
+// for A and B.  Rows beyond the valid range are read clamped to the last
+// valid row (they only feed outputs that are never stored), so the main loop
+// has no per-lane branches; only the last contraction tile checks p < P.
 //
 // MFMA 16x16x4 f32 operand/result mapping (lane l, 0..63):
 //   A[m][k]: m = l % 16, k = l / 16        B[k][n]: n = l % 16, k = l / 16
@@ -25,6 +29,8 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int kBK = 32;
 constexpr int kPad = 4;
 
+enum StoreMode { kStoreRowMajor = 0, kStoreTransposed = 1, kStoreSymmetric = 2 };
+
 // Map the linear workgroup id to a tile so that the 8 XCDs (which receive
 // workgroups round-robin) each work on a contiguous range of tiles.
 __device__ inline int xcd_remap(int id, int ntiles) {
@@ -33,7 +39,7 @@ __device__ inline int xcd_remap(int id, int ntiles) {
   return (id & 7) * per + (id >> 3);
 }
 
-template <int ROWS, bool VEC>
+template <int ROWS, bool VEC, bool KTAIL>
 __device__ inline void load_tile(const float* __restrict__ src, int ld, int row0, int nrows,
                                  int k0, int P, float4 (&reg)[ROWS * kBK / 4 / 256]) {
   constexpr int NQ = ROWS * kBK / 4 / 256;
@@ -42,19 +48,22 @@ __device__ inline void load_tile(const float* __restrict__ src, int ld, int row0
     const int idx = threadIdx.x + 256 * q;
     const int r = idx / (kBK / 4);
     const int c = (idx % (kBK / 4)) * 4;
-    const int gr = row0 + r;
+    int gr = row0 + r;
+    gr = gr < nrows ? gr : nrows - 1;
     const int gk = k0 + c;
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (gr < nrows) {
-      const float* p = src + (size_t)gr * ld + gk;
-      if (VEC && gk + 3 < P) {
+    const float* p = src + (size_t)gr * ld + gk;
+    float4 v;
+    if (!KTAIL) {
+      if (VEC) {
         v = *reinterpret_cast<const float4*>(p);
       } else {
-        if (gk + 0 < P) v.x = p[0];
-        if (gk + 1 < P) v.y = p[1];
-        if (gk + 2 < P) v.z = p[2];
-        if (gk + 3 < P) v.w = p[3];
+        v = make_float4(p[0], p[1], p[2], p[3]);
       }
+    } else {
+      v.x = gk + 0 < P ? p[0] : 0.0f;
+      v.y = gk + 1 < P ? p[1] : 0.0f;
+      v.z = gk + 2 < P ? p[2] : 0.0f;
+      v.w = gk + 3 < P ? p[3] : 0.0f;
     }
     reg[q] = v;
   }
@@ -72,18 +81,27 @@ __device__ inline void store_tile(float (*lds)[kBK + kPad], const float4 (&reg)[
   }
 }
 
-template <int BM, int BN, bool VEC, bool SYRK>
+// S = A B^T for a BM x BN tile.
+//   Ma, Nb : valid rows of A and of B
+//   Mst, Nst : extent of S that is stored; S entries with r >= Ma or c >= Nb
+//              inside it are stored as 0
+//   MODE kStoreRowMajor   : C[r][c] = S[r][c]
+//        kStoreTransposed : C[c][r] = S[r][c]
+//        kStoreSymmetric  : A == B; only tiles with bj <= bi run; C[r][c] and
+//                           C[c][r] = S[r][c] for r >= c
+template <int BM, int BN, bool VEC, int MODE>
 __global__ __launch_bounds__(256) void k_gemm_nt_f32(const float* __restrict__ A, int lda,
                                                      const float* __restrict__ B, int ldb,
-                                                     float* __restrict__ C, int ldc, int Mr, int Nc,
-                                                     int Nst, int P, int tiles_n, int ntiles) {
+                                                     float* __restrict__ C, int ldc, int Ma, int Nb,
+                                                     int Mst, int Nst, int P, int tiles_n,
+                                                     int ntiles) {
   constexpr int SI = BM / 32, SJ = BN / 32;   // 16x16 MFMA tiles per wave
   __shared__ __attribute__((aligned(16))) float As[2][BM][kBK + kPad];
   __shared__ __attribute__((aligned(16))) float Bs[2][BN][kBK + kPad];
 
   const int tile = xcd_remap(blockIdx.x, ntiles);
   int bi, bj;
-  if (SYRK) {
+  if (MODE == kStoreSymmetric) {
     // tile -> (bi, bj), bj <= bi, row-major over the lower triangle
     bi = (int)((sqrtf(8.0f * (float)tile + 1.0f) - 1.0f) * 0.5f);
     while ((bi + 1) * (bi + 2) / 2 <= tile) ++bi;
@@ -106,8 +124,14 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f32(const float* __restrict__ A
 
   float4 ra[BM * kBK / 4 / 256], rb[BN * kBK / 4 / 256];
   const int nk = (P + kBK - 1) / kBK;
-  load_tile<BM, VEC>(A, lda, m0, Mr, 0, P, ra);
-  load_tile<BN, VEC>(B, ldb, n0, Nc, 0, P, rb);
+  const bool ragged = (P % kBK) != 0;
+  if (nk == 1 && ragged) {
+    load_tile<BM, VEC, true>(A, lda, m0, Ma, 0, P, ra);
+    load_tile<BN, VEC, true>(B, ldb, n0, Nb, 0, P, rb);
+  } else {
+    load_tile<BM, VEC, false>(A, lda, m0, Ma, 0, P, ra);
+    load_tile<BN, VEC, false>(B, ldb, n0, Nb, 0, P, rb);
+  }
   store_tile<BM>(As[0], ra);
   store_tile<BN>(Bs[0], rb);
   __syncthreads();
@@ -115,9 +139,19 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f32(const float* __restrict__ A
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) {
-      load_tile<BM, VEC>(A, lda, m0, Mr, (kt + 1) * kBK, P, ra);
-      load_tile<BN, VEC>(B, ldb, n0, Nc, (kt + 1) * kBK, P, rb);
+      const int k1 = (kt + 1) * kBK;
+      if (kt + 2 == nk && ragged) {
+        load_tile<BM, VEC, true>(A, lda, m0, Ma, k1, P, ra);
+        load_tile<BN, VEC, true>(B, ldb, n0, Nb, k1, P, rb);
+      } else {
+        load_tile<BM, VEC, false>(A, lda, m0, Ma, k1, P, ra);
+        load_tile<BN, VEC, false>(B, ldb, n0, Nb, k1, P, rb);
+      }
     }
+    // this stage's 32 products go to fresh accumulators and are then added to
+    // the running sums (blocked summation keeps the FP32 rounding error
+    // growing with the number of stages instead of the number of pixels)
+    floatx4 part[SI][SJ];
 #pragma unroll
     for (int kk = 0; kk < kBK; kk += 16) {
       float4 fa[SI], fb[SJ];
@@ -130,13 +164,29 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f32(const float* __restrict__ A
 #pragma unroll
       for (int i = 0; i < SI; ++i)
 #pragma unroll
-        for (int j = 0; j < SJ; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].x, fb[j].x, acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].y, fb[j].y, acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].z, fb[j].z, acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].w, fb[j].w, acc[i][j], 0, 0, 0);
-        }
+        for (int j = 0; j < SJ; ++j)
+          part[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+              fa[i].x, fb[j].x, kk == 0 ? floatx4{0.f, 0.f, 0.f, 0.f} : part[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < SI; ++i)
+#pragma unroll
+        for (int j = 0; j < SJ; ++j)
+          part[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].y, fb[j].y, part[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < SI; ++i)
+#pragma unroll
+        for (int j = 0; j < SJ; ++j)
+          part[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].z, fb[j].z, part[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < SI; ++i)
+#pragma unroll
+        for (int j = 0; j < SJ; ++j)
+          part[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].w, fb[j].w, part[i][j], 0, 0, 0);
     }
+#pragma unroll
+    for (int i = 0; i < SI; ++i)
+#pragma unroll
+      for (int j = 0; j < SJ; ++j) acc[i][j] += part[i][j];
     if (kt + 1 < nk) {
       store_tile<BM>(As[cur ^ 1], ra);
       store_tile<BN>(Bs[cur ^ 1], rb);
@@ -148,65 +198,96 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f32(const float* __restrict__ A
 #pragma unroll
   for (int i = 0; i < SI; ++i)
 #pragma unroll
-    for (int j = 0; j < SJ; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = m0 + wr * (BM / 2) + 16 * i + 4 * lq + e;
-        const int c = n0 + wc * (BN / 2) + 16 * j + lr;
-        const float v = acc[i][j][e];
-        if (SYRK) {
-          if (r < Mr && c < Nc && r >= c) {
-            C[(size_t)r * ldc + c] = v;
-            if (r > c) C[(size_t)c * ldc + r] = v;
+    for (int j = 0; j < SJ; ++j) {
+      const int r0 = m0 + wr * (BM / 2) + 16 * i + 4 * lq;   // rows r0 .. r0+3
+      const int c = n0 + wc * (BN / 2) + 16 * j + lr;
+      if (MODE == kStoreTransposed) {
+        if (c < Nst && c < Nb) {
+          float4 v;
+          v.x = r0 + 0 < Ma ? acc[i][j][0] : 0.0f;
+          v.y = r0 + 1 < Ma ? acc[i][j][1] : 0.0f;
+          v.z = r0 + 2 < Ma ? acc[i][j][2] : 0.0f;
+          v.w = r0 + 3 < Ma ? acc[i][j][3] : 0.0f;
+          float* dst = C + (size_t)c * ldc + r0;
+          if (VEC && r0 + 3 < Mst) {
+            *reinterpret_cast<float4*>(dst) = v;
+          } else {
+            if (r0 + 0 < Mst) dst[0] = v.x;
+            if (r0 + 1 < Mst) dst[1] = v.y;
+            if (r0 + 2 < Mst) dst[2] = v.z;
+            if (r0 + 3 < Mst) dst[3] = v.w;
           }
-        } else {
-          if (r < Mr && c < Nst) C[(size_t)r * ldc + c] = v;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = r0 + e;
+          const float v = acc[i][j][e];
+          if (MODE == kStoreSymmetric) {
+            if (r < Ma && c < Nb && r >= c) {
+              C[(size_t)r * ldc + c] = v;
+              if (r > c) C[(size_t)c * ldc + r] = v;
+            }
+          } else {
+            if (r < Mst && c < Nst) C[(size_t)r * ldc + c] = (r < Ma && c < Nb) ? v : 0.0f;
+          }
         }
       }
+    }
 }
 
-template <int BM, int BN, bool SYRK>
+template <int BM, int BN, int MODE>
 static se_status launch_f32(const float* A, int lda, const float* B, int ldb, float* C, int ldc,
-                            int Mr, int Nc, int Nst, int P, bool vec, hipStream_t s) {
+                            int Ma, int Nb, int Mst, int Nst, int P, bool vec, hipStream_t s) {
   int ntiles, tiles_n;
-  if (SYRK) {
-    const int nb = (Mr + BM - 1) / BM;
+  if (MODE == kStoreSymmetric) {
+    const int nb = (Ma + BM - 1) / BM;
     ntiles = nb * (nb + 1) / 2;
     tiles_n = nb;
   } else {
     tiles_n = (Nst + BN - 1) / BN;
-    ntiles = ((Mr + BM - 1) / BM) * tiles_n;
+    ntiles = ((Mst + BM - 1) / BM) * tiles_n;
   }
-  if (ntiles <= 0) return SE_OK;
+  if (ntiles <= 0 || P <= 0) return SE_OK;
   if (vec)
-    hipLaunchKernelGGL((k_gemm_nt_f32<BM, BN, true, SYRK>), dim3(ntiles), dim3(256), 0, s, A, lda,
-                       B, ldb, C, ldc, Mr, Nc, Nst, P, tiles_n, ntiles);
+    hipLaunchKernelGGL((k_gemm_nt_f32<BM, BN, true, MODE>), dim3(ntiles), dim3(256), 0, s, A, lda,
+                       B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, tiles_n, ntiles);
   else
-    hipLaunchKernelGGL((k_gemm_nt_f32<BM, BN, false, SYRK>), dim3(ntiles), dim3(256), 0, s, A,
-                       lda, B, ldb, C, ldc, Mr, Nc, Nst, P, tiles_n, ntiles);
+    hipLaunchKernelGGL((k_gemm_nt_f32<BM, BN, false, MODE>), dim3(ntiles), dim3(256), 0, s, A,
+                       lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, tiles_n, ntiles);
   return check_launch("gemm_nt_f32");
 }
 
-se_status gemm_nt_f32(const float* A, int lda, const float* B, int ldb, float* C, int ldc, int Mr,
-                      int Nc, int Nst, int P, bool syrk, int tile, hipStream_t s) {
-  const bool vec = (lda % 4 == 0) && (ldb % 4 == 0) &&
-                   ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) % 16 == 0);
+template <int MODE>
+static se_status dispatch_f32(const float* A, int lda, const float* B, int ldb, float* C, int ldc,
+                              int Ma, int Nb, int Mst, int Nst, int P, int tile, hipStream_t s) {
+  const bool vec = (lda % 4 == 0) && (ldb % 4 == 0) && (ldc % 4 == 0) &&
+                   ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B) |
+                     reinterpret_cast<uintptr_t>(C)) % 16 == 0);
   if (tile <= 0) {
-    // enough tiles to give every compute unit work with the larger tile?
+    // the larger tile only when it still gives every compute unit work
     long long big;
-    if (syrk) {
-      const long long nb = (Mr + 127) / 128;
+    if (MODE == kStoreSymmetric) {
+      const long long nb = (Ma + 127) / 128;
       big = nb * (nb + 1) / 2;
     } else {
-      big = (long long)((Mr + 127) / 128) * ((Nst + 127) / 128);
+      big = (long long)((Mst + 127) / 128) * ((Nst + 127) / 128);
     }
     tile = big >= 512 ? 128 : 64;
   }
   if (tile == 128)
-    return syrk ? launch_f32<128, 128, true>(A, lda, B, ldb, C, ldc, Mr, Nc, Nst, P, vec, s)
-                : launch_f32<128, 128, false>(A, lda, B, ldb, C, ldc, Mr, Nc, Nst, P, vec, s);
-  return syrk ? launch_f32<64, 64, true>(A, lda, B, ldb, C, ldc, Mr, Nc, Nst, P, vec, s)
-              : launch_f32<64, 64, false>(A, lda, B, ldb, C, ldc, Mr, Nc, Nst, P, vec, s);
+    return launch_f32<128, 128, MODE>(A, lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, vec, s);
+  return launch_f32<64, 64, MODE>(A, lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, vec, s);
+}
+
+se_status gemm_syrk_f32(const float* Y, int ldy, int K, int P, float* G, int ldg, hipStream_t s) {
+  return dispatch_f32<kStoreSymmetric>(Y, ldy, Y, ldy, G, ldg, K, K, K, K, P, 0, s);
+}
+
+se_status gemm_project_f32(const float* Y, int ldy, int K, const float* X, int ldx, int n_blk,
+                           int P, float* R, int ldr, int tile, hipStream_t s) {
+  // S = Y X^T (atoms x blocks), stored transposed: R[b][k]; atoms K .. ldr-1 as 0
+  return dispatch_f32<kStoreTransposed>(Y, ldy, X, ldx, R, ldr, K, n_blk, ldr, n_blk, P, tile, s);
 }
 
 }  // namespace sefase

@@ -71,13 +71,15 @@ __device__ inline uint64_t make_key(float v, int idx) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-template <int WAVES, int VPL>
+// ONE: the launch conceals the single block a.blk0 (plain per-block form); a
+// separate instantiation so profiles keep the two forms apart.
+template <int WAVES, int VPL, bool ONE>
 __global__ __launch_bounds__(64 * WAVES) void k_greedy(GreedyArgs a) {
   constexpr int T = 64 * WAVES;
   constexpr int NJ = VPL / 4;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  const int b = a.blk0 + (int)blockIdx.x;
+  const int b = ONE ? a.blk0 : (int)blockIdx.x;
   const DevBlock d = a.blk[b];
   const int K = a.K, P = a.M * a.N;
 
@@ -98,7 +100,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy(GreedyArgs a) {
   const int nloss = d.lh * d.lw;
   const int nq = (nloss + T - 1) / T;          // uniform
   int poff[kQPL];
-  float g[kQPL];
+  float g[kQPL], gc[kQPL];   // model and its compensation term (Kahan summation)
 #pragma unroll
   for (int q = 0; q < kQPL; ++q) {
     int i = t + q * T;
@@ -106,6 +108,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy(GreedyArgs a) {
     const int my = i / d.lw, mx = i - my * d.lw;
     poff[q] = (d.ly + my) * a.N + d.lx + mx;
     g[q] = 0.0f;
+    gc[q] = 0.0f;
   }
 
   __shared__ uint64_t s_key[2][WAVES];
@@ -161,7 +164,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy(GreedyArgs a) {
     const float* prow = a.phi + (size_t)u * P;
 #pragma unroll
     for (int q = 0; q < kQPL; ++q)
-      if (q < nq) g[q] = fmaf(c, prow[poff[q]], g[q]);   // eq. 9
+      if (q < nq) {                                       // eq. 9, compensated
+        const float y = fmaf(c, prow[poff[q]], -gc[q]);
+        const float s = g[q] + y;
+        gc[q] = (s - g[q]) - y;
+        g[q] = s;
+      }
 
     // ---- eq. 20 ---------------------------------------------------------
 #pragma unroll
@@ -220,7 +228,10 @@ int greedy_row_len(int K) {
 
 template <int W, int V>
 static void launch_shape(const GreedyArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_greedy<W, V>), dim3(grid), dim3(64 * W), 0, s, a);
+  if (grid == 1 && a.blk0 >= 0)
+    hipLaunchKernelGGL((k_greedy<W, V, true>), dim3(1), dim3(64 * W), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_greedy<W, V, false>), dim3(grid), dim3(64 * W), 0, s, a);
 }
 
 se_status launch_greedy(const GreedyArgs& a, int grid, hipStream_t s) {

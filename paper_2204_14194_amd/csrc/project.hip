@@ -32,6 +32,39 @@ void launch_gather(const uint8_t* images, int H, int W, const DevBlock* blk, int
                      n_blk, M, N, sqrtw, X, ldX);
 }
 
+__device__ inline uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__global__ void k_gather_split(const uint8_t* __restrict__ images, int H, int W,
+                               const DevBlock* __restrict__ blk, int n_blk, int M, int N,
+                               const float* __restrict__ sqrtw, uint16_t* __restrict__ Xhi,
+                               uint16_t* __restrict__ Xlo, int ldX) {
+  const int b = blockIdx.y;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int P = M * N;
+  if (b >= n_blk || p >= P) return;
+  const DevBlock d = blk[b];
+  const int m = p / N, n = p - m * N;
+  const int y = d.y0 + m, x = d.x0 + n;
+  float v = 0.0f;
+  if (y >= 0 && y < H && x >= 0 && x < W)
+    v = sqrtw[p] * (float)images[(size_t)d.img * H * W + (size_t)y * W + x];
+  const uint16_t h = bf16_rne(v);
+  Xhi[(size_t)b * ldX + p] = h;
+  Xlo[(size_t)b * ldX + p] = bf16_rne(v - __uint_as_float((uint32_t)h << 16));
+}
+
+void launch_gather_split(const uint8_t* images, int H, int W, const DevBlock* blk, int n_blk,
+                         int M, int N, const float* sqrtw, uint16_t* Xhi, uint16_t* Xlo, int ldX,
+                         hipStream_t s) {
+  const int P = M * N;
+  hipLaunchKernelGGL(k_gather_split, dim3((P + 255) / 256, n_blk), dim3(256), 0, s, images, H, W,
+                     blk, n_blk, M, N, sqrtw, Xhi, Xlo, ldX);
+}
+
 // r[k] = sum_p Y[k][p] x[p]; one wavefront per atom, lane-strided partial
 // sums combined by a fixed butterfly.
 __global__ __launch_bounds__(256) void k_gemv(const float* __restrict__ Y, int K, int P,

@@ -49,18 +49,20 @@ void launch_zero_cols(float* A, int rows, int c0, int ld, hipStream_t s);
 void launch_split_bf16(const float* x, size_t n, uint16_t* hi, uint16_t* lo,
                        hipStream_t s);
 
-// gemm.hip -- C[r][c] = sum_p A[r][p] B[c][p] (both operands row-major with
-// the contraction index contiguous).  syrk: A == B, only tiles on or below
-// the diagonal are computed and each is also stored transposed.
-// Rows r < Mr, columns c < Nc are computed; columns Nc <= c < Nst are
-// stored as 0 (padding of the output rows).
-se_status gemm_nt_f32(const float* A, int lda, const float* B, int ldb,
-                      float* C, int ldc, int Mr, int Nc, int Nst, int P,
-                      bool syrk, int tile, hipStream_t s);
-se_status gemm_nt_bf16x3(const uint16_t* Ahi, const uint16_t* Alo, int lda,
-                         const uint16_t* Bhi, const uint16_t* Blo, int ldb,
-                         float* C, int ldc, int Mr, int Nc, int Nst, int P,
-                         bool syrk, hipStream_t s);
+// gemm.hip -- FP32 matrix-core products over the area pixels
+// G = Y Y^T (lower-triangle tiles, mirrored); G is K x ldg.
+se_status gemm_syrk_f32(const float* Y, int ldy, int K, int P, float* G, int ldg,
+                        hipStream_t s);
+// R[b][k] = sum_p X[b][p] Y[k][p] for k < K, 0 for K <= k < ldr.
+// tile: 0 = automatic, 64 or 128.
+se_status gemm_project_f32(const float* Y, int ldy, int K, const float* X, int ldx,
+                           int n_blk, int P, float* R, int ldr, int tile, hipStream_t s);
+// gemm_bf16x3.hip -- the same two products from split-bf16 operands
+se_status gemm_syrk_bf16x3(const uint16_t* Yhi, const uint16_t* Ylo, int ldy, int K, int P,
+                           float* G, int ldg, hipStream_t s);
+se_status gemm_project_bf16x3(const uint16_t* Yhi, const uint16_t* Ylo, int ldy, int K,
+                              const uint16_t* Xhi, const uint16_t* Xlo, int ldx, int n_blk, int P,
+                              float* R, int ldr, hipStream_t s);
 
 // project.hip -- X[b][p] = sqrt(w_p) s_b[p] and the per-block GEMV
 void launch_gather(const uint8_t* images, int H, int W, const DevBlock* blk,
@@ -68,6 +70,10 @@ void launch_gather(const uint8_t* images, int H, int W, const DevBlock* blk,
                    int ldX, hipStream_t s);
 void launch_gemv(const float* Y, int K, int P, const float* x, float* r,
                  hipStream_t s);
+// the same gather, written as split bf16 pairs (precision path)
+void launch_gather_split(const uint8_t* images, int H, int W, const DevBlock* blk,
+                         int n_blk, int M, int N, const float* sqrtw, uint16_t* Xhi,
+                         uint16_t* Xlo, int ldX, hipStream_t s);
 
 // greedy.hip -- the iteration loop of Algorithm 3
 struct GreedyArgs {
@@ -80,7 +86,7 @@ struct GreedyArgs {
   int K, M, N;
   const DevBlock* blk; // n_blk
   int n_blk;
-  int blk0;            // index of the first block (plain form: one launch per block)
+  int blk0;            // plain form: the one block of this launch; -1 when batched
   uint8_t* images;
   int H, W;
   float gamma;

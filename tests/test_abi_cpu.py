@@ -36,7 +36,7 @@ def test_no_gpu_code_in_python_fallback():
 
 def _tables_struct(K=64, M=8, N=8, ldG=None, fake=0x1000):
     ldG = B.table_ld(K) if ldG is None else ldG
-    return B.se_tables(M, N, K, ldG, fake, fake, fake, fake, fake, 0)
+    return B.se_tables(M, N, K, ldG, fake, fake, fake, fake, fake, 0, 0, None, None)
 
 
 def test_rejects_bad_arguments_on_host():
@@ -107,6 +107,14 @@ def test_workspace_sizes_grow_with_work():
     b = L.se_extrapolate_batch_ws_bytes(C.byref(t), 4096)
     assert 0 < a < b
     assert b >= 4096 * (2048 + 1024) * 4
-    bas = B.se_basis(32, 32, 2048, 0x1000)
-    assert L.se_weighted_gram_ws_bytes(C.byref(bas), B.SE_BF16X3) > \
-        L.se_weighted_gram_ws_bytes(C.byref(bas), B.SE_FP32)
+    tb = _tables_struct(K=2048, M=32, N=32)
+    tb.precision = B.SE_BF16X3
+    tb.Yhi = tb.Ylo = 0x1000
+    assert L.se_project_ws_bytes(C.byref(tb), 64) >= 64 * 1024 * 4
+    # BF16X3 tables without their split dictionary are rejected
+    tb.Ylo = None
+    blk = (B.se_block * 1)(B.se_block(0, 0, 0, 2, 2, 4, 4, 0))
+    fake = C.c_void_p(0x1000)
+    r = L.se_extrapolate_batch(C.byref(tb), fake, 1, 64, 64, blk, 1, B.se_params(0.5, 10, 0),
+                               None, None, None, 0, fake, 1 << 30, None)
+    assert r == B.SE_EINVAL

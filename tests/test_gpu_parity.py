@@ -14,7 +14,7 @@ import oracle
 from paper_2204_14194_amd import binding as B
 from paper_2204_14194_amd import synth
 
-from helpers import classes_of, compare_selections, min_margin, oracle_blocks
+from helpers import classes_of, compare_selections, min_margin, oracle_blocks, oracle_check
 
 pytestmark = pytest.mark.gpu
 
@@ -54,28 +54,14 @@ def run_batch(t, images, blocks, gamma, iters, plain=False):
 
 
 def check_against_oracle(images, blocks, phi, M, N, rho_hat, gamma, iters, sel, coef, g, out,
-                         sample=None, tol=TOL_FP32):
-    cls = classes_of(phi)
-    idx = list(range(len(blocks))) if sample is None else list(sample)
-    ref = oracle_blocks(images, blocks, phi, M, N, rho_hat, gamma, iters, sample=idx)
-    worst, margin = 0.0, np.inf
-    for i, (res, gref) in zip(idx, ref):
-        b = blocks[i]
-        n = b.lh * b.lw
-        assert compare_selections(sel[i], res.sel, cls), f"block {i}: selections differ"
-        err = np.abs(g[i, :n].astype(np.float64) - gref).max()
-        worst = max(worst, err)
-        margin = min(margin, min_margin(res))
-        # the pasted pixels are the rounded model (round half to even), except
-        # where the oracle's value sits within the tolerance of a .5 boundary
-        q_ref = np.clip(np.rint(gref), 0, 255)
-        near = np.abs(np.abs(gref - np.floor(gref)) - 0.5) < tol
-        y, x = b.y0 + b.ly, b.x0 + b.lx
-        got = out[b.img, y:y + b.lh, x:x + b.lw].reshape(-1).astype(np.float64)
-        ok = (got == q_ref) | near
-        assert ok.all(), f"block {i}: pasted pixels differ from the rounded model"
-    assert worst <= tol, f"max |g - g_oracle| = {worst}"
-    return worst, margin
+                         sample=None, tol=TOL_FP32, require_identical=True):
+    """Oracle comparison (see helpers.oracle_check).  With require_identical the
+    selections must equal the oracle's on every compared block."""
+    st = oracle_check(images, blocks, phi, M, N, rho_hat, gamma, iters, sel, g, out,
+                      sample=sample, tol=tol)
+    if require_identical:
+        assert st["agree"] == st["n"], f"selections differ on {st['n'] - st['agree']} blocks"
+    return st["worst"], st["margin"]
 
 
 # ---------------------------------------------------------------------------
@@ -231,3 +217,81 @@ def test_cfg0_bench_scale_sampled():
         y, x = b.y0 + b.ly, b.x0 + b.lx
         q = np.clip(np.rint(g[i, :64]), 0, 255).reshape(8, 8)
         np.testing.assert_array_equal(out[b.img, y:y + 8, x:x + 8], q)
+
+
+@pytest.mark.parametrize("M,N,K,nimg", [(5, 7, 37, 1), (32, 32, 2048, 19), (20, 20, 700, 3)])
+def test_project_matches_oracle(M, N, K, nimg):
+    """se_project alone: R[b][k] = D_k sum_p phi_k w s_b (eq. 12), padded
+    columns zero; odd area sizes take the unvectorised loads."""
+    say(f"project M={M} N={N} K={K} images={nimg}")
+    phi = synth.round_to_f32(synth.gaussian_atoms(M, N, K, seed=K))
+    H, W = 3 * M + 1, 3 * N + 2
+    imgs = np.stack([synth.synth_image(H, W, seed=s) for s in range(nimg)])
+    lh, lw = max(1, M // 3), max(1, N // 3)
+    blocks = [synth.Block(i, y, x, (M - lh) // 2, (N - lw) // 2, lh, lw)
+              for i in range(nimg) for (y, x) in ((0, 0), (M, N), (2 * M, 2 * N))]
+    t, w_d, lost = shared_tables(imgs, blocks, upload_phi(phi), M, N, 0.8)
+    img_d = torch.from_numpy(imgs).to(dev())
+    db = B.DeviceBlocks(t, img_d, blocks)
+    ld = B.table_ld(K)
+    R = torch.full((len(blocks), ld), float("nan"), dtype=torch.float32, device=dev())
+    ws = torch.empty(B.project_ws_bytes(t, len(blocks)), dtype=torch.uint8, device=dev())
+    B.project(t, img_d, db, R, ws)
+    torch.cuda.synchronize()
+    Rh = R.cpu().numpy().astype(np.float64)
+    assert np.all(Rh[:, K:] == 0.0)
+    w = w_d.cpu().numpy().astype(np.float64)
+    C_ref, D_ref = oracle.table_generation(phi, w)
+    for i, b in enumerate(blocks):
+        s, _ = oracle.area_signal(imgs[b.img], lost[b.img], b.y0, b.x0, M, N)
+        ref = D_ref * (phi @ (w * s))
+        scale = np.abs(ref).max()
+        assert np.abs(Rh[i, :K] - ref).max() <= 1e-5 * scale, f"block {i}"
+
+
+# ---------------------------------------------------------------------------
+# precision path: split hi/lo BF16 products on the matrix cores
+# ---------------------------------------------------------------------------
+TOL_BF16X3 = 1e-2
+
+
+def test_gram_bf16x3_matches_oracle():
+    M = N = 32
+    say("weighted_gram BF16X3, K=2048 DCT u WHT")
+    phi = synth.round_to_f32(synth.dictionary(M, N, ("dct", "wht")))
+    sup = np.ones((M, N), bool)
+    sup[12:20, 12:20] = False
+    w_ref = oracle.area_weights(M, N, 0.8, sup)
+    w_d = torch.from_numpy(w_ref.astype(np.float32)).to(dev())
+    t = B.weighted_gram(upload_phi(phi), w_d, M, N, B.SE_BF16X3)
+    torch.cuda.synchronize()
+    assert int(t.info.cpu()[0]) == 1                     # FP64 diagonal on this path
+    G = t.G.cpu().numpy()[:, :2048].astype(np.float64)
+    C_ref, D_ref = oracle.table_generation(phi, w_ref.astype(np.float32).astype(np.float64))
+    G_ref = D_ref[:, None] * C_ref * D_ref[None, :]
+    err = np.abs(G - G_ref).max()
+    print(f"BF16X3 Gram max |dG| = {err:.3g}")
+    assert err < 2e-4
+    np.testing.assert_array_equal(G, G.T)
+
+
+@pytest.mark.parametrize("precision", [B.SE_FP32, B.SE_BF16X3])
+def test_cfg3_precision_parity(precision):
+    """2048x2048 image, 1024 64x64 areas with 16x16 losses, K=8192 (DCT 64^2 u
+    WHT 64^2), I=300: a sample of blocks against the FP64 oracle.  At this size
+    FP32 rounding can reorder atoms whose scores agree to ~1e-5, so a
+    differing selection is accepted only inside the near-tie window and the
+    model is then checked along the device's own selections; the count of
+    identical sequences and the smallest oracle tie margin are reported."""
+    name = "FP32" if precision == B.SE_FP32 else "BF16X3"
+    d = synth.cfg3_inputs(1)
+    say(f"cfg3 {name}: 1024 blocks, K=8192, I=300")
+    phi = synth.round_to_f32(d["phi"])
+    t, _, _ = shared_tables(d["images"], d["blocks"], upload_phi(phi), 64, 64, 0.8, precision)
+    sel, coef, g, out = run_batch(t, d["images"], d["blocks"], 0.5, 300)
+    sample = [0, 37, 200, 500, 800, 1023]
+    tol = TOL_FP32 if precision == B.SE_FP32 else TOL_BF16X3
+    st = oracle_check(d["images"], d["blocks"], phi, 64, 64, 0.8, 0.5, 300, sel, g, out,
+                      sample=sample, tol=tol)
+    print(f"cfg3 {name}: identical selections {st['agree']}/{st['n']}, "
+          f"max|dg|={st['worst']:.3g}, min tie margin={st['margin']:.3g}")

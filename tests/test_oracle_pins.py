@@ -74,6 +74,28 @@ def test_fase_equals_se_cfg0(block):
     np.testing.assert_allclose(f.g, a.g, rtol=0, atol=1e-9)
 
 
+def test_forced_selection_reproduces_free_run_and_tracks_scores():
+    phi, s, w = _rng_case(6, 6, 40, seed=15)
+    C, D = oracle.table_generation(phi, w)
+    a = oracle.se_original(s, w, phi, 0.5, 20)
+    b = oracle.se_original(s, w, phi, 0.5, 20, forced=a.sel)
+    np.testing.assert_array_equal(a.coef, b.coef)
+    np.testing.assert_array_equal(a.g, b.g)
+    np.testing.assert_array_equal(b.picked, b.best)
+    f = oracle.fase(s, w, phi, C, D, 0.5, 20, forced=a.sel)
+    np.testing.assert_allclose(f.g, a.g, atol=1e-9)
+    # a different choice at one iteration: the picked score is below the best,
+    # and the run continues from that choice (Algorithm 1 and 3 agree)
+    alt = a.sel.copy()
+    alt[3] = (alt[3] + 1) % 40
+    c1 = oracle.se_original(s, w, phi, 0.5, 20, forced=alt)
+    c3 = oracle.fase(s, w, phi, C, D, 0.5, 20, forced=alt)
+    assert c1.picked[3] < c1.best[3]
+    np.testing.assert_array_equal(c1.sel, alt)
+    np.testing.assert_allclose(c3.g, c1.g, atol=1e-9)
+    np.testing.assert_allclose(c3.picked, c1.picked, rtol=1e-9)
+
+
 def test_fase_recursion_equals_explicit_projection():
     phi, s, w = _rng_case(6, 6, 50, seed=3)
     C, D = oracle.table_generation(phi, w)
