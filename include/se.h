@@ -269,6 +269,43 @@ se_status se_extrapolate_plain(const se_tables* t, uint8_t* images,
                                float* g_loss, int32_t g_loss_ld, void* ws,
                                size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Model generation when every block has its own weighting function         */
+/* ------------------------------------------------------------------------ */
+
+/* Conceals n_blk blocks whose weights differ (other losses or the image
+ * border inside their areas), so no table can be shared: the paper notes
+ * that C and D then have to be adapted to each weighting function.  Only
+ * the table rows the loop reads are formed: per iteration, the rows
+ * C_b[u_b][:] of every still-iterating block are one matrix product of the
+ * dictionary with the vectors w_b * phi_{u_b} (FP32 MFMA), as are the
+ * per-block diagonals C_b[k][k] (giving D_b) and the initial projections.
+ * Selection, coefficients, model update and paste are those of
+ * se_extrapolate_batch, so both calls give the same result for the same
+ * weights (up to FP32 rounding).
+ *   b       : dictionary (device phi)
+ *   w       : device float32 n_blk x (M*N), block i's weights in row i (as
+ *             written by se_area_weights)
+ *   iters   : host, optional per-block iteration counts (NULL: prm.iters
+ *             for every block)
+ *   sel, coef : optional device outputs of n_blk rows with stride
+ *             max(iteration counts); entries past a block's own count are
+ *             left unchanged
+ *   g_loss  : optional, as for se_extrapolate_batch
+ *   ws      : se_extrapolate_ondemand_ws_bytes(b, n_blk, max_loss) bytes,
+ *             max_loss = the largest lh*lw of the blocks
+ * Errors as for se_extrapolate_batch; the loss size is not limited. */
+size_t se_extrapolate_ondemand_ws_bytes(const se_basis* b, int32_t n_blk,
+                                        int32_t max_loss);
+se_status se_extrapolate_ondemand(const se_basis* b, const float* w,
+                                  uint8_t* images, int32_t n_img, int32_t H,
+                                  int32_t W, const se_block* blocks,
+                                  int32_t n_blk, se_params prm,
+                                  const int32_t* iters, int32_t* sel,
+                                  float* coef, float* g_loss,
+                                  int32_t g_loss_ld, void* ws, size_t ws_bytes,
+                                  void* stream);
+
 #ifdef __cplusplus
 }
 #endif

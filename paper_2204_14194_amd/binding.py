@@ -26,7 +26,8 @@ EXPORTED = (
     "se_last_error", "se_version", "se_area_weights_ws_bytes", "se_area_weights",
     "se_weighted_gram_ws_bytes", "se_weighted_gram", "se_extrapolate_batch_ws_bytes",
     "se_extrapolate_batch", "se_extrapolate_plain", "se_blocks_upload", "se_project_ws_bytes",
-    "se_project", "se_iterate", "se_table_ld",
+    "se_project", "se_iterate", "se_table_ld", "se_extrapolate_ondemand_ws_bytes",
+    "se_extrapolate_ondemand",
 )
 
 
@@ -100,6 +101,11 @@ def lib():
     L.se_iterate.restype = i32
     L.se_iterate.argtypes = [C.POINTER(se_tables), vp, i32, vp, i32, i32, i32, vp, i32,
                              se_params, vp, vp, vp, i32, vp]
+    L.se_extrapolate_ondemand_ws_bytes.restype = sz
+    L.se_extrapolate_ondemand_ws_bytes.argtypes = [C.POINTER(se_basis), i32, i32]
+    L.se_extrapolate_ondemand.restype = i32
+    L.se_extrapolate_ondemand.argtypes = [C.POINTER(se_basis), vp, vp, i32, i32, i32, vp, i32,
+                                          se_params, vp, vp, vp, vp, i32, vp, sz, vp]
     _lib = L
     return L
 
@@ -320,3 +326,37 @@ def iterate(t: Tables, R: torch.Tensor, images: torch.Tensor, dblocks: DeviceBlo
     _check(L.se_iterate(C.byref(st), _ptr(R), R.shape[1], _ptr(images), n_img, H, W,
                         _ptr(dblocks.buf), dblocks.n, se_params(float(gamma), int(iters), 0),
                         _ptr(sel), _ptr(coef), _ptr(g_loss), gld, _stream(stream)))
+
+
+def extrapolate_ondemand(phi: torch.Tensor, M: int, N: int, w: torch.Tensor,
+                         images: torch.Tensor, blocks: Sequence, gamma: float, iters,
+                         want_sel=True, want_coef=True, want_g=True, ws=None, stream=None):
+    """se_extrapolate_ondemand: per-block weights ``w`` (n_blk, M*N); ``iters``
+    an int or a per-block sequence.  Returns (sel, coef, g_loss)."""
+    L = lib()
+    _dev_f32(phi, "phi")
+    _dev_f32(w, "w")
+    n_img, H, W = images.shape
+    n = len(blocks)
+    dev = images.device
+    per = None
+    if isinstance(iters, int):
+        imax = iters
+    else:
+        per = (C.c_int32 * max(n, 1))(*[int(v) for v in iters])
+        imax = max([int(v) for v in iters] + [0])
+    sel = torch.empty((n, imax), dtype=torch.int32, device=dev) if want_sel else None
+    coef = torch.empty((n, imax), dtype=torch.float32, device=dev) if want_coef else None
+    gld = max([b.lh * b.lw for b in blocks] + [1])
+    g = torch.zeros((n, gld), dtype=torch.float32, device=dev) if want_g else None
+    bas = se_basis(M, N, phi.shape[0], phi.data_ptr())
+    nb = L.se_extrapolate_ondemand_ws_bytes(C.byref(bas), n, gld)
+    if ws is None:
+        ws = _workspace(nb, dev)
+    elif ws.numel() < nb:
+        raise ValueError(f"workspace of {ws.numel()} bytes < {nb}")
+    prm = se_params(float(gamma), int(imax), 0)
+    _check(L.se_extrapolate_ondemand(C.byref(bas), _ptr(w), _ptr(images), n_img, H, W,
+                                     blocks_array(blocks), n, prm, per, _ptr(sel), _ptr(coef),
+                                     _ptr(g), gld, _ptr(ws), ws.numel(), _stream(stream)))
+    return sel, coef, g

@@ -5,6 +5,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <numeric>
 #include <vector>
 
 #include "se_internal.h"
@@ -359,6 +361,116 @@ static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, in
     if ((st = launch_greedy(ga, 1, s))) return st;
   }
   return SE_OK;
+}
+
+// ---------------------------------------------------------------------------
+static inline int round1024(int v) { return (v + 1023) & ~1023; }
+
+size_t se_extrapolate_ondemand_ws_bytes(const se_basis* b, int32_t n_blk, int32_t max_loss) {
+  if (!b || b->K < 1 || b->M < 1 || b->N < 1 || n_blk < 0 || max_loss < 0) return 0;
+  const size_t K = (size_t)b->K, P = (size_t)b->M * b->N, n = (size_t)n_blk;
+  const size_t ld = (size_t)round1024(b->K), ldV = (size_t)round4((int)P);
+  Carver cv(nullptr);
+  cv.take<se_block>(n);
+  cv.take<int32_t>(n);
+  cv.take<float>(K * P);
+  cv.take<float>(n * ldV);
+  cv.take<float>(n * ldV);
+  cv.take<float>(n * ld);
+  cv.take<float>(n * ld);
+  cv.take<float>(n * ld);
+  cv.take<float>(2 * n);
+  cv.take<float>(2 * n * (size_t)(max_loss > 0 ? max_loss : 1));
+  return cv.off + 256;
+}
+
+se_status se_extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* images,
+                                  int32_t n_img, int32_t H, int32_t W, const se_block* blocks,
+                                  int32_t n_blk, se_params prm, const int32_t* iters,
+                                  int32_t* sel, float* coef, float* g_loss, int32_t g_loss_ld,
+                                  void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  if (!b || !b->phi || !w || !images) return fail(SE_EINVAL, "NULL argument");
+  if (b->M < 1 || b->N < 1 || b->K < 1) return fail(SE_EINVAL, "bad basis shape");
+  if (b->K > 32768) return fail(SE_EINVAL, "K=%d exceeds 32768", b->K);
+  if ((long long)b->M * b->N > (1 << 24)) return fail(SE_EINVAL, "area too large");
+  if (n_img < 1 || H < 1 || W < 1) return fail(SE_EINVAL, "bad image batch");
+  if (n_blk < 0 || (n_blk > 0 && !blocks)) return fail(SE_EINVAL, "bad block list");
+  se_status st;
+  if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
+  int max_loss = 1, iters_max = 0;
+  std::vector<int> it((size_t)n_blk);
+  for (int i = 0; i < n_blk; ++i) {
+    const se_block& bl = blocks[i];
+    if (bl.img < 0 || bl.img >= n_img) return fail(SE_EINVAL, "block %d: img out of range", i);
+    if (bl.lh < 1 || bl.lw < 1 || bl.ly < 0 || bl.lx < 0 || bl.ly + bl.lh > b->M ||
+        bl.lx + bl.lw > b->N)
+      return fail(SE_EINVAL, "block %d: loss rectangle not inside the %dx%d area", i, b->M, b->N);
+    max_loss = std::max(max_loss, bl.lh * bl.lw);
+    it[(size_t)i] = iters ? iters[i] : prm.iters;
+    if (it[(size_t)i] < 0) return fail(SE_EINVAL, "block %d: negative iteration count", i);
+    iters_max = std::max(iters_max, it[(size_t)i]);
+  }
+  if (n_blk == 0) return SE_OK;
+  const size_t need = se_extrapolate_ondemand_ws_bytes(b, n_blk, max_loss);
+  if (!ws || ws_bytes < need) return fail(SE_ENOMEM, "workspace too small: need %zu bytes", need);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // decreasing iteration counts: the blocks still iterating form a prefix
+  std::vector<int32_t> order((size_t)n_blk);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return it[(size_t)x] > it[(size_t)y]; });
+  std::vector<se_block> sorted((size_t)n_blk);
+  for (int i = 0; i < n_blk; ++i) sorted[(size_t)i] = blocks[order[(size_t)i]];
+  std::vector<int> active((size_t)std::max(iters_max, 1), 0);
+  for (int nu = 0; nu < iters_max; ++nu) {
+    int c = 0;
+    while (c < n_blk && it[(size_t)order[(size_t)c]] > nu) ++c;
+    active[(size_t)nu] = c;
+  }
+  const int K = b->K, P = b->M * b->N, n = n_blk;
+  const int ld = round1024(K), ldV = round4(P);
+  Carver cv(ws);
+  OnDemandPlan pl;
+  se_block* dblk = cv.take<se_block>((size_t)n);
+  int32_t* dorig = cv.take<int32_t>((size_t)n);
+  pl.phi2 = cv.take<float>((size_t)K * P);
+  pl.X = cv.take<float>((size_t)n * ldV);
+  pl.V = cv.take<float>((size_t)n * ldV);
+  pl.R = cv.take<float>((size_t)n * ld);
+  pl.D = cv.take<float>((size_t)n * ld);
+  pl.rows = cv.take<float>((size_t)n * ld);
+  pl.st = cv.take<float>((size_t)2 * n);
+  pl.g = cv.take<float>((size_t)2 * n * max_loss);
+  pl.gc = pl.g + (size_t)n * max_loss;
+  hipError_t e = hipMemcpyAsync(dblk, sorted.data(), sorted.size() * sizeof(se_block),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dorig, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                       s);
+  if (e != hipSuccess) return fail(SE_EHIP, "descriptor upload: %s", hipGetErrorString(e));
+  pl.K = K;
+  pl.M = b->M;
+  pl.N = b->N;
+  pl.n_blk = n;
+  pl.phi = b->phi;
+  pl.w = w;
+  pl.images = images;
+  pl.H = H;
+  pl.W = W;
+  pl.blk = dblk;
+  pl.orig = dorig;
+  pl.active = active.data();
+  pl.iters_max = iters_max;
+  pl.gamma = prm.gamma;
+  pl.ldV = ldV;
+  pl.ld = ld;
+  pl.ldg = max_loss;
+  pl.sel = sel;
+  pl.coef = coef;
+  pl.g_loss = g_loss;
+  pl.g_loss_ld = g_loss ? g_loss_ld : 0;
+  return ondemand_run(pl, s);
 }
 
 se_status se_extrapolate_batch(const se_tables* t, uint8_t* images, int32_t n_img, int32_t H,

@@ -26,50 +26,11 @@
 // exact ties, the lowest index k.  Workgroups of several waves combine the
 // wave winners through LDS.
 #include "se_internal.h"
+#include "argmax.h"
 
 namespace sefase {
 
 constexpr int kQPL = 4;   // loss pixels per lane (the loss may hold <= 4 T pixels)
-
-// DPP controls (gfx9 encoding)
-constexpr int kQuadXor1 = 0xB1;       // quad_perm [1,0,3,2]
-constexpr int kQuadXor2 = 0x4E;       // quad_perm [2,3,0,1]
-constexpr int kRowHalfMirror = 0x141;
-constexpr int kRowMirror = 0x140;
-constexpr int kRowBcast15 = 0x142;
-constexpr int kRowBcast31 = 0x143;
-
-template <int CTRL, int ROWMASK>
-__device__ inline void key_step(uint32_t& hi, uint32_t& lo) {
-  const uint32_t ohi = (uint32_t)__builtin_amdgcn_update_dpp((int)hi, (int)hi, CTRL, ROWMASK, 0xF, false);
-  const uint32_t olo = (uint32_t)__builtin_amdgcn_update_dpp((int)lo, (int)lo, CTRL, ROWMASK, 0xF, false);
-  const uint64_t a = ((uint64_t)ohi << 32) | olo;
-  const uint64_t b = ((uint64_t)hi << 32) | lo;
-  if (a > b) {
-    hi = ohi;
-    lo = olo;
-  }
-}
-
-// Maximum 64-bit key over the wave, returned wave-uniform.
-__device__ inline uint64_t wave_max_key(uint32_t hi, uint32_t lo) {
-  key_step<kQuadXor1, 0xF>(hi, lo);
-  key_step<kQuadXor2, 0xF>(hi, lo);
-  key_step<kRowHalfMirror, 0xF>(hi, lo);
-  key_step<kRowMirror, 0xF>(hi, lo);          // every row of 16 lanes now uniform
-  key_step<kRowBcast15, 0xA>(hi, lo);         // rows 1, 3 take rows 0, 2
-  key_step<kRowBcast31, 0xC>(hi, lo);         // rows 2, 3 take row 1 -> lane 63 holds the max
-  const uint32_t h = (uint32_t)__builtin_amdgcn_readlane((int)hi, 63);
-  const uint32_t l = (uint32_t)__builtin_amdgcn_readlane((int)lo, 63);
-  return ((uint64_t)h << 32) | l;
-}
-
-__device__ inline uint64_t make_key(float v, int idx) {
-  const uint32_t bits = __float_as_uint(v);
-  const uint32_t hi = bits & 0x7FFFFFFFu;
-  const uint32_t lo = ((uint32_t)(0xFFFF - idx) << 16) | ((bits >> 31) << 15);
-  return ((uint64_t)hi << 32) | lo;
-}
 
 // ONE: the launch conceals the single block a.blk0 (plain per-block form); a
 // separate instantiation so profiles keep the two forms apart.
@@ -142,13 +103,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy(GreedyArgs a) {
       par ^= 1;
     }
     // ---- decode the winner (wave-uniform) -------------------------------
-    const uint32_t khi = (uint32_t)(key >> 32), klo = (uint32_t)key;
-    int u = 0xFFFF - (int)(klo >> 16);
-    float rv = __uint_as_float(khi | ((klo & 0x8000u) << 16));
-    if (khi == 0u || u < 0 || u >= K) {   // every score is zero: no-op on atom 0
-      u = 0;
-      rv = 0.0f;
-    }
+    int u;
+    float rv;
+    decode_key(key, K, u, rv);
     const float tc = gamma * rv;              // coefficient of the unit-norm atom
     const float c = tc * a.D[u];              // eq. 19
     if (t == 0) {

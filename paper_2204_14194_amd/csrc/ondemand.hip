@@ -1,0 +1,251 @@
+// Fast SE when every block has its own weighting function (eq. 4 with a
+// different support per block: other losses or the image border inside the
+// area), so no table C can be shared (the paper notes C and D must then be
+// adapted to each weighting function).  Instead of building a whole K x K
+// table per block, only the rows that the iteration loop actually reads are
+// formed, on demand:
+//   C_b[u][k] = sum_p phi_k[p] w_b[p] phi_u[p]        (eq. 16, row u)
+// For a group of blocks sharing the dictionary that advance one iteration at
+// a time, the rows of all blocks are one matrix product on the matrix cores:
+//   rows = Phi V^T,  V[b][p] = w_b[p] phi_{u_b}[p].
+// Likewise C_b[k][k] = sum_p phi_k[p]^2 w_b[p] (the per-block D_b, eq. 17)
+// and the initial projections R_b^(0) = Phi (w_b s_b) (eq. 12) are products
+// with the same dictionary.
+//
+// Per iteration a workgroup per block applies the previous update (eq. 20,
+// in units of D_b), selects the next atom (eq. 18), records c (eq. 19),
+// updates the model over the loss (eq. 9) and writes its V row.  All state
+// lives in device memory between the launches.  Blocks are processed in
+// decreasing order of their iteration counts, so the blocks still running at
+// iteration nu form a prefix and each launch covers only that prefix.
+#include "argmax.h"
+#include "se_internal.h"
+
+namespace sefase {
+
+constexpr int kOdThreads = 256;
+
+// X[b][p] = w_b[p] s_b[p] (the weighted signal, eq. 12); V rows reuse the
+// same layout.
+__global__ void k_od_gather(const uint8_t* __restrict__ images, int H, int W,
+                            const DevBlock* __restrict__ blk, int n_blk, int M, int N,
+                            const float* __restrict__ w, const int32_t* __restrict__ orig,
+                            float* __restrict__ X, int ldX) {
+  const int b = blockIdx.y;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int P = M * N;
+  if (b >= n_blk || p >= P) return;
+  const DevBlock d = blk[b];
+  const int m = p / N, n = p - m * N;
+  const int y = d.y0 + m, x = d.x0 + n;
+  float v = 0.0f;
+  if (y >= 0 && y < H && x >= 0 && x < W)
+    v = w[(size_t)orig[b] * P + p] * (float)images[(size_t)d.img * H * W + (size_t)y * W + x];
+  X[(size_t)b * ldX + p] = v;
+}
+
+// V[b][p] = w_b[p] (the weights as rows of the diagonal product)
+__global__ void k_od_gather_w(const float* __restrict__ w, const int32_t* __restrict__ orig,
+                              int n_blk, int P, float* __restrict__ V, int ldV) {
+  const int b = blockIdx.y;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_blk || p >= P) return;
+  V[(size_t)b * ldV + p] = w[(size_t)orig[b] * P + p];
+}
+
+__global__ void k_fill0(float* __restrict__ a, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0.0f;
+}
+
+__global__ void k_square(const float* __restrict__ phi, size_t n, float* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = phi[i] * phi[i];
+}
+
+// D_b = 1/sqrt(C_b[k][k]) (0 for a non-positive diagonal); R~ = D_b R^(0).
+// Dd holds the diagonal on entry and D_b on exit.
+__global__ void k_od_init(float* __restrict__ Dd, float* __restrict__ R, int n_blk, int ld) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)n_blk * ld) return;
+  const float dd = Dd[i];
+  const float D = dd > 0.0f ? 1.0f / sqrtf(dd) : 0.0f;
+  Dd[i] = D;
+  R[i] = D * R[i];
+}
+
+struct OdArgs {
+  float* R;            // n_blk x ld, R~ = D_b R (units of D_b)
+  const float* D;      // n_blk x ld
+  const float* rows;   // n_blk x ld, C_b[u_prev][k] from the last product
+  float* V;            // n_blk x ldV
+  int ld, ldV;
+  const float* phi;    // K x P
+  const float* w;      // original-order blocks x P
+  const DevBlock* blk; // sorted by decreasing iteration count
+  const int32_t* orig; // sorted position -> caller's block index
+  float* st;           // n_blk x 2: t_prev, D_u_prev (per block)
+  float* g;            // n_blk x ldg model over the loss (sorted order)
+  float* gc;           // Kahan compensation
+  int ldg;
+  int K, M, N;
+  int nu, iters_max;
+  float gamma;
+  int32_t* sel;        // optional, caller order, stride iters_max
+  float* coef;         // optional
+};
+
+__global__ __launch_bounds__(kOdThreads) void k_od_step(OdArgs a) {
+  const int b = blockIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int K = a.K, P = a.M * a.N;
+  float* R = a.R + (size_t)b * a.ld;
+  const float* D = a.D + (size_t)b * a.ld;
+  const float* rows = a.rows + (size_t)b * a.ld;
+  const bool upd = a.nu > 0;
+  float sc = 0.0f;
+  if (upd) sc = a.st[2 * b] * a.st[2 * b + 1];   // gamma R~_u D_u: the eq. 20 factor
+  // update with the previous row, then find this lane's first strict maximum
+  float bv = 0.0f;
+  int bi = 0x7fffffff;
+  const int nj = a.ld / (4 * kOdThreads);
+  for (int j = 0; j < nj; ++j) {
+    const int k0 = 4 * (j * kOdThreads + t);
+    float4 r = *reinterpret_cast<const float4*>(R + k0);
+    if (upd) {
+      const float4 d = *reinterpret_cast<const float4*>(D + k0);
+      const float4 c = *reinterpret_cast<const float4*>(rows + k0);
+      r.x = fmaf(-sc * d.x, c.x, r.x);
+      r.y = fmaf(-sc * d.y, c.y, r.y);
+      r.z = fmaf(-sc * d.z, c.z, r.z);
+      r.w = fmaf(-sc * d.w, c.w, r.w);
+      *reinterpret_cast<float4*>(R + k0) = r;
+    }
+    if (fabsf(r.x) > fabsf(bv)) { bv = r.x; bi = k0; }
+    if (fabsf(r.y) > fabsf(bv)) { bv = r.y; bi = k0 + 1; }
+    if (fabsf(r.z) > fabsf(bv)) { bv = r.z; bi = k0 + 2; }
+    if (fabsf(r.w) > fabsf(bv)) { bv = r.w; bi = k0 + 3; }
+  }
+  const uint64_t mine = make_key(bv, bi == 0x7fffffff ? 0 : bi);
+  uint64_t key = wave_max_key((uint32_t)(mine >> 32), (uint32_t)mine);
+  __shared__ uint64_t s_key[kOdThreads / 64];
+  if (lane == 0) s_key[wave] = key;
+  __syncthreads();
+  key = s_key[0];
+#pragma unroll
+  for (int i = 1; i < kOdThreads / 64; ++i) key = s_key[i] > key ? s_key[i] : key;
+  int u;
+  float rv;
+  decode_key(key, K, u, rv);
+  const float Du = D[u];
+  const float tc = a.gamma * rv;          // coefficient of the unit-norm atom
+  const float c = tc * Du;                // eq. 19
+  const int ob = a.orig[b];
+  if (t == 0) {
+    a.st[2 * b] = tc;
+    a.st[2 * b + 1] = Du;
+    if (a.sel) a.sel[(size_t)ob * a.iters_max + a.nu] = u;
+    if (a.coef) a.coef[(size_t)ob * a.iters_max + a.nu] = c;
+  }
+  // model over the loss (eq. 9), compensated
+  const DevBlock d = a.blk[b];
+  const float* prow = a.phi + (size_t)u * P;
+  const int nloss = d.lh * d.lw;
+  for (int q = t; q < nloss; q += kOdThreads) {
+    const int my = q / d.lw, mx = q - my * d.lw;
+    const float pv = prow[(d.ly + my) * a.N + d.lx + mx];
+    float* gp = a.g + (size_t)b * a.ldg + q;
+    float* cp = a.gc + (size_t)b * a.ldg + q;
+    const float y = fmaf(c, pv, -*cp);
+    const float s = *gp + y;
+    *cp = (s - *gp) - y;
+    *gp = s;
+  }
+  // V row for the next product: w_b phi_u
+  const float* wb = a.w + (size_t)ob * P;
+  float* V = a.V + (size_t)b * a.ldV;
+  for (int p = t; p < P; p += kOdThreads) V[p] = wb[p] * prow[p];
+}
+
+// paste the model into the image and (optionally) report it
+__global__ void k_od_finish(const DevBlock* __restrict__ blk, const int32_t* __restrict__ orig,
+                            const float* __restrict__ g, int ldg, uint8_t* __restrict__ images,
+                            int H, int W, float* __restrict__ g_loss, int g_loss_ld) {
+  const int b = blockIdx.x;
+  const DevBlock d = blk[b];
+  const int nloss = d.lh * d.lw;
+  const int ob = orig[b];
+  for (int q = threadIdx.x; q < nloss; q += blockDim.x) {
+    const float v = g[(size_t)b * ldg + q];
+    if (g_loss && q < g_loss_ld) g_loss[(size_t)ob * g_loss_ld + q] = v;
+    const int my = q / d.lw, mx = q - my * d.lw;
+    const int y = d.y0 + d.ly + my, x = d.x0 + d.lx + mx;
+    if (y >= 0 && y < H && x >= 0 && x < W)
+      images[(size_t)d.img * H * W + (size_t)y * W + x] =
+          (uint8_t)fminf(fmaxf(rintf(v), 0.0f), 255.0f);
+  }
+}
+
+// ---------------------------------------------------------------------------
+se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s) {
+  se_status st;
+  const int K = pl.K, P = pl.M * pl.N, n = pl.n_blk;
+  // model accumulators start at 0 (g and gc are adjacent)
+  hipLaunchKernelGGL(k_fill0, dim3((unsigned)(((size_t)2 * n * pl.ldg + 255) / 256)), dim3(256), 0,
+                     s, pl.g, (size_t)2 * n * pl.ldg);
+  if ((st = check_launch("fill0"))) return st;
+  // dictionary squared (for the per-block diagonal)
+  hipLaunchKernelGGL(k_square, dim3((unsigned)(((size_t)K * P + 255) / 256)), dim3(256), 0, s,
+                     pl.phi, (size_t)K * P, pl.phi2);
+  if ((st = check_launch("square"))) return st;
+  // weighted signal and weights as row blocks of the products
+  hipLaunchKernelGGL(k_od_gather, dim3((P + 255) / 256, n), dim3(256), 0, s, pl.images, pl.H,
+                     pl.W, pl.blk, n, pl.M, pl.N, pl.w, pl.orig, pl.X, pl.ldV);
+  if ((st = check_launch("od_gather"))) return st;
+  hipLaunchKernelGGL(k_od_gather_w, dim3((P + 255) / 256, n), dim3(256), 0, s, pl.w, pl.orig, n,
+                     P, pl.V, pl.ldV);
+  if ((st = check_launch("od_gather_w"))) return st;
+  if ((st = gemm_project_f32(pl.phi2, P, K, pl.V, pl.ldV, n, P, pl.D, pl.ld, 0, s))) return st;
+  if ((st = gemm_project_f32(pl.phi, P, K, pl.X, pl.ldV, n, P, pl.R, pl.ld, 0, s))) return st;
+  hipLaunchKernelGGL(k_od_init, dim3((unsigned)(((size_t)n * pl.ld + 255) / 256)), dim3(256), 0,
+                     s, pl.D, pl.R, n, pl.ld);
+  if ((st = check_launch("od_init"))) return st;
+  OdArgs a;
+  a.R = pl.R;
+  a.D = pl.D;
+  a.rows = pl.rows;
+  a.V = pl.V;
+  a.ld = pl.ld;
+  a.ldV = pl.ldV;
+  a.phi = pl.phi;
+  a.w = pl.w;
+  a.blk = pl.blk;
+  a.orig = pl.orig;
+  a.st = pl.st;
+  a.g = pl.g;
+  a.gc = pl.gc;
+  a.ldg = pl.ldg;
+  a.K = K;
+  a.M = pl.M;
+  a.N = pl.N;
+  a.iters_max = pl.iters_max;
+  a.gamma = pl.gamma;
+  a.sel = pl.sel;
+  a.coef = pl.coef;
+  for (int nu = 0; nu < pl.iters_max; ++nu) {
+    const int act = pl.active[nu];        // blocks still iterating at nu (a prefix)
+    if (act <= 0) break;
+    a.nu = nu;
+    hipLaunchKernelGGL(k_od_step, dim3(act), dim3(kOdThreads), 0, s, a);
+    if ((st = check_launch("od_step"))) return st;
+    const int nxt = nu + 1 < pl.iters_max ? pl.active[nu + 1] : 0;
+    if (nxt > 0)   // rows C_b[u_b][:] for the blocks that iterate again
+      if ((st = gemm_project_f32(pl.phi, P, K, pl.V, pl.ldV, nxt, P, pl.rows, pl.ld, 0, s)))
+        return st;
+  }
+  hipLaunchKernelGGL(k_od_finish, dim3(n), dim3(256), 0, s, pl.blk, pl.orig, pl.g, pl.ldg,
+                     pl.images, pl.H, pl.W, pl.g_loss, pl.g_loss_ld);
+  return check_launch("od_finish");
+}
+
+}  // namespace sefase

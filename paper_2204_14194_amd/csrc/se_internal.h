@@ -96,6 +96,39 @@ struct GreedyArgs {
   float* g_loss;       // optional
   int g_loss_ld;
 };
+// ondemand.hip -- per-block weights, rows of C_b formed on demand
+struct OnDemandPlan {
+  int K, M, N, n_blk;
+  const float* phi;     // K x P
+  const float* w;       // caller-order blocks x P weights
+  uint8_t* images;
+  int H, W;
+  const DevBlock* blk;  // n_blk, sorted by decreasing iteration count
+  const int32_t* orig;  // sorted position -> caller index
+  const int* active;    // host: active[nu] = blocks with more than nu iterations
+  int iters_max;
+  float gamma;
+  // device workspace
+  float* phi2;          // K x P
+  float* X;             // n_blk x ldV
+  float* V;             // n_blk x ldV
+  int ldV;
+  float* R;             // n_blk x ld
+  float* D;             // n_blk x ld
+  float* rows;          // n_blk x ld
+  int ld;               // multiple of 1024
+  float* st;            // n_blk x 2
+  float* g;             // n_blk x ldg, followed by gc (n_blk x ldg)
+  float* gc;
+  int ldg;
+  // outputs (optional)
+  int32_t* sel;
+  float* coef;
+  float* g_loss;
+  int g_loss_ld;
+};
+se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s);
+
 int greedy_waves_for(int K);   // 0 if K is too large
 int greedy_row_len(int K);     // padded row length (table row stride minimum)
 se_status launch_greedy(const GreedyArgs& a, int grid, hipStream_t s);

@@ -251,3 +251,78 @@ def cfg3_inputs(n_img: int = 1, seed0: int = 300):
     phi = dictionary(64, 64, ("dct", "wht"))
     return dict(images=imgs, blocks=blocks, phi=phi, M=64, N=64,
                 rho_hat=0.8, gamma=0.5, iters=300)
+
+
+def clustered_layout(H: int, W: int, n_blocks: int, seed: int, img: int = 0,
+                     n_centres=(3, 6), blob_sigma: float = 0.08,
+                     burst_frac: float = 0.3, burst_len=(4, 16)):
+    """Losses of a damaged frame: 8x8 and 16x16 lost blocks on the 8-pixel grid,
+    partly clustered (Gaussian blobs around 3-6 seeded centres, sigma given as
+    a fraction of the frame size) and partly in bursts (runs of 4-16 adjacent
+    grid cells along a raster row).  Losses never overlap.  Each loss gets an
+    extrapolation area centred on it: 8x8 -> 24 or 32, 16x16 -> 32 or 48
+    (seeded).  Returns a list of Block (area coordinates may leave the
+    frame)."""
+    rng = np.random.default_rng(seed)
+    gh, gw = H // 8, W // 8
+    occ = np.zeros((gh, gw), dtype=bool)
+    out: List[Block] = []
+    centres = rng.uniform(0.1, 0.9, size=(int(rng.integers(n_centres[0], n_centres[1] + 1)), 2))
+
+    def place(cy: int, cx: int, size: int) -> bool:
+        c = size // 8
+        if cy < 0 or cx < 0 or cy + c > gh or cx + c > gw or occ[cy:cy + c, cx:cx + c].any():
+            return False
+        occ[cy:cy + c, cx:cx + c] = True
+        if size == 8:
+            area = 24 if rng.random() < 0.5 else 32
+        else:
+            area = 32 if rng.random() < 0.5 else 48
+        off = (area - size) // 2
+        out.append(Block(img, cy * 8 - off, cx * 8 - off, off, off, size, size))
+        return True
+
+    tries = 0
+    while len(out) < n_blocks and tries < 200 * n_blocks:
+        tries += 1
+        size = 16 if rng.random() < 0.4 else 8
+        if rng.random() < burst_frac:
+            cy = int(rng.integers(0, gh))
+            cx = int(rng.integers(0, gw))
+            run = int(rng.integers(burst_len[0], burst_len[1] + 1))
+            for k in range(run):
+                if len(out) >= n_blocks:
+                    break
+                if not place(cy, cx + k * (size // 8), size):
+                    break
+        else:
+            c = centres[int(rng.integers(0, len(centres)))]
+            y = int(rng.normal(c[0], blob_sigma) * gh)
+            x = int(rng.normal(c[1], blob_sigma) * gw)
+            if size == 16:
+                y, x = y - y % 2, x - x % 2
+            place(y, x, size)
+    return out
+
+
+def cfg2_dictionaries():
+    """Dictionary per area size for the uneven workload: DCT u WHT for 32x32
+    (K = 2048), DCT u seeded Gaussian atoms for 24x24 and 48x48 (no Sylvester
+    Walsh-Hadamard exists there), K = 2 * area pixels."""
+    return {24: dictionary(24, 24, ("dct", "gauss"), seed=124, n_gauss=576),
+            32: dictionary(32, 32, ("dct", "wht")),
+            48: dictionary(48, 48, ("dct", "gauss"), seed=148, n_gauss=2304)}
+
+
+def cfg2_inputs(n_img: int = 8, blocks_per_img: int = 500, seed0: int = 200,
+                iter_range=(100, 200)):
+    """8 seeded 1024x1024 frames with clustered/burst losses, 500 blocks each;
+    per-block iteration counts I ~ U{100..200}; rho_hat = 0.8, gamma = 0.5."""
+    imgs = np.stack([synth_image(1024, 1024, seed0 + i) for i in range(n_img)])
+    blocks: List[Block] = []
+    for i in range(n_img):
+        blocks += clustered_layout(1024, 1024, blocks_per_img, seed=seed0 + 1000 + i, img=i)
+    rng = np.random.default_rng(seed0 + 99)
+    iters = rng.integers(iter_range[0], iter_range[1] + 1, size=len(blocks))
+    return dict(images=imgs, blocks=blocks, iters=iters, dicts=cfg2_dictionaries(),
+                rho_hat=0.8, gamma=0.5)

@@ -295,3 +295,80 @@ def test_cfg3_precision_parity(precision):
                       sample=sample, tol=tol)
     print(f"cfg3 {name}: identical selections {st['agree']}/{st['n']}, "
           f"max|dg|={st['worst']:.3g}, min tie margin={st['margin']:.3g}")
+
+
+# ---------------------------------------------------------------------------
+# per-block weights: table rows formed on demand
+# ---------------------------------------------------------------------------
+def run_ondemand(phi32, M, N, images, blocks, gamma, iters):
+    n_img, H, W = images.shape
+    lost = np.stack([synth.lost_mask(H, W, blocks, i) for i in range(n_img)])
+    w = B.area_weights(M, N, 0.8, torch.from_numpy(lost).to(dev()), blocks)
+    img_d = torch.from_numpy(images).to(dev())
+    sel, coef, g = B.extrapolate_ondemand(phi32, M, N, w, img_d, blocks, gamma, iters)
+    torch.cuda.synchronize()
+    return sel.cpu().numpy(), coef.cpu().numpy(), g.cpu().numpy(), img_d.cpu().numpy()
+
+
+def test_ondemand_equals_shared_tables_on_isolated_blocks():
+    """Identical weights for every block: forming rows on demand must give
+    the same result as the shared table (and the oracle)."""
+    d = synth.cfg0_inputs(1)
+    say("on-demand rows vs shared tables: cfg0, 16 isolated blocks, I=100")
+    phi = synth.round_to_f32(d["phi"])
+    phi_d = upload_phi(phi)
+    sel, coef, g, out = run_ondemand(phi_d, 32, 32, d["images"], d["blocks"], 0.5, 100)
+    check_against_oracle(d["images"], d["blocks"], phi, 32, 32, 0.8, 0.5, 100, sel, coef, g, out)
+    t, _, _ = shared_tables(d["images"], d["blocks"], phi_d, 32, 32, 0.8)
+    sel_b, coef_b, g_b, out_b = run_batch(t, d["images"], d["blocks"], 0.5, 100)
+    np.testing.assert_array_equal(sel, sel_b)
+    assert np.abs(g - g_b).max() <= TOL_FP32
+
+
+@pytest.mark.parametrize("area", [24, 32, 48])
+def test_ondemand_clustered_losses(area):
+    """Blocks of the clustered/burst workload (other losses and the frame
+    border inside the areas, so every block has its own weights), one area
+    size per dictionary, per-block iteration counts; a sample against the
+    FP64 oracle."""
+    say(f"on-demand clustered losses: area {area}")
+    d = synth.cfg2_inputs(n_img=1, blocks_per_img=500)
+    blocks = [b for b in d["blocks"] if b.ly * 2 + b.lh == area]
+    iters = [int(v) for v, b in zip(d["iters"], d["blocks"]) if b.ly * 2 + b.lh == area]
+    phi = synth.round_to_f32(d["dicts"][area])
+    # the oracle weights come from every loss of the frame
+    lost = synth.lost_mask(1024, 1024, d["blocks"])[None]
+    img = d["images"][:1]
+    w = B.area_weights(area, area, 0.8, torch.from_numpy(lost).to(dev()), blocks)
+    img_d = torch.from_numpy(img).to(dev())
+    sel, coef, g = B.extrapolate_ondemand(upload_phi(phi), area, area, w, img_d, blocks, 0.5,
+                                          iters)
+    torch.cuda.synchronize()
+    sel, g, out = sel.cpu().numpy(), g.cpu().numpy(), img_d.cpu().numpy()
+    rng = np.random.default_rng(area)
+    sample = sorted(rng.choice(len(blocks), 6 if area < 48 else 3, replace=False))
+    cls = classes_of(phi)
+    worst, agree = 0.0, 0
+    for i in sample:
+        b = blocks[i]
+        s, sup = oracle.area_signal(img[0], lost[0], b.y0, b.x0, area, area)
+        wo = oracle.area_weights(area, area, 0.8, sup)
+        C, D = oracle.table_generation(phi, wo)
+        I = iters[i]
+        res = oracle.fase(s, wo, phi, C, D, 0.5, I, cls)
+        if compare_selections(sel[i, :I], res.sel, cls):
+            agree += 1
+        else:
+            res = oracle.fase(s, wo, phi, C, D, 0.5, I, cls, forced=sel[i, :I])
+            assert (np.sqrt(res.picked) >= np.sqrt(res.best) * (1 - 1e-3)).all(), f"block {i}"
+        n = b.lh * b.lw
+        gref = res.g.reshape(area, area)[b.ly:b.ly + b.lh, b.lx:b.lx + b.lw].reshape(-1)
+        err = np.abs(g[i, :n] - gref).max()
+        worst = max(worst, err)
+        assert err <= TOL_FP32, f"block {i}: {err}"
+        y, x = b.y0 + b.ly, b.x0 + b.lx
+        got = out[0, y:y + b.lh, x:x + b.lw].reshape(-1)
+        near = np.abs(np.abs(gref - np.floor(gref)) - 0.5) < TOL_FP32
+        assert ((got == np.clip(np.rint(gref), 0, 255)) | near).all()
+    print(f"on-demand area {area}: {len(blocks)} blocks, identical selections "
+          f"{agree}/{len(sample)}, max|dg|={worst:.3g}")
