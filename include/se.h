@@ -306,6 +306,88 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w,
                                   int32_t g_loss_ld, void* ws, size_t ws_bytes,
                                   void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of concealment requests                      */
+/* ------------------------------------------------------------------------ */
+
+/* A server conceals lost blocks of whole frames submitted over time.  The
+ * paper's tables depend only on the weighting pattern, so they are computed
+ * "in advance" for the patterns that occur and kept (Section III); the
+ * server builds them on first use and keeps them in a device cache, limited
+ * by an HBM budget.  A block whose area lies inside the frame and holds no
+ * other loss has the isolated pattern of its (dictionary, loss rectangle)
+ * and uses the cached tables; every other block has its own weights and
+ * takes the on-demand path of se_extrapolate_ondemand.
+ *
+ * Requests are admitted as frame slots free up; each admitted frame is
+ * copied into a slot, and all admitted frames not yet launched are batched
+ * together (blocks of every frame grouped by pattern) and launched on one
+ * of several streams, so a batch launched while earlier batches still run
+ * overlaps with them on the device.  Results do not depend on which other
+ * requests share a batch.  Completion times are taken on the host
+ * (CLOCK_MONOTONIC, ns). */
+
+typedef struct se_server se_server;
+
+typedef struct {
+  int32_t device;            /* HIP device ordinal                             */
+  int32_t frame_H, frame_W;  /* frame size served (every request must match)   */
+  int32_t max_slots;         /* frames in flight on the device (>= 1)          */
+  int32_t max_queue;         /* frames waiting for a slot (>= 1)               */
+  int32_t n_streams;         /* streams batches are spread over (1 .. 8)       */
+  float rho_hat;             /* decay of eq. 5, (0, 1]                         */
+  size_t hbm_budget_bytes;   /* device memory for slots, tables and scratch    */
+} se_serve_config;
+
+/* One lost rectangle of a frame; its extrapolation area is the basis set's
+ * M x N window centred on the loss (offset (M-h)/2, (N-w)/2). */
+typedef struct {
+  int32_t y, x, h, w;        /* loss rectangle in frame coordinates            */
+  int32_t basis;             /* index of the basis set (see se_serve_create)   */
+} se_loss;
+
+typedef struct {
+  uint8_t* frame;            /* device uint8 H x W; the losses are replaced in
+                                place when the request completes; the caller
+                                must not touch it until then                  */
+  int32_t H, W;
+  const se_loss* losses;     /* host, copied during submit                    */
+  int32_t n_losses;
+  se_params prm;             /* gamma and iteration count for every block     */
+} se_request;
+
+typedef struct {
+  se_status status;          /* SE_OK, or the error the request ended with    */
+  int32_t n_blocks, n_isolated, n_ondemand;
+  uint64_t t_submit_ns, t_admit_ns, t_done_ns;
+} se_result;
+
+typedef struct {
+  uint64_t submitted, completed, batches;
+  uint64_t table_hits, table_builds, table_evictions, degraded_blocks;
+  size_t bytes_tables, bytes_slots, bytes_scratch;
+} se_serve_stats;
+
+/* Creates a server (allocates its slots and streams on `device`).  sets:
+ * host array of n_sets dictionaries (device phi, owned by the caller, must
+ * outlive the server).  Errors: SE_EINVAL for bad sizes, SE_ENOMEM if the
+ * slots alone exceed the budget, SE_EHIP for runtime failures. */
+se_status se_serve_create(const se_serve_config* cfg, const se_basis* sets,
+                          int32_t n_sets, se_server** out);
+/* Queues a request; never blocks.  SE_EBUSY when the queue is full,
+ * SE_EINVAL for a bad request (frame size, loss outside the frame, unknown
+ * basis, loss larger than the basis area, overlapping losses),
+ * SE_ECANCELED after destroy began.  *ticket identifies the request. */
+se_status se_serve_submit(se_server* s, const se_request* r, uint64_t* ticket);
+/* SE_EAGAIN while the request is queued or running; SE_OK once done, with
+ * *out filled and the ticket released; SE_EINVAL for an unknown ticket. */
+se_status se_serve_poll(se_server* s, uint64_t ticket, se_result* out);
+/* Blocks until the request is done, then as se_serve_poll. */
+se_status se_serve_wait(se_server* s, uint64_t ticket, se_result* out);
+se_status se_serve_stats_get(se_server* s, se_serve_stats* out);
+/* Finishes every admitted and queued request, then frees the server. */
+se_status se_serve_destroy(se_server* s);
+
 #ifdef __cplusplus
 }
 #endif

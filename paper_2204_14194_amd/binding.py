@@ -360,3 +360,127 @@ def extrapolate_ondemand(phi: torch.Tensor, M: int, N: int, w: torch.Tensor,
                                      blocks_array(blocks), n, prm, per, _ptr(sel), _ptr(coef),
                                      _ptr(g), gld, _ptr(ws), ws.numel(), _stream(stream)))
     return sel, coef, g
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+class se_serve_config(C.Structure):
+    _fields_ = [("device", C.c_int32), ("frame_H", C.c_int32), ("frame_W", C.c_int32),
+                ("max_slots", C.c_int32), ("max_queue", C.c_int32), ("n_streams", C.c_int32),
+                ("rho_hat", C.c_float), ("hbm_budget_bytes", C.c_size_t)]
+
+
+class se_loss(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("y", "x", "h", "w", "basis")]
+
+
+class se_request(C.Structure):
+    _fields_ = [("frame", C.c_void_p), ("H", C.c_int32), ("W", C.c_int32),
+                ("losses", C.c_void_p), ("n_losses", C.c_int32), ("prm", se_params)]
+
+
+class se_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("n_blocks", C.c_int32), ("n_isolated", C.c_int32),
+                ("n_ondemand", C.c_int32), ("t_submit_ns", C.c_uint64),
+                ("t_admit_ns", C.c_uint64), ("t_done_ns", C.c_uint64)]
+
+
+class se_serve_stats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("submitted", "completed", "batches", "table_hits",
+                                          "table_builds", "table_evictions",
+                                          "degraded_blocks")] + \
+               [(n, C.c_size_t) for n in ("bytes_tables", "bytes_slots", "bytes_scratch")]
+
+
+def _serve_lib():
+    L = lib()
+    if getattr(L, "_serve_ready", False):
+        return L
+    vp, i32 = C.c_void_p, C.c_int32
+    L.se_serve_create.restype = i32
+    L.se_serve_create.argtypes = [C.POINTER(se_serve_config), vp, i32, C.POINTER(vp)]
+    L.se_serve_submit.restype = i32
+    L.se_serve_submit.argtypes = [vp, C.POINTER(se_request), C.POINTER(C.c_uint64)]
+    for name in ("se_serve_poll", "se_serve_wait"):
+        f = getattr(L, name)
+        f.restype = i32
+        f.argtypes = [vp, C.c_uint64, C.POINTER(se_result)]
+    L.se_serve_stats_get.restype = i32
+    L.se_serve_stats_get.argtypes = [vp, C.POINTER(se_serve_stats)]
+    L.se_serve_destroy.restype = i32
+    L.se_serve_destroy.argtypes = [vp]
+    L._serve_ready = True
+    return L
+
+
+SERVE_EXPORTED = ("se_serve_create", "se_serve_submit", "se_serve_poll", "se_serve_wait",
+                  "se_serve_stats_get", "se_serve_destroy")
+EXPORTED = EXPORTED + SERVE_EXPORTED
+
+
+class Server:
+    """se_serve_*: a continuous-batching concealment server.  ``bases`` is a
+    list of (phi (K, M*N) float32 CUDA tensor, M, N); the tensors must stay
+    alive as long as the server."""
+
+    def __init__(self, bases, frame_H: int, frame_W: int, max_slots: int = 8,
+                 max_queue: int = 64, n_streams: int = 4, rho_hat: float = 0.8,
+                 hbm_budget_bytes: int = 8 << 30, device: int = 0):
+        L = _serve_lib()
+        self._bases = [b[0] for b in bases]
+        arr = (se_basis * len(bases))()
+        for i, (phi, M, N) in enumerate(bases):
+            _dev_f32(phi, "phi")
+            arr[i] = se_basis(M, N, phi.shape[0], phi.data_ptr())
+        cfg = se_serve_config(device, frame_H, frame_W, max_slots, max_queue, n_streams,
+                              float(rho_hat), int(hbm_budget_bytes))
+        h = C.c_void_p()
+        _check(L.se_serve_create(C.byref(cfg), arr, len(bases), C.byref(h)))
+        self._h = h
+        self.frame_H, self.frame_W = frame_H, frame_W
+
+    def submit(self, frame: torch.Tensor, losses, gamma: float, iters: int):
+        """Queue a frame (device uint8 H x W, modified in place when done)
+        with ``losses`` = [(y, x, h, w, basis), ...].  Returns the ticket, or
+        raises SEError (code SE_EBUSY when the queue is full)."""
+        L = _serve_lib()
+        n = len(losses)
+        arr = (se_loss * max(n, 1))()
+        for i, l in enumerate(losses):
+            arr[i] = se_loss(*[int(v) for v in l])
+        req = se_request(frame.data_ptr(), frame.shape[0], frame.shape[1],
+                         C.cast(arr, C.c_void_p), n, se_params(float(gamma), int(iters), 0))
+        t = C.c_uint64()
+        _check(L.se_serve_submit(self._h, C.byref(req), C.byref(t)))
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """The se_result once done, else None."""
+        res = se_result()
+        r = _serve_lib().se_serve_poll(self._h, ticket, C.byref(res))
+        if r == SE_EAGAIN:
+            return None
+        _check(r)
+        return res
+
+    def wait(self, ticket: int):
+        res = se_result()
+        _check(_serve_lib().se_serve_wait(self._h, ticket, C.byref(res)))
+        return res
+
+    def stats(self):
+        st = se_serve_stats()
+        _check(_serve_lib().se_serve_stats_get(self._h, C.byref(st)))
+        return {n: getattr(st, n) for n, _ in se_serve_stats._fields_}
+
+    def close(self):
+        if self._h:
+            _check(_serve_lib().se_serve_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -31,20 +31,6 @@ se_status check_launch(const char* what) {
 
 static inline int round4(int v) { return (v + 3) & ~3; }
 
-// Carves aligned sub-buffers out of the caller's workspace.
-struct Carver {
-  char* base;
-  size_t off = 0;
-  explicit Carver(void* p) : base(static_cast<char*>(p)) {}
-  template <class T>
-  T* take(size_t count) {
-    off = align_up(off, 256);
-    T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
-    off += count * sizeof(T);
-    return p;
-  }
-};
-
 static se_status upload_blocks(const se_block* blocks, int n_blk, DevBlock* dst,
                                hipStream_t s) {
   std::vector<DevBlock> tmp((size_t)n_blk);

@@ -19,6 +19,21 @@ se_status check_launch(const char* what);
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Carves 256-byte aligned sub-buffers out of a caller's workspace (with a
+// NULL base it only measures).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* p) : base(static_cast<char*>(p)) {}
+  template <class T>
+  T* take(size_t count) {
+    off = align_up(off, 256);
+    T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
 // Device copy of one block descriptor (same layout as se_block), validated
 // on the host by se_blocks_upload.
 using DevBlock = se_block;
@@ -31,6 +46,9 @@ using DevBlock = se_block;
 void launch_area_weights(int M, int N, float rho_hat, const uint8_t* lost,
                          int H, int W, const DevBlock* blk, int n_blk,
                          float* w, hipStream_t s);
+
+// lost-pixel mask of one H x W frame from loss rectangles (y, x, h, w)
+void launch_lost_mask(uint8_t* mask, int H, int W, const int4* rects, int n, hipStream_t s);
 
 // gram.hip -- Algorithm 2 support kernels
 // diag32/diag64: C_kk summed in fp32 and fp64 with one fixed order.

@@ -39,3 +39,32 @@ void launch_area_weights(int M, int N, float rho_hat, const uint8_t* lost, int H
 }
 
 }  // namespace sefase
+
+namespace sefase {
+
+// Lost-pixel mask of a frame: zero it, then mark each loss rectangle
+// (rects: y, x, h, w in frame coordinates, already validated).
+__global__ void k_fill_u8(uint8_t* __restrict__ a, size_t n, uint8_t v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+__global__ void k_mark_rects(uint8_t* __restrict__ mask, int H, int W,
+                             const int4* __restrict__ rects, int n) {
+  const int r = blockIdx.x;
+  if (r >= n) return;
+  const int4 q = rects[r];
+  for (int i = threadIdx.x; i < q.z * q.w; i += blockDim.x) {
+    const int y = q.x + i / q.w, x = q.y + i % q.w;
+    if (y >= 0 && y < H && x >= 0 && x < W) mask[(size_t)y * W + x] = 1;
+  }
+}
+
+void launch_lost_mask(uint8_t* mask, int H, int W, const int4* rects, int n, hipStream_t s) {
+  const size_t total = (size_t)H * W;
+  hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, mask,
+                     total, (uint8_t)0);
+  if (n > 0) hipLaunchKernelGGL(k_mark_rects, dim3(n), dim3(256), 0, s, mask, H, W, rects, n);
+}
+
+}  // namespace sefase

@@ -326,3 +326,35 @@ def cfg2_inputs(n_img: int = 8, blocks_per_img: int = 500, seed0: int = 200,
     iters = rng.integers(iter_range[0], iter_range[1] + 1, size=len(blocks))
     return dict(images=imgs, blocks=blocks, iters=iters, dicts=cfg2_dictionaries(),
                 rho_hat=0.8, gamma=0.5)
+
+
+def frame_losses(H: int, W: int, coverage: float, seed: int, p16: float = 0.5,
+                 p64: float = 0.5):
+    """Lost blocks of one frame for serving: 8x8 and 16x16 losses on the
+    8-pixel grid, placed uniformly at random without overlap until
+    ``coverage`` of the frame is lost.  Returns (y, x, h, w, basis) tuples
+    with basis 0 for 8x8 losses (32x32 areas), and 1 (48x48) or 2 (64x64)
+    for 16x16 losses."""
+    rng = np.random.default_rng(seed)
+    gh, gw = H // 8, W // 8
+    occ = np.zeros((gh, gw), dtype=bool)
+    out = []
+    lost = 0
+    target = coverage * H * W
+    tries = 0
+    while lost < target and tries < 100000:
+        tries += 1
+        big = rng.random() < p16
+        c = 2 if big else 1
+        cy = int(rng.integers(0, gh - c + 1))
+        cx = int(rng.integers(0, gw - c + 1))
+        if big:
+            cy, cx = cy - cy % 2, cx - cx % 2
+        if occ[cy:cy + c, cx:cx + c].any():
+            continue
+        occ[cy:cy + c, cx:cx + c] = True
+        s = 8 * c
+        basis = 0 if not big else (2 if rng.random() < p64 else 1)
+        out.append((cy * 8, cx * 8, s, s, basis))
+        lost += s * s
+    return out
