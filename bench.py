@@ -109,6 +109,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--plain-reps", type=int, default=2,
                     help="passes of the plain per-block form over one image's 16 blocks")
+    ap.add_argument("--config", default="cfg0",
+                    choices=["cfg0", "cfg1", "cfg2", "cfg3", "cfg4"],
+                    help="cfg0 (default) is the headline line; the others measure the "
+                         "secondary workloads")
+    ap.add_argument("--frames", type=int, default=120, help="cfg4: frames per arrival rate")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -117,6 +122,10 @@ def main():
               "(blocks are independent; sharding them across GPUs is described in the "
               "design notes but not built). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.config != "cfg0":
+        print(json.dumps(SECONDARY[args.config](args)), flush=True)
+        return
 
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_blocks)
 
@@ -251,6 +260,215 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# secondary workloads (python bench.py --config cfgN); each prints one line
+# ---------------------------------------------------------------------------
+def _events(n):
+    import torch
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def _timed(fn, steps, warmup):
+    """Run fn() warmup times, then time `steps` calls; returns per-call ms."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(steps):
+        e0, e1 = _events(2)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return out
+
+
+def _shared_tables(B, torch, dev, images, blocks, phi, M, N, precision):
+    n_img, H, W = images.shape
+    lost = np.stack([synth.lost_mask(H, W, blocks, i) for i in range(n_img)])
+    w = B.area_weights(M, N, RHO, torch.from_numpy(lost).to(dev), blocks[:1])
+    return B.weighted_gram(torch.from_numpy(phi.astype(np.float32)).to(dev), w[0].contiguous(),
+                           M, N, precision)
+
+
+def bench_cfg1(args):
+    """Batched FP32: 512x512 image (544x544 canvas), 256 isolated 16x16
+    losses, 48x48 areas, K = 4096 (DCT 48^2 u 1792 Gaussian atoms), I = 200."""
+    import torch
+    from paper_2204_14194_amd import binding as B
+    dev = torch.device("cuda:0")
+    n_img = max(1, args.images if args.images != 256 else 1)
+    d = synth.cfg1_inputs(n_img)
+    blocks = d["blocks"]
+    t = _shared_tables(B, torch, dev, d["images"], blocks, d["phi"], 48, 48, B.SE_FP32)
+    img = torch.from_numpy(d["images"]).to(dev)
+    ws = torch.empty(B.extrapolate_batch_ws_bytes(t, len(blocks)), dtype=torch.uint8, device=dev)
+    arr = B.blocks_array(blocks)
+    ms = _timed(lambda: B.extrapolate_batch(t, img, blocks, 0.5, 200, False, False, False, ws=ws,
+                                            blocks_arr=arr), args.steps, args.warmup)
+    med = float(np.median(ms))
+    return {"metric": "concealed blocks/s, 48x48 areas, K=4096, I=200 (batched FP32)",
+            "value": len(blocks) / (med * 1e-3), "unit": "blocks/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": med,
+            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{n_img} x 512x512 image(s), {len(blocks)} isolated 16x16 "
+                                   f"losses, 48x48 areas, K=4096, I=200"},
+            "latency_ms": {"p50": percentile(ms, 50), "p99": percentile(ms, 99)}}
+
+
+def bench_cfg2(args):
+    """Uneven batch: 8 1024x1024 frames with clustered/burst losses, 4000
+    blocks, areas 24/32/48, per-block weights (rows on demand), I ~ U{100..200}."""
+    import torch
+    from paper_2204_14194_amd import binding as B
+    dev = torch.device("cuda:0")
+    d = synth.cfg2_inputs()
+    blocks, iters = d["blocks"], d["iters"]
+    lost = np.stack([synth.lost_mask(1024, 1024, blocks, i) for i in range(8)])
+    lost_d = torch.from_numpy(lost).to(dev)
+    img = torch.from_numpy(d["images"]).to(dev)
+    groups = []
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    for k, area in enumerate((24, 32, 48)):
+        idx = [i for i, b in enumerate(blocks) if b.ly * 2 + b.lh == area]
+        bl = [blocks[i] for i in idx]
+        it = [int(iters[i]) for i in idx]
+        phi = torch.from_numpy(d["dicts"][area].astype(np.float32)).to(dev)
+        w = B.area_weights(area, area, RHO, lost_d, bl)
+        groups.append((phi, area, w, bl, it, streams[k]))
+
+    def step():
+        cur = torch.cuda.current_stream()
+        for phi, area, w, bl, it, st in groups:
+            st.wait_stream(cur)
+            with torch.cuda.stream(st):
+                B.extrapolate_ondemand(phi, area, area, w, img, bl, 0.5, it, False, False, False,
+                                       stream=st)
+        for *_, st in groups:
+            cur.wait_stream(st)
+
+    ms = _timed(step, max(1, args.steps // 4), 1)
+    med = float(np.median(ms))
+    return {"metric": "concealed blocks/s, uneven batch with per-block weights (rows on demand)",
+            "value": len(blocks) / (med * 1e-3), "unit": "blocks/s", "n_gpus": 1,
+            "steps": len(ms), "warmup": 1, "ms_per_step": med, "higher_is_better": True,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "8 x 1024x1024 frames, 4000 clustered/burst 8x8 and 16x16 "
+                                   "losses, areas 24/32/48 (K=1152/2048/4608), I~U{100..200}, "
+                                   "one dictionary group per stream"},
+            "blocks_per_area": {str(a): len(g[3]) for a, g in zip((24, 32, 48), groups)}}
+
+
+def bench_cfg3(args):
+    """Precision: 1024 blocks of one geometry, 64x64 areas, K = 8192 (DCT u
+    WHT 64^2), I = 300; FP32 vs split-BF16 tables and projections."""
+    import torch
+    from paper_2204_14194_amd import binding as B
+    dev = torch.device("cuda:0")
+    d = synth.cfg3_inputs(1)
+    blocks = d["blocks"]
+    out = {"metric": "concealed blocks/s, 64x64 areas, K=8192, I=300 (FP32 vs BF16x3)",
+           "unit": "blocks/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "config": {"workload": "2048x2048 image, 1024 64x64 areas with 16x16 losses, "
+                                  "K=8192, I=300"}}
+    for name, prec in (("fp32", B.SE_FP32), ("bf16x3", B.SE_BF16X3)):
+        gram = []
+        for _ in range(3):
+            e0, e1 = _events(2)
+            e0.record()
+            t = _shared_tables(B, torch, dev, d["images"], blocks, d["phi"], 64, 64, prec)
+            e1.record()
+            e1.synchronize()
+            gram.append(e0.elapsed_time(e1))
+        img = torch.from_numpy(d["images"]).to(dev)
+        dblk = B.DeviceBlocks(t, img, blocks)
+        R = torch.empty((len(blocks), B.table_ld(8192)), dtype=torch.float32, device=dev)
+        ws = torch.empty(B.project_ws_bytes(t, len(blocks)), dtype=torch.uint8, device=dev)
+        proj = _timed(lambda: B.project(t, img, dblk, R, ws), args.steps, args.warmup)
+        loop = _timed(lambda: B.iterate(t, R, img, dblk, 0.5, 300), max(2, args.steps // 4), 1)
+        step = float(np.median(proj)) + float(np.median(loop))
+        flops = 2.0 * 8192 * 4096 * len(blocks)
+        out[name] = {"blocks_per_s": len(blocks) / (step * 1e-3), "ms_per_step": step,
+                     "project_ms": float(np.median(proj)),
+                     "project_tflops": flops / (np.median(proj) * 1e-3) / 1e12,
+                     "loop_ms": float(np.median(loop)), "gram_ms": min(gram),
+                     "gram_tflops": 8192 * 8193 * 4096 / (min(gram) * 1e-3) / 1e12}
+        del t
+    out["value"] = out["bf16x3"]["blocks_per_s"]
+    out["dtype"] = "bf16x3"
+    return out
+
+
+def bench_cfg4(args):
+    """Serving: Poisson arrivals of 1920x1080 frames with 1-10% of 8x8/16x16
+    losses (areas 32/48/64, the dictionaries of the other workloads)."""
+    import torch
+    from paper_2204_14194_amd import binding as B
+    dev = torch.device("cuda:0")
+    bases = [(torch.from_numpy(synth.dictionary(32, 32, ("dct", "wht")).astype(np.float32))
+              .to(dev), 32, 32),
+             (torch.from_numpy(synth.dictionary(48, 48, ("dct", "gauss"), seed=101, n_gauss=1792)
+                               .astype(np.float32)).to(dev), 48, 48),
+             (torch.from_numpy(synth.dictionary(64, 64, ("dct", "wht")).astype(np.float32))
+              .to(dev), 64, 64)]
+    H, W = 1080, 1920
+    n_frames = args.frames
+    rng = np.random.default_rng(4)
+    frames = [synth.synth_image(H, W, seed=400 + i) for i in range(8)]
+    cov = rng.uniform(0.01, 0.10, size=n_frames)
+    losses = [synth.frame_losses(H, W, float(c), seed=500 + i) for i, c in enumerate(cov)]
+    results = {}
+    srv = B.Server(bases, H, W, max_slots=16, max_queue=64, n_streams=4,
+                   hbm_budget_bytes=64 << 30)
+    # warm the table cache with one frame
+    f0 = torch.from_numpy(frames[0].copy()).to(dev)
+    srv.wait(srv.submit(f0, losses[0], 0.5, 100))
+    bufs = [torch.from_numpy(frames[i % 8].copy()).to(dev) for i in range(n_frames)]
+    for lam in (30, 60, 120, 240):
+        gaps = rng.exponential(1.0 / lam, size=n_frames)
+        t0 = time.perf_counter()
+        due = t0 + np.cumsum(gaps)
+        tickets, dropped, blocks = [], 0, 0
+        for i in range(n_frames):
+            while time.perf_counter() < due[i]:
+                pass
+            try:
+                tickets.append(srv.submit(bufs[i], losses[i], 0.5, 100))
+                blocks += len(losses[i])
+            except B.SEError as e:
+                if e.code != B.SE_EBUSY:
+                    raise
+                dropped += 1
+        lat = []
+        t_first, t_last = None, None
+        for tk in tickets:
+            r = srv.wait(tk)
+            lat.append((r.t_done_ns - r.t_submit_ns) * 1e-6)
+            t_first = r.t_submit_ns if t_first is None else min(t_first, r.t_submit_ns)
+            t_last = r.t_done_ns if t_last is None else max(t_last, r.t_done_ns)
+        span = (t_last - t_first) * 1e-9
+        results[str(lam)] = {"blocks_per_s": blocks / span, "frames": len(tickets),
+                             "dropped": dropped, "p50_ms": percentile(lat, 50),
+                             "p99_ms": percentile(lat, 99), "offered_fps": lam,
+                             "served_fps": len(tickets) / span}
+    st = srv.stats()
+    srv.close()
+    best = max(results.values(), key=lambda r: r["blocks_per_s"])
+    return {"metric": "served blocks/s and p50/p99 latency, Poisson 1920x1080 frames",
+            "value": best["blocks_per_s"], "unit": "blocks/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{n_frames} frames per rate, 1-10% lost (8x8 -> 32x32 areas "
+                                   "K=2048; 16x16 -> 48x48 K=4096 or 64x64 K=8192), I=100, "
+                                   "16 slots, 4 streams"},
+            "rates": results,
+            "server": {k: int(v) for k, v in st.items()}}
+
+
+SECONDARY = {"cfg1": bench_cfg1, "cfg2": bench_cfg2, "cfg3": bench_cfg3, "cfg4": bench_cfg4}
 
 
 if __name__ == "__main__":
