@@ -224,12 +224,27 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f32(const float* __restrict__ A
           const int r = r0 + e;
           const float v = acc[i][j][e];
           if (MODE == kStoreSymmetric) {
-            if (r < Ma && c < Nb && r >= c) {
+            if (bi == bj && r < Ma && c < Nb && r >= c) {   // diagonal tile
               C[(size_t)r * ldc + c] = v;
               if (r > c) C[(size_t)c * ldc + r] = v;
+            } else if (bi != bj && r < Ma && c < Nb) {
+              C[(size_t)r * ldc + c] = v;                   // mirror below, as float4
             }
           } else {
             if (r < Mst && c < Nst) C[(size_t)r * ldc + c] = (r < Ma && c < Nb) ? v : 0.0f;
+          }
+        }
+        if (MODE == kStoreSymmetric && bi != bj && c < Nb) {
+          // off-diagonal tile: rows r0..r0+3 of column c are one row segment of
+          // the mirrored tile
+          float* dst = C + (size_t)c * ldc + r0;
+          if ((ldc & 3) == 0 && r0 + 3 < Ma) {
+            *reinterpret_cast<float4*>(dst) =
+                make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (r0 + e < Ma) dst[e] = acc[i][j][e];
           }
         }
       }
