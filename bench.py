@@ -68,7 +68,7 @@ def cpu_baseline(n_blocks: int):
     blocks of the workload with one process per core.  Runs before the GPU
     is initialised, in forked workers."""
     n_img = (n_blocks + 15) // 16
-    d = synth.cfg0_inputs(n_img)
+    d = synth.area32_inputs(n_img)
     d["blocks"] = d["blocks"][:n_blocks]
     _CPU["d"] = d
     _CPU["phi"] = synth.round_to_f32(d["phi"])
@@ -102,7 +102,7 @@ def measured_loop_traffic(images: int):
     import hashlib
     if images != 256:
         return None
-    prof = os.path.join(ROOT, "profiles", "k_greedy_cfg0_traffic.txt")
+    prof = os.path.join(ROOT, "profiles", "k_greedy_area32_k2048_traffic.txt")
     csrc = os.path.join(ROOT, "paper_2204_14194_amd", "csrc")
     try:
         kv = {}
@@ -136,11 +136,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--plain-reps", type=int, default=2,
                     help="passes of the plain per-block form over one image's 16 blocks")
-    ap.add_argument("--config", default="cfg0",
-                    choices=["cfg0", "cfg1", "cfg2", "cfg3", "cfg4"],
-                    help="cfg0 (default) is the headline line; the others measure the "
+    ap.add_argument("--config", default="area32",
+                    choices=["area32", "area48", "clustered", "area64", "serving"],
+                    help="area32 (default) is the headline line; the others measure the "
                          "secondary workloads")
-    ap.add_argument("--frames", type=int, default=120, help="cfg4: frames per arrival rate")
+    ap.add_argument("--frames", type=int, default=120, help="serving: frames per arrival rate")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="before timing, copy a buffer of this many MiB once (a kernel of "
                          "known traffic for scaling memory counters)")
@@ -148,12 +148,12 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: there is no multi-GPU path "
               "(blocks are independent; sharding them across GPUs is described in the "
               "design notes but not built). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    if args.config != "cfg0":
+    if args.config != "area32":
         print(json.dumps(SECONDARY[args.config](args)), flush=True)
         return
 
@@ -166,7 +166,7 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
 
-    d = synth.cfg0_inputs(args.images)
+    d = synth.area32_inputs(args.images)
     blocks = d["blocks"]
     nblk = len(blocks)
     phi_d = torch.from_numpy(d["phi"].astype(np.float32)).to(dev)
@@ -300,7 +300,7 @@ def main():
 
 
 # ---------------------------------------------------------------------------
-# secondary workloads (python bench.py --config cfgN); each prints one line
+# secondary workloads (python bench.py --config NAME); each prints one line
 # ---------------------------------------------------------------------------
 def _events(n):
     import torch
@@ -332,14 +332,14 @@ def _shared_tables(B, torch, dev, images, blocks, phi, M, N, precision):
                            M, N, precision)
 
 
-def bench_cfg1(args):
+def bench_area48(args):
     """Batched FP32: 512x512 image (544x544 canvas), 256 isolated 16x16
     losses, 48x48 areas, K = 4096 (DCT 48^2 u 1792 Gaussian atoms), I = 200."""
     import torch
     from paper_2204_14194_amd import binding as B
     dev = torch.device("cuda:0")
     n_img = max(1, args.images if args.images != 256 else 1)
-    d = synth.cfg1_inputs(n_img)
+    d = synth.area48_inputs(n_img)
     blocks = d["blocks"]
     t = _shared_tables(B, torch, dev, d["images"], blocks, d["phi"], 48, 48, B.SE_FP32)
     img = torch.from_numpy(d["images"]).to(dev)
@@ -357,13 +357,13 @@ def bench_cfg1(args):
             "latency_ms": {"p50": percentile(ms, 50), "p99": percentile(ms, 99)}}
 
 
-def bench_cfg2(args):
+def bench_clustered(args):
     """Uneven batch: 8 1024x1024 frames with clustered/burst losses, 4000
     blocks, areas 24/32/48, per-block weights (rows on demand), I ~ U{100..200}."""
     import torch
     from paper_2204_14194_amd import binding as B
     dev = torch.device("cuda:0")
-    d = synth.cfg2_inputs()
+    d = synth.clustered_inputs()
     blocks, iters = d["blocks"], d["iters"]
     lost = np.stack([synth.lost_mask(1024, 1024, blocks, i) for i in range(8)])
     lost_d = torch.from_numpy(lost).to(dev)
@@ -400,13 +400,13 @@ def bench_cfg2(args):
             "blocks_per_area": {str(a): len(g[3]) for a, g in zip((24, 32, 48), groups)}}
 
 
-def bench_cfg3(args):
+def bench_area64(args):
     """Precision: 1024 blocks of one geometry, 64x64 areas, K = 8192 (DCT u
     WHT 64^2), I = 300; FP32 vs split-BF16 tables and projections."""
     import torch
     from paper_2204_14194_amd import binding as B
     dev = torch.device("cuda:0")
-    d = synth.cfg3_inputs(1)
+    d = synth.area64_inputs(1)
     blocks = d["blocks"]
     out = {"metric": "concealed blocks/s, 64x64 areas, K=8192, I=300 (FP32 vs BF16x3)",
            "unit": "blocks/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
@@ -440,7 +440,7 @@ def bench_cfg3(args):
     return out
 
 
-def bench_cfg4(args):
+def bench_serving(args):
     """Serving: Poisson arrivals of 1920x1080 frames with 1-10% of 8x8/16x16
     losses (areas 32/48/64, the dictionaries of the other workloads)."""
     import torch
@@ -505,7 +505,8 @@ def bench_cfg4(args):
             "server": {k: int(v) for k, v in st.items()}}
 
 
-SECONDARY = {"cfg1": bench_cfg1, "cfg2": bench_cfg2, "cfg3": bench_cfg3, "cfg4": bench_cfg4}
+SECONDARY = {"area48": bench_area48, "clustered": bench_clustered, "area64": bench_area64,
+             "serving": bench_serving}
 
 
 if __name__ == "__main__":

@@ -34,8 +34,9 @@ import numpy as np
 __all__ = [
     "synth_image", "dct_rows", "wht_rows", "separable_atoms", "dct2_atoms",
     "wht2_atoms", "gaussian_atoms", "dictionary", "Block", "grid_layout",
-    "parity_lattice_layout", "lost_mask", "round_to_f32", "cfg0_inputs",
-    "cfg1_inputs", "cfg3_inputs",
+    "parity_lattice_layout", "lost_mask", "round_to_f32", "area32_inputs",
+    "area48_inputs", "area64_inputs", "clustered_layout", "clustered_dictionaries",
+    "clustered_inputs", "frame_losses",
 ]
 
 
@@ -220,7 +221,7 @@ def lost_mask(H: int, W: int, blocks: Sequence[Block], img: int = 0) -> np.ndarr
 # ----------------------------------------------------------------------------
 # the workloads (one geometry each)
 # ----------------------------------------------------------------------------
-def cfg0_inputs(n_img: int = 1, seed0: int = 0):
+def area32_inputs(n_img: int = 1, seed0: int = 0):
     """128x128 images (seeds seed0..), 4x4 grid of 32x32 areas with centred
     8x8 losses (support width 12); K = 2048 (DCT-II 32^2 u WHT 32^2);
     rho_hat = 0.8, gamma = 0.5, I = 100."""
@@ -231,7 +232,7 @@ def cfg0_inputs(n_img: int = 1, seed0: int = 0):
                 rho_hat=0.8, gamma=0.5, iters=100)
 
 
-def cfg1_inputs(n_img: int = 1, seed0: int = 1, layout_seed: int = 7):
+def area48_inputs(n_img: int = 1, seed0: int = 1, layout_seed: int = 7):
     """512x512 image generated on a 544x544 canvas (areas read from the
     canvas); 256 isolated 16x16 losses on one parity lattice of the 16-px
     grid; area 48x48; K = 4096 (DCT 48^2 u 1792 seeded Gaussian atoms);
@@ -243,7 +244,7 @@ def cfg1_inputs(n_img: int = 1, seed0: int = 1, layout_seed: int = 7):
                 rho_hat=0.8, gamma=0.5, iters=200)
 
 
-def cfg3_inputs(n_img: int = 1, seed0: int = 300):
+def area64_inputs(n_img: int = 1, seed0: int = 300):
     """2048x2048 image, 1024 64x64 areas with centred 16x16 losses;
     K = 8192 (DCT 64^2 u WHT 64^2); rho_hat = 0.8, gamma = 0.5, I = 300."""
     imgs = np.stack([synth_image(2048, 2048, seed0 + i) for i in range(n_img)])
@@ -305,7 +306,7 @@ def clustered_layout(H: int, W: int, n_blocks: int, seed: int, img: int = 0,
     return out
 
 
-def cfg2_dictionaries():
+def clustered_dictionaries():
     """Dictionary per area size for the uneven workload: DCT u WHT for 32x32
     (K = 2048), DCT u seeded Gaussian atoms for 24x24 and 48x48 (no Sylvester
     Walsh-Hadamard exists there), K = 2 * area pixels."""
@@ -314,7 +315,7 @@ def cfg2_dictionaries():
             48: dictionary(48, 48, ("dct", "gauss"), seed=148, n_gauss=2304)}
 
 
-def cfg2_inputs(n_img: int = 8, blocks_per_img: int = 500, seed0: int = 200,
+def clustered_inputs(n_img: int = 8, blocks_per_img: int = 500, seed0: int = 200,
                 iter_range=(100, 200)):
     """8 seeded 1024x1024 frames with clustered/burst losses, 500 blocks each;
     per-block iteration counts I ~ U{100..200}; rho_hat = 0.8, gamma = 0.5."""
@@ -324,7 +325,7 @@ def cfg2_inputs(n_img: int = 8, blocks_per_img: int = 500, seed0: int = 200,
         blocks += clustered_layout(1024, 1024, blocks_per_img, seed=seed0 + 1000 + i, img=i)
     rng = np.random.default_rng(seed0 + 99)
     iters = rng.integers(iter_range[0], iter_range[1] + 1, size=len(blocks))
-    return dict(images=imgs, blocks=blocks, iters=iters, dicts=cfg2_dictionaries(),
+    return dict(images=imgs, blocks=blocks, iters=iters, dicts=clustered_dictionaries(),
                 rho_hat=0.8, gamma=0.5)
 
 

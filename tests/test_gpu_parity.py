@@ -107,15 +107,15 @@ def test_gram_matches_oracle(M, N, K, kind):
             assert D[k] == D[cls[k]]
 
 
-def test_cfg0_batch_parity():
-    d = synth.cfg0_inputs(1)
-    say("cfg0 batched: 1 image 128x128, 16 blocks, K=2048, I=100")
+def test_area32_batch_parity():
+    d = synth.area32_inputs(1)
+    say("32x32 areas batched: 1 image 128x128, 16 blocks, K=2048, I=100")
     phi = synth.round_to_f32(d["phi"])
     t, _, _ = shared_tables(d["images"], d["blocks"], upload_phi(phi), 32, 32, 0.8)
     sel, coef, g, out = run_batch(t, d["images"], d["blocks"], 0.5, 100)
     worst, margin = check_against_oracle(d["images"], d["blocks"], phi, 32, 32, 0.8, 0.5, 100,
                                          sel, coef, g, out)
-    print(f"cfg0 batched: max|dg|={worst:.3g} min tie margin={margin:.3g}")
+    print(f"32x32 areas batched: max|dg|={worst:.3g} min tie margin={margin:.3g}")
     # the higher-indexed twin is never selected (exact ties go to the lowest k)
     assert not set(np.unique(sel)) & {1024, 1027, 1120, 1123}
     # nothing outside the losses changed
@@ -125,9 +125,9 @@ def test_cfg0_batch_parity():
     np.testing.assert_array_equal(out[mask], d["images"][mask])
 
 
-def test_cfg0_plain_parity_and_agreement_with_batch():
-    d = synth.cfg0_inputs(1)
-    say("cfg0 plain (per-block launches): 16 blocks, K=2048, I=100")
+def test_area32_plain_parity_and_agreement_with_batch():
+    d = synth.area32_inputs(1)
+    say("32x32 areas plain (per-block launches): 16 blocks, K=2048, I=100")
     phi = synth.round_to_f32(d["phi"])
     t, _, _ = shared_tables(d["images"], d["blocks"], upload_phi(phi), 32, 32, 0.8)
     sel_p, coef_p, g_p, out_p = run_batch(t, d["images"], d["blocks"], 0.5, 100, plain=True)
@@ -138,10 +138,10 @@ def test_cfg0_plain_parity_and_agreement_with_batch():
     assert np.abs(g_p - g_b).max() <= TOL_FP32
 
 
-def test_cfg0_se_original_anchor():
+def test_area32_se_original_anchor():
     """Two blocks against Algorithm 1 itself (not only its fast form)."""
-    d = synth.cfg0_inputs(1)
-    say("cfg0 vs original SE (Algorithm 1): blocks 3 and 12")
+    d = synth.area32_inputs(1)
+    say("32x32 areas vs original SE (Algorithm 1): blocks 3 and 12")
     phi = synth.round_to_f32(d["phi"])
     t, _, _ = shared_tables(d["images"], d["blocks"], upload_phi(phi), 32, 32, 0.8)
     sel, coef, g, out = run_batch(t, d["images"], d["blocks"], 0.5, 100)
@@ -202,10 +202,10 @@ def test_degenerate_atom_and_zero_signal():
     np.testing.assert_array_equal(g0, 0.0)
 
 
-def test_cfg0_bench_scale_sampled():
+def test_area32_bench_scale_sampled():
     """The launch configuration the benchmark times: 256 images x 16 blocks."""
-    d = synth.cfg0_inputs(256)
-    say("cfg0 at benchmark scale: 256 images, 4096 blocks, sampled oracle check")
+    d = synth.area32_inputs(256)
+    say("32x32 areas at benchmark scale: 256 images, 4096 blocks, sampled oracle check")
     phi = synth.round_to_f32(d["phi"])
     t, _, _ = shared_tables(d["images"], d["blocks"], upload_phi(phi), 32, 32, 0.8)
     sel, coef, g, out = run_batch(t, d["images"], d["blocks"], 0.5, 100)
@@ -276,7 +276,7 @@ def test_gram_bf16x3_matches_oracle():
 
 
 @pytest.mark.parametrize("precision", [B.SE_FP32, B.SE_BF16X3])
-def test_cfg3_precision_parity(precision):
+def test_area64_precision_parity(precision):
     """2048x2048 image, 1024 64x64 areas with 16x16 losses, K=8192 (DCT 64^2 u
     WHT 64^2), I=300: a sample of blocks against the FP64 oracle.  At this size
     FP32 rounding can reorder atoms whose scores agree to ~1e-5, so a
@@ -284,8 +284,8 @@ def test_cfg3_precision_parity(precision):
     model is then checked along the device's own selections; the count of
     identical sequences and the smallest oracle tie margin are reported."""
     name = "FP32" if precision == B.SE_FP32 else "BF16X3"
-    d = synth.cfg3_inputs(1)
-    say(f"cfg3 {name}: 1024 blocks, K=8192, I=300")
+    d = synth.area64_inputs(1)
+    say(f"64x64 areas {name}: 1024 blocks, K=8192, I=300")
     phi = synth.round_to_f32(d["phi"])
     t, _, _ = shared_tables(d["images"], d["blocks"], upload_phi(phi), 64, 64, 0.8, precision)
     sel, coef, g, out = run_batch(t, d["images"], d["blocks"], 0.5, 300)
@@ -293,7 +293,7 @@ def test_cfg3_precision_parity(precision):
     tol = TOL_FP32 if precision == B.SE_FP32 else TOL_BF16X3
     st = oracle_check(d["images"], d["blocks"], phi, 64, 64, 0.8, 0.5, 300, sel, g, out,
                       sample=sample, tol=tol)
-    print(f"cfg3 {name}: identical selections {st['agree']}/{st['n']}, "
+    print(f"64x64 areas {name}: identical selections {st['agree']}/{st['n']}, "
           f"max|dg|={st['worst']:.3g}, min tie margin={st['margin']:.3g}")
 
 
@@ -313,8 +313,8 @@ def run_ondemand(phi32, M, N, images, blocks, gamma, iters):
 def test_ondemand_equals_shared_tables_on_isolated_blocks():
     """Identical weights for every block: forming rows on demand must give
     the same result as the shared table (and the oracle)."""
-    d = synth.cfg0_inputs(1)
-    say("on-demand rows vs shared tables: cfg0, 16 isolated blocks, I=100")
+    d = synth.area32_inputs(1)
+    say("on-demand rows vs shared tables: 32x32 areas, 16 isolated blocks, I=100")
     phi = synth.round_to_f32(d["phi"])
     phi_d = upload_phi(phi)
     sel, coef, g, out = run_ondemand(phi_d, 32, 32, d["images"], d["blocks"], 0.5, 100)
@@ -332,7 +332,7 @@ def test_ondemand_clustered_losses(area):
     size per dictionary, per-block iteration counts; a sample against the
     FP64 oracle."""
     say(f"on-demand clustered losses: area {area}")
-    d = synth.cfg2_inputs(n_img=1, blocks_per_img=500)
+    d = synth.clustered_inputs(n_img=1, blocks_per_img=500)
     blocks = [b for b in d["blocks"] if b.ly * 2 + b.lh == area]
     iters = [int(v) for v, b in zip(d["iters"], d["blocks"]) if b.ly * 2 + b.lh == area]
     phi = synth.round_to_f32(d["dicts"][area])

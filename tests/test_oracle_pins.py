@@ -58,8 +58,8 @@ def test_weights_closed_form():
 # P-a: FaSE behaves identically to SE (the paper's central claim)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("block", [0, 5])
-def test_fase_equals_se_cfg0(block):
-    d = synth.cfg0_inputs(1)
+def test_fase_equals_se_area32(block):
+    d = synth.area32_inputs(1)
     phi = d["phi"]
     cls = oracle.duplicate_classes(phi)
     lost = synth.lost_mask(128, 128, d["blocks"])
@@ -337,7 +337,7 @@ def test_degenerate_atom_never_selected():
 
 
 def test_twins_tie_and_lowest_index_wins():
-    d = synth.cfg0_inputs(1)
+    d = synth.area32_inputs(1)
     phi = d["phi"]
     cls = oracle.duplicate_classes(phi)
     twins = [(int(c), k) for k, c in enumerate(cls) if c != k]
@@ -375,7 +375,7 @@ def test_table1_reproduces_fig3():
 # conceal(): the whole task on an image
 # ---------------------------------------------------------------------------
 def test_conceal_pastes_only_the_loss():
-    d = synth.cfg0_inputs(1)
+    d = synth.area32_inputs(1)
     img = d["images"][0]
     blocks = d["blocks"]
     lost = synth.lost_mask(128, 128, blocks)
