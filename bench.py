@@ -141,6 +141,9 @@ def main():
                     help="area32 (default) is the headline line; the others measure the "
                          "secondary workloads")
     ap.add_argument("--frames", type=int, default=120, help="serving: frames per arrival rate")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuner (default: tune loop shape and GEMM tile on the "
+                         "benchmark batch before timing)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="before timing, copy a buffer of this many MiB once (a kernel of "
                          "known traffic for scaling memory counters)")
@@ -196,6 +199,10 @@ def main():
     R = torch.empty((nblk, ldR), dtype=torch.float32, device=dev)
     ws = torch.empty(B.project_ws_bytes(t, nblk), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
+
+    tuned = None
+    if not args.no_autotune:
+        tuned = B.autotune_batch(t, images_d, dblk, R, ws, GAMMA, ITERS, reps=3)
 
     def step(ev=None):
         if ev is not None:
@@ -289,6 +296,7 @@ def main():
                           "single-workgroup loop)", "blocks": len(plain_ms)},
         "chosen_over_plain": value / plain_bps,
         "gram_ms": gram_ms,
+        "autotune": tuned,
         "kernels": {"project_ms": proj_avg, "project_tflops": proj_tfs,
                     "loop_ms": loop_avg, "loop_gbs": loop_gbs,
                     "loop_bytes_per_block": loop_bytes_per_block,

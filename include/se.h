@@ -270,6 +270,39 @@ se_status se_extrapolate_plain(const se_tables* t, uint8_t* images,
                                size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Autotuning of the batched path                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Choices of the batched path for one (K, M*N, batch-size bucket): the
+ * workgroup shape of the iteration loop (waves x values per lane; every
+ * candidate has the padded row length se_table_ld(K), so tables stay
+ * valid) and the projection GEMM's tile (64 or 128). */
+typedef struct {
+  int32_t loop_waves, loop_vpl, proj_tile;
+  float loop_ms, proj_ms;   /* best measured times */
+} se_tune_result;
+
+/* Times every loop shape and projection tile on the caller's batch (the
+ * arguments of se_project / se_iterate; images are rewritten with the same
+ * values), `reps` runs each after one warm-up, synchronising on `stream`,
+ * and records the fastest; later batched calls with the same K, area and
+ * batch-size bucket (power of two) use it.  Process-wide, thread-safe. */
+se_status se_autotune_batch(const se_tables* t, uint8_t* images, int32_t n_img,
+                            int32_t H, int32_t W, const se_block* dev_blocks,
+                            int32_t n_blk, se_params prm, float* R,
+                            int32_t ldR, void* ws, size_t ws_bytes,
+                            int32_t reps, void* stream, se_tune_result* out);
+/* The records as text, one "K MN bucket waves vpl tile" line per entry;
+ * returns the length (without the terminating 0) and writes at most cap-1
+ * characters plus a terminating 0 into buf (may be NULL). */
+int32_t se_tune_export(char* buf, int32_t cap);
+/* Adds records from such text; SE_EINVAL for a malformed or out-of-range
+ * line (records before it are kept). */
+se_status se_tune_import(const char* text);
+/* Forgets every record (defaults apply again). */
+void se_tune_clear(void);
+
+/* ------------------------------------------------------------------------ */
 /* Model generation when every block has its own weighting function         */
 /* ------------------------------------------------------------------------ */
 

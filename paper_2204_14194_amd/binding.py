@@ -416,7 +416,8 @@ def _serve_lib():
 
 SERVE_EXPORTED = ("se_serve_create", "se_serve_submit", "se_serve_poll", "se_serve_wait",
                   "se_serve_stats_get", "se_serve_destroy")
-EXPORTED = EXPORTED + SERVE_EXPORTED
+TUNE_EXPORTED = ("se_autotune_batch", "se_tune_export", "se_tune_import", "se_tune_clear")
+EXPORTED = EXPORTED + SERVE_EXPORTED + TUNE_EXPORTED
 
 
 class Server:
@@ -484,3 +485,59 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# autotuning
+# ---------------------------------------------------------------------------
+class se_tune_result(C.Structure):
+    _fields_ = [("loop_waves", C.c_int32), ("loop_vpl", C.c_int32), ("proj_tile", C.c_int32),
+                ("loop_ms", C.c_float), ("proj_ms", C.c_float)]
+
+
+def _tune_lib():
+    L = lib()
+    if getattr(L, "_tune_ready", False):
+        return L
+    vp, i32 = C.c_void_p, C.c_int32
+    L.se_autotune_batch.restype = i32
+    L.se_autotune_batch.argtypes = [C.POINTER(se_tables), vp, i32, i32, i32, vp, i32, se_params,
+                                    vp, i32, vp, C.c_size_t, i32, vp, C.POINTER(se_tune_result)]
+    L.se_tune_export.restype = i32
+    L.se_tune_export.argtypes = [C.c_char_p, i32]
+    L.se_tune_import.restype = i32
+    L.se_tune_import.argtypes = [C.c_char_p]
+    L.se_tune_clear.restype = None
+    L.se_tune_clear.argtypes = []
+    L._tune_ready = True
+    return L
+
+
+def autotune_batch(t: Tables, images: torch.Tensor, dblocks: "DeviceBlocks", R: torch.Tensor,
+                   ws: torch.Tensor, gamma: float, iters: int, reps: int = 3, stream=None):
+    """se_autotune_batch: returns dict(loop_waves, loop_vpl, proj_tile, loop_ms, proj_ms)."""
+    L = _tune_lib()
+    n_img, H, W = images.shape
+    st = t.struct()
+    out = se_tune_result()
+    _check(L.se_autotune_batch(C.byref(st), _ptr(images), n_img, H, W, _ptr(dblocks.buf),
+                               dblocks.n, se_params(float(gamma), int(iters), 0), _ptr(R),
+                               R.shape[1], _ptr(ws), ws.numel(), int(reps), _stream(stream),
+                               C.byref(out)))
+    return {n: getattr(out, n) for n, _ in se_tune_result._fields_}
+
+
+def tune_export() -> str:
+    L = _tune_lib()
+    n = L.se_tune_export(None, 0)
+    buf = C.create_string_buffer(n + 1)
+    L.se_tune_export(buf, n + 1)
+    return buf.value.decode()
+
+
+def tune_import(text: str) -> None:
+    _check(_tune_lib().se_tune_import(text.encode()))
+
+
+def tune_clear() -> None:
+    _tune_lib().se_tune_clear()

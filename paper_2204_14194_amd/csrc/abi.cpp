@@ -96,7 +96,8 @@ static se_status project_into(const se_tables* t, const uint8_t* images, int H, 
   float* X = cv.take<float>((size_t)n_blk * ldX);
   launch_gather(images, H, W, dblk, n_blk, t->M, t->N, t->sqrtw, X, ldX, s);
   if ((st = check_launch("gather"))) return st;
-  return gemm_project_f32(t->Y, P, t->K, X, ldX, n_blk, P, R, ldR, 0, s);
+  const int tile = tune_lookup(t->K, P, n_blk).proj_tile;
+  return gemm_project_f32(t->Y, P, t->K, X, ldX, n_blk, P, R, ldR, tile, s);
 }
 
 static se_status check_blocks(const se_tables* t, int n_img, int H, int W, const se_block* blocks,
@@ -298,7 +299,8 @@ se_status se_iterate(const se_tables* t, const float* R, int32_t ldR, uint8_t* i
                 greedy_row_len(t->K));
   GreedyArgs ga = greedy_args(t, R, ldR, images, H, W, dev_blocks, n_blk, prm, sel, coef, g_loss,
                               g_loss_ld);
-  return launch_greedy(ga, n_blk, static_cast<hipStream_t>(stream));
+  const TuneChoice tc = tune_lookup(t->K, t->M * t->N, n_blk);
+  return launch_greedy(ga, n_blk, static_cast<hipStream_t>(stream), tc.loop_waves, tc.loop_vpl);
 }
 
 size_t se_extrapolate_batch_ws_bytes(const se_tables* t, int32_t n_blk) {
@@ -334,7 +336,8 @@ static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, in
                               g_loss_ld);
   if (!plain) {
     if ((st = project_into(t, images, H, W, dblk, n_blk, R, ldR, pws, s))) return st;
-    return launch_greedy(ga, n_blk, s);
+    const TuneChoice tc = tune_lookup(t->K, P, n_blk);
+    return launch_greedy(ga, n_blk, s, tc.loop_waves, tc.loop_vpl);
   }
   // one block at a time: gather, matrix-vector product (FP32), single-workgroup loop
   float* X = reinterpret_cast<float*>(pws);
@@ -344,7 +347,7 @@ static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, in
     launch_gemv(t->Y, t->K, P, X, R, s);
     if ((st = check_launch("gemv"))) return st;
     ga.blk0 = i;
-    if ((st = launch_greedy(ga, 1, s))) return st;
+    if ((st = launch_greedy(ga, 1, s, 0, 0))) return st;
   }
   return SE_OK;
 }

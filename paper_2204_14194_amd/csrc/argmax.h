@@ -52,6 +52,24 @@ __device__ __forceinline__ uint64_t make_key(float v, int idx) {
 }
 
 
+// Float max over the wave (all lanes see the result); v >= 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float fmax_step(float v) {
+  const float o = __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROWMASK, 0xF, false));
+  return fmaxf(v, o);
+}
+
+__device__ __forceinline__ float wave_max_f32(float v) {
+  v = fmax_step<kQuadXor1, 0xF>(v);
+  v = fmax_step<kQuadXor2, 0xF>(v);
+  v = fmax_step<kRowHalfMirror, 0xF>(v);
+  v = fmax_step<kRowMirror, 0xF>(v);
+  v = fmax_step<kRowBcast15, 0xA>(v);
+  v = fmax_step<kRowBcast31, 0xC>(v);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // Decode the winner of a key: index and signed value; an all-zero key (no
 // positive score anywhere) decodes to atom 0 with value 0.
 __device__ __forceinline__ void decode_key(uint64_t key, int K, int& u, float& rv) {

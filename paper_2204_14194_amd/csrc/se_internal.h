@@ -149,6 +149,16 @@ se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s);
 
 int greedy_waves_for(int K);   // 0 if K is too large
 int greedy_row_len(int K);     // padded row length (table row stride minimum)
-se_status launch_greedy(const GreedyArgs& a, int grid, hipStream_t s);
+// loop shapes (waves, values per lane) with the row length of K; returns count
+int greedy_shapes_for(int K, int* waves, int* vpl, int cap);
+// waves = 0: the tuned or default shape for K
+se_status launch_greedy(const GreedyArgs& a, int grid, hipStream_t s, int waves, int vpl);
+
+// tune.cpp -- choices recorded by the autotuner (or imported), per K and
+// batch size; 0 when nothing is recorded
+struct TuneChoice {
+  int loop_waves = 0, loop_vpl = 0, proj_tile = 0;
+};
+TuneChoice tune_lookup(int K, int P, int n_blk);
 
 }  // namespace sefase

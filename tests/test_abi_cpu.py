@@ -118,3 +118,19 @@ def test_workspace_sizes_grow_with_work():
     r = L.se_extrapolate_batch(C.byref(tb), fake, 1, 64, 64, blk, 1, B.se_params(0.5, 10, 0),
                                None, None, None, 0, fake, 1 << 30, None)
     assert r == B.SE_EINVAL
+
+
+def test_tune_records_roundtrip_and_validation():
+    B.tune_clear()
+    assert B.tune_export() == ""
+    B.tune_import("2048 1024 12 2 16 128\n4096 2304 8 4 16 64\n")
+    text = B.tune_export()
+    assert "2048 1024 12 2 16 128" in text and "4096 2304 8 4 16 64" in text
+    with pytest.raises(B.SEError):
+        B.tune_import("2048 1024 12 3 16 128\n")      # 3 x 16 has another row length
+    with pytest.raises(B.SEError):
+        B.tune_import("2048 1024 12 2 16 96\n")       # unknown tile
+    with pytest.raises(B.SEError):
+        B.tune_import("garbage")
+    B.tune_clear()
+    assert B.tune_export() == ""

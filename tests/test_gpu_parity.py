@@ -372,3 +372,36 @@ def test_ondemand_clustered_losses(area):
         assert ((got == np.clip(np.rint(gref), 0, 255)) | near).all()
     print(f"on-demand area {area}: {len(blocks)} blocks, identical selections "
           f"{agree}/{len(sample)}, max|dg|={worst:.3g}")
+
+
+def test_autotuned_shapes_give_identical_results():
+    """Every loop shape and projection tile computes the same per-atom
+    arithmetic and the same exact argmax, so the tuned configuration must
+    reproduce the default one bit for bit."""
+    d = synth.area32_inputs(16)
+    say("autotune: 16 images, 256 blocks, K=2048")
+    phi = synth.round_to_f32(d["phi"])
+    t, _, _ = shared_tables(d["images"], d["blocks"], upload_phi(phi), 32, 32, 0.8)
+    B.tune_clear()
+    sel0, coef0, g0, out0 = run_batch(t, d["images"], d["blocks"], 0.5, 100)
+    img = torch.from_numpy(d["images"]).to(dev())
+    db = B.DeviceBlocks(t, img, d["blocks"])
+    R = torch.empty((len(d["blocks"]), B.table_ld(2048)), dtype=torch.float32, device=dev())
+    ws = torch.empty(B.project_ws_bytes(t, len(d["blocks"])), dtype=torch.uint8, device=dev())
+    res = B.autotune_batch(t, img, db, R, ws, 0.5, 100, reps=2)
+    print(f"autotune: {res}")
+    assert (res["loop_waves"], res["loop_vpl"]) in {(1, 32), (2, 16), (4, 8)}
+    assert res["proj_tile"] in (64, 128)
+    assert B.tune_export().strip()
+    sel1, coef1, g1, out1 = run_batch(t, d["images"], d["blocks"], 0.5, 100)
+    np.testing.assert_array_equal(sel0, sel1)
+    np.testing.assert_array_equal(g0, g1)
+    np.testing.assert_array_equal(out0, out1)
+    # each alternative shape, forced through an imported record
+    for w, v in ((2, 16), (4, 8)):
+        B.tune_clear()
+        B.tune_import(f"2048 1024 8 {w} {v} 64\n")
+        sel2, _, g2, _ = run_batch(t, d["images"], d["blocks"], 0.5, 100)
+        np.testing.assert_array_equal(sel0, sel2)
+        np.testing.assert_array_equal(g0, g2)
+    B.tune_clear()
