@@ -18,13 +18,15 @@
 // table row stride), so no load needs a bounds check; padded atoms hold 0
 // and are never candidates.
 //
-// Selection: a lane scans its atoms in increasing index order keeping the
-// first strict maximum of |R~| (the position is tracked as a compile-time
-// code), then the wave reduces 64-bit keys
+// Selection: the wave's largest |R~| is found from per-lane maxima with a
+// DPP reduction; a lane that alone holds it reports its lowest-index atom
+// with that value (ballots over its groups of four atoms, then over the four
+// atoms of the first matching group).  When several lanes hold the maximum
+// (exact ties, e.g. parallel atoms), every lane scans its atoms in index
+// order and the wave reduces 64-bit keys
 //     |R~| bits << 32  |  (0xFFFF - k) << 16  |  sign << 15
-// with DPP lane permutations; the maximum key is the largest |R~| and, among
-// exact ties, the lowest index k.  Workgroups of several waves combine the
-// wave winners through LDS.
+// so the lowest index wins.  Workgroups of several waves combine the wave
+// winners' keys through LDS.
 #include "se_internal.h"
 #include "argmax.h"
 
@@ -77,20 +79,66 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy(GreedyArgs a) {
   const float gamma = a.gamma;
 
   for (int it = 0; it < a.iters; ++it) {
-    // ---- local candidate: first strict maximum of |R~| ------------------
-    float bv = 0.0f;
-    int code = 0;
+    // ---- this wave's largest |R~| and its lowest index -------------------
+    // Group maxima (4 atoms each) and the lane maximum, then the wave maximum
+    // by DPP.  When exactly one lane holds the maximum, a ballot per group
+    // and per atom of the winning group locates the lowest index in that
+    // lane (the lane's atoms increase with the group and position).  Ties
+    // across lanes take the exact 64-bit key scan.
+    float gm[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j)
+      gm[j] = fmaxf(fmaxf(fabsf(R[j][0]), fabsf(R[j][1])), fmaxf(fabsf(R[j][2]), fabsf(R[j][3])));
+    float lm = gm[0];
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (fabsf(R[j][e]) > fabsf(bv)) {
-          bv = R[j][e];
-          code = 4 * j + e;
+    for (int j = 1; j < NJ; ++j) lm = fmaxf(lm, gm[j]);
+    const float M = wave_max_f32(lm);
+    const uint64_t holders = __builtin_amdgcn_ballot_w64(lm == M);
+    uint64_t key;
+    if (M == 0.0f) {
+      key = 0;                                   // every score is zero
+    } else if (__builtin_popcountll(holders) == 1) {
+      const int L = __builtin_ctzll(holders);
+      int gsel = -1;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const uint64_t bj = __builtin_amdgcn_ballot_w64(gm[j] == M);
+        if (gsel < 0 && ((bj >> L) & 1ull)) gsel = j;
+      }
+      int code = 0;
+      uint32_t vbits = 0;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        if (j == gsel) {                         // uniform branch
+          int csel = -1;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const uint64_t be = __builtin_amdgcn_ballot_w64(fabsf(R[j][e]) == M);
+            if (csel < 0 && ((be >> L) & 1ull)) csel = e;
+          }
+          const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(R[j][0]), L);
+          const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(R[j][1]), L);
+          const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(R[j][2]), L);
+          const uint32_t r3 = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(R[j][3]), L);
+          vbits = csel == 0 ? r0 : csel == 1 ? r1 : csel == 2 ? r2 : r3;
+          code = 4 * j + csel;
         }
-    const int idx = 4 * ((code >> 2) * T + t) + (code & 3);
-    const uint64_t mine = make_key(bv, idx);
-    uint64_t key = wave_max_key((uint32_t)(mine >> 32), (uint32_t)mine);
+      }
+      key = make_key(__uint_as_float(vbits), 4 * ((code >> 2) * T + wave * 64 + L) + (code & 3));
+    } else {
+      float bv = 0.0f;
+      int c = 0;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (fabsf(R[j][e]) > fabsf(bv)) {
+            bv = R[j][e];
+            c = 4 * j + e;
+          }
+      const uint64_t mine = make_key(bv, 4 * ((c >> 2) * T + t) + (c & 3));
+      key = wave_max_key((uint32_t)(mine >> 32), (uint32_t)mine);
+    }
     if (WAVES > 1) {
       if (lane == 0) s_key[par][wave] = key;
       __syncthreads();
@@ -159,14 +207,17 @@ struct LoopShape {
   int waves, vpl;
 };
 static const LoopShape kShapes[] = {
-    {1, 8}, {1, 16}, {1, 24}, {1, 32}, {2, 24}, {2, 32}, {4, 24}, {4, 32},
-    {8, 24}, {8, 32}, {16, 24}, {16, 32},
+    {1, 8}, {1, 16}, {1, 24}, {1, 32}, {2, 8}, {2, 16}, {2, 24}, {2, 32}, {4, 8}, {4, 16},
+    {4, 24}, {4, 32}, {8, 8}, {8, 16}, {8, 24}, {8, 32}, {16, 24}, {16, 32},
 };
-
-static LoopShape shape_for(int K) {
+// The default shape for K: the smallest capacity >= K, then the fewest waves.
+// Only shapes with 24 or 32 values per lane are defaults; the others share
+// their capacity with a default and are alternatives for the tuner.
+static LoopShape default_shape(int K) {
   LoopShape best{0, 0};
   long long cap_best = 1LL << 40;
   for (const LoopShape& s : kShapes) {
+    if (s.vpl < 24 && !(s.waves == 1)) continue;
     const long long cap = 64LL * s.waves * s.vpl;
     if (cap >= K && (cap < cap_best || (cap == cap_best && s.waves < best.waves))) {
       best = s;
@@ -176,11 +227,23 @@ static LoopShape shape_for(int K) {
   return best;
 }
 
-int greedy_waves_for(int K) { return shape_for(K).waves; }
+int greedy_waves_for(int K) { return default_shape(K).waves; }
 
 int greedy_row_len(int K) {
-  const LoopShape s = shape_for(K);
+  const LoopShape s = default_shape(K);
   return 64 * s.waves * s.vpl;
+}
+
+int greedy_shapes_for(int K, int* waves, int* vpl, int cap) {
+  const int len = greedy_row_len(K);
+  int n = 0;
+  for (const LoopShape& s : kShapes)
+    if (64 * s.waves * s.vpl == len && n < cap) {
+      waves[n] = s.waves;
+      vpl[n] = s.vpl;
+      ++n;
+    }
+  return n;
 }
 
 template <int W, int V>
@@ -191,11 +254,17 @@ static void launch_shape(const GreedyArgs& a, int grid, hipStream_t s) {
     hipLaunchKernelGGL((k_greedy<W, V, false>), dim3(grid), dim3(64 * W), 0, s, a);
 }
 
-se_status launch_greedy(const GreedyArgs& a, int grid, hipStream_t s) {
+se_status launch_greedy(const GreedyArgs& a, int grid, hipStream_t s, int waves, int vpl) {
   if (grid <= 0) return SE_OK;
-  const LoopShape sh = shape_for(a.K);
-  const int cap = 64 * sh.waves * sh.vpl;
+  LoopShape sh = default_shape(a.K);
   if (sh.waves == 0) return fail(SE_EINVAL, "K=%d exceeds the largest loop configuration", a.K);
+  if (waves > 0) {
+    if (64 * waves * vpl != 64 * sh.waves * sh.vpl)
+      return fail(SE_EINVAL, "loop shape %dx%d does not match the row length of K=%d", waves,
+                  vpl, a.K);
+    sh = LoopShape{waves, vpl};
+  }
+  const int cap = 64 * sh.waves * sh.vpl;
   if (a.ldG < cap || a.ldR < cap)
     return fail(SE_EINVAL, "row strides (ldG=%d, ldR=%d) below the padded length %d", a.ldG,
                 a.ldR, cap);
@@ -204,10 +273,16 @@ se_status launch_greedy(const GreedyArgs& a, int grid, hipStream_t s) {
     case 116: launch_shape<1, 16>(a, grid, s); break;
     case 124: launch_shape<1, 24>(a, grid, s); break;
     case 132: launch_shape<1, 32>(a, grid, s); break;
+    case 208: launch_shape<2, 8>(a, grid, s); break;
+    case 216: launch_shape<2, 16>(a, grid, s); break;
     case 224: launch_shape<2, 24>(a, grid, s); break;
     case 232: launch_shape<2, 32>(a, grid, s); break;
+    case 408: launch_shape<4, 8>(a, grid, s); break;
+    case 416: launch_shape<4, 16>(a, grid, s); break;
     case 424: launch_shape<4, 24>(a, grid, s); break;
     case 432: launch_shape<4, 32>(a, grid, s); break;
+    case 808: launch_shape<8, 8>(a, grid, s); break;
+    case 816: launch_shape<8, 16>(a, grid, s); break;
     case 824: launch_shape<8, 24>(a, grid, s); break;
     case 832: launch_shape<8, 32>(a, grid, s); break;
     case 1624: launch_shape<16, 24>(a, grid, s); break;
