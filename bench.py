@@ -6,8 +6,11 @@ centred 8x8 losses (support width 12), dictionary = 2-D DCT-II 32x32 u 2-D
 Walsh-Hadamard 32x32 (K = 2048), w = 0.8^distance to the area centre on the
 support, gamma = 0.5, I = 100.  One step conceals every block of a batch of
 seeded synthetic 128x128 images (16 blocks per image, 256 images = 4096
-blocks by default): gather + initial projections (one MFMA GEMM) + the
-iteration loop + paste.  The tables of the shared weight pattern are built
+blocks by default): initial projections + the iteration loop + paste.  The
+dictionary's two halves are declared as transform parts (Section VI), so the
+initial projections are separable DCT-II / Walsh-Hadamard transforms of the
+weighted area signals (--no-parts: one MFMA GEMM against the whole
+dictionary instead).  The tables of the shared weight pattern are built
 once before timing (as the paper reports per-block times without table
 generation); their build time is reported separately as gram_ms.
 
@@ -144,6 +147,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (default: tune loop shape and GEMM tile on the "
                          "benchmark batch before timing)")
+    ap.add_argument("--no-parts", action="store_true",
+                    help="do not declare the dictionary's transform parts (projections by "
+                         "GEMM against every atom)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="before timing, copy a buffer of this many MiB once (a kernel of "
                          "known traffic for scaling memory counters)")
@@ -182,7 +188,8 @@ def main():
     torch.cuda.synchronize()
     g0.record(stream)
     w = B.area_weights(M, N, RHO, lost_d, blocks[:1])
-    t = B.weighted_gram(phi_d, w[0].contiguous(), M, N)
+    parts = () if args.no_parts else d["tx_parts"]
+    t = B.weighted_gram(phi_d, w[0].contiguous(), M, N, parts=parts)
     g1.record(stream)
     torch.cuda.synchronize()
     gram_ms = g0.elapsed_time(g1)
@@ -248,11 +255,14 @@ def main():
     plain_ms = [a.elapsed_time(b) for a, b in plain_lat]
     plain_bps = len(plain_lat) / (pt1 - pt0)
 
-    # roofline: algorithmic bytes of the loop kernel and flops of the projection GEMM
+    # roofline: algorithmic bytes of the loop kernel and flops of the projections
     P = M * N
     loss_px = 64
     loop_bytes_per_block = ITERS * (K_ATOMS + loss_px) * 4 + K_ATOMS * 4
-    proj_flops_per_block = 2.0 * K_ATOMS * P
+    # GEMM: 2 K P per block; transforms: two separable products per part,
+    # 2 P (M + N) flops each
+    proj_flops_per_block = (2.0 * K_ATOMS * P if args.no_parts
+                            else 2.0 * len(parts) * P * (M + N))
     loop_avg = float(np.mean(loop_ms))
     proj_avg = float(np.mean(proj_ms))
     loop_gbs = loop_bytes_per_block * nblk / (loop_avg * 1e-3) / 1e9
@@ -262,6 +272,12 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": loop_gbs / HBM_PEAK_GBS,
                 "traffic": measured_loop_traffic(args.images),
                 "bytes_per_launch": loop_bytes_per_block * nblk, "avg_ms": loop_avg}
+    elif not args.no_parts:
+        proj_bytes = nblk * (ldR * 4 + P)      # R written, the area's pixels read
+        roof = {"kernel": "k_project_tx (initial projections)", "bound": "hbm",
+                "achieved": proj_bytes / (proj_avg * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": proj_bytes / (proj_avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "traffic": None, "bytes_per_launch": proj_bytes, "avg_ms": proj_avg}
     else:
         roof = {"kernel": "k_gemm_nt_f32 (initial projections)", "bound": "mfma",
                 "achieved": proj_tfs, "peak": FP32_MFMA_PEAK_TFS, "unit": "TFLOP/s",
@@ -286,7 +302,9 @@ def main():
                         f"WHT 32x32), rho_hat=0.8, gamma=0.5, I=100; {args.images} seeded "
                         f"128x128 images x 16 blocks = {nblk} blocks per step; tables cached",
             "blocks_per_step": nblk, "K": K_ATOMS, "iters": ITERS, "area": [M, N],
-            "loss": [8, 8], "form": "batched (project GEMM + one workgroup per block)",
+            "loss": [8, 8],
+            "form": ("batched (project GEMM + one workgroup per block)" if args.no_parts else
+                     "batched (separable transforms + one workgroup per block)"),
         },
         "latency_ms": {"p50": percentile(step_ms, 50), "p99": percentile(step_ms, 99),
                        "what": "per step; every block of a step completes with it"},
@@ -300,7 +318,8 @@ def main():
         "kernels": {"project_ms": proj_avg, "project_tflops": proj_tfs,
                     "loop_ms": loop_avg, "loop_gbs": loop_gbs,
                     "loop_bytes_per_block": loop_bytes_per_block,
-                    "project_flops_per_block": proj_flops_per_block},
+                    "project_flops_per_block": proj_flops_per_block,
+                    "project_form": "gemm" if args.no_parts else "transform"},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -332,12 +351,12 @@ def _timed(fn, steps, warmup):
     return out
 
 
-def _shared_tables(B, torch, dev, images, blocks, phi, M, N, precision):
+def _shared_tables(B, torch, dev, images, blocks, phi, M, N, precision, parts=()):
     n_img, H, W = images.shape
     lost = np.stack([synth.lost_mask(H, W, blocks, i) for i in range(n_img)])
     w = B.area_weights(M, N, RHO, torch.from_numpy(lost).to(dev), blocks[:1])
     return B.weighted_gram(torch.from_numpy(phi.astype(np.float32)).to(dev), w[0].contiguous(),
-                           M, N, precision)
+                           M, N, precision, parts=parts)
 
 
 def bench_area48(args):
@@ -349,7 +368,8 @@ def bench_area48(args):
     n_img = max(1, args.images if args.images != 256 else 1)
     d = synth.area48_inputs(n_img)
     blocks = d["blocks"]
-    t = _shared_tables(B, torch, dev, d["images"], blocks, d["phi"], 48, 48, B.SE_FP32)
+    t = _shared_tables(B, torch, dev, d["images"], blocks, d["phi"], 48, 48, B.SE_FP32,
+                       () if args.no_parts else d["tx_parts"])
     img = torch.from_numpy(d["images"]).to(dev)
     ws = torch.empty(B.extrapolate_batch_ws_bytes(t, len(blocks)), dtype=torch.uint8, device=dev)
     arr = B.blocks_array(blocks)
@@ -384,17 +404,18 @@ def bench_clustered(args):
         it = [int(iters[i]) for i in idx]
         phi = torch.from_numpy(d["dicts"][area].astype(np.float32)).to(dev)
         w = B.area_weights(area, area, RHO, lost_d, bl)
-        groups.append((phi, area, w, bl, it, streams[k]))
+        groups.append((phi, area, w, bl, it, streams[k],
+                       () if args.no_parts else d["tx_parts"][area]))
 
     def step():
         cur = torch.cuda.current_stream()
-        for phi, area, w, bl, it, st in groups:
+        for phi, area, w, bl, it, st, parts in groups:
             st.wait_stream(cur)
             with torch.cuda.stream(st):
                 B.extrapolate_ondemand(phi, area, area, w, img, bl, 0.5, it, False, False, False,
-                                       stream=st)
-        for *_, st in groups:
-            cur.wait_stream(st)
+                                       stream=st, parts=parts)
+        for g in groups:
+            cur.wait_stream(g[5])
 
     ms = _timed(step, max(1, args.steps // 4), 1)
     med = float(np.median(ms))
@@ -425,7 +446,8 @@ def bench_area64(args):
         for _ in range(3):
             e0, e1 = _events(2)
             e0.record()
-            t = _shared_tables(B, torch, dev, d["images"], blocks, d["phi"], 64, 64, prec)
+            t = _shared_tables(B, torch, dev, d["images"], blocks, d["phi"], 64, 64, prec,
+                               () if args.no_parts else d["tx_parts"])
             e1.record()
             e1.synchronize()
             gram.append(e0.elapsed_time(e1))
@@ -454,12 +476,15 @@ def bench_serving(args):
     import torch
     from paper_2204_14194_amd import binding as B
     dev = torch.device("cuda:0")
+    def part(M, names, n_gauss=0):
+        return () if args.no_parts else synth.dictionary_parts(M, M, names, n_gauss)
     bases = [(torch.from_numpy(synth.dictionary(32, 32, ("dct", "wht")).astype(np.float32))
-              .to(dev), 32, 32),
+              .to(dev), 32, 32, part(32, ("dct", "wht"))),
              (torch.from_numpy(synth.dictionary(48, 48, ("dct", "gauss"), seed=101, n_gauss=1792)
-                               .astype(np.float32)).to(dev), 48, 48),
+                               .astype(np.float32)).to(dev), 48, 48,
+              part(48, ("dct", "gauss"), 1792)),
              (torch.from_numpy(synth.dictionary(64, 64, ("dct", "wht")).astype(np.float32))
-              .to(dev), 64, 64)]
+              .to(dev), 64, 64, part(64, ("dct", "wht")))]
     H, W = 1080, 1920
     n_frames = args.frames
     rng = np.random.default_rng(4)

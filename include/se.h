@@ -64,11 +64,32 @@ typedef enum { SE_FP32 = 0, SE_BF16X3 = 1 } se_precision;
 #define SE_DIAG_FP64 1u        /* always FP64                              */
 #define SE_DIAG_FP32 2u        /* always FP32                              */
 
+/* Known structure of a range of atoms (Section VI): rows first ..
+ * first + M*N - 1 of phi are the separable 2-D atoms of a discrete
+ * transform, atom k1*N + k2 = row k1 of the vertical 1-D transform times row
+ * k2 of the horizontal one.  For such atoms the weighted scalar products of
+ * a vector are that transform's coefficients of the weighted vector
+ * (eq. 21-23), which the library then computes as a separable transform
+ * instead of a product with the dictionary.
+ *   SE_PART_DCT2: orthonormal DCT-II rows, alpha_k cos(pi (2m+1) k / 2M)
+ *   SE_PART_WHT2: Walsh-Hadamard rows in natural (Sylvester) order,
+ *                 (-1)^popcount(m & k) / sqrt(M); M and N powers of two
+ * Parts need M, N <= 64; se_weighted_gram checks every declared atom
+ * against phi (|difference| <= 2e-6) and fails with SE_EINVAL otherwise. */
+#define SE_PART_DCT2 1
+#define SE_PART_WHT2 2
+typedef struct {
+  int32_t kind, first;
+} se_part;
+
 /* A dictionary (Section II: phi_k[m, n], k in the dictionary D).
- * phi: device, K x (M*N) float32, row-major. */
+ * phi: device, K x (M*N) float32, row-major.  n_parts (0..2) declared
+ * transform ranges, non-overlapping; every other atom is dense. */
 typedef struct {
   int32_t M, N, K;
   const float* phi;
+  int32_t n_parts;
+  se_part parts[2];
 } se_basis;
 
 /* One lost block and its extrapolation area L = A u B (Section II, Fig. 2).
@@ -103,6 +124,8 @@ typedef struct {
  *          summed in FP64, 0 if in FP32.
  *   precision : set by se_weighted_gram; the initial projections of blocks
  *          using these tables are computed in the same precision.
+ *   n_parts, parts : the dictionary's verified transform ranges; the
+ *          projections of those atoms are computed as transforms.
  *   Yhi, Ylo : K x (M*N) bfloat16 bit patterns, Y = Yhi + Ylo (hi = bf16(Y),
  *          lo = bf16(Y - hi)); required (non-NULL) for SE_BF16X3, unused
  *          for SE_FP32.                                                   */
@@ -117,6 +140,8 @@ typedef struct {
   int32_t precision;
   uint16_t* Yhi;
   uint16_t* Ylo;
+  int32_t n_parts;       /* copied from the dictionary by se_weighted_gram */
+  se_part parts[2];
 } se_tables;
 
 /* Model-generation parameters: gamma of eq. 8 (0 < gamma <= 1) and the
@@ -173,7 +198,8 @@ se_status se_area_weights(int32_t M, int32_t N, float rho_hat,
  * split into t->Yhi + t->Ylo and the products hi*hi + hi*lo + lo*hi are
  * accumulated in FP32 on the BF16 matrix cores), mirrored to the upper
  * triangle -- Algorithm 2 computes (|D|^2 + |D|)/2 products and mirrors the
- * rest.
+ * rest.  With declared transform parts the call first verifies them and
+ * synchronises `stream` once to read the verdict.
  * ws: device scratch of se_weighted_gram_ws_bytes(b, prec) bytes.
  * Errors: SE_EINVAL for a NULL pointer, K < 1, ldG < K or not a multiple
  * of 4, an unknown precision or flag, ws too small. */

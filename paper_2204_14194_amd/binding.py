@@ -20,6 +20,7 @@ SE_OK, SE_EINVAL, SE_ENOMEM, SE_EHIP, SE_EAGAIN, SE_EBUSY, SE_ENUMERIC, SE_ECANC
     0, -1, -2, -3, -4, -5, -6, -7)
 SE_FP32, SE_BF16X3 = 0, 1
 SE_DIAG_AUTO, SE_DIAG_FP64, SE_DIAG_FP32 = 0, 1, 2
+SE_PART_DCT2, SE_PART_WHT2 = 1, 2
 
 # every symbol include/se.h declares
 EXPORTED = (
@@ -37,8 +38,38 @@ class SEError(RuntimeError):
         self.code = code
 
 
+class se_part(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("first", C.c_int32)]
+
+
 class se_basis(C.Structure):
-    _fields_ = [("M", C.c_int32), ("N", C.c_int32), ("K", C.c_int32), ("phi", C.c_void_p)]
+    _fields_ = [("M", C.c_int32), ("N", C.c_int32), ("K", C.c_int32), ("phi", C.c_void_p),
+                ("n_parts", C.c_int32), ("parts", se_part * 2)]
+
+
+_PART_NAMES = {"dct": SE_PART_DCT2, "wht": SE_PART_WHT2}
+
+
+def _parts_arg(parts) -> tuple:
+    """(kind, first) pairs; kind an SE_PART_* value or 'dct' / 'wht'."""
+    parts = tuple((_PART_NAMES[k] if isinstance(k, str) else int(k), int(f)) for k, f in parts)
+    if len(parts) > 2:
+        raise ValueError("at most two transform parts")
+    return parts
+
+
+def _part_array(parts):
+    arr = (se_part * 2)()
+    for i, (k, f) in enumerate(parts):
+        arr[i] = se_part(k, f)
+    return arr
+
+
+def make_basis(M: int, N: int, K: int, phi_ptr, parts=()) -> se_basis:
+    """se_basis for a dictionary at device address ``phi_ptr``; ``parts`` is a
+    sequence of (SE_PART_*, first atom) transform ranges."""
+    parts = _parts_arg(parts)
+    return se_basis(M, N, K, phi_ptr, len(parts), _part_array(parts))
 
 
 class se_block(C.Structure):
@@ -49,7 +80,8 @@ class se_tables(C.Structure):
     _fields_ = [("M", C.c_int32), ("N", C.c_int32), ("K", C.c_int32), ("ldG", C.c_int32),
                 ("G", C.c_void_p), ("D", C.c_void_p), ("Y", C.c_void_p),
                 ("sqrtw", C.c_void_p), ("phi", C.c_void_p), ("info", C.c_void_p),
-                ("precision", C.c_int32), ("Yhi", C.c_void_p), ("Ylo", C.c_void_p)]
+                ("precision", C.c_int32), ("Yhi", C.c_void_p), ("Ylo", C.c_void_p),
+                ("n_parts", C.c_int32), ("parts", se_part * 2)]
 
 
 class se_params(C.Structure):
@@ -189,13 +221,15 @@ class Tables:
     precision: int
     Yhi: Optional[torch.Tensor] = None
     Ylo: Optional[torch.Tensor] = None
+    parts: tuple = ()
 
     def struct(self) -> se_tables:
         return se_tables(self.M, self.N, self.K, self.ldG, self.G.data_ptr(), self.D.data_ptr(),
                          self.Y.data_ptr(), self.sqrtw.data_ptr(), self.phi.data_ptr(),
                          self.info.data_ptr(), self.precision,
                          self.Yhi.data_ptr() if self.Yhi is not None else None,
-                         self.Ylo.data_ptr() if self.Ylo is not None else None)
+                         self.Ylo.data_ptr() if self.Ylo is not None else None,
+                         len(self.parts), _part_array(self.parts))
 
     def nbytes(self) -> int:
         parts = [self.G, self.D, self.Y, self.sqrtw]
@@ -204,9 +238,11 @@ class Tables:
 
 
 def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
-                  precision: int = SE_FP32, flags: int = SE_DIAG_AUTO, stream=None) -> Tables:
+                  precision: int = SE_FP32, flags: int = SE_DIAG_AUTO, stream=None,
+                  parts=()) -> Tables:
     """se_weighted_gram (Algorithm 2) for dictionary ``phi`` (K, M*N) and weight
-    pattern ``w`` (M*N,)."""
+    pattern ``w`` (M*N,).  ``parts``: declared transform ranges, as
+    (SE_PART_*, first atom) pairs (verified by the library)."""
     L = lib()
     _dev_f32(phi, "phi")
     _dev_f32(w, "w")
@@ -224,7 +260,8 @@ def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
     if precision == SE_BF16X3:
         t.Yhi = torch.empty((K, M * N), dtype=torch.int16, device=dev)
         t.Ylo = torch.empty((K, M * N), dtype=torch.int16, device=dev)
-    b = se_basis(M, N, K, phi.data_ptr())
+    t.parts = _parts_arg(parts)
+    b = make_basis(M, N, K, phi.data_ptr(), t.parts)
     nb = L.se_weighted_gram_ws_bytes(C.byref(b), int(precision))
     ws = _workspace(nb, dev)
     st = t.struct()
@@ -330,7 +367,8 @@ def iterate(t: Tables, R: torch.Tensor, images: torch.Tensor, dblocks: DeviceBlo
 
 def extrapolate_ondemand(phi: torch.Tensor, M: int, N: int, w: torch.Tensor,
                          images: torch.Tensor, blocks: Sequence, gamma: float, iters,
-                         want_sel=True, want_coef=True, want_g=True, ws=None, stream=None):
+                         want_sel=True, want_coef=True, want_g=True, ws=None, stream=None,
+                         parts=()):
     """se_extrapolate_ondemand: per-block weights ``w`` (n_blk, M*N); ``iters``
     an int or a per-block sequence.  Returns (sel, coef, g_loss)."""
     L = lib()
@@ -349,7 +387,7 @@ def extrapolate_ondemand(phi: torch.Tensor, M: int, N: int, w: torch.Tensor,
     coef = torch.empty((n, imax), dtype=torch.float32, device=dev) if want_coef else None
     gld = max([b.lh * b.lw for b in blocks] + [1])
     g = torch.zeros((n, gld), dtype=torch.float32, device=dev) if want_g else None
-    bas = se_basis(M, N, phi.shape[0], phi.data_ptr())
+    bas = make_basis(M, N, phi.shape[0], phi.data_ptr(), parts)
     nb = L.se_extrapolate_ondemand_ws_bytes(C.byref(bas), n, gld)
     if ws is None:
         ws = _workspace(nb, dev)
@@ -422,8 +460,8 @@ EXPORTED = EXPORTED + SERVE_EXPORTED + TUNE_EXPORTED
 
 class Server:
     """se_serve_*: a continuous-batching concealment server.  ``bases`` is a
-    list of (phi (K, M*N) float32 CUDA tensor, M, N); the tensors must stay
-    alive as long as the server."""
+    list of (phi (K, M*N) float32 CUDA tensor, M, N) or (phi, M, N, parts); the
+    tensors must stay alive as long as the server."""
 
     def __init__(self, bases, frame_H: int, frame_W: int, max_slots: int = 8,
                  max_queue: int = 64, n_streams: int = 4, rho_hat: float = 0.8,
@@ -431,9 +469,10 @@ class Server:
         L = _serve_lib()
         self._bases = [b[0] for b in bases]
         arr = (se_basis * len(bases))()
-        for i, (phi, M, N) in enumerate(bases):
+        for i, b in enumerate(bases):
+            phi, M, N = b[:3]
             _dev_f32(phi, "phi")
-            arr[i] = se_basis(M, N, phi.shape[0], phi.data_ptr())
+            arr[i] = make_basis(M, N, phi.shape[0], phi.data_ptr(), b[3] if len(b) > 3 else ())
         cfg = se_serve_config(device, frame_H, frame_W, max_slots, max_queue, n_streams,
                               float(rho_hat), int(hbm_budget_bytes))
         h = C.c_void_p()

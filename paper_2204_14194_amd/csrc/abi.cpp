@@ -45,6 +45,34 @@ static se_status upload_blocks(const se_block* blocks, int n_blk, DevBlock* dst,
   return SE_OK;
 }
 
+static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Declared transform parts: known kinds, inside [0, K), disjoint, areas up to
+// 64 x 64 (powers of two for Walsh-Hadamard).
+static se_status check_parts(int M, int N, int K, int n_parts, const se_part* parts) {
+  if (n_parts < 0 || n_parts > 2) return fail(SE_EINVAL, "n_parts=%d must be 0, 1 or 2", n_parts);
+  if (n_parts == 0) return SE_OK;
+  if (M > 64 || N > 64) return fail(SE_EINVAL, "transform parts need M, N <= 64 (got %dx%d)", M, N);
+  const int P = M * N;
+  for (int q = 0; q < n_parts; ++q) {
+    const se_part& p = parts[q];
+    if (p.kind != SE_PART_DCT2 && p.kind != SE_PART_WHT2)
+      return fail(SE_EINVAL, "part %d: unknown kind %d", q, p.kind);
+    if (p.kind == SE_PART_WHT2 && (!is_pow2(M) || !is_pow2(N)))
+      return fail(SE_EINVAL, "part %d: Walsh-Hadamard needs power-of-two M, N", q);
+    if (p.first < 0 || (long long)p.first + P > K)
+      return fail(SE_EINVAL, "part %d: atoms %d .. %d outside the dictionary", q, p.first,
+                  p.first + P - 1);
+  }
+  if (n_parts == 2 && parts[0].first < parts[1].first + P && parts[1].first < parts[0].first + P)
+    return fail(SE_EINVAL, "parts overlap");
+  return SE_OK;
+}
+
+se_status check_basis_parts(const se_basis* b) {
+  return check_parts(b->M, b->N, b->K, b->n_parts, b->parts);
+}
+
 static se_status check_tables(const se_tables* t) {
   if (!t) return fail(SE_EINVAL, "tables is NULL");
   if (t->M < 1 || t->N < 1 || t->K < 1) return fail(SE_EINVAL, "bad table shape M=%d N=%d K=%d", t->M, t->N, t->K);
@@ -59,7 +87,7 @@ static se_status check_tables(const se_tables* t) {
     return fail(SE_EINVAL, "unknown table precision %d", t->precision);
   if (t->precision == SE_BF16X3 && (!t->Yhi || !t->Ylo))
     return fail(SE_EINVAL, "BF16X3 tables need Yhi and Ylo");
-  return SE_OK;
+  return check_parts(t->M, t->N, t->K, t->n_parts, t->parts);
 }
 
 static inline int round8(int v) { return (v + 7) & ~7; }
@@ -77,12 +105,36 @@ static size_t project_ws(const se_tables* t, int n_blk) {
   return cv.off + 256;
 }
 
-// gather + projection GEMM in the tables' precision; ws holds project_ws().
+// Atom ranges [lo, hi) not covered by the tables' transform parts.
+static int dense_ranges(const se_tables* t, int lo[3], int hi[3]) {
+  const int P = t->M * t->N;
+  int f[2] = {0, 0}, n = t->n_parts;
+  for (int q = 0; q < n; ++q) f[q] = t->parts[q].first;
+  if (n == 2 && f[1] < f[0]) std::swap(f[0], f[1]);
+  int c = 0, r = 0;
+  for (int q = 0; q < n; ++q) {
+    if (f[q] > c) { lo[r] = c; hi[r] = f[q]; ++r; }
+    c = f[q] + P;
+  }
+  if (c < t->K) { lo[r] = c; hi[r] = t->K; ++r; }
+  return r;
+}
+
+// gather + projection GEMM in the tables' precision, over the dense atoms;
+// the transform parts as separable transforms.  ws holds project_ws().
 static se_status project_into(const se_tables* t, const uint8_t* images, int H, int W,
                               const se_block* dblk, int n_blk, float* R, int ldR, void* ws,
                               hipStream_t s) {
   se_status st;
   const int P = t->M * t->N;
+  int lo[3] = {0, 0, 0}, hi[3] = {t->K, 0, 0};
+  int nr = 1;
+  if (t->n_parts > 0) {
+    if ((st = project_tx(t, images, H, W, dblk, n_blk, R, ldR, s))) return st;
+    nr = dense_ranges(t, lo, hi);
+    if (nr == 0) return SE_OK;
+  }
+  const bool pad = t->n_parts == 0;   // else the transform kernel wrote the padding
   Carver cv(ws);
   if (t->precision == SE_BF16X3) {
     const int ldX = round8(P);
@@ -90,14 +142,24 @@ static se_status project_into(const se_tables* t, const uint8_t* images, int H, 
     uint16_t* xl = cv.take<uint16_t>((size_t)n_blk * ldX);
     launch_gather_split(images, H, W, dblk, n_blk, t->M, t->N, t->sqrtw, xh, xl, ldX, s);
     if ((st = check_launch("gather_split"))) return st;
-    return gemm_project_bf16x3(t->Yhi, t->Ylo, P, t->K, xh, xl, ldX, n_blk, P, R, ldR, s);
+    for (int r = 0; r < nr; ++r) {
+      const size_t off = (size_t)lo[r] * P;
+      if ((st = gemm_project_bf16x3(t->Yhi + off, t->Ylo + off, P, hi[r] - lo[r], xh, xl, ldX,
+                                    n_blk, P, R + lo[r], ldR, s, pad)))
+        return st;
+    }
+    return SE_OK;
   }
   const int ldX = round4(P);
   float* X = cv.take<float>((size_t)n_blk * ldX);
   launch_gather(images, H, W, dblk, n_blk, t->M, t->N, t->sqrtw, X, ldX, s);
   if ((st = check_launch("gather"))) return st;
   const int tile = tune_lookup(t->K, P, n_blk).proj_tile;
-  return gemm_project_f32(t->Y, P, t->K, X, ldX, n_blk, P, R, ldR, tile, s);
+  for (int r = 0; r < nr; ++r)
+    if ((st = gemm_project_f32(t->Y + (size_t)lo[r] * P, P, hi[r] - lo[r], X, ldX, n_blk, P,
+                               R + lo[r], ldR, tile, s, pad)))
+      return st;
+  return SE_OK;
 }
 
 static se_status check_blocks(const se_tables* t, int n_img, int H, int W, const se_block* blocks,
@@ -165,6 +227,7 @@ size_t se_weighted_gram_ws_bytes(const se_basis* b, se_precision prec) {
   const size_t K = (size_t)b->K;
   cv.take<float>(K);
   cv.take<double>(K);
+  cv.take<int32_t>(1);
   return cv.off + 256;
 }
 
@@ -181,6 +244,8 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
   t->K = b->K;
   t->phi = b->phi;
   t->precision = (int32_t)prec;
+  t->n_parts = b->n_parts;
+  for (int q = 0; q < 2; ++q) t->parts[q] = q < b->n_parts ? b->parts[q] : se_part{0, 0};
   se_status st = check_tables(t);
   if (st) return st;
   if (!ws || ws_bytes < se_weighted_gram_ws_bytes(b, prec)) return fail(SE_ENOMEM, "workspace too small");
@@ -189,6 +254,24 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
   Carver cv(ws);
   float* diag32 = cv.take<float>((size_t)K);
   double* diag64 = cv.take<double>((size_t)K);
+  int32_t* flag = cv.take<int32_t>(1);
+  if (b->n_parts > 0) {
+    // the projections of declared parts are computed from their definition,
+    // so the declaration must match the atoms actually given
+    if (hipMemsetAsync(flag, 0, sizeof(int32_t), s) != hipSuccess)
+      return fail(SE_EHIP, "flag clear failed");
+    for (int q = 0; q < b->n_parts; ++q)
+      if ((st = check_part(b->phi, b->M, b->N, b->parts[q].kind, b->parts[q].first, flag, s)))
+        return st;
+    int32_t bad = 0;
+    if (hipMemcpyAsync(&bad, flag, sizeof(bad), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(SE_EHIP, "part verification: %s", hipGetErrorString(hipGetLastError()));
+    if (bad) {
+      t->n_parts = 0;
+      return fail(SE_EINVAL, "a declared transform part does not match phi");
+    }
+  }
   launch_diag(b->phi, w, K, P, diag32, diag64, s);
   if ((st = check_launch("diag"))) return st;
   launch_finalize_d(diag32, diag64, w, K, P, (int)flags, prec == SE_BF16X3 ? 1 : 0, t->D, t->sqrtw,
@@ -386,6 +469,7 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* im
   if (n_img < 1 || H < 1 || W < 1) return fail(SE_EINVAL, "bad image batch");
   if (n_blk < 0 || (n_blk > 0 && !blocks)) return fail(SE_EINVAL, "bad block list");
   se_status st;
+  if ((st = check_basis_parts(b))) return st;
   if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
   int max_loss = 1, iters_max = 0;
   std::vector<int> it((size_t)n_blk);

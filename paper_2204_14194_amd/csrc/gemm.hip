@@ -300,9 +300,10 @@ se_status gemm_syrk_f32(const float* Y, int ldy, int K, int P, float* G, int ldg
 }
 
 se_status gemm_project_f32(const float* Y, int ldy, int K, const float* X, int ldx, int n_blk,
-                           int P, float* R, int ldr, int tile, hipStream_t s) {
+                           int P, float* R, int ldr, int tile, hipStream_t s, bool pad) {
   // S = Y X^T (atoms x blocks), stored transposed: R[b][k]; atoms K .. ldr-1 as 0
-  return dispatch_f32<kStoreTransposed>(Y, ldy, X, ldx, R, ldr, K, n_blk, ldr, n_blk, P, tile, s);
+  return dispatch_f32<kStoreTransposed>(Y, ldy, X, ldx, R, ldr, K, n_blk, pad ? ldr : K, n_blk, P,
+                                        tile, s);
 }
 
 }  // namespace sefase

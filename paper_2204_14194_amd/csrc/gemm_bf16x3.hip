@@ -201,7 +201,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt_bf16x3(
           v.z = r0 + 2 < Ma ? acc[i][j][2] : 0.0f;
           v.w = r0 + 3 < Ma ? acc[i][j][3] : 0.0f;
           float* dst = C + (size_t)c * ldc + r0;
-          if ((ldc & 3) == 0 && r0 + 3 < Mst) {
+          if ((ldc & 3) == 0 && (reinterpret_cast<uintptr_t>(C) & 15) == 0 && r0 + 3 < Mst) {
             *reinterpret_cast<float4*>(dst) = v;
           } else {
             if (r0 + 0 < Mst) dst[0] = v.x;
@@ -292,9 +292,9 @@ se_status gemm_syrk_bf16x3(const uint16_t* Yhi, const uint16_t* Ylo, int ldy, in
 
 se_status gemm_project_bf16x3(const uint16_t* Yhi, const uint16_t* Ylo, int ldy, int K,
                               const uint16_t* Xhi, const uint16_t* Xlo, int ldx, int n_blk, int P,
-                              float* R, int ldr, hipStream_t s) {
-  return dispatch_h<hStoreTransposed>(Yhi, Ylo, ldy, Xhi, Xlo, ldx, R, ldr, K, n_blk, ldr, n_blk,
-                                      P, s);
+                              float* R, int ldr, hipStream_t s, bool pad) {
+  return dispatch_h<hStoreTransposed>(Yhi, Ylo, ldy, Xhi, Xlo, ldx, R, ldr, K, n_blk,
+                                      pad ? ldr : K, n_blk, P, s);
 }
 
 }  // namespace sefase

@@ -71,16 +71,17 @@ void launch_split_bf16(const float* x, size_t n, uint16_t* hi, uint16_t* lo,
 // G = Y Y^T (lower-triangle tiles, mirrored); G is K x ldg.
 se_status gemm_syrk_f32(const float* Y, int ldy, int K, int P, float* G, int ldg,
                         hipStream_t s);
-// R[b][k] = sum_p X[b][p] Y[k][p] for k < K, 0 for K <= k < ldr.
-// tile: 0 = automatic, 64 or 128.
+// R[b][k] = sum_p X[b][p] Y[k][p] for k < K, and 0 for K <= k < ldr when
+// pad (else those columns are left alone).  tile: 0 = automatic, 64 or 128.
 se_status gemm_project_f32(const float* Y, int ldy, int K, const float* X, int ldx,
-                           int n_blk, int P, float* R, int ldr, int tile, hipStream_t s);
+                           int n_blk, int P, float* R, int ldr, int tile, hipStream_t s,
+                           bool pad = true);
 // gemm_bf16x3.hip -- the same two products from split-bf16 operands
 se_status gemm_syrk_bf16x3(const uint16_t* Yhi, const uint16_t* Ylo, int ldy, int K, int P,
                            float* G, int ldg, hipStream_t s);
 se_status gemm_project_bf16x3(const uint16_t* Yhi, const uint16_t* Ylo, int ldy, int K,
                               const uint16_t* Xhi, const uint16_t* Xlo, int ldx, int n_blk, int P,
-                              float* R, int ldr, hipStream_t s);
+                              float* R, int ldr, hipStream_t s, bool pad = true);
 
 // project.hip -- X[b][p] = sqrt(w_p) s_b[p] and the per-block GEMV
 void launch_gather(const uint8_t* images, int H, int W, const DevBlock* blk,
@@ -92,6 +93,17 @@ void launch_gemv(const float* Y, int K, int P, const float* x, float* r,
 void launch_gather_split(const uint8_t* images, int H, int W, const DevBlock* blk,
                          int n_blk, int M, int N, const float* sqrtw, uint16_t* Xhi,
                          uint16_t* Xlo, int ldX, hipStream_t s);
+
+// transform.hip -- declared transform parts of a dictionary (Section VI)
+// sets *dflag (device) to 1 if an atom of the part differs from its definition
+se_status check_part(const float* phi, int M, int N, int kind, int first, int* dflag,
+                     hipStream_t s);
+// R[b][first + k] of every part of t, and 0 in columns K .. ldR-1
+se_status project_tx(const se_tables* t, const uint8_t* images, int H, int W,
+                     const DevBlock* blk, int n_blk, float* R, int ldR, hipStream_t s);
+size_t tx_lds_bytes(int M, int N, int n_parts);
+// abi.cpp -- the host-side checks of a basis' part declaration
+se_status check_basis_parts(const se_basis* b);
 
 // greedy.hip -- the iteration loop of Algorithm 3
 struct GreedyArgs {

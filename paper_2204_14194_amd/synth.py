@@ -33,10 +33,10 @@ import numpy as np
 
 __all__ = [
     "synth_image", "dct_rows", "wht_rows", "separable_atoms", "dct2_atoms",
-    "wht2_atoms", "gaussian_atoms", "dictionary", "Block", "grid_layout",
+    "wht2_atoms", "gaussian_atoms", "dictionary", "dictionary_parts", "Block", "grid_layout",
     "parity_lattice_layout", "lost_mask", "round_to_f32", "area32_inputs",
     "area48_inputs", "area64_inputs", "clustered_layout", "clustered_dictionaries",
-    "clustered_inputs", "frame_losses",
+    "clustered_dictionary_parts", "clustered_inputs", "frame_losses",
 ]
 
 
@@ -149,6 +149,19 @@ def dictionary(M: int, N: int, parts: Sequence[str], seed: int = 101,
     return np.ascontiguousarray(np.concatenate(blocks, axis=0))
 
 
+def dictionary_parts(M: int, N: int, parts: Sequence[str], n_gauss: int = 0):
+    """Where the transform sub-dictionaries of dictionary(M, N, parts, ...)
+    start: a list of (name, first atom) for each 'dct' and 'wht' part."""
+    out, first = [], 0
+    for p in parts:
+        if p in ("dct", "wht"):
+            out.append((p, first))
+            first += M * N
+        else:
+            first += n_gauss
+    return out
+
+
 def round_to_f32(a: np.ndarray) -> np.ndarray:
     """Round to the nearest float32 and return float64: the exact values a
     float32 device buffer holds, so both sides start from identical inputs."""
@@ -229,6 +242,7 @@ def area32_inputs(n_img: int = 1, seed0: int = 0):
     blocks = grid_layout(128, 128, 32, 8, n_img)
     phi = dictionary(32, 32, ("dct", "wht"))
     return dict(images=imgs, blocks=blocks, phi=phi, M=32, N=32,
+                tx_parts=dictionary_parts(32, 32, ("dct", "wht")),
                 rho_hat=0.8, gamma=0.5, iters=100)
 
 
@@ -241,6 +255,7 @@ def area48_inputs(n_img: int = 1, seed0: int = 1, layout_seed: int = 7):
     blocks = parity_lattice_layout(512, 512, 16, 48, layout_seed, 16, n_img)
     phi = dictionary(48, 48, ("dct", "gauss"), seed=101, n_gauss=1792)
     return dict(images=imgs, blocks=blocks, phi=phi, M=48, N=48,
+                tx_parts=dictionary_parts(48, 48, ("dct", "gauss"), 1792),
                 rho_hat=0.8, gamma=0.5, iters=200)
 
 
@@ -251,6 +266,7 @@ def area64_inputs(n_img: int = 1, seed0: int = 300):
     blocks = grid_layout(2048, 2048, 64, 16, n_img)
     phi = dictionary(64, 64, ("dct", "wht"))
     return dict(images=imgs, blocks=blocks, phi=phi, M=64, N=64,
+                tx_parts=dictionary_parts(64, 64, ("dct", "wht")),
                 rho_hat=0.8, gamma=0.5, iters=300)
 
 
@@ -315,6 +331,13 @@ def clustered_dictionaries():
             48: dictionary(48, 48, ("dct", "gauss"), seed=148, n_gauss=2304)}
 
 
+def clustered_dictionary_parts():
+    """The transform ranges of clustered_dictionaries(), per area size."""
+    return {24: dictionary_parts(24, 24, ("dct", "gauss"), 576),
+            32: dictionary_parts(32, 32, ("dct", "wht")),
+            48: dictionary_parts(48, 48, ("dct", "gauss"), 2304)}
+
+
 def clustered_inputs(n_img: int = 8, blocks_per_img: int = 500, seed0: int = 200,
                 iter_range=(100, 200)):
     """8 seeded 1024x1024 frames with clustered/burst losses, 500 blocks each;
@@ -326,7 +349,7 @@ def clustered_inputs(n_img: int = 8, blocks_per_img: int = 500, seed0: int = 200
     rng = np.random.default_rng(seed0 + 99)
     iters = rng.integers(iter_range[0], iter_range[1] + 1, size=len(blocks))
     return dict(images=imgs, blocks=blocks, iters=iters, dicts=clustered_dictionaries(),
-                rho_hat=0.8, gamma=0.5)
+                tx_parts=clustered_dictionary_parts(), rho_hat=0.8, gamma=0.5)
 
 
 def frame_losses(H: int, W: int, coverage: float, seed: int, p16: float = 0.5,

@@ -87,6 +87,43 @@ def test_rejects_bad_arguments_on_host():
     assert r == B.SE_EINVAL
 
 
+def test_rejects_bad_transform_parts_on_host():
+    """Declared transform parts (Section VI) are validated before any device
+    work: known kind, inside the dictionary, disjoint, M, N <= 64, powers of
+    two for Walsh-Hadamard."""
+    L = B.lib()
+    fake = C.c_void_p(0x1000)
+    t = _tables_struct(K=2048, M=32, N=32)
+    cases = [
+        ((3, 0),), ((B.SE_PART_DCT2, -1),), ((B.SE_PART_DCT2, 1025),),
+        ((B.SE_PART_DCT2, 0), (B.SE_PART_WHT2, 1000)),
+        ((B.SE_PART_DCT2, 0), (B.SE_PART_WHT2, 1024), (B.SE_PART_DCT2, 0)),
+    ]
+    for parts in cases:
+        bas = B.se_basis(32, 32, 2048, 0x1000, len(parts), B._part_array(parts[:2]))
+        r = L.se_weighted_gram(C.byref(bas), fake, 0, 0, C.byref(t), fake, 1 << 20, None)
+        assert r == B.SE_EINVAL, parts
+    # Walsh-Hadamard needs power-of-two sides; transforms need sides <= 64
+    t48 = _tables_struct(K=4096, M=48, N=48)
+    bas = B.make_basis(48, 48, 4096, 0x1000, [(B.SE_PART_WHT2, 0)])
+    assert L.se_weighted_gram(C.byref(bas), fake, 0, 0, C.byref(t48), fake, 1 << 20,
+                              None) == B.SE_EINVAL
+    assert b"power-of-two" in L.se_last_error()
+    t80 = _tables_struct(K=6400, M=80, N=80)
+    bas = B.make_basis(80, 80, 6400, 0x1000, [(B.SE_PART_DCT2, 0)])
+    assert L.se_weighted_gram(C.byref(bas), fake, 0, 0, C.byref(t80), fake, 1 << 20,
+                              None) == B.SE_EINVAL
+    # hand-built tables with an overlapping declaration are refused by the loop calls
+    tb = _tables_struct(K=2048, M=32, N=32)
+    tb.n_parts = 2
+    tb.parts[0] = B.se_part(B.SE_PART_DCT2, 0)
+    tb.parts[1] = B.se_part(B.SE_PART_DCT2, 512)
+    blk = (B.se_block * 1)(B.se_block(0, 0, 0, 2, 2, 4, 4, 0))
+    r = L.se_extrapolate_batch(C.byref(tb), fake, 1, 64, 64, blk, 1, B.se_params(0.5, 10, 0),
+                               None, None, None, 0, fake, 1 << 30, None)
+    assert r == B.SE_EINVAL and b"overlap" in L.se_last_error()
+
+
 def test_table_ld_is_padded_row_length():
     assert B.table_ld(2048) == 2048
     assert B.table_ld(2000) == 2048

@@ -409,3 +409,24 @@ def test_generators_deterministic():
     g1 = synth.gaussian_atoms(8, 8, 5, 101)
     np.testing.assert_allclose(np.linalg.norm(g1, axis=1), 1.0)
     np.testing.assert_array_equal(g1, synth.gaussian_atoms(8, 8, 5, 101))
+
+
+def test_weighted_projection_is_transform_of_weighted_signal():
+    """Section VI (eq. 21-22): for atoms of a discrete transform the weighted
+    scalar products of eq. 12 are that transform's coefficients of the
+    weighted signal w s, here with a general (non-unit) weighting function."""
+    M = N = 16
+    phi = synth.dictionary(M, N, ("dct", "wht"))
+    _, s, w = _rng_case(M, N, 0, seed=31, loss=(5, 6, 4, 4), gauss=False)
+    C, D = oracle.table_generation(phi, w)
+    f = oracle.fase(s, w, phi, C, D, 0.5, 1, keep_R=True)
+    x = (w * s).reshape(M, N)
+    dct = scipy.fft.dctn(x, type=2, norm="ortho").reshape(-1)
+    H = scipy.linalg.hadamard(M) / np.sqrt(M)
+    wht = (H @ x @ H.T).reshape(-1)
+    np.testing.assert_allclose(f.R_history[0][:M * N], dct, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(f.R_history[0][M * N:], wht, rtol=0, atol=1e-9)
+    # and a table column is the transform of w times the other atom (eq. 23)
+    l = 37
+    col = scipy.fft.dctn((w * phi[l]).reshape(M, N), norm="ortho").reshape(-1)
+    np.testing.assert_allclose(C[:M * N, l], col, atol=1e-12)
