@@ -126,6 +126,11 @@ typedef struct {
  *          using these tables are computed in the same precision.
  *   n_parts, parts : the dictionary's verified transform ranges; the
  *          projections of those atoms are computed as transforms.
+ *   tx   : se_tables_tx_bytes(M, N, n_parts) bytes, 16-byte aligned;
+ *          required (non-NULL) when the dictionary declares transform
+ *          parts: se_weighted_gram writes the operands of those transforms
+ *          there (the 1-D transform matrices, D and w, in the order the
+ *          matrix cores read them).  Unused without parts (may be NULL).
  *   Yhi, Ylo : K x (M*N) bfloat16 bit patterns, Y = Yhi + Ylo (hi = bf16(Y),
  *          lo = bf16(Y - hi)); required (non-NULL) for SE_BF16X3, unused
  *          for SE_FP32.                                                   */
@@ -142,6 +147,7 @@ typedef struct {
   uint16_t* Ylo;
   int32_t n_parts;       /* copied from the dictionary by se_weighted_gram */
   se_part parts[2];
+  float* tx;
 } se_tables;
 
 /* Model-generation parameters: gamma of eq. 8 (0 < gamma <= 1) and the
@@ -165,6 +171,10 @@ int32_t se_version(void);
  * iteration loop's workgroup shape (64 * waves * values per lane).  0 if K
  * is below 1 or above 32768, the largest supported dictionary. */
 int32_t se_table_ld(int32_t K);
+/* Size of the transform operand buffer se_tables.tx for an M x N area with
+ * n_parts declared transform parts; 0 if n_parts is 0 or out of range, or
+ * M or N outside 1..64. */
+size_t se_tables_tx_bytes(int32_t M, int32_t N, int32_t n_parts);
 
 /* ------------------------------------------------------------------------ */
 /* Weighting function: eq. 4 and eq. 5                                      */

@@ -27,8 +27,8 @@ EXPORTED = (
     "se_last_error", "se_version", "se_area_weights_ws_bytes", "se_area_weights",
     "se_weighted_gram_ws_bytes", "se_weighted_gram", "se_extrapolate_batch_ws_bytes",
     "se_extrapolate_batch", "se_extrapolate_plain", "se_blocks_upload", "se_project_ws_bytes",
-    "se_project", "se_iterate", "se_table_ld", "se_extrapolate_ondemand_ws_bytes",
-    "se_extrapolate_ondemand",
+    "se_project", "se_iterate", "se_table_ld", "se_tables_tx_bytes",
+    "se_extrapolate_ondemand_ws_bytes", "se_extrapolate_ondemand",
 )
 
 
@@ -81,7 +81,7 @@ class se_tables(C.Structure):
                 ("G", C.c_void_p), ("D", C.c_void_p), ("Y", C.c_void_p),
                 ("sqrtw", C.c_void_p), ("phi", C.c_void_p), ("info", C.c_void_p),
                 ("precision", C.c_int32), ("Yhi", C.c_void_p), ("Ylo", C.c_void_p),
-                ("n_parts", C.c_int32), ("parts", se_part * 2)]
+                ("n_parts", C.c_int32), ("parts", se_part * 2), ("tx", C.c_void_p)]
 
 
 class se_params(C.Structure):
@@ -106,6 +106,8 @@ def lib():
     L.se_version.restype = i32
     L.se_table_ld.restype = i32
     L.se_table_ld.argtypes = [i32]
+    L.se_tables_tx_bytes.restype = sz
+    L.se_tables_tx_bytes.argtypes = [i32, i32, i32]
     L.se_area_weights_ws_bytes.restype = sz
     L.se_area_weights_ws_bytes.argtypes = [i32]
     L.se_area_weights.restype = i32
@@ -222,6 +224,7 @@ class Tables:
     Yhi: Optional[torch.Tensor] = None
     Ylo: Optional[torch.Tensor] = None
     parts: tuple = ()
+    tx: Optional[torch.Tensor] = None
 
     def struct(self) -> se_tables:
         return se_tables(self.M, self.N, self.K, self.ldG, self.G.data_ptr(), self.D.data_ptr(),
@@ -229,7 +232,8 @@ class Tables:
                          self.info.data_ptr(), self.precision,
                          self.Yhi.data_ptr() if self.Yhi is not None else None,
                          self.Ylo.data_ptr() if self.Ylo is not None else None,
-                         len(self.parts), _part_array(self.parts))
+                         len(self.parts), _part_array(self.parts),
+                         self.tx.data_ptr() if self.tx is not None else None)
 
     def nbytes(self) -> int:
         parts = [self.G, self.D, self.Y, self.sqrtw]
@@ -261,6 +265,11 @@ def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
         t.Yhi = torch.empty((K, M * N), dtype=torch.int16, device=dev)
         t.Ylo = torch.empty((K, M * N), dtype=torch.int16, device=dev)
     t.parts = _parts_arg(parts)
+    if t.parts:
+        nb_tx = int(L.se_tables_tx_bytes(M, N, len(t.parts)))
+        if nb_tx == 0:
+            raise ValueError(f"no transform parts for a {M}x{N} area")
+        t.tx = torch.empty(nb_tx // 4, dtype=torch.float32, device=dev)
     b = make_basis(M, N, K, phi.data_ptr(), t.parts)
     nb = L.se_weighted_gram_ws_bytes(C.byref(b), int(precision))
     ws = _workspace(nb, dev)

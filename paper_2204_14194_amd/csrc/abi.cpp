@@ -87,7 +87,11 @@ static se_status check_tables(const se_tables* t) {
     return fail(SE_EINVAL, "unknown table precision %d", t->precision);
   if (t->precision == SE_BF16X3 && (!t->Yhi || !t->Ylo))
     return fail(SE_EINVAL, "BF16X3 tables need Yhi and Ylo");
-  return check_parts(t->M, t->N, t->K, t->n_parts, t->parts);
+  se_status st = check_parts(t->M, t->N, t->K, t->n_parts, t->parts);
+  if (st) return st;
+  if (t->n_parts > 0 && (!t->tx || reinterpret_cast<uintptr_t>(t->tx) % 16))
+    return fail(SE_EINVAL, "tables with transform parts need a 16-byte aligned tx buffer");
+  return SE_OK;
 }
 
 static inline int round8(int v) { return (v + 7) & ~7; }
@@ -190,6 +194,9 @@ extern "C" {
 const char* se_last_error(void) { return g_err; }
 int32_t se_version(void) { return 100; }
 int32_t se_table_ld(int32_t K) { return K >= 1 && greedy_waves_for(K) ? greedy_row_len(K) : 0; }
+size_t se_tables_tx_bytes(int32_t M, int32_t N, int32_t n_parts) {
+  return tx_const_bytes(M, N, n_parts);
+}
 
 // ---------------------------------------------------------------------------
 size_t se_area_weights_ws_bytes(int32_t n_blk) {
@@ -279,6 +286,7 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
   if ((st = check_launch("finalize_d"))) return st;
   launch_scale_y(b->phi, t->D, t->sqrtw, K, P, t->Y, s);
   if ((st = check_launch("scale_y"))) return st;
+  if (t->n_parts > 0 && (st = build_tx(t, s))) return st;
   launch_zero_cols(t->G, K, K, t->ldG, s);
   if ((st = check_launch("zero_cols"))) return st;
   if (prec == SE_FP32) return gemm_syrk_f32(t->Y, P, K, P, t->G, t->ldG, s);

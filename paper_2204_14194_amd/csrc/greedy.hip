@@ -150,30 +150,39 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy(GreedyArgs a) {
       }
       par ^= 1;
     }
-    // ---- decode the winner (wave-uniform) -------------------------------
+    // ---- decode the winner (wave-uniform, kept in scalar registers) ------
     int u;
     float rv;
     decode_key(key, K, u, rv);
+    u = __builtin_amdgcn_readfirstlane(u);
+    rv = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rv)));
     const float tc = gamma * rv;              // coefficient of the unit-norm atom
+
+    // ---- stream row u of the table and the atom over the loss -------------
+    // Issued before the scalar load of D_u, so the only memory latency on the
+    // iteration's critical path is that of the row.
+    const float* prow = a.phi + (size_t)u * P;
+    float pv[kQPL];
+#pragma unroll
+    for (int q = 0; q < kQPL; ++q)
+      if (q < nq) pv[q] = prow[poff[q]];
+    const float* grow = a.G + (size_t)u * a.ldG;
+    float4 row[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) row[j] = *reinterpret_cast<const float4*>(grow + 4 * (j * T + t));
     const float c = tc * a.D[u];              // eq. 19
     if (t == 0) {
       if (a.sel) a.sel[(size_t)b * a.iters + it] = u;
       if (a.coef) a.coef[(size_t)b * a.iters + it] = c;
     }
-
-    // ---- stream row u of the table and the atom over the loss -------------
-    const float* grow = a.G + (size_t)u * a.ldG;
-    float4 row[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) row[j] = *reinterpret_cast<const float4*>(grow + 4 * (j * T + t));
-    const float* prow = a.phi + (size_t)u * P;
 #pragma unroll
     for (int q = 0; q < kQPL; ++q)
       if (q < nq) {                                       // eq. 9, compensated
-        const float y = fmaf(c, prow[poff[q]], -gc[q]);
+        const float y = fmaf(c, pv[q], -gc[q]);
         const float s = g[q] + y;
         gc[q] = (s - g[q]) - y;
         g[q] = s;
+        asm volatile("" ::: "memory");   // keep the uniform branch (no if-conversion)
       }
 
     // ---- eq. 20 ---------------------------------------------------------

@@ -102,6 +102,10 @@ se_status check_part(const float* phi, int M, int N, int kind, int first, int* d
 se_status project_tx(const se_tables* t, const uint8_t* images, int H, int W,
                      const DevBlock* blk, int n_blk, float* R, int ldR, hipStream_t s);
 size_t tx_lds_bytes(int M, int N, int n_parts);
+// bytes of se_tables.tx (0 for an unsupported shape); build_tx writes it
+// from t->D and t->sqrtw
+size_t tx_const_bytes(int M, int N, int n_parts);
+se_status build_tx(const se_tables* t, hipStream_t s);
 // abi.cpp -- the host-side checks of a basis' part declaration
 se_status check_basis_parts(const se_basis* b);
 

@@ -109,10 +109,12 @@ namespace sefase {
 
 using Server = se_server;
 
-static size_t tables_bytes(int K, int P) {
+static size_t tables_bytes(const se_basis& b) {
+  const int K = b.K, P = b.M * b.N;
   const size_t ld = (size_t)greedy_row_len(K);
   return align_up((size_t)K * ld * 4, 256) + align_up((size_t)K * 4, 256) +
-         align_up((size_t)K * P * 4, 256) + align_up((size_t)P * 4, 256) + 256;
+         align_up((size_t)K * P * 4, 256) + align_up((size_t)P * 4, 256) +
+         align_up(tx_const_bytes(b.M, b.N, b.n_parts), 256) + 256;
 }
 
 static void evict_for(Server* s, size_t need) {
@@ -162,7 +164,7 @@ static CachedTables* get_tables(Server* s, const PatternKey& key, hipStream_t st
   }
   const se_basis& b = s->sets[(size_t)key.basis];
   const int K = b.K, P = b.M * b.N, ld = greedy_row_len(K);
-  const size_t bytes = tables_bytes(K, P);
+  const size_t bytes = tables_bytes(b);
   evict_for(s, bytes);
   if (s->bytes_tables + s->bytes_slots + s->bytes_scratch + bytes > s->cfg.hbm_budget_bytes)
     return nullptr;
@@ -191,6 +193,8 @@ static CachedTables* get_tables(Server* s, const PatternKey& key, hipStream_t st
   t.info = nullptr;
   t.precision = SE_FP32;
   t.Yhi = t.Ylo = nullptr;
+  t.tx = b.n_parts > 0 ? reinterpret_cast<float*>(take(tx_const_bytes(b.M, b.N, b.n_parts)))
+                       : nullptr;
   // the pattern's weights: an M x N mask with the loss marked, one block at 0,0
   Carver cv(scratch);
   uint8_t* mask = cv.take<uint8_t>((size_t)P);

@@ -22,13 +22,14 @@ __device__ void build_cos_table(int n, double* ct) {
   for (int j = threadIdx.x; j < 4 * n; j += blockDim.x) ct[j] = cospi((double)j / (double)(2 * n));
 }
 
-// entry (k, m) of the n-point 1-D transform of `kind`; ct from build_cos_table
-__device__ inline float basis_1d(int kind, int n, int k, int m, const double* ct) {
-  const double inv = 1.0 / sqrt((double)n);
+// Entry (k, m) of the n-point 1-D transform of `kind`.  ct from
+// build_cos_table; inv = 1/sqrt(n), a2 = sqrt(2/n) (FP64).
+__device__ inline float basis_1d(int kind, int n, int k, int m, const double* ct, double inv,
+                                 double a2) {
   if (kind == SE_PART_WHT2) return (float)((__popc(k & m) & 1) ? -inv : inv);
   if (k == 0) return (float)inv;
   if (2 * k == n) return (float)(((m & 3) == 0 || (m & 3) == 3) ? inv : -inv);
-  return (float)(sqrt(2.0 / (double)n) * ct[((2 * m + 1) * k) % (4 * n)]);
+  return (float)(a2 * ct[((2 * m + 1) * k) % (4 * n)]);
 }
 
 // ---------------------------------------------------------------------------
@@ -45,8 +46,12 @@ __global__ __launch_bounds__(kTxThreads) void k_check_part(const float* __restri
   build_cos_table(M, ctM);
   build_cos_table(N, ctN);
   __syncthreads();
-  for (int i = threadIdx.x; i < M * M; i += blockDim.x) A[i] = basis_1d(kind, M, i / M, i % M, ctM);
-  for (int i = threadIdx.x; i < N * N; i += blockDim.x) Bm[i] = basis_1d(kind, N, i / N, i % N, ctN);
+  const double iM = 1.0 / sqrt((double)M), aM = sqrt(2.0 / (double)M);
+  const double iN = 1.0 / sqrt((double)N), aN = sqrt(2.0 / (double)N);
+  for (int i = threadIdx.x; i < M * M; i += blockDim.x)
+    A[i] = basis_1d(kind, M, i / M, i % M, ctM, iM, aM);
+  for (int i = threadIdx.x; i < N * N; i += blockDim.x)
+    Bm[i] = basis_1d(kind, N, i / N, i % N, ctN, iN, aN);
   __syncthreads();
   const int P = M * N;
   int bad = 0;
@@ -62,168 +67,347 @@ __global__ __launch_bounds__(kTxThreads) void k_check_part(const float* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Shared layout of the separable transform in LDS (floats):
-//   A  : Mp x lda   rows k1 of the vertical transform (rows >= M zero)
-//   Bt : N  x Np    Bt[n][k2] = B[k2][n] (columns >= N zero)
-//   X  : Mp x ldx   the weighted vector as an M x N image (rows >= M zero)
-//   Y1 : Mp x Np    X B^T
-// Mp, Np = M, N rounded up to even; lda = M + 1, ldx = N + 1 (odd strides,
-// so the rows a wave reads at once fall in different banks).
+// Separable transform on the FP32 matrix cores (v_mfma_f32_16x16x4f32).
+// Areas are padded to Mp = 16 MT rows and Np = 16 NT columns (zeros); one
+// wave transforms one block.  With j = l/16 the lane's group of 16:
+//   stage 1   Y1 = X B^T   tile (i, c), k-steps (sq, t): the k index j
+//             stands for column n = 16 sq + 4 j + t, so a lane's four
+//             t-values are four adjacent pixels of one row.  A-operand
+//             X[16i + l%16][n], B-operand B[16c + l%16][n]; lane l then
+//             holds Y1[16i + 4j + e][16c + l%16], e < 4
+//   stage 2   Z = A Y1     tile (r, c): the stage-1 registers serve as the
+//             B-operands unchanged, k-step (i, e) standing for the rows
+//             m = 16i + 4j + e, with the A-operand A[16r + l%16][m]; lane l
+//             then holds Z[16r + 4j + e][16c + l%16]
+// (both sums run in a permuted order, so nothing moves between the
+// stages).  Operands are stored in fragment order -- lane l's four
+// consecutive floats at (tile * 64 + l) * 4, one conflict-free
+// ds_read_b128 each.  The constant operands (se_tables.tx, written once
+// by se_weighted_gram, copied to LDS by every workgroup):
+//   Af [part][r][i]  [l][e]  A[16r + l%16][16i + 4j + e]
+//   Btf[part][c][sq] [l][t]  B[16c + l%16][16sq + 4j + t]
+//   Df [part][c][r]  [l][e]  D_k of output (16r + 4j + e, 16c + l%16)
+//   Wf [i][sq]       [l][t]  w of pixel (16i + l%16, 16sq + 4j + t)
+// and per wave in LDS, the block's X = w s in the order of Wf (Xf).
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
 struct TxLayout {
-  int M, N, Mp, Np, lda, ldx;
-  int oA, oBt, oX, oY1, nfloat;   // offsets per part (A, Bt) and shared (X, Y1)
-  __host__ __device__ TxLayout(int M_, int N_, int parts) : M(M_), N(N_) {
-    Mp = (M + 1) & ~1;
-    Np = (N + 1) & ~1;
-    lda = M + 1;
-    ldx = N + 1;
-    const int szA = (Mp * lda + 3) & ~3, szB = (N * Np + 3) & ~3;
-    oA = 0;
-    oBt = parts * szA;
-    oX = oBt + parts * szB;
-    oY1 = oX + ((Mp * ldx + 3) & ~3);
-    nfloat = oY1 + Mp * Np;
+  int M, N, MT, NT, parts, waves;
+  // offsets in floats; [0, nconst) is the copy of se_tables.tx
+  int oAf, oBtf, oDf, oWf, nconst, oXf, nfloat;
+  __host__ __device__ TxLayout(int M_, int N_, int parts_, int waves_)
+      : M(M_), N(N_), parts(parts_), waves(waves_) {
+    MT = (M + 15) / 16;
+    NT = (N + 15) / 16;
+    oAf = 0;
+    oBtf = oAf + parts * MT * MT * 256;
+    oDf = oBtf + parts * NT * NT * 256;
+    oWf = oDf + parts * MT * NT * 256;
+    nconst = oWf + MT * NT * 256;
+    oXf = nconst;
+    nfloat = oXf + waves * MT * NT * 256;
   }
-  __host__ __device__ int szA() const { return (Mp * lda + 3) & ~3; }
-  __host__ __device__ int szB() const { return (N * Np + 3) & ~3; }
-  // bytes: the floats, then the two FP64 cosine tables
-  __host__ __device__ size_t bytes() const {
-    return (((size_t)nfloat * 4 + 7) & ~(size_t)7) + (size_t)4 * (M + N) * 8;
-  }
+  __host__ __device__ size_t bytes() const { return (size_t)nfloat * 4; }
 };
 
-// Build A and Bt of one part (all threads; ends synchronised).
-__device__ void build_part(const TxLayout& L, int kind, float* A, float* Bt, double* ctM,
-                           double* ctN) {
-  build_cos_table(L.M, ctM);
-  build_cos_table(L.N, ctN);
+// ---------------------------------------------------------------------------
+// The constant operands (se_weighted_gram, once per table set): entry x of
+// se_tables.tx, every workgroup computing a slice.
+struct TxBuildArgs {
+  int M, N, parts;
+  int kind0, kind1, first0, first1;
+  const float* D;
+  const float* sqrtw;
+  float* tx;
+};
+
+__global__ __launch_bounds__(kTxThreads) void k_build_tx(TxBuildArgs a, TxLayout L) {
+  extern __shared__ double ctab[];   // 4M + 4N cosines
+  double* ctM = ctab;
+  double* ctN = ctab + 4 * a.M;
+  build_cos_table(a.M, ctM);
+  build_cos_table(a.N, ctN);
   __syncthreads();
-  for (int i = threadIdx.x; i < L.Mp * L.lda; i += blockDim.x) {
-    const int k = i / L.lda, m = i - k * L.lda;
-    A[i] = (k < L.M && m < L.M) ? basis_1d(kind, L.M, k, m, ctM) : 0.0f;
+  const int M = a.M, N = a.N, MT = L.MT, NT = L.NT;
+  const double iM = 1.0 / sqrt((double)M), aM = sqrt(2.0 / (double)M);
+  const double iN = 1.0 / sqrt((double)N), aN = sqrt(2.0 / (double)N);
+  const int nA = MT * MT * 256, nB = NT * NT * 256, nD = MT * NT * 256;
+  for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < L.nconst; x += gridDim.x * blockDim.x) {
+    float v = 0.0f;
+    if (x < L.oBtf) {                       // Af
+      const int q = x / nA, y = x - q * nA;
+      const int e = y & 3, l = (y >> 2) & 63, ri = y >> 8;
+      const int r = ri / MT, i = ri - r * MT;
+      const int row = 16 * r + (l & 15), col = 16 * i + 4 * (l >> 4) + e;
+      if (row < M && col < M) v = basis_1d(q ? a.kind1 : a.kind0, M, row, col, ctM, iM, aM);
+    } else if (x < L.oDf) {                 // Btf
+      const int z = x - L.oBtf, q = z / nB, y = z - q * nB;
+      const int t = y & 3, l = (y >> 2) & 63, cs = y >> 8;
+      const int c = cs / NT, sq = cs - c * NT;
+      const int k2 = 16 * c + (l & 15), n = 16 * sq + 4 * (l >> 4) + t;
+      if (k2 < N && n < N) v = basis_1d(q ? a.kind1 : a.kind0, N, k2, n, ctN, iN, aN);
+    } else if (x < L.oWf) {                 // Df
+      const int z = x - L.oDf, q = z / nD, y = z - q * nD;
+      const int e = y & 3, l = (y >> 2) & 63, cr = y >> 8;
+      const int c = cr / MT, r = cr - c * MT;
+      const int k1 = 16 * r + 4 * (l >> 4) + e, k2 = 16 * c + (l & 15);
+      if (k1 < M && k2 < N) v = a.D[(q ? a.first1 : a.first0) + k1 * N + k2];
+    } else {                                // Wf
+      const int y = x - L.oWf;
+      const int t = y & 3, l = (y >> 2) & 63, is = y >> 8;
+      const int i = is / NT, sq = is - i * NT;
+      const int m = 16 * i + (l & 15), n = 16 * sq + 4 * (l >> 4) + t;
+      if (m < M && n < N) {
+        const float sw = a.sqrtw[m * N + n];
+        v = sw * sw;
+      }
+    }
+    a.tx[x] = v;
   }
-  for (int i = threadIdx.x; i < L.N * L.Np; i += blockDim.x) {
-    const int n = i / L.Np, k = i - n * L.Np;
-    Bt[i] = k < L.N ? basis_1d(kind, L.N, k, n, ctN) : 0.0f;
-  }
-  __syncthreads();
 }
 
-// Z = A X B^T for X, Y1 in LDS; calls out(k1, k2, z) for every k1 < M,
-// k2 < N.  Each thread computes 2 x 2 outputs per pass.  Starts and ends
-// with the caller's X complete; ends synchronised.
-template <typename Out>
-__device__ void separable_2d(const TxLayout& L, const float* A, const float* Bt, const float* X,
-                             float* Y1, Out out) {
-  const int hp = L.Np >> 1, pairs = (L.Mp >> 1) * hp;
-  for (int q = threadIdx.x; q < pairs; q += blockDim.x) {
-    const int mi = q / hp, m = 2 * mi, k2 = 2 * (q - mi * hp);
-    const float* x0 = X + m * L.ldx;
-    const float* x1 = x0 + L.ldx;
-    const float* bt = Bt + k2;
-    float a00 = 0.f, a01 = 0.f, a10 = 0.f, a11 = 0.f;
-    for (int n = 0; n < L.N; ++n) {
-      const float2 b = *reinterpret_cast<const float2*>(bt + n * L.Np);
-      const float u = x0[n], v = x1[n];
-      a00 = fmaf(u, b.x, a00);
-      a01 = fmaf(u, b.y, a01);
-      a10 = fmaf(v, b.x, a10);
-      a11 = fmaf(v, b.y, a11);
+// Z_q = A_q X B_q^T of every part q < NP for the X operands x (registers,
+// x[i][sq][t] as above); the parts share the X operands and run as
+// independent accumulation chains.  out(q, k1, k2, D_k z) for every
+// k1 < M, k2 < N.
+template <int MT, int NT, int NP, typename Out>
+__device__ void tx_mfma(const float* Af, const float* Btf, const float* Df,
+                        const floatx4 (&x)[MT][NT], int M, int N, Out out) {
+  const int l = threadIdx.x & 63;
+#pragma unroll 1
+  for (int c = 0; c < NT; ++c) {
+    // re-read the A operands per column tile instead of holding them all
+    // in registers across the loop (they would cost 16 NP MT^2 / 4 VGPRs)
+    asm volatile("" : "+s"(Af));
+    floatx4 y[NP][MT];
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+      for (int i = 0; i < MT; ++i) y[q][i] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int sq = 0; sq < NT; ++sq) {
+      floatx4 bv[NP];
+#pragma unroll
+      for (int q = 0; q < NP; ++q)
+        bv[q] = *reinterpret_cast<const floatx4*>(Btf + q * NT * NT * 256 +
+                                                  ((c * NT + sq) * 64 + l) * 4);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int q = 0; q < NP; ++q)
+#pragma unroll
+          for (int i = 0; i < MT; ++i)
+            y[q][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[i][sq][t], bv[q][t], y[q][i], 0, 0, 0);
     }
-    *reinterpret_cast<float2*>(Y1 + m * L.Np + k2) = make_float2(a00, a01);
-    *reinterpret_cast<float2*>(Y1 + (m + 1) * L.Np + k2) = make_float2(a10, a11);
+    floatx4 z[NP][MT];
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+      for (int r = 0; r < MT; ++r) z[q][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+      floatx4 av[NP][MT];
+#pragma unroll
+      for (int q = 0; q < NP; ++q)
+#pragma unroll
+        for (int r = 0; r < MT; ++r)
+          av[q][r] = *reinterpret_cast<const floatx4*>(Af + q * MT * MT * 256 +
+                                                       ((r * MT + i) * 64 + l) * 4);
+      // consecutive products go to different accumulators
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int q = 0; q < NP; ++q)
+#pragma unroll
+          for (int r = 0; r < MT; ++r)
+            z[q][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q][r][e], y[q][i][e], z[q][r], 0, 0, 0);
+    }
+    const int k2 = 16 * c + (l & 15);
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+      for (int r = 0; r < MT; ++r) {
+        const floatx4 dv =
+            *reinterpret_cast<const floatx4*>(Df + q * MT * NT * 256 + ((c * MT + r) * 64 + l) * 4);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int k1 = 16 * r + 4 * (l >> 4) + e;
+          if (k1 < M && k2 < N) out(q, k1, k2, dv[e] * z[q][r][e]);
+        }
+      }
   }
-  __syncthreads();
-  for (int q = threadIdx.x; q < pairs; q += blockDim.x) {
-    const int mi = q / hp, k1 = 2 * mi, k2 = 2 * (q - mi * hp);
-    const float* r0 = A + k1 * L.lda;
-    const float* r1 = r0 + L.lda;
-    const float* y = Y1 + k2;
-    float z00 = 0.f, z01 = 0.f, z10 = 0.f, z11 = 0.f;
-    for (int m = 0; m < L.M; ++m) {
-      const float2 c = *reinterpret_cast<const float2*>(y + m * L.Np);
-      const float u = r0[m], v = r1[m];
-      z00 = fmaf(u, c.x, z00);
-      z01 = fmaf(u, c.y, z01);
-      z10 = fmaf(v, c.x, z10);
-      z11 = fmaf(v, c.y, z11);
-    }
-    if (k1 < L.M) {
-      out(k1, k2, z00);
-      if (k2 + 1 < L.N) out(k1, k2 + 1, z01);
-    }
-    if (k1 + 1 < L.M) {
-      out(k1 + 1, k2, z10);
-      if (k2 + 1 < L.N) out(k1 + 1, k2 + 1, z11);
-    }
-  }
-  __syncthreads();
+}
+
+// Orders this wave's LDS writes before its later reads (and reads before
+// later writes).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // ---------------------------------------------------------------------------
 // Initial projections of the transform parts (eq. 12 via eq. 22), fused with
 // the gather: x = w s over the block's area (0 outside the image), then per
 // part R[b][first + k1 N + k2] = D_k (A x B^T)[k1][k2].  Columns K .. ldR-1
-// of R are written as 0.  Workgroups loop over blocks, so the 1-D matrices
-// are built once per workgroup.
+// of R are written as 0.  One wave per block; each workgroup copies the
+// constant operands to LDS once and its waves loop over blocks.
 struct TxArgs {
   const uint8_t* images;
   int H, W;
   const DevBlock* blk;
   int n_blk;
   int K;
-  const float* sqrtw;
-  const float* D;
-  int n_parts;
-  int kind[2], first[2];
+  const float* tx;
+  int first0, first1;
   float* R;
   int ldR;
 };
 
-__global__ __launch_bounds__(kTxThreads) void k_project_tx(TxArgs a, TxLayout L) {
-  extern __shared__ double smd[];
-  float* sm = reinterpret_cast<float*>(smd);
-  double* ctM = smd + (((size_t)L.nfloat * 4 + 7) >> 3);
-  double* ctN = ctM + 4 * L.M;
-  float* X = sm + L.oX;
-  float* Y1 = sm + L.oY1;
-  for (int q = 0; q < a.n_parts; ++q)
-    build_part(L, a.kind[q], sm + L.oA + q * L.szA(), sm + L.oBt + q * L.szB(), ctM, ctN);
-  const int M = L.M, N = L.N;
-  for (int b = blockIdx.x; b < a.n_blk; b += gridDim.x) {
-    const DevBlock d = a.blk[b];
-    const uint8_t* img = a.images + (size_t)d.img * a.H * a.W;
-    for (int p = threadIdx.x; p < L.Mp * L.ldx; p += blockDim.x) {
-      const int m = p / L.ldx, n = p - m * L.ldx;
-      const int y = d.y0 + m, x = d.x0 + n;
-      float v = 0.0f;
-      if (m < M && n < N && y >= 0 && y < a.H && x >= 0 && x < a.W) {
-        const float sw = a.sqrtw[m * N + n];
-        v = (sw * sw) * (float)img[(size_t)y * a.W + x];
-      }
-      X[p] = v;
+// Pixels of one block, as the lane holds them until they become X operands:
+// whole 16-pixel row segments when the area lies inside the image on a
+// 16-byte grid (one 16-byte load each), else single pixels at clamped
+// coordinates.
+template <int MT, int NT>
+struct TxPixels {
+  static constexpr int CH = (MT * NT + 3) / 4;   // row segments per lane
+  bool fast;
+  // single pixels: v[(i * NT + sq) * 4 + t]; segments: v[4 k .. 4 k + 3]
+  uint32_t v[MT * NT * 4];
+};
+
+template <int MT, int NT>
+__device__ inline void tx_load(const TxArgs& a, const DevBlock& d, int M, int N,
+                               TxPixels<MT, NT>& P) {
+  const int l = threadIdx.x & 63, lr = l & 15, lc = 4 * (l >> 4);
+  const uint8_t* img = a.images + (size_t)d.img * a.H * a.W;
+  P.fast = (M & 15) == 0 && (N & 15) == 0 && (a.W & 15) == 0 && (d.x0 & 15) == 0 &&
+           d.y0 >= 0 && d.x0 >= 0 && d.y0 + M <= a.H && d.x0 + N <= a.W;
+  if (P.fast) {
+    const int spr = N >> 4, nseg = M * spr;
+#pragma unroll
+    for (int k = 0; k < P.CH; ++k) {
+      const int c = min(l + 64 * k, nseg - 1);
+      const int m = c / spr, sg = c - m * spr;
+      const uint4 q = *reinterpret_cast<const uint4*>(img + (size_t)(d.y0 + m) * a.W + d.x0 + 16 * sg);
+      P.v[4 * k] = q.x;
+      P.v[4 * k + 1] = q.y;
+      P.v[4 * k + 2] = q.z;
+      P.v[4 * k + 3] = q.w;
     }
-    float* Rb = a.R + (size_t)b * a.ldR;
-    for (int k = a.K + threadIdx.x; k < a.ldR; k += blockDim.x) Rb[k] = 0.0f;
-    __syncthreads();
-    for (int q = 0; q < a.n_parts; ++q) {
-      const int f = a.first[q];
-      const float* Dq = a.D + f;
-      float* Rq = Rb + f;
-      separable_2d(L, sm + L.oA + q * L.szA(), sm + L.oBt + q * L.szB(), X, Y1,
-                   [&](int k1, int k2, float z) {
-                     const int k = k1 * N + k2;
-                     Rq[k] = Dq[k] * z;
-                   });
+  } else {
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+      const uint8_t* row = img + (size_t)min(max(d.y0 + 16 * i + lr, 0), a.H - 1) * a.W;
+#pragma unroll
+      for (int sq = 0; sq < NT; ++sq)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          P.v[(i * NT + sq) * 4 + t] = row[min(max(d.x0 + 16 * sq + lc + t, 0), a.W - 1)];
     }
   }
 }
 
-static int tx_grid(size_t lds, int n_blk) {
-  int per_cu = (int)((160 * 1024) / (lds ? lds : 1));
-  per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
-  const int cap = 256 * per_cu;
-  return n_blk < cap ? n_blk : cap;
+// X operands x = w s (s = 0 outside the area and the image).
+template <int MT, int NT>
+__device__ inline void tx_x_operands(const TxArgs& a, const DevBlock& d, int M, int N,
+                                     TxPixels<MT, NT>& P, const float* Wf, float* Xf,
+                                     floatx4 (&xv)[MT][NT]) {
+  const int l = threadIdx.x & 63, lr = l & 15, lc = 4 * (l >> 4);
+  if (P.fast) {
+    // segment (row m, columns 16 sg .. 16 sg + 15) covers, for j < 4, the
+    // four t-values of fragment lane (m & 15) + 16 j of tile (m >> 4, sg)
+    const int spr = N >> 4, nseg = M * spr;
+#pragma unroll
+    for (int k = 0; k < P.CH; ++k) {
+      const int c = l + 64 * k;
+      if (c < nseg) {
+        const int m = c / spr, sg = c - m * spr;
+        const uint32_t wd[4] = {P.v[4 * k], P.v[4 * k + 1], P.v[4 * k + 2], P.v[4 * k + 3]};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int o = (((m >> 4) * NT + sg) * 64 + (m & 15) + 16 * j) * 4;
+          const floatx4 w = *reinterpret_cast<const floatx4*>(Wf + o);
+          floatx4 v;
+          v[0] = w[0] * (float)(wd[j] & 0xFFu);
+          v[1] = w[1] * (float)((wd[j] >> 8) & 0xFFu);
+          v[2] = w[2] * (float)((wd[j] >> 16) & 0xFFu);
+          v[3] = w[3] * (float)(wd[j] >> 24);
+          *reinterpret_cast<floatx4*>(Xf + o) = v;
+        }
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int sq = 0; sq < NT; ++sq)
+        xv[i][sq] = *reinterpret_cast<const floatx4*>(Xf + ((i * NT + sq) * 64 + l) * 4);
+    wave_sync();   // read before the next block's writes
+  } else {
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+      const int y = d.y0 + 16 * i + lr;
+      const bool row_in = 16 * i + lr < M && y >= 0 && y < a.H;
+#pragma unroll
+      for (int sq = 0; sq < NT; ++sq) {
+        const floatx4 w = *reinterpret_cast<const floatx4*>(Wf + ((i * NT + sq) * 64 + l) * 4);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int n = 16 * sq + lc + t, x = d.x0 + n;
+          // the value is taken as used here, so its load stays
+          // unconditional (not moved under the test below, which would
+          // serialise the loads)
+          uint32_t& pv = P.v[(i * NT + sq) * 4 + t];
+          asm volatile("" : "+v"(pv));
+          xv[i][sq][t] = (row_in && n < N && x >= 0 && x < a.W) ? w[t] * (float)pv : 0.0f;
+        }
+      }
+    }
+  }
+}
+
+// Workgroup size bound: 16 waves for areas up to 32 x 32 (or 16 x 64), 4
+// waves above (more registers per lane for the larger tiles).
+template <int MT, int NT>
+constexpr int tx_max_threads() {
+  return (MT >= 3 || MT * NT >= 6) ? 256 : 1024;
+}
+
+template <int MT, int NT, int NP>
+__global__ __launch_bounds__((tx_max_threads<MT, NT>())) void k_project_tx(TxArgs a, TxLayout L) {
+  extern __shared__ floatx4 smv[];
+  float* sm = reinterpret_cast<float*>(smv);
+  const int M = L.M, N = L.N;
+  const int l = threadIdx.x & 63, wave = threadIdx.x >> 6, W = blockDim.x >> 6;
+  float* Xf = sm + L.oXf + wave * MT * NT * 256;
+  // the first block's pixel loads and the copy of the constant operands
+  // are in flight together
+  int b = blockIdx.x * W + wave;
+  DevBlock d = a.blk[b < a.n_blk ? b : 0];
+  TxPixels<MT, NT> P;
+  tx_load<MT, NT>(a, d, M, N, P);
+  {
+    const floatx4* src = reinterpret_cast<const floatx4*>(a.tx);
+    for (int x = threadIdx.x; x < L.nconst / 4; x += blockDim.x) smv[x] = src[x];
+  }
+  __syncthreads();
+  for (bool first = true; b < a.n_blk; b += gridDim.x * W, first = false) {
+    if (!first) {
+      d = a.blk[b];
+      tx_load<MT, NT>(a, d, M, N, P);
+    }
+    floatx4 xv[MT][NT];
+    tx_x_operands<MT, NT>(a, d, M, N, P, sm + L.oWf, Xf, xv);
+    float* Rb = a.R + (size_t)b * a.ldR;
+    for (int k = a.K + l; k < a.ldR; k += 64) Rb[k] = 0.0f;
+    float* R0 = Rb + a.first0;
+    float* R1 = Rb + a.first1;
+    tx_mfma<MT, NT, NP>(sm + L.oAf, sm + L.oBtf, sm + L.oDf, xv, M, N,
+                        [&](int q, int k1, int k2, float v) {
+                          (q ? R1 : R0)[k1 * N + k2] = v;
+                        });
+  }
 }
 
 se_status check_part(const float* phi, int M, int N, int kind, int first, int* dflag,
@@ -236,10 +420,66 @@ se_status check_part(const float* phi, int M, int N, int kind, int first, int* d
   return check_launch("check_part");
 }
 
-size_t tx_lds_bytes(int M, int N, int n_parts) { return TxLayout(M, N, n_parts).bytes(); }
+size_t tx_const_bytes(int M, int N, int n_parts) {
+  if (M < 1 || N < 1 || M > 64 || N > 64 || n_parts < 1 || n_parts > 2) return 0;
+  return (size_t)TxLayout(M, N, n_parts, 0).nconst * 4;
+}
+
+se_status build_tx(const se_tables* t, hipStream_t s) {
+  TxBuildArgs a;
+  a.M = t->M;
+  a.N = t->N;
+  a.parts = t->n_parts;
+  a.kind0 = t->parts[0].kind;
+  a.first0 = t->parts[0].first;
+  a.kind1 = t->n_parts > 1 ? t->parts[1].kind : 0;
+  a.first1 = t->n_parts > 1 ? t->parts[1].first : 0;
+  a.D = t->D;
+  a.sqrtw = t->sqrtw;
+  a.tx = t->tx;
+  const TxLayout L(t->M, t->N, t->n_parts, 0);
+  const int grid = (L.nconst + kTxThreads - 1) / kTxThreads;
+  hipLaunchKernelGGL(k_build_tx, dim3(grid), dim3(kTxThreads), (size_t)4 * (t->M + t->N) * 8, s,
+                     a, L);
+  return check_launch("build_tx");
+}
+
+// Waves per workgroup: the kernel's workgroup bound, fewer when that leaves
+// compute units without a workgroup or exceeds the LDS.
+static int tx_waves(int M, int N, int n_parts, int n_blk) {
+  const int MT = (M + 15) / 16, NT = (N + 15) / 16;
+  int w = (MT >= 3 || MT * NT >= 6) ? 4 : 16;
+  while (w > 1 && (long long)w * 256 > n_blk) w /= 2;
+  while (w >= 1 && TxLayout(M, N, n_parts, w).bytes() > 160 * 1024) w /= 2;
+  return w;
+}
+
+size_t tx_lds_bytes(int M, int N, int n_parts) {
+  const int w = tx_waves(M, N, n_parts, 1 << 30);
+  return w ? TxLayout(M, N, n_parts, w).bytes() : 0;
+}
+
+template <int MT, int NT, int NP>
+static se_status launch_tx(const TxArgs& a, const TxLayout& L, int grid, size_t lds,
+                           hipStream_t s) {
+  if (lds > 64 * 1024 &&
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_project_tx<MT, NT, NP>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return fail(SE_EHIP, "project_tx: %zu bytes of LDS refused", lds);
+  hipLaunchKernelGGL((k_project_tx<MT, NT, NP>), dim3(grid), dim3(64 * L.waves), lds, s, a, L);
+  return check_launch("project_tx");
+}
+
+template <int MT, int NT>
+static se_status launch_tx_np(const TxArgs& a, const TxLayout& L, int grid, size_t lds,
+                              hipStream_t s) {
+  return L.parts == 2 ? launch_tx<MT, NT, 2>(a, L, grid, lds, s)
+                      : launch_tx<MT, NT, 1>(a, L, grid, lds, s);
+}
 
 se_status project_tx(const se_tables* t, const uint8_t* images, int H, int W, const DevBlock* blk,
                      int n_blk, float* R, int ldR, hipStream_t s) {
+  if (t->n_parts < 1 || t->n_parts > 2) return fail(SE_EINVAL, "no transform part declared");
   TxArgs a;
   a.images = images;
   a.H = H;
@@ -247,24 +487,29 @@ se_status project_tx(const se_tables* t, const uint8_t* images, int H, int W, co
   a.blk = blk;
   a.n_blk = n_blk;
   a.K = t->K;
-  a.sqrtw = t->sqrtw;
-  a.D = t->D;
-  a.n_parts = t->n_parts;
-  for (int q = 0; q < 2; ++q) {
-    a.kind[q] = q < t->n_parts ? t->parts[q].kind : 0;
-    a.first[q] = q < t->n_parts ? t->parts[q].first : 0;
-  }
+  a.tx = t->tx;
+  a.first0 = t->parts[0].first;
+  a.first1 = t->n_parts > 1 ? t->parts[1].first : 0;
   a.R = R;
   a.ldR = ldR;
-  const TxLayout L(t->M, t->N, t->n_parts);
+  const int waves = tx_waves(t->M, t->N, t->n_parts, n_blk);
+  if (waves == 0) return fail(SE_EINVAL, "transform of a %dx%d area exceeds LDS", t->M, t->N);
+  const TxLayout L(t->M, t->N, t->n_parts, waves);
   const size_t lds = L.bytes();
-  if (lds > 160 * 1024) return fail(SE_EINVAL, "transform of a %dx%d area exceeds LDS", t->M, t->N);
-  if (lds > 64 * 1024 &&
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_project_tx),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-    return fail(SE_EHIP, "project_tx: %zu bytes of LDS refused", lds);
-  hipLaunchKernelGGL(k_project_tx, dim3(tx_grid(lds, n_blk)), dim3(kTxThreads), lds, s, a, L);
-  return check_launch("project_tx");
+  // about one block per wave, at most four workgroups per compute unit
+  const int per_cu = (int)std::min<size_t>(4, (160 * 1024) / lds);
+  const int grid = std::max(1, std::min((n_blk + waves - 1) / waves, 256 * per_cu));
+  switch (L.MT * 10 + L.NT) {
+#define SE_TX_CASE(mt, nt) \
+  case mt * 10 + nt:       \
+    return launch_tx_np<mt, nt>(a, L, grid, lds, s);
+    SE_TX_CASE(1, 1) SE_TX_CASE(1, 2) SE_TX_CASE(1, 3) SE_TX_CASE(1, 4)
+    SE_TX_CASE(2, 1) SE_TX_CASE(2, 2) SE_TX_CASE(2, 3) SE_TX_CASE(2, 4)
+    SE_TX_CASE(3, 1) SE_TX_CASE(3, 2) SE_TX_CASE(3, 3) SE_TX_CASE(3, 4)
+    SE_TX_CASE(4, 1) SE_TX_CASE(4, 2) SE_TX_CASE(4, 3) SE_TX_CASE(4, 4)
+#undef SE_TX_CASE
+    default: return fail(SE_EINVAL, "transform parts need M, N <= 64");
+  }
 }
 
 }  // namespace sefase

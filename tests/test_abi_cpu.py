@@ -118,10 +118,21 @@ def test_rejects_bad_transform_parts_on_host():
     tb.n_parts = 2
     tb.parts[0] = B.se_part(B.SE_PART_DCT2, 0)
     tb.parts[1] = B.se_part(B.SE_PART_DCT2, 512)
+    tb.tx = 0x1000
     blk = (B.se_block * 1)(B.se_block(0, 0, 0, 2, 2, 4, 4, 0))
     r = L.se_extrapolate_batch(C.byref(tb), fake, 1, 64, 64, blk, 1, B.se_params(0.5, 10, 0),
                                None, None, None, 0, fake, 1 << 30, None)
     assert r == B.SE_EINVAL and b"overlap" in L.se_last_error()
+    # declared parts need the operand buffer
+    tb.parts[1] = B.se_part(B.SE_PART_WHT2, 1024)
+    tb.tx = None
+    r = L.se_extrapolate_batch(C.byref(tb), fake, 1, 64, 64, blk, 1, B.se_params(0.5, 10, 0),
+                               None, None, None, 0, fake, 1 << 30, None)
+    assert r == B.SE_EINVAL and b"tx" in L.se_last_error()
+    # its size: fragments of A, B (per part), D (per part) and w, 1 KiB per 16 x 16 tile
+    assert L.se_tables_tx_bytes(32, 32, 2) == (2 * 4 + 2 * 4 + 2 * 4 + 4) * 1024
+    assert L.se_tables_tx_bytes(7, 5, 1) == 4 * 1024
+    assert L.se_tables_tx_bytes(32, 32, 0) == 0 and L.se_tables_tx_bytes(65, 8, 1) == 0
 
 
 def test_table_ld_is_padded_row_length():
