@@ -147,6 +147,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (default: tune loop shape and GEMM tile on the "
                          "benchmark batch before timing)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the timing of the step captured as a HIP graph")
     ap.add_argument("--no-parts", action="store_true",
                     help="do not declare the dictionary's transform parts (projections by "
                          "GEMM against every atom)")
@@ -236,6 +238,31 @@ def main():
     loop_ms = [e[1].elapsed_time(e[2]) for e in evs]
     step_ms = [e[0].elapsed_time(e[2]) for e in evs]
 
+    # the same step captured once into a HIP graph and replayed
+    graph_info = None
+    if not args.no_graph:
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            B.project(t, images_d, dblk, R, ws, stream=side)
+            B.iterate(t, R, images_d, dblk, GAMMA, ITERS, stream=side)
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=side):
+            B.project(t, images_d, dblk, R, ws, stream=side)
+            B.iterate(t, R, images_d, dblk, GAMMA, ITERS, stream=side)
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        gt0 = time.perf_counter()
+        for _ in range(args.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        g_ms = (time.perf_counter() - gt0) * 1e3 / max(args.steps, 1)
+        graph_info = {"ms_per_step": g_ms, "blocks_per_s": nblk / (g_ms * 1e-3),
+                      "what": "project + loop captured once as a HIP graph, replayed per step"}
+
     # plain form: one block at a time, 3 launches per block
     one = blocks[:16]
     plain_lat = []
@@ -313,6 +340,7 @@ def main():
                   "what": "se_extrapolate_plain, one block per call (gather, GEMV, "
                           "single-workgroup loop)", "blocks": len(plain_ms)},
         "chosen_over_plain": value / plain_bps,
+        "graph": graph_info,
         "gram_ms": gram_ms,
         "autotune": tuned,
         "kernels": {"project_ms": proj_avg, "project_tflops": proj_tfs,

@@ -52,22 +52,27 @@ __device__ __forceinline__ uint64_t make_key(float v, int idx) {
 }
 
 
-// Float max over the wave (all lanes see the result); v >= 0.
+// Maximum over the wave of a non-negative float, returned wave-uniform.
+// Non-negative floats order like their bit patterns, so the reduction runs
+// on unsigned integers: with 0 (the identity of unsigned max) as the value
+// of lanes a step does not write, each step folds into one v_max_u32 with a
+// DPP operand.  Lanes outside rows 1 and 3 hold partial values after the
+// broadcast steps; lane 63 holds the maximum.
 template <int CTRL, int ROWMASK>
-__device__ __forceinline__ float fmax_step(float v) {
-  const float o = __int_as_float(
-      __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROWMASK, 0xF, false));
-  return fmaxf(v, o);
+__device__ __forceinline__ uint32_t umax_step(uint32_t v) {
+  const uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWMASK, 0xF, false);
+  return v > o ? v : o;
 }
 
-__device__ __forceinline__ float wave_max_f32(float v) {
-  v = fmax_step<kQuadXor1, 0xF>(v);
-  v = fmax_step<kQuadXor2, 0xF>(v);
-  v = fmax_step<kRowHalfMirror, 0xF>(v);
-  v = fmax_step<kRowMirror, 0xF>(v);
-  v = fmax_step<kRowBcast15, 0xA>(v);
-  v = fmax_step<kRowBcast31, 0xC>(v);
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+__device__ __forceinline__ float wave_max_f32(float x) {
+  uint32_t v = __float_as_uint(x);
+  v = umax_step<kQuadXor1, 0xF>(v);
+  v = umax_step<kQuadXor2, 0xF>(v);
+  v = umax_step<kRowHalfMirror, 0xF>(v);
+  v = umax_step<kRowMirror, 0xF>(v);
+  v = umax_step<kRowBcast15, 0xA>(v);
+  v = umax_step<kRowBcast31, 0xC>(v);
+  return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)v, 63));
 }
 
 // Decode the winner of a key: index and signed value; an all-zero key (no

@@ -10,6 +10,8 @@
 //   DCT-II:  A[k][m] = alpha_k cos(pi (2m+1) k / 2M), alpha_0 = 1/sqrt(M),
 //            alpha_k = sqrt(2/M); row M/2 takes its exact values +-1/sqrt(M)
 //   WHT:     A[k][m] = (-1)^popcount(k & m) / sqrt(M), natural order
+#include <atomic>
+
 #include "se_internal.h"
 
 namespace sefase {
@@ -462,10 +464,18 @@ size_t tx_lds_bytes(int M, int N, int n_parts) {
 template <int MT, int NT, int NP>
 static se_status launch_tx(const TxArgs& a, const TxLayout& L, int grid, size_t lds,
                            hipStream_t s) {
-  if (lds > 64 * 1024 &&
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_project_tx<MT, NT, NP>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-    return fail(SE_EHIP, "project_tx: %zu bytes of LDS refused", lds);
+  // the LDS limit is raised once per device and instantiation, so that the
+  // launches of a caller's stream capture contain no attribute call
+  static std::atomic<uint64_t> raised{0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev > 63)
+    return fail(SE_EHIP, "project_tx: no current device");
+  if (lds > 64 * 1024 && !(raised.load() & (1ull << dev))) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_project_tx<MT, NT, NP>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+      return fail(SE_EHIP, "project_tx: %zu bytes of LDS refused", lds);
+    raised.fetch_or(1ull << dev);
+  }
   hipLaunchKernelGGL((k_project_tx<MT, NT, NP>), dim3(grid), dim3(64 * L.waves), lds, s, a, L);
   return check_launch("project_tx");
 }
