@@ -109,19 +109,37 @@ static size_t project_ws(const se_tables* t, int n_blk) {
   return cv.off + 256;
 }
 
-// Atom ranges [lo, hi) not covered by the tables' transform parts.
-static int dense_ranges(const se_tables* t, int lo[3], int hi[3]) {
-  const int P = t->M * t->N;
-  int f[2] = {0, 0}, n = t->n_parts;
-  for (int q = 0; q < n; ++q) f[q] = t->parts[q].first;
+// Atom ranges [lo, hi) not covered by transform parts.
+int dense_ranges(int K, int M, int N, int n_parts, const se_part* parts, int lo[3], int hi[3]) {
+  const int P = M * N;
+  int f[2] = {0, 0}, n = n_parts;
+  for (int q = 0; q < n; ++q) f[q] = parts[q].first;
   if (n == 2 && f[1] < f[0]) std::swap(f[0], f[1]);
   int c = 0, r = 0;
   for (int q = 0; q < n; ++q) {
     if (f[q] > c) { lo[r] = c; hi[r] = f[q]; ++r; }
     c = f[q] + P;
   }
-  if (c < t->K) { lo[r] = c; hi[r] = t->K; ++r; }
+  if (c < K) { lo[r] = c; hi[r] = K; ++r; }
   return r;
+}
+
+// Checks every atom of the declared parts against phi on the device and
+// waits for the verdict (flag: one device int32 of scratch).
+static se_status verify_parts(const se_basis* b, int32_t* flag, hipStream_t s) {
+  if (b->n_parts == 0) return SE_OK;
+  se_status st;
+  if (hipMemsetAsync(flag, 0, sizeof(int32_t), s) != hipSuccess)
+    return fail(SE_EHIP, "flag clear failed");
+  for (int q = 0; q < b->n_parts; ++q)
+    if ((st = check_part(b->phi, b->M, b->N, b->parts[q].kind, b->parts[q].first, flag, s)))
+      return st;
+  int32_t bad = 0;
+  if (hipMemcpyAsync(&bad, flag, sizeof(bad), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(SE_EHIP, "part verification: %s", hipGetErrorString(hipGetLastError()));
+  if (bad) return fail(SE_EINVAL, "a declared transform part does not match phi");
+  return SE_OK;
 }
 
 // gather + projection GEMM in the tables' precision, over the dense atoms;
@@ -135,7 +153,7 @@ static se_status project_into(const se_tables* t, const uint8_t* images, int H, 
   int nr = 1;
   if (t->n_parts > 0) {
     if ((st = project_tx(t, images, H, W, dblk, n_blk, R, ldR, s))) return st;
-    nr = dense_ranges(t, lo, hi);
+    nr = dense_ranges(t->K, t->M, t->N, t->n_parts, t->parts, lo, hi);
     if (nr == 0) return SE_OK;
   }
   const bool pad = t->n_parts == 0;   // else the transform kernel wrote the padding
@@ -262,22 +280,11 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
   float* diag32 = cv.take<float>((size_t)K);
   double* diag64 = cv.take<double>((size_t)K);
   int32_t* flag = cv.take<int32_t>(1);
-  if (b->n_parts > 0) {
-    // the projections of declared parts are computed from their definition,
-    // so the declaration must match the atoms actually given
-    if (hipMemsetAsync(flag, 0, sizeof(int32_t), s) != hipSuccess)
-      return fail(SE_EHIP, "flag clear failed");
-    for (int q = 0; q < b->n_parts; ++q)
-      if ((st = check_part(b->phi, b->M, b->N, b->parts[q].kind, b->parts[q].first, flag, s)))
-        return st;
-    int32_t bad = 0;
-    if (hipMemcpyAsync(&bad, flag, sizeof(bad), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return fail(SE_EHIP, "part verification: %s", hipGetErrorString(hipGetLastError()));
-    if (bad) {
-      t->n_parts = 0;
-      return fail(SE_EINVAL, "a declared transform part does not match phi");
-    }
+  // the projections of declared parts are computed from their definition,
+  // so the declaration must match the atoms actually given
+  if ((st = verify_parts(b, flag, s))) {
+    t->n_parts = 0;
+    return st;
   }
   launch_diag(b->phi, w, K, P, diag32, diag64, s);
   if ((st = check_launch("diag"))) return st;
@@ -461,6 +468,8 @@ size_t se_extrapolate_ondemand_ws_bytes(const se_basis* b, int32_t n_blk, int32_
   cv.take<float>(n * ld);
   cv.take<float>(2 * n);
   cv.take<float>(2 * n * (size_t)(max_loss > 0 ? max_loss : 1));
+  cv.take<int32_t>(1);
+  cv.take<float>(tx_const_bytes(b->M, b->N, b->n_parts) / 4);
   return cv.off + 256;
 }
 
@@ -524,6 +533,14 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* im
   pl.st = cv.take<float>((size_t)2 * n);
   pl.g = cv.take<float>((size_t)2 * n * max_loss);
   pl.gc = pl.g + (size_t)n * max_loss;
+  int32_t* flag = cv.take<int32_t>(1);
+  float* tx = cv.take<float>(tx_const_bytes(b->M, b->N, b->n_parts) / 4);
+  // declared transform parts: verified (one synchronisation of the stream),
+  // then their table rows are formed as transforms
+  if ((st = verify_parts(b, flag, s))) return st;
+  if (b->n_parts > 0 && (st = build_tx_basis(b, tx, s))) return st;
+  pl.basis = b;
+  pl.tx = tx;
   hipError_t e = hipMemcpyAsync(dblk, sorted.data(), sorted.size() * sizeof(se_block),
                                 hipMemcpyHostToDevice, s);
   if (e == hipSuccess)

@@ -232,6 +232,17 @@ se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s) {
   a.gamma = pl.gamma;
   a.sel = pl.sel;
   a.coef = pl.coef;
+  // atoms whose rows come from the dictionary product (all of them without
+  // transform parts)
+  const se_basis* bs = pl.basis;
+  const bool tx = bs && bs->n_parts > 0;
+  int lo[3] = {0, 0, 0}, hi[3] = {K, 0, 0};
+  const int nr = tx ? dense_ranges(K, pl.M, pl.N, bs->n_parts, bs->parts, lo, hi) : 1;
+  if (tx) {   // the row products no longer write the padding columns
+    hipLaunchKernelGGL(k_fill0, dim3((unsigned)(((size_t)n * pl.ld + 255) / 256)), dim3(256), 0, s,
+                       pl.rows, (size_t)n * pl.ld);
+    if ((st = check_launch("fill0"))) return st;
+  }
   for (int nu = 0; nu < pl.iters_max; ++nu) {
     const int act = pl.active[nu];        // blocks still iterating at nu (a prefix)
     if (act <= 0) break;
@@ -239,8 +250,13 @@ se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s) {
     hipLaunchKernelGGL(k_od_step, dim3(act), dim3(kOdThreads), 0, s, a);
     if ((st = check_launch("od_step"))) return st;
     const int nxt = nu + 1 < pl.iters_max ? pl.active[nu + 1] : 0;
-    if (nxt > 0)   // rows C_b[u_b][:] for the blocks that iterate again
-      if ((st = gemm_project_f32(pl.phi, P, K, pl.V, pl.ldV, nxt, P, pl.rows, pl.ld, 0, s)))
+    if (nxt <= 0) continue;
+    // rows C_b[u_b][:] for the blocks that iterate again: transforms of
+    // w_b phi_u for the parts, a product with the dictionary for the rest
+    if (tx && (st = rows_tx(bs, pl.tx, pl.V, pl.ldV, nxt, pl.rows, pl.ld, s))) return st;
+    for (int r = 0; r < nr; ++r)
+      if ((st = gemm_project_f32(pl.phi + (size_t)lo[r] * P, P, hi[r] - lo[r], pl.V, pl.ldV, nxt,
+                                 P, pl.rows + lo[r], pl.ld, 0, s, !tx)))
         return st;
   }
   hipLaunchKernelGGL(k_od_finish, dim3(n), dim3(256), 0, s, pl.blk, pl.orig, pl.g, pl.ldg,

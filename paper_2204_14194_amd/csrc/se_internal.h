@@ -106,8 +106,15 @@ size_t tx_lds_bytes(int M, int N, int n_parts);
 // from t->D and t->sqrtw
 size_t tx_const_bytes(int M, int N, int n_parts);
 se_status build_tx(const se_tables* t, hipStream_t s);
-// abi.cpp -- the host-side checks of a basis' part declaration
+// the A and B operands alone (for unscaled transforms) into tx
+se_status build_tx_basis(const se_basis* b, float* tx, hipStream_t s);
+// rows[b][first + k] = transform k of V[b] (M x N), for the parts of b
+se_status rows_tx(const se_basis* b, const float* tx, const float* V, int ldV, int n_blk,
+                  float* rows, int ld, hipStream_t s);
+// abi.cpp -- the host-side checks of a basis' part declaration; the atom
+// ranges outside the parts
 se_status check_basis_parts(const se_basis* b);
+int dense_ranges(int K, int M, int N, int n_parts, const se_part* parts, int lo[3], int hi[3]);
 
 // greedy.hip -- the iteration loop of Algorithm 3
 struct GreedyArgs {
@@ -151,6 +158,8 @@ struct OnDemandPlan {
   float* D;             // n_blk x ld
   float* rows;          // n_blk x ld
   int ld;               // multiple of 1024
+  const se_basis* basis;  // transform parts (rows formed as transforms)
+  const float* tx;        // their A and B operands (when n_parts > 0)
   float* st;            // n_blk x 2
   float* g;             // n_blk x ldg, followed by gc (n_blk x ldg)
   float* gc;

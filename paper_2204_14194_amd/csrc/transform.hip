@@ -148,6 +148,8 @@ __global__ __launch_bounds__(kTxThreads) void k_build_tx(TxBuildArgs a, TxLayout
       const int c = cs / NT, sq = cs - c * NT;
       const int k2 = 16 * c + (l & 15), n = 16 * sq + 4 * (l >> 4) + t;
       if (k2 < N && n < N) v = basis_1d(q ? a.kind1 : a.kind0, N, k2, n, ctN, iN, aN);
+    } else if (!a.D) {                      // operands of unscaled transforms only
+      break;
     } else if (x < L.oWf) {                 // Df
       const int z = x - L.oDf, q = z / nD, y = z - q * nD;
       const int e = y & 3, l = (y >> 2) & 63, cr = y >> 8;
@@ -170,9 +172,9 @@ __global__ __launch_bounds__(kTxThreads) void k_build_tx(TxBuildArgs a, TxLayout
 
 // Z_q = A_q X B_q^T of every part q < NP for the X operands x (registers,
 // x[i][sq][t] as above); the parts share the X operands and run as
-// independent accumulation chains.  out(q, k1, k2, D_k z) for every
-// k1 < M, k2 < N.
-template <int MT, int NT, int NP, typename Out>
+// independent accumulation chains.  out(q, k1, k2, v) for every k1 < M,
+// k2 < N, with v = D_k z when SCALE (Df read), else z.
+template <int MT, int NT, int NP, bool SCALE = true, typename Out>
 __device__ void tx_mfma(const float* Af, const float* Btf, const float* Df,
                         const floatx4 (&x)[MT][NT], int M, int N, Out out) {
   const int l = threadIdx.x & 63;
@@ -229,8 +231,9 @@ __device__ void tx_mfma(const float* Af, const float* Btf, const float* Df,
     for (int q = 0; q < NP; ++q)
 #pragma unroll
       for (int r = 0; r < MT; ++r) {
-        const floatx4 dv =
-            *reinterpret_cast<const floatx4*>(Df + q * MT * NT * 256 + ((c * MT + r) * 64 + l) * 4);
+        floatx4 dv = floatx4{1.f, 1.f, 1.f, 1.f};
+        if (SCALE)
+          dv = *reinterpret_cast<const floatx4*>(Df + q * MT * NT * 256 + ((c * MT + r) * 64 + l) * 4);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int k1 = 16 * r + 4 * (l >> 4) + e;
@@ -412,6 +415,73 @@ __global__ __launch_bounds__((tx_max_threads<MT, NT>())) void k_project_tx(TxArg
   }
 }
 
+// ---------------------------------------------------------------------------
+// Rows of the per-block tables formed on demand (eq. 16, row u of C_b) for
+// the transform parts: rows[b][first + k] = sum_p phi_k[p] V[b][p] with
+// V[b] = w_b phi_u (M x N floats), i.e. the transform A V_b B^T.  Same
+// matrix-core scheme as k_project_tx without the D scaling; the fragments of
+// A and B come first in the operand buffer.
+struct TxRowsArgs {
+  const float* V;
+  int ldV, n_blk;
+  const float* tx;
+  int first0, first1;
+  float* rows;
+  int ld;
+};
+
+template <int MT, int NT, int NP>
+__global__ __launch_bounds__((tx_max_threads<MT, NT>())) void k_rows_tx(TxRowsArgs a, TxLayout L) {
+  extern __shared__ floatx4 smv[];
+  float* sm = reinterpret_cast<float*>(smv);
+  {
+    const floatx4* src = reinterpret_cast<const floatx4*>(a.tx);
+    for (int x = threadIdx.x; x < L.oDf / 4; x += blockDim.x) smv[x] = src[x];
+  }
+  __syncthreads();
+  const int M = L.M, N = L.N;
+  const int l = threadIdx.x & 63, wave = threadIdx.x >> 6, W = blockDim.x >> 6;
+  const int lr = l & 15, lc = 4 * (l >> 4);
+  const bool vec = (N & 3) == 0;
+  for (int b = blockIdx.x * W + wave; b < a.n_blk; b += gridDim.x * W) {
+    const float* Vb = a.V + (size_t)b * a.ldV;
+    // every load at clamped (valid) coordinates and issued before the
+    // first use; entries outside the area are zeroed afterwards
+    floatx4 xv[MT][NT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+      const int m = 16 * i + lr;
+      const float* row = Vb + (size_t)min(m, M - 1) * N;
+#pragma unroll
+      for (int sq = 0; sq < NT; ++sq) {
+        const int n0 = 16 * sq + lc;
+        if (vec) {
+          xv[i][sq] = *reinterpret_cast<const floatx4*>(row + min(n0, N - 4));
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) xv[i][sq][t] = row[min(n0 + t, N - 1)];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int sq = 0; sq < NT; ++sq)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          float v = xv[i][sq][t];
+          asm volatile("" : "+v"(v));   // keeps the loads above unconditional
+          xv[i][sq][t] = (16 * i + lr < M && 16 * sq + lc + t < N) ? v : 0.0f;
+        }
+    float* R0 = a.rows + (size_t)b * a.ld + a.first0;
+    float* R1 = a.rows + (size_t)b * a.ld + a.first1;
+    tx_mfma<MT, NT, NP, false>(sm + L.oAf, sm + L.oBtf, nullptr, xv, M, N,
+                               [&](int q, int k1, int k2, float v) {
+                                 (q ? R1 : R0)[k1 * N + k2] = v;
+                               });
+  }
+}
+
 se_status check_part(const float* phi, int M, int N, int kind, int first, int* dflag,
                      hipStream_t s) {
   const size_t lds = (size_t)4 * (M + N) * 8 + (size_t)(M * M + N * N) * 4;
@@ -444,6 +514,25 @@ se_status build_tx(const se_tables* t, hipStream_t s) {
   hipLaunchKernelGGL(k_build_tx, dim3(grid), dim3(kTxThreads), (size_t)4 * (t->M + t->N) * 8, s,
                      a, L);
   return check_launch("build_tx");
+}
+
+se_status build_tx_basis(const se_basis* b, float* tx, hipStream_t s) {
+  TxBuildArgs a;
+  a.M = b->M;
+  a.N = b->N;
+  a.parts = b->n_parts;
+  a.kind0 = b->parts[0].kind;
+  a.first0 = b->parts[0].first;
+  a.kind1 = b->n_parts > 1 ? b->parts[1].kind : 0;
+  a.first1 = b->n_parts > 1 ? b->parts[1].first : 0;
+  a.D = nullptr;
+  a.sqrtw = nullptr;
+  a.tx = tx;
+  const TxLayout L(b->M, b->N, b->n_parts, 0);
+  const int grid = (L.oDf + kTxThreads - 1) / kTxThreads;
+  hipLaunchKernelGGL(k_build_tx, dim3(grid), dim3(kTxThreads), (size_t)4 * (b->M + b->N) * 8, s,
+                     a, L);
+  return check_launch("build_tx_basis");
 }
 
 // Waves per workgroup: the kernel's workgroup bound, fewer when that leaves
@@ -485,6 +574,63 @@ static se_status launch_tx_np(const TxArgs& a, const TxLayout& L, int grid, size
                               hipStream_t s) {
   return L.parts == 2 ? launch_tx<MT, NT, 2>(a, L, grid, lds, s)
                       : launch_tx<MT, NT, 1>(a, L, grid, lds, s);
+}
+
+template <int MT, int NT, int NP>
+static se_status launch_rows(const TxRowsArgs& a, const TxLayout& L, int grid, size_t lds,
+                             hipStream_t s) {
+  static std::atomic<uint64_t> raised{0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev > 63)
+    return fail(SE_EHIP, "rows_tx: no current device");
+  if (lds > 64 * 1024 && !(raised.load() & (1ull << dev))) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rows_tx<MT, NT, NP>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+      return fail(SE_EHIP, "rows_tx: %zu bytes of LDS refused", lds);
+    raised.fetch_or(1ull << dev);
+  }
+  hipLaunchKernelGGL((k_rows_tx<MT, NT, NP>), dim3(grid), dim3(64 * L.waves), lds, s, a, L);
+  return check_launch("rows_tx");
+}
+
+template <int MT, int NT>
+static se_status launch_rows_np(const TxRowsArgs& a, const TxLayout& L, int grid, size_t lds,
+                                hipStream_t s) {
+  return L.parts == 2 ? launch_rows<MT, NT, 2>(a, L, grid, lds, s)
+                      : launch_rows<MT, NT, 1>(a, L, grid, lds, s);
+}
+
+se_status rows_tx(const se_basis* b, const float* tx, const float* V, int ldV, int n_blk,
+                  float* rows, int ld, hipStream_t s) {
+  if (n_blk <= 0) return SE_OK;
+  if (b->n_parts < 1 || b->n_parts > 2) return fail(SE_EINVAL, "no transform part declared");
+  TxRowsArgs a;
+  a.V = V;
+  a.ldV = ldV;
+  a.n_blk = n_blk;
+  a.tx = tx;
+  a.first0 = b->parts[0].first;
+  a.first1 = b->n_parts > 1 ? b->parts[1].first : 0;
+  a.rows = rows;
+  a.ld = ld;
+  const int MT = (b->M + 15) / 16, NT = (b->N + 15) / 16;
+  int waves = (MT >= 3 || MT * NT >= 6) ? 4 : 16;
+  while (waves > 1 && (long long)waves * 256 > n_blk) waves /= 2;
+  const TxLayout L(b->M, b->N, b->n_parts, waves);
+  const size_t lds = (size_t)L.oDf * 4;
+  const int per_cu = (int)std::min<size_t>(4, (160 * 1024) / lds);
+  const int grid = std::max(1, std::min((n_blk + waves - 1) / waves, 256 * per_cu));
+  switch (MT * 10 + NT) {
+#define SE_TX_CASE(mt, nt) \
+  case mt * 10 + nt:       \
+    return launch_rows_np<mt, nt>(a, L, grid, lds, s);
+    SE_TX_CASE(1, 1) SE_TX_CASE(1, 2) SE_TX_CASE(1, 3) SE_TX_CASE(1, 4)
+    SE_TX_CASE(2, 1) SE_TX_CASE(2, 2) SE_TX_CASE(2, 3) SE_TX_CASE(2, 4)
+    SE_TX_CASE(3, 1) SE_TX_CASE(3, 2) SE_TX_CASE(3, 3) SE_TX_CASE(3, 4)
+    SE_TX_CASE(4, 1) SE_TX_CASE(4, 2) SE_TX_CASE(4, 3) SE_TX_CASE(4, 4)
+#undef SE_TX_CASE
+    default: return fail(SE_EINVAL, "transform parts need M, N <= 64");
+  }
 }
 
 se_status project_tx(const se_tables* t, const uint8_t* images, int H, int W, const DevBlock* blk,

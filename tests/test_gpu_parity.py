@@ -325,13 +325,16 @@ def test_ondemand_equals_shared_tables_on_isolated_blocks():
     assert np.abs(g - g_b).max() <= TOL_FP32
 
 
+@pytest.mark.parametrize("with_parts", [False, True])
 @pytest.mark.parametrize("area", [24, 32, 48])
-def test_ondemand_clustered_losses(area):
+def test_ondemand_clustered_losses(area, with_parts):
     """Blocks of the clustered/burst workload (other losses and the frame
     border inside the areas, so every block has its own weights), one area
     size per dictionary, per-block iteration counts; a sample against the
-    FP64 oracle."""
-    say(f"on-demand clustered losses: area {area}")
+    FP64 oracle.  With parts, the rows of the DCT/WHT atoms are formed as
+    transforms of w_b phi_u (Section VI) and the rest by the product with the
+    dictionary."""
+    say(f"on-demand clustered losses: area {area}, transform parts {with_parts}")
     d = synth.clustered_inputs(n_img=1, blocks_per_img=500)
     blocks = [b for b in d["blocks"] if b.ly * 2 + b.lh == area]
     iters = [int(v) for v, b in zip(d["iters"], d["blocks"]) if b.ly * 2 + b.lh == area]
@@ -342,7 +345,7 @@ def test_ondemand_clustered_losses(area):
     w = B.area_weights(area, area, 0.8, torch.from_numpy(lost).to(dev()), blocks)
     img_d = torch.from_numpy(img).to(dev())
     sel, coef, g = B.extrapolate_ondemand(upload_phi(phi), area, area, w, img_d, blocks, 0.5,
-                                          iters)
+                                          iters, parts=d["tx_parts"][area] if with_parts else ())
     torch.cuda.synchronize()
     sel, g, out = sel.cpu().numpy(), g.cpu().numpy(), img_d.cpu().numpy()
     rng = np.random.default_rng(area)
