@@ -399,12 +399,20 @@ def bench_area48(args):
     t = _shared_tables(B, torch, dev, d["images"], blocks, d["phi"], 48, 48, B.SE_FP32,
                        () if args.no_parts else d["tx_parts"])
     img = torch.from_numpy(d["images"]).to(dev)
+    tuned = None
+    if not args.no_autotune:   # loop shape and GEMM tile for this batch
+        dblk = B.DeviceBlocks(t, img, blocks)
+        R = torch.empty((len(blocks), t.ldG), dtype=torch.float32, device=dev)
+        wsp = torch.empty(max(1, B.project_ws_bytes(t, len(blocks))), dtype=torch.uint8,
+                          device=dev)
+        tuned = B.autotune_batch(t, img, dblk, R, wsp, 0.5, 200, reps=3)
     ws = torch.empty(B.extrapolate_batch_ws_bytes(t, len(blocks)), dtype=torch.uint8, device=dev)
     arr = B.blocks_array(blocks)
     ms = _timed(lambda: B.extrapolate_batch(t, img, blocks, 0.5, 200, False, False, False, ws=ws,
                                             blocks_arr=arr), args.steps, args.warmup)
     med = float(np.median(ms))
     return {"metric": "concealed blocks/s, 48x48 areas, K=4096, I=200 (batched FP32)",
+            "autotune": tuned,
             "value": len(blocks) / (med * 1e-3), "unit": "blocks/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": med,
             "higher_is_better": True, "dtype": "f32", "data": "synthetic",
@@ -469,26 +477,34 @@ def bench_area64(args):
            "unit": "blocks/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
            "config": {"workload": "2048x2048 image, 1024 64x64 areas with 16x16 losses, "
                                   "K=8192, I=300"}}
+    parts = () if args.no_parts else d["tx_parts"]
+    phi_d = torch.from_numpy(d["phi"].astype(np.float32)).to(dev)
+    lost = synth.lost_mask(2048, 2048, blocks)[None]
+    lost_d = torch.from_numpy(lost).to(dev)
     for name, prec in (("fp32", B.SE_FP32), ("bf16x3", B.SE_BF16X3)):
         gram = []
-        for _ in range(3):
+        for _ in range(3):   # weights + Algorithm 2 (inputs already on the device)
             e0, e1 = _events(2)
             e0.record()
-            t = _shared_tables(B, torch, dev, d["images"], blocks, d["phi"], 64, 64, prec,
-                               () if args.no_parts else d["tx_parts"])
+            w = B.area_weights(64, 64, RHO, lost_d, blocks[:1])
+            t = B.weighted_gram(phi_d, w[0].contiguous(), 64, 64, prec, parts=parts)
             e1.record()
             e1.synchronize()
             gram.append(e0.elapsed_time(e1))
         img = torch.from_numpy(d["images"]).to(dev)
         dblk = B.DeviceBlocks(t, img, blocks)
         R = torch.empty((len(blocks), B.table_ld(8192)), dtype=torch.float32, device=dev)
-        ws = torch.empty(B.project_ws_bytes(t, len(blocks)), dtype=torch.uint8, device=dev)
+        ws = torch.empty(max(1, B.project_ws_bytes(t, len(blocks))), dtype=torch.uint8,
+                         device=dev)
         proj = _timed(lambda: B.project(t, img, dblk, R, ws), args.steps, args.warmup)
         loop = _timed(lambda: B.iterate(t, R, img, dblk, 0.5, 300), max(2, args.steps // 4), 1)
         step = float(np.median(proj)) + float(np.median(loop))
-        flops = 2.0 * 8192 * 4096 * len(blocks)
+        # projection work: the GEMM against all atoms, or two separable
+        # products per declared part
+        flops = (2.0 * 8192 * 4096 if not parts else 2.0 * len(parts) * 4096 * 128) * len(blocks)
         out[name] = {"blocks_per_s": len(blocks) / (step * 1e-3), "ms_per_step": step,
                      "project_ms": float(np.median(proj)),
+                     "project_form": "transform" if parts else "gemm",
                      "project_tflops": flops / (np.median(proj) * 1e-3) / 1e12,
                      "loop_ms": float(np.median(loop)), "gram_ms": min(gram),
                      "gram_tflops": 8192 * 8193 * 4096 / (min(gram) * 1e-3) / 1e12}
