@@ -95,9 +95,11 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 struct TxLayout {
   int M, N, MT, NT, parts, waves;
-  // offsets in floats; [0, nconst) is the copy of se_tables.tx
-  int oAf, oBtf, oDf, oWf, nconst, oXf, nfloat;
-  __host__ __device__ TxLayout(int M_, int N_, int parts_, int waves_)
+  // offsets in floats; [0, nconst) is the copy of se_tables.tx.  Each wave
+  // owns wsz floats at oXf: its X fragments, and with staging (zs > 0) one
+  // part's M x N output at row stride zs.
+  int oAf, oBtf, oDf, oWf, nconst, oXf, zs, wsz, nfloat;
+  __host__ __device__ TxLayout(int M_, int N_, int parts_, int waves_, bool stage = false)
       : M(M_), N(N_), parts(parts_), waves(waves_) {
     MT = (M + 15) / 16;
     NT = (N + 15) / 16;
@@ -107,7 +109,9 @@ struct TxLayout {
     oWf = oDf + parts * MT * NT * 256;
     nconst = oWf + MT * NT * 256;
     oXf = nconst;
-    nfloat = oXf + waves * MT * NT * 256;
+    zs = stage ? N + 4 : 0;
+    wsz = MT * NT * 256 > M * zs ? MT * NT * 256 : M * zs;
+    nfloat = oXf + waves * wsz;
   }
   __host__ __device__ size_t bytes() const { return (size_t)nfloat * 4; }
 };
@@ -170,77 +174,83 @@ __global__ __launch_bounds__(kTxThreads) void k_build_tx(TxBuildArgs a, TxLayout
   }
 }
 
-// Z_q = A_q X B_q^T of every part q < NP for the X operands x (registers,
-// x[i][sq][t] as above); the parts share the X operands and run as
-// independent accumulation chains.  out(q, k1, k2, v) for every k1 < M,
-// k2 < N, with v = D_k z when SCALE (Df read), else z.
-template <int MT, int NT, int NP, bool SCALE = true, typename Out>
-__device__ void tx_mfma(const float* Af, const float* Btf, const float* Df,
-                        const floatx4 (&x)[MT][NT], int M, int N, Out out) {
+// Column tiles c0 .. c0 + CP - 1 of Z = A X B^T for one part, from the X
+// operands x (registers, x[i][sq][t] as above); the CP tiles share the X and
+// A operands and run as independent accumulation chains.  out(k1, k2, v)
+// for every k1 < M, k2 < N of those tiles, v = D_k z when SCALE (Df read),
+// else z.
+template <int MT, int NT, int CP, bool SCALE, typename Out>
+__device__ inline void tx_cols(int c0, const float* Af, const float* Btf, const float* Df,
+                               const floatx4 (&x)[MT][NT], int M, int N, Out& out) {
   const int l = threadIdx.x & 63;
-#pragma unroll 1
-  for (int c = 0; c < NT; ++c) {
-    // re-read the A operands per column tile instead of holding them all
-    // in registers across the loop (they would cost 16 NP MT^2 / 4 VGPRs)
-    asm volatile("" : "+s"(Af));
-    floatx4 y[NP][MT];
+  floatx4 y[CP][MT];
 #pragma unroll
-    for (int q = 0; q < NP; ++q)
+  for (int cc = 0; cc < CP; ++cc)
 #pragma unroll
-      for (int i = 0; i < MT; ++i) y[q][i] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < MT; ++i) y[cc][i] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int sq = 0; sq < NT; ++sq) {
-      floatx4 bv[NP];
+  for (int sq = 0; sq < NT; ++sq) {
+    floatx4 bv[CP];
 #pragma unroll
-      for (int q = 0; q < NP; ++q)
-        bv[q] = *reinterpret_cast<const floatx4*>(Btf + q * NT * NT * 256 +
-                                                  ((c * NT + sq) * 64 + l) * 4);
+    for (int cc = 0; cc < CP; ++cc)
+      bv[cc] = *reinterpret_cast<const floatx4*>(Btf + (((c0 + cc) * NT + sq) * 64 + l) * 4);
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int q = 0; q < NP; ++q)
+      for (int cc = 0; cc < CP; ++cc)
 #pragma unroll
-          for (int i = 0; i < MT; ++i)
-            y[q][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[i][sq][t], bv[q][t], y[q][i], 0, 0, 0);
-    }
-    floatx4 z[NP][MT];
+        for (int i = 0; i < MT; ++i)
+          y[cc][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[i][sq][t], bv[cc][t], y[cc][i], 0, 0, 0);
+  }
+  floatx4 z[CP][MT];
 #pragma unroll
-    for (int q = 0; q < NP; ++q)
+  for (int cc = 0; cc < CP; ++cc)
 #pragma unroll
-      for (int r = 0; r < MT; ++r) z[q][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int r = 0; r < MT; ++r) z[cc][r] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int i = 0; i < MT; ++i) {
-      floatx4 av[NP][MT];
+  for (int i = 0; i < MT; ++i) {
+    floatx4 av[MT];
 #pragma unroll
-      for (int q = 0; q < NP; ++q)
+    for (int r = 0; r < MT; ++r)
+      av[r] = *reinterpret_cast<const floatx4*>(Af + ((r * MT + i) * 64 + l) * 4);
+    // consecutive products go to different accumulators
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int cc = 0; cc < CP; ++cc)
 #pragma unroll
         for (int r = 0; r < MT; ++r)
-          av[q][r] = *reinterpret_cast<const floatx4*>(Af + q * MT * MT * 256 +
-                                                       ((r * MT + i) * 64 + l) * 4);
-      // consecutive products go to different accumulators
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-#pragma unroll
-        for (int q = 0; q < NP; ++q)
-#pragma unroll
-          for (int r = 0; r < MT; ++r)
-            z[q][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q][r][e], y[q][i][e], z[q][r], 0, 0, 0);
-    }
-    const int k2 = 16 * c + (l & 15);
-#pragma unroll
-    for (int q = 0; q < NP; ++q)
-#pragma unroll
-      for (int r = 0; r < MT; ++r) {
-        floatx4 dv = floatx4{1.f, 1.f, 1.f, 1.f};
-        if (SCALE)
-          dv = *reinterpret_cast<const floatx4*>(Df + q * MT * NT * 256 + ((c * MT + r) * 64 + l) * 4);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int k1 = 16 * r + 4 * (l >> 4) + e;
-          if (k1 < M && k2 < N) out(q, k1, k2, dv[e] * z[q][r][e]);
-        }
-      }
+          z[cc][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r][e], y[cc][i][e], z[cc][r], 0, 0, 0);
   }
+#pragma unroll
+  for (int cc = 0; cc < CP; ++cc) {
+    const int c = c0 + cc, k2 = 16 * c + (l & 15);
+#pragma unroll
+    for (int r = 0; r < MT; ++r) {
+      floatx4 dv = floatx4{1.f, 1.f, 1.f, 1.f};
+      if (SCALE) dv = *reinterpret_cast<const floatx4*>(Df + ((c * MT + r) * 64 + l) * 4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k1 = 16 * r + 4 * (l >> 4) + e;
+        if (k1 < M && k2 < N) out(k1, k2, dv[e] * z[cc][r][e]);
+      }
+    }
+  }
+}
+
+// Z = A X B^T of one part (operand fragments of that part), two column
+// tiles per pass.
+template <int MT, int NT, bool SCALE, typename Out>
+__device__ void tx_part(const float* Af, const float* Btf, const float* Df,
+                        const floatx4 (&x)[MT][NT], int M, int N, Out out) {
+#pragma unroll 1
+  for (int c0 = 0; c0 + 1 < NT; c0 += 2) {
+    // re-read the A operands per pass instead of holding them in registers
+    // across the loop
+    asm volatile("" : "+s"(Af));
+    tx_cols<MT, NT, 2, SCALE>(c0, Af, Btf, Df, x, M, N, out);
+  }
+  if (NT & 1) tx_cols<MT, NT, 1, SCALE>(NT - 1, Af, Btf, Df, x, M, N, out);
 }
 
 // Orders this wave's LDS writes before its later reads (and reads before
@@ -379,13 +389,13 @@ constexpr int tx_max_threads() {
   return (MT >= 3 || MT * NT >= 6) ? 256 : 1024;
 }
 
-template <int MT, int NT, int NP>
+template <int MT, int NT, int NP, bool STAGE>
 __global__ __launch_bounds__((tx_max_threads<MT, NT>())) void k_project_tx(TxArgs a, TxLayout L) {
   extern __shared__ floatx4 smv[];
   float* sm = reinterpret_cast<float*>(smv);
   const int M = L.M, N = L.N;
   const int l = threadIdx.x & 63, wave = threadIdx.x >> 6, W = blockDim.x >> 6;
-  float* Xf = sm + L.oXf + wave * MT * NT * 256;
+  float* Xf = sm + L.oXf + wave * L.wsz;
   // the first block's pixel loads and the copy of the constant operands
   // are in flight together
   int b = blockIdx.x * W + wave;
@@ -406,12 +416,29 @@ __global__ __launch_bounds__((tx_max_threads<MT, NT>())) void k_project_tx(TxArg
     tx_x_operands<MT, NT>(a, d, M, N, P, sm + L.oWf, Xf, xv);
     float* Rb = a.R + (size_t)b * a.ldR;
     for (int k = a.K + l; k < a.ldR; k += 64) Rb[k] = 0.0f;
-    float* R0 = Rb + a.first0;
-    float* R1 = Rb + a.first1;
-    tx_mfma<MT, NT, NP>(sm + L.oAf, sm + L.oBtf, sm + L.oDf, xv, M, N,
-                        [&](int q, int k1, int k2, float v) {
-                          (q ? R1 : R0)[k1 * N + k2] = v;
-                        });
+#pragma unroll 1
+    for (int q = 0; q < NP; ++q) {
+      float* Rq = Rb + (q ? a.first1 : a.first0);
+      const float* Af = sm + L.oAf + q * MT * MT * 256;
+      const float* Btf = sm + L.oBtf + q * NT * NT * 256;
+      const float* Df = sm + L.oDf + q * MT * NT * 256;
+      if (STAGE) {
+        // the part's output goes to this wave's LDS first and then to R as
+        // whole 16-byte lanes of contiguous memory (full cache lines)
+        wave_sync();   // the X operands and the previous part are read
+        tx_part<MT, NT, true>(Af, Btf, Df, xv, M, N,
+                              [&](int k1, int k2, float v) { Xf[k1 * L.zs + k2] = v; });
+        wave_sync();
+        for (int k = 4 * l; k < M * N; k += 256) {
+          const int k1 = k / N, k2 = k - k1 * N;
+          *reinterpret_cast<floatx4*>(Rq + k) = *reinterpret_cast<const floatx4*>(Xf + k1 * L.zs + k2);
+        }
+      } else {
+        tx_part<MT, NT, true>(Af, Btf, Df, xv, M, N,
+                              [&](int k1, int k2, float v) { Rq[k1 * N + k2] = v; });
+      }
+    }
+    if (STAGE) wave_sync();   // the copies read before the next block's X writes
   }
 }
 
@@ -473,12 +500,13 @@ __global__ __launch_bounds__((tx_max_threads<MT, NT>())) void k_rows_tx(TxRowsAr
           asm volatile("" : "+v"(v));   // keeps the loads above unconditional
           xv[i][sq][t] = (16 * i + lr < M && 16 * sq + lc + t < N) ? v : 0.0f;
         }
-    float* R0 = a.rows + (size_t)b * a.ld + a.first0;
-    float* R1 = a.rows + (size_t)b * a.ld + a.first1;
-    tx_mfma<MT, NT, NP, false>(sm + L.oAf, sm + L.oBtf, nullptr, xv, M, N,
-                               [&](int q, int k1, int k2, float v) {
-                                 (q ? R1 : R0)[k1 * N + k2] = v;
-                               });
+#pragma unroll 1
+    for (int q = 0; q < NP; ++q) {
+      float* Rq = a.rows + (size_t)b * a.ld + (q ? a.first1 : a.first0);
+      tx_part<MT, NT, false>(sm + L.oAf + q * MT * MT * 256, sm + L.oBtf + q * NT * NT * 256,
+                             nullptr, xv, M, N,
+                             [&](int k1, int k2, float v) { Rq[k1 * N + k2] = v; });
+    }
   }
 }
 
@@ -550,7 +578,7 @@ size_t tx_lds_bytes(int M, int N, int n_parts) {
   return w ? TxLayout(M, N, n_parts, w).bytes() : 0;
 }
 
-template <int MT, int NT, int NP>
+template <int MT, int NT, int NP, bool STAGE>
 static se_status launch_tx(const TxArgs& a, const TxLayout& L, int grid, size_t lds,
                            hipStream_t s) {
   // the LDS limit is raised once per device and instantiation, so that the
@@ -560,20 +588,24 @@ static se_status launch_tx(const TxArgs& a, const TxLayout& L, int grid, size_t 
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev > 63)
     return fail(SE_EHIP, "project_tx: no current device");
   if (lds > 64 * 1024 && !(raised.load() & (1ull << dev))) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_project_tx<MT, NT, NP>),
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_project_tx<MT, NT, NP, STAGE>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
       return fail(SE_EHIP, "project_tx: %zu bytes of LDS refused", lds);
     raised.fetch_or(1ull << dev);
   }
-  hipLaunchKernelGGL((k_project_tx<MT, NT, NP>), dim3(grid), dim3(64 * L.waves), lds, s, a, L);
+  hipLaunchKernelGGL((k_project_tx<MT, NT, NP, STAGE>), dim3(grid), dim3(64 * L.waves), lds, s, a,
+                     L);
   return check_launch("project_tx");
 }
 
 template <int MT, int NT>
 static se_status launch_tx_np(const TxArgs& a, const TxLayout& L, int grid, size_t lds,
                               hipStream_t s) {
-  return L.parts == 2 ? launch_tx<MT, NT, 2>(a, L, grid, lds, s)
-                      : launch_tx<MT, NT, 1>(a, L, grid, lds, s);
+  if (L.zs > 0)
+    return L.parts == 2 ? launch_tx<MT, NT, 2, true>(a, L, grid, lds, s)
+                        : launch_tx<MT, NT, 1, true>(a, L, grid, lds, s);
+  return L.parts == 2 ? launch_tx<MT, NT, 2, false>(a, L, grid, lds, s)
+                      : launch_tx<MT, NT, 1, false>(a, L, grid, lds, s);
 }
 
 template <int MT, int NT, int NP>
@@ -650,7 +682,11 @@ se_status project_tx(const se_tables* t, const uint8_t* images, int H, int W, co
   a.ldR = ldR;
   const int waves = tx_waves(t->M, t->N, t->n_parts, n_blk);
   if (waves == 0) return fail(SE_EINVAL, "transform of a %dx%d area exceeds LDS", t->M, t->N);
-  const TxLayout L(t->M, t->N, t->n_parts, waves);
+  // staged (coalesced) output when rows of four floats stay aligned and the
+  // staging area fits beside the operands
+  bool stage = (t->N & 3) == 0 && (a.first0 & 3) == 0 && (a.first1 & 3) == 0 && (ldR & 3) == 0 &&
+               TxLayout(t->M, t->N, t->n_parts, waves, true).bytes() <= 160 * 1024;
+  const TxLayout L(t->M, t->N, t->n_parts, waves, stage);
   const size_t lds = L.bytes();
   // about one block per wave, at most four workgroups per compute unit
   const int per_cu = (int)std::min<size_t>(4, (160 * 1024) / lds);
