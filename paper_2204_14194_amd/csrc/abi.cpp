@@ -296,9 +296,31 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
   if (t->n_parts > 0 && (st = build_tx(t, s))) return st;
   launch_zero_cols(t->G, K, K, t->ldG, s);
   if ((st = check_launch("zero_cols"))) return st;
+  if (prec == SE_BF16X3) {
+    launch_split_bf16(t->Y, (size_t)K * P, t->Yhi, t->Ylo, s);
+    if ((st = check_launch("split_bf16"))) return st;
+  }
+  // With transform parts and at most one dense range (starting on a 4-float
+  // boundary), every row over the part columns is a transform of the
+  // weighted atom (Section VI), the dense x dense block is the product of the
+  // dense atoms, and a mirror pass fills the parts' rows over the dense
+  // columns; otherwise the whole table is one symmetric product.
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  const int nr = t->n_parts > 0 ? dense_ranges(K, b->M, b->N, t->n_parts, t->parts, lo, hi) : 3;
+  if (nr <= 1 && (lo[0] & 3) == 0) {
+    if ((st = gram_tx(t, s))) return st;
+    if (nr == 1) {
+      const int kd = hi[0] - lo[0];
+      float* Gd = t->G + (size_t)lo[0] * t->ldG + lo[0];
+      st = prec == SE_FP32
+               ? gemm_syrk_f32(t->Y + (size_t)lo[0] * P, P, kd, P, Gd, t->ldG, s)
+               : gemm_syrk_bf16x3(t->Yhi + (size_t)lo[0] * P, t->Ylo + (size_t)lo[0] * P, P, kd, P,
+                                  Gd, t->ldG, s);
+      if (st) return st;
+    }
+    return gram_mirror(t, s);
+  }
   if (prec == SE_FP32) return gemm_syrk_f32(t->Y, P, K, P, t->G, t->ldG, s);
-  launch_split_bf16(t->Y, (size_t)K * P, t->Yhi, t->Ylo, s);
-  if ((st = check_launch("split_bf16"))) return st;
   return gemm_syrk_bf16x3(t->Yhi, t->Ylo, P, K, P, t->G, t->ldG, s);
 }
 

@@ -106,6 +106,10 @@ size_t tx_lds_bytes(int M, int N, int n_parts);
 // from t->D and t->sqrtw
 size_t tx_const_bytes(int M, int N, int n_parts);
 se_status build_tx(const se_tables* t, hipStream_t s);
+// table rows of every atom over the part columns (transforms of w phi_k),
+// then the mirror pass that completes the parts' rows and exact symmetry
+se_status gram_tx(const se_tables* t, hipStream_t s);
+se_status gram_mirror(const se_tables* t, hipStream_t s);
 // the A and B operands alone (for unscaled transforms) into tx
 se_status build_tx_basis(const se_basis* b, float* tx, hipStream_t s);
 // rows[b][first + k] = transform k of V[b] (M x N), for the parts of b

@@ -510,6 +510,118 @@ __global__ __launch_bounds__((tx_max_threads<MT, NT>())) void k_rows_tx(TxRowsAr
   }
 }
 
+// ---------------------------------------------------------------------------
+// Table rows from transforms (Algorithm 2 for the transform parts, eq. 16):
+// for atom k and part q, G[k][first_q + j] = D_k D_{first_q + j}
+// sum_p w phi_k phi_{first_q + j} = D_k (D_q ⊙ T_q(w phi_k))_j -- the
+// transform of the weighted atom, the same scheme as k_project_tx with the
+// atom's FP32 values in place of the pixels.  Every atom's row is formed over
+// the part columns; the rest of the table comes from the product of the
+// dense atoms and a mirror pass.
+struct TxGramArgs {
+  const float* phi;
+  int K;
+  const float* tx;
+  const float* D;
+  int first0, first1;
+  float* G;
+  int ldG;
+};
+
+template <int MT, int NT, int NP>
+__global__ __launch_bounds__((tx_max_threads<MT, NT>())) void k_gram_tx(TxGramArgs a, TxLayout L) {
+  extern __shared__ floatx4 smv[];
+  float* sm = reinterpret_cast<float*>(smv);
+  {
+    const floatx4* src = reinterpret_cast<const floatx4*>(a.tx);
+    for (int x = threadIdx.x; x < L.nconst / 4; x += blockDim.x) smv[x] = src[x];
+  }
+  __syncthreads();
+  const int M = L.M, N = L.N, P = M * N;
+  const int l = threadIdx.x & 63, wave = threadIdx.x >> 6, W = blockDim.x >> 6;
+  const int lr = l & 15, lc = 4 * (l >> 4);
+  const bool vec = (N & 3) == 0;
+  float* Zs = sm + L.oXf + wave * L.wsz;
+  for (int k = blockIdx.x * W + wave; k < a.K; k += gridDim.x * W) {
+    const float* row = a.phi + (size_t)k * P;
+    // X operands w phi_k, loaded at clamped coordinates (issued before the
+    // first use) and zeroed outside the area
+    floatx4 xv[MT][NT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+      const float* r = row + (size_t)min(16 * i + lr, M - 1) * N;
+#pragma unroll
+      for (int sq = 0; sq < NT; ++sq) {
+        const int n0 = 16 * sq + lc;
+        if (vec) {
+          xv[i][sq] = *reinterpret_cast<const floatx4*>(r + min(n0, N - 4));
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) xv[i][sq][t] = r[min(n0 + t, N - 1)];
+        }
+      }
+    }
+    const float Dk = a.D[k];
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int sq = 0; sq < NT; ++sq) {
+        const floatx4 w = *reinterpret_cast<const floatx4*>(sm + L.oWf + ((i * NT + sq) * 64 + l) * 4);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          float v = xv[i][sq][t];
+          asm volatile("" : "+v"(v));   // keeps the loads above unconditional
+          xv[i][sq][t] = (16 * i + lr < M && 16 * sq + lc + t < N) ? w[t] * v : 0.0f;
+        }
+      }
+    float* Gk = a.G + (size_t)k * a.ldG;
+#pragma unroll 1
+    for (int q = 0; q < NP; ++q) {
+      float* Gq = Gk + (q ? a.first1 : a.first0);
+      const float* Af = sm + L.oAf + q * MT * MT * 256;
+      const float* Btf = sm + L.oBtf + q * NT * NT * 256;
+      const float* Df = sm + L.oDf + q * MT * NT * 256;
+      if (L.zs > 0) {   // staged: the row segment is written as whole lines
+        wave_sync();
+        tx_part<MT, NT, true>(Af, Btf, Df, xv, M, N,
+                              [&](int k1, int k2, float v) { Zs[k1 * L.zs + k2] = Dk * v; });
+        wave_sync();
+        for (int j = 4 * l; j < P; j += 256) {
+          const int k1 = j / N, k2 = j - k1 * N;
+          *reinterpret_cast<floatx4*>(Gq + j) = *reinterpret_cast<const floatx4*>(Zs + k1 * L.zs + k2);
+        }
+      } else {
+        tx_part<MT, NT, true>(Af, Btf, Df, xv, M, N,
+                              [&](int k1, int k2, float v) { Gq[k1 * N + k2] = Dk * v; });
+      }
+    }
+    wave_sync();
+  }
+}
+
+// The entries no transform row produced, and exact symmetry: for rows r of
+// a part, G[r][c] = G[c][r] where column c is a dense atom (the dense row c
+// holds the value over its part columns) or a part atom with c > r (the
+// lower triangle's value).  Dense x dense entries come from the product of
+// the dense atoms.  32 x 32 tiles, transposed through LDS.
+__global__ __launch_bounds__(256) void k_gram_mirror(float* __restrict__ G, int ldG, int K, int p0,
+                                                     int q0, int P) {
+  __shared__ float tile[32][33];
+  const int rb = blockIdx.y * 32, cb = blockIdx.x * 32;
+  auto in_part = [&](int i) { return (i >= p0 && i < p0 + P) || (i >= q0 && i < q0 + P); };
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int y = ty; y < 32; y += 8) {   // source G[c][r]: rows cb.., columns rb..
+    const int c = cb + y, r = rb + tx;
+    tile[y][tx] = (c < K && r < K) ? G[(size_t)c * ldG + r] : 0.0f;
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int r = rb + y, c = cb + tx;
+    if (r < K && c < K && in_part(r) && (!in_part(c) || c > r))
+      G[(size_t)r * ldG + c] = tile[tx][y];
+  }
+}
+
 se_status check_part(const float* phi, int M, int N, int kind, int first, int* dflag,
                      hipStream_t s) {
   const size_t lds = (size_t)4 * (M + N) * 8 + (size_t)(M * M + N * N) * 4;
@@ -561,6 +673,76 @@ se_status build_tx_basis(const se_basis* b, float* tx, hipStream_t s) {
   hipLaunchKernelGGL(k_build_tx, dim3(grid), dim3(kTxThreads), (size_t)4 * (b->M + b->N) * 8, s,
                      a, L);
   return check_launch("build_tx_basis");
+}
+
+template <int MT, int NT, int NP>
+static se_status launch_gram(const TxGramArgs& a, const TxLayout& L, int grid, size_t lds,
+                             hipStream_t s) {
+  static std::atomic<uint64_t> raised{0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev > 63)
+    return fail(SE_EHIP, "gram_tx: no current device");
+  if (lds > 64 * 1024 && !(raised.load() & (1ull << dev))) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_tx<MT, NT, NP>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+      return fail(SE_EHIP, "gram_tx: %zu bytes of LDS refused", lds);
+    raised.fetch_or(1ull << dev);
+  }
+  hipLaunchKernelGGL((k_gram_tx<MT, NT, NP>), dim3(grid), dim3(64 * L.waves), lds, s, a, L);
+  return check_launch("gram_tx");
+}
+
+template <int MT, int NT>
+static se_status launch_gram_np(const TxGramArgs& a, const TxLayout& L, int grid, size_t lds,
+                                hipStream_t s) {
+  return L.parts == 2 ? launch_gram<MT, NT, 2>(a, L, grid, lds, s)
+                      : launch_gram<MT, NT, 1>(a, L, grid, lds, s);
+}
+
+static int tx_waves(int M, int N, int n_parts, int n_blk);
+
+se_status gram_tx(const se_tables* t, hipStream_t s) {
+  TxGramArgs a;
+  a.phi = t->phi;
+  a.K = t->K;
+  a.tx = t->tx;
+  a.D = t->D;
+  a.first0 = t->parts[0].first;
+  a.first1 = t->n_parts > 1 ? t->parts[1].first : 0;
+  a.G = t->G;
+  a.ldG = t->ldG;
+  const int waves = tx_waves(t->M, t->N, t->n_parts, t->K);
+  if (waves == 0) return fail(SE_EINVAL, "transform of a %dx%d area exceeds LDS", t->M, t->N);
+  const bool stage = (t->N & 3) == 0 && (a.first0 & 3) == 0 && (a.first1 & 3) == 0 &&
+                     (t->ldG & 3) == 0 &&
+                     TxLayout(t->M, t->N, t->n_parts, waves, true).bytes() <= 160 * 1024;
+  const TxLayout L(t->M, t->N, t->n_parts, waves, stage);
+  const size_t lds = L.bytes();
+  const int per_cu = (int)std::min<size_t>(4, (160 * 1024) / lds);
+  const int grid = std::max(1, std::min((t->K + waves - 1) / waves, 256 * per_cu));
+  se_status st = SE_OK;
+  switch (L.MT * 10 + L.NT) {
+#define SE_TX_CASE(mt, nt)                                \
+  case mt * 10 + nt:                                      \
+    st = launch_gram_np<mt, nt>(a, L, grid, lds, s); \
+    break;
+    SE_TX_CASE(1, 1) SE_TX_CASE(1, 2) SE_TX_CASE(1, 3) SE_TX_CASE(1, 4)
+    SE_TX_CASE(2, 1) SE_TX_CASE(2, 2) SE_TX_CASE(2, 3) SE_TX_CASE(2, 4)
+    SE_TX_CASE(3, 1) SE_TX_CASE(3, 2) SE_TX_CASE(3, 3) SE_TX_CASE(3, 4)
+    SE_TX_CASE(4, 1) SE_TX_CASE(4, 2) SE_TX_CASE(4, 3) SE_TX_CASE(4, 4)
+#undef SE_TX_CASE
+    default: return fail(SE_EINVAL, "transform parts need M, N <= 64");
+  }
+  return st;
+}
+
+se_status gram_mirror(const se_tables* t, hipStream_t s) {
+  const int P = t->M * t->N;
+  const int p0 = t->parts[0].first;
+  const int q0 = t->n_parts > 1 ? t->parts[1].first : p0;
+  const int nb = (t->K + 31) / 32;
+  hipLaunchKernelGGL(k_gram_mirror, dim3(nb, nb), dim3(256), 0, s, t->G, t->ldG, t->K, p0, q0, P);
+  return check_launch("gram_mirror");
 }
 
 // Waves per workgroup: the kernel's workgroup bound, fewer when that leaves

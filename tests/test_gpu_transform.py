@@ -60,6 +60,42 @@ def test_project_with_parts_matches_oracle(M, N, parts, n_gauss):
         assert err <= 1e-5 * scale, f"block {i}: {err} vs scale {scale}"
 
 
+@pytest.mark.parametrize("M,N,parts,n_gauss,precision", [
+    (32, 32, ("dct", "wht"), 0, B.SE_FP32),        # every row from transforms
+    (48, 48, ("dct", "gauss"), 300, B.SE_FP32),    # dense block after the part
+    (16, 8, ("gauss", "wht", "dct"), 72, B.SE_FP32),  # dense block first
+    (7, 5, ("dct", "gauss"), 13, B.SE_FP32),       # unaligned dense start: one product
+    (32, 32, ("dct", "wht"), 0, B.SE_BF16X3),
+    (48, 48, ("dct", "gauss"), 300, B.SE_BF16X3),
+])
+def test_gram_with_parts_matches_oracle(M, N, parts, n_gauss, precision):
+    """Algorithm 2 with transform parts: rows over the part columns are
+    transforms of the weighted atoms (Section VI), the dense block a product;
+    the table must equal the oracle's D C D and be exactly symmetric."""
+    say(f"weighted_gram with parts M={M} N={N} parts={parts} precision={precision}")
+    phi = synth.round_to_f32(synth.dictionary(M, N, parts, seed=M * N, n_gauss=n_gauss))
+    tx = synth.dictionary_parts(M, N, parts, n_gauss)
+    K = phi.shape[0]
+    sup = np.ones((M, N), bool)
+    sup[M // 3:M // 3 + 3, N // 4:N // 4 + 2] = False
+    sup[0, :] = False                      # a border row outside the image
+    w_ref = oracle.area_weights(M, N, 0.8, sup)
+    w_d = torch.from_numpy(w_ref.astype(np.float32)).to(dev())
+    t = B.weighted_gram(upload_phi(phi), w_d, M, N, precision, parts=tx)
+    torch.cuda.synchronize()
+    G = t.G.cpu().numpy()[:, :K].astype(np.float64)
+    assert np.all(t.G.cpu().numpy()[:, K:] == 0.0)
+    D = t.D.cpu().numpy().astype(np.float64)
+    C_ref, D_ref = oracle.table_generation(phi, w_ref.astype(np.float32).astype(np.float64))
+    np.testing.assert_allclose(D, D_ref, rtol=2e-6)
+    G_ref = D_ref[:, None] * C_ref * D_ref[None, :]
+    tol = 2e-5 if precision == B.SE_FP32 else 2e-4
+    err = np.abs(G - G_ref).max()
+    print(f"max |G - G_oracle| = {err:.3g}")
+    assert err < tol
+    np.testing.assert_array_equal(G, G.T)
+
+
 def test_parts_equal_dense_projection():
     """With and without the declaration the projections agree to FP32
     rounding (same tables, two routes to R)."""
