@@ -209,7 +209,12 @@ se_status se_area_weights(int32_t M, int32_t N, float rho_hat,
  * accumulated in FP32 on the BF16 matrix cores), mirrored to the upper
  * triangle -- Algorithm 2 computes (|D|^2 + |D|)/2 products and mirrors the
  * rest.  With declared transform parts the call first verifies them and
- * synchronises `stream` once to read the verdict.
+ * synchronises `stream` once to read the verdict; it then writes t->tx,
+ * and when the atoms outside the parts form at most one range starting at
+ * a multiple of 4, forms every row over the part columns as the transform
+ * of the weighted atom, D_k (D o T(w phi_k)) (eq. 21-23 applied to eq. 16,
+ * FP32 matrix cores in both precisions), takes the product above for the
+ * dense atoms only, and mirrors the rest, so G stays exactly symmetric.
  * ws: device scratch of se_weighted_gram_ws_bytes(b, prec) bytes.
  * Errors: SE_EINVAL for a NULL pointer, K < 1, ldG < K or not a multiple
  * of 4, an unknown precision or flag, ws too small. */
@@ -349,6 +354,9 @@ void se_tune_clear(void);
  * C_b[u_b][:] of every still-iterating block are one matrix product of the
  * dictionary with the vectors w_b * phi_{u_b} (FP32 MFMA), as are the
  * per-block diagonals C_b[k][k] (giving D_b) and the initial projections.
+ * Rows of declared transform parts (Section VI) are instead the separable
+ * transforms of w_b * phi_{u_b} on the matrix cores; the declaration is
+ * verified against phi first, which synchronises `stream` once.
  * Selection, coefficients, model update and paste are those of
  * se_extrapolate_batch, so both calls give the same result for the same
  * weights (up to FP32 rounding).
@@ -381,7 +389,7 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w,
 
 /* A server conceals lost blocks of whole frames submitted over time.  The
  * paper's tables depend only on the weighting pattern, so they are computed
- * "in advance" for the patterns that occur and kept (Section III); the
+ * ahead of use for the patterns that occur and kept (Section III); the
  * server builds them on first use and keeps them in a device cache, limited
  * by an HBM budget.  A block whose area lies inside the frame and holds no
  * other loss has the isolated pattern of its (dictionary, loss rectangle)
