@@ -31,8 +31,14 @@ def bases(with64=True):
     return b
 
 
-def to_dev(bs):
-    return [(torch.from_numpy(p.astype(np.float32)).cuda(), M, N) for p, M, N in bs]
+# the transform ranges of the dictionaries above (DCT first, then WHT or
+# Gaussian atoms)
+PARTS = {32: [("dct", 0), ("wht", 1024)], 48: [("dct", 0)], 64: [("dct", 0), ("wht", 4096)]}
+
+
+def to_dev(bs, with_parts=False):
+    return [(torch.from_numpy(p.astype(np.float32)).cuda(), M, N,
+             PARTS[M] if with_parts else ()) for p, M, N in bs]
 
 
 def losses_for(seed, coverage=0.03, with64=True):
@@ -73,10 +79,11 @@ def check_frame(img, out, losses, bs, iters, tol=1e-3, per_basis=2):
             assert ((got == q) | near).all(), f"dictionary {k}, block {b}"
 
 
-def test_serve_single_frame_against_oracle():
-    say("serve: one 192x256 frame, 3 dictionaries, I=40")
+@pytest.mark.parametrize("with_parts", [False, True])
+def test_serve_single_frame_against_oracle(with_parts):
+    say(f"serve: one 192x256 frame, 3 dictionaries, I=40, transform parts {with_parts}")
     bs = bases()
-    srv = B.Server(to_dev(bs), H, W, max_slots=2, max_queue=4, n_streams=2)
+    srv = B.Server(to_dev(bs, with_parts), H, W, max_slots=2, max_queue=4, n_streams=2)
     img = synth.synth_image(H, W, seed=11)
     losses = losses_for(3)
     fr = torch.from_numpy(img.copy()).cuda()
@@ -94,10 +101,11 @@ def test_serve_single_frame_against_oracle():
     srv.close()
 
 
-def test_serve_alone_equals_in_mix():
-    say("serve: the same frame alone and among 5 concurrent frames")
+@pytest.mark.parametrize("with_parts", [False, True])
+def test_serve_alone_equals_in_mix(with_parts):
+    say(f"serve: the same frame alone and among 5 concurrent frames, parts {with_parts}")
     bs = bases()
-    srv = B.Server(to_dev(bs), H, W, max_slots=4, max_queue=16, n_streams=3)
+    srv = B.Server(to_dev(bs, with_parts), H, W, max_slots=4, max_queue=16, n_streams=3)
     imgs = [synth.synth_image(H, W, seed=20 + i) for i in range(6)]
     losses = [losses_for(40 + i) for i in range(6)]
     a = torch.from_numpy(imgs[0].copy()).cuda()
@@ -118,12 +126,13 @@ def test_serve_alone_equals_in_mix():
     srv.close()
 
 
-def test_serve_budget_degrades_to_ondemand():
-    say("serve: HBM budget too small for the 48x48 tables")
+@pytest.mark.parametrize("with_parts", [False, True])
+def test_serve_budget_degrades_to_ondemand(with_parts):
+    say(f"serve: HBM budget too small for the 48x48 tables, parts {with_parts}")
     bs = bases(with64=False)
     losses = losses_for(7, with64=False)
     img = synth.synth_image(H, W, seed=5)
-    srv = B.Server(to_dev(bs), H, W, max_slots=1, max_queue=2, n_streams=1,
+    srv = B.Server(to_dev(bs, with_parts), H, W, max_slots=1, max_queue=2, n_streams=1,
                    hbm_budget_bytes=110 << 20)
     fr = torch.from_numpy(img.copy()).cuda()
     res = srv.wait(srv.submit(fr, losses, 0.5, 40))
