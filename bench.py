@@ -302,7 +302,10 @@ def main():
         roof = {"kernel": "k_greedy (iteration loop)", "bound": "hbm", "achieved": loop_gbs,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": loop_gbs / HBM_PEAK_GBS,
                 "traffic": measured_loop_traffic(args.images),
-                "bytes_per_launch": loop_bytes_per_block * nblk, "avg_ms": loop_avg}
+                "bytes_per_launch": loop_bytes_per_block * nblk, "avg_ms": loop_avg,
+                "note": "requested row bytes; frac > 1 because the rows of the 16 MiB table "
+                        "are served by L2 and the Infinity Cache (traffic = measured HBM "
+                        "bytes); the limiter is the L1-to-register return path"}
     elif not args.no_parts:
         proj_bytes = nblk * (ldR * 4 + P)      # R written, the area's pixels read
         roof = {"kernel": "k_project_tx (initial projections)", "bound": "hbm",
