@@ -96,7 +96,21 @@ static se_status check_tables(const se_tables* t) {
 
 static inline int round8(int v) { return (v + 7) & ~7; }
 
-// Workspace of the projection stage: X as float32, or as split bf16 pairs.
+// Partial products when the FP32 projection splits its contraction (few
+// blocks): sized for rows of the minimum table row length.
+static size_t project_splitk_floats(const se_tables* t, int n_blk) {
+  const int P = t->M * t->N;
+  if (t->n_parts == 0) return gemm_splitk_floats(greedy_row_len(t->K), n_blk, P);
+  if (t->n_parts > 2) return 0;
+  int lo[3], hi[3];
+  const int nr = dense_ranges(t->K, t->M, t->N, t->n_parts, t->parts, lo, hi);
+  size_t f = 0;
+  for (int r = 0; r < nr; ++r) f = std::max(f, gemm_splitk_floats(hi[r] - lo[r], n_blk, P));
+  return f;
+}
+
+// Workspace of the projection stage: X as float32 (and the partial
+// products), or as split bf16 pairs.
 static size_t project_ws(const se_tables* t, int n_blk) {
   Carver cv(nullptr);
   const int P = t->M * t->N;
@@ -105,6 +119,7 @@ static size_t project_ws(const se_tables* t, int n_blk) {
     cv.take<uint16_t>((size_t)n_blk * round8(P));
   } else {
     cv.take<float>((size_t)n_blk * round4(P));
+    cv.take<float>(project_splitk_floats(t, n_blk));
   }
   return cv.off + 256;
 }
@@ -174,12 +189,14 @@ static se_status project_into(const se_tables* t, const uint8_t* images, int H, 
   }
   const int ldX = round4(P);
   float* X = cv.take<float>((size_t)n_blk * ldX);
+  const size_t split_floats = project_splitk_floats(t, n_blk);
+  float* split = cv.take<float>(split_floats);
   launch_gather(images, H, W, dblk, n_blk, t->M, t->N, t->sqrtw, X, ldX, s);
   if ((st = check_launch("gather"))) return st;
   const int tile = tune_lookup(t->K, P, n_blk).proj_tile;
   for (int r = 0; r < nr; ++r)
     if ((st = gemm_project_f32(t->Y + (size_t)lo[r] * P, P, hi[r] - lo[r], X, ldX, n_blk, P,
-                               R + lo[r], ldR, tile, s, pad)))
+                               R + lo[r], ldR, tile, s, pad, split, split_floats)))
       return st;
   return SE_OK;
 }
@@ -475,6 +492,20 @@ static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, in
 // ---------------------------------------------------------------------------
 static inline int round1024(int v) { return (v + 1023) & ~1023; }
 
+// workspace for the split products of the on-demand path: the per-block
+// diagonal and projections (every atom, padded rows) and the per-iteration
+// rows (the dense ranges when transform parts are declared)
+static size_t ondemand_splitk_floats(const se_basis* b, int n_blk) {
+  const int P = b->M * b->N, ld = round1024(b->K);
+  size_t f = gemm_splitk_floats(ld, n_blk, P);
+  if (b->n_parts > 0 && b->n_parts <= 2) {
+    int lo[3], hi[3];
+    const int nr = dense_ranges(b->K, b->M, b->N, b->n_parts, b->parts, lo, hi);
+    for (int r = 0; r < nr; ++r) f = std::max(f, gemm_splitk_floats(hi[r] - lo[r], n_blk, P));
+  }
+  return f;
+}
+
 size_t se_extrapolate_ondemand_ws_bytes(const se_basis* b, int32_t n_blk, int32_t max_loss) {
   if (!b || b->K < 1 || b->M < 1 || b->N < 1 || n_blk < 0 || max_loss < 0) return 0;
   const size_t K = (size_t)b->K, P = (size_t)b->M * b->N, n = (size_t)n_blk;
@@ -492,6 +523,7 @@ size_t se_extrapolate_ondemand_ws_bytes(const se_basis* b, int32_t n_blk, int32_
   cv.take<float>(2 * n * (size_t)(max_loss > 0 ? max_loss : 1));
   cv.take<int32_t>(1);
   cv.take<float>(tx_const_bytes(b->M, b->N, b->n_parts) / 4);
+  cv.take<float>(ondemand_splitk_floats(b, n_blk));
   return cv.off + 256;
 }
 
@@ -557,6 +589,8 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* im
   pl.gc = pl.g + (size_t)n * max_loss;
   int32_t* flag = cv.take<int32_t>(1);
   float* tx = cv.take<float>(tx_const_bytes(b->M, b->N, b->n_parts) / 4);
+  pl.splitk_floats = ondemand_splitk_floats(b, n);
+  pl.splitk = cv.take<float>(pl.splitk_floats);
   // declared transform parts: verified (one synchronisation of the stream),
   // then their table rows are formed as transforms
   if ((st = verify_parts(b, flag, s))) return st;

@@ -20,6 +20,8 @@
 // MFMA 16x16x4 f32 operand/result mapping (lane l, 0..63):
 //   A[m][k]: m = l % 16, k = l / 16        B[k][n]: n = l % 16, k = l / 16
 //   D[m][n] (4 floats e = 0..3): m = 4 (l / 16) + e, n = l % 16
+#include <algorithm>
+
 #include "se_internal.h"
 
 namespace sefase {
@@ -94,8 +96,17 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f32(const float* __restrict__ A
                                                      const float* __restrict__ B, int ldb,
                                                      float* __restrict__ C, int ldc, int Ma, int Nb,
                                                      int Mst, int Nst, int P, int tiles_n,
-                                                     int ntiles) {
+                                                     int ntiles, int kchunk, size_t cstride) {
   constexpr int SI = BM / 32, SJ = BN / 32;   // 16x16 MFMA tiles per wave
+  // split contraction: slice z covers p in [z kchunk, (z + 1) kchunk) and
+  // writes its partial S to C + z cstride
+  {
+    const int kz = blockIdx.y;
+    A += (size_t)kz * kchunk;
+    B += (size_t)kz * kchunk;
+    C += (size_t)kz * cstride;
+    P = min(kchunk, P - kz * kchunk);
+  }
   __shared__ __attribute__((aligned(16))) float As[2][BM][kBK + kPad];
   __shared__ __attribute__((aligned(16))) float Bs[2][BN][kBK + kPad];
 
@@ -251,9 +262,68 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f32(const float* __restrict__ A
     }
 }
 
+// C[c][r] = sum_z W[z][c][r] for c < rows, r < cols (the partial products of
+// a split contraction, summed in a fixed order)
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_splitk_sum(const float* __restrict__ W, int ldw,
+                                                    size_t wstride, int S,
+                                                    float* __restrict__ C, int ldc, int rows,
+                                                    int cols) {
+  const int c = blockIdx.y;
+  const int r = 4 * (blockIdx.x * blockDim.x + threadIdx.x);
+  if (c >= rows || r >= cols) return;
+  const float* w = W + (size_t)c * ldw + r;
+  float* dst = C + (size_t)c * ldc + r;
+  if (VEC && r + 3 < cols) {
+    float4 v = *reinterpret_cast<const float4*>(w);
+    for (int z = 1; z < S; ++z) {
+      const float4 u = *reinterpret_cast<const float4*>(w + (size_t)z * wstride);
+      v.x += u.x;
+      v.y += u.y;
+      v.z += u.z;
+      v.w += u.w;
+    }
+    *reinterpret_cast<float4*>(dst) = v;
+  } else {
+    for (int e = 0; e < 4 && r + e < cols; ++e) {
+      float v = w[e];
+      for (int z = 1; z < S; ++z) v += w[(size_t)z * wstride + e];
+      dst[e] = v;
+    }
+  }
+}
+
+// Slices of a split contraction for a transposed product of 64 x 64 tiles:
+// enough workgroups to give every compute unit several, each slice at least
+// 8 stages of kBK.  Returns 1 (no split) when the tiles alone fill the chip.
+static int splitk_slices(int Mst, int Nst, int P) {
+  const long long tiles = (long long)((Mst + 63) / 64) * ((Nst + 63) / 64);
+  const int nk = (P + kBK - 1) / kBK;
+  if (tiles <= 0 || tiles >= 512) return 1;
+  int S = (int)((768 + tiles - 1) / tiles);
+  S = std::min(S, std::min(8, nk / 8));
+  if (S < 2) return 1;
+  const int per = (nk + S - 1) / S;    // stages per slice
+  return (nk + per - 1) / per;
+}
+
+static inline int ldw_of(int Mst) { return (Mst + 3) & ~3; }
+
+size_t gemm_splitk_floats(int Mst, int Nst_max, int P) {
+  // the largest S * Nst * ldw over every block count up to Nst_max
+  size_t best = 0;
+  for (int tn = 1; 64 * (tn - 1) < Nst_max; ++tn) {
+    const int Nst = std::min(64 * tn, Nst_max);
+    const int S = splitk_slices(Mst, Nst, P);
+    if (S > 1) best = std::max(best, (size_t)S * Nst * ldw_of(Mst));
+  }
+  return best;
+}
+
 template <int BM, int BN, int MODE>
 static se_status launch_f32(const float* A, int lda, const float* B, int ldb, float* C, int ldc,
-                            int Ma, int Nb, int Mst, int Nst, int P, bool vec, hipStream_t s) {
+                            int Ma, int Nb, int Mst, int Nst, int P, bool vec, hipStream_t s,
+                            int S = 1, int kchunk = 0, size_t cstride = 0) {
   int ntiles, tiles_n;
   if (MODE == kStoreSymmetric) {
     const int nb = (Ma + BM - 1) / BM;
@@ -264,18 +334,20 @@ static se_status launch_f32(const float* A, int lda, const float* B, int ldb, fl
     ntiles = ((Mst + BM - 1) / BM) * tiles_n;
   }
   if (ntiles <= 0 || P <= 0) return SE_OK;
+  if (S <= 1) kchunk = P;
   if (vec)
-    hipLaunchKernelGGL((k_gemm_nt_f32<BM, BN, true, MODE>), dim3(ntiles), dim3(256), 0, s, A, lda,
-                       B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, tiles_n, ntiles);
+    hipLaunchKernelGGL((k_gemm_nt_f32<BM, BN, true, MODE>), dim3(ntiles, S), dim3(256), 0, s, A,
+                       lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, tiles_n, ntiles, kchunk, cstride);
   else
-    hipLaunchKernelGGL((k_gemm_nt_f32<BM, BN, false, MODE>), dim3(ntiles), dim3(256), 0, s, A,
-                       lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, tiles_n, ntiles);
+    hipLaunchKernelGGL((k_gemm_nt_f32<BM, BN, false, MODE>), dim3(ntiles, S), dim3(256), 0, s, A,
+                       lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, tiles_n, ntiles, kchunk, cstride);
   return check_launch("gemm_nt_f32");
 }
 
 template <int MODE>
 static se_status dispatch_f32(const float* A, int lda, const float* B, int ldb, float* C, int ldc,
-                              int Ma, int Nb, int Mst, int Nst, int P, int tile, hipStream_t s) {
+                              int Ma, int Nb, int Mst, int Nst, int P, int tile, hipStream_t s,
+                              float* ws = nullptr, size_t ws_floats = 0) {
   const bool vec = (lda % 4 == 0) && (ldb % 4 == 0) && (ldc % 4 == 0) &&
                    ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B) |
                      reinterpret_cast<uintptr_t>(C)) % 16 == 0);
@@ -292,6 +364,25 @@ static se_status dispatch_f32(const float* A, int lda, const float* B, int ldb, 
   }
   if (tile == 128)
     return launch_f32<128, 128, MODE>(A, lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, vec, s);
+  if (MODE == kStoreTransposed && ws && vec && Mst > 0 && Nst > 0) {
+    // few tiles: split the contraction over slices that write partial
+    // products to the workspace, then sum them in slice order
+    const int S = splitk_slices(Mst, Nst, P);
+    const int ldw = ldw_of(Mst);
+    const size_t wstride = (size_t)Nst * ldw;
+    if (S > 1 && (size_t)S * wstride <= ws_floats &&
+        reinterpret_cast<uintptr_t>(ws) % 16 == 0) {
+      const int nk = (P + kBK - 1) / kBK;
+      const int kchunk = ((nk + S - 1) / S) * kBK;
+      se_status st = launch_f32<64, 64, MODE>(A, lda, B, ldb, ws, ldw, Ma, Nb, Mst, Nst, P, true,
+                                              s, S, kchunk, wstride);
+      if (st) return st;
+      const dim3 grid((unsigned)((Mst + 1023) / 1024), (unsigned)Nst);
+      hipLaunchKernelGGL(k_splitk_sum<true>, grid, dim3(256), 0, s, ws, ldw, wstride, S, C, ldc,
+                         Nst, Mst);
+      return check_launch("splitk_sum");
+    }
+  }
   return launch_f32<64, 64, MODE>(A, lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, vec, s);
 }
 
@@ -300,10 +391,11 @@ se_status gemm_syrk_f32(const float* Y, int ldy, int K, int P, float* G, int ldg
 }
 
 se_status gemm_project_f32(const float* Y, int ldy, int K, const float* X, int ldx, int n_blk,
-                           int P, float* R, int ldr, int tile, hipStream_t s, bool pad) {
+                           int P, float* R, int ldr, int tile, hipStream_t s, bool pad, float* ws,
+                           size_t ws_floats) {
   // S = Y X^T (atoms x blocks), stored transposed: R[b][k]; atoms K .. ldr-1 as 0
   return dispatch_f32<kStoreTransposed>(Y, ldy, X, ldx, R, ldr, K, n_blk, pad ? ldr : K, n_blk, P,
-                                        tile, s);
+                                        tile, s, ws, ws_floats);
 }
 
 }  // namespace sefase

@@ -205,8 +205,12 @@ se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s) {
   hipLaunchKernelGGL(k_od_gather_w, dim3((P + 255) / 256, n), dim3(256), 0, s, pl.w, pl.orig, n,
                      P, pl.V, pl.ldV);
   if ((st = check_launch("od_gather_w"))) return st;
-  if ((st = gemm_project_f32(pl.phi2, P, K, pl.V, pl.ldV, n, P, pl.D, pl.ld, 0, s))) return st;
-  if ((st = gemm_project_f32(pl.phi, P, K, pl.X, pl.ldV, n, P, pl.R, pl.ld, 0, s))) return st;
+  if ((st = gemm_project_f32(pl.phi2, P, K, pl.V, pl.ldV, n, P, pl.D, pl.ld, 0, s, true,
+                             pl.splitk, pl.splitk_floats)))
+    return st;
+  if ((st = gemm_project_f32(pl.phi, P, K, pl.X, pl.ldV, n, P, pl.R, pl.ld, 0, s, true, pl.splitk,
+                             pl.splitk_floats)))
+    return st;
   hipLaunchKernelGGL(k_od_init, dim3((unsigned)(((size_t)n * pl.ld + 255) / 256)), dim3(256), 0,
                      s, pl.D, pl.R, n, pl.ld);
   if ((st = check_launch("od_init"))) return st;
@@ -256,7 +260,8 @@ se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s) {
     if (tx && (st = rows_tx(bs, pl.tx, pl.V, pl.ldV, nxt, pl.rows, pl.ld, s))) return st;
     for (int r = 0; r < nr; ++r)
       if ((st = gemm_project_f32(pl.phi + (size_t)lo[r] * P, P, hi[r] - lo[r], pl.V, pl.ldV, nxt,
-                                 P, pl.rows + lo[r], pl.ld, 0, s, !tx)))
+                                 P, pl.rows + lo[r], pl.ld, 0, s, !tx, pl.splitk,
+                                 pl.splitk_floats)))
         return st;
   }
   hipLaunchKernelGGL(k_od_finish, dim3(n), dim3(256), 0, s, pl.blk, pl.orig, pl.g, pl.ldg,

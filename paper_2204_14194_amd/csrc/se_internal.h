@@ -75,7 +75,11 @@ se_status gemm_syrk_f32(const float* Y, int ldy, int K, int P, float* G, int ldg
 // pad (else those columns are left alone).  tile: 0 = automatic, 64 or 128.
 se_status gemm_project_f32(const float* Y, int ldy, int K, const float* X, int ldx,
                            int n_blk, int P, float* R, int ldr, int tile, hipStream_t s,
-                           bool pad = true);
+                           bool pad = true, float* ws = nullptr, size_t ws_floats = 0);
+// workspace (floats) that lets gemm_project_f32 split the contraction of a
+// product with Mst stored atoms, up to Nst_max blocks and P pixels; 0 when it
+// never splits.  Without it (or with less) the product runs unsplit.
+size_t gemm_splitk_floats(int Mst, int Nst_max, int P);
 // gemm_bf16x3.hip -- the same two products from split-bf16 operands
 se_status gemm_syrk_bf16x3(const uint16_t* Yhi, const uint16_t* Ylo, int ldy, int K, int P,
                            float* G, int ldg, hipStream_t s);
@@ -164,6 +168,8 @@ struct OnDemandPlan {
   int ld;               // multiple of 1024
   const se_basis* basis;  // transform parts (rows formed as transforms)
   const float* tx;        // their A and B operands (when n_parts > 0)
+  float* splitk;        // partial products of split contractions
+  size_t splitk_floats;
   float* st;            // n_blk x 2
   float* g;             // n_blk x ldg, followed by gc (n_blk x ldg)
   float* gc;

@@ -306,6 +306,8 @@ static se_status launch_batch(Server* s, std::vector<Req*>& reqs, Batch& bt) {
     t.N = b.N;
     t.K = b.K;
     t.precision = SE_FP32;
+    t.n_parts = b.n_parts;
+    for (int q = 0; q < b.n_parts && q < 2; ++q) t.parts[q] = b.parts[q];
     call_max = std::max(call_max, se_extrapolate_batch_ws_bytes(&t, (int)e.second.size()));
     se_basis bb = b;
     call_max = std::max(call_max, se_weighted_gram_ws_bytes(&bb, SE_FP32) + 4096 +
