@@ -19,9 +19,9 @@
 // and are never candidates.
 //
 // Selection: the wave's largest |R~| is found from per-lane maxima with a
-// DPP reduction; a lane that alone holds it reports its lowest-index atom
-// with that value (ballots over its groups of four atoms, then over the four
-// atoms of the first matching group).  When several lanes hold the maximum
+// DPP reduction; when one lane alone holds it, that lane's group maxima and
+// then the four values of its first matching group are read into scalar
+// registers and scanned for the lowest index.  When several lanes hold the maximum
 // (exact ties, e.g. parallel atoms), every lane scans its atoms in index
 // order and the wave reduces 64-bit keys
 //     |R~| bits << 32  |  (0xFFFF - k) << 16  |  sign << 15
@@ -79,12 +79,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy(GreedyArgs a) {
   const float gamma = a.gamma;
 
   for (int it = 0; it < a.iters; ++it) {
-    // ---- this wave's largest |R~| and its lowest index -------------------
-    // Group maxima (4 atoms each) and the lane maximum, then the wave maximum
-    // by DPP.  When exactly one lane holds the maximum, a ballot per group
-    // and per atom of the winning group locates the lowest index in that
-    // lane (the lane's atoms increase with the group and position).  Ties
-    // across lanes take the exact 64-bit key scan.
+    // ---- this wave's largest |R~| and its lowest index ---------------------
+    // Group maxima (4 atoms each) and the lane maximum, then the wave
+    // maximum by DPP.
     float gm[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j)
@@ -94,38 +91,41 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy(GreedyArgs a) {
     for (int j = 1; j < NJ; ++j) lm = fmaxf(lm, gm[j]);
     const float M = wave_max_f32(lm);
     const uint64_t holders = __builtin_amdgcn_ballot_w64(lm == M);
-    uint64_t key;
-    if (M == 0.0f) {
-      key = 0;                                   // every score is zero
-    } else if (__builtin_popcountll(holders) == 1) {
+    int u = 0;
+    float rv = 0.0f;
+    uint64_t key = 0;                          // every score zero: atom 0, value 0
+    bool direct = WAVES == 1;
+    if (M != 0.0f && __builtin_popcountll(holders) == 1) {
+      // lane L alone holds the maximum: its group maxima, then the four
+      // values of the first matching group, are read into scalar
+      // registers and scanned there (lowest index first)
       const int L = __builtin_ctzll(holders);
-      int gsel = -1;
+      const uint32_t Mb = __float_as_uint(M);
+      int gsel = NJ - 1;
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const uint64_t bj = __builtin_amdgcn_ballot_w64(gm[j] == M);
-        if (gsel < 0 && ((bj >> L) & 1ull)) gsel = j;
-      }
-      int code = 0;
-      uint32_t vbits = 0;
+      for (int j = NJ - 2; j >= 0; --j)
+        gsel = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(gm[j]), L) == Mb ? j : gsel;
+      uint32_t r[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        if (j == gsel) {                         // uniform branch
-          int csel = -1;
+      for (int j = 0; j < NJ; ++j)
+        if (j == gsel) {                       // uniform branch
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const uint64_t be = __builtin_amdgcn_ballot_w64(fabsf(R[j][e]) == M);
-            if (csel < 0 && ((be >> L) & 1ull)) csel = e;
-          }
-          const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(R[j][0]), L);
-          const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(R[j][1]), L);
-          const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(R[j][2]), L);
-          const uint32_t r3 = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(R[j][3]), L);
-          vbits = csel == 0 ? r0 : csel == 1 ? r1 : csel == 2 ? r2 : r3;
-          code = 4 * j + csel;
+          for (int e = 0; e < 4; ++e)
+            r[e] = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(R[j][e]), L);
         }
+      int csel = 3;
+#pragma unroll
+      for (int e = 2; e >= 0; --e) csel = (r[e] & 0x7FFFFFFFu) == Mb ? e : csel;
+      const uint32_t vbits = csel == 0 ? r[0] : csel == 1 ? r[1] : csel == 2 ? r[2] : r[3];
+      u = 4 * (gsel * T + wave * 64 + L) + csel;
+      rv = __uint_as_float(vbits);
+      if (u >= K) {                            // only with nonzero padding of R
+        u = 0;
+        rv = 0.0f;
       }
-      key = make_key(__uint_as_float(vbits), 4 * ((code >> 2) * T + wave * 64 + L) + (code & 3));
-    } else {
+      if (WAVES > 1) key = make_key(rv, u);
+    } else if (M != 0.0f) {
+      // exact ties across lanes: every lane's first maximum as a key
       float bv = 0.0f;
       int c = 0;
 #pragma unroll
@@ -138,6 +138,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy(GreedyArgs a) {
           }
       const uint64_t mine = make_key(bv, 4 * ((c >> 2) * T + t) + (c & 3));
       key = wave_max_key((uint32_t)(mine >> 32), (uint32_t)mine);
+      direct = false;
     }
     if (WAVES > 1) {
       if (lane == 0) s_key[par][wave] = key;
@@ -150,42 +151,53 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy(GreedyArgs a) {
       }
       par ^= 1;
     }
-    // ---- decode the winner (wave-uniform, kept in scalar registers) ------
-    int u;
-    float rv;
-    decode_key(key, K, u, rv);
+    // ---- the winner (wave-uniform, kept in scalar registers) ----------------
+    if (!direct) decode_key(key, K, u, rv);
     u = __builtin_amdgcn_readfirstlane(u);
     rv = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rv)));
     const float tc = gamma * rv;              // coefficient of the unit-norm atom
 
-    // ---- stream row u of the table and the atom over the loss -------------
-    // Issued before the scalar load of D_u, so the only memory latency on the
-    // iteration's critical path is that of the row.
+    // ---- stream row u of the table and the atom over the loss ---------------
+    // (the first pixel of every lane always exists; more pixels per lane
+    // only for losses larger than the workgroup, one uniform branch)
     const float* prow = a.phi + (size_t)u * P;
     float pv[kQPL];
+    pv[0] = prow[poff[0]];
+    if (nq > 1) {
 #pragma unroll
-    for (int q = 0; q < kQPL; ++q)
-      if (q < nq) pv[q] = prow[poff[q]];
+      for (int q = 1; q < kQPL; ++q)
+        if (q < nq) pv[q] = prow[poff[q]];
+    }
     const float* grow = a.G + (size_t)u * a.ldG;
     float4 row[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) row[j] = *reinterpret_cast<const float4*>(grow + 4 * (j * T + t));
-    const float c = tc * a.D[u];              // eq. 19
+    // D is read-only for the whole launch: a scalar load (constant address
+    // space) that does not wait behind the row's vector loads
+    const float Du = ((const __attribute__((address_space(4))) float*)a.D)[u];
+    const float c = tc * Du;                  // eq. 19
     if (t == 0) {
       if (a.sel) a.sel[(size_t)b * a.iters + it] = u;
       if (a.coef) a.coef[(size_t)b * a.iters + it] = c;
     }
+    {                                         // eq. 9, compensated
+      const float y = fmaf(c, pv[0], -gc[0]);
+      const float s = g[0] + y;
+      gc[0] = (s - g[0]) - y;
+      g[0] = s;
+    }
+    if (nq > 1) {
 #pragma unroll
-    for (int q = 0; q < kQPL; ++q)
-      if (q < nq) {                                       // eq. 9, compensated
-        const float y = fmaf(c, pv[q], -gc[q]);
-        const float s = g[q] + y;
-        gc[q] = (s - g[q]) - y;
-        g[q] = s;
-        asm volatile("" ::: "memory");   // keep the uniform branch (no if-conversion)
-      }
+      for (int q = 1; q < kQPL; ++q)
+        if (q < nq) {
+          const float y = fmaf(c, pv[q], -gc[q]);
+          const float s = g[q] + y;
+          gc[q] = (s - g[q]) - y;
+          g[q] = s;
+        }
+    }
 
-    // ---- eq. 20 ---------------------------------------------------------
+    // ---- eq. 20 -------------------------------------------------------------
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       R[j][0] = fmaf(-tc, row[j].x, R[j][0]);
