@@ -98,14 +98,14 @@ def cpu_baseline(n_blocks: int):
 
 
 # ---------------------------------------------------------------------------
-def measured_loop_traffic(images: int):
-    """HBM bytes per launch of the loop kernel from the committed rocprofv3
-    counter summary, or None when the kernel source changed since the
+def measured_traffic(images: int, profile: str, sources):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 counter
+    summary, or None when one of the kernel's source files changed since the
     counters were taken (or the workload differs from the one profiled)."""
     import hashlib
     if images != 256:
         return None
-    prof = os.path.join(ROOT, "profiles", "k_greedy_area32_k2048_traffic.txt")
+    prof = os.path.join(ROOT, "profiles", profile)
     csrc = os.path.join(ROOT, "paper_2204_14194_amd", "csrc")
     try:
         kv = {}
@@ -115,7 +115,7 @@ def measured_loop_traffic(images: int):
                     k, v = line.strip().split("=", 1)
                     kv[k] = v
         src = b""
-        for f in ("greedy.hip", "argmax.h"):
+        for f in sources:
             with open(os.path.join(csrc, f), "rb") as fh:
                 src += fh.read()
     except OSError:
@@ -123,6 +123,10 @@ def measured_loop_traffic(images: int):
     if hashlib.sha256(src).hexdigest() != kv.get("kernel_source_sha256"):
         return None
     return int(float(kv["traffic_bytes_per_launch"]))
+
+
+LOOP_SOURCES = ("greedy.hip", "greedy_device.h", "argmax.h")
+FUSED_SOURCES = ("fused.hip", "greedy_device.h", "tx_device.h", "argmax.h")
 
 
 def percentile(xs, q):
@@ -149,6 +153,9 @@ def main():
                          "benchmark batch before timing)")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the timing of the step captured as a HIP graph")
+    ap.add_argument("--two-launch", action="store_true",
+                    help="time the projection and the loop as two launches even when one "
+                         "launch can do both")
     ap.add_argument("--no-parts", action="store_true",
                     help="do not declare the dictionary's transform parts (projections by "
                          "GEMM against every atom)")
@@ -217,30 +224,57 @@ def main():
     if not args.no_autotune:
         tuned = B.autotune_batch(t, images_d, dblk, R, ws, GAMMA, ITERS, reps=3)
 
-    def step(ev=None):
+    # the chosen form: one launch per step when every atom lies in a declared
+    # transform part (projections inside the loop's workgroups), else the
+    # projection launch and the loop launch
+    fused = not args.no_parts and not args.two_launch and \
+        B.extrapolate_device_ws_bytes(t, nblk) == 0
+
+    def two_launch(ev=None, st=None):
         if ev is not None:
             ev[0].record(stream)
-        B.project(t, images_d, dblk, R, ws)
+        B.project(t, images_d, dblk, R, ws, stream=st)
         if ev is not None:
             ev[1].record(stream)
-        B.iterate(t, R, images_d, dblk, GAMMA, ITERS)
+        B.iterate(t, R, images_d, dblk, GAMMA, ITERS, stream=st)
         if ev is not None:
             ev[2].record(stream)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(evs[i])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / max(args.steps, 1)
+    def one_launch(ev=None, st=None):
+        if ev is not None:
+            ev[0].record(stream)
+            ev[1].record(stream)
+        B.extrapolate_device(t, images_d, dblk, GAMMA, ITERS, stream=st)
+        if ev is not None:
+            ev[2].record(stream)
+
+    step = one_launch if fused else two_launch
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        t0 = time.perf_counter()
+        for i in range(steps):
+            fn(evs[i])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        return (t1 - t0) * 1e3 / max(steps, 1), evs
+
+    ms_per_step, evs = timed(step, args.steps)
     value = nblk / (ms_per_step * 1e-3)
     proj_ms = [e[0].elapsed_time(e[1]) for e in evs]
     loop_ms = [e[1].elapsed_time(e[2]) for e in evs]
     step_ms = [e[0].elapsed_time(e[2]) for e in evs]
+    # the two-launch form of the same step, for comparison
+    split = None
+    if fused:
+        s_ms, s_evs = timed(two_launch, args.steps)
+        split = {"ms_per_step": s_ms, "blocks_per_s": nblk / (s_ms * 1e-3),
+                 "project_ms": float(np.mean([e[0].elapsed_time(e[1]) for e in s_evs])),
+                 "loop_ms": float(np.mean([e[1].elapsed_time(e[2]) for e in s_evs])),
+                 "what": "se_project + se_iterate (projections written to R, then the loop)"}
 
     # the same step captured once into a HIP graph and replayed
     graph_info = None
@@ -249,13 +283,11 @@ def main():
         side = torch.cuda.Stream()
         side.wait_stream(stream)
         with torch.cuda.stream(side):
-            B.project(t, images_d, dblk, R, ws, stream=side)
-            B.iterate(t, R, images_d, dblk, GAMMA, ITERS, stream=side)
+            step(st=side)
         stream.wait_stream(side)
         torch.cuda.synchronize()
         with torch.cuda.graph(graph, stream=side):
-            B.project(t, images_d, dblk, R, ws, stream=side)
-            B.iterate(t, R, images_d, dblk, GAMMA, ITERS, stream=side)
+            step(st=side)
         for _ in range(args.warmup):
             graph.replay()
         torch.cuda.synchronize()
@@ -265,7 +297,7 @@ def main():
         torch.cuda.synchronize()
         g_ms = (time.perf_counter() - gt0) * 1e3 / max(args.steps, 1)
         graph_info = {"ms_per_step": g_ms, "blocks_per_s": nblk / (g_ms * 1e-3),
-                      "what": "project + loop captured once as a HIP graph, replayed per step"}
+                      "what": "the step captured once as a HIP graph, replayed per step"}
 
     # plain form: one block at a time, 3 launches per block
     one = blocks[:16]
@@ -296,27 +328,43 @@ def main():
                             else 2.0 * len(parts) * P * (M + N))
     loop_avg = float(np.mean(loop_ms))
     proj_avg = float(np.mean(proj_ms))
-    loop_gbs = loop_bytes_per_block * nblk / (loop_avg * 1e-3) / 1e9
-    proj_tfs = proj_flops_per_block * nblk / (proj_avg * 1e-3) / 1e12
-    if loop_avg >= proj_avg:
-        roof = {"kernel": "k_greedy (iteration loop)", "bound": "hbm", "achieved": loop_gbs,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": loop_gbs / HBM_PEAK_GBS,
-                "traffic": measured_loop_traffic(args.images),
-                "bytes_per_launch": loop_bytes_per_block * nblk, "avg_ms": loop_avg,
-                "note": "requested row bytes; frac > 1 because the rows of the 16 MiB table "
-                        "are served by L2 and the Infinity Cache (traffic = measured HBM "
-                        "bytes); the limiter is the L1-to-register return path"}
-    elif not args.no_parts:
-        proj_bytes = nblk * (ldR * 4 + P)      # R written, the area's pixels read
-        roof = {"kernel": "k_project_tx (initial projections)", "bound": "hbm",
-                "achieved": proj_bytes / (proj_avg * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": proj_bytes / (proj_avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                "traffic": None, "bytes_per_launch": proj_bytes, "avg_ms": proj_avg}
+    note = ("requested row bytes; frac > 1 because the rows of the 16 MiB table are served by "
+            "L2 and the Infinity Cache (traffic = measured HBM bytes); the limiter is the "
+            "compute units' vector memory pipeline (address and data units busy 83-87%)")
+    if fused:
+        # rows of G and the atom over the loss per iteration, the area's pixels once
+        fused_bytes_per_block = ITERS * (K_ATOMS + loss_px) * 4 + P
+        loop_gbs = fused_bytes_per_block * nblk / (loop_avg * 1e-3) / 1e9
+        proj_tfs = None
+        roof = {"kernel": "k_conceal_tx (transform projections + iteration loop)",
+                "bound": "hbm", "achieved": loop_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": loop_gbs / HBM_PEAK_GBS,
+                "traffic": measured_traffic(args.images, "k_conceal_tx_area32_k2048_traffic.txt",
+                                            FUSED_SOURCES),
+                "bytes_per_launch": fused_bytes_per_block * nblk, "avg_ms": loop_avg,
+                "note": note}
     else:
-        roof = {"kernel": "k_gemm_nt_f32 (initial projections)", "bound": "mfma",
-                "achieved": proj_tfs, "peak": FP32_MFMA_PEAK_TFS, "unit": "TFLOP/s",
-                "frac": proj_tfs / FP32_MFMA_PEAK_TFS, "traffic": None,
-                "flops_per_launch": proj_flops_per_block * nblk, "avg_ms": proj_avg}
+        loop_gbs = loop_bytes_per_block * nblk / (loop_avg * 1e-3) / 1e9
+        proj_tfs = proj_flops_per_block * nblk / (proj_avg * 1e-3) / 1e12
+        if loop_avg >= proj_avg:
+            roof = {"kernel": "k_greedy (iteration loop)", "bound": "hbm", "achieved": loop_gbs,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": loop_gbs / HBM_PEAK_GBS,
+                    "traffic": measured_traffic(args.images, "k_greedy_area32_k2048_traffic.txt",
+                                                LOOP_SOURCES),
+                    "bytes_per_launch": loop_bytes_per_block * nblk, "avg_ms": loop_avg,
+                    "note": note}
+        elif not args.no_parts:
+            proj_bytes = nblk * (ldR * 4 + P)      # R written, the area's pixels read
+            roof = {"kernel": "k_project_tx (initial projections)", "bound": "hbm",
+                    "achieved": proj_bytes / (proj_avg * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s",
+                    "frac": proj_bytes / (proj_avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "traffic": None, "bytes_per_launch": proj_bytes, "avg_ms": proj_avg}
+        else:
+            roof = {"kernel": "k_gemm_nt_f32 (initial projections)", "bound": "mfma",
+                    "achieved": proj_tfs, "peak": FP32_MFMA_PEAK_TFS, "unit": "TFLOP/s",
+                    "frac": proj_tfs / FP32_MFMA_PEAK_TFS, "traffic": None,
+                    "flops_per_launch": proj_flops_per_block * nblk, "avg_ms": proj_avg}
 
     out = {
         "metric": METRIC,
@@ -337,7 +385,9 @@ def main():
                         f"128x128 images x 16 blocks = {nblk} blocks per step; tables cached",
             "blocks_per_step": nblk, "K": K_ATOMS, "iters": ITERS, "area": [M, N],
             "loss": [8, 8],
-            "form": ("batched (project GEMM + one workgroup per block)" if args.no_parts else
+            "form": ("batched, one launch per step: each block's workgroup computes its "
+                     "projections as separable transforms, then runs the loop" if fused else
+                     "batched (project GEMM + one workgroup per block)" if args.no_parts else
                      "batched (separable transforms + one workgroup per block)"),
         },
         "latency_ms": {"p50": percentile(step_ms, 50), "p99": percentile(step_ms, 99),
@@ -350,11 +400,15 @@ def main():
         "graph": graph_info,
         "gram_ms": gram_ms,
         "autotune": tuned,
-        "kernels": {"project_ms": proj_avg, "project_tflops": proj_tfs,
-                    "loop_ms": loop_avg, "loop_gbs": loop_gbs,
-                    "loop_bytes_per_block": loop_bytes_per_block,
-                    "project_flops_per_block": proj_flops_per_block,
-                    "project_form": "gemm" if args.no_parts else "transform"},
+        "kernels": ({"fused_ms": loop_avg, "fused_gbs": loop_gbs,
+                     "fused_bytes_per_block": fused_bytes_per_block,
+                     "project_flops_per_block": proj_flops_per_block} if fused else
+                    {"project_ms": proj_avg, "project_tflops": proj_tfs,
+                     "loop_ms": loop_avg, "loop_gbs": loop_gbs,
+                     "loop_bytes_per_block": loop_bytes_per_block,
+                     "project_flops_per_block": proj_flops_per_block,
+                     "project_form": "gemm" if args.no_parts else "transform"}),
+        "two_launch": split,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

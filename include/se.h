@@ -297,6 +297,26 @@ se_status se_iterate(const se_tables* t, const float* R, int32_t ldR,
                      int32_t* sel, float* coef, float* g_loss,
                      int32_t g_loss_ld, void* stream);
 
+/* se_project followed by se_iterate, for descriptors already on the device
+ * (se_blocks_upload), with the same results bit for bit.  When every atom of
+ * t lies in its declared transform parts (Section VI) -- two parts covering
+ * the dictionary of a 32 x 32 or 64 x 64 area -- each block's workgroup
+ * computes its own initial projections as transforms on the matrix cores
+ * and keeps them in LDS for the loop (eq. 12 via eq. 22, then eq. 18-20):
+ * one launch, no R in device memory, and se_extrapolate_device_ws_bytes is
+ * 0.  Otherwise R and the projection workspace come from ws
+ * (se_extrapolate_device_ws_bytes(t, n_blk) bytes).  se_extrapolate_batch
+ * takes the same single-launch route for such tables.
+ * Arguments and errors as for se_iterate (plus SE_ENOMEM when ws is needed
+ * and too small). */
+size_t se_extrapolate_device_ws_bytes(const se_tables* t, int32_t n_blk);
+se_status se_extrapolate_device(const se_tables* t, uint8_t* images,
+                                int32_t n_img, int32_t H, int32_t W,
+                                const se_block* dev_blocks, int32_t n_blk,
+                                se_params prm, int32_t* sel, float* coef,
+                                float* g_loss, int32_t g_loss_ld, void* ws,
+                                size_t ws_bytes, void* stream);
+
 /* Same contract and results as se_extrapolate_batch, executed one block at
  * a time: per block one gather launch, one matrix-vector launch for R^(0)
  * and one single-workgroup launch of the iteration loop.  This is the

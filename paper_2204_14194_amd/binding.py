@@ -27,7 +27,8 @@ EXPORTED = (
     "se_last_error", "se_version", "se_area_weights_ws_bytes", "se_area_weights",
     "se_weighted_gram_ws_bytes", "se_weighted_gram", "se_extrapolate_batch_ws_bytes",
     "se_extrapolate_batch", "se_extrapolate_plain", "se_blocks_upload", "se_project_ws_bytes",
-    "se_project", "se_iterate", "se_table_ld", "se_tables_tx_bytes",
+    "se_project", "se_iterate", "se_extrapolate_device_ws_bytes", "se_extrapolate_device",
+    "se_table_ld", "se_tables_tx_bytes",
     "se_extrapolate_ondemand_ws_bytes", "se_extrapolate_ondemand",
 )
 
@@ -135,6 +136,11 @@ def lib():
     L.se_iterate.restype = i32
     L.se_iterate.argtypes = [C.POINTER(se_tables), vp, i32, vp, i32, i32, i32, vp, i32,
                              se_params, vp, vp, vp, i32, vp]
+    L.se_extrapolate_device_ws_bytes.restype = sz
+    L.se_extrapolate_device_ws_bytes.argtypes = [C.POINTER(se_tables), i32]
+    L.se_extrapolate_device.restype = i32
+    L.se_extrapolate_device.argtypes = [C.POINTER(se_tables), vp, i32, i32, i32, vp, i32,
+                                        se_params, vp, vp, vp, i32, vp, sz, vp]
     L.se_extrapolate_ondemand_ws_bytes.restype = sz
     L.se_extrapolate_ondemand_ws_bytes.argtypes = [C.POINTER(se_basis), i32, i32]
     L.se_extrapolate_ondemand.restype = i32
@@ -372,6 +378,26 @@ def iterate(t: Tables, R: torch.Tensor, images: torch.Tensor, dblocks: DeviceBlo
     _check(L.se_iterate(C.byref(st), _ptr(R), R.shape[1], _ptr(images), n_img, H, W,
                         _ptr(dblocks.buf), dblocks.n, se_params(float(gamma), int(iters), 0),
                         _ptr(sel), _ptr(coef), _ptr(g_loss), gld, _stream(stream)))
+
+
+def extrapolate_device_ws_bytes(t: Tables, n_blk: int) -> int:
+    st = t.struct()
+    return int(lib().se_extrapolate_device_ws_bytes(C.byref(st), n_blk))
+
+
+def extrapolate_device(t: Tables, images: torch.Tensor, dblocks: DeviceBlocks, gamma: float,
+                       iters: int, ws=None, sel=None, coef=None, g_loss=None, stream=None):
+    """se_extrapolate_device: projections and loop for device descriptors (one
+    launch when every atom lies in a transform part; ``ws`` of
+    extrapolate_device_ws_bytes bytes otherwise)."""
+    L = lib()
+    n_img, H, W = images.shape
+    st = t.struct()
+    gld = g_loss.shape[1] if g_loss is not None else 0
+    _check(L.se_extrapolate_device(C.byref(st), _ptr(images), n_img, H, W, _ptr(dblocks.buf),
+                                   dblocks.n, se_params(float(gamma), int(iters), 0), _ptr(sel),
+                                   _ptr(coef), _ptr(g_loss), gld, _ptr(ws),
+                                   ws.numel() if ws is not None else 0, _stream(stream)))
 
 
 def extrapolate_ondemand(phi: torch.Tensor, M: int, N: int, w: torch.Tensor,

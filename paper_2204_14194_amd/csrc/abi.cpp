@@ -440,6 +440,43 @@ se_status se_iterate(const se_tables* t, const float* R, int32_t ldR, uint8_t* i
   return launch_greedy(ga, n_blk, static_cast<hipStream_t>(stream), tc.loop_waves, tc.loop_vpl);
 }
 
+size_t se_extrapolate_device_ws_bytes(const se_tables* t, int32_t n_blk) {
+  if (!t || t->K < 1 || t->M < 1 || t->N < 1 || n_blk < 0) return 0;
+  if (conceal_tx_supported(t)) return 0;
+  Carver cv(nullptr);
+  cv.take<float>((size_t)n_blk * greedy_row_len(t->K));
+  cv.take<char>(project_ws(t, n_blk));
+  return cv.off + 256;
+}
+
+se_status se_extrapolate_device(const se_tables* t, uint8_t* images, int32_t n_img, int32_t H,
+                                int32_t W, const se_block* dev_blocks, int32_t n_blk,
+                                se_params prm, int32_t* sel, float* coef, float* g_loss,
+                                int32_t g_loss_ld, void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  se_status st = check_common(t, n_img, H, W, n_blk, images, dev_blocks);
+  if (st) return st;
+  if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
+  if (n_blk == 0) return SE_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int ldR = greedy_row_len(t->K);
+  const TuneChoice tc = tune_lookup(t->K, t->M * t->N, n_blk);
+  if (conceal_tx_supported(t)) {
+    const GreedyArgs ga = greedy_args(t, nullptr, ldR, images, H, W, dev_blocks, n_blk, prm, sel,
+                                      coef, g_loss, g_loss_ld);
+    return conceal_tx(t, ga, images, H, W, n_blk, s, tc.loop_waves, tc.loop_vpl);
+  }
+  const size_t need = se_extrapolate_device_ws_bytes(t, n_blk);
+  if (!ws || ws_bytes < need) return fail(SE_ENOMEM, "workspace too small: need %zu bytes", need);
+  Carver cv(ws);
+  float* R = cv.take<float>((size_t)n_blk * ldR);
+  char* pws = cv.take<char>(project_ws(t, n_blk));
+  if ((st = project_into(t, images, H, W, dev_blocks, n_blk, R, ldR, pws, s))) return st;
+  const GreedyArgs ga = greedy_args(t, R, ldR, images, H, W, dev_blocks, n_blk, prm, sel, coef,
+                                    g_loss, g_loss_ld);
+  return launch_greedy(ga, n_blk, s, tc.loop_waves, tc.loop_vpl);
+}
+
 size_t se_extrapolate_batch_ws_bytes(const se_tables* t, int32_t n_blk) {
   if (!t || t->K < 1 || t->M < 1 || t->N < 1 || n_blk < 0) return 0;
   Carver cv(nullptr);
@@ -472,8 +509,10 @@ static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, in
   GreedyArgs ga = greedy_args(t, R, ldR, images, H, W, dblk, n_blk, prm, sel, coef, g_loss,
                               g_loss_ld);
   if (!plain) {
-    if ((st = project_into(t, images, H, W, dblk, n_blk, R, ldR, pws, s))) return st;
     const TuneChoice tc = tune_lookup(t->K, P, n_blk);
+    if (conceal_tx_supported(t))   // projections inside the loop's workgroups
+      return conceal_tx(t, ga, images, H, W, n_blk, s, tc.loop_waves, tc.loop_vpl);
+    if ((st = project_into(t, images, H, W, dblk, n_blk, R, ldR, pws, s))) return st;
     return launch_greedy(ga, n_blk, s, tc.loop_waves, tc.loop_vpl);
   }
   // one block at a time: gather, matrix-vector product (FP32), single-workgroup loop

@@ -1,0 +1,127 @@
+// Initial projections and the iteration loop in one launch, for tables whose
+// every atom lies in a declared transform part (Section VI): each block's
+// workgroup computes R~^(0) = D ⊙ T(w s) of its own area on the matrix cores
+// (eq. 12 via eq. 22, the scheme of the projection kernel), stages it in LDS
+// in the loop's atom order and runs Algorithm 3 from there.  R~^(0) never
+// goes to device memory, and no second launch is needed.  The arithmetic of
+// both stages is that of the separate kernels, so the results are the same
+// bit for bit.
+#include "greedy_device.h"
+#include "tx_device.h"
+
+namespace sefase {
+
+// LDS (floats): the padded row R~^(0) of T * VPL atoms; before the projection
+// writes it, the same space holds the X operands of the waves that compute a
+// part (MT * NT * 256 floats each, for areas inside the image on a 16-byte
+// grid).
+template <int WAVES, int VPL, int MT, int NT, int NP>
+constexpr int conceal_lds_floats() {
+  constexpr int row = 64 * WAVES * VPL;
+  constexpr int xs = (WAVES < NP ? WAVES : NP) * MT * NT * 256;
+  return row > xs ? row : xs;
+}
+
+// Areas up to 32 x 32: the projection stage fits the loop's register budget
+// (96 VGPRs, five waves per SIMD) when the compiler is held to it; larger
+// areas take what they need.
+template <int WAVES, int VPL, int MT, int NT, int NP>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(MT * NT <= 4 ? 5 : 1)))
+void k_conceal_tx(GreedyArgs a, TxArgs x, TxLayout L) {
+  constexpr int T = 64 * WAVES;
+  constexpr int NJ = VPL / 4;
+  extern __shared__ floatx4 smv[];
+  float* Rs = reinterpret_cast<float*>(smv);
+  const int t = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);   // uniform: operand addresses in SGPRs
+  const int b = blockIdx.x;
+  const DevBlock d = a.blk[b];
+  const int M = L.M, N = L.N;
+
+  // ---- projections: wave q computes part q (a single wave both) -----------
+  const bool computes = wave < NP;
+  floatx4 xv[MT][NT];
+  if (computes) {
+    TxPixels<MT, NT> P;
+    tx_load<MT, NT>(x, d, M, N, P);
+    tx_x_operands<MT, NT>(x, d, M, N, P, x.tx + L.oWf, Rs + wave * MT * NT * 256, xv);
+  }
+  __syncthreads();   // every X operand is in registers: the LDS becomes the row
+  if (computes) {
+#pragma unroll 1
+    for (int q = wave; q < NP; q += WAVES) {
+      float* Rq = Rs + (q ? x.first1 : x.first0);
+      tx_part<MT, NT, true>(x.tx + L.oAf + q * MT * MT * 256, x.tx + L.oBtf + q * NT * NT * 256,
+                            x.tx + L.oDf + q * MT * NT * 256, xv, M, N,
+                            [&](int k1, int k2, float v) { Rq[k1 * N + k2] = v; });
+    }
+  }
+  for (int k = a.K + t; k < T * VPL; k += T) Rs[k] = 0.0f;   // padding atoms
+  __syncthreads();
+
+  // ---- Algorithm 3 from R~^(0) ------------------------------------------------
+  float R[NJ][4];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const floatx4 v = *reinterpret_cast<const floatx4*>(Rs + 4 * (j * T + t));
+    R[j][0] = v[0]; R[j][1] = v[1]; R[j][2] = v[2]; R[j][3] = v[3];
+  }
+  greedy_block<WAVES, VPL>(a, b, R);
+}
+
+template <int WAVES, int VPL, int MT, int NT, int NP>
+static se_status launch_conceal(const GreedyArgs& a, const TxArgs& x, const TxLayout& L, int grid,
+                                hipStream_t s) {
+  const size_t lds = (size_t)conceal_lds_floats<WAVES, VPL, MT, NT, NP>() * 4;
+  hipLaunchKernelGGL((k_conceal_tx<WAVES, VPL, MT, NT, NP>), dim3(grid), dim3(64 * WAVES), lds, s,
+                     a, x, L);
+  return check_launch("conceal_tx");
+}
+
+// The instantiated combinations: two parts covering every atom of 32 x 32 or
+// 64 x 64 areas (K = 2048 or 8192), with every loop shape of that row length.
+static int conceal_case(int M, int N, int n_parts) {
+  if (n_parts != 2 || M != N) return 0;
+  return M == 32 ? 2 : M == 64 ? 4 : 0;
+}
+
+bool conceal_tx_supported(const se_tables* t) {
+  if (!t || t->n_parts < 1 || !t->tx || conceal_case(t->M, t->N, t->n_parts) == 0) return false;
+  int lo[3], hi[3];
+  return dense_ranges(t->K, t->M, t->N, t->n_parts, t->parts, lo, hi) == 0;
+}
+
+se_status conceal_tx(const se_tables* t, const GreedyArgs& a, const uint8_t* images, int H, int W,
+                     int n_blk, hipStream_t s, int waves, int vpl) {
+  if (n_blk <= 0) return SE_OK;
+  if (!conceal_tx_supported(t)) return fail(SE_EINVAL, "no fused projection for these tables");
+  if (waves <= 0) {
+    waves = greedy_waves_for(t->K);
+    vpl = greedy_row_len(t->K) / (64 * waves);
+  }
+  if (64 * waves * vpl != greedy_row_len(t->K) || a.ldG < 64 * waves * vpl)
+    return fail(SE_EINVAL, "loop shape %dx%d does not match the row length of K=%d", waves, vpl,
+                t->K);
+  TxArgs x{};
+  x.images = images;
+  x.H = H;
+  x.W = W;
+  x.blk = a.blk;
+  x.n_blk = n_blk;
+  x.K = t->K;
+  x.tx = t->tx;
+  x.first0 = t->parts[0].first;
+  x.first1 = t->n_parts > 1 ? t->parts[1].first : 0;
+  const TxLayout L(t->M, t->N, t->n_parts, 0);
+  const int key = conceal_case(t->M, t->N, t->n_parts) * 10000 + waves * 100 + vpl;
+  switch (key) {
+    case 20132: return launch_conceal<1, 32, 2, 2, 2>(a, x, L, n_blk, s);
+    case 20216: return launch_conceal<2, 16, 2, 2, 2>(a, x, L, n_blk, s);
+    case 20408: return launch_conceal<4, 8, 2, 2, 2>(a, x, L, n_blk, s);
+    case 40432: return launch_conceal<4, 32, 4, 4, 2>(a, x, L, n_blk, s);
+    case 40816: return launch_conceal<8, 16, 4, 4, 2>(a, x, L, n_blk, s);
+    default: return fail(SE_EINVAL, "no fused loop shape %dx%d for K=%d", waves, vpl, t->K);
+  }
+}
+
+}  // namespace sefase

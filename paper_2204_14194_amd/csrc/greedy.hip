@@ -1,38 +1,9 @@
 // The iteration loop of Fast Selective Extrapolation (Algorithm 3), one
-// workgroup per lost block.
-//
-// State: the K weighted scalar products R_k (eq. 11) live in registers,
-// VPL per lane, in units of D_k (R~_k = D_k R_k; the initial values come
-// from the projection GEMM).  With the unit-diagonal table
-// G[k][l] = D_k C_(k,l) D_l the three per-iteration formulas become
-//   u  = argmax_k |R~_k|                       (eq. 18: |R_k| D_k = |R~_k|)
-//   c  = gamma R~_u D_u                        (eq. 19: gamma R_u D_u^2)
-//   R~_k -= gamma R~_u G[u][k]  for all k      (eq. 20 scaled by D_k, using
-//                                               C symmetric: row u = column u)
-// and the model update g += c phi_u (eq. 9) is applied to the loss pixels
-// only, in registers, every iteration (the rest of g is never used).
-//
-// Atom ownership: lane t of the workgroup (T = 64 * WAVES lanes) holds atoms
-// 4 (j T + t) + e, j < VPL/4, e < 4, so every row load is a coalesced float4
-// sweep.  Rows of G and of R are padded with zeros to T * VPL columns (the
-// table row stride), so no load needs a bounds check; padded atoms hold 0
-// and are never candidates.
-//
-// Selection: the wave's largest |R~| is found from per-lane maxima with a
-// DPP reduction; when one lane alone holds it, that lane's group maxima and
-// then the four values of its first matching group are read into scalar
-// registers and scanned for the lowest index.  When several lanes hold the maximum
-// (exact ties, e.g. parallel atoms), every lane scans its atoms in index
-// order and the wave reduces 64-bit keys
-//     |R~| bits << 32  |  (0xFFFF - k) << 16  |  sign << 15
-// so the lowest index wins.  Workgroups of several waves combine the wave
-// winners' keys through LDS.
-#include "se_internal.h"
-#include "argmax.h"
+// workgroup per lost block, from initial projections in device memory; the
+// loop itself is greedy_block (greedy_device.h).
+#include "greedy_device.h"
 
 namespace sefase {
-
-constexpr int kQPL = 4;   // loss pixels per lane (the loss may hold <= 4 T pixels)
 
 // ONE: the launch conceals the single block a.blk0 (plain per-block form); a
 // separate instantiation so profiles keep the two forms apart.
@@ -41,185 +12,15 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy(GreedyArgs a) {
   constexpr int T = 64 * WAVES;
   constexpr int NJ = VPL / 4;
   const int t = threadIdx.x;
-  const int lane = t & 63, wave = t >> 6;
-  const int b = ONE ? a.blk0 : (int)blockIdx.x;
-  const DevBlock d = a.blk[b];
-  const int K = a.K, P = a.M * a.N;
-
-  // ---- load R~^(0) (rows padded with zeros to T * VPL) -------------------
+  // R~^(0), rows padded with zeros to T * VPL
   float R[NJ][4];
-  {
-    const float* src = a.R0 + (size_t)blockIdx.x * a.ldR;
+  const float* src = a.R0 + (size_t)blockIdx.x * a.ldR;
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const float4 v = *reinterpret_cast<const float4*>(src + 4 * (j * T + t));
-      R[j][0] = v.x; R[j][1] = v.y; R[j][2] = v.z; R[j][3] = v.w;
-    }
+  for (int j = 0; j < NJ; ++j) {
+    const float4 v = *reinterpret_cast<const float4*>(src + 4 * (j * T + t));
+    R[j][0] = v.x; R[j][1] = v.y; R[j][2] = v.z; R[j][3] = v.w;
   }
-
-  // ---- loss pixels owned by this lane ----------------------------------
-  // Lanes past the end of the loss repeat its last pixel (a valid address);
-  // their sums are never written.
-  const int nloss = d.lh * d.lw;
-  const int nq = (nloss + T - 1) / T;          // uniform
-  int poff[kQPL];
-  float g[kQPL], gc[kQPL];   // model and its compensation term (Kahan summation)
-#pragma unroll
-  for (int q = 0; q < kQPL; ++q) {
-    int i = t + q * T;
-    i = i < nloss ? i : nloss - 1;
-    const int my = i / d.lw, mx = i - my * d.lw;
-    poff[q] = (d.ly + my) * a.N + d.lx + mx;
-    g[q] = 0.0f;
-    gc[q] = 0.0f;
-  }
-
-  __shared__ uint64_t s_key[2][WAVES];
-  int par = 0;
-  const float gamma = a.gamma;
-
-  for (int it = 0; it < a.iters; ++it) {
-    // ---- this wave's largest |R~| and its lowest index ---------------------
-    // Group maxima (4 atoms each) and the lane maximum, then the wave
-    // maximum by DPP.
-    float gm[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j)
-      gm[j] = fmaxf(fmaxf(fabsf(R[j][0]), fabsf(R[j][1])), fmaxf(fabsf(R[j][2]), fabsf(R[j][3])));
-    float lm = gm[0];
-#pragma unroll
-    for (int j = 1; j < NJ; ++j) lm = fmaxf(lm, gm[j]);
-    const float M = wave_max_f32(lm);
-    const uint64_t holders = __builtin_amdgcn_ballot_w64(lm == M);
-    int u = 0;
-    float rv = 0.0f;
-    uint64_t key = 0;                          // every score zero: atom 0, value 0
-    bool direct = WAVES == 1;
-    if (M != 0.0f && __builtin_popcountll(holders) == 1) {
-      // lane L alone holds the maximum: its group maxima, then the four
-      // values of the first matching group, are read into scalar
-      // registers and scanned there (lowest index first)
-      const int L = __builtin_ctzll(holders);
-      const uint32_t Mb = __float_as_uint(M);
-      int gsel = NJ - 1;
-#pragma unroll
-      for (int j = NJ - 2; j >= 0; --j)
-        gsel = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(gm[j]), L) == Mb ? j : gsel;
-      uint32_t r[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-      for (int j = 0; j < NJ; ++j)
-        if (j == gsel) {                       // uniform branch
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            r[e] = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(R[j][e]), L);
-        }
-      int csel = 3;
-#pragma unroll
-      for (int e = 2; e >= 0; --e) csel = (r[e] & 0x7FFFFFFFu) == Mb ? e : csel;
-      const uint32_t vbits = csel == 0 ? r[0] : csel == 1 ? r[1] : csel == 2 ? r[2] : r[3];
-      u = 4 * (gsel * T + wave * 64 + L) + csel;
-      rv = __uint_as_float(vbits);
-      if (u >= K) {                            // only with nonzero padding of R
-        u = 0;
-        rv = 0.0f;
-      }
-      if (WAVES > 1) key = make_key(rv, u);
-    } else if (M != 0.0f) {
-      // exact ties across lanes: every lane's first maximum as a key
-      float bv = 0.0f;
-      int c = 0;
-#pragma unroll
-      for (int j = 0; j < NJ; ++j)
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (fabsf(R[j][e]) > fabsf(bv)) {
-            bv = R[j][e];
-            c = 4 * j + e;
-          }
-      const uint64_t mine = make_key(bv, 4 * ((c >> 2) * T + t) + (c & 3));
-      key = wave_max_key((uint32_t)(mine >> 32), (uint32_t)mine);
-      direct = false;
-    }
-    if (WAVES > 1) {
-      if (lane == 0) s_key[par][wave] = key;
-      __syncthreads();
-      key = s_key[par][0];
-#pragma unroll
-      for (int w = 1; w < WAVES; ++w) {
-        const uint64_t o = s_key[par][w];
-        key = o > key ? o : key;
-      }
-      par ^= 1;
-    }
-    // ---- the winner (wave-uniform, kept in scalar registers) ----------------
-    if (!direct) decode_key(key, K, u, rv);
-    u = __builtin_amdgcn_readfirstlane(u);
-    rv = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rv)));
-    const float tc = gamma * rv;              // coefficient of the unit-norm atom
-
-    // ---- stream row u of the table and the atom over the loss ---------------
-    // (the first pixel of every lane always exists; more pixels per lane
-    // only for losses larger than the workgroup, one uniform branch)
-    const float* prow = a.phi + (size_t)u * P;
-    float pv[kQPL];
-    pv[0] = prow[poff[0]];
-    if (nq > 1) {
-#pragma unroll
-      for (int q = 1; q < kQPL; ++q)
-        if (q < nq) pv[q] = prow[poff[q]];
-    }
-    const float* grow = a.G + (size_t)u * a.ldG;
-    float4 row[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) row[j] = *reinterpret_cast<const float4*>(grow + 4 * (j * T + t));
-    // D is read-only for the whole launch: a scalar load (constant address
-    // space) that does not wait behind the row's vector loads
-    const float Du = ((const __attribute__((address_space(4))) float*)a.D)[u];
-    const float c = tc * Du;                  // eq. 19
-    if (t == 0) {
-      if (a.sel) a.sel[(size_t)b * a.iters + it] = u;
-      if (a.coef) a.coef[(size_t)b * a.iters + it] = c;
-    }
-    {                                         // eq. 9, compensated
-      const float y = fmaf(c, pv[0], -gc[0]);
-      const float s = g[0] + y;
-      gc[0] = (s - g[0]) - y;
-      g[0] = s;
-    }
-    if (nq > 1) {
-#pragma unroll
-      for (int q = 1; q < kQPL; ++q)
-        if (q < nq) {
-          const float y = fmaf(c, pv[q], -gc[q]);
-          const float s = g[q] + y;
-          gc[q] = (s - g[q]) - y;
-          g[q] = s;
-        }
-    }
-
-    // ---- eq. 20 -------------------------------------------------------------
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      R[j][0] = fmaf(-tc, row[j].x, R[j][0]);
-      R[j][1] = fmaf(-tc, row[j].y, R[j][1]);
-      R[j][2] = fmaf(-tc, row[j].z, R[j][2]);
-      R[j][3] = fmaf(-tc, row[j].w, R[j][3]);
-    }
-  }
-
-  // ---- replace the loss area by the model ----------------------------------
-#pragma unroll
-  for (int q = 0; q < kQPL; ++q) {
-    const int i = t + q * T;
-    if (i >= nloss) continue;
-    if (a.g_loss && i < a.g_loss_ld) a.g_loss[(size_t)b * a.g_loss_ld + i] = g[q];
-    const int my = i / d.lw, mx = i - my * d.lw;
-    const int y = d.y0 + d.ly + my, x = d.x0 + d.lx + mx;
-    if (y >= 0 && y < a.H && x >= 0 && x < a.W) {
-      const float v = fminf(fmaxf(rintf(g[q]), 0.0f), 255.0f);
-      a.images[(size_t)d.img * a.H * a.W + (size_t)y * a.W + x] = (uint8_t)v;
-    }
-  }
+  greedy_block<WAVES, VPL>(a, ONE ? a.blk0 : (int)blockIdx.x, R);
 }
 
 // Workgroup shapes: (waves, values per lane).  The capacity 64 * waves * vpl

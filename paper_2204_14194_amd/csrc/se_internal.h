@@ -182,6 +182,11 @@ struct OnDemandPlan {
 };
 se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s);
 
+// fused.hip -- projections of transform parts and the loop in one launch
+bool conceal_tx_supported(const se_tables* t);
+se_status conceal_tx(const se_tables* t, const GreedyArgs& a, const uint8_t* images, int H, int W,
+                     int n_blk, hipStream_t s, int waves, int vpl);
+
 int greedy_waves_for(int K);   // 0 if K is too large
 int greedy_row_len(int K);     // padded row length (table row stride minimum)
 // loop shapes (waves, values per lane) with the row length of K; returns count

@@ -13,6 +13,7 @@
 #include <atomic>
 
 #include "se_internal.h"
+#include "tx_device.h"
 
 namespace sefase {
 
@@ -67,54 +68,6 @@ __global__ __launch_bounds__(kTxThreads) void k_check_part(const float* __restri
   }
   if (bad) atomicOr(flag, 1);
 }
-
-// ---------------------------------------------------------------------------
-// Separable transform on the FP32 matrix cores (v_mfma_f32_16x16x4f32).
-// Areas are padded to Mp = 16 MT rows and Np = 16 NT columns (zeros); one
-// wave transforms one block.  With j = l/16 the lane's group of 16:
-//   stage 1   Y1 = X B^T   tile (i, c), k-steps (sq, t): the k index j
-//             stands for column n = 16 sq + 4 j + t, so a lane's four
-//             t-values are four adjacent pixels of one row.  A-operand
-//             X[16i + l%16][n], B-operand B[16c + l%16][n]; lane l then
-//             holds Y1[16i + 4j + e][16c + l%16], e < 4
-//   stage 2   Z = A Y1     tile (r, c): the stage-1 registers serve as the
-//             B-operands unchanged, k-step (i, e) standing for the rows
-//             m = 16i + 4j + e, with the A-operand A[16r + l%16][m]; lane l
-//             then holds Z[16r + 4j + e][16c + l%16]
-// (both sums run in a permuted order, so nothing moves between the
-// stages).  Operands are stored in fragment order -- lane l's four
-// consecutive floats at (tile * 64 + l) * 4, one conflict-free
-// ds_read_b128 each.  The constant operands (se_tables.tx, written once
-// by se_weighted_gram, copied to LDS by every workgroup):
-//   Af [part][r][i]  [l][e]  A[16r + l%16][16i + 4j + e]
-//   Btf[part][c][sq] [l][t]  B[16c + l%16][16sq + 4j + t]
-//   Df [part][c][r]  [l][e]  D_k of output (16r + 4j + e, 16c + l%16)
-//   Wf [i][sq]       [l][t]  w of pixel (16i + l%16, 16sq + 4j + t)
-// and per wave in LDS, the block's X = w s in the order of Wf (Xf).
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-struct TxLayout {
-  int M, N, MT, NT, parts, waves;
-  // offsets in floats; [0, nconst) is the copy of se_tables.tx.  Each wave
-  // owns wsz floats at oXf: its X fragments, and with staging (zs > 0) one
-  // part's M x N output at row stride zs.
-  int oAf, oBtf, oDf, oWf, nconst, oXf, zs, wsz, nfloat;
-  __host__ __device__ TxLayout(int M_, int N_, int parts_, int waves_, bool stage = false)
-      : M(M_), N(N_), parts(parts_), waves(waves_) {
-    MT = (M + 15) / 16;
-    NT = (N + 15) / 16;
-    oAf = 0;
-    oBtf = oAf + parts * MT * MT * 256;
-    oDf = oBtf + parts * NT * NT * 256;
-    oWf = oDf + parts * MT * NT * 256;
-    nconst = oWf + MT * NT * 256;
-    oXf = nconst;
-    zs = stage ? N + 4 : 0;
-    wsz = MT * NT * 256 > M * zs ? MT * NT * 256 : M * zs;
-    nfloat = oXf + waves * wsz;
-  }
-  __host__ __device__ size_t bytes() const { return (size_t)nfloat * 4; }
-};
 
 // ---------------------------------------------------------------------------
 // The constant operands (se_weighted_gram, once per table set): entry x of
@@ -172,221 +125,6 @@ __global__ __launch_bounds__(kTxThreads) void k_build_tx(TxBuildArgs a, TxLayout
     }
     a.tx[x] = v;
   }
-}
-
-// Column tiles c0 .. c0 + CP - 1 of Z = A X B^T for one part, from the X
-// operands x (registers, x[i][sq][t] as above); the CP tiles share the X and
-// A operands and run as independent accumulation chains.  out(k1, k2, v)
-// for every k1 < M, k2 < N of those tiles, v = D_k z when SCALE (Df read),
-// else z.
-template <int MT, int NT, int CP, bool SCALE, typename Out>
-__device__ inline void tx_cols(int c0, const float* Af, const float* Btf, const float* Df,
-                               const floatx4 (&x)[MT][NT], int M, int N, Out& out) {
-  const int l = threadIdx.x & 63;
-  floatx4 y[CP][MT];
-#pragma unroll
-  for (int cc = 0; cc < CP; ++cc)
-#pragma unroll
-    for (int i = 0; i < MT; ++i) y[cc][i] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int sq = 0; sq < NT; ++sq) {
-    floatx4 bv[CP];
-#pragma unroll
-    for (int cc = 0; cc < CP; ++cc)
-      bv[cc] = *reinterpret_cast<const floatx4*>(Btf + (((c0 + cc) * NT + sq) * 64 + l) * 4);
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int cc = 0; cc < CP; ++cc)
-#pragma unroll
-        for (int i = 0; i < MT; ++i)
-          y[cc][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[i][sq][t], bv[cc][t], y[cc][i], 0, 0, 0);
-  }
-  floatx4 z[CP][MT];
-#pragma unroll
-  for (int cc = 0; cc < CP; ++cc)
-#pragma unroll
-    for (int r = 0; r < MT; ++r) z[cc][r] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int i = 0; i < MT; ++i) {
-    floatx4 av[MT];
-#pragma unroll
-    for (int r = 0; r < MT; ++r)
-      av[r] = *reinterpret_cast<const floatx4*>(Af + ((r * MT + i) * 64 + l) * 4);
-    // consecutive products go to different accumulators
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-#pragma unroll
-      for (int cc = 0; cc < CP; ++cc)
-#pragma unroll
-        for (int r = 0; r < MT; ++r)
-          z[cc][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r][e], y[cc][i][e], z[cc][r], 0, 0, 0);
-  }
-#pragma unroll
-  for (int cc = 0; cc < CP; ++cc) {
-    const int c = c0 + cc, k2 = 16 * c + (l & 15);
-#pragma unroll
-    for (int r = 0; r < MT; ++r) {
-      floatx4 dv = floatx4{1.f, 1.f, 1.f, 1.f};
-      if (SCALE) dv = *reinterpret_cast<const floatx4*>(Df + ((c * MT + r) * 64 + l) * 4);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int k1 = 16 * r + 4 * (l >> 4) + e;
-        if (k1 < M && k2 < N) out(k1, k2, dv[e] * z[cc][r][e]);
-      }
-    }
-  }
-}
-
-// Z = A X B^T of one part (operand fragments of that part), two column
-// tiles per pass.
-template <int MT, int NT, bool SCALE, typename Out>
-__device__ void tx_part(const float* Af, const float* Btf, const float* Df,
-                        const floatx4 (&x)[MT][NT], int M, int N, Out out) {
-#pragma unroll 1
-  for (int c0 = 0; c0 + 1 < NT; c0 += 2) {
-    // re-read the A operands per pass instead of holding them in registers
-    // across the loop
-    asm volatile("" : "+s"(Af));
-    tx_cols<MT, NT, 2, SCALE>(c0, Af, Btf, Df, x, M, N, out);
-  }
-  if (NT & 1) tx_cols<MT, NT, 1, SCALE>(NT - 1, Af, Btf, Df, x, M, N, out);
-}
-
-// Orders this wave's LDS writes before its later reads (and reads before
-// later writes).
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// ---------------------------------------------------------------------------
-// Initial projections of the transform parts (eq. 12 via eq. 22), fused with
-// the gather: x = w s over the block's area (0 outside the image), then per
-// part R[b][first + k1 N + k2] = D_k (A x B^T)[k1][k2].  Columns K .. ldR-1
-// of R are written as 0.  One wave per block; each workgroup copies the
-// constant operands to LDS once and its waves loop over blocks.
-struct TxArgs {
-  const uint8_t* images;
-  int H, W;
-  const DevBlock* blk;
-  int n_blk;
-  int K;
-  const float* tx;
-  int first0, first1;
-  float* R;
-  int ldR;
-};
-
-// Pixels of one block, as the lane holds them until they become X operands:
-// whole 16-pixel row segments when the area lies inside the image on a
-// 16-byte grid (one 16-byte load each), else single pixels at clamped
-// coordinates.
-template <int MT, int NT>
-struct TxPixels {
-  static constexpr int CH = (MT * NT + 3) / 4;   // row segments per lane
-  bool fast;
-  // single pixels: v[(i * NT + sq) * 4 + t]; segments: v[4 k .. 4 k + 3]
-  uint32_t v[MT * NT * 4];
-};
-
-template <int MT, int NT>
-__device__ inline void tx_load(const TxArgs& a, const DevBlock& d, int M, int N,
-                               TxPixels<MT, NT>& P) {
-  const int l = threadIdx.x & 63, lr = l & 15, lc = 4 * (l >> 4);
-  const uint8_t* img = a.images + (size_t)d.img * a.H * a.W;
-  P.fast = (M & 15) == 0 && (N & 15) == 0 && (a.W & 15) == 0 && (d.x0 & 15) == 0 &&
-           d.y0 >= 0 && d.x0 >= 0 && d.y0 + M <= a.H && d.x0 + N <= a.W;
-  if (P.fast) {
-    const int spr = N >> 4, nseg = M * spr;
-#pragma unroll
-    for (int k = 0; k < P.CH; ++k) {
-      const int c = min(l + 64 * k, nseg - 1);
-      const int m = c / spr, sg = c - m * spr;
-      const uint4 q = *reinterpret_cast<const uint4*>(img + (size_t)(d.y0 + m) * a.W + d.x0 + 16 * sg);
-      P.v[4 * k] = q.x;
-      P.v[4 * k + 1] = q.y;
-      P.v[4 * k + 2] = q.z;
-      P.v[4 * k + 3] = q.w;
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < MT; ++i) {
-      const uint8_t* row = img + (size_t)min(max(d.y0 + 16 * i + lr, 0), a.H - 1) * a.W;
-#pragma unroll
-      for (int sq = 0; sq < NT; ++sq)
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-          P.v[(i * NT + sq) * 4 + t] = row[min(max(d.x0 + 16 * sq + lc + t, 0), a.W - 1)];
-    }
-  }
-}
-
-// X operands x = w s (s = 0 outside the area and the image).
-template <int MT, int NT>
-__device__ inline void tx_x_operands(const TxArgs& a, const DevBlock& d, int M, int N,
-                                     TxPixels<MT, NT>& P, const float* Wf, float* Xf,
-                                     floatx4 (&xv)[MT][NT]) {
-  const int l = threadIdx.x & 63, lr = l & 15, lc = 4 * (l >> 4);
-  if (P.fast) {
-    // segment (row m, columns 16 sg .. 16 sg + 15) covers, for j < 4, the
-    // four t-values of fragment lane (m & 15) + 16 j of tile (m >> 4, sg)
-    const int spr = N >> 4, nseg = M * spr;
-#pragma unroll
-    for (int k = 0; k < P.CH; ++k) {
-      const int c = l + 64 * k;
-      if (c < nseg) {
-        const int m = c / spr, sg = c - m * spr;
-        const uint32_t wd[4] = {P.v[4 * k], P.v[4 * k + 1], P.v[4 * k + 2], P.v[4 * k + 3]};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int o = (((m >> 4) * NT + sg) * 64 + (m & 15) + 16 * j) * 4;
-          const floatx4 w = *reinterpret_cast<const floatx4*>(Wf + o);
-          floatx4 v;
-          v[0] = w[0] * (float)(wd[j] & 0xFFu);
-          v[1] = w[1] * (float)((wd[j] >> 8) & 0xFFu);
-          v[2] = w[2] * (float)((wd[j] >> 16) & 0xFFu);
-          v[3] = w[3] * (float)(wd[j] >> 24);
-          *reinterpret_cast<floatx4*>(Xf + o) = v;
-        }
-      }
-    }
-    wave_sync();
-#pragma unroll
-    for (int i = 0; i < MT; ++i)
-#pragma unroll
-      for (int sq = 0; sq < NT; ++sq)
-        xv[i][sq] = *reinterpret_cast<const floatx4*>(Xf + ((i * NT + sq) * 64 + l) * 4);
-    wave_sync();   // read before the next block's writes
-  } else {
-#pragma unroll
-    for (int i = 0; i < MT; ++i) {
-      const int y = d.y0 + 16 * i + lr;
-      const bool row_in = 16 * i + lr < M && y >= 0 && y < a.H;
-#pragma unroll
-      for (int sq = 0; sq < NT; ++sq) {
-        const floatx4 w = *reinterpret_cast<const floatx4*>(Wf + ((i * NT + sq) * 64 + l) * 4);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int n = 16 * sq + lc + t, x = d.x0 + n;
-          // the value is taken as used here, so its load stays
-          // unconditional (not moved under the test below, which would
-          // serialise the loads)
-          uint32_t& pv = P.v[(i * NT + sq) * 4 + t];
-          asm volatile("" : "+v"(pv));
-          xv[i][sq][t] = (row_in && n < N && x >= 0 && x < a.W) ? w[t] * (float)pv : 0.0f;
-        }
-      }
-    }
-  }
-}
-
-// Workgroup size bound: 16 waves for areas up to 32 x 32 (or 16 x 64), 4
-// waves above (more registers per lane for the larger tiles).
-template <int MT, int NT>
-constexpr int tx_max_threads() {
-  return (MT >= 3 || MT * NT >= 6) ? 256 : 1024;
 }
 
 template <int MT, int NT, int NP, bool STAGE>
