@@ -22,11 +22,12 @@ constexpr int conceal_lds_floats() {
   return row > xs ? row : xs;
 }
 
-// Areas up to 32 x 32: the projection stage fits the loop's register budget
-// (96 VGPRs, five waves per SIMD) when the compiler is held to it; larger
-// areas take what they need.
+// Areas up to 32 x 32: held to four waves per SIMD (128 registers), so the
+// compiler keeps the projection stage in vector registers without the
+// accumulation registers it would otherwise add (four resident blocks per
+// SIMD cover a 4096-block batch at once); larger areas take what they need.
 template <int WAVES, int VPL, int MT, int NT, int NP>
-__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(MT * NT <= 4 ? 5 : 1)))
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(MT * NT <= 4 ? 4 : 1)))
 void k_conceal_tx(GreedyArgs a, TxArgs x, TxLayout L) {
   constexpr int T = 64 * WAVES;
   constexpr int NJ = VPL / 4;
@@ -51,8 +52,11 @@ void k_conceal_tx(GreedyArgs a, TxArgs x, TxLayout L) {
 #pragma unroll 1
     for (int q = wave; q < NP; q += WAVES) {
       float* Rq = Rs + (q ? x.first1 : x.first0);
-      tx_part<MT, NT, true>(x.tx + L.oAf + q * MT * MT * 256, x.tx + L.oBtf + q * NT * NT * 256,
-                            x.tx + L.oDf + q * MT * NT * 256, xv, M, N,
+      // a square area transforms rows and columns with the same matrix, whose
+      // two fragment orders then coincide: one copy is read
+      const float* Af = x.tx + L.oAf + q * MT * MT * 256;
+      const float* Btf = M == N ? Af : x.tx + L.oBtf + q * NT * NT * 256;
+      tx_part<MT, NT, true>(Af, Btf, x.tx + L.oDf + q * MT * NT * 256, xv, M, N,
                             [&](int k1, int k2, float v) { Rq[k1 * N + k2] = v; });
     }
   }

@@ -127,9 +127,12 @@ __device__ void tx_part(const float* Af, const float* Btf, const float* Df,
 #pragma unroll 1
   for (int c0 = 0; c0 + 1 < NT; c0 += 2) {
     // re-read the A operands per pass instead of holding them in registers
-    // across the loop
-    asm volatile("" : "+s"(Af));
-    tx_cols<MT, NT, 2, SCALE>(c0, Af, Btf, Df, x, M, N, out);
+    // across the loop: an offset the compiler cannot see through (the
+    // pointer itself keeps its address space, so the reads stay LDS or
+    // global loads rather than flat ones)
+    int opaque = 0;
+    asm volatile("" : "+s"(opaque));
+    tx_cols<MT, NT, 2, SCALE>(c0, Af + opaque, Btf, Df, x, M, N, out);
   }
   if (NT & 1) tx_cols<MT, NT, 1, SCALE>(NT - 1, Af, Btf, Df, x, M, N, out);
 }
