@@ -66,6 +66,18 @@ def _oracle_block(i):
     return time.process_time() - t0
 
 
+def _fase_block(i):
+    import oracle
+    from threadpoolctl import threadpool_limits
+    d = _CPU["d"]
+    b = d["blocks"][i]
+    t0 = time.process_time()
+    with threadpool_limits(1):
+        s, sup = oracle.area_signal(d["images"][b.img], _CPU["lost"][b.img], b.y0, b.x0, M, N)
+        oracle.fase(s, _CPU["w"], _CPU["phi"], _CPU["C"], _CPU["D"], GAMMA, ITERS)
+    return time.process_time() - t0
+
+
 def cpu_baseline(n_blocks: int):
     """Times ``oracle.se_original`` (Algorithm 1, float64) on ``n_blocks``
     blocks of the workload with one process per core.  Runs before the GPU
@@ -82,6 +94,21 @@ def cpu_baseline(n_blocks: int):
     with ctx.Pool(cores) as pool:
         cpu_s = pool.map(_oracle_block, range(n_blocks), chunksize=1)
     wall = time.perf_counter() - t0
+    # context: the fast algorithm on the same cores -- Algorithm 2 once for
+    # the shared weight pattern (one core), then Algorithm 3 per block
+    import oracle
+    from threadpoolctl import threadpool_limits
+    b0 = d["blocks"][0]
+    _, sup0 = oracle.area_signal(d["images"][b0.img], _CPU["lost"][b0.img], b0.y0, b0.x0, M, N)
+    _CPU["w"] = oracle.area_weights(M, N, RHO, sup0)
+    tt0 = time.perf_counter()
+    with threadpool_limits(1):
+        _CPU["C"], _CPU["D"] = oracle.table_generation(_CPU["phi"], _CPU["w"])
+    tables_s = time.perf_counter() - tt0
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        fase_s = pool.map(_fase_block, range(n_blocks), chunksize=1)
+    fase_wall = time.perf_counter() - t0
     model = ""
     try:
         with open("/proc/cpuinfo") as fh:
@@ -94,7 +121,12 @@ def cpu_baseline(n_blocks: int):
     return {"value": n_blocks / wall, "unit": "blocks/s", "cores": cores, "kind": "oracle",
             "sample": f"{n_blocks} blocks of the benchmark workload, Algorithm 1 (original SE, "
                       f"FP64 NumPy), one process per core; "
-                      f"{float(np.mean(cpu_s)):.3f} s/block on one core; CPU: {model}"}
+                      f"{float(np.mean(cpu_s)):.3f} s/block on one core; CPU: {model}",
+            "fase": {"value": n_blocks / fase_wall, "unit": "blocks/s", "cores": cores,
+                     "s_per_block_one_core": float(np.mean(fase_s)), "tables_s": tables_s,
+                     "what": "context: the oracle's Algorithm 3 (FP64 NumPy) on the same blocks "
+                             "and cores, after Algorithm 2 once for the shared weight pattern "
+                             "(tables_s, one core)"}}
 
 
 # ---------------------------------------------------------------------------
