@@ -6,9 +6,14 @@ and the CPU-baseline leg of the benchmark may import it; the library never
 does, and it shares no code with the library (it reads only the seeded inputs
 of ``paper_2204_14194_amd.synth``).
 
-Everything is real-valued float64.  The paper states the method for complex
-basis functions; for real signals and atoms the conjugations drop out
-(Section III, opening paragraph), which is the reading used throughout.
+Arithmetic is float64, complex128 for complex dictionaries.  The paper
+states the method for complex basis functions (eq. 3, 7, 11, 16 with the
+conjugate of the atom); for real signals and atoms the conjugations drop out
+(Section III, opening paragraph), and a real dictionary takes exactly the
+real-valued expressions.  Signals are real images; with a complex dictionary
+the model g is complex and its real part replaces the loss (a reading: the
+paper cuts "the model" out without saying how a complex model becomes a
+pixel value).
 
 Contents, in the paper's notation:
   * ``area_weights``      -- weighting function w = rho on A, 0 on B (eq. 4)
@@ -89,6 +94,25 @@ def area_signal(image: np.ndarray, lost: np.ndarray, y0: int, x0: int,
     return s.reshape(M * N), support
 
 
+def _basis(phi: np.ndarray) -> np.ndarray:
+    """The dictionary as float64, or complex128 when it is complex."""
+    if np.iscomplexobj(phi):
+        return np.asarray(phi, dtype=np.complex128)
+    return np.asarray(phi, dtype=np.float64)
+
+
+def _conj(a: np.ndarray) -> np.ndarray:
+    """Complex conjugate (the identity on a real array)."""
+    return np.conj(a) if np.iscomplexobj(a) else a
+
+
+def _abs2(a):
+    """|a|^2; for real a exactly a * a."""
+    if np.iscomplexobj(a):
+        return a.real * a.real + a.imag * a.imag
+    return a * a
+
+
 # ----------------------------------------------------------------------------
 # Algorithm 1: original SE
 # ----------------------------------------------------------------------------
@@ -131,25 +155,27 @@ def se_original(s: np.ndarray, w: np.ndarray, phi: np.ndarray, gamma: float,
     algorithm along a selection sequence that another implementation chose
     at a near-tie.
     """
-    s = np.asarray(s, dtype=np.float64)
     w = np.asarray(w, dtype=np.float64)
-    phi = np.asarray(phi, dtype=np.float64)
+    phi = _basis(phi)
+    cplx = np.iscomplexobj(phi)
+    s = np.asarray(s, dtype=np.complex128 if cplx else np.float64)
+    phic = _conj(phi)
     r = s.copy()                         # r^(0) = s  (eq. 2)
     g = np.zeros_like(s)                 # g^(0) = 0
     sel = np.zeros(iters, dtype=np.int64)
-    coef = np.zeros(iters)
+    coef = np.zeros(iters, dtype=s.dtype)
     best = np.zeros(iters)
     second = np.zeros(iters)
     picked = np.zeros(iters)
     energy = np.zeros(iters + 1)
-    energy[0] = float(np.sum(w * r * r))
+    energy[0] = float(np.sum(w * _abs2(r)))
     for nu in range(iters):
-        num = np.sum(phi * (r * w)[None, :], axis=1)        # sum r phi_k w
-        den = np.sum(phi * w[None, :] * phi, axis=1)         # sum phi_k w phi_k
+        num = np.sum(phic * (r * w)[None, :], axis=1)       # sum r phi_k^* w
+        den = np.sum(phic * w[None, :] * phi, axis=1).real   # sum phi_k^* w phi_k
         safe = den > 0.0
         p = np.zeros_like(num)
         p[safe] = num[safe] / den[safe]                      # eq. 3
-        score = np.where(safe, p * p * den, 0.0)             # eq. 7
+        score = np.where(safe, _abs2(p) * den, 0.0)          # eq. 7
         top = int(np.argmax(score))
         u = top if forced is None else int(forced[nu])
         c = gamma * p[u]                                     # eq. 8
@@ -160,7 +186,7 @@ def se_original(s: np.ndarray, w: np.ndarray, phi: np.ndarray, gamma: float,
         best[nu] = score[top]
         picked[nu] = score[u]
         second[nu] = _second_best(score, top, classes)
-        energy[nu + 1] = float(np.sum(w * r * r))
+        energy[nu + 1] = float(np.sum(w * _abs2(r)))
     return SEResult(sel, coef, g, best, second, energy, picked=picked)
 
 
@@ -168,15 +194,18 @@ def se_original(s: np.ndarray, w: np.ndarray, phi: np.ndarray, gamma: float,
 # Algorithm 2: table generation
 # ----------------------------------------------------------------------------
 def table_generation(phi: np.ndarray, w: np.ndarray):
-    """C_(k,l) = sum phi_k w phi_l (eq. 16) for l >= k, mirrored to l < k as
-    Algorithm 2 does; D_k = 1/sqrt(C_(k,k)) (eq. 17), 0 for an atom with a
-    zero weighted norm.  One matrix product serves as the summation step."""
-    phi = np.asarray(phi, dtype=np.float64)
+    """C_(k,l) = sum phi_k^* w phi_l (eq. 16) for l >= k, and C_(l,k) its
+    conjugate as Algorithm 2 does; D_k = 1/sqrt(C_(k,k)) (eq. 17), 0 for an
+    atom with a zero weighted norm.  One matrix product serves as the
+    summation step."""
+    phi = _basis(phi)
     w = np.asarray(w, dtype=np.float64)
-    full = (phi * w[None, :]) @ phi.T
+    full = (_conj(phi) * w[None, :]) @ phi.T
     upper = np.triu(full)
-    C = upper + np.triu(full, 1).T
-    diag = np.diag(C).copy()
+    C = upper + _conj(np.triu(full, 1)).T
+    if np.iscomplexobj(C):
+        C[np.diag_indices_from(C)] = C.diagonal().real   # sum of |phi_k|^2 w: real
+    diag = np.diag(C).real.copy()
     D = np.zeros_like(diag)
     pos = diag > 0.0
     D[pos] = 1.0 / np.sqrt(diag[pos])
@@ -194,19 +223,20 @@ def fase(s: np.ndarray, w: np.ndarray, phi: np.ndarray, C: np.ndarray,
     u = argmax |R_k| D_k (eq. 18), c-hat = gamma R_u D_u^2 (eq. 19),
     g += c-hat phi_u (eq. 9), R_k -= c-hat C_(k,u) (eq. 20).
     ``forced`` as in se_original."""
-    s = np.asarray(s, dtype=np.float64)
     w = np.asarray(w, dtype=np.float64)
-    phi = np.asarray(phi, dtype=np.float64)
-    R = np.sum(phi * (s * w)[None, :], axis=1)
+    phi = _basis(phi)
+    cplx = np.iscomplexobj(phi)
+    s = np.asarray(s, dtype=np.complex128 if cplx else np.float64)
+    R = np.sum(_conj(phi) * (s * w)[None, :], axis=1)       # eq. 12
     g = np.zeros_like(s)
     r = s.copy()                          # tracked only for the energy report
     sel = np.zeros(iters, dtype=np.int64)
-    coef = np.zeros(iters)
+    coef = np.zeros(iters, dtype=s.dtype)
     best = np.zeros(iters)
     second = np.zeros(iters)
     picked = np.zeros(iters)
     energy = np.zeros(iters + 1)
-    energy[0] = float(np.sum(w * r * r))
+    energy[0] = float(np.sum(w * _abs2(r)))
     hist = [R.copy()] if keep_R else None
     for nu in range(iters):
         score = np.abs(R) * D
@@ -223,7 +253,7 @@ def fase(s: np.ndarray, w: np.ndarray, phi: np.ndarray, C: np.ndarray,
         best[nu] = score[top] ** 2
         picked[nu] = score[u] ** 2
         second[nu] = _second_best(score, top, classes) ** 2
-        energy[nu + 1] = float(np.sum(w * r * r))
+        energy[nu + 1] = float(np.sum(w * _abs2(r)))
         if keep_R:
             hist.append(R.copy())
     return SEResult(sel, coef, g, best, second, energy, hist, picked)
@@ -267,7 +297,7 @@ def conceal(image: np.ndarray, lost: np.ndarray, blocks: Sequence, phi: np.ndarr
             res = fase(s, w, phi, C, D, gamma, iters, classes)
         else:
             raise ValueError(method)
-        g = res.g.reshape(M, N)[b.ly:b.ly + b.lh, b.lx:b.lx + b.lw]
+        g = res.g.real.reshape(M, N)[b.ly:b.ly + b.lh, b.lx:b.lx + b.lw]
         H, W = image.shape
         for i in range(b.lh):
             for j in range(b.lw):
@@ -286,9 +316,9 @@ def duplicate_classes(phi: np.ndarray, rtol: float = 1e-12) -> np.ndarray:
     the whole area, |<phi_k, phi_l>| >= (1 - rtol) |phi_k| |phi_l|.  The id is
     the lowest index in the class.  Parallel atoms always tie in the selection
     and give the same model, so selections are compared modulo these classes."""
-    phi = np.asarray(phi, dtype=np.float64)
+    phi = _basis(phi)
     norms = np.linalg.norm(phi, axis=1)
-    gram = phi @ phi.T
+    gram = _conj(phi) @ phi.T
     lim = (1.0 - rtol) * np.outer(norms, norms)
     par = (np.abs(gram) >= lim) & (np.outer(norms, norms) > 0)
     K = phi.shape[0]

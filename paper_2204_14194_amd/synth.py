@@ -133,9 +133,40 @@ def gaussian_atoms(M: int, N: int, count: int, seed: int) -> np.ndarray:
     return a / np.linalg.norm(a, axis=1, keepdims=True)
 
 
+def _dft_phase(M: int, N: int):
+    """Phase index q = (mu m N + eta n M) mod MN of the 2-D DFT atom
+    (mu, eta) at pixel (m, n), atom mu*N + eta, pixel m*N + n: the atom is
+    exp(j 2 pi q / MN)."""
+    mu = np.arange(M)[:, None, None, None]
+    eta = np.arange(N)[None, :, None, None]
+    m = np.arange(M)[None, None, :, None]
+    n = np.arange(N)[None, None, None, :]
+    q = (mu * m * N + eta * n * M) % (M * N)
+    return q.reshape(M * N, M * N)
+
+
+def dft2_atoms(M: int, N: int) -> np.ndarray:
+    """Complex 2-D DFT atoms exp(j 2 pi mu m / M) exp(j 2 pi eta n / N)
+    (Section VI), scaled to unit norm over the M x N area; atom mu*N + eta."""
+    q = _dft_phase(M, N)
+    return np.exp(2j * np.pi * q / (M * N)) / np.sqrt(float(M * N))
+
+
+def bdft2_atoms(M: int, N: int) -> np.ndarray:
+    """Binarized 2-D DFT atoms: each of the real and imaginary parts of the
+    DFT atom replaced by its sign (+1 where it is 0), scaled to unit norm.
+    The signs are decided on the integer phase index, so no rounding enters."""
+    q = _dft_phase(M, N)
+    Q = M * N
+    re = np.where((4 * q <= Q) | (4 * q >= 3 * Q), 1.0, -1.0)   # cos >= 0
+    im = np.where(2 * q <= Q, 1.0, -1.0)                         # sin >= 0
+    return (re + 1j * im) / np.sqrt(2.0 * Q)
+
+
 def dictionary(M: int, N: int, parts: Sequence[str], seed: int = 101,
                n_gauss: int = 0) -> np.ndarray:
-    """Union of sub-dictionaries, in the order given: 'dct', 'wht', 'gauss'."""
+    """Union of sub-dictionaries, in the order given: 'dct', 'wht', 'gauss'
+    (real), 'dft', 'bdft' (complex; the union is then complex)."""
     blocks = []
     for p in parts:
         if p == "dct":
@@ -144,6 +175,10 @@ def dictionary(M: int, N: int, parts: Sequence[str], seed: int = 101,
             blocks.append(wht2_atoms(M, N))
         elif p == "gauss":
             blocks.append(gaussian_atoms(M, N, n_gauss, seed))
+        elif p == "dft":
+            blocks.append(dft2_atoms(M, N))
+        elif p == "bdft":
+            blocks.append(bdft2_atoms(M, N))
         else:
             raise ValueError(p)
     return np.ascontiguousarray(np.concatenate(blocks, axis=0))
@@ -163,8 +198,11 @@ def dictionary_parts(M: int, N: int, parts: Sequence[str], n_gauss: int = 0):
 
 
 def round_to_f32(a: np.ndarray) -> np.ndarray:
-    """Round to the nearest float32 and return float64: the exact values a
-    float32 device buffer holds, so both sides start from identical inputs."""
+    """Round to the nearest float32 and return float64 (complex64 ->
+    complex128 for a complex array): the exact values a float32 device buffer
+    holds, so both sides start from identical inputs."""
+    if np.iscomplexobj(a):
+        return np.asarray(a, dtype=np.complex64).astype(np.complex128)
     return np.asarray(a, dtype=np.float32).astype(np.float64)
 
 
@@ -243,6 +281,17 @@ def area32_inputs(n_img: int = 1, seed0: int = 0):
     phi = dictionary(32, 32, ("dct", "wht"))
     return dict(images=imgs, blocks=blocks, phi=phi, M=32, N=32,
                 tx_parts=dictionary_parts(32, 32, ("dct", "wht")),
+                rho_hat=0.8, gamma=0.5, iters=100)
+
+
+def dft32_inputs(n_img: int = 1, seed0: int = 0):
+    """The 32x32-area layout of area32_inputs with the complex dictionary of
+    the paper's Fig. 1 (bottom row): 2-D DFT 32^2 u binarized DFT 32^2
+    (K = 2048); rho_hat = 0.8, gamma = 0.5, I = 100."""
+    imgs = np.stack([synth_image(128, 128, seed0 + i) for i in range(n_img)])
+    blocks = grid_layout(128, 128, 32, 8, n_img)
+    phi = dictionary(32, 32, ("dft", "bdft"))
+    return dict(images=imgs, blocks=blocks, phi=phi, M=32, N=32,
                 rho_hat=0.8, gamma=0.5, iters=100)
 
 

@@ -92,7 +92,9 @@ def oracle_check(images, blocks, phi, M, N, rho_hat, gamma, iters, sel, g, out,
             assert ok.all(), (f"block {i}: iteration {int(np.argmin(ok))} picked an atom "
                               f"outside the near-tie window")
         n = b.lh * b.lw
-        gref = ref.g.reshape(M, N)[b.ly:b.ly + b.lh, b.lx:b.lx + b.lw].reshape(-1)
+        # the model's real part replaces the loss (a complex dictionary gives
+        # a complex model)
+        gref = np.real(ref.g).reshape(M, N)[b.ly:b.ly + b.lh, b.lx:b.lx + b.lw].reshape(-1)
         err = float(np.abs(g[i, :n].astype(np.float64) - gref).max())
         worst = max(worst, err)
         assert err <= tol, f"block {i}: max |g - g_oracle| = {err}"

@@ -430,3 +430,115 @@ def test_weighted_projection_is_transform_of_weighted_signal():
     l = 37
     col = scipy.fft.dctn((w * phi[l]).reshape(M, N), norm="ortho").reshape(-1)
     np.testing.assert_allclose(C[:M * N, l], col, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# complex dictionaries (Section II-III with conjugated atoms; Section VI DFT)
+# ---------------------------------------------------------------------------
+def _complex_case(M, N, K, seed, loss=(2, 2, 2, 3)):
+    phi, s, w = _rng_case(M, N, K, seed, loss=loss)
+    rng = np.random.default_rng(seed + 1)
+    phi = phi + 1j * rng.standard_normal(phi.shape)
+    return phi, s, w
+
+
+def test_complex_dft_unit_weights_are_fft_coefficients():
+    """eq. 12 with the DFT atoms and unit weights is the 2-D DFT of the signal
+    (eq. 22, checked against numpy's FFT), the tables are the identity, and
+    with gamma = 1 Algorithm 1 keeps the I largest DFT coefficients."""
+    M, N = 8, 4
+    rng = np.random.default_rng(21)
+    s2 = rng.uniform(0, 255, (M, N))
+    s = s2.reshape(-1)
+    w = np.ones(M * N)
+    phi = synth.dft2_atoms(M, N)
+    coeffs = np.fft.fft2(s2).reshape(-1) / np.sqrt(M * N)
+    C, D = oracle.table_generation(phi, w)
+    np.testing.assert_allclose(C, np.eye(M * N), atol=1e-12)
+    np.testing.assert_allclose(D, 1.0, atol=1e-12)
+    f = oracle.fase(s, w, phi, C, D, 0.5, 10, keep_R=True)
+    np.testing.assert_allclose(f.R_history[0], coeffs, atol=1e-9)
+    I = 6
+    a = oracle.se_original(s, w, phi, 1.0, I)
+    top = np.argsort(-np.abs(coeffs), kind="stable")[:I]
+    assert set(a.sel.tolist()) == set(top.tolist())
+    keep = np.zeros_like(coeffs)
+    keep[top] = coeffs[top]
+    g_ref = np.fft.ifft2(keep.reshape(M, N) * np.sqrt(M * N)).reshape(-1)
+    np.testing.assert_allclose(a.g, g_ref, atol=1e-9)
+
+
+def test_complex_fase_equals_se():
+    """The paper's central claim for complex atoms: Algorithm 3 selects the
+    same atoms as Algorithm 1 and yields the same (complex) model."""
+    phi, s, w = _complex_case(6, 7, 70, seed=31)
+    gamma, iters = 0.5, 40
+    a = oracle.se_original(s, w, phi, gamma, iters)
+    C, D = oracle.table_generation(phi, w)
+    f = oracle.fase(s, w, phi, C, D, gamma, iters)
+    np.testing.assert_array_equal(a.sel, f.sel)
+    np.testing.assert_allclose(a.coef, f.coef, rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(a.g, f.g, atol=1e-8)
+    assert np.abs(a.g.imag).max() > 1e-3          # the model really is complex
+
+
+def test_complex_tables_hermitian_and_bruteforce():
+    phi, _, w = _complex_case(5, 4, 12, seed=41)
+    C, D = oracle.table_generation(phi, w)
+    np.testing.assert_array_equal(C, np.conj(C).T)              # Algorithm 2 mirror
+    assert np.all(C.diagonal().imag == 0) and np.all(C.diagonal().real > 0)
+    for k, l in ((0, 0), (1, 7), (7, 1), (11, 3)):
+        ref = sum(np.conj(phi[k, p]) * w[p] * phi[l, p] for p in range(20))
+        assert C[k, l] == pytest.approx(ref, rel=1e-12, abs=1e-12)
+    np.testing.assert_allclose(D, 1.0 / np.sqrt((np.abs(phi) ** 2 * w).sum(axis=1)),
+                               rtol=1e-12)
+
+
+@pytest.mark.parametrize("gamma", [0.5, 1.0])
+def test_complex_energy_decrement(gamma):
+    """sum w |r|^2 drops by gamma (2 - gamma) |p_u|^2 C_uu per iteration, and
+    that atom gives the smallest weighted distance (eq. 6) by trial."""
+    phi, s, w = _complex_case(6, 5, 40, seed=51)
+    a = oracle.se_original(s, w, phi, gamma, 20)
+    dec = a.energy[:-1] - a.energy[1:]
+    np.testing.assert_allclose(dec, gamma * (2 - gamma) * a.best, rtol=1e-9)
+    r = s.astype(np.complex128)
+    for nu in range(4):
+        trial = []
+        for k in range(phi.shape[0]):
+            den = np.sum(np.conj(phi[k]) * w * phi[k]).real
+            p = np.sum(r * np.conj(phi[k]) * w) / den
+            rr = r - gamma * p * phi[k]
+            trial.append(np.sum(w * np.abs(rr) ** 2))
+        assert int(np.argmin(trial)) == a.sel[nu]
+        r = r - a.coef[nu] * phi[a.sel[nu]]
+
+
+def test_real_dictionary_as_complex_is_the_real_path():
+    """A real dictionary given as complex numbers: the conjugations drop out
+    and the results equal the real-valued path's."""
+    phi, s, w = _rng_case(6, 6, 50, seed=61, loss=(2, 2, 2, 2))
+    C, D = oracle.table_generation(phi, w)
+    Cc, Dc = oracle.table_generation(phi.astype(np.complex128), w)
+    np.testing.assert_allclose(Cc, C, atol=1e-12)
+    f = oracle.fase(s, w, phi, C, D, 0.5, 30)
+    fc = oracle.fase(s, w, phi.astype(np.complex128), Cc, Dc, 0.5, 30)
+    np.testing.assert_array_equal(f.sel, fc.sel)
+    np.testing.assert_allclose(fc.g.real, f.g, atol=1e-9)
+    np.testing.assert_allclose(fc.g.imag, 0.0, atol=1e-9)
+
+
+def test_binarized_dft_atoms():
+    """The binarized DFT atoms: unit norm, entries (+-1 +- j)/sqrt(2MN) with
+    the signs of the DFT atom's real and imaginary parts (0 counts as +)."""
+    M, N = 8, 8
+    b = synth.bdft2_atoms(M, N)
+    d = synth.dft2_atoms(M, N)
+    np.testing.assert_allclose(np.linalg.norm(b, axis=1), 1.0, atol=1e-12)
+    scale = np.sqrt(2.0 * M * N)
+    np.testing.assert_allclose(np.abs(b.real) * scale, 1.0)
+    np.testing.assert_allclose(np.abs(b.imag) * scale, 1.0)
+    ok_re = (d.real > 1e-9) <= (b.real > 0)
+    ok_im = (d.imag > 1e-9) <= (b.imag > 0)
+    assert ok_re.all() and ok_im.all()
+    assert ((d.real < -1e-9) <= (b.real < 0)).all() and ((d.imag < -1e-9) <= (b.imag < 0)).all()
