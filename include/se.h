@@ -84,12 +84,19 @@ typedef struct {
 
 /* A dictionary (Section II: phi_k[m, n], k in the dictionary D).
  * phi: device, K x (M*N) float32, row-major.  n_parts (0..2) declared
- * transform ranges, non-overlapping; every other atom is dense. */
+ * transform ranges, non-overlapping; every other atom is dense.
+ * phi_im: NULL for a real dictionary; for a complex one (the paper's general
+ * case, e.g. 2-D DFT atoms) the imaginary parts, device K x (M*N) float32,
+ * with phi holding the real parts.  Complex dictionaries take FP32 tables,
+ * declare no transform parts, and are concealed by the batched calls
+ * (se_extrapolate_batch, se_project/se_iterate, se_extrapolate_device);
+ * the other calls refuse them (SE_EINVAL). */
 typedef struct {
   int32_t M, N, K;
   const float* phi;
   int32_t n_parts;
   se_part parts[2];
+  const float* phi_im;
 } se_basis;
 
 /* One lost block and its extrapolation area L = A u B (Section II, Fig. 2).
@@ -133,7 +140,15 @@ typedef struct {
  *          matrix cores read them).  Unused without parts (may be NULL).
  *   Yhi, Ylo : K x (M*N) bfloat16 bit patterns, Y = Yhi + Ylo (hi = bf16(Y),
  *          lo = bf16(Y - hi)); required (non-NULL) for SE_BF16X3, unused
- *          for SE_FP32.                                                   */
+ *          for SE_FP32.
+ * A complex dictionary (se_basis.phi_im) makes the tables complex:
+ *   G, G_im : real and imaginary parts of the Hermitian D C D (eq. 16 with
+ *          the conjugated atom, Algorithm 2's mirror C_(l,k) = conj C_(k,l));
+ *          G_im K x ldG float32, 16-byte aligned, columns K .. ldG-1 0.
+ *   Y    : 2K x (M*N): rows 0..K-1 the real and rows K..2K-1 the imaginary
+ *          parts of D_k sqrt(w) conj(phi_k), so eq. 12 is Y (sqrt(w) s).
+ *   phi_im : copied from the dictionary.
+ * For a real dictionary G_im and phi_im are NULL (G_im is not written). */
 typedef struct {
   int32_t M, N, K, ldG;
   float* G;
@@ -148,6 +163,8 @@ typedef struct {
   int32_t n_parts;       /* copied from the dictionary by se_weighted_gram */
   se_part parts[2];
   float* tx;
+  float* G_im;
+  const float* phi_im;   /* copied from the dictionary by se_weighted_gram */
 } se_tables;
 
 /* Model-generation parameters: gamma of eq. 8 (0 < gamma <= 1) and the
@@ -249,7 +266,8 @@ se_status se_weighted_gram(const se_basis* b, const float* w,
  *   sel     : optional device int32 n_blk x iters, selected atom per
  *             iteration (NULL to skip)
  *   coef    : optional device float32 n_blk x iters, coefficient c per
- *             iteration (NULL to skip)
+ *             iteration (NULL to skip); for complex tables n_blk x iters
+ *             pairs (real, imaginary part)
  *   g_loss  : optional device float32 n_blk x g_loss_ld, the model over the
  *             loss before rounding, row-major lh x lw (NULL to skip)
  *   ws      : device scratch of se_extrapolate_batch_ws_bytes() bytes
@@ -277,6 +295,9 @@ se_status se_extrapolate_batch(const se_tables* t, uint8_t* images,
  *   the matrix cores (FP32, or split BF16 when t->precision is SE_BF16X3);
  *   columns K .. ldR-1 are written as 0.  ldR >=
  *   se_table_ld(K).  ws: se_project_ws_bytes(t, n_blk) bytes.
+ *   For complex tables a row of R holds the real parts at [0, ldR/2) and
+ *   the imaginary parts at [ldR/2, ldR); ldR >= 2 se_table_ld(K), a
+ *   multiple of 8.
  * se_iterate: the iteration loop (eq. 18, 19, 9, 20) from R and the
  *   replacement of every loss in `images`; R is read only.  Outputs as for
  *   se_extrapolate_batch; g_loss rows hold g_loss_ld values (a longer loss

@@ -45,7 +45,7 @@ class se_part(C.Structure):
 
 class se_basis(C.Structure):
     _fields_ = [("M", C.c_int32), ("N", C.c_int32), ("K", C.c_int32), ("phi", C.c_void_p),
-                ("n_parts", C.c_int32), ("parts", se_part * 2)]
+                ("n_parts", C.c_int32), ("parts", se_part * 2), ("phi_im", C.c_void_p)]
 
 
 _PART_NAMES = {"dct": SE_PART_DCT2, "wht": SE_PART_WHT2}
@@ -66,11 +66,12 @@ def _part_array(parts):
     return arr
 
 
-def make_basis(M: int, N: int, K: int, phi_ptr, parts=()) -> se_basis:
+def make_basis(M: int, N: int, K: int, phi_ptr, parts=(), phi_im_ptr=None) -> se_basis:
     """se_basis for a dictionary at device address ``phi_ptr``; ``parts`` is a
-    sequence of (SE_PART_*, first atom) transform ranges."""
+    sequence of (SE_PART_*, first atom) transform ranges; ``phi_im_ptr`` the
+    imaginary parts of a complex dictionary (None for a real one)."""
     parts = _parts_arg(parts)
-    return se_basis(M, N, K, phi_ptr, len(parts), _part_array(parts))
+    return se_basis(M, N, K, phi_ptr, len(parts), _part_array(parts), phi_im_ptr)
 
 
 class se_block(C.Structure):
@@ -82,7 +83,8 @@ class se_tables(C.Structure):
                 ("G", C.c_void_p), ("D", C.c_void_p), ("Y", C.c_void_p),
                 ("sqrtw", C.c_void_p), ("phi", C.c_void_p), ("info", C.c_void_p),
                 ("precision", C.c_int32), ("Yhi", C.c_void_p), ("Ylo", C.c_void_p),
-                ("n_parts", C.c_int32), ("parts", se_part * 2), ("tx", C.c_void_p)]
+                ("n_parts", C.c_int32), ("parts", se_part * 2), ("tx", C.c_void_p),
+                ("G_im", C.c_void_p), ("phi_im", C.c_void_p)]
 
 
 class se_params(C.Structure):
@@ -231,6 +233,18 @@ class Tables:
     Ylo: Optional[torch.Tensor] = None
     parts: tuple = ()
     tx: Optional[torch.Tensor] = None
+    G_im: Optional[torch.Tensor] = None
+    phi_im: Optional[torch.Tensor] = None
+
+    @property
+    def complex(self) -> bool:
+        return self.phi_im is not None
+
+    @property
+    def ldR(self) -> int:
+        """Row length of R (real parts, then imaginary parts for a complex
+        dictionary)."""
+        return (2 if self.complex else 1) * self.ldG
 
     def struct(self) -> se_tables:
         return se_tables(self.M, self.N, self.K, self.ldG, self.G.data_ptr(), self.D.data_ptr(),
@@ -239,34 +253,46 @@ class Tables:
                          self.Yhi.data_ptr() if self.Yhi is not None else None,
                          self.Ylo.data_ptr() if self.Ylo is not None else None,
                          len(self.parts), _part_array(self.parts),
-                         self.tx.data_ptr() if self.tx is not None else None)
+                         self.tx.data_ptr() if self.tx is not None else None,
+                         self.G_im.data_ptr() if self.G_im is not None else None,
+                         self.phi_im.data_ptr() if self.phi_im is not None else None)
 
     def nbytes(self) -> int:
         parts = [self.G, self.D, self.Y, self.sqrtw]
-        parts += [x for x in (self.Yhi, self.Ylo) if x is not None]
+        parts += [x for x in (self.Yhi, self.Ylo, self.G_im) if x is not None]
         return sum(t.numel() * t.element_size() for t in parts)
 
 
 def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
                   precision: int = SE_FP32, flags: int = SE_DIAG_AUTO, stream=None,
-                  parts=()) -> Tables:
+                  parts=(), phi_im: Optional[torch.Tensor] = None) -> Tables:
     """se_weighted_gram (Algorithm 2) for dictionary ``phi`` (K, M*N) and weight
     pattern ``w`` (M*N,).  ``parts``: declared transform ranges, as
-    (SE_PART_*, first atom) pairs (verified by the library)."""
+    (SE_PART_*, first atom) pairs (verified by the library).  ``phi_im``: the
+    imaginary parts of a complex dictionary (``phi`` then holds the real
+    parts); the tables are then complex (G, G_im)."""
     L = lib()
     _dev_f32(phi, "phi")
     _dev_f32(w, "w")
     K = phi.shape[0]
     if phi.shape[1] != M * N or w.numel() != M * N:
         raise ValueError("phi must be (K, M*N) and w (M*N,)")
+    if phi_im is not None:
+        _dev_f32(phi_im, "phi_im")
+        if tuple(phi_im.shape) != tuple(phi.shape):
+            raise ValueError("phi_im must have the shape of phi")
     ldG = table_ld(K)
     dev = phi.device
+    y_rows = 2 * K if phi_im is not None else K
     t = Tables(M, N, K, ldG,
                torch.empty((K, ldG), dtype=torch.float32, device=dev),
                torch.empty(K, dtype=torch.float32, device=dev),
-               torch.empty((K, M * N), dtype=torch.float32, device=dev),
+               torch.empty((y_rows, M * N), dtype=torch.float32, device=dev),
                torch.empty(M * N, dtype=torch.float32, device=dev),
                phi, torch.zeros(1, dtype=torch.int32, device=dev), int(precision))
+    if phi_im is not None:
+        t.phi_im = phi_im
+        t.G_im = torch.empty((K, ldG), dtype=torch.float32, device=dev)
     if precision == SE_BF16X3:
         t.Yhi = torch.empty((K, M * N), dtype=torch.int16, device=dev)
         t.Ylo = torch.empty((K, M * N), dtype=torch.int16, device=dev)
@@ -276,7 +302,8 @@ def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
         if nb_tx == 0:
             raise ValueError(f"no transform parts for a {M}x{N} area")
         t.tx = torch.empty(nb_tx // 4, dtype=torch.float32, device=dev)
-    b = make_basis(M, N, K, phi.data_ptr(), t.parts)
+    b = make_basis(M, N, K, phi.data_ptr(), t.parts,
+                   phi_im.data_ptr() if phi_im is not None else None)
     nb = L.se_weighted_gram_ws_bytes(C.byref(b), int(precision))
     ws = _workspace(nb, dev)
     st = t.struct()
@@ -301,7 +328,9 @@ def _extrapolate(name: str, t: Tables, images: torch.Tensor, blocks: Sequence, g
     n = len(blocks)
     dev = images.device
     sel = torch.empty((n, iters), dtype=torch.int32, device=dev) if want_sel else None
-    coef = torch.empty((n, iters), dtype=torch.float32, device=dev) if want_coef else None
+    # complex tables: (real, imaginary) pairs per iteration
+    coef = (torch.empty((n, iters * (2 if t.complex else 1)), dtype=torch.float32, device=dev)
+            if want_coef else None)
     gld = max([b.lh * b.lw for b in blocks] + [1])
     g = torch.zeros((n, gld), dtype=torch.float32, device=dev) if want_g else None
     st = t.struct()

@@ -21,7 +21,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = [
     "abi.cpp", "weights.hip", "gram.hip", "gemm.hip", "gemm_bf16x3.hip", "project.hip",
-    "greedy.hip", "ondemand.hip", "transform.hip", "fused.hip", "serve.cpp", "tune.cpp",
+    "greedy.hip", "ondemand.hip", "transform.hip", "fused.hip", "complex.hip", "serve.cpp", "tune.cpp",
 ]
 
 FLAGS = [
@@ -37,7 +37,8 @@ FLAGS = [
 # (uint8 pixels, finite atoms and tables), so its float maxima need no NaN
 # quieting: without it each |R| maximum is one v_max3 instead of a
 # canonicalise-and-max sequence.
-SOURCE_FLAGS = {"greedy.hip": ["-fno-honor-nans"], "fused.hip": ["-fno-honor-nans"]}
+SOURCE_FLAGS = {"greedy.hip": ["-fno-honor-nans"], "fused.hip": ["-fno-honor-nans"],
+                "complex.hip": ["-fno-honor-nans"]}
 
 
 def _compile(src: str) -> str:

@@ -91,6 +91,27 @@ static se_status check_tables(const se_tables* t) {
   if (st) return st;
   if (t->n_parts > 0 && (!t->tx || reinterpret_cast<uintptr_t>(t->tx) % 16))
     return fail(SE_EINVAL, "tables with transform parts need a 16-byte aligned tx buffer");
+  if (t->phi_im) {
+    if (t->precision != SE_FP32) return fail(SE_EINVAL, "complex dictionaries take FP32 tables");
+    if (t->n_parts != 0) return fail(SE_EINVAL, "complex dictionaries declare no transform parts");
+    if (!t->G_im || reinterpret_cast<uintptr_t>(t->G_im) % 16)
+      return fail(SE_EINVAL, "complex tables need a 16-byte aligned G_im");
+    if (!complex_loop_for(t->K)) return fail(SE_EINVAL, "no complex loop shape for K=%d", t->K);
+  }
+  return SE_OK;
+}
+
+// Row length of R for the tables: real parts, and for a complex dictionary
+// the imaginary parts after them.
+static int r_row_len(const se_tables* t) {
+  return (t->phi_im ? 2 : 1) * greedy_row_len(t->K);
+}
+
+static se_status check_r(const se_tables* t, const float* R, int ldR) {
+  const int need = r_row_len(t), mult = t->phi_im ? 8 : 4;
+  if (!R || ldR < need || ldR % mult || reinterpret_cast<uintptr_t>(R) % 16)
+    return fail(SE_EINVAL, "R must be 16-byte aligned with ldR >= %d, a multiple of %d", need,
+                mult);
   return SE_OK;
 }
 
@@ -193,6 +214,18 @@ static se_status project_into(const se_tables* t, const uint8_t* images, int H, 
   float* split = cv.take<float>(split_floats);
   launch_gather(images, H, W, dblk, n_blk, t->M, t->N, t->sqrtw, X, ldX, s);
   if ((st = check_launch("gather"))) return st;
+  if (t->phi_im) {
+    // complex dictionary: real and imaginary parts of eq. 12 from the two
+    // halves of Y, into the two halves of each row of R
+    const int K = t->K, half = ldR / 2;
+    for (int part = 0; part < 2; ++part)
+      if ((st = gemm_project_f32(t->Y + (size_t)part * K * P, P, K, X, ldX, n_blk, P,
+                                 R + part * half, ldR, 0, s, false, split, split_floats)))
+        return st;
+    launch_zero_range(R, n_blk, ldR, K, half, s);
+    launch_zero_range(R, n_blk, ldR, half + K, ldR, s);
+    return check_launch("zero_range");
+  }
   const int tile = tune_lookup(t->K, P, n_blk).proj_tile;
   for (int r = 0; r < nr; ++r)
     if ((st = gemm_project_f32(t->Y + (size_t)lo[r] * P, P, hi[r] - lo[r], X, ldX, n_blk, P,
@@ -270,6 +303,7 @@ size_t se_weighted_gram_ws_bytes(const se_basis* b, se_precision prec) {
   cv.take<float>(K);
   cv.take<double>(K);
   cv.take<int32_t>(1);
+  if (b->phi_im) cv.take<float>(2 * K * (size_t)round4(2 * b->K));   // the stacked product
   return cv.off + 256;
 }
 
@@ -288,6 +322,7 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
   t->precision = (int32_t)prec;
   t->n_parts = b->n_parts;
   for (int q = 0; q < 2; ++q) t->parts[q] = q < b->n_parts ? b->parts[q] : se_part{0, 0};
+  t->phi_im = b->phi_im;
   se_status st = check_tables(t);
   if (st) return st;
   if (!ws || ws_bytes < se_weighted_gram_ws_bytes(b, prec)) return fail(SE_ENOMEM, "workspace too small");
@@ -303,11 +338,27 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
     t->n_parts = 0;
     return st;
   }
-  launch_diag(b->phi, w, K, P, diag32, diag64, s);
+  launch_diag(b->phi, b->phi_im, w, K, P, diag32, diag64, s);
   if ((st = check_launch("diag"))) return st;
   launch_finalize_d(diag32, diag64, w, K, P, (int)flags, prec == SE_BF16X3 ? 1 : 0, t->D, t->sqrtw,
                     t->info, s);
   if ((st = check_launch("finalize_d"))) return st;
+  if (b->phi_im) {
+    // complex dictionary: Y = D sqrt(w) conj(phi) as stacked real and
+    // imaginary rows; G = Y Y^H from their symmetric product (Algorithm 2's
+    // Hermitian mirror is exact: Re G symmetric, Im G antisymmetric)
+    launch_scale_y(b->phi, t->D, t->sqrtw, K, P, t->Y, s);
+    launch_scale_y(b->phi_im, t->D, t->sqrtw, K, P, t->Y + (size_t)K * P, s, true);
+    if ((st = check_launch("scale_y"))) return st;
+    launch_zero_cols(t->G, K, K, t->ldG, s);
+    launch_zero_cols(t->G_im, K, K, t->ldG, s);
+    if ((st = check_launch("zero_cols"))) return st;
+    const int ldS = round4(2 * K);
+    float* S = cv.take<float>((size_t)2 * K * ldS);
+    if ((st = gemm_syrk_f32(t->Y, P, 2 * K, P, S, ldS, s))) return st;
+    launch_combine_c(S, ldS, K, t->G, t->G_im, t->ldG, s);
+    return check_launch("combine_c");
+  }
   launch_scale_y(b->phi, t->D, t->sqrtw, K, P, t->Y, s);
   if ((st = check_launch("scale_y"))) return st;
   if (t->n_parts > 0 && (st = build_tx(t, s))) return st;
@@ -379,9 +430,7 @@ se_status se_project(const se_tables* t, const uint8_t* images, int32_t n_img, i
   se_status st = check_common(t, n_img, H, W, n_blk, images, dev_blocks);
   if (st) return st;
   if (n_blk == 0) return SE_OK;
-  if (!R || ldR < greedy_row_len(t->K) || (ldR & 3) || reinterpret_cast<uintptr_t>(R) % 16)
-    return fail(SE_EINVAL, "R must be 16-byte aligned with ldR >= se_table_ld(K)=%d, a multiple of 4",
-                greedy_row_len(t->K));
+  if ((st = check_r(t, R, ldR))) return st;
   if (!ws || ws_bytes < se_project_ws_bytes(t, n_blk)) return fail(SE_ENOMEM, "workspace too small");
   return project_into(t, images, H, W, dev_blocks, n_blk, R, ldR, ws,
                       static_cast<hipStream_t>(stream));
@@ -415,6 +464,13 @@ static GreedyArgs greedy_args(const se_tables* t, const float* R, int ldR, uint8
   return ga;
 }
 
+// the loop for the tables' kind: real (the tuned or default shape) or complex
+static se_status launch_loop(const se_tables* t, const GreedyArgs& ga, int n_blk, hipStream_t s,
+                             const TuneChoice& tc) {
+  if (t->phi_im) return launch_greedy_c(ga, t->G_im, t->phi_im, n_blk, s);
+  return launch_greedy(ga, n_blk, s, tc.loop_waves, tc.loop_vpl);
+}
+
 static se_status check_params(se_params prm, const float* g_loss, int g_loss_ld) {
   if (!(prm.gamma > 0.0f && prm.gamma <= 1.0f)) return fail(SE_EINVAL, "gamma must lie in (0, 1]");
   if (prm.iters < 0) return fail(SE_EINVAL, "iters < 0");
@@ -431,20 +487,18 @@ se_status se_iterate(const se_tables* t, const float* R, int32_t ldR, uint8_t* i
   if (st) return st;
   if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
   if (n_blk == 0) return SE_OK;
-  if (!R || ldR < greedy_row_len(t->K) || (ldR & 3) || reinterpret_cast<uintptr_t>(R) % 16)
-    return fail(SE_EINVAL, "R must be 16-byte aligned with ldR >= se_table_ld(K)=%d, a multiple of 4",
-                greedy_row_len(t->K));
+  if ((st = check_r(t, R, ldR))) return st;
   GreedyArgs ga = greedy_args(t, R, ldR, images, H, W, dev_blocks, n_blk, prm, sel, coef, g_loss,
                               g_loss_ld);
   const TuneChoice tc = tune_lookup(t->K, t->M * t->N, n_blk);
-  return launch_greedy(ga, n_blk, static_cast<hipStream_t>(stream), tc.loop_waves, tc.loop_vpl);
+  return launch_loop(t, ga, n_blk, static_cast<hipStream_t>(stream), tc);
 }
 
 size_t se_extrapolate_device_ws_bytes(const se_tables* t, int32_t n_blk) {
   if (!t || t->K < 1 || t->M < 1 || t->N < 1 || n_blk < 0) return 0;
   if (conceal_tx_supported(t)) return 0;
   Carver cv(nullptr);
-  cv.take<float>((size_t)n_blk * greedy_row_len(t->K));
+  cv.take<float>((size_t)n_blk * r_row_len(t));
   cv.take<char>(project_ws(t, n_blk));
   return cv.off + 256;
 }
@@ -459,7 +513,7 @@ se_status se_extrapolate_device(const se_tables* t, uint8_t* images, int32_t n_i
   if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
   if (n_blk == 0) return SE_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int ldR = greedy_row_len(t->K);
+  const int ldR = r_row_len(t);
   const TuneChoice tc = tune_lookup(t->K, t->M * t->N, n_blk);
   if (conceal_tx_supported(t)) {
     const GreedyArgs ga = greedy_args(t, nullptr, ldR, images, H, W, dev_blocks, n_blk, prm, sel,
@@ -474,14 +528,14 @@ se_status se_extrapolate_device(const se_tables* t, uint8_t* images, int32_t n_i
   if ((st = project_into(t, images, H, W, dev_blocks, n_blk, R, ldR, pws, s))) return st;
   const GreedyArgs ga = greedy_args(t, R, ldR, images, H, W, dev_blocks, n_blk, prm, sel, coef,
                                     g_loss, g_loss_ld);
-  return launch_greedy(ga, n_blk, s, tc.loop_waves, tc.loop_vpl);
+  return launch_loop(t, ga, n_blk, s, tc);
 }
 
 size_t se_extrapolate_batch_ws_bytes(const se_tables* t, int32_t n_blk) {
   if (!t || t->K < 1 || t->M < 1 || t->N < 1 || n_blk < 0) return 0;
   Carver cv(nullptr);
   cv.take<se_block>((size_t)n_blk);
-  cv.take<float>((size_t)n_blk * greedy_row_len(t->K));
+  cv.take<float>((size_t)n_blk * r_row_len(t));
   cv.take<char>(project_ws(t, n_blk > 0 ? n_blk : 0));
   return cv.off + 256;
 }
@@ -496,11 +550,12 @@ static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, in
   if (!images) return fail(SE_EINVAL, "images is NULL");
   if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
   if ((st = check_blocks(t, n_img, H, W, blocks, n_blk, g_loss_ld, g_loss))) return st;
+  if (plain && t->phi_im) return fail(SE_EINVAL, "the per-block form takes real dictionaries");
   if (n_blk == 0) return SE_OK;
   const size_t need = se_extrapolate_batch_ws_bytes(t, n_blk);
   if (!ws || ws_bytes < need) return fail(SE_ENOMEM, "workspace too small: need %zu bytes", need);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int P = t->M * t->N, ldR = greedy_row_len(t->K);
+  const int P = t->M * t->N, ldR = r_row_len(t);
   Carver cv(ws);
   se_block* dblk = cv.take<se_block>((size_t)n_blk);
   float* R = cv.take<float>((size_t)n_blk * ldR);
@@ -513,7 +568,7 @@ static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, in
     if (conceal_tx_supported(t))   // projections inside the loop's workgroups
       return conceal_tx(t, ga, images, H, W, n_blk, s, tc.loop_waves, tc.loop_vpl);
     if ((st = project_into(t, images, H, W, dblk, n_blk, R, ldR, pws, s))) return st;
-    return launch_greedy(ga, n_blk, s, tc.loop_waves, tc.loop_vpl);
+    return launch_loop(t, ga, n_blk, s, tc);
   }
   // one block at a time: gather, matrix-vector product (FP32), single-workgroup loop
   float* X = reinterpret_cast<float*>(pws);
@@ -572,6 +627,7 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* im
                                   int32_t* sel, float* coef, float* g_loss, int32_t g_loss_ld,
                                   void* ws, size_t ws_bytes, void* stream) {
   g_err[0] = 0;
+  if (b && b->phi_im) return fail(SE_EINVAL, "rows on demand take real dictionaries");
   if (!b || !b->phi || !w || !images) return fail(SE_EINVAL, "NULL argument");
   if (b->M < 1 || b->N < 1 || b->K < 1) return fail(SE_EINVAL, "bad basis shape");
   if (b->K > 32768) return fail(SE_EINVAL, "K=%d exceeds 32768", b->K);

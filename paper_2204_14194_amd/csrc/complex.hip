@@ -1,0 +1,234 @@
+// Algorithm 3 for a complex dictionary (the paper's general case, Sections
+// II-III): R, the table G = D C D (Hermitian) and the coefficients are
+// complex; the image is real and the real part of the model replaces the
+// loss.  With the unit-diagonal table, per iteration
+//   u  = argmax_k |R~_k|                        (eq. 18)
+//   c  = gamma R~_u D_u                         (eq. 19)
+//   R~_k -= gamma R~_u G[k][u],  G[k][u] = conj(G[u][k])   (eq. 20)
+//   g  += c phi_u over the loss (real part)     (eq. 9)
+// One workgroup per block.  Lane t holds atoms 4 (j T + t) + e as in the
+// real loop, with separate real and imaginary registers; the rows of Re G
+// and Im G are streamed as float4 sweeps.  The selection compares |R~|^2
+// (same order as |R~|): each lane finds its first maximum in index order,
+// the wave and the workgroup reduce 64-bit (|R~|^2, lowest index) keys, and
+// the winner's complex value travels with its key.
+#include "argmax.h"
+#include "se_internal.h"
+
+namespace sefase {
+
+constexpr int kCQPL = 4;   // loss pixels per lane (the loss may hold <= 4 T pixels)
+
+struct CplxArgs {
+  const float* G_im;     // K x ldG, Im G
+  const float* phi_im;   // K x M*N, Im phi
+};
+
+template <int WAVES, int VPL>
+__global__ __launch_bounds__(64 * WAVES) void k_greedy_c(GreedyArgs a, CplxArgs x) {
+  constexpr int T = 64 * WAVES;
+  constexpr int NJ = VPL / 4;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int b = blockIdx.x;
+  const DevBlock d = a.blk[b];
+  const int K = a.K, P = a.M * a.N;
+  const int L = a.ldR / 2;   // R row: real parts at [0, L), imaginary at [L, 2 L)
+
+  float Rr[NJ][4], Ri[NJ][4];
+  {
+    const float* src = a.R0 + (size_t)b * a.ldR;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const float4 v = *reinterpret_cast<const float4*>(src + 4 * (j * T + t));
+      const float4 u = *reinterpret_cast<const float4*>(src + L + 4 * (j * T + t));
+      Rr[j][0] = v.x; Rr[j][1] = v.y; Rr[j][2] = v.z; Rr[j][3] = v.w;
+      Ri[j][0] = u.x; Ri[j][1] = u.y; Ri[j][2] = u.z; Ri[j][3] = u.w;
+    }
+  }
+
+  // loss pixels owned by this lane (lanes past the end repeat the last one)
+  const int nloss = d.lh * d.lw;
+  const int nq = (nloss + T - 1) / T;
+  int poff[kCQPL];
+  float g[kCQPL], gc[kCQPL];
+#pragma unroll
+  for (int q = 0; q < kCQPL; ++q) {
+    int i = t + q * T;
+    i = i < nloss ? i : nloss - 1;
+    const int my = i / d.lw, mx = i - my * d.lw;
+    poff[q] = (d.ly + my) * a.N + d.lx + mx;
+    g[q] = 0.0f;
+    gc[q] = 0.0f;
+  }
+
+  __shared__ uint64_t s_key[2][WAVES];
+  __shared__ float s_val[2][WAVES][2];
+  int par = 0;
+  const float gamma = a.gamma;
+
+  for (int it = 0; it < a.iters; ++it) {
+    // ---- this lane's first largest |R~|^2, then the wave's and the group's --
+    float bm = 0.0f, bre = 0.0f, bim = 0.0f;
+    int bc = 0;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float m2 = fmaf(Rr[j][e], Rr[j][e], Ri[j][e] * Ri[j][e]);
+        if (m2 > bm) {
+          bm = m2;
+          bre = Rr[j][e];
+          bim = Ri[j][e];
+          bc = 4 * j + e;
+        }
+      }
+    const uint64_t mine = make_key(bm, 4 * ((bc >> 2) * T + t) + (bc & 3));
+    uint64_t key = wave_max_key((uint32_t)(mine >> 32), (uint32_t)mine);
+    // the owner of the wave's winner holds its complex value (an all-zero
+    // key decodes to atom 0 of lane 0, whose best value is then 0)
+    const int kw = 0xFFFF - (int)((uint32_t)key >> 16);
+    const int owner = ((kw >> 2) % T) & 63;
+    float vre = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bre), owner));
+    float vim = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bim), owner));
+    if (WAVES > 1) {
+      if (lane == 0) {
+        s_key[par][wave] = key;
+        s_val[par][wave][0] = vre;
+        s_val[par][wave][1] = vim;
+      }
+      __syncthreads();
+      int win = 0;
+      key = s_key[par][0];
+#pragma unroll
+      for (int w = 1; w < WAVES; ++w) {
+        const uint64_t o = s_key[par][w];
+        if (o > key) {
+          key = o;
+          win = w;
+        }
+      }
+      vre = s_val[par][win][0];
+      vim = s_val[par][win][1];
+      par ^= 1;
+    }
+    int u;
+    float mag2;
+    decode_key(key, K, u, mag2);
+    if (mag2 == 0.0f) {
+      vre = 0.0f;
+      vim = 0.0f;
+    }
+    u = __builtin_amdgcn_readfirstlane(u);
+    const float tr = gamma * __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(vre)));
+    const float ti = gamma * __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(vim)));
+
+    // ---- rows u of Re G and Im G, the atom over the loss ---------------------
+    const float* pr = a.phi + (size_t)u * P;
+    const float* pi = x.phi_im + (size_t)u * P;
+    float pvr[kCQPL], pvi[kCQPL];
+#pragma unroll
+    for (int q = 0; q < kCQPL; ++q)
+      if (q < nq) {
+        pvr[q] = pr[poff[q]];
+        pvi[q] = pi[poff[q]];
+      }
+    const float* gr = a.G + (size_t)u * a.ldG;
+    const float* gi = x.G_im + (size_t)u * a.ldG;
+    float4 rr[NJ], ri[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      rr[j] = *reinterpret_cast<const float4*>(gr + 4 * (j * T + t));
+      ri[j] = *reinterpret_cast<const float4*>(gi + 4 * (j * T + t));
+    }
+    const float Du = a.D[u];
+    const float cr = tr * Du, ci = ti * Du;      // eq. 19
+    if (t == 0) {
+      if (a.sel) a.sel[(size_t)b * a.iters + it] = u;
+      if (a.coef) {
+        a.coef[((size_t)b * a.iters + it) * 2] = cr;
+        a.coef[((size_t)b * a.iters + it) * 2 + 1] = ci;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kCQPL; ++q)
+      if (q < nq) {                              // eq. 9, real part, compensated
+        const float y = fmaf(cr, pvr[q], -fmaf(ci, pvi[q], gc[q]));
+        const float s = g[q] + y;
+        gc[q] = (s - g[q]) - y;
+        g[q] = s;
+        asm volatile("" ::: "memory");
+      }
+
+    // ---- eq. 20: R~_k -= (tr + j ti) (Re G[u][k] - j Im G[u][k]) --------------
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const float xr[4] = {rr[j].x, rr[j].y, rr[j].z, rr[j].w};
+      const float xi[4] = {ri[j].x, ri[j].y, ri[j].z, ri[j].w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        Rr[j][e] = fmaf(-ti, xi[e], fmaf(-tr, xr[e], Rr[j][e]));
+        Ri[j][e] = fmaf(tr, xi[e], fmaf(-ti, xr[e], Ri[j][e]));
+      }
+    }
+  }
+
+  // ---- replace the loss by the model's real part ------------------------------
+#pragma unroll
+  for (int q = 0; q < kCQPL; ++q) {
+    const int i = t + q * T;
+    if (i >= nloss) continue;
+    if (a.g_loss && i < a.g_loss_ld) a.g_loss[(size_t)b * a.g_loss_ld + i] = g[q];
+    const int my = i / d.lw, mx = i - my * d.lw;
+    const int yy = d.y0 + d.ly + my, xx = d.x0 + d.lx + mx;
+    if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
+      const float v = fminf(fmaxf(rintf(g[q]), 0.0f), 255.0f);
+      a.images[(size_t)d.img * a.H * a.W + (size_t)yy * a.W + xx] = (uint8_t)v;
+    }
+  }
+}
+
+// Shapes (waves, complex atoms per lane) with the row lengths of the real
+// loop, so a complex table has the same padded rows.
+struct CShape {
+  int waves, vpl;
+};
+static const CShape kCShapes[] = {{1, 8},  {1, 16}, {2, 12}, {2, 16},  {4, 12},
+                                  {4, 16}, {8, 12}, {8, 16}, {16, 12}, {16, 16}};
+
+bool complex_loop_for(int K) {
+  const int cap = greedy_row_len(K);
+  for (const CShape& c : kCShapes)
+    if (64 * c.waves * c.vpl == cap) return true;
+  return false;
+}
+
+se_status launch_greedy_c(const GreedyArgs& a, const float* G_im, const float* phi_im, int grid,
+                          hipStream_t s) {
+  if (grid <= 0) return SE_OK;
+  const int cap = greedy_row_len(a.K);
+  CShape sh{0, 0};
+  for (const CShape& c : kCShapes)
+    if (64 * c.waves * c.vpl == cap) {
+      sh = c;
+      break;
+    }
+  if (sh.waves == 0) return fail(SE_EINVAL, "no complex loop shape for K=%d", a.K);
+  if (a.ldG < cap || a.ldR < 2 * cap)
+    return fail(SE_EINVAL, "row strides (ldG=%d, ldR=%d) below %d and %d", a.ldG, a.ldR, cap,
+                2 * cap);
+  const CplxArgs x{G_im, phi_im};
+  switch (sh.waves * 100 + sh.vpl) {
+#define SE_C_CASE(w, v)                                                                  \
+  case w * 100 + v:                                                                      \
+    hipLaunchKernelGGL((k_greedy_c<w, v>), dim3(grid), dim3(64 * w), 0, s, a, x); \
+    break;
+    SE_C_CASE(1, 8) SE_C_CASE(1, 16) SE_C_CASE(2, 12) SE_C_CASE(2, 16) SE_C_CASE(4, 12)
+    SE_C_CASE(4, 16) SE_C_CASE(8, 12) SE_C_CASE(8, 16) SE_C_CASE(16, 12) SE_C_CASE(16, 16)
+#undef SE_C_CASE
+    default: return fail(SE_EINVAL, "no complex loop shape for K=%d", a.K);
+  }
+  return check_launch("greedy_c");
+}
+
+}  // namespace sefase

@@ -11,7 +11,9 @@ namespace sefase {
 // then the 64 partials are combined by a fixed butterfly.  The order depends
 // only on the pixel index, never on the atom's position, so bit-identical
 // atoms get bit-identical sums.
+// A complex dictionary (phi_im non-NULL) sums |phi|^2 w = (re^2 + im^2) w.
 __global__ __launch_bounds__(256) void k_diag(const float* __restrict__ phi,
+                                              const float* __restrict__ phi_im,
                                               const float* __restrict__ w, int K, int P,
                                               float* __restrict__ diag32,
                                               double* __restrict__ diag64) {
@@ -26,6 +28,11 @@ __global__ __launch_bounds__(256) void k_diag(const float* __restrict__ phi,
     const float wp = w[p];
     s32 = fmaf(v * wp, v, s32);
     s64 = fma((double)v * (double)wp, (double)v, s64);
+    if (phi_im) {
+      const float vi = phi_im[(size_t)k * P + p];
+      s32 = fmaf(vi * wp, vi, s32);
+      s64 = fma((double)vi * (double)wp, (double)vi, s64);
+    }
   }
   for (int off = 32; off >= 1; off >>= 1) {
     s32 += __shfl_xor(s32, off);
@@ -88,13 +95,31 @@ __global__ __launch_bounds__(1024) void k_finalize_d(const float* __restrict__ d
   for (int p = tid; p < P; p += blockDim.x) sqrtw[p] = sqrtf(fmaxf(w[p], 0.0f));
 }
 
+// neg: the imaginary rows of a complex dictionary, Y = D sqrt(w) conj(phi)
 __global__ void k_scale_y(const float* __restrict__ phi, const float* __restrict__ D,
-                          const float* __restrict__ sqrtw, int K, int P, float* __restrict__ Y) {
+                          const float* __restrict__ sqrtw, int K, int P, bool neg,
+                          float* __restrict__ Y) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long long)K * P) return;
   const int k = (int)(i / P);
   const int p = (int)(i - (long long)k * P);
-  Y[i] = D[k] * (sqrtw[p] * phi[i]);
+  const float v = D[k] * (sqrtw[p] * phi[i]);
+  Y[i] = neg ? -v : v;
+}
+
+// The Hermitian table of a complex dictionary from S = Z Z^T, Z = [A; B]
+// the real and imaginary rows of Y = D sqrt(w) conj(phi) (2K x P):
+//   G = Y Y^H:  Re G[k][l] = S[k][l] + S[K+k][K+l],
+//               Im G[k][l] = S[K+k][l] - S[k][K+l].
+__global__ void k_combine_c(const float* __restrict__ S, int ldS, int K,
+                            float* __restrict__ G, float* __restrict__ G_im, int ldG) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (l >= K) return;
+  const float* top = S + (size_t)k * ldS;
+  const float* bot = S + (size_t)(K + k) * ldS;
+  G[(size_t)k * ldG + l] = top[l] + bot[K + l];
+  G_im[(size_t)k * ldG + l] = bot[l] - top[K + l];
 }
 
 // Round-to-nearest-even float32 -> bfloat16 bits (finite inputs).
@@ -123,6 +148,21 @@ __global__ void k_zero_cols(float* __restrict__ A, int rows, int c0, int ld) {
   A[(size_t)r * ld + c0 + (int)(i - (long long)r * w)] = 0.0f;
 }
 
+__global__ void k_zero_range(float* __restrict__ A, int rows, int ld, int c0, int c1) {
+  const int w = c1 - c0;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)rows * w) return;
+  const int r = (int)(i / w);
+  A[(size_t)r * ld + c0 + (int)(i - (long long)r * w)] = 0.0f;
+}
+
+void launch_zero_range(float* A, int rows, int ld, int c0, int c1, hipStream_t s) {
+  const long long total = (long long)rows * (c1 - c0);
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_zero_range, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, A, rows,
+                     ld, c0, c1);
+}
+
 void launch_zero_cols(float* A, int rows, int c0, int ld, hipStream_t s) {
   const long long total = (long long)rows * (ld - c0);
   if (total <= 0) return;
@@ -130,9 +170,16 @@ void launch_zero_cols(float* A, int rows, int c0, int ld, hipStream_t s) {
                      c0, ld);
 }
 
-void launch_diag(const float* phi, const float* w, int K, int P, float* diag32, double* diag64,
-                 hipStream_t s) {
-  hipLaunchKernelGGL(k_diag, dim3((K + 3) / 4), dim3(256), 0, s, phi, w, K, P, diag32, diag64);
+void launch_diag(const float* phi, const float* phi_im, const float* w, int K, int P,
+                 float* diag32, double* diag64, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag, dim3((K + 3) / 4), dim3(256), 0, s, phi, phi_im, w, K, P, diag32,
+                     diag64);
+}
+
+void launch_combine_c(const float* S, int ldS, int K, float* G, float* G_im, int ldG,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_combine_c, dim3((K + 255) / 256, K), dim3(256), 0, s, S, ldS, K, G, G_im,
+                     ldG);
 }
 
 void launch_finalize_d(const float* diag32, const double* diag64, const float* w, int K, int P,
@@ -143,10 +190,10 @@ void launch_finalize_d(const float* diag32, const double* diag64, const float* w
 }
 
 void launch_scale_y(const float* phi, const float* D, const float* sqrtw, int K, int P, float* Y,
-                    hipStream_t s) {
+                    hipStream_t s, bool neg) {
   const long long total = (long long)K * P;
   hipLaunchKernelGGL(k_scale_y, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, phi, D,
-                     sqrtw, K, P, Y);
+                     sqrtw, K, P, neg, Y);
 }
 
 void launch_split_bf16(const float* x, size_t n, uint16_t* hi, uint16_t* lo, hipStream_t s) {

@@ -51,16 +51,21 @@ void launch_area_weights(int M, int N, float rho_hat, const uint8_t* lost,
 void launch_lost_mask(uint8_t* mask, int H, int W, const int4* rects, int n, hipStream_t s);
 
 // gram.hip -- Algorithm 2 support kernels
-// diag32/diag64: C_kk summed in fp32 and fp64 with one fixed order.
-void launch_diag(const float* phi, const float* w, int K, int P,
+// diag32/diag64: C_kk summed in fp32 and fp64 with one fixed order
+// (phi_im: imaginary parts of a complex dictionary, or NULL).
+void launch_diag(const float* phi, const float* phi_im, const float* w, int K, int P,
                  float* diag32, double* diag64, hipStream_t s);
+// Re G and Im G of a complex dictionary from the 2K x 2K product S of the
+// stacked real and imaginary rows of Y.
+void launch_combine_c(const float* S, int ldS, int K, float* G, float* G_im, int ldG,
+                      hipStream_t s);
 // D_k from the diagonal (mode 0 auto, 1 fp64, 2 fp32), sqrt(w), info word.
 void launch_finalize_d(const float* diag32, const double* diag64,
                        const float* w, int K, int P, int mode, int force64,
                        float* D, float* sqrtw, int32_t* info, hipStream_t s);
-// Y[k][p] = D_k sqrt(w_p) phi[k][p]
+// Y[k][p] = D_k sqrt(w_p) phi[k][p] (negated with neg)
 void launch_scale_y(const float* phi, const float* D, const float* sqrtw,
-                    int K, int P, float* Y, hipStream_t s);
+                    int K, int P, float* Y, hipStream_t s, bool neg = false);
 // zero columns [c0, ld) of a rows x ld matrix
 void launch_zero_cols(float* A, int rows, int c0, int ld, hipStream_t s);
 // split x = hi + lo into two bf16 arrays (precision path)
@@ -186,6 +191,13 @@ se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s);
 bool conceal_tx_supported(const se_tables* t);
 se_status conceal_tx(const se_tables* t, const GreedyArgs& a, const uint8_t* images, int H, int W,
                      int n_blk, hipStream_t s, int waves, int vpl);
+
+// complex.hip -- the loop for complex dictionaries (R rows: real | imaginary)
+bool complex_loop_for(int K);
+se_status launch_greedy_c(const GreedyArgs& a, const float* G_im, const float* phi_im, int grid,
+                          hipStream_t s);
+// zero columns [c0, c1) of rows x ld
+void launch_zero_range(float* A, int rows, int ld, int c0, int c1, hipStream_t s);
 
 int greedy_waves_for(int K);   // 0 if K is too large
 int greedy_row_len(int K);     // padded row length (table row stride minimum)

@@ -534,8 +534,10 @@ se_status se_serve_create(const se_serve_config* cfg, const se_basis* sets, int3
     if (!sets[i].phi || sets[i].M < 1 || sets[i].N < 1 || sets[i].K < 1 ||
         greedy_waves_for(sets[i].K) == 0)
       return fail(SE_EINVAL, "basis set %d invalid", i);
-  for (int i = 0; i < n_sets; ++i)
+  for (int i = 0; i < n_sets; ++i) {
     if (se_status st = check_basis_parts(&sets[i])) return st;
+    if (sets[i].phi_im) return fail(SE_EINVAL, "basis set %d: the server takes real dictionaries", i);
+  }
   if (hipSetDevice(cfg->device) != hipSuccess) return fail(SE_EHIP, "hipSetDevice failed");
   std::unique_ptr<se_server> s(new se_server());
   s->cfg = *cfg;

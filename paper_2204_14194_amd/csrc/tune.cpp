@@ -48,6 +48,7 @@ se_status se_autotune_batch(const se_tables* t, uint8_t* images, int32_t n_img, 
                             float* R, int32_t ldR, void* ws, size_t ws_bytes, int32_t reps,
                             void* stream, se_tune_result* out) {
   if (!out || reps < 1 || n_blk < 1) return fail(SE_EINVAL, "bad autotune arguments");
+  if (t && t->phi_im) return fail(SE_EINVAL, "the autotuner takes tables of real dictionaries");
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
