@@ -176,7 +176,7 @@ def main():
     ap.add_argument("--plain-reps", type=int, default=2,
                     help="passes of the plain per-block form over one image's 16 blocks")
     ap.add_argument("--config", default="area32",
-                    choices=["area32", "area48", "clustered", "area64", "serving"],
+                    choices=["area32", "area48", "clustered", "area64", "serving", "dft32"],
                     help="area32 (default) is the headline line; the others measure the "
                          "secondary workloads")
     ap.add_argument("--frames", type=int, default=120, help="serving: frames per arrival rate")
@@ -514,6 +514,60 @@ def bench_area48(args):
             "latency_ms": {"p50": percentile(ms, 50), "p99": percentile(ms, 99)}}
 
 
+def bench_dft32(args):
+    """Complex dictionary (the paper's Fig. 1 bottom row): 32x32 areas with
+    centred 8x8 losses, K = 2048 (2-D DFT 32^2 u binarized DFT 32^2), I = 100,
+    the headline's 4096 blocks per step; projections and loop as two launches."""
+    import torch
+    from paper_2204_14194_amd import binding as B
+    dev = torch.device("cuda:0")
+    d = synth.dft32_inputs(args.images)
+    blocks = d["blocks"]
+    n = len(blocks)
+    phi = d["phi"]
+    lost = np.stack([synth.lost_mask(128, 128, blocks, i) for i in range(args.images)])
+    w = B.area_weights(M, N, RHO, torch.from_numpy(lost).to(dev), blocks[:1])
+    pr = torch.from_numpy(phi.real.astype(np.float32)).to(dev)
+    pi = torch.from_numpy(phi.imag.astype(np.float32)).to(dev)
+    gram = []
+    for _ in range(3):
+        e0, e1 = _events(2)
+        e0.record()
+        t = B.weighted_gram(pr, w[0].contiguous(), M, N, phi_im=pi)
+        e1.record()
+        e1.synchronize()
+        gram.append(e0.elapsed_time(e1))
+    img = torch.from_numpy(d["images"]).to(dev)
+    db = B.DeviceBlocks(t, img, blocks)
+    R = torch.empty((n, t.ldR), dtype=torch.float32, device=dev)
+    ws = torch.empty(max(1, B.project_ws_bytes(t, n)), dtype=torch.uint8, device=dev)
+    proj = _timed(lambda: B.project(t, img, db, R, ws), args.steps, args.warmup)
+    loop = _timed(lambda: B.iterate(t, R, img, db, GAMMA, ITERS), args.steps, args.warmup)
+
+    def step():
+        B.project(t, img, db, R, ws)
+        B.iterate(t, R, img, db, GAMMA, ITERS)
+    ms = _timed(step, args.steps, args.warmup)
+    med = float(np.median(ms))
+    loop_ms = float(np.median(loop))
+    # rows of Re G and Im G and the atom's two parts over the loss per
+    # iteration, R^(0) (two parts) once
+    bytes_per_block = ITERS * (2 * K_ATOMS + 2 * 64) * 4 + 2 * K_ATOMS * 4
+    gbs = bytes_per_block * n / (loop_ms * 1e-3) / 1e9
+    return {"metric": "concealed blocks/s, complex dictionary (DFT u binarized DFT), K=2048, "
+                      "I=100",
+            "value": n / (med * 1e-3), "unit": "blocks/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": med,
+            "higher_is_better": True, "dtype": "f32 (complex)", "data": "synthetic",
+            "config": {"workload": f"{args.images} x 128x128 images, 16 blocks each = {n} "
+                                   f"blocks, 32x32 areas, 8x8 losses, K=2048 (DFT 32^2 u "
+                                   f"binarized DFT 32^2), I=100"},
+            "latency_ms": {"p50": percentile(ms, 50), "p99": percentile(ms, 99)},
+            "kernels": {"project_ms": float(np.median(proj)), "loop_ms": loop_ms,
+                        "loop_gbs": gbs, "loop_bytes_per_block": bytes_per_block,
+                        "gram_ms": min(gram)}}
+
+
 def bench_clustered(args):
     """Uneven batch: 8 1024x1024 frames with clustered/burst losses, 4000
     blocks, areas 24/32/48, per-block weights (rows on demand), I ~ U{100..200}."""
@@ -676,7 +730,7 @@ def bench_serving(args):
 
 
 SECONDARY = {"area48": bench_area48, "clustered": bench_clustered, "area64": bench_area64,
-             "serving": bench_serving}
+             "serving": bench_serving, "dft32": bench_dft32}
 
 
 if __name__ == "__main__":
