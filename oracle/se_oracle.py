@@ -32,6 +32,12 @@ Contents, in the paper's notation:
                              (last step of Algorithms 1 and 3)
   * ``duplicate_classes`` -- atoms that are parallel over the whole area
   * ``operation_counts``  -- Table I
+  * ``volume_weights``, ``volume_signal``, ``conceal_video`` -- the same
+                             model over areas of T consecutive video frames,
+                             the three-dimensional extension named in the
+                             paper's closing section (generated exactly as in
+                             two dimensions, Algorithms 1-3 unchanged on the
+                             T*M*N sample vector)
 
 Readings where the paper is silent (each is listed in the design notes):
   * exact ties in the selection go to the lowest atom index (np.argmax);
@@ -41,7 +47,10 @@ Readings where the paper is silent (each is listed in the design notes):
     zero coefficient, which changes nothing;
   * pixels outside the image or inside any lost block are not support:
     their weight is 0 and their sample value is taken as 0;
-  * the model is cut into the image as clip(round-half-even(g), 0, 255).
+  * the model is cut into the image as clip(round-half-even(g), 0, 255);
+  * in three dimensions the decay of eq. 5 takes the Euclidean distance to
+    the centre of the T x M x N box, one frame counting as one pixel, and
+    sample (tau, m, n) sits at index (tau*M + m)*N + n.
 """
 from __future__ import annotations
 
@@ -54,7 +63,7 @@ import numpy as np
 __all__ = [
     "area_weights", "area_signal", "se_original", "table_generation", "fase",
     "conceal", "duplicate_classes", "quantise", "operation_counts",
-    "SEResult",
+    "SEResult", "volume_weights", "volume_signal", "conceal_video",
 ]
 
 
@@ -92,6 +101,47 @@ def area_signal(image: np.ndarray, lost: np.ndarray, y0: int, x0: int,
             s[m, n] = float(image[y, x])
             support[m, n] = True
     return s.reshape(M * N), support
+
+
+def volume_weights(T: int, M: int, N: int, rho_hat: float, support: np.ndarray) -> np.ndarray:
+    """Eq. 4 and eq. 5 over a T x M x N area of consecutive frames:
+    w[tau, m, n] = rho_hat ** sqrt((tau-(T-1)/2)^2 + (m-(M-1)/2)^2 +
+    (n-(N-1)/2)^2) on the support (``support`` True), 0 elsewhere.  Returns
+    a flat (T*M*N,) float64 vector, sample (tau, m, n) at (tau*M + m)*N + n."""
+    t = np.arange(T, dtype=np.float64)[:, None, None]
+    m = np.arange(M, dtype=np.float64)[None, :, None]
+    n = np.arange(N, dtype=np.float64)[None, None, :]
+    dist = np.sqrt((t - (T - 1) / 2.0) ** 2 + (m - (M - 1) / 2.0) ** 2
+                   + (n - (N - 1) / 2.0) ** 2)
+    rho = float(rho_hat) ** dist
+    w = np.where(np.asarray(support, dtype=bool).reshape(T, M, N), rho, 0.0)
+    return w.reshape(T * M * N)
+
+
+def volume_signal(frames: np.ndarray, lost: np.ndarray, t0: int, y0: int, x0: int,
+                  T: int, M: int, N: int):
+    """Cut the T x M x N area whose first frame is ``t0`` and whose top-left
+    corner is (y0, x0) out of ``frames`` (F x H x W).  Returns (s, support):
+    s as float64 (T*M*N,), 0 where the sample is outside the frames or lost;
+    support True exactly where the sample is available."""
+    F, H, W = frames.shape
+    s = np.zeros((T, M, N))
+    support = np.zeros((T, M, N), dtype=bool)
+    for tau in range(T):
+        f = t0 + tau
+        if f < 0 or f >= F:
+            continue
+        for m in range(M):
+            y = y0 + m
+            if y < 0 or y >= H:
+                continue
+            for n in range(N):
+                x = x0 + n
+                if x < 0 or x >= W or lost[f, y, x]:
+                    continue
+                s[tau, m, n] = float(frames[f, y, x])
+                support[tau, m, n] = True
+    return s.reshape(T * M * N), support
 
 
 def _basis(phi: np.ndarray) -> np.ndarray:
@@ -304,6 +354,50 @@ def conceal(image: np.ndarray, lost: np.ndarray, blocks: Sequence, phi: np.ndarr
                 y, x = b.y0 + b.ly + i, b.x0 + b.lx + j
                 if 0 <= y < H and 0 <= x < W:
                     out[y, x] = quantise(g[i, j])
+        per_block.append((res, g.copy()))
+    return out, per_block
+
+
+def conceal_video(frames: np.ndarray, lost: np.ndarray, blocks: Sequence, phi: np.ndarray,
+                  T: int, M: int, N: int, rho_hat: float, gamma: float, iters: int,
+                  method: str = "fase", classes: Optional[np.ndarray] = None,
+                  table_cache: Optional[Dict] = None):
+    """``conceal`` for areas of T consecutive frames.  ``frames`` is F x H x W
+    (not modified), ``lost`` marks every lost sample, and each block has
+    img (the area's first frame), y0, x0, and the loss box: frames lt ..
+    lt+ld-1 of the area times the rectangle ly, lx, lh, lw.  The atoms of
+    ``phi`` are vectors over T*M*N samples.
+
+    Returns (out, per_block) with per_block[i] = (SEResult, g over the loss
+    box as float64 ld x lh x lw)."""
+    out = frames.copy()
+    F, H, W = frames.shape
+    per_block = []
+    for b in blocks:
+        lt, ld = int(getattr(b, "lt", 0)), int(getattr(b, "ld", 1))
+        s, support = volume_signal(frames, lost, b.img, b.y0, b.x0, T, M, N)
+        w = volume_weights(T, M, N, rho_hat, support)
+        if method == "se":
+            res = se_original(s, w, phi, gamma, iters, classes)
+        elif method == "fase":
+            key = w.tobytes()
+            if table_cache is not None and key in table_cache:
+                C, D = table_cache[key]
+            else:
+                C, D = table_generation(phi, w)
+                if table_cache is not None:
+                    table_cache[key] = (C, D)
+            res = fase(s, w, phi, C, D, gamma, iters, classes)
+        else:
+            raise ValueError(method)
+        g = res.g.real.reshape(T, M, N)[lt:lt + ld, b.ly:b.ly + b.lh, b.lx:b.lx + b.lw]
+        for a in range(ld):
+            f = b.img + lt + a
+            for i in range(b.lh):
+                for j in range(b.lw):
+                    y, x = b.y0 + b.ly + i, b.x0 + b.lx + j
+                    if 0 <= f < F and 0 <= y < H and 0 <= x < W:
+                        out[f, y, x] = quantise(g[a, i, j])
         per_block.append((res, g.copy()))
     return out, per_block
 

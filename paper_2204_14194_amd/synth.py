@@ -18,6 +18,9 @@ defined, basis functions, Section II):
     vertical frequency;
   * DCT-II rows are orthonormal; Walsh-Hadamard rows are in natural
     (Sylvester) order with entries +-1/sqrt(M);
+  * video areas of T frames: an atom is a length T*M*N vector, sample
+    (tau, m, n) at index (tau*M + m)*N + n; 3-D transform atoms are
+    separable, index (kt*M + k1)*N + k2;
   * the DCT-II rows 0 and M/2 take exactly the values +-1/sqrt(M) in exact
     arithmetic, the same as two Walsh-Hadamard rows.  Both dictionaries use
     the identical float64 constant for those entries and the same outer
@@ -36,7 +39,9 @@ __all__ = [
     "wht2_atoms", "gaussian_atoms", "dictionary", "dictionary_parts", "Block", "grid_layout",
     "parity_lattice_layout", "lost_mask", "round_to_f32", "area32_inputs",
     "area48_inputs", "area64_inputs", "clustered_layout", "clustered_dictionaries",
-    "clustered_dictionary_parts", "clustered_inputs", "frame_losses",
+    "clustered_dictionary_parts", "clustered_inputs", "frame_losses", "synth_video",
+    "separable_atoms3", "video_dictionary", "video_lost_mask", "video_grid_layout",
+    "video_inputs",
 ]
 
 
@@ -218,6 +223,8 @@ class Block:
                may lie partly outside the image)
     ly, lx   : top-left corner of the loss rectangle, relative to the area
     lh, lw   : loss rectangle size
+    lt, ld   : for areas of several video frames (img then the area's first
+               frame): the loss covers frames lt .. lt+ld-1 of the area
     """
     img: int
     y0: int
@@ -226,6 +233,8 @@ class Block:
     lx: int
     lh: int
     lw: int
+    lt: int = 0
+    ld: int = 1
 
 
 def grid_layout(H: int, W: int, cell: int, loss: int, n_img: int = 1) -> List[Block]:
@@ -431,3 +440,85 @@ def frame_losses(H: int, W: int, coverage: float, seed: int, p16: float = 0.5,
         out.append((cy * 8, cx * 8, s, s, basis))
         lost += s * s
     return out
+
+
+# ----------------------------------------------------------------------------
+# video: areas of T consecutive frames
+# ----------------------------------------------------------------------------
+def synth_video(F: int, H: int, W: int, seed: int, max_speed: int = 2) -> np.ndarray:
+    """Seeded uint8 video of F frames of H x W: one synthetic image (seed
+    ``seed + 1``) on a canvas larger by the whole motion, seen through a
+    window that moves by a seeded integer velocity (vy, vx), each component
+    uniform in [-max_speed, max_speed] pixels per frame (global translation,
+    as in a camera pan).  Draw order: vy, vx."""
+    rng = np.random.default_rng(seed)
+    vy, vx = (int(v) for v in rng.integers(-max_speed, max_speed + 1, size=2))
+    R = max_speed * max(F - 1, 0)
+    canvas = synth_image(H + 2 * R, W + 2 * R, seed + 1)
+    frames = [canvas[R + vy * f:R + vy * f + H, R + vx * f:R + vx * f + W] for f in range(F)]
+    return np.ascontiguousarray(np.stack(frames))
+
+
+def separable_atoms3(rows_t: np.ndarray, rows_v: np.ndarray, rows_h: np.ndarray) -> np.ndarray:
+    """3-D atoms phi_{(kt*Kv + k1)*Kh + k2}[(tau*M + m)*N + n] =
+    (rows_t[kt, tau] * rows_v[k1, m]) * rows_h[k2, n]."""
+    Kt, T = rows_t.shape
+    Kv, M = rows_v.shape
+    Kh, N = rows_h.shape
+    tv = rows_t[:, None, :, None] * rows_v[None, :, None, :]          # (Kt, Kv, T, M)
+    out = tv[:, :, None, :, :, None] * rows_h[None, None, :, None, None, :]
+    return np.ascontiguousarray(out.reshape(Kt * Kv * Kh, T * M * N))
+
+
+def video_dictionary(T: int, M: int, N: int, parts: Sequence[str] = ("dct", "wht")) -> np.ndarray:
+    """Union of 3-D separable transform dictionaries over T x M x N areas, in
+    the order given: 'dct' (DCT-II along every axis) and 'wht' (Walsh-Hadamard,
+    powers of two).  Parallel atoms of the two halves are bit-identical (the
+    same constants and the same product order)."""
+    rows = {"dct": dct_rows, "wht": wht_rows}
+    return np.ascontiguousarray(np.concatenate(
+        [separable_atoms3(rows[p](T), rows[p](M), rows[p](N)) for p in parts], axis=0))
+
+
+def video_lost_mask(F: int, H: int, W: int, blocks: Sequence[Block]) -> np.ndarray:
+    """uint8 (F, H, W) mask, 1 on every lost sample (each block's loss box:
+    frames img+lt .. img+lt+ld-1)."""
+    mask = np.zeros((F, H, W), dtype=np.uint8)
+    for b in blocks:
+        f0 = b.img + b.lt
+        y, x = b.y0 + b.ly, b.x0 + b.lx
+        mask[max(f0, 0):max(f0 + b.ld, 0), max(y, 0):max(y + b.lh, 0),
+             max(x, 0):max(x + b.lw, 0)] = 1
+    return mask
+
+
+def video_grid_layout(F: int, H: int, W: int, T: int, cell: int, loss: int,
+                      lt: int) -> List[Block]:
+    """Losses in every T-th frame: the areas span frames T j .. T j + T - 1
+    (j = 0 .. F/T - 1) and every cell x cell cell of the frame, each with a
+    centred loss x loss rectangle in frame lt of the area.  No area holds a
+    second loss, so every block has the same weight pattern."""
+    off = (cell - loss) // 2
+    out = []
+    for j in range(F // T):
+        for cy in range(H // cell):
+            for cx in range(W // cell):
+                out.append(Block(j * T, cy * cell, cx * cell, off, off, loss, loss, lt, 1))
+    return out
+
+
+def video_inputs(n_videos: int = 1, frames: int = 8, seed0: int = 500):
+    """``n_videos`` seeded videos of ``frames`` 128x128 frames each, stacked
+    into one batch of frames; areas of T = 4 frames x 16 x 16 pixels, one
+    centred 8x8 loss in frame 2 of every area (two frames before it, one
+    after), every 16x16 cell of every fourth frame; K = 2048 (3-D DCT-II
+    4x16x16 u 3-D WHT 4x16x16); rho_hat = 0.8, gamma = 0.5, I = 100."""
+    T, M, N = 4, 16, 16
+    vids = [synth_video(frames, 128, 128, seed0 + 10 * v) for v in range(n_videos)]
+    blocks: List[Block] = []
+    for v in range(n_videos):
+        for b in video_grid_layout(frames, 128, 128, T, 16, 8, 2):
+            blocks.append(dataclasses.replace(b, img=b.img + v * frames))
+    return dict(frames=np.concatenate(vids, axis=0), blocks=blocks,
+                phi=video_dictionary(T, M, N), T=T, M=M, N=N,
+                rho_hat=0.8, gamma=0.5, iters=100)
