@@ -8,6 +8,9 @@
  *
  *   se_area_weights        -- the weighting function w (eq. 4) with the
  *                             isotropic decay rho (eq. 5), per block
+ *   se_volume_weights      -- the same over T x M x N areas of consecutive
+ *                             frames (the three-dimensional model of the
+ *                             paper's closing section)
  *   se_weighted_gram       -- table generation, Algorithm 2 (eq. 16, 17)
  *   se_extrapolate_batch   -- model generation, Algorithm 3 (eq. 12, 18-20,
  *                             model update eq. 9, replacement of the loss
@@ -22,6 +25,10 @@
  *     argument says otherwise.
  *   * An atom is a vector over the M x N extrapolation area, pixel (m, n) at
  *     index m*N + n.  A dictionary is K atoms, row-major K x (M*N).
+ *   * Video: an area may span T consecutive frames (se_basis.T); an atom is
+ *     then a vector over T x M x N samples, sample (tau, m, n) at index
+ *     (tau*M + m)*N + n, and the batch of images is read as frames.  T = 1
+ *     (or 0) is the two-dimensional case every statement below describes.
  *   * Pointers documented "device" point to GPU memory the CALLER allocates
  *     and owns (e.g. torch tensors); pointers documented "host" point to
  *     host memory read during the call only.  The library never frees
@@ -90,13 +97,20 @@ typedef struct {
  * with phi holding the real parts.  Complex dictionaries take FP32 tables,
  * declare no transform parts, and are concealed by the batched calls
  * (se_extrapolate_batch, se_project/se_iterate, se_extrapolate_device);
- * the other calls refuse them (SE_EINVAL). */
+ * the other calls refuse them (SE_EINVAL).
+ * T: frames per area (0 or 1: a two-dimensional area).  With T > 1 the
+ * atoms are K x (T*M*N) (sample (tau, m, n) at (tau*M + m)*N + n), the
+ * dictionary declares no transform parts, and it is concealed by the
+ * batched calls, se_project/se_iterate, se_extrapolate_device and
+ * se_extrapolate_plain; rows on demand and the server refuse it, and it
+ * must be real (phi_im NULL). */
 typedef struct {
   int32_t M, N, K;
   const float* phi;
   int32_t n_parts;
   se_part parts[2];
   const float* phi_im;
+  int32_t T;
 } se_basis;
 
 /* One lost block and its extrapolation area L = A u B (Section II, Fig. 2).
@@ -107,9 +121,15 @@ typedef struct {
  * ly, lx   : top-left corner of the loss rectangle B relative to the area
  * lh, lw   : loss rectangle size; B must lie inside the area
  * geom     : caller's tag of the weight pattern (not interpreted by the
- *            batch calls, which take one table set for all blocks)       */
+ *            batch calls, which take one table set for all blocks)
+ * lt, ld   : for areas of T > 1 frames: img is the area's first frame (the
+ *            frames img .. img+T-1 of the batch must exist), and the loss
+ *            is the box of frames lt .. lt+ld-1 of the area (inside it)
+ *            times the rectangle above.  ld = 0 is read as 1, so a
+ *            two-dimensional caller may leave both fields 0.            */
 typedef struct {
   int32_t img, y0, x0, ly, lx, lh, lw, geom;
+  int32_t lt, ld;
 } se_block;
 
 /* Tables for one weight pattern (Algorithm 2), as written by
@@ -165,6 +185,7 @@ typedef struct {
   float* tx;
   float* G_im;
   const float* phi_im;   /* copied from the dictionary by se_weighted_gram */
+  int32_t T;             /* frames per area, copied (0 read as 1)          */
 } se_tables;
 
 /* Model-generation parameters: gamma of eq. 8 (0 < gamma <= 1) and the
@@ -213,6 +234,20 @@ se_status se_area_weights(int32_t M, int32_t N, float rho_hat,
                           int32_t W, const se_block* blocks, int32_t n_blk,
                           float* w, void* ws, size_t ws_bytes, void* stream);
 
+/* The weighting function over a T x M x N area of consecutive frames (the
+ * three-dimensional model of the paper's closing section, built like the
+ * two-dimensional one): w_b[(tau*M + m)*N + n] =
+ *   rho_hat ^ sqrt((tau-(T-1)/2)^2 + (m-(M-1)/2)^2 + (n-(N-1)/2)^2)
+ * for every sample of frame img+tau that lies inside the frame and is not
+ * lost, 0 elsewhere.  `lost` and the batch are n_img frames of H x W;
+ * every block's frames img .. img+T-1 must exist (SE_EINVAL otherwise).
+ * Only img, y0, x0 are read.  T = 1 gives se_area_weights exactly.  Other
+ * arguments and errors as for se_area_weights (T < 1 is SE_EINVAL). */
+se_status se_volume_weights(int32_t T, int32_t M, int32_t N, float rho_hat,
+                            const uint8_t* lost, int32_t n_img, int32_t H,
+                            int32_t W, const se_block* blocks, int32_t n_blk,
+                            float* w, void* ws, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Table generation: Algorithm 2, eq. 16, eq. 17                            */
 /* ------------------------------------------------------------------------ */
@@ -257,8 +292,9 @@ se_status se_weighted_gram(const se_basis* b, const float* w,
  * Arguments:
  *   images  : device uint8, n_img images H x W (row pitch W, image stride
  *             H*W); read on the support, written on each loss (in place)
- *   blocks  : host, n_blk descriptors; every loss rectangle must lie inside
- *             its area and hold at most 256*waves pixels (waves = the
+ *   blocks  : host, n_blk descriptors; every loss rectangle (box, for
+ *             areas of several frames) must lie inside its area and hold at
+ *             most 256*waves pixels (waves = the
  *             workgroup size of the loop for K: 1 for K <= 2048, 2 for
  *             K <= 4096, 4 for K <= 8192, 8 for K <= 16384, 16 above; so 256
  *             pixels are always accepted); losses of different blocks must
@@ -269,7 +305,8 @@ se_status se_weighted_gram(const se_basis* b, const float* w,
  *             iteration (NULL to skip); for complex tables n_blk x iters
  *             pairs (real, imaginary part)
  *   g_loss  : optional device float32 n_blk x g_loss_ld, the model over the
- *             loss before rounding, row-major lh x lw (NULL to skip)
+ *             loss before rounding, row-major lh x lw (ld x lh x lw for a
+ *             loss over several frames) (NULL to skip)
  *   ws      : device scratch of se_extrapolate_batch_ws_bytes() bytes
  * Errors: SE_EINVAL for bad descriptors or parameters (nothing launched),
  * SE_ENOMEM for ws too small, SE_EHIP for launch failures. */

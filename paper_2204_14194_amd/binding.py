@@ -25,6 +25,7 @@ SE_PART_DCT2, SE_PART_WHT2 = 1, 2
 # every symbol include/se.h declares
 EXPORTED = (
     "se_last_error", "se_version", "se_area_weights_ws_bytes", "se_area_weights",
+    "se_volume_weights",
     "se_weighted_gram_ws_bytes", "se_weighted_gram", "se_extrapolate_batch_ws_bytes",
     "se_extrapolate_batch", "se_extrapolate_plain", "se_blocks_upload", "se_project_ws_bytes",
     "se_project", "se_iterate", "se_extrapolate_device_ws_bytes", "se_extrapolate_device",
@@ -45,7 +46,8 @@ class se_part(C.Structure):
 
 class se_basis(C.Structure):
     _fields_ = [("M", C.c_int32), ("N", C.c_int32), ("K", C.c_int32), ("phi", C.c_void_p),
-                ("n_parts", C.c_int32), ("parts", se_part * 2), ("phi_im", C.c_void_p)]
+                ("n_parts", C.c_int32), ("parts", se_part * 2), ("phi_im", C.c_void_p),
+                ("T", C.c_int32)]
 
 
 _PART_NAMES = {"dct": SE_PART_DCT2, "wht": SE_PART_WHT2}
@@ -66,16 +68,21 @@ def _part_array(parts):
     return arr
 
 
-def make_basis(M: int, N: int, K: int, phi_ptr, parts=(), phi_im_ptr=None) -> se_basis:
+def make_basis(M: int, N: int, K: int, phi_ptr, parts=(), phi_im_ptr=None, T: int = 1) -> se_basis:
     """se_basis for a dictionary at device address ``phi_ptr``; ``parts`` is a
     sequence of (SE_PART_*, first atom) transform ranges; ``phi_im_ptr`` the
-    imaginary parts of a complex dictionary (None for a real one)."""
+    imaginary parts of a complex dictionary (None for a real one); ``T`` the
+    frames per area (atoms over T*M*N samples)."""
     parts = _parts_arg(parts)
-    return se_basis(M, N, K, phi_ptr, len(parts), _part_array(parts), phi_im_ptr)
+    return se_basis(M, N, K, phi_ptr, len(parts), _part_array(parts), phi_im_ptr, int(T))
 
 
 class se_block(C.Structure):
-    _fields_ = [(n, C.c_int32) for n in ("img", "y0", "x0", "ly", "lx", "lh", "lw", "geom")]
+    _fields_ = [(n, C.c_int32)
+                for n in ("img", "y0", "x0", "ly", "lx", "lh", "lw", "geom", "lt", "ld")]
+
+
+BLOCK_INTS = 10   # int32 fields of se_block
 
 
 class se_tables(C.Structure):
@@ -84,7 +91,7 @@ class se_tables(C.Structure):
                 ("sqrtw", C.c_void_p), ("phi", C.c_void_p), ("info", C.c_void_p),
                 ("precision", C.c_int32), ("Yhi", C.c_void_p), ("Ylo", C.c_void_p),
                 ("n_parts", C.c_int32), ("parts", se_part * 2), ("tx", C.c_void_p),
-                ("G_im", C.c_void_p), ("phi_im", C.c_void_p)]
+                ("G_im", C.c_void_p), ("phi_im", C.c_void_p), ("T", C.c_int32)]
 
 
 class se_params(C.Structure):
@@ -115,6 +122,8 @@ def lib():
     L.se_area_weights_ws_bytes.argtypes = [i32]
     L.se_area_weights.restype = i32
     L.se_area_weights.argtypes = [i32, i32, f32, vp, i32, i32, i32, vp, i32, vp, vp, sz, vp]
+    L.se_volume_weights.restype = i32
+    L.se_volume_weights.argtypes = [i32, i32, i32, f32, vp, i32, i32, i32, vp, i32, vp, vp, sz, vp]
     L.se_weighted_gram_ws_bytes.restype = sz
     L.se_weighted_gram_ws_bytes.argtypes = [C.POINTER(se_basis), i32]
     L.se_weighted_gram.restype = i32
@@ -178,11 +187,17 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 def blocks_array(blocks: Sequence) -> C.Array:
     """Host array of se_block from objects with img, y0, x0, ly, lx, lh, lw
-    (and optionally geom)."""
+    (and optionally geom, and lt, ld for a loss over several frames)."""
     arr = (se_block * max(len(blocks), 1))()
     for i, b in enumerate(blocks):
-        arr[i] = se_block(b.img, b.y0, b.x0, b.ly, b.lx, b.lh, b.lw, getattr(b, "geom", 0))
+        arr[i] = se_block(b.img, b.y0, b.x0, b.ly, b.lx, b.lh, b.lw, getattr(b, "geom", 0),
+                          getattr(b, "lt", 0), getattr(b, "ld", 1))
     return arr
+
+
+def loss_size(b) -> int:
+    """Samples in a block's loss (frames x rows x columns)."""
+    return max(int(getattr(b, "ld", 1)), 1) * b.lh * b.lw
 
 
 def version() -> int:
@@ -199,19 +214,26 @@ def table_ld(K: int) -> int:
 
 # ---------------------------------------------------------------------------
 def area_weights(M: int, N: int, rho_hat: float, lost: torch.Tensor, blocks: Sequence,
-                 stream=None) -> torch.Tensor:
-    """se_area_weights: per-block weights (n_blk, M*N) float32 on the device."""
+                 stream=None, T: Optional[int] = None) -> torch.Tensor:
+    """se_area_weights: per-block weights (n_blk, M*N) float32 on the device;
+    with ``T``, se_volume_weights over T x M x N areas of consecutive frames
+    (n_blk, T*M*N)."""
     L = lib()
     if not (lost.is_cuda and lost.dtype == torch.uint8 and lost.dim() == 3 and lost.is_contiguous()):
         raise ValueError("lost must be a contiguous (n_img, H, W) uint8 CUDA tensor")
     n_img, H, W = lost.shape
     n = len(blocks)
-    w = torch.empty((n, M * N), dtype=torch.float32, device=lost.device)
+    F = 1 if T is None else int(T)
+    w = torch.empty((n, F * M * N), dtype=torch.float32, device=lost.device)
     nb = L.se_area_weights_ws_bytes(n)
     ws = _workspace(nb, lost.device)
     arr = blocks_array(blocks)
-    _check(L.se_area_weights(M, N, float(rho_hat), _ptr(lost), n_img, H, W, arr, n, _ptr(w),
-                             _ptr(ws), nb, _stream(stream)))
+    if T is None:
+        _check(L.se_area_weights(M, N, float(rho_hat), _ptr(lost), n_img, H, W, arr, n, _ptr(w),
+                                 _ptr(ws), nb, _stream(stream)))
+    else:
+        _check(L.se_volume_weights(F, M, N, float(rho_hat), _ptr(lost), n_img, H, W, arr, n,
+                                   _ptr(w), _ptr(ws), nb, _stream(stream)))
     return w
 
 
@@ -235,6 +257,7 @@ class Tables:
     tx: Optional[torch.Tensor] = None
     G_im: Optional[torch.Tensor] = None
     phi_im: Optional[torch.Tensor] = None
+    T: int = 1
 
     @property
     def complex(self) -> bool:
@@ -255,7 +278,7 @@ class Tables:
                          len(self.parts), _part_array(self.parts),
                          self.tx.data_ptr() if self.tx is not None else None,
                          self.G_im.data_ptr() if self.G_im is not None else None,
-                         self.phi_im.data_ptr() if self.phi_im is not None else None)
+                         self.phi_im.data_ptr() if self.phi_im is not None else None, self.T)
 
     def nbytes(self) -> int:
         parts = [self.G, self.D, self.Y, self.sqrtw]
@@ -265,18 +288,20 @@ class Tables:
 
 def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
                   precision: int = SE_FP32, flags: int = SE_DIAG_AUTO, stream=None,
-                  parts=(), phi_im: Optional[torch.Tensor] = None) -> Tables:
-    """se_weighted_gram (Algorithm 2) for dictionary ``phi`` (K, M*N) and weight
-    pattern ``w`` (M*N,).  ``parts``: declared transform ranges, as
+                  parts=(), phi_im: Optional[torch.Tensor] = None, T: int = 1) -> Tables:
+    """se_weighted_gram (Algorithm 2) for dictionary ``phi`` (K, T*M*N) and
+    weight pattern ``w`` (T*M*N,).  ``parts``: declared transform ranges, as
     (SE_PART_*, first atom) pairs (verified by the library).  ``phi_im``: the
     imaginary parts of a complex dictionary (``phi`` then holds the real
-    parts); the tables are then complex (G, G_im)."""
+    parts); the tables are then complex (G, G_im).  ``T``: frames per area
+    (1: two-dimensional areas)."""
     L = lib()
     _dev_f32(phi, "phi")
     _dev_f32(w, "w")
     K = phi.shape[0]
-    if phi.shape[1] != M * N or w.numel() != M * N:
-        raise ValueError("phi must be (K, M*N) and w (M*N,)")
+    P = int(T) * M * N
+    if phi.shape[1] != P or w.numel() != P:
+        raise ValueError("phi must be (K, T*M*N) and w (T*M*N,)")
     if phi_im is not None:
         _dev_f32(phi_im, "phi_im")
         if tuple(phi_im.shape) != tuple(phi.shape):
@@ -287,15 +312,15 @@ def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
     t = Tables(M, N, K, ldG,
                torch.empty((K, ldG), dtype=torch.float32, device=dev),
                torch.empty(K, dtype=torch.float32, device=dev),
-               torch.empty((y_rows, M * N), dtype=torch.float32, device=dev),
-               torch.empty(M * N, dtype=torch.float32, device=dev),
-               phi, torch.zeros(1, dtype=torch.int32, device=dev), int(precision))
+               torch.empty((y_rows, P), dtype=torch.float32, device=dev),
+               torch.empty(P, dtype=torch.float32, device=dev),
+               phi, torch.zeros(1, dtype=torch.int32, device=dev), int(precision), T=int(T))
     if phi_im is not None:
         t.phi_im = phi_im
         t.G_im = torch.empty((K, ldG), dtype=torch.float32, device=dev)
     if precision == SE_BF16X3:
-        t.Yhi = torch.empty((K, M * N), dtype=torch.int16, device=dev)
-        t.Ylo = torch.empty((K, M * N), dtype=torch.int16, device=dev)
+        t.Yhi = torch.empty((K, P), dtype=torch.int16, device=dev)
+        t.Ylo = torch.empty((K, P), dtype=torch.int16, device=dev)
     t.parts = _parts_arg(parts)
     if t.parts:
         nb_tx = int(L.se_tables_tx_bytes(M, N, len(t.parts)))
@@ -303,7 +328,7 @@ def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
             raise ValueError(f"no transform parts for a {M}x{N} area")
         t.tx = torch.empty(nb_tx // 4, dtype=torch.float32, device=dev)
     b = make_basis(M, N, K, phi.data_ptr(), t.parts,
-                   phi_im.data_ptr() if phi_im is not None else None)
+                   phi_im.data_ptr() if phi_im is not None else None, int(T))
     nb = L.se_weighted_gram_ws_bytes(C.byref(b), int(precision))
     ws = _workspace(nb, dev)
     st = t.struct()
@@ -331,7 +356,7 @@ def _extrapolate(name: str, t: Tables, images: torch.Tensor, blocks: Sequence, g
     # complex tables: (real, imaginary) pairs per iteration
     coef = (torch.empty((n, iters * (2 if t.complex else 1)), dtype=torch.float32, device=dev)
             if want_coef else None)
-    gld = max([b.lh * b.lw for b in blocks] + [1])
+    gld = max([loss_size(b) for b in blocks] + [1])
     g = torch.zeros((n, gld), dtype=torch.float32, device=dev) if want_g else None
     st = t.struct()
     nb = L.se_extrapolate_batch_ws_bytes(C.byref(st), n)
@@ -374,7 +399,8 @@ class DeviceBlocks:
         L = lib()
         n_img, H, W = images.shape
         self.n = len(blocks)
-        self.buf = torch.empty((max(self.n, 1), 8), dtype=torch.int32, device=images.device)
+        self.buf = torch.empty((max(self.n, 1), BLOCK_INTS), dtype=torch.int32,
+                               device=images.device)
         mx = C.c_int32(0)
         st = t.struct()
         _check(L.se_blocks_upload(C.byref(st), n_img, H, W, blocks_array(blocks), self.n,
@@ -449,7 +475,7 @@ def extrapolate_ondemand(phi: torch.Tensor, M: int, N: int, w: torch.Tensor,
         imax = max([int(v) for v in iters] + [0])
     sel = torch.empty((n, imax), dtype=torch.int32, device=dev) if want_sel else None
     coef = torch.empty((n, imax), dtype=torch.float32, device=dev) if want_coef else None
-    gld = max([b.lh * b.lw for b in blocks] + [1])
+    gld = max([loss_size(b) for b in blocks] + [1])
     g = torch.zeros((n, gld), dtype=torch.float32, device=dev) if want_g else None
     bas = make_basis(M, N, phi.shape[0], phi.data_ptr(), parts)
     nb = L.se_extrapolate_ondemand_ws_bytes(C.byref(bas), n, gld)

@@ -36,7 +36,8 @@ static se_status upload_blocks(const se_block* blocks, int n_blk, DevBlock* dst,
   std::vector<DevBlock> tmp((size_t)n_blk);
   for (int i = 0; i < n_blk; ++i) {
     const se_block& b = blocks[i];
-    tmp[(size_t)i] = DevBlock{b.img, b.y0, b.x0, b.ly, b.lx, b.lh, b.lw, 0};
+    tmp[(size_t)i] = DevBlock{b.img, b.y0, b.x0, b.ly, b.lx, b.lh, b.lw, 0, b.lt,
+                              b.ld < 1 ? 1 : b.ld};
   }
   // pageable source: the call returns once the data has been staged
   const hipError_t e = hipMemcpyAsync(dst, tmp.data(), tmp.size() * sizeof(DevBlock),
@@ -48,10 +49,11 @@ static se_status upload_blocks(const se_block* blocks, int n_blk, DevBlock* dst,
 static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 // Declared transform parts: known kinds, inside [0, K), disjoint, areas up to
-// 64 x 64 (powers of two for Walsh-Hadamard).
-static se_status check_parts(int M, int N, int K, int n_parts, const se_part* parts) {
+// 64 x 64 (powers of two for Walsh-Hadamard), of one frame.
+static se_status check_parts(int T, int M, int N, int K, int n_parts, const se_part* parts) {
   if (n_parts < 0 || n_parts > 2) return fail(SE_EINVAL, "n_parts=%d must be 0, 1 or 2", n_parts);
   if (n_parts == 0) return SE_OK;
+  if (T > 1) return fail(SE_EINVAL, "transform parts are two-dimensional (T=%d)", T);
   if (M > 64 || N > 64) return fail(SE_EINVAL, "transform parts need M, N <= 64 (got %dx%d)", M, N);
   const int P = M * N;
   for (int q = 0; q < n_parts; ++q) {
@@ -70,13 +72,14 @@ static se_status check_parts(int M, int N, int K, int n_parts, const se_part* pa
 }
 
 se_status check_basis_parts(const se_basis* b) {
-  return check_parts(b->M, b->N, b->K, b->n_parts, b->parts);
+  return check_parts(area_frames(b->T), b->M, b->N, b->K, b->n_parts, b->parts);
 }
 
 static se_status check_tables(const se_tables* t) {
   if (!t) return fail(SE_EINVAL, "tables is NULL");
-  if (t->M < 1 || t->N < 1 || t->K < 1) return fail(SE_EINVAL, "bad table shape M=%d N=%d K=%d", t->M, t->N, t->K);
-  if ((long long)t->M * t->N > (1 << 24)) return fail(SE_EINVAL, "area too large");
+  if (t->M < 1 || t->N < 1 || t->K < 1 || t->T < 0)
+    return fail(SE_EINVAL, "bad table shape T=%d M=%d N=%d K=%d", t->T, t->M, t->N, t->K);
+  if ((long long)area_frames(t->T) * t->M * t->N > (1 << 24)) return fail(SE_EINVAL, "area too large");
   if (greedy_waves_for(t->K) == 0) return fail(SE_EINVAL, "K=%d exceeds %d", t->K, 32768);
   if (t->ldG < greedy_row_len(t->K) || (t->ldG & 3))
     return fail(SE_EINVAL, "ldG=%d must be >= se_table_ld(K)=%d and a multiple of 4", t->ldG,
@@ -87,7 +90,7 @@ static se_status check_tables(const se_tables* t) {
     return fail(SE_EINVAL, "unknown table precision %d", t->precision);
   if (t->precision == SE_BF16X3 && (!t->Yhi || !t->Ylo))
     return fail(SE_EINVAL, "BF16X3 tables need Yhi and Ylo");
-  se_status st = check_parts(t->M, t->N, t->K, t->n_parts, t->parts);
+  se_status st = check_parts(area_frames(t->T), t->M, t->N, t->K, t->n_parts, t->parts);
   if (st) return st;
   if (t->n_parts > 0 && (!t->tx || reinterpret_cast<uintptr_t>(t->tx) % 16))
     return fail(SE_EINVAL, "tables with transform parts need a 16-byte aligned tx buffer");
@@ -97,6 +100,7 @@ static se_status check_tables(const se_tables* t) {
     if (!t->G_im || reinterpret_cast<uintptr_t>(t->G_im) % 16)
       return fail(SE_EINVAL, "complex tables need a 16-byte aligned G_im");
     if (!complex_loop_for(t->K)) return fail(SE_EINVAL, "no complex loop shape for K=%d", t->K);
+    if (area_frames(t->T) > 1) return fail(SE_EINVAL, "complex dictionaries take two-dimensional areas");
   }
   return SE_OK;
 }
@@ -120,7 +124,7 @@ static inline int round8(int v) { return (v + 7) & ~7; }
 // Partial products when the FP32 projection splits its contraction (few
 // blocks): sized for rows of the minimum table row length.
 static size_t project_splitk_floats(const se_tables* t, int n_blk) {
-  const int P = t->M * t->N;
+  const int P = area_samples(t);
   if (t->n_parts == 0) return gemm_splitk_floats(greedy_row_len(t->K), n_blk, P);
   if (t->n_parts > 2) return 0;
   int lo[3], hi[3];
@@ -134,7 +138,7 @@ static size_t project_splitk_floats(const se_tables* t, int n_blk) {
 // products), or as split bf16 pairs.
 static size_t project_ws(const se_tables* t, int n_blk) {
   Carver cv(nullptr);
-  const int P = t->M * t->N;
+  const int P = area_samples(t);
   if (t->precision == SE_BF16X3) {
     cv.take<uint16_t>((size_t)n_blk * round8(P));
     cv.take<uint16_t>((size_t)n_blk * round8(P));
@@ -184,7 +188,7 @@ static se_status project_into(const se_tables* t, const uint8_t* images, int H, 
                               const se_block* dblk, int n_blk, float* R, int ldR, void* ws,
                               hipStream_t s) {
   se_status st;
-  const int P = t->M * t->N;
+  const int P = area_samples(t);
   int lo[3] = {0, 0, 0}, hi[3] = {t->K, 0, 0};
   int nr = 1;
   if (t->n_parts > 0) {
@@ -198,7 +202,8 @@ static se_status project_into(const se_tables* t, const uint8_t* images, int H, 
     const int ldX = round8(P);
     uint16_t* xh = cv.take<uint16_t>((size_t)n_blk * ldX);
     uint16_t* xl = cv.take<uint16_t>((size_t)n_blk * ldX);
-    launch_gather_split(images, H, W, dblk, n_blk, t->M, t->N, t->sqrtw, xh, xl, ldX, s);
+    launch_gather_split(images, H, W, dblk, n_blk, area_frames(t->T), t->M, t->N, t->sqrtw, xh, xl,
+                        ldX, s);
     if ((st = check_launch("gather_split"))) return st;
     for (int r = 0; r < nr; ++r) {
       const size_t off = (size_t)lo[r] * P;
@@ -212,7 +217,7 @@ static se_status project_into(const se_tables* t, const uint8_t* images, int H, 
   float* X = cv.take<float>((size_t)n_blk * ldX);
   const size_t split_floats = project_splitk_floats(t, n_blk);
   float* split = cv.take<float>(split_floats);
-  launch_gather(images, H, W, dblk, n_blk, t->M, t->N, t->sqrtw, X, ldX, s);
+  launch_gather(images, H, W, dblk, n_blk, area_frames(t->T), t->M, t->N, t->sqrtw, X, ldX, s);
   if ((st = check_launch("gather"))) return st;
   if (t->phi_im) {
     // complex dictionary: real and imaginary parts of eq. 12 from the two
@@ -239,16 +244,21 @@ static se_status check_blocks(const se_tables* t, int n_img, int H, int W, const
   if (n_blk < 0) return fail(SE_EINVAL, "n_blk < 0");
   if (n_blk > 0 && !blocks) return fail(SE_EINVAL, "blocks is NULL");
   if (n_img < 1 || H < 1 || W < 1) return fail(SE_EINVAL, "bad image batch %d x %d x %d", n_img, H, W);
-  const int T = 64 * greedy_waves_for(t->K);
+  const int T = 64 * greedy_waves_for(t->K), F = area_frames(t->T);
   for (int i = 0; i < n_blk; ++i) {
     const se_block& b = blocks[i];
-    if (b.img < 0 || b.img >= n_img) return fail(SE_EINVAL, "block %d: img %d out of range", i, b.img);
+    if (b.img < 0 || (long long)b.img + F > n_img)
+      return fail(SE_EINVAL, "block %d: frames %d .. %d out of range", i, b.img, b.img + F - 1);
     if (b.lh < 1 || b.lw < 1 || b.ly < 0 || b.lx < 0 || b.ly + b.lh > t->M || b.lx + b.lw > t->N)
       return fail(SE_EINVAL, "block %d: loss rectangle not inside the %dx%d area", i, t->M, t->N);
-    if (b.lh * b.lw > 4 * T)
-      return fail(SE_EINVAL, "block %d: loss of %d pixels exceeds %d", i, b.lh * b.lw, 4 * T);
-    if (g_loss && b.lh * b.lw > g_loss_ld)
-      return fail(SE_EINVAL, "block %d: g_loss_ld=%d < loss size %d", i, g_loss_ld, b.lh * b.lw);
+    const int ld = b.ld < 1 ? 1 : b.ld;
+    if (b.lt < 0 || b.lt + ld > F)
+      return fail(SE_EINVAL, "block %d: loss frames %d .. %d not inside the %d frames of the area",
+                  i, b.lt, b.lt + ld - 1, F);
+    const long long n = (long long)ld * b.lh * b.lw;
+    if (n > 4 * T) return fail(SE_EINVAL, "block %d: loss of %lld pixels exceeds %d", i, n, 4 * T);
+    if (g_loss && n > g_loss_ld)
+      return fail(SE_EINVAL, "block %d: g_loss_ld=%d < loss size %lld", i, g_loss_ld, n);
   }
   return SE_OK;
 }
@@ -271,18 +281,20 @@ size_t se_area_weights_ws_bytes(int32_t n_blk) {
   return align_up((size_t)(n_blk > 0 ? n_blk : 0) * sizeof(DevBlock), 256) + 256;
 }
 
-se_status se_area_weights(int32_t M, int32_t N, float rho_hat, const uint8_t* lost, int32_t n_img,
-                          int32_t H, int32_t W, const se_block* blocks, int32_t n_blk, float* w,
-                          void* ws, size_t ws_bytes, void* stream) {
+se_status se_volume_weights(int32_t T, int32_t M, int32_t N, float rho_hat, const uint8_t* lost,
+                            int32_t n_img, int32_t H, int32_t W, const se_block* blocks,
+                            int32_t n_blk, float* w, void* ws, size_t ws_bytes, void* stream) {
   g_err[0] = 0;
-  if (M < 1 || N < 1) return fail(SE_EINVAL, "bad area %dx%d", M, N);
+  if (T < 1 || M < 1 || N < 1) return fail(SE_EINVAL, "bad area %dx%dx%d", T, M, N);
+  if ((long long)T * M * N > (1 << 24)) return fail(SE_EINVAL, "area too large");
   if (!(rho_hat > 0.0f && rho_hat <= 1.0f)) return fail(SE_EINVAL, "rho_hat must lie in (0, 1]");
   if (!lost || !w || (n_blk > 0 && !blocks)) return fail(SE_EINVAL, "NULL pointer");
   if (n_img < 1 || H < 1 || W < 1) return fail(SE_EINVAL, "bad image batch");
   if (n_blk < 0) return fail(SE_EINVAL, "n_blk < 0");
   for (int i = 0; i < n_blk; ++i)
-    if (blocks[i].img < 0 || blocks[i].img >= n_img)
-      return fail(SE_EINVAL, "block %d: img out of range", i);
+    if (blocks[i].img < 0 || (long long)blocks[i].img + T > n_img)
+      return fail(SE_EINVAL, "block %d: frames %d .. %d out of range", i, blocks[i].img,
+                  blocks[i].img + T - 1);
   if (n_blk == 0) return SE_OK;
   if (!ws || ws_bytes < se_area_weights_ws_bytes(n_blk)) return fail(SE_ENOMEM, "workspace too small");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -290,8 +302,15 @@ se_status se_area_weights(int32_t M, int32_t N, float rho_hat, const uint8_t* lo
   DevBlock* dblk = cv.take<DevBlock>((size_t)n_blk);
   se_status st = upload_blocks(blocks, n_blk, dblk, s);
   if (st) return st;
-  launch_area_weights(M, N, rho_hat, lost, H, W, dblk, n_blk, w, s);
+  launch_area_weights(T, M, N, rho_hat, lost, H, W, dblk, n_blk, w, s);
   return check_launch("area_weights");
+}
+
+se_status se_area_weights(int32_t M, int32_t N, float rho_hat, const uint8_t* lost, int32_t n_img,
+                          int32_t H, int32_t W, const se_block* blocks, int32_t n_blk, float* w,
+                          void* ws, size_t ws_bytes, void* stream) {
+  return se_volume_weights(1, M, N, rho_hat, lost, n_img, H, W, blocks, n_blk, w, ws, ws_bytes,
+                           stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -323,11 +342,12 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
   t->n_parts = b->n_parts;
   for (int q = 0; q < 2; ++q) t->parts[q] = q < b->n_parts ? b->parts[q] : se_part{0, 0};
   t->phi_im = b->phi_im;
+  t->T = area_frames(b->T);
   se_status st = check_tables(t);
   if (st) return st;
   if (!ws || ws_bytes < se_weighted_gram_ws_bytes(b, prec)) return fail(SE_ENOMEM, "workspace too small");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int K = b->K, P = b->M * b->N;
+  const int K = b->K, P = area_samples(t);
   Carver cv(ws);
   float* diag32 = cv.take<float>((size_t)K);
   double* diag64 = cv.take<double>((size_t)K);
@@ -401,7 +421,8 @@ se_status se_blocks_upload(const se_tables* t, int32_t n_img, int32_t H, int32_t
   if (st) return st;
   if ((st = check_blocks(t, n_img, H, W, blocks, n_blk, 0, nullptr))) return st;
   int mx = 0;
-  for (int i = 0; i < n_blk; ++i) mx = blocks[i].lh * blocks[i].lw > mx ? blocks[i].lh * blocks[i].lw : mx;
+  for (int i = 0; i < n_blk; ++i)
+    mx = std::max(mx, (blocks[i].ld < 1 ? 1 : blocks[i].ld) * blocks[i].lh * blocks[i].lw);
   if (max_loss) *max_loss = mx;
   if (n_blk == 0) return SE_OK;
   if (!dev_blocks) return fail(SE_EINVAL, "dev_blocks is NULL");
@@ -449,6 +470,7 @@ static GreedyArgs greedy_args(const se_tables* t, const float* R, int ldR, uint8
   ga.K = t->K;
   ga.M = t->M;
   ga.N = t->N;
+  ga.P = area_samples(t);
   ga.blk = dev_blocks;
   ga.n_blk = n_blk;
   ga.blk0 = -1;   // batched: block = workgroup index
@@ -490,7 +512,7 @@ se_status se_iterate(const se_tables* t, const float* R, int32_t ldR, uint8_t* i
   if ((st = check_r(t, R, ldR))) return st;
   GreedyArgs ga = greedy_args(t, R, ldR, images, H, W, dev_blocks, n_blk, prm, sel, coef, g_loss,
                               g_loss_ld);
-  const TuneChoice tc = tune_lookup(t->K, t->M * t->N, n_blk);
+  const TuneChoice tc = tune_lookup(t->K, area_samples(t), n_blk);
   return launch_loop(t, ga, n_blk, static_cast<hipStream_t>(stream), tc);
 }
 
@@ -514,7 +536,7 @@ se_status se_extrapolate_device(const se_tables* t, uint8_t* images, int32_t n_i
   if (n_blk == 0) return SE_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int ldR = r_row_len(t);
-  const TuneChoice tc = tune_lookup(t->K, t->M * t->N, n_blk);
+  const TuneChoice tc = tune_lookup(t->K, area_samples(t), n_blk);
   if (conceal_tx_supported(t)) {
     const GreedyArgs ga = greedy_args(t, nullptr, ldR, images, H, W, dev_blocks, n_blk, prm, sel,
                                       coef, g_loss, g_loss_ld);
@@ -555,7 +577,7 @@ static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, in
   const size_t need = se_extrapolate_batch_ws_bytes(t, n_blk);
   if (!ws || ws_bytes < need) return fail(SE_ENOMEM, "workspace too small: need %zu bytes", need);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int P = t->M * t->N, ldR = r_row_len(t);
+  const int P = area_samples(t), ldR = r_row_len(t);
   Carver cv(ws);
   se_block* dblk = cv.take<se_block>((size_t)n_blk);
   float* R = cv.take<float>((size_t)n_blk * ldR);
@@ -573,7 +595,8 @@ static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, in
   // one block at a time: gather, matrix-vector product (FP32), single-workgroup loop
   float* X = reinterpret_cast<float*>(pws);
   for (int i = 0; i < n_blk; ++i) {
-    launch_gather(images, H, W, dblk + i, 1, t->M, t->N, t->sqrtw, X, round4(P), s);
+    launch_gather(images, H, W, dblk + i, 1, area_frames(t->T), t->M, t->N, t->sqrtw, X, round4(P),
+                  s);
     if ((st = check_launch("gather"))) return st;
     launch_gemv(t->Y, t->K, P, X, R, s);
     if ((st = check_launch("gemv"))) return st;
@@ -628,6 +651,7 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* im
                                   void* ws, size_t ws_bytes, void* stream) {
   g_err[0] = 0;
   if (b && b->phi_im) return fail(SE_EINVAL, "rows on demand take real dictionaries");
+  if (b && b->T > 1) return fail(SE_EINVAL, "rows on demand take two-dimensional areas");
   if (!b || !b->phi || !w || !images) return fail(SE_EINVAL, "NULL argument");
   if (b->M < 1 || b->N < 1 || b->K < 1) return fail(SE_EINVAL, "bad basis shape");
   if (b->K > 32768) return fail(SE_EINVAL, "K=%d exceeds 32768", b->K);
@@ -643,7 +667,7 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* im
     const se_block& bl = blocks[i];
     if (bl.img < 0 || bl.img >= n_img) return fail(SE_EINVAL, "block %d: img out of range", i);
     if (bl.lh < 1 || bl.lw < 1 || bl.ly < 0 || bl.lx < 0 || bl.ly + bl.lh > b->M ||
-        bl.lx + bl.lw > b->N)
+        bl.lx + bl.lw > b->N || bl.lt != 0 || bl.ld > 1)
       return fail(SE_EINVAL, "block %d: loss rectangle not inside the %dx%d area", i, b->M, b->N);
     max_loss = std::max(max_loss, bl.lh * bl.lw);
     it[(size_t)i] = iters ? iters[i] : prm.iters;

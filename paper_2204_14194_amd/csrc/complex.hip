@@ -32,7 +32,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy_c(GreedyArgs a, CplxArgs 
   const int lane = t & 63, wave = t >> 6;
   const int b = blockIdx.x;
   const DevBlock d = a.blk[b];
-  const int K = a.K, P = a.M * a.N;
+  const int K = a.K, P = a.P;
   const int L = a.ldR / 2;   // R row: real parts at [0, L), imaginary at [L, 2 L)
 
   float Rr[NJ][4], Ri[NJ][4];
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy_c(GreedyArgs a, CplxArgs 
   }
 
   // loss pixels owned by this lane (lanes past the end repeat the last one)
-  const int nloss = d.lh * d.lw;
+  const int nloss = d.ld * d.lh * d.lw;
   const int nq = (nloss + T - 1) / T;
   int poff[kCQPL];
   float g[kCQPL], gc[kCQPL];
@@ -56,8 +56,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy_c(GreedyArgs a, CplxArgs 
   for (int q = 0; q < kCQPL; ++q) {
     int i = t + q * T;
     i = i < nloss ? i : nloss - 1;
-    const int my = i / d.lw, mx = i - my * d.lw;
-    poff[q] = (d.ly + my) * a.N + d.lx + mx;
+    poff[q] = loss_sample(d, i, a.M, a.N).off;
     g[q] = 0.0f;
     gc[q] = 0.0f;
   }
@@ -179,11 +178,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy_c(GreedyArgs a, CplxArgs 
     const int i = t + q * T;
     if (i >= nloss) continue;
     if (a.g_loss && i < a.g_loss_ld) a.g_loss[(size_t)b * a.g_loss_ld + i] = g[q];
-    const int my = i / d.lw, mx = i - my * d.lw;
-    const int yy = d.y0 + d.ly + my, xx = d.x0 + d.lx + mx;
-    if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
+    const LossSample ls = loss_sample(d, i, a.M, a.N);
+    if (ls.y >= 0 && ls.y < a.H && ls.x >= 0 && ls.x < a.W) {
       const float v = fminf(fmaxf(rintf(g[q]), 0.0f), 255.0f);
-      a.images[(size_t)d.img * a.H * a.W + (size_t)yy * a.W + xx] = (uint8_t)v;
+      a.images[(size_t)ls.frame * a.H * a.W + (size_t)ls.y * a.W + ls.x] = (uint8_t)v;
     }
   }
 }

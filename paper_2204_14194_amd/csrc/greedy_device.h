@@ -45,12 +45,12 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const DevBlock d = a.blk[b];
-  const int K = a.K, P = a.M * a.N;
+  const int K = a.K, P = a.P;
 
   // ---- loss pixels owned by this lane ----------------------------------
   // Lanes past the end of the loss repeat its last pixel (a valid address);
   // their sums are never written.
-  const int nloss = d.lh * d.lw;
+  const int nloss = d.ld * d.lh * d.lw;
   const int nq = (nloss + T - 1) / T;          // uniform
   int poff[kQPL];
   float g[kQPL], gc[kQPL];   // model and its compensation term (Kahan summation)
@@ -58,8 +58,7 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
   for (int q = 0; q < kQPL; ++q) {
     int i = t + q * T;
     i = i < nloss ? i : nloss - 1;
-    const int my = i / d.lw, mx = i - my * d.lw;
-    poff[q] = (d.ly + my) * a.N + d.lx + mx;
+    poff[q] = loss_sample(d, i, a.M, a.N).off;
     g[q] = 0.0f;
     gc[q] = 0.0f;
   }
@@ -203,11 +202,10 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     const int i = t + q * T;
     if (i >= nloss) continue;
     if (a.g_loss && i < a.g_loss_ld) a.g_loss[(size_t)b * a.g_loss_ld + i] = g[q];
-    const int my = i / d.lw, mx = i - my * d.lw;
-    const int y = d.y0 + d.ly + my, x = d.x0 + d.lx + mx;
-    if (y >= 0 && y < a.H && x >= 0 && x < a.W) {
+    const LossSample ls = loss_sample(d, i, a.M, a.N);
+    if (ls.y >= 0 && ls.y < a.H && ls.x >= 0 && ls.x < a.W) {
       const float v = fminf(fmaxf(rintf(g[q]), 0.0f), 255.0f);
-      a.images[(size_t)d.img * a.H * a.W + (size_t)y * a.W + x] = (uint8_t)v;
+      a.images[(size_t)ls.frame * a.H * a.W + (size_t)ls.y * a.W + ls.x] = (uint8_t)v;
     }
   }
 }

@@ -35,15 +35,34 @@ struct Carver {
 };
 
 // Device copy of one block descriptor (same layout as se_block), validated
-// on the host by se_blocks_upload.
+// on the host by se_blocks_upload (which also writes ld >= 1).
 using DevBlock = se_block;
+
+// frames per area of a dictionary or table set (0 is read as 1)
+inline int area_frames(int T) { return T < 1 ? 1 : T; }
+// samples per area of a table set: T M N
+inline int area_samples(const se_tables* t) { return area_frames(t->T) * t->M * t->N; }
+
+// Loss sample i of a block (i < ld lh lw, frames, then rows, then columns):
+// its index in the area's sample vector (T x M x N, (tau M + m) N + n), and
+// its frame and position in the batch of images.
+struct LossSample {
+  int off, frame, y, x;
+};
+__device__ __forceinline__ LossSample loss_sample(const DevBlock& d, int i, int M, int N) {
+  const int plane = d.lh * d.lw;
+  const int mt = i / plane, r = i - mt * plane;
+  const int my = r / d.lw, mx = r - my * d.lw;
+  return LossSample{((d.lt + mt) * M + d.ly + my) * N + d.lx + mx, d.img + d.lt + mt,
+                    d.y0 + d.ly + my, d.x0 + d.lx + mx};
+}
 
 // ---------------------------------------------------------------------------
 // kernel launchers (defined in the .hip files)
 // ---------------------------------------------------------------------------
 
-// weights.hip -- eq. 4 / eq. 5 per block
-void launch_area_weights(int M, int N, float rho_hat, const uint8_t* lost,
+// weights.hip -- eq. 4 / eq. 5 per block (T x M x N samples)
+void launch_area_weights(int T, int M, int N, float rho_hat, const uint8_t* lost,
                          int H, int W, const DevBlock* blk, int n_blk,
                          float* w, hipStream_t s);
 
@@ -94,13 +113,13 @@ se_status gemm_project_bf16x3(const uint16_t* Yhi, const uint16_t* Ylo, int ldy,
 
 // project.hip -- X[b][p] = sqrt(w_p) s_b[p] and the per-block GEMV
 void launch_gather(const uint8_t* images, int H, int W, const DevBlock* blk,
-                   int n_blk, int M, int N, const float* sqrtw, float* X,
+                   int n_blk, int T, int M, int N, const float* sqrtw, float* X,
                    int ldX, hipStream_t s);
 void launch_gemv(const float* Y, int K, int P, const float* x, float* r,
                  hipStream_t s);
 // the same gather, written as split bf16 pairs (precision path)
 void launch_gather_split(const uint8_t* images, int H, int W, const DevBlock* blk,
-                         int n_blk, int M, int N, const float* sqrtw, uint16_t* Xhi,
+                         int n_blk, int T, int M, int N, const float* sqrtw, uint16_t* Xhi,
                          uint16_t* Xlo, int ldX, hipStream_t s);
 
 // transform.hip -- declared transform parts of a dictionary (Section VI)
@@ -136,8 +155,9 @@ struct GreedyArgs {
   const float* G;      // K x ldG unit-diagonal Gram
   int ldG;
   const float* D;      // K
-  const float* phi;    // K x M*N
+  const float* phi;    // K x P
   int K, M, N;
+  int P;               // samples per atom: T M N (M N for a two-dimensional area)
   const DevBlock* blk; // n_blk
   int n_blk;
   int blk0;            // plain form: the one block of this launch; -1 when batched

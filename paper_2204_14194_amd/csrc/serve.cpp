@@ -206,11 +206,11 @@ static CachedTables* get_tables(Server* s, const PatternKey& key, hipStream_t st
   bool ok = hipMemcpyAsync(rect, &r, sizeof(r), hipMemcpyHostToDevice, st) == hipSuccess;
   if (ok) {
     launch_lost_mask(mask, b.M, b.N, rect, 1, st);
-    DevBlock blk{0, 0, 0, key.ly, key.lx, key.lh, key.lw, 0};
+    DevBlock blk{0, 0, 0, key.ly, key.lx, key.lh, key.lw, 0, 0, 1};
     DevBlock* dblk = reinterpret_cast<DevBlock*>(ws);
     ok = hipMemcpyAsync(dblk, &blk, sizeof(blk), hipMemcpyHostToDevice, st) == hipSuccess;
     if (ok) {
-      launch_area_weights(b.M, b.N, s->cfg.rho_hat, mask, b.M, b.N, dblk, 1, w, st);
+      launch_area_weights(1, b.M, b.N, s->cfg.rho_hat, mask, b.M, b.N, dblk, 1, w, st);
       ok = se_weighted_gram(&b, w, SE_FP32, SE_DIAG_AUTO, &t, ws + 256, ws_left - 256, st) ==
            SE_OK;
     }
@@ -250,7 +250,7 @@ static void group_request(Server* s, Req* r, Grouped& g) {
     const se_loss& l = L[i];
     const se_basis& b = s->sets[(size_t)l.basis];
     const int ly = (b.M - l.h) / 2, lx = (b.N - l.w) / 2;
-    se_block blk{r->slot, l.y - ly, l.x - lx, ly, lx, l.h, l.w, l.basis};
+    se_block blk{r->slot, l.y - ly, l.x - lx, ly, lx, l.h, l.w, l.basis, 0, 1};
     bool iso = blk.y0 >= 0 && blk.x0 >= 0 && blk.y0 + b.M <= H && blk.x0 + b.N <= W;
     if (iso) {
       const int y1 = blk.y0 + b.M, x1 = blk.x0 + b.N;
@@ -537,6 +537,8 @@ se_status se_serve_create(const se_serve_config* cfg, const se_basis* sets, int3
   for (int i = 0; i < n_sets; ++i) {
     if (se_status st = check_basis_parts(&sets[i])) return st;
     if (sets[i].phi_im) return fail(SE_EINVAL, "basis set %d: the server takes real dictionaries", i);
+    if (sets[i].T > 1)
+      return fail(SE_EINVAL, "basis set %d: the server takes two-dimensional areas", i);
   }
   if (hipSetDevice(cfg->device) != hipSuccess) return fail(SE_EHIP, "hipSetDevice failed");
   std::unique_ptr<se_server> s(new se_server());

@@ -56,7 +56,7 @@ se_status se_autotune_batch(const se_tables* t, uint8_t* images, int32_t n_img, 
   se_status st = SE_OK;
   TuneChoice best;
   float best_proj = 1e30f, best_loop = 1e30f;
-  const int P = t ? t->M * t->N : 0;
+  const int P = t ? area_samples(t) : 0;
   // projection: both tiles (FP32 tables only; the split path has one tile rule)
   const int tiles[2] = {64, 128};
   for (int ti = 0; ti < 2 && st == SE_OK; ++ti) {

@@ -54,6 +54,38 @@ def min_margin(res) -> float:
     return float(np.min(m))
 
 
+def _check_block(i, s, w, phi, cls, cache, gamma, iters, sel_i, g_i, loss_idx, got, tol, delta,
+                 pasted=None):
+    """One block of oracle_check: returns (err, margin, agreed).  ``got``: the
+    pasted values of the loss samples selected by ``pasted`` (all if None)."""
+    key = w.tobytes()
+    if key not in cache:
+        cache[key] = oracle.table_generation(phi, w)
+    C, D = cache[key]
+    res = oracle.fase(s, w, phi, C, D, gamma, iters, cls)
+    margin = min_margin(res)
+    agreed = compare_selections(sel_i, res.sel, cls)
+    if agreed:
+        ref = res
+    else:
+        ref = oracle.fase(s, w, phi, C, D, gamma, iters, cls, forced=sel_i)
+        ok = np.sqrt(ref.picked) >= np.sqrt(ref.best) * (1.0 - delta)
+        assert ok.all(), (f"block {i}: iteration {int(np.argmin(ok))} picked an atom "
+                          f"outside the near-tie window")
+    # the model's real part replaces the loss (a complex dictionary gives a
+    # complex model)
+    gref = np.real(ref.g)[loss_idx]
+    n = len(loss_idx)
+    err = float(np.abs(g_i[:n].astype(np.float64) - gref).max())
+    assert err <= tol, f"block {i}: max |g - g_oracle| = {err}"
+    if pasted is not None:
+        gref = gref[pasted]
+    q_ref = np.clip(np.rint(gref), 0, 255)
+    near = np.abs(np.abs(gref - np.floor(gref)) - 0.5) < tol
+    assert ((got.astype(np.float64) == q_ref) | near).all(), f"block {i}: pasted pixels differ"
+    return err, margin, agreed
+
+
 def oracle_check(images, blocks, phi, M, N, rho_hat, gamma, iters, sel, g, out,
                  sample=None, tol=1e-3, delta=1e-3):
     """Compare device results with the FP64 oracle (Algorithm 3, which the CPU
@@ -77,30 +109,40 @@ def oracle_check(images, blocks, phi, M, N, rho_hat, gamma, iters, sel, g, out,
         b = blocks[i]
         s, sup = oracle.area_signal(images[b.img], lost[b.img], b.y0, b.x0, M, N)
         w = oracle.area_weights(M, N, rho_hat, sup)
-        key = w.tobytes()
-        if key not in cache:
-            cache[key] = oracle.table_generation(phi, w)
-        C, D = cache[key]
-        res = oracle.fase(s, w, phi, C, D, gamma, iters, cls)
-        margin = min(margin, min_margin(res))
-        if compare_selections(sel[i], res.sel, cls):
-            ref = res
-            agree += 1
-        else:
-            ref = oracle.fase(s, w, phi, C, D, gamma, iters, cls, forced=sel[i])
-            ok = np.sqrt(ref.picked) >= np.sqrt(ref.best) * (1.0 - delta)
-            assert ok.all(), (f"block {i}: iteration {int(np.argmin(ok))} picked an atom "
-                              f"outside the near-tie window")
-        n = b.lh * b.lw
-        # the model's real part replaces the loss (a complex dictionary gives
-        # a complex model)
-        gref = np.real(ref.g).reshape(M, N)[b.ly:b.ly + b.lh, b.lx:b.lx + b.lw].reshape(-1)
-        err = float(np.abs(g[i, :n].astype(np.float64) - gref).max())
-        worst = max(worst, err)
-        assert err <= tol, f"block {i}: max |g - g_oracle| = {err}"
-        q_ref = np.clip(np.rint(gref), 0, 255)
-        near = np.abs(np.abs(gref - np.floor(gref)) - 0.5) < tol
+        loss_idx = (np.arange(M)[b.ly:b.ly + b.lh, None] * N
+                    + np.arange(N)[None, b.lx:b.lx + b.lw]).reshape(-1)
         y, x = b.y0 + b.ly, b.x0 + b.lx
-        got = out[b.img, y:y + b.lh, x:x + b.lw].reshape(-1).astype(np.float64)
-        assert ((got == q_ref) | near).all(), f"block {i}: pasted pixels differ"
+        got = out[b.img, y:y + b.lh, x:x + b.lw].reshape(-1)
+        err, mg, ok = _check_block(i, s, w, phi, cls, cache, gamma, iters, sel[i], g[i],
+                                   loss_idx, got, tol, delta)
+        worst, margin, agree = max(worst, err), min(margin, mg), agree + int(ok)
+    return dict(worst=worst, margin=margin, agree=agree, n=len(idx))
+
+
+def oracle_check_video(frames, blocks, phi, T, M, N, rho_hat, gamma, iters, sel, g, out,
+                       sample=None, tol=1e-3, delta=1e-3):
+    """oracle_check for areas of T consecutive frames (blocks with lt, ld;
+    the model over the loss box in frames x rows x columns order).  Loss
+    samples outside the frames are compared in the model only."""
+    F, H, W = frames.shape
+    lost = synth.video_lost_mask(F, H, W, blocks)
+    cls = classes_of(phi)
+    idx = list(range(len(blocks))) if sample is None else [int(i) for i in sample]
+    cache = {}
+    worst, margin, agree = 0.0, np.inf, 0
+    for i in idx:
+        b = blocks[i]
+        s, sup = oracle.volume_signal(frames, lost, b.img, b.y0, b.x0, T, M, N)
+        w = oracle.volume_weights(T, M, N, rho_hat, sup)
+        tt, mm, nn = np.meshgrid(np.arange(b.lt, b.lt + b.ld), np.arange(b.ly, b.ly + b.lh),
+                                 np.arange(b.lx, b.lx + b.lw), indexing="ij")
+        loss_idx = ((tt * M + mm) * N + nn).reshape(-1)
+        ff = (b.img + tt).reshape(-1)
+        yy = (b.y0 + mm).reshape(-1)
+        xx = (b.x0 + nn).reshape(-1)
+        inside = (ff >= 0) & (ff < F) & (yy >= 0) & (yy < H) & (xx >= 0) & (xx < W)
+        got = out[ff[inside], yy[inside], xx[inside]]
+        err, mg, ok = _check_block(i, s, w, phi, cls, cache, gamma, iters, sel[i], g[i],
+                                   loss_idx, got, tol, delta, pasted=inside)
+        worst, margin, agree = max(worst, err), min(margin, mg), agree + int(ok)
     return dict(worst=worst, margin=margin, agree=agree, n=len(idx))

@@ -182,3 +182,82 @@ def test_tune_records_roundtrip_and_validation():
         B.tune_import("garbage")
     B.tune_clear()
     assert B.tune_export() == ""
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets of
+    the C declaration (compiled here with the host compiler)."""
+    structs = [B.se_part, B.se_basis, B.se_block, B.se_tables, B.se_params, B.se_serve_config,
+               B.se_loss, B.se_request, B.se_result, B.se_serve_stats, B.se_tune_result]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "se.h"', "int main(void) {"]
+    for S in structs:
+        name = S.__name__
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for f in S._fields_:
+            lines.append(f'  printf("{name} {f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                               text=True).stdout.splitlines():
+        a, b, v = line.split()
+        got[(a, b)] = int(v)
+    for S in structs:
+        name = S.__name__
+        assert got[(name, "size")] == C.sizeof(S), name
+        for f in S._fields_:
+            assert got[(name, f[0])] == getattr(S, f[0]).offset, (name, f[0])
+
+
+def test_rejects_bad_video_areas_on_host():
+    """Areas of several frames: the area's frames must exist in the batch,
+    the loss box must lie in the area's frames, T >= 1 for the weights, no
+    transform parts, and the calls limited to two-dimensional areas refuse."""
+    L = B.lib()
+    fake = C.c_void_p(0x1000)
+    prm = B.se_params(0.5, 10, 0)
+    t = _tables_struct(K=2048, M=16, N=16)
+    t.T = 4
+    blk = (B.se_block * 1)(B.se_block(0, 0, 0, 4, 4, 8, 8, 0, 2, 1))
+
+    def batch(n_img, ws_bytes=16):
+        # a workspace too small for any batch: descriptors that pass every
+        # check end in SE_ENOMEM before anything touches a device
+        return L.se_extrapolate_batch(C.byref(t), fake, n_img, 64, 64, blk, 1, prm, None, None,
+                                      None, 0, fake, ws_bytes, None)
+    assert batch(3) == B.SE_EINVAL and b"frames" in L.se_last_error()   # frames 0..3 of 3
+    blk[0] = B.se_block(1, 0, 0, 4, 4, 8, 8, 0, 2, 2)                    # loss frames 2..3
+    assert batch(5) == B.SE_ENOMEM
+    blk[0] = B.se_block(1, 0, 0, 4, 4, 8, 8, 0, 3, 2)                    # loss frames 3..4
+    assert batch(5) == B.SE_EINVAL and b"loss frames" in L.se_last_error()
+    blk[0] = B.se_block(1, 0, 0, 4, 4, 8, 8, 0, -1, 1)
+    assert batch(5) == B.SE_EINVAL
+    blk[0] = B.se_block(1, 0, 0, 0, 0, 16, 16, 0, 0, 2)                  # 512 > 256 samples
+    assert batch(5) == B.SE_EINVAL and b"exceeds" in L.se_last_error()
+    # a two-dimensional table accepts only lt = 0 and ld <= 1
+    t2 = _tables_struct(K=2048, M=16, N=16)
+    blk[0] = B.se_block(0, 0, 0, 4, 4, 8, 8, 0, 0, 2)
+    assert L.se_extrapolate_batch(C.byref(t2), fake, 4, 64, 64, blk, 1, prm, None, None, None,
+                                  0, fake, 16, None) == B.SE_EINVAL
+    # weights
+    blk[0] = B.se_block(2, 0, 0, 4, 4, 8, 8, 0, 0, 1)
+    assert L.se_volume_weights(0, 8, 8, 0.8, fake, 4, 32, 32, blk, 1, fake, fake, 1 << 20,
+                               None) == B.SE_EINVAL
+    assert L.se_volume_weights(3, 8, 8, 0.8, fake, 4, 32, 32, blk, 1, fake, fake, 1 << 20,
+                               None) == B.SE_EINVAL                      # frames 2..4 of 4
+    # transform parts are two-dimensional
+    bas = B.make_basis(16, 16, 2048, 0x1000, [(B.SE_PART_DCT2, 0)], T=4)
+    t4 = _tables_struct(K=2048, M=16, N=16)
+    assert L.se_weighted_gram(C.byref(bas), fake, 0, 0, C.byref(t4), fake, 1 << 20,
+                              None) == B.SE_EINVAL
+    assert b"two-dimensional" in L.se_last_error()
+    # rows on demand take two-dimensional areas
+    bas = B.make_basis(16, 16, 2048, 0x1000, T=4)
+    r = L.se_extrapolate_ondemand(C.byref(bas), fake, fake, 8, 64, 64, blk, 1, prm, None,
+                                  None, None, None, 0, fake, 16, None)
+    assert r == B.SE_EINVAL and b"two-dimensional" in L.se_last_error()

@@ -1,0 +1,174 @@
+"""Areas of T consecutive video frames on the GPU (the three-dimensional model
+the paper's closing section extends the method to): the weights, the tables
+and the loop over T*M*N samples against the FP64 oracle, every route of the
+library bit for bit against the others, losses over several frames and areas
+that leave the frame."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2204_14194_amd import binding as B
+from paper_2204_14194_amd import synth
+
+from helpers import oracle_check_video
+from test_gpu_parity import TOL_FP32, dev, say, upload_phi
+
+pytestmark = pytest.mark.gpu
+
+TOL_BF16X3 = 1e-2
+
+
+def _tables(phi32, frames, blocks, T, M, N, ref_block=0, precision=B.SE_FP32):
+    F, H, W = frames.shape
+    lost = torch.from_numpy(synth.video_lost_mask(F, H, W, blocks)).to(dev())
+    w = B.area_weights(M, N, 0.8, lost, [blocks[ref_block]], T=T)
+    return B.weighted_gram(upload_phi(phi32), w[0].contiguous(), M, N, precision, T=T)
+
+
+def _batch(t, frames, blocks, iters, plain=False):
+    img = torch.from_numpy(frames).to(dev())
+    fn = B.extrapolate_plain if plain else B.extrapolate_batch
+    sel, coef, g = fn(t, img, blocks, 0.5, iters)
+    torch.cuda.synchronize()
+    return sel.cpu().numpy(), coef.cpu().numpy(), g.cpu().numpy(), img.cpu().numpy()
+
+
+def test_volume_weights_match_oracle():
+    F, H, W = 6, 40, 44
+    T, M, N = 3, 12, 10
+    blocks = [synth.Block(0, -4, 3, 5, 4, 4, 3, 1, 1), synth.Block(2, 10, 20, 4, 4, 5, 5, 0, 2),
+              synth.Block(3, 12, 24, 2, 2, 4, 4, 2, 1), synth.Block(1, 30, 38, 3, 3, 6, 5, 1, 1)]
+    say(f"volume weights: {len(blocks)} areas of {T}x{M}x{N}, across the border and "
+        "holding other losses")
+    lost = synth.video_lost_mask(F, H, W, blocks)
+    w = B.area_weights(M, N, 0.8, torch.from_numpy(lost).to(dev()), blocks, T=T).cpu().numpy()
+    assert w.shape == (len(blocks), T * M * N)
+    for i, b in enumerate(blocks):
+        _, sup = oracle.volume_signal(np.zeros((F, H, W), np.uint8), lost, b.img, b.y0, b.x0,
+                                      T, M, N)
+        ref = oracle.volume_weights(T, M, N, 0.8, sup)
+        np.testing.assert_array_equal(w[i] == 0, ref == 0)
+        np.testing.assert_allclose(w[i], ref, rtol=2e-6, atol=0)
+    # one frame: the two-dimensional call, bit for bit
+    w1 = B.area_weights(M, N, 0.8, torch.from_numpy(lost).to(dev()), blocks, T=1).cpu().numpy()
+    w2 = B.area_weights(M, N, 0.8, torch.from_numpy(lost).to(dev()), blocks).cpu().numpy()
+    np.testing.assert_array_equal(w1, w2)
+
+
+def test_video_gram_matches_oracle():
+    T, M, N = 4, 16, 16
+    say("video tables: 3-D DCT u WHT 4x16x16 (K=2048), one loss box")
+    phi = synth.round_to_f32(synth.video_dictionary(T, M, N))
+    sup = np.ones((T, M, N), bool)
+    sup[2, 4:12, 4:12] = False
+    w_ref = oracle.volume_weights(T, M, N, 0.8, sup).astype(np.float32).astype(np.float64)
+    t = B.weighted_gram(upload_phi(phi), torch.from_numpy(w_ref.astype(np.float32)).to(dev()),
+                        M, N, T=T)
+    torch.cuda.synchronize()
+    K = phi.shape[0]
+    G = t.G.cpu().numpy()[:, :K].astype(np.float64)
+    np.testing.assert_array_equal(G, G.T)
+    C_ref, D_ref = oracle.table_generation(phi, w_ref)
+    np.testing.assert_allclose(t.D.cpu().numpy(), D_ref, rtol=2e-6)
+    err = np.abs(G - D_ref[:, None] * C_ref * D_ref[None, :]).max()
+    print(f"max |G - G_oracle| = {err:.3g}")
+    assert err < 2e-5
+
+
+def test_video_batch_parity():
+    d = synth.video_inputs(1, frames=8)
+    T, M, N = d["T"], d["M"], d["N"]
+    say(f"video batch: {len(d['blocks'])} areas of {T}x{M}x{N}, K=2048, I=100")
+    phi = synth.round_to_f32(d["phi"])
+    t = _tables(phi, d["frames"], d["blocks"], T, M, N)
+    sel, coef, g, out = _batch(t, d["frames"], d["blocks"], 100)
+    st = oracle_check_video(d["frames"], d["blocks"], phi, T, M, N, 0.8, 0.5, 100, sel, g, out,
+                            tol=TOL_FP32)
+    print(f"identical selections {st['agree']}/{st['n']}, max|dg|={st['worst']:.3g}, "
+          f"min margin {st['margin']:.2g}")
+    assert st["worst"] <= TOL_FP32
+    # frames without losses are untouched
+    lost = synth.video_lost_mask(*d["frames"].shape, d["blocks"])
+    np.testing.assert_array_equal(out[lost == 0], d["frames"][lost == 0])
+
+
+def test_video_routes_agree():
+    """Batched, two-stage and device-descriptor calls give the same bits;
+    the per-block call (its projections a matrix-vector product, summed in
+    another order) the same selections and the model within the FP32 bar;
+    split-BF16 tables stay within their bar."""
+    d = synth.video_inputs(1, frames=8)
+    T, M, N = d["T"], d["M"], d["N"]
+    blocks = d["blocks"][:48]
+    say(f"video routes: {len(blocks)} areas of {T}x{M}x{N}")
+    phi = synth.round_to_f32(d["phi"])
+    t = _tables(phi, d["frames"], blocks, T, M, N)
+    sel0, coef0, g0, out0 = _batch(t, d["frames"], blocks, 60)
+    sel1, coef1, g1, out1 = _batch(t, d["frames"], blocks[:6], 60, plain=True)
+    np.testing.assert_array_equal(sel1, sel0[:6])
+    assert np.abs(g1 - g0[:6]).max() <= TOL_FP32
+    n = len(blocks)
+    img = torch.from_numpy(d["frames"]).to(dev())
+    db = B.DeviceBlocks(t, img, blocks)
+    R = torch.empty((n, t.ldR), dtype=torch.float32, device=dev())
+    ws = torch.empty(max(1, B.project_ws_bytes(t, n)), dtype=torch.uint8, device=dev())
+    sel = torch.zeros((n, 60), dtype=torch.int32, device=dev())
+    g = torch.zeros((n, g0.shape[1]), dtype=torch.float32, device=dev())
+    B.project(t, img, db, R, ws)
+    B.iterate(t, R, img, db, 0.5, 60, sel, None, g)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(sel.cpu().numpy(), sel0)
+    np.testing.assert_array_equal(g.cpu().numpy(), g0)
+    np.testing.assert_array_equal(img.cpu().numpy(), out0)
+    img2 = torch.from_numpy(d["frames"]).to(dev())
+    db2 = B.DeviceBlocks(t, img2, blocks)
+    nb = B.extrapolate_device_ws_bytes(t, n)
+    assert nb > 0
+    g2 = torch.zeros_like(g)
+    B.extrapolate_device(t, img2, db2, 0.5, 60, torch.empty(nb, dtype=torch.uint8, device=dev()),
+                         None, None, g2)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(g2.cpu().numpy(), g0)
+    # split-BF16 tables and projections
+    tb = _tables(phi, d["frames"], blocks, T, M, N, precision=B.SE_BF16X3)
+    selb, _, gb, outb = _batch(tb, d["frames"], blocks, 60)
+    st = oracle_check_video(d["frames"], blocks, phi, T, M, N, 0.8, 0.5, 60, selb, gb, outb,
+                            sample=range(0, n, 6), tol=TOL_BF16X3)
+    print(f"bf16x3: identical selections {st['agree']}/{st['n']}, max|dg|={st['worst']:.3g}")
+
+
+def test_video_loss_boxes_and_border_areas():
+    """Losses over two frames with more samples than the workgroup has lanes,
+    losses in the first and last frame of the area, and areas that leave the
+    frame (each block concealed with the tables of its own weights)."""
+    T, M, N = 2, 8, 8
+    F, H, W = 6, 30, 34
+    frames = synth.synth_video(F, H, W, seed=77)
+    blocks = [synth.Block(0, -3, -2, 1, 0, 6, 8, 0, 2),      # 96 samples, across the corner
+              synth.Block(2, 10, 12, 2, 2, 4, 5, 1, 1),     # loss in the last frame
+              synth.Block(4, 24, 28, 0, 1, 5, 4, 0, 1),     # across the far border
+              synth.Block(3, 14, 2, 3, 3, 2, 2, 0, 2)]
+    say(f"video loss boxes: {len(blocks)} areas of {T}x{M}x{N}, K=256, per-block tables")
+    phi = synth.round_to_f32(synth.video_dictionary(T, M, N))
+    lost = torch.from_numpy(synth.video_lost_mask(F, H, W, blocks)).to(dev())
+    w = B.area_weights(M, N, 0.8, lost, blocks, T=T)
+    out = frames.copy()
+    sels, gs = [], []
+    for i, b in enumerate(blocks):
+        t = B.weighted_gram(upload_phi(phi), w[i].contiguous(), M, N, T=T)
+        img = torch.from_numpy(out).to(dev())
+        sel, _, g = B.extrapolate_batch(t, img, [b], 0.5, 40)
+        torch.cuda.synchronize()
+        out = img.cpu().numpy()
+        sels.append(sel.cpu().numpy()[0])
+        gs.append(g.cpu().numpy()[0])
+    gl = max(len(x) for x in gs)
+    g_all = np.stack([np.pad(x, (0, gl - len(x))) for x in gs])
+    st = oracle_check_video(frames, blocks, phi, T, M, N, 0.8, 0.5, 40, np.stack(sels), g_all,
+                            out, tol=TOL_FP32)
+    print(f"identical selections {st['agree']}/{st['n']}, max|dg|={st['worst']:.3g}")
+    assert st["worst"] <= TOL_FP32
+    # samples outside every loss are untouched
+    keep = synth.video_lost_mask(F, H, W, blocks) == 0
+    np.testing.assert_array_equal(out[keep], frames[keep])
