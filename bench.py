@@ -176,7 +176,8 @@ def main():
     ap.add_argument("--plain-reps", type=int, default=2,
                     help="passes of the plain per-block form over one image's 16 blocks")
     ap.add_argument("--config", default="area32",
-                    choices=["area32", "area48", "clustered", "area64", "serving", "dft32"],
+                    choices=["area32", "area48", "clustered", "area64", "serving", "dft32",
+                             "video"],
                     help="area32 (default) is the headline line; the others measure the "
                          "secondary workloads")
     ap.add_argument("--frames", type=int, default=120, help="serving: frames per arrival rate")
@@ -577,6 +578,72 @@ def bench_dft32(args):
                         "gram_ms": min(gram)}}
 
 
+def bench_video(args):
+    """Areas of T = 4 consecutive frames (the three-dimensional model): 16x16
+    pixels x 4 frames, a centred 8x8 loss in frame 2 of each area, K = 2048
+    (3-D DCT-II u 3-D WHT over 4x16x16), I = 100; 64-frame 128x128 videos
+    (one per 64 images of --images), 1024 blocks each; projections and loop
+    as two launches.  The two halves are declared as transform parts, so the
+    projections are separable transforms of the four frames stacked
+    (--no-parts: the FP32 GEMM over all atoms)."""
+    import torch
+    from paper_2204_14194_amd import binding as B
+    dev = torch.device("cuda:0")
+    n_vid = max(1, args.images // 64)
+    d = synth.video_inputs(n_vid, frames=64)
+    T, Mv, Nv = d["T"], d["M"], d["N"]
+    blocks = d["blocks"]
+    n = len(blocks)
+    frames = d["frames"]
+    lost = synth.video_lost_mask(*frames.shape, blocks)
+    w = B.area_weights(Mv, Nv, RHO, torch.from_numpy(lost).to(dev), blocks[:1], T=T)
+    phi = torch.from_numpy(d["phi"].astype(np.float32)).to(dev)
+    gram = []
+    for _ in range(3):
+        e0, e1 = _events(2)
+        e0.record()
+        t = B.weighted_gram(phi, w[0].contiguous(), Mv, Nv, T=T,
+                            parts=() if args.no_parts else d["tx_parts"])
+        e1.record()
+        e1.synchronize()
+        gram.append(e0.elapsed_time(e1))
+    img = torch.from_numpy(frames).to(dev)
+    db = B.DeviceBlocks(t, img, blocks)
+    R = torch.empty((n, t.ldR), dtype=torch.float32, device=dev)
+    ws = torch.empty(max(1, B.project_ws_bytes(t, n)), dtype=torch.uint8, device=dev)
+    proj = _timed(lambda: B.project(t, img, db, R, ws), args.steps, args.warmup)
+    loop = _timed(lambda: B.iterate(t, R, img, db, GAMMA, ITERS), args.steps, args.warmup)
+
+    def step():
+        B.project(t, img, db, R, ws)
+        B.iterate(t, R, img, db, GAMMA, ITERS)
+    ms = _timed(step, args.steps, args.warmup)
+    med = float(np.median(ms))
+    loop_ms, proj_ms = float(np.median(loop)), float(np.median(proj))
+    P = T * Mv * Nv
+    # per iteration a row of G and the atom over the loss; R^(0) once
+    bytes_per_block = ITERS * (K_ATOMS + 64) * 4 + K_ATOMS * 4
+    # dense: the product with every atom; transform parts: the separable
+    # transform of each half, (T M + N) multiply-adds per sample and part
+    proj_flops = (2.0 * K_ATOMS * P if args.no_parts else 2.0 * 2 * P * (T * Mv + Nv)) * n
+    return {"metric": "concealed blocks/s, areas of 4 video frames, K=2048, I=100",
+            "value": n / (med * 1e-3), "unit": "blocks/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": med,
+            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{n_vid} seeded videos x 64 frames of 128x128, areas of "
+                                   f"4 frames x 16x16 with a centred 8x8 loss in frame 2, "
+                                   f"{n} blocks, K=2048 (3-D DCT-II u 3-D WHT 4x16x16), "
+                                   f"I=100",
+                       "projection": "dense FP32 GEMM" if args.no_parts else
+                                     "separable transforms of the stacked frames"},
+            "latency_ms": {"p50": percentile(ms, 50), "p99": percentile(ms, 99)},
+            "kernels": {"project_ms": proj_ms,
+                        "project_tflops": proj_flops / (proj_ms * 1e-3) / 1e12,
+                        "loop_ms": loop_ms,
+                        "loop_gbs": bytes_per_block * n / (loop_ms * 1e-3) / 1e9,
+                        "loop_bytes_per_block": bytes_per_block, "gram_ms": min(gram)}}
+
+
 def bench_clustered(args):
     """Uneven batch: 8 1024x1024 frames with clustered/burst losses, 4000
     blocks, areas 24/32/48, per-block weights (rows on demand), I ~ U{100..200}."""
@@ -739,7 +806,7 @@ def bench_serving(args):
 
 
 SECONDARY = {"area48": bench_area48, "clustered": bench_clustered, "area64": bench_area64,
-             "serving": bench_serving, "dft32": bench_dft32}
+             "serving": bench_serving, "dft32": bench_dft32, "video": bench_video}
 
 
 if __name__ == "__main__":

@@ -82,7 +82,13 @@ typedef enum { SE_FP32 = 0, SE_BF16X3 = 1 } se_precision;
  *   SE_PART_WHT2: Walsh-Hadamard rows in natural (Sylvester) order,
  *                 (-1)^popcount(m & k) / sqrt(M); M and N powers of two
  * Parts need M, N <= 64; se_weighted_gram checks every declared atom
- * against phi (|difference| <= 2e-6) and fails with SE_EINVAL otherwise. */
+ * against phi (|difference| <= 2e-6) and fails with SE_EINVAL otherwise.
+ * For areas of T > 1 frames a part holds the separable 3-D atoms: the same
+ * 1-D transform along frames, rows and columns, atom (kt*M + k1)*N + k2 =
+ * row kt of the T-point transform times row k1 of the M-point one times row
+ * k2 of the N-point one (powers of two T, M, N for Walsh-Hadamard); the
+ * library transforms the frames stacked as a T*M x N area, so T*M <= 64,
+ * and M must be a power of two. */
 #define SE_PART_DCT2 1
 #define SE_PART_WHT2 2
 typedef struct {
@@ -99,11 +105,10 @@ typedef struct {
  * (se_extrapolate_batch, se_project/se_iterate, se_extrapolate_device);
  * the other calls refuse them (SE_EINVAL).
  * T: frames per area (0 or 1: a two-dimensional area).  With T > 1 the
- * atoms are K x (T*M*N) (sample (tau, m, n) at (tau*M + m)*N + n), the
- * dictionary declares no transform parts, and it is concealed by the
- * batched calls, se_project/se_iterate, se_extrapolate_device and
- * se_extrapolate_plain; rows on demand and the server refuse it, and it
- * must be real (phi_im NULL). */
+ * atoms are K x (T*M*N) (sample (tau, m, n) at (tau*M + m)*N + n), and
+ * the dictionary is concealed by the batched calls, se_project/se_iterate,
+ * se_extrapolate_device and se_extrapolate_plain; rows on demand and the
+ * server refuse it, and it must be real (phi_im NULL). */
 typedef struct {
   int32_t M, N, K;
   const float* phi;
@@ -211,7 +216,8 @@ int32_t se_version(void);
 int32_t se_table_ld(int32_t K);
 /* Size of the transform operand buffer se_tables.tx for an M x N area with
  * n_parts declared transform parts; 0 if n_parts is 0 or out of range, or
- * M or N outside 1..64. */
+ * M or N outside 1..64.  For areas of T frames pass T*M as M (the frames
+ * are transformed stacked). */
 size_t se_tables_tx_bytes(int32_t M, int32_t N, int32_t n_parts);
 
 /* ------------------------------------------------------------------------ */

@@ -323,9 +323,9 @@ def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
         t.Ylo = torch.empty((K, P), dtype=torch.int16, device=dev)
     t.parts = _parts_arg(parts)
     if t.parts:
-        nb_tx = int(L.se_tables_tx_bytes(M, N, len(t.parts)))
+        nb_tx = int(L.se_tables_tx_bytes(int(T) * M, N, len(t.parts)))
         if nb_tx == 0:
-            raise ValueError(f"no transform parts for a {M}x{N} area")
+            raise ValueError(f"no transform parts for a {T}x{M}x{N} area")
         t.tx = torch.empty(nb_tx // 4, dtype=torch.float32, device=dev)
     b = make_basis(M, N, K, phi.data_ptr(), t.parts,
                    phi_im.data_ptr() if phi_im is not None else None, int(T))

@@ -49,19 +49,22 @@ static se_status upload_blocks(const se_block* blocks, int n_blk, DevBlock* dst,
 static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 // Declared transform parts: known kinds, inside [0, K), disjoint, areas up to
-// 64 x 64 (powers of two for Walsh-Hadamard), of one frame.
+// 64 x 64 (powers of two for Walsh-Hadamard); an area of T frames is
+// transformed with its frames stacked, so T M <= 64.
 static se_status check_parts(int T, int M, int N, int K, int n_parts, const se_part* parts) {
   if (n_parts < 0 || n_parts > 2) return fail(SE_EINVAL, "n_parts=%d must be 0, 1 or 2", n_parts);
   if (n_parts == 0) return SE_OK;
-  if (T > 1) return fail(SE_EINVAL, "transform parts are two-dimensional (T=%d)", T);
-  if (M > 64 || N > 64) return fail(SE_EINVAL, "transform parts need M, N <= 64 (got %dx%d)", M, N);
-  const int P = M * N;
+  if ((long long)T * M > 64 || N > 64)
+    return fail(SE_EINVAL, "transform parts need T M, N <= 64 (got %dx%dx%d)", T, M, N);
+  if (T > 1 && !is_pow2(M))
+    return fail(SE_EINVAL, "transform parts of areas of several frames need a power-of-two M");
+  const int P = T * M * N;
   for (int q = 0; q < n_parts; ++q) {
     const se_part& p = parts[q];
     if (p.kind != SE_PART_DCT2 && p.kind != SE_PART_WHT2)
       return fail(SE_EINVAL, "part %d: unknown kind %d", q, p.kind);
-    if (p.kind == SE_PART_WHT2 && (!is_pow2(M) || !is_pow2(N)))
-      return fail(SE_EINVAL, "part %d: Walsh-Hadamard needs power-of-two M, N", q);
+    if (p.kind == SE_PART_WHT2 && (!is_pow2(T) || !is_pow2(M) || !is_pow2(N)))
+      return fail(SE_EINVAL, "part %d: Walsh-Hadamard needs power-of-two T, M, N", q);
     if (p.first < 0 || (long long)p.first + P > K)
       return fail(SE_EINVAL, "part %d: atoms %d .. %d outside the dictionary", q, p.first,
                   p.first + P - 1);
@@ -128,7 +131,7 @@ static size_t project_splitk_floats(const se_tables* t, int n_blk) {
   if (t->n_parts == 0) return gemm_splitk_floats(greedy_row_len(t->K), n_blk, P);
   if (t->n_parts > 2) return 0;
   int lo[3], hi[3];
-  const int nr = dense_ranges(t->K, t->M, t->N, t->n_parts, t->parts, lo, hi);
+  const int nr = dense_ranges(t->K, P, t->n_parts, t->parts, lo, hi);
   size_t f = 0;
   for (int r = 0; r < nr; ++r) f = std::max(f, gemm_splitk_floats(hi[r] - lo[r], n_blk, P));
   return f;
@@ -150,8 +153,7 @@ static size_t project_ws(const se_tables* t, int n_blk) {
 }
 
 // Atom ranges [lo, hi) not covered by transform parts.
-int dense_ranges(int K, int M, int N, int n_parts, const se_part* parts, int lo[3], int hi[3]) {
-  const int P = M * N;
+int dense_ranges(int K, int P, int n_parts, const se_part* parts, int lo[3], int hi[3]) {
   int f[2] = {0, 0}, n = n_parts;
   for (int q = 0; q < n; ++q) f[q] = parts[q].first;
   if (n == 2 && f[1] < f[0]) std::swap(f[0], f[1]);
@@ -172,7 +174,8 @@ static se_status verify_parts(const se_basis* b, int32_t* flag, hipStream_t s) {
   if (hipMemsetAsync(flag, 0, sizeof(int32_t), s) != hipSuccess)
     return fail(SE_EHIP, "flag clear failed");
   for (int q = 0; q < b->n_parts; ++q)
-    if ((st = check_part(b->phi, b->M, b->N, b->parts[q].kind, b->parts[q].first, flag, s)))
+    if ((st = check_part(b->phi, area_frames(b->T), b->M, b->N, b->parts[q].kind,
+                         b->parts[q].first, flag, s)))
       return st;
   int32_t bad = 0;
   if (hipMemcpyAsync(&bad, flag, sizeof(bad), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -193,7 +196,7 @@ static se_status project_into(const se_tables* t, const uint8_t* images, int H, 
   int nr = 1;
   if (t->n_parts > 0) {
     if ((st = project_tx(t, images, H, W, dblk, n_blk, R, ldR, s))) return st;
-    nr = dense_ranges(t->K, t->M, t->N, t->n_parts, t->parts, lo, hi);
+    nr = dense_ranges(t->K, P, t->n_parts, t->parts, lo, hi);
     if (nr == 0) return SE_OK;
   }
   const bool pad = t->n_parts == 0;   // else the transform kernel wrote the padding
@@ -394,7 +397,7 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
   // dense atoms, and a mirror pass fills the parts' rows over the dense
   // columns; otherwise the whole table is one symmetric product.
   int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-  const int nr = t->n_parts > 0 ? dense_ranges(K, b->M, b->N, t->n_parts, t->parts, lo, hi) : 3;
+  const int nr = t->n_parts > 0 ? dense_ranges(K, P, t->n_parts, t->parts, lo, hi) : 3;
   if (nr <= 1 && (lo[0] & 3) == 0) {
     if ((st = gram_tx(t, s))) return st;
     if (nr == 1) {
@@ -617,7 +620,7 @@ static size_t ondemand_splitk_floats(const se_basis* b, int n_blk) {
   size_t f = gemm_splitk_floats(ld, n_blk, P);
   if (b->n_parts > 0 && b->n_parts <= 2) {
     int lo[3], hi[3];
-    const int nr = dense_ranges(b->K, b->M, b->N, b->n_parts, b->parts, lo, hi);
+    const int nr = dense_ranges(b->K, P, b->n_parts, b->parts, lo, hi);
     for (int r = 0; r < nr; ++r) f = std::max(f, gemm_splitk_floats(hi[r] - lo[r], n_blk, P));
   }
   return f;

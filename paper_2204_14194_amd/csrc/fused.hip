@@ -90,9 +90,11 @@ static int conceal_case(int M, int N, int n_parts) {
 }
 
 bool conceal_tx_supported(const se_tables* t) {
-  if (!t || t->n_parts < 1 || !t->tx || conceal_case(t->M, t->N, t->n_parts) == 0) return false;
+  if (!t || t->n_parts < 1 || !t->tx || area_frames(t->T) > 1 ||
+      conceal_case(t->M, t->N, t->n_parts) == 0)
+    return false;
   int lo[3], hi[3];
-  return dense_ranges(t->K, t->M, t->N, t->n_parts, t->parts, lo, hi) == 0;
+  return dense_ranges(t->K, t->M * t->N, t->n_parts, t->parts, lo, hi) == 0;
 }
 
 se_status conceal_tx(const se_tables* t, const GreedyArgs& a, const uint8_t* images, int H, int W,
@@ -116,6 +118,7 @@ se_status conceal_tx(const se_tables* t, const GreedyArgs& a, const uint8_t* ima
   x.tx = t->tx;
   x.first0 = t->parts[0].first;
   x.first1 = t->n_parts > 1 ? t->parts[1].first : 0;
+  x.fs = 0;   // one frame (the two-dimensional loaders)
   const TxLayout L(t->M, t->N, t->n_parts, 0);
   const int key = conceal_case(t->M, t->N, t->n_parts) * 10000 + waves * 100 + vpl;
   switch (key) {

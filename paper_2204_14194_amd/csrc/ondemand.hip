@@ -241,7 +241,7 @@ se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s) {
   const se_basis* bs = pl.basis;
   const bool tx = bs && bs->n_parts > 0;
   int lo[3] = {0, 0, 0}, hi[3] = {K, 0, 0};
-  const int nr = tx ? dense_ranges(K, pl.M, pl.N, bs->n_parts, bs->parts, lo, hi) : 1;
+  const int nr = tx ? dense_ranges(K, pl.M * pl.N, bs->n_parts, bs->parts, lo, hi) : 1;
   if (tx) {   // the row products no longer write the padding columns
     hipLaunchKernelGGL(k_fill0, dim3((unsigned)(((size_t)n * pl.ld + 255) / 256)), dim3(256), 0, s,
                        pl.rows, (size_t)n * pl.ld);

@@ -42,6 +42,8 @@ using DevBlock = se_block;
 inline int area_frames(int T) { return T < 1 ? 1 : T; }
 // samples per area of a table set: T M N
 inline int area_samples(const se_tables* t) { return area_frames(t->T) * t->M * t->N; }
+// rows of the area as transformed: the T frames of M rows stacked (T M)
+inline int tx_rows(const se_tables* t) { return area_frames(t->T) * t->M; }
 
 // Loss sample i of a block (i < ld lh lw, frames, then rows, then columns):
 // its index in the area's sample vector (T x M x N, (tau M + m) N + n), and
@@ -124,7 +126,8 @@ void launch_gather_split(const uint8_t* images, int H, int W, const DevBlock* bl
 
 // transform.hip -- declared transform parts of a dictionary (Section VI)
 // sets *dflag (device) to 1 if an atom of the part differs from its definition
-se_status check_part(const float* phi, int M, int N, int kind, int first, int* dflag,
+// (T frames of Ms rows stacked: the vertical transform is A_T (x) A_Ms)
+se_status check_part(const float* phi, int T, int Ms, int N, int kind, int first, int* dflag,
                      hipStream_t s);
 // R[b][first + k] of every part of t, and 0 in columns K .. ldR-1
 se_status project_tx(const se_tables* t, const uint8_t* images, int H, int W,
@@ -146,7 +149,8 @@ se_status rows_tx(const se_basis* b, const float* tx, const float* V, int ldV, i
 // abi.cpp -- the host-side checks of a basis' part declaration; the atom
 // ranges outside the parts
 se_status check_basis_parts(const se_basis* b);
-int dense_ranges(int K, int M, int N, int n_parts, const se_part* parts, int lo[3], int hi[3]);
+// (P: samples per atom, the length of a part)
+int dense_ranges(int K, int P, int n_parts, const se_part* parts, int lo[3], int hi[3]);
 
 // greedy.hip -- the iteration loop of Algorithm 3
 struct GreedyArgs {

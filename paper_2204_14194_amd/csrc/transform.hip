@@ -10,6 +10,11 @@
 //   DCT-II:  A[k][m] = alpha_k cos(pi (2m+1) k / 2M), alpha_0 = 1/sqrt(M),
 //            alpha_k = sqrt(2/M); row M/2 takes its exact values +-1/sqrt(M)
 //   WHT:     A[k][m] = (-1)^popcount(k & m) / sqrt(M), natural order
+// An area of T > 1 frames is transformed as the T M x N matrix of its
+// frames stacked row-wise (sample (tau, m, n) at row tau M + m): the 3-D
+// separable transform is then the 2-D one with the vertical matrix the
+// Kronecker product A_T (x) A_M, entry (kt M + k1, tau M + m) =
+// A_T[kt][tau] A_M[k1][m] (formed in FP64, rounded once).
 #include <atomic>
 
 #include "se_internal.h"
@@ -25,34 +30,58 @@ __device__ void build_cos_table(int n, double* ct) {
   for (int j = threadIdx.x; j < 4 * n; j += blockDim.x) ct[j] = cospi((double)j / (double)(2 * n));
 }
 
-// Entry (k, m) of the n-point 1-D transform of `kind`.  ct from
+// Entry (k, m) of the n-point 1-D transform of `kind`, in FP64.  ct from
 // build_cos_table; inv = 1/sqrt(n), a2 = sqrt(2/n) (FP64).
+__device__ inline double basis_1d_d(int kind, int n, int k, int m, const double* ct, double inv,
+                                    double a2) {
+  if (kind == SE_PART_WHT2) return (__popc(k & m) & 1) ? -inv : inv;
+  if (k == 0) return inv;
+  if (2 * k == n) return ((m & 3) == 0 || (m & 3) == 3) ? inv : -inv;
+  return a2 * ct[((2 * m + 1) * k) % (4 * n)];
+}
+
 __device__ inline float basis_1d(int kind, int n, int k, int m, const double* ct, double inv,
                                  double a2) {
-  if (kind == SE_PART_WHT2) return (float)((__popc(k & m) & 1) ? -inv : inv);
-  if (k == 0) return (float)inv;
-  if (2 * k == n) return (float)(((m & 3) == 0 || (m & 3) == 3) ? inv : -inv);
-  return (float)(a2 * ct[((2 * m + 1) * k) % (4 * n)]);
+  return (float)basis_1d_d(kind, n, k, m, ct, inv, a2);
 }
+
+// The vertical transform of a stack of T frames of Ms rows (M = T Ms rows
+// in all): entry (k, m); the 1-D matrix itself when T = 1.  ctT, ctS:
+// cosine tables of T and Ms points.
+struct VertBasis {
+  int T, Ms;
+  const double* ctT;
+  const double* ctS;
+  __device__ float operator()(int kind, int k, int m) const {
+    const double iS = 1.0 / sqrt((double)Ms), aS = sqrt(2.0 / (double)Ms);
+    if (T == 1) return basis_1d(kind, Ms, k, m, ctS, iS, aS);
+    const double iT = 1.0 / sqrt((double)T), aT = sqrt(2.0 / (double)T);
+    return (float)(basis_1d_d(kind, T, k / Ms, m / Ms, ctT, iT, aT) *
+                   basis_1d_d(kind, Ms, k % Ms, m % Ms, ctS, iS, aS));
+  }
+};
 
 // ---------------------------------------------------------------------------
 // Verification of a declared part against phi: every atom k of the part,
-// every pixel (m, n), |phi[first + k][m N + n] - A[k1][m] B[k2][n]| <= tol.
-__global__ __launch_bounds__(kTxThreads) void k_check_part(const float* __restrict__ phi, int M,
-                                                          int N, int kind, int first, float tol,
-                                                          int* __restrict__ flag) {
+// every pixel (m, n), |phi[first + k][m N + n] - A[k1][m] B[k2][n]| <= tol
+// (M = T Ms rows: T frames of Ms rows, A the vertical transform above).
+__global__ __launch_bounds__(kTxThreads) void k_check_part(const float* __restrict__ phi, int T,
+                                                          int Ms, int N, int kind, int first,
+                                                          float tol, int* __restrict__ flag) {
   extern __shared__ double smd[];
-  double* ctM = smd;              // 4M
-  double* ctN = ctM + 4 * M;      // 4N
-  float* A = reinterpret_cast<float*>(ctN + 4 * N);   // M x M
+  const int M = T * Ms;
+  double* ctS = smd;              // 4 Ms
+  double* ctN = ctS + 4 * Ms;     // 4N
+  double* ctT = ctN + 4 * N;      // 4T
+  float* A = reinterpret_cast<float*>(ctT + 4 * T);   // M x M
   float* Bm = A + M * M;                               // N x N
-  build_cos_table(M, ctM);
+  build_cos_table(Ms, ctS);
   build_cos_table(N, ctN);
+  build_cos_table(T, ctT);
   __syncthreads();
-  const double iM = 1.0 / sqrt((double)M), aM = sqrt(2.0 / (double)M);
   const double iN = 1.0 / sqrt((double)N), aN = sqrt(2.0 / (double)N);
-  for (int i = threadIdx.x; i < M * M; i += blockDim.x)
-    A[i] = basis_1d(kind, M, i / M, i % M, ctM, iM, aM);
+  const VertBasis vb{T, Ms, ctT, ctS};
+  for (int i = threadIdx.x; i < M * M; i += blockDim.x) A[i] = vb(kind, i / M, i % M);
   for (int i = threadIdx.x; i < N * N; i += blockDim.x)
     Bm[i] = basis_1d(kind, N, i / N, i % N, ctN, iN, aN);
   __syncthreads();
@@ -74,6 +103,7 @@ __global__ __launch_bounds__(kTxThreads) void k_check_part(const float* __restri
 // se_tables.tx, every workgroup computing a slice.
 struct TxBuildArgs {
   int M, N, parts;
+  int T, Ms;   // M = T Ms: frames of Ms rows stacked
   int kind0, kind1, first0, first1;
   const float* D;
   const float* sqrtw;
@@ -81,15 +111,17 @@ struct TxBuildArgs {
 };
 
 __global__ __launch_bounds__(kTxThreads) void k_build_tx(TxBuildArgs a, TxLayout L) {
-  extern __shared__ double ctab[];   // 4M + 4N cosines
-  double* ctM = ctab;
-  double* ctN = ctab + 4 * a.M;
-  build_cos_table(a.M, ctM);
+  extern __shared__ double ctab[];   // 4 Ms + 4N + 4T cosines
+  double* ctS = ctab;
+  double* ctN = ctS + 4 * a.Ms;
+  double* ctT = ctN + 4 * a.N;
+  build_cos_table(a.Ms, ctS);
   build_cos_table(a.N, ctN);
+  build_cos_table(a.T, ctT);
   __syncthreads();
   const int M = a.M, N = a.N, MT = L.MT, NT = L.NT;
-  const double iM = 1.0 / sqrt((double)M), aM = sqrt(2.0 / (double)M);
   const double iN = 1.0 / sqrt((double)N), aN = sqrt(2.0 / (double)N);
+  const VertBasis vb{a.T, a.Ms, ctT, ctS};
   const int nA = MT * MT * 256, nB = NT * NT * 256, nD = MT * NT * 256;
   for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < L.nconst; x += gridDim.x * blockDim.x) {
     float v = 0.0f;
@@ -98,7 +130,7 @@ __global__ __launch_bounds__(kTxThreads) void k_build_tx(TxBuildArgs a, TxLayout
       const int e = y & 3, l = (y >> 2) & 63, ri = y >> 8;
       const int r = ri / MT, i = ri - r * MT;
       const int row = 16 * r + (l & 15), col = 16 * i + 4 * (l >> 4) + e;
-      if (row < M && col < M) v = basis_1d(q ? a.kind1 : a.kind0, M, row, col, ctM, iM, aM);
+      if (row < M && col < M) v = vb(q ? a.kind1 : a.kind0, row, col);
     } else if (x < L.oDf) {                 // Btf
       const int z = x - L.oBtf, q = z / nB, y = z - q * nB;
       const int t = y & 3, l = (y >> 2) & 63, cs = y >> 8;
@@ -127,7 +159,7 @@ __global__ __launch_bounds__(kTxThreads) void k_build_tx(TxBuildArgs a, TxLayout
   }
 }
 
-template <int MT, int NT, int NP, bool STAGE>
+template <int MT, int NT, int NP, bool STAGE, bool VOL>
 __global__ __launch_bounds__((tx_max_threads<MT, NT>())) void k_project_tx(TxArgs a, TxLayout L) {
   extern __shared__ floatx4 smv[];
   float* sm = reinterpret_cast<float*>(smv);
@@ -139,7 +171,7 @@ __global__ __launch_bounds__((tx_max_threads<MT, NT>())) void k_project_tx(TxArg
   int b = blockIdx.x * W + wave;
   DevBlock d = a.blk[b < a.n_blk ? b : 0];
   TxPixels<MT, NT> P;
-  tx_load<MT, NT>(a, d, M, N, P);
+  tx_load<MT, NT, VOL>(a, d, M, N, P);
   {
     const floatx4* src = reinterpret_cast<const floatx4*>(a.tx);
     for (int x = threadIdx.x; x < L.nconst / 4; x += blockDim.x) smv[x] = src[x];
@@ -148,10 +180,10 @@ __global__ __launch_bounds__((tx_max_threads<MT, NT>())) void k_project_tx(TxArg
   for (bool first = true; b < a.n_blk; b += gridDim.x * W, first = false) {
     if (!first) {
       d = a.blk[b];
-      tx_load<MT, NT>(a, d, M, N, P);
+      tx_load<MT, NT, VOL>(a, d, M, N, P);
     }
     floatx4 xv[MT][NT];
-    tx_x_operands<MT, NT>(a, d, M, N, P, sm + L.oWf, Xf, xv);
+    tx_x_operands<MT, NT, VOL>(a, d, M, N, P, sm + L.oWf, Xf, xv);
     float* Rb = a.R + (size_t)b * a.ldR;
     for (int k = a.K + l; k < a.ldR; k += 64) Rb[k] = 0.0f;
 #pragma unroll 1
@@ -360,13 +392,14 @@ __global__ __launch_bounds__(256) void k_gram_mirror(float* __restrict__ G, int 
   }
 }
 
-se_status check_part(const float* phi, int M, int N, int kind, int first, int* dflag,
+se_status check_part(const float* phi, int T, int Ms, int N, int kind, int first, int* dflag,
                      hipStream_t s) {
-  const size_t lds = (size_t)4 * (M + N) * 8 + (size_t)(M * M + N * N) * 4;
+  const int M = T * Ms;
+  const size_t lds = (size_t)4 * (Ms + N + T) * 8 + (size_t)(M * M + N * N) * 4;
   const int P = M * N;
   const int grid = P < 2048 ? P : 2048;
-  hipLaunchKernelGGL(k_check_part, dim3(grid), dim3(kTxThreads), lds, s, phi, M, N, kind, first,
-                     2e-6f, dflag);
+  hipLaunchKernelGGL(k_check_part, dim3(grid), dim3(kTxThreads), lds, s, phi, T, Ms, N, kind,
+                     first, 2e-6f, dflag);
   return check_launch("check_part");
 }
 
@@ -377,7 +410,9 @@ size_t tx_const_bytes(int M, int N, int n_parts) {
 
 se_status build_tx(const se_tables* t, hipStream_t s) {
   TxBuildArgs a;
-  a.M = t->M;
+  a.T = area_frames(t->T);
+  a.Ms = t->M;
+  a.M = tx_rows(t);
   a.N = t->N;
   a.parts = t->n_parts;
   a.kind0 = t->parts[0].kind;
@@ -387,15 +422,17 @@ se_status build_tx(const se_tables* t, hipStream_t s) {
   a.D = t->D;
   a.sqrtw = t->sqrtw;
   a.tx = t->tx;
-  const TxLayout L(t->M, t->N, t->n_parts, 0);
+  const TxLayout L(a.M, t->N, t->n_parts, 0);
   const int grid = (L.nconst + kTxThreads - 1) / kTxThreads;
-  hipLaunchKernelGGL(k_build_tx, dim3(grid), dim3(kTxThreads), (size_t)4 * (t->M + t->N) * 8, s,
-                     a, L);
+  hipLaunchKernelGGL(k_build_tx, dim3(grid), dim3(kTxThreads),
+                     (size_t)4 * (a.Ms + a.N + a.T) * 8, s, a, L);
   return check_launch("build_tx");
 }
 
 se_status build_tx_basis(const se_basis* b, float* tx, hipStream_t s) {
   TxBuildArgs a;
+  a.T = 1;    // rows on demand: two-dimensional areas
+  a.Ms = b->M;
   a.M = b->M;
   a.N = b->N;
   a.parts = b->n_parts;
@@ -408,8 +445,8 @@ se_status build_tx_basis(const se_basis* b, float* tx, hipStream_t s) {
   a.tx = tx;
   const TxLayout L(b->M, b->N, b->n_parts, 0);
   const int grid = (L.oDf + kTxThreads - 1) / kTxThreads;
-  hipLaunchKernelGGL(k_build_tx, dim3(grid), dim3(kTxThreads), (size_t)4 * (b->M + b->N) * 8, s,
-                     a, L);
+  hipLaunchKernelGGL(k_build_tx, dim3(grid), dim3(kTxThreads),
+                     (size_t)4 * (a.Ms + a.N + a.T) * 8, s, a, L);
   return check_launch("build_tx_basis");
 }
 
@@ -449,12 +486,13 @@ se_status gram_tx(const se_tables* t, hipStream_t s) {
   a.first1 = t->n_parts > 1 ? t->parts[1].first : 0;
   a.G = t->G;
   a.ldG = t->ldG;
-  const int waves = tx_waves(t->M, t->N, t->n_parts, t->K);
-  if (waves == 0) return fail(SE_EINVAL, "transform of a %dx%d area exceeds LDS", t->M, t->N);
+  const int Mv = tx_rows(t);
+  const int waves = tx_waves(Mv, t->N, t->n_parts, t->K);
+  if (waves == 0) return fail(SE_EINVAL, "transform of a %dx%d area exceeds LDS", Mv, t->N);
   const bool stage = (t->N & 3) == 0 && (a.first0 & 3) == 0 && (a.first1 & 3) == 0 &&
                      (t->ldG & 3) == 0 &&
-                     TxLayout(t->M, t->N, t->n_parts, waves, true).bytes() <= 160 * 1024;
-  const TxLayout L(t->M, t->N, t->n_parts, waves, stage);
+                     TxLayout(Mv, t->N, t->n_parts, waves, true).bytes() <= 160 * 1024;
+  const TxLayout L(Mv, t->N, t->n_parts, waves, stage);
   const size_t lds = L.bytes();
   const int per_cu = (int)std::min<size_t>(4, (160 * 1024) / lds);
   const int grid = std::max(1, std::min((t->K + waves - 1) / waves, 256 * per_cu));
@@ -475,7 +513,7 @@ se_status gram_tx(const se_tables* t, hipStream_t s) {
 }
 
 se_status gram_mirror(const se_tables* t, hipStream_t s) {
-  const int P = t->M * t->N;
+  const int P = area_samples(t);
   const int p0 = t->parts[0].first;
   const int q0 = t->n_parts > 1 ? t->parts[1].first : p0;
   const int nb = (t->K + 31) / 32;
@@ -498,7 +536,7 @@ size_t tx_lds_bytes(int M, int N, int n_parts) {
   return w ? TxLayout(M, N, n_parts, w).bytes() : 0;
 }
 
-template <int MT, int NT, int NP, bool STAGE>
+template <int MT, int NT, int NP, bool STAGE, bool VOL>
 static se_status launch_tx(const TxArgs& a, const TxLayout& L, int grid, size_t lds,
                            hipStream_t s) {
   // the LDS limit is raised once per device and instantiation, so that the
@@ -508,24 +546,32 @@ static se_status launch_tx(const TxArgs& a, const TxLayout& L, int grid, size_t 
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev > 63)
     return fail(SE_EHIP, "project_tx: no current device");
   if (lds > 64 * 1024 && !(raised.load() & (1ull << dev))) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_project_tx<MT, NT, NP, STAGE>),
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_project_tx<MT, NT, NP, STAGE, VOL>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
       return fail(SE_EHIP, "project_tx: %zu bytes of LDS refused", lds);
     raised.fetch_or(1ull << dev);
   }
-  hipLaunchKernelGGL((k_project_tx<MT, NT, NP, STAGE>), dim3(grid), dim3(64 * L.waves), lds, s, a,
-                     L);
+  hipLaunchKernelGGL((k_project_tx<MT, NT, NP, STAGE, VOL>), dim3(grid), dim3(64 * L.waves), lds, s,
+                     a, L);
   return check_launch("project_tx");
 }
 
+template <int MT, int NT, bool VOL>
+static se_status launch_tx_vol(const TxArgs& a, const TxLayout& L, int grid, size_t lds,
+                               hipStream_t s) {
+  if (L.zs > 0)
+    return L.parts == 2 ? launch_tx<MT, NT, 2, true, VOL>(a, L, grid, lds, s)
+                        : launch_tx<MT, NT, 1, true, VOL>(a, L, grid, lds, s);
+  return L.parts == 2 ? launch_tx<MT, NT, 2, false, VOL>(a, L, grid, lds, s)
+                      : launch_tx<MT, NT, 1, false, VOL>(a, L, grid, lds, s);
+}
+
+// areas of several frames take the loaders that stack the frames
 template <int MT, int NT>
 static se_status launch_tx_np(const TxArgs& a, const TxLayout& L, int grid, size_t lds,
-                              hipStream_t s) {
-  if (L.zs > 0)
-    return L.parts == 2 ? launch_tx<MT, NT, 2, true>(a, L, grid, lds, s)
-                        : launch_tx<MT, NT, 1, true>(a, L, grid, lds, s);
-  return L.parts == 2 ? launch_tx<MT, NT, 2, false>(a, L, grid, lds, s)
-                      : launch_tx<MT, NT, 1, false>(a, L, grid, lds, s);
+                              hipStream_t s, bool vol) {
+  return vol ? launch_tx_vol<MT, NT, true>(a, L, grid, lds, s)
+             : launch_tx_vol<MT, NT, false>(a, L, grid, lds, s);
 }
 
 template <int MT, int NT, int NP>
@@ -600,13 +646,18 @@ se_status project_tx(const se_tables* t, const uint8_t* images, int H, int W, co
   a.first1 = t->n_parts > 1 ? t->parts[1].first : 0;
   a.R = R;
   a.ldR = ldR;
-  const int waves = tx_waves(t->M, t->N, t->n_parts, n_blk);
-  if (waves == 0) return fail(SE_EINVAL, "transform of a %dx%d area exceeds LDS", t->M, t->N);
+  const bool vol = area_frames(t->T) > 1;
+  a.fs = 0;
+  if (vol)
+    while ((1 << a.fs) < t->M) ++a.fs;   // rows per frame: a power of two (checked)
+  const int Mv = tx_rows(t);
+  const int waves = tx_waves(Mv, t->N, t->n_parts, n_blk);
+  if (waves == 0) return fail(SE_EINVAL, "transform of a %dx%d area exceeds LDS", Mv, t->N);
   // staged (coalesced) output when rows of four floats stay aligned and the
   // staging area fits beside the operands
   bool stage = (t->N & 3) == 0 && (a.first0 & 3) == 0 && (a.first1 & 3) == 0 && (ldR & 3) == 0 &&
-               TxLayout(t->M, t->N, t->n_parts, waves, true).bytes() <= 160 * 1024;
-  const TxLayout L(t->M, t->N, t->n_parts, waves, stage);
+               TxLayout(Mv, t->N, t->n_parts, waves, true).bytes() <= 160 * 1024;
+  const TxLayout L(Mv, t->N, t->n_parts, waves, stage);
   const size_t lds = L.bytes();
   // about one block per wave, at most four workgroups per compute unit
   const int per_cu = (int)std::min<size_t>(4, (160 * 1024) / lds);
@@ -614,7 +665,7 @@ se_status project_tx(const se_tables* t, const uint8_t* images, int H, int W, co
   switch (L.MT * 10 + L.NT) {
 #define SE_TX_CASE(mt, nt) \
   case mt * 10 + nt:       \
-    return launch_tx_np<mt, nt>(a, L, grid, lds, s);
+    return launch_tx_np<mt, nt>(a, L, grid, lds, s, vol);
     SE_TX_CASE(1, 1) SE_TX_CASE(1, 2) SE_TX_CASE(1, 3) SE_TX_CASE(1, 4)
     SE_TX_CASE(2, 1) SE_TX_CASE(2, 2) SE_TX_CASE(2, 3) SE_TX_CASE(2, 4)
     SE_TX_CASE(3, 1) SE_TX_CASE(3, 2) SE_TX_CASE(3, 3) SE_TX_CASE(3, 4)

@@ -148,7 +148,10 @@ __device__ inline void wave_sync() {
 // ---------------------------------------------------------------------------
 // Initial projections of the transform parts (eq. 12 via eq. 22), fused with
 // the gather: x = w s over the block's area (0 outside the image), then per
-// part R[b][first + k1 N + k2] = D_k (A x B^T)[k1][k2].  Columns K .. ldR-1
+// part R[b][first + k1 N + k2] = D_k (A x B^T)[k1][k2].  An area of several
+// frames of 2^fs rows (the loaders' VOL form) is read as its frames stacked:
+// row m of the M-row area is row m - (f << fs) of frame img + f,
+// f = m >> fs.  Columns K .. ldR-1
 // of R are written as 0.  One wave per block; each workgroup copies the
 // constant operands to LDS once and its waves loop over blocks.
 struct TxArgs {
@@ -161,6 +164,7 @@ struct TxArgs {
   int first0, first1;
   float* R;
   int ldR;
+  int fs;   // log2 of the rows per frame (read by the VOL loaders only)
 };
 
 // Pixels of one block, as the lane holds them until they become X operands:
@@ -175,20 +179,25 @@ struct TxPixels {
   uint32_t v[MT * NT * 4];
 };
 
-template <int MT, int NT>
+template <int MT, int NT, bool VOL = false>
 __device__ inline void tx_load(const TxArgs& a, const DevBlock& d, int M, int N,
                                TxPixels<MT, NT>& P) {
   const int l = threadIdx.x & 63, lr = l & 15, lc = 4 * (l >> 4);
   const uint8_t* img = a.images + (size_t)d.img * a.H * a.W;
+  const int Ms = VOL ? 1 << a.fs : M;   // rows per frame
+  const size_t plane = (size_t)a.H * a.W;
   P.fast = (M & 15) == 0 && (N & 15) == 0 && (a.W & 15) == 0 && (d.x0 & 15) == 0 &&
-           d.y0 >= 0 && d.x0 >= 0 && d.y0 + M <= a.H && d.x0 + N <= a.W;
+           d.y0 >= 0 && d.x0 >= 0 && d.y0 + Ms <= a.H && d.x0 + N <= a.W;
   if (P.fast) {
     const int spr = N >> 4, nseg = M * spr;
 #pragma unroll
     for (int k = 0; k < P.CH; ++k) {
       const int c = min(l + 64 * k, nseg - 1);
       const int m = c / spr, sg = c - m * spr;
-      const uint4 q = *reinterpret_cast<const uint4*>(img + (size_t)(d.y0 + m) * a.W + d.x0 + 16 * sg);
+      const int f = VOL ? m >> a.fs : 0;
+      const uint4 q = *reinterpret_cast<const uint4*>(img + f * plane +
+                                                      (size_t)(d.y0 + m - f * Ms) * a.W +
+                                                      d.x0 + 16 * sg);
       P.v[4 * k] = q.x;
       P.v[4 * k + 1] = q.y;
       P.v[4 * k + 2] = q.z;
@@ -197,7 +206,10 @@ __device__ inline void tx_load(const TxArgs& a, const DevBlock& d, int M, int N,
   } else {
 #pragma unroll
     for (int i = 0; i < MT; ++i) {
-      const uint8_t* row = img + (size_t)min(max(d.y0 + 16 * i + lr, 0), a.H - 1) * a.W;
+      const int m = 16 * i + lr;
+      const int mc = VOL ? min(m, M - 1) : m, f = VOL ? mc >> a.fs : 0;
+      const uint8_t* row =
+          img + f * plane + (size_t)min(max(d.y0 + mc - f * Ms, 0), a.H - 1) * a.W;
 #pragma unroll
       for (int sq = 0; sq < NT; ++sq)
 #pragma unroll
@@ -208,7 +220,7 @@ __device__ inline void tx_load(const TxArgs& a, const DevBlock& d, int M, int N,
 }
 
 // X operands x = w s (s = 0 outside the area and the image).
-template <int MT, int NT>
+template <int MT, int NT, bool VOL = false>
 __device__ inline void tx_x_operands(const TxArgs& a, const DevBlock& d, int M, int N,
                                      TxPixels<MT, NT>& P, const float* Wf, float* Xf,
                                      floatx4 (&xv)[MT][NT]) {
@@ -246,8 +258,9 @@ __device__ inline void tx_x_operands(const TxArgs& a, const DevBlock& d, int M, 
   } else {
 #pragma unroll
     for (int i = 0; i < MT; ++i) {
-      const int y = d.y0 + 16 * i + lr;
-      const bool row_in = 16 * i + lr < M && y >= 0 && y < a.H;
+      const int m = 16 * i + lr;
+      const int y = d.y0 + (VOL ? m - ((m >> a.fs) << a.fs) : m);
+      const bool row_in = m < M && y >= 0 && y < a.H;
 #pragma unroll
       for (int sq = 0; sq < NT; ++sq) {
         const floatx4 w = *reinterpret_cast<const floatx4*>(Wf + ((i * NT + sq) * 64 + l) * 4);

@@ -40,8 +40,8 @@ __all__ = [
     "parity_lattice_layout", "lost_mask", "round_to_f32", "area32_inputs",
     "area48_inputs", "area64_inputs", "clustered_layout", "clustered_dictionaries",
     "clustered_dictionary_parts", "clustered_inputs", "frame_losses", "synth_video",
-    "separable_atoms3", "video_dictionary", "video_lost_mask", "video_grid_layout",
-    "video_inputs",
+    "separable_atoms3", "video_dictionary", "video_dictionary_parts", "video_lost_mask",
+    "video_grid_layout", "video_inputs",
 ]
 
 
@@ -480,6 +480,12 @@ def video_dictionary(T: int, M: int, N: int, parts: Sequence[str] = ("dct", "wht
         [separable_atoms3(rows[p](T), rows[p](M), rows[p](N)) for p in parts], axis=0))
 
 
+def video_dictionary_parts(T: int, M: int, N: int, parts: Sequence[str] = ("dct", "wht")):
+    """Where the sub-dictionaries of video_dictionary(T, M, N, parts) start:
+    (name, first atom) per part."""
+    return [(p, i * T * M * N) for i, p in enumerate(parts)]
+
+
 def video_lost_mask(F: int, H: int, W: int, blocks: Sequence[Block]) -> np.ndarray:
     """uint8 (F, H, W) mask, 1 on every lost sample (each block's loss box:
     frames img+lt .. img+lt+ld-1)."""
@@ -521,4 +527,5 @@ def video_inputs(n_videos: int = 1, frames: int = 8, seed0: int = 500):
             blocks.append(dataclasses.replace(b, img=b.img + v * frames))
     return dict(frames=np.concatenate(vids, axis=0), blocks=blocks,
                 phi=video_dictionary(T, M, N), T=T, M=M, N=N,
+                tx_parts=video_dictionary_parts(T, M, N),
                 rho_hat=0.8, gamma=0.5, iters=100)

@@ -250,12 +250,17 @@ def test_rejects_bad_video_areas_on_host():
                                None) == B.SE_EINVAL
     assert L.se_volume_weights(3, 8, 8, 0.8, fake, 4, 32, 32, blk, 1, fake, fake, 1 << 20,
                                None) == B.SE_EINVAL                      # frames 2..4 of 4
-    # transform parts are two-dimensional
-    bas = B.make_basis(16, 16, 2048, 0x1000, [(B.SE_PART_DCT2, 0)], T=4)
-    t4 = _tables_struct(K=2048, M=16, N=16)
+    # transform parts of areas of several frames: the stacked frames T M <= 64
+    # rows, M a power of two
+    t4 = _tables_struct(K=4096, M=16, N=16)
+    bas = B.make_basis(16, 16, 4096, 0x1000, [(B.SE_PART_DCT2, 0)], T=8)
     assert L.se_weighted_gram(C.byref(bas), fake, 0, 0, C.byref(t4), fake, 1 << 20,
                               None) == B.SE_EINVAL
-    assert b"two-dimensional" in L.se_last_error()
+    assert b"T M, N <= 64" in L.se_last_error()
+    bas = B.make_basis(12, 16, 2048, 0x1000, [(B.SE_PART_DCT2, 0)], T=4)
+    assert L.se_weighted_gram(C.byref(bas), fake, 0, 0, C.byref(t4), fake, 1 << 20,
+                              None) == B.SE_EINVAL
+    assert b"power-of-two M" in L.se_last_error()
     # rows on demand take two-dimensional areas
     bas = B.make_basis(16, 16, 2048, 0x1000, T=4)
     r = L.se_extrapolate_ondemand(C.byref(bas), fake, fake, 8, 64, 64, blk, 1, prm, None,

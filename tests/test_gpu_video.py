@@ -19,11 +19,12 @@ pytestmark = pytest.mark.gpu
 TOL_BF16X3 = 1e-2
 
 
-def _tables(phi32, frames, blocks, T, M, N, ref_block=0, precision=B.SE_FP32):
+def _tables(phi32, frames, blocks, T, M, N, ref_block=0, precision=B.SE_FP32, parts=()):
     F, H, W = frames.shape
     lost = torch.from_numpy(synth.video_lost_mask(F, H, W, blocks)).to(dev())
     w = B.area_weights(M, N, 0.8, lost, [blocks[ref_block]], T=T)
-    return B.weighted_gram(upload_phi(phi32), w[0].contiguous(), M, N, precision, T=T)
+    return B.weighted_gram(upload_phi(phi32), w[0].contiguous(), M, N, precision, T=T,
+                           parts=parts)
 
 
 def _batch(t, frames, blocks, iters, plain=False):
@@ -172,3 +173,64 @@ def test_video_loss_boxes_and_border_areas():
     # samples outside every loss are untouched
     keep = synth.video_lost_mask(F, H, W, blocks) == 0
     np.testing.assert_array_equal(out[keep], frames[keep])
+
+
+@pytest.mark.parametrize("precision", [B.SE_FP32, B.SE_BF16X3])
+def test_video_transform_parts(precision):
+    """3-D DCT and WHT halves declared as transform parts: the projections
+    are separable transforms of the stacked frames (vertical matrix the
+    Kronecker product of the frame and row transforms) and the table rows
+    over the part columns transforms of the weighted atoms.  Both must match
+    the dense route, and the loop must match the oracle."""
+    d = synth.video_inputs(1, frames=8)
+    T, M, N = d["T"], d["M"], d["N"]
+    blocks = d["blocks"]
+    say(f"video transform parts: {len(blocks)} areas of {T}x{M}x{N}, precision {precision}")
+    phi = synth.round_to_f32(d["phi"])
+    tp = _tables(phi, d["frames"], blocks, T, M, N, precision=precision, parts=d["tx_parts"])
+    td = _tables(phi, d["frames"], blocks, T, M, N, precision=precision)
+    torch.cuda.synchronize()
+    K = phi.shape[0]
+    Gp, Gd = tp.G.cpu().numpy()[:, :K], td.G.cpu().numpy()[:, :K]
+    np.testing.assert_array_equal(Gp, Gp.T)
+    assert np.abs(Gp - Gd).max() < (2e-5 if precision == B.SE_FP32 else 2e-4)
+    n = len(blocks)
+    img = torch.from_numpy(d["frames"]).to(dev())
+    R = {}
+    for name, t in (("parts", tp), ("dense", td)):
+        db = B.DeviceBlocks(t, img, blocks)
+        R[name] = torch.full((n, t.ldR), float("nan"), dtype=torch.float32, device=dev())
+        ws = torch.empty(max(1, B.project_ws_bytes(t, n)), dtype=torch.uint8, device=dev())
+        B.project(t, img, db, R[name], ws)
+    torch.cuda.synchronize()
+    Rp, Rd = R["parts"].cpu().numpy(), R["dense"].cpu().numpy()
+    assert np.all(Rp[:, K:] == 0)
+    scale = np.abs(Rd[:, :K]).max()
+    err = np.abs(Rp[:, :K] - Rd[:, :K]).max()
+    print(f"max |R_parts - R_dense| = {err:.3g} (scale {scale:.3g})")
+    assert err <= (2e-6 if precision == B.SE_FP32 else 2e-4) * scale
+    sel, _, g, out = _batch(tp, d["frames"], blocks, 100)
+    tol = TOL_FP32 if precision == B.SE_FP32 else TOL_BF16X3
+    sample = None if precision == B.SE_FP32 else range(0, n, 8)
+    st = oracle_check_video(d["frames"], blocks, phi, T, M, N, 0.8, 0.5, 100, sel, g, out,
+                            sample=sample, tol=tol)
+    print(f"identical selections {st['agree']}/{st['n']}, max|dg|={st['worst']:.3g}")
+    assert st["worst"] <= tol
+
+
+def test_video_part_declaration_is_verified():
+    """A 3-D part is the transform along every axis: a dictionary of 2-D
+    atoms of the 64 x 16 stack (a 64-point DCT down the stacked rows) is not
+    it, and declaring it is refused."""
+    T, M, N = 4, 16, 16
+    wrong = synth.round_to_f32(np.concatenate([synth.dct2_atoms(T * M, N),
+                                               synth.wht2_atoms(T * M, N)]))
+    w = torch.ones(T * M * N, dtype=torch.float32, device=dev())
+    say("video part verification: 64-point DCT rows declared as a 3-D part")
+    with pytest.raises(B.SEError) as e:
+        B.weighted_gram(upload_phi(wrong), w, M, N, T=T,
+                        parts=synth.video_dictionary_parts(T, M, N))
+    assert e.value.code == B.SE_EINVAL
+    # the Walsh-Hadamard half alone is the same either way (Sylvester order
+    # is a Kronecker power), so it is accepted
+    B.weighted_gram(upload_phi(wrong), w, M, N, T=T, parts=[("wht", T * M * N)])
