@@ -9,9 +9,10 @@
 // One workgroup per block.  Lane t holds atoms 4 (j T + t) + e as in the
 // real loop, with separate real and imaginary registers; the rows of Re G
 // and Im G are streamed as float4 sweeps.  The selection compares |R~|^2
-// (same order as |R~|): each lane finds its first maximum in index order,
-// the wave and the workgroup reduce 64-bit (|R~|^2, lowest index) keys, and
-// the winner's complex value travels with its key.
+// (same order as |R~|) as the real loop compares |R~|: a DPP wave maximum,
+// a scalar scan of the one holding lane (or, for exact ties across lanes,
+// 64-bit (|R~|^2, lowest index) keys), and across waves the keys through
+// LDS, the winner's complex value travelling with its key.
 #include "argmax.h"
 #include "se_internal.h"
 
@@ -67,29 +68,76 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy_c(GreedyArgs a, CplxArgs 
   const float gamma = a.gamma;
 
   for (int it = 0; it < a.iters; ++it) {
-    // ---- this lane's first largest |R~|^2, then the wave's and the group's --
-    float bm = 0.0f, bre = 0.0f, bim = 0.0f;
-    int bc = 0;
+    // ---- the wave's largest |R~|^2 and its lowest index ----------------------
+    // Group maxima (4 atoms each) and the lane maximum, then the wave
+    // maximum by DPP.  When one lane alone holds it, that lane's group
+    // maxima and then the complex values of its first matching group are
+    // read into scalar registers and scanned (lowest index first); several
+    // holding lanes (exact ties) take the key reduction.
+    float gm[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
+    for (int j = 0; j < NJ; ++j) {
+      float m[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float m2 = fmaf(Rr[j][e], Rr[j][e], Ri[j][e] * Ri[j][e]);
-        if (m2 > bm) {
-          bm = m2;
-          bre = Rr[j][e];
-          bim = Ri[j][e];
-          bc = 4 * j + e;
+      for (int e = 0; e < 4; ++e) m[e] = fmaf(Rr[j][e], Rr[j][e], Ri[j][e] * Ri[j][e]);
+      gm[j] = fmaxf(fmaxf(m[0], m[1]), fmaxf(m[2], m[3]));
+    }
+    float lm = gm[0];
+#pragma unroll
+    for (int j = 1; j < NJ; ++j) lm = fmaxf(lm, gm[j]);
+    const float Mx = wave_max_f32(lm);
+    const uint64_t holders = __builtin_amdgcn_ballot_w64(lm == Mx);
+    uint64_t key = 0;                          // every score zero: atom 0, value 0
+    float vre = 0.0f, vim = 0.0f;
+    if (Mx != 0.0f && __builtin_popcountll(holders) == 1) {
+      const int L = __builtin_ctzll(holders);
+      const uint32_t Mb = __float_as_uint(Mx);
+      int gsel = NJ - 1;
+#pragma unroll
+      for (int j = NJ - 2; j >= 0; --j)
+        gsel = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(gm[j]), L) == Mb ? j : gsel;
+      float re[4] = {0.0f, 0.0f, 0.0f, 0.0f}, im[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+        if (j == gsel) {                       // uniform branch
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            re[e] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Rr[j][e]), L));
+            im[e] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Ri[j][e]), L));
+          }
         }
-      }
-    const uint64_t mine = make_key(bm, 4 * ((bc >> 2) * T + t) + (bc & 3));
-    uint64_t key = wave_max_key((uint32_t)(mine >> 32), (uint32_t)mine);
-    // the owner of the wave's winner holds its complex value (an all-zero
-    // key decodes to atom 0 of lane 0, whose best value is then 0)
-    const int kw = 0xFFFF - (int)((uint32_t)key >> 16);
-    const int owner = ((kw >> 2) % T) & 63;
-    float vre = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bre), owner));
-    float vim = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bim), owner));
+      // the same expression as the lane's own, so the winner compares equal
+      int csel = 3;
+#pragma unroll
+      for (int e = 2; e >= 0; --e)
+        csel = __float_as_uint(fmaf(re[e], re[e], im[e] * im[e])) == Mb ? e : csel;
+      vre = csel == 0 ? re[0] : csel == 1 ? re[1] : csel == 2 ? re[2] : re[3];
+      vim = csel == 0 ? im[0] : csel == 1 ? im[1] : csel == 2 ? im[2] : im[3];
+      key = make_key(Mx, 4 * (gsel * T + wave * 64 + L) + csel);
+    } else if (Mx != 0.0f) {
+      // exact ties across lanes: every lane's first maximum as a key; the
+      // owner of the wave's winner holds its complex value
+      float bm = 0.0f, bre = 0.0f, bim = 0.0f;
+      int bc = 0;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float m2 = fmaf(Rr[j][e], Rr[j][e], Ri[j][e] * Ri[j][e]);
+          if (m2 > bm) {
+            bm = m2;
+            bre = Rr[j][e];
+            bim = Ri[j][e];
+            bc = 4 * j + e;
+          }
+        }
+      const uint64_t mine = make_key(bm, 4 * ((bc >> 2) * T + t) + (bc & 3));
+      key = wave_max_key((uint32_t)(mine >> 32), (uint32_t)mine);
+      const int kw = 0xFFFF - (int)((uint32_t)key >> 16);
+      const int owner = ((kw >> 2) % T) & 63;
+      vre = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bre), owner));
+      vim = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bim), owner));
+    }
     if (WAVES > 1) {
       if (lane == 0) {
         s_key[par][wave] = key;
@@ -191,7 +239,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy_c(GreedyArgs a, CplxArgs 
 struct CShape {
   int waves, vpl;
 };
-static const CShape kCShapes[] = {{1, 8},  {1, 16}, {2, 12}, {2, 16},  {4, 12},
+static const CShape kCShapes[] = {{1, 8},  {1, 16}, {1, 32}, {2, 12}, {2, 16},  {4, 12},
                                   {4, 16}, {8, 12}, {8, 16}, {16, 12}, {16, 16}};
 
 bool complex_loop_for(int K) {
@@ -221,7 +269,7 @@ se_status launch_greedy_c(const GreedyArgs& a, const float* G_im, const float* p
   case w * 100 + v:                                                                      \
     hipLaunchKernelGGL((k_greedy_c<w, v>), dim3(grid), dim3(64 * w), 0, s, a, x); \
     break;
-    SE_C_CASE(1, 8) SE_C_CASE(1, 16) SE_C_CASE(2, 12) SE_C_CASE(2, 16) SE_C_CASE(4, 12)
+    SE_C_CASE(1, 8) SE_C_CASE(1, 16) SE_C_CASE(1, 32) SE_C_CASE(2, 12) SE_C_CASE(2, 16) SE_C_CASE(4, 12)
     SE_C_CASE(4, 16) SE_C_CASE(8, 12) SE_C_CASE(8, 16) SE_C_CASE(16, 12) SE_C_CASE(16, 16)
 #undef SE_C_CASE
     default: return fail(SE_EINVAL, "no complex loop shape for K=%d", a.K);
