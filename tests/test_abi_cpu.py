@@ -266,3 +266,10 @@ def test_rejects_bad_video_areas_on_host():
     r = L.se_extrapolate_ondemand(C.byref(bas), fake, fake, 8, 64, 64, blk, 1, prm, None,
                                   None, None, None, 0, fake, 16, None)
     assert r == B.SE_EINVAL and b"two-dimensional" in L.se_last_error()
+    # the server takes two-dimensional areas (refused before any device call)
+    SL = B._serve_lib()
+    cfg = B.se_serve_config(0, 64, 64, 1, 1, 1, 0.8, 1 << 30)
+    sets = (B.se_basis * 1)(B.make_basis(16, 16, 2048, 0x1000, T=4))
+    out = C.c_void_p()
+    assert SL.se_serve_create(C.byref(cfg), sets, 1, C.byref(out)) == B.SE_EINVAL
+    assert b"two-dimensional" in L.se_last_error()
