@@ -173,7 +173,27 @@ typedef struct {
  *   Y    : 2K x (M*N): rows 0..K-1 the real and rows K..2K-1 the imaginary
  *          parts of D_k sqrt(w) conj(phi_k), so eq. 12 is Y (sqrt(w) s).
  *   phi_im : copied from the dictionary.
- * For a real dictionary G_im and phi_im are NULL (G_im is not written). */
+ * For a real dictionary G_im and phi_im are NULL (G_im is not written).
+ * Class tables (optional; Gc and cls may be NULL): when every atom lies in
+ * the two declared transform parts of a two-dimensional area with even M
+ * and N, K equals se_table_ld(K) and is a multiple of 1024, and the weight
+ * pattern is mirror-symmetric in both axes (w[m][n] = w[M-1-m][n] =
+ * w[m][N-1-n], bit for bit), every DCT-II and Walsh-Hadamard atom is even
+ * or odd about the area's centre in each axis, so C_(k,l) of eq. 16 is 0
+ * whenever k and l differ in either parity: the atoms fall into four
+ * classes of Kc = K/4 and eq. 20 changes only the selected atom's class.
+ * se_weighted_gram then writes, in class order (class 2 pv + ph for the
+ * vertical and horizontal parities; in a class the parts in the order of
+ * their first atoms, each by (k1/2, k2/2)):
+ *   Gc   : K x (K/4) float32, 16-byte aligned: row p holds the entries of
+ *          G between the p-th atom of the class order and the atoms of its
+ *          own class, in class order;
+ *   cls  : K pairs of int32 (original atom index, D_k as float bits), by
+ *          position in the class order;
+ * and sets n_classes = 4 (else 0, and Gc, cls are not written).  The
+ * one-launch route (se_extrapolate_device and se_extrapolate_batch for
+ * all-transform tables) then streams a quarter of a row per iteration;
+ * selections are reported as original atom indices. */
 typedef struct {
   int32_t M, N, K, ldG;
   float* G;
@@ -191,6 +211,9 @@ typedef struct {
   float* G_im;
   const float* phi_im;   /* copied from the dictionary by se_weighted_gram */
   int32_t T;             /* frames per area, copied (0 read as 1)          */
+  float* Gc;             /* class tables (may be NULL, see above)          */
+  int32_t* cls;
+  int32_t n_classes;     /* written by se_weighted_gram: 4 or 0            */
 } se_tables;
 
 /* Model-generation parameters: gamma of eq. 8 (0 < gamma <= 1) and the

@@ -91,7 +91,8 @@ class se_tables(C.Structure):
                 ("sqrtw", C.c_void_p), ("phi", C.c_void_p), ("info", C.c_void_p),
                 ("precision", C.c_int32), ("Yhi", C.c_void_p), ("Ylo", C.c_void_p),
                 ("n_parts", C.c_int32), ("parts", se_part * 2), ("tx", C.c_void_p),
-                ("G_im", C.c_void_p), ("phi_im", C.c_void_p), ("T", C.c_int32)]
+                ("G_im", C.c_void_p), ("phi_im", C.c_void_p), ("T", C.c_int32),
+                ("Gc", C.c_void_p), ("cls", C.c_void_p), ("n_classes", C.c_int32)]
 
 
 class se_params(C.Structure):
@@ -258,6 +259,9 @@ class Tables:
     G_im: Optional[torch.Tensor] = None
     phi_im: Optional[torch.Tensor] = None
     T: int = 1
+    Gc: Optional[torch.Tensor] = None
+    cls: Optional[torch.Tensor] = None
+    n_classes: int = 0
 
     @property
     def complex(self) -> bool:
@@ -278,23 +282,28 @@ class Tables:
                          len(self.parts), _part_array(self.parts),
                          self.tx.data_ptr() if self.tx is not None else None,
                          self.G_im.data_ptr() if self.G_im is not None else None,
-                         self.phi_im.data_ptr() if self.phi_im is not None else None, self.T)
+                         self.phi_im.data_ptr() if self.phi_im is not None else None, self.T,
+                         self.Gc.data_ptr() if self.Gc is not None else None,
+                         self.cls.data_ptr() if self.cls is not None else None, self.n_classes)
 
     def nbytes(self) -> int:
         parts = [self.G, self.D, self.Y, self.sqrtw]
-        parts += [x for x in (self.Yhi, self.Ylo, self.G_im) if x is not None]
+        parts += [x for x in (self.Yhi, self.Ylo, self.G_im, self.Gc, self.cls) if x is not None]
         return sum(t.numel() * t.element_size() for t in parts)
 
 
 def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
                   precision: int = SE_FP32, flags: int = SE_DIAG_AUTO, stream=None,
-                  parts=(), phi_im: Optional[torch.Tensor] = None, T: int = 1) -> Tables:
+                  parts=(), phi_im: Optional[torch.Tensor] = None, T: int = 1,
+                  classes: bool = True) -> Tables:
     """se_weighted_gram (Algorithm 2) for dictionary ``phi`` (K, T*M*N) and
     weight pattern ``w`` (T*M*N,).  ``parts``: declared transform ranges, as
     (SE_PART_*, first atom) pairs (verified by the library).  ``phi_im``: the
     imaginary parts of a complex dictionary (``phi`` then holds the real
     parts); the tables are then complex (G, G_im).  ``T``: frames per area
-    (1: two-dimensional areas)."""
+    (1: two-dimensional areas).  ``classes``: offer buffers for the parity
+    class tables (used when the library finds the class structure; then
+    ``n_classes`` is 4)."""
     L = lib()
     _dev_f32(phi, "phi")
     _dev_f32(w, "w")
@@ -327,6 +336,10 @@ def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
         if nb_tx == 0:
             raise ValueError(f"no transform parts for a {T}x{M}x{N} area")
         t.tx = torch.empty(nb_tx // 4, dtype=torch.float32, device=dev)
+    if (classes and len(t.parts) == 2 and int(T) == 1 and phi_im is None and M % 2 == 0
+            and N % 2 == 0 and K % 1024 == 0 and ldG == K):
+        t.Gc = torch.empty((K, K // 4), dtype=torch.float32, device=dev)
+        t.cls = torch.empty((K, 2), dtype=torch.int32, device=dev)
     b = make_basis(M, N, K, phi.data_ptr(), t.parts,
                    phi_im.data_ptr() if phi_im is not None else None, int(T))
     nb = L.se_weighted_gram_ws_bytes(C.byref(b), int(precision))
@@ -334,6 +347,9 @@ def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
     st = t.struct()
     _check(L.se_weighted_gram(C.byref(b), _ptr(w), int(precision), int(flags), C.byref(st),
                               _ptr(ws), nb, _stream(stream)))
+    t.n_classes = int(st.n_classes)
+    if t.n_classes == 0:
+        t.Gc = t.cls = None
     return t
 
 

@@ -21,7 +21,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = [
     "abi.cpp", "weights.hip", "gram.hip", "gemm.hip", "gemm_bf16x3.hip", "project.hip",
-    "greedy.hip", "ondemand.hip", "transform.hip", "fused.hip", "complex.hip", "serve.cpp", "tune.cpp",
+    "greedy.hip", "ondemand.hip", "transform.hip", "fused.hip", "complex.hip", "classes.hip",
+    "serve.cpp", "tune.cpp",
 ]
 
 FLAGS = [

@@ -105,6 +105,12 @@ static se_status check_tables(const se_tables* t) {
     if (!complex_loop_for(t->K)) return fail(SE_EINVAL, "no complex loop shape for K=%d", t->K);
     if (area_frames(t->T) > 1) return fail(SE_EINVAL, "complex dictionaries take two-dimensional areas");
   }
+  if (t->n_classes != 0) {
+    if (t->n_classes != 4 || !classes_possible(t) ||
+        reinterpret_cast<uintptr_t>(t->Gc) % 16 || reinterpret_cast<uintptr_t>(t->cls) % 16)
+      return fail(SE_EINVAL, "n_classes=%d does not describe class tables of these tables",
+                  t->n_classes);
+  }
   return SE_OK;
 }
 
@@ -167,8 +173,11 @@ int dense_ranges(int K, int P, int n_parts, const se_part* parts, int lo[3], int
 }
 
 // Checks every atom of the declared parts against phi on the device and
-// waits for the verdict (flag: one device int32 of scratch).
-static se_status verify_parts(const se_basis* b, int32_t* flag, hipStream_t s) {
+// waits for the verdict (flag: one device int32 of scratch).  With extra,
+// the int32 after the flag (written by work the caller queued after
+// clearing it) is read back in the same synchronisation.
+static se_status verify_parts(const se_basis* b, int32_t* flag, hipStream_t s,
+                              int32_t* extra = nullptr) {
   if (b->n_parts == 0) return SE_OK;
   se_status st;
   if (hipMemsetAsync(flag, 0, sizeof(int32_t), s) != hipSuccess)
@@ -177,11 +186,13 @@ static se_status verify_parts(const se_basis* b, int32_t* flag, hipStream_t s) {
     if ((st = check_part(b->phi, area_frames(b->T), b->M, b->N, b->parts[q].kind,
                          b->parts[q].first, flag, s)))
       return st;
-  int32_t bad = 0;
-  if (hipMemcpyAsync(&bad, flag, sizeof(bad), hipMemcpyDeviceToHost, s) != hipSuccess ||
+  int32_t got[2] = {0, 0};
+  if (hipMemcpyAsync(got, flag, (extra ? 2 : 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return fail(SE_EHIP, "part verification: %s", hipGetErrorString(hipGetLastError()));
-  if (bad) return fail(SE_EINVAL, "a declared transform part does not match phi");
+  if (extra) *extra = got[1];
+  if (got[0]) return fail(SE_EINVAL, "a declared transform part does not match phi");
   return SE_OK;
 }
 
@@ -324,7 +335,7 @@ size_t se_weighted_gram_ws_bytes(const se_basis* b, se_precision prec) {
   const size_t K = (size_t)b->K;
   cv.take<float>(K);
   cv.take<double>(K);
-  cv.take<int32_t>(1);
+  cv.take<int32_t>(2);
   if (b->phi_im) cv.take<float>(2 * K * (size_t)round4(2 * b->K));   // the stacked product
   return cv.off + 256;
 }
@@ -346,6 +357,7 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
   for (int q = 0; q < 2; ++q) t->parts[q] = q < b->n_parts ? b->parts[q] : se_part{0, 0};
   t->phi_im = b->phi_im;
   t->T = area_frames(b->T);
+  t->n_classes = 0;
   se_status st = check_tables(t);
   if (st) return st;
   if (!ws || ws_bytes < se_weighted_gram_ws_bytes(b, prec)) return fail(SE_ENOMEM, "workspace too small");
@@ -354,10 +366,20 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
   Carver cv(ws);
   float* diag32 = cv.take<float>((size_t)K);
   double* diag64 = cv.take<double>((size_t)K);
-  int32_t* flag = cv.take<int32_t>(1);
+  int32_t* flag = cv.take<int32_t>(2);
   // the projections of declared parts are computed from their definition,
-  // so the declaration must match the atoms actually given
-  if ((st = verify_parts(b, flag, s))) {
+  // so the declaration must match the atoms actually given; the weight
+  // pattern's mirror symmetry (for class tables) is read back in the same
+  // synchronisation
+  const bool want_classes = classes_possible(t);
+  int32_t asym = 1;
+  if (want_classes) {
+    if (hipMemsetAsync(flag + 1, 0, sizeof(int32_t), s) != hipSuccess)
+      return fail(SE_EHIP, "flag clear failed");
+    launch_sym_check(w, b->M, b->N, flag + 1, s);
+    if ((st = check_launch("sym_check"))) return st;
+  }
+  if ((st = verify_parts(b, flag, s, want_classes ? &asym : nullptr))) {
     t->n_parts = 0;
     return st;
   }
@@ -409,7 +431,12 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
                                   Gd, t->ldG, s);
       if (st) return st;
     }
-    return gram_mirror(t, s);
+    if ((st = gram_mirror(t, s))) return st;
+    if (want_classes && asym == 0) {
+      if ((st = build_classes(t, s))) return st;
+      t->n_classes = 4;
+    }
+    return SE_OK;
   }
   if (prec == SE_FP32) return gemm_syrk_f32(t->Y, P, K, P, t->G, t->ldG, s);
   return gemm_syrk_bf16x3(t->Yhi, t->Ylo, P, K, P, t->G, t->ldG, s);
@@ -486,6 +513,8 @@ static GreedyArgs greedy_args(const se_tables* t, const float* R, int ldR, uint8
   ga.coef = coef;
   ga.g_loss = g_loss;
   ga.g_loss_ld = g_loss ? g_loss_ld : 0;
+  ga.Gc = t->n_classes == 4 ? t->Gc : nullptr;
+  ga.cls = t->n_classes == 4 ? reinterpret_cast<const int2*>(t->cls) : nullptr;
   return ga;
 }
 

@@ -1,0 +1,102 @@
+// Parity classes of a dictionary of DCT-II and Walsh-Hadamard atoms under a
+// mirror-symmetric weight pattern (eq. 16).  A 1-D DCT-II row k is even
+// about the centre of its M points for even k and odd for odd k; a
+// Walsh-Hadamard row k in natural order is even or odd as popcount(k) is
+// even or odd (reversing the point index complements its bits).  A 2-D atom
+// is the product of a vertical and a horizontal row, so it is even or odd
+// in each axis.  When w[m][n] = w[M-1-m][n] = w[m][N-1-n], the weighted
+// scalar product of two atoms that differ in either parity is a sum whose
+// terms cancel in mirrored pairs: C_(k,l) = 0.  The table is then block
+// diagonal in the four classes (vertical parity, horizontal parity), and
+// the recursion of eq. 20 changes R only inside the selected atom's class.
+//
+// Class order: class c = 2 pv + ph; in a class the two parts in the order of
+// their first atoms; in a part the atoms (k1, k2) of the class by
+// (k1 / 2, k2 / 2), row-major.  Each part contributes M N / 4 atoms to each
+// class (M, N even: k = 2 i and k = 2 i + 1 always differ in parity).
+#include "se_internal.h"
+
+namespace sefase {
+
+struct ClassLayout {
+  int M, N, K, Kc;
+  int first_lo, kind_lo, first_hi, kind_hi;
+};
+
+// the row (2 i or 2 i + 1) of a 1-D transform of `kind` with parity `par`
+__device__ inline int parity_row(int kind, int i, int par) {
+  const int even = 2 * i;
+  const int p_even = kind == SE_PART_WHT2 ? (__popc(even) & 1) : 0;
+  return even + (p_even ^ par);
+}
+
+// original atom index of position p of the class order
+__device__ inline int class_orig(const ClassLayout& L, int p) {
+  const int c = p / L.Kc, r = p - c * L.Kc;
+  const int Q = L.M * L.N / 4, h = L.N / 2;
+  const int q = r / Q, s = r - q * Q;
+  const int kind = q ? L.kind_hi : L.kind_lo, first = q ? L.first_hi : L.first_lo;
+  const int i1 = s / h, i2 = s - i1 * h;
+  return first + parity_row(kind, i1, c >> 1) * L.N + parity_row(kind, i2, c & 1);
+}
+
+// flag = 1 if the weight pattern is not mirror-symmetric in both axes (bit
+// for bit)
+__global__ void k_sym_check(const float* __restrict__ w, int M, int N, int* __restrict__ flag) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= M * N) return;
+  const int m = p / N, n = p - m * N;
+  const uint32_t v = __float_as_uint(w[p]);
+  if (v != __float_as_uint(w[(M - 1 - m) * N + n]) || v != __float_as_uint(w[m * N + N - 1 - n]))
+    atomicOr(flag, 1);
+}
+
+// Gc[p][i] = G[orig(p)][orig(c(p) Kc + i)], cls[p] = (orig(p), D_orig(p)).
+// One workgroup per class-order row.
+__global__ __launch_bounds__(256) void k_build_classes(ClassLayout L, const float* __restrict__ G,
+                                                       int ldG, const float* __restrict__ D,
+                                                       float* __restrict__ Gc, int ldGc,
+                                                       int2* __restrict__ cls) {
+  const int p = blockIdx.x;
+  if (p >= L.K) return;
+  const int o = class_orig(L, p);
+  const int base = (p / L.Kc) * L.Kc;
+  const float* row = G + (size_t)o * ldG;
+  for (int i = threadIdx.x; i < L.Kc; i += blockDim.x)
+    Gc[(size_t)p * ldGc + i] = row[class_orig(L, base + i)];
+  if (threadIdx.x == 0) cls[p] = make_int2(o, __float_as_int(D[o]));
+}
+
+// The static conditions of the class tables (the weight symmetry is
+// checked on the device).
+bool classes_possible(const se_tables* t) {
+  if (!t->Gc || !t->cls || area_frames(t->T) != 1 || t->n_parts != 2 || t->phi_im) return false;
+  if ((t->M & 1) || (t->N & 1) || t->K % 1024 || t->K != greedy_row_len(t->K)) return false;
+  int lo[3], hi[3];
+  return dense_ranges(t->K, t->M * t->N, t->n_parts, t->parts, lo, hi) == 0;
+}
+
+void launch_sym_check(const float* w, int M, int N, int* flag, hipStream_t s) {
+  const int P = M * N;
+  hipLaunchKernelGGL(k_sym_check, dim3((P + 255) / 256), dim3(256), 0, s, w, M, N, flag);
+}
+
+se_status build_classes(se_tables* t, hipStream_t s) {
+  ClassLayout L;
+  L.M = t->M;
+  L.N = t->N;
+  L.K = t->K;
+  L.Kc = t->K / 4;
+  const bool swap = t->parts[1].first < t->parts[0].first;
+  const se_part& lo = t->parts[swap ? 1 : 0];
+  const se_part& hi = t->parts[swap ? 0 : 1];
+  L.first_lo = lo.first;
+  L.kind_lo = lo.kind;
+  L.first_hi = hi.first;
+  L.kind_hi = hi.kind;
+  hipLaunchKernelGGL(k_build_classes, dim3(t->K), dim3(256), 0, s, L, t->G, t->ldG, t->D, t->Gc,
+                     L.Kc, reinterpret_cast<int2*>(t->cls));
+  return check_launch("build_classes");
+}
+
+}  // namespace sefase

@@ -26,7 +26,7 @@ constexpr int conceal_lds_floats() {
 // compiler keeps the projection stage in vector registers without the
 // accumulation registers it would otherwise add (four resident blocks per
 // SIMD cover a 4096-block batch at once); larger areas take what they need.
-template <int WAVES, int VPL, int MT, int NT, int NP>
+template <int WAVES, int VPL, int MT, int NT, int NP, bool CLS>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(MT * NT <= 4 ? 4 : 1)))
 void k_conceal_tx(GreedyArgs a, TxArgs x, TxLayout L) {
   constexpr int T = 64 * WAVES;
@@ -65,20 +65,30 @@ void k_conceal_tx(GreedyArgs a, TxArgs x, TxLayout L) {
 
   // ---- Algorithm 3 from R~^(0) ------------------------------------------------
   float R[NJ][4];
+  if (CLS) {
+    // the class order: position 4 (j T + t) + e holds the atom cls[.].x
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const floatx4 v = *reinterpret_cast<const floatx4*>(Rs + 4 * (j * T + t));
-    R[j][0] = v[0]; R[j][1] = v[1]; R[j][2] = v[2]; R[j][3] = v[3];
+    for (int j = 0; j < NJ; ++j) {
+      const int4 q0 = *reinterpret_cast<const int4*>(a.cls + 4 * (j * T + t));
+      const int4 q1 = *reinterpret_cast<const int4*>(a.cls + 4 * (j * T + t) + 2);
+      R[j][0] = Rs[q0.x]; R[j][1] = Rs[q0.z]; R[j][2] = Rs[q1.x]; R[j][3] = Rs[q1.z];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const floatx4 v = *reinterpret_cast<const floatx4*>(Rs + 4 * (j * T + t));
+      R[j][0] = v[0]; R[j][1] = v[1]; R[j][2] = v[2]; R[j][3] = v[3];
+    }
   }
-  greedy_block<WAVES, VPL>(a, b, R);
+  greedy_block<WAVES, VPL, CLS>(a, b, R);
 }
 
-template <int WAVES, int VPL, int MT, int NT, int NP>
+template <int WAVES, int VPL, int MT, int NT, int NP, bool CLS>
 static se_status launch_conceal(const GreedyArgs& a, const TxArgs& x, const TxLayout& L, int grid,
                                 hipStream_t s) {
   const size_t lds = (size_t)conceal_lds_floats<WAVES, VPL, MT, NT, NP>() * 4;
-  hipLaunchKernelGGL((k_conceal_tx<WAVES, VPL, MT, NT, NP>), dim3(grid), dim3(64 * WAVES), lds, s,
-                     a, x, L);
+  hipLaunchKernelGGL((k_conceal_tx<WAVES, VPL, MT, NT, NP, CLS>), dim3(grid), dim3(64 * WAVES),
+                     lds, s, a, x, L);
   return check_launch("conceal_tx");
 }
 
@@ -101,7 +111,10 @@ se_status conceal_tx(const se_tables* t, const GreedyArgs& a, const uint8_t* ima
                      int n_blk, hipStream_t s, int waves, int vpl) {
   if (n_blk <= 0) return SE_OK;
   if (!conceal_tx_supported(t)) return fail(SE_EINVAL, "no fused projection for these tables");
-  if (waves <= 0) {
+  // class tables: the class form, at the default shape when the requested
+  // one does not hold whole class sweeps
+  const bool cls = t->n_classes == 4 && a.Gc && a.cls;
+  if (waves <= 0 || (cls && (vpl / 4) % 4 != 0)) {
     waves = greedy_waves_for(t->K);
     vpl = greedy_row_len(t->K) / (64 * waves);
   }
@@ -121,12 +134,21 @@ se_status conceal_tx(const se_tables* t, const GreedyArgs& a, const uint8_t* ima
   x.fs = 0;   // one frame (the two-dimensional loaders)
   const TxLayout L(t->M, t->N, t->n_parts, 0);
   const int key = conceal_case(t->M, t->N, t->n_parts) * 10000 + waves * 100 + vpl;
+  if (cls) {
+    switch (key) {
+      case 20132: return launch_conceal<1, 32, 2, 2, 2, true>(a, x, L, n_blk, s);
+      case 20216: return launch_conceal<2, 16, 2, 2, 2, true>(a, x, L, n_blk, s);
+      case 40432: return launch_conceal<4, 32, 4, 4, 2, true>(a, x, L, n_blk, s);
+      case 40816: return launch_conceal<8, 16, 4, 4, 2, true>(a, x, L, n_blk, s);
+      default: return fail(SE_EINVAL, "no fused class loop shape %dx%d for K=%d", waves, vpl, t->K);
+    }
+  }
   switch (key) {
-    case 20132: return launch_conceal<1, 32, 2, 2, 2>(a, x, L, n_blk, s);
-    case 20216: return launch_conceal<2, 16, 2, 2, 2>(a, x, L, n_blk, s);
-    case 20408: return launch_conceal<4, 8, 2, 2, 2>(a, x, L, n_blk, s);
-    case 40432: return launch_conceal<4, 32, 4, 4, 2>(a, x, L, n_blk, s);
-    case 40816: return launch_conceal<8, 16, 4, 4, 2>(a, x, L, n_blk, s);
+    case 20132: return launch_conceal<1, 32, 2, 2, 2, false>(a, x, L, n_blk, s);
+    case 20216: return launch_conceal<2, 16, 2, 2, 2, false>(a, x, L, n_blk, s);
+    case 20408: return launch_conceal<4, 8, 2, 2, 2, false>(a, x, L, n_blk, s);
+    case 40432: return launch_conceal<4, 32, 4, 4, 2, false>(a, x, L, n_blk, s);
+    case 40816: return launch_conceal<8, 16, 4, 4, 2, false>(a, x, L, n_blk, s);
     default: return fail(SE_EINVAL, "no fused loop shape %dx%d for K=%d", waves, vpl, t->K);
   }
 }

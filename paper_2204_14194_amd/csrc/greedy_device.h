@@ -27,6 +27,13 @@
 //     |R~| bits << 32  |  (0xFFFF - k) << 16  |  sign << 15
 // so the lowest index wins.  Workgroups of several waves combine the wave
 // winners' keys through LDS.
+//
+// Class form (CLS): R~ is held in the class order of the tables' parity
+// classes (four classes of K/4 atoms, class c in the sweeps j of
+// [c NJ/4, (c+1) NJ/4)), the table rows are the class rows Gc (K/4 entries),
+// and eq. 20 updates only the selected atom's class -- every other entry of
+// its row of D C D is 0.  The selected position maps to its original atom
+// (for the model, the reported selection and D) through the class table.
 #pragma once
 
 #include "argmax.h"
@@ -38,10 +45,12 @@ constexpr int kQPL = 4;   // loss pixels per lane (the loss may hold <= 4 T pixe
 
 // The iterations and the paste for block b of a workgroup of WAVES waves,
 // from R~^(0) in registers (lane t: atoms 4 (j T + t) + e).
-template <int WAVES, int VPL>
+template <int WAVES, int VPL, bool CLS = false>
 __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (&R)[VPL / 4][4]) {
   constexpr int T = 64 * WAVES;
   constexpr int NJ = VPL / 4;
+  constexpr int NJC = NJ / 4;                  // sweeps of one class (CLS)
+  static_assert(!CLS || NJ % 4 == 0, "the class form needs whole sweeps per class");
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const DevBlock d = a.blk[b];
@@ -145,11 +154,20 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     u = __builtin_amdgcn_readfirstlane(u);
     rv = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rv)));
     const float tc = gamma * rv;              // coefficient of the unit-norm atom
+    // the selected atom's original index and D (the class form: from the
+    // class table; a scalar load that does not wait behind vector loads)
+    int ou = u;
+    float Du = 0.0f;
+    if (CLS) {
+      const uint64_t cu = ((const __attribute__((address_space(4))) uint64_t*)a.cls)[u];
+      ou = (int)(uint32_t)cu;
+      Du = __uint_as_float((uint32_t)(cu >> 32));
+    }
 
     // ---- stream row u of the table and the atom over the loss ---------------
     // (the first pixel of every lane always exists; more pixels per lane
     // only for losses larger than the workgroup, one uniform branch)
-    const float* prow = a.phi + (size_t)u * P;
+    const float* prow = a.phi + (size_t)ou * P;
     float pv[kQPL];
     pv[0] = prow[poff[0]];
     if (nq > 1) {
@@ -157,16 +175,17 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
       for (int q = 1; q < kQPL; ++q)
         if (q < nq) pv[q] = prow[poff[q]];
     }
-    const float* grow = a.G + (size_t)u * a.ldG;
-    float4 row[NJ];
+    constexpr int NR = CLS ? NJC : NJ;
+    const float* grow = CLS ? a.Gc + (size_t)u * (T * NJ) : a.G + (size_t)u * a.ldG;
+    float4 row[NR];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) row[j] = *reinterpret_cast<const float4*>(grow + 4 * (j * T + t));
+    for (int j = 0; j < NR; ++j) row[j] = *reinterpret_cast<const float4*>(grow + 4 * (j * T + t));
     // D is read-only for the whole launch: a scalar load (constant address
     // space) that does not wait behind the row's vector loads
-    const float Du = ((const __attribute__((address_space(4))) float*)a.D)[u];
+    if (!CLS) Du = ((const __attribute__((address_space(4))) float*)a.D)[u];
     const float c = tc * Du;                  // eq. 19
     if (t == 0) {
-      if (a.sel) a.sel[(size_t)b * a.iters + it] = u;
+      if (a.sel) a.sel[(size_t)b * a.iters + it] = ou;
       if (a.coef) a.coef[(size_t)b * a.iters + it] = c;
     }
     {                                         // eq. 9, compensated
@@ -187,12 +206,27 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     }
 
     // ---- eq. 20 -------------------------------------------------------------
+    if (CLS) {
+      const int cu = u / (T * NJC * 4);         // the selected atom's class (uniform)
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      R[j][0] = fmaf(-tc, row[j].x, R[j][0]);
-      R[j][1] = fmaf(-tc, row[j].y, R[j][1]);
-      R[j][2] = fmaf(-tc, row[j].z, R[j][2]);
-      R[j][3] = fmaf(-tc, row[j].w, R[j][3]);
+      for (int cc = 0; cc < 4; ++cc)
+        if (cc == cu) {
+#pragma unroll
+          for (int j = 0; j < NR; ++j) {
+            R[cc * NJC + j][0] = fmaf(-tc, row[j].x, R[cc * NJC + j][0]);
+            R[cc * NJC + j][1] = fmaf(-tc, row[j].y, R[cc * NJC + j][1]);
+            R[cc * NJC + j][2] = fmaf(-tc, row[j].z, R[cc * NJC + j][2]);
+            R[cc * NJC + j][3] = fmaf(-tc, row[j].w, R[cc * NJC + j][3]);
+          }
+        }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        R[j][0] = fmaf(-tc, row[j].x, R[j][0]);
+        R[j][1] = fmaf(-tc, row[j].y, R[j][1]);
+        R[j][2] = fmaf(-tc, row[j].z, R[j][2]);
+        R[j][3] = fmaf(-tc, row[j].w, R[j][3]);
+      }
     }
   }
 

@@ -173,6 +173,11 @@ struct GreedyArgs {
   float* coef;         // optional
   float* g_loss;       // optional
   int g_loss_ld;
+  // class tables (the one-launch route of tables with n_classes = 4):
+  // rows of K/4 entries by position in the class order, and per position
+  // (original atom index, D bits)
+  const float* Gc;
+  const int2* cls;
 };
 // ondemand.hip -- per-block weights, rows of C_b formed on demand
 struct OnDemandPlan {
@@ -210,6 +215,14 @@ struct OnDemandPlan {
   int g_loss_ld;
 };
 se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s);
+
+// classes.hip -- parity classes of DCT / Walsh-Hadamard tables under a
+// mirror-symmetric weight pattern
+bool classes_possible(const se_tables* t);
+// flag (device) = 1 if w is not mirror-symmetric in both axes
+void launch_sym_check(const float* w, int M, int N, int* flag, hipStream_t s);
+// t->Gc and t->cls from t->G and t->D
+se_status build_classes(se_tables* t, hipStream_t s);
 
 // fused.hip -- projections of transform parts and the loop in one launch
 bool conceal_tx_supported(const se_tables* t);

@@ -3,7 +3,9 @@ atoms all lie in declared transform parts: every output must equal the
 two-launch route (se_project + se_iterate) bit for bit, for every loop shape
 of the row length, for areas inside the image (16-byte pixel segments) and
 across its border (single pixels), and the route must agree with the FP64
-oracle.  Tables with dense atoms take the two-launch route inside the call."""
+oracle.  Tables with dense atoms take the two-launch route inside the call.
+(The tables here carry no parity-class tables, with which the one-launch
+route streams class rows instead; tests/test_gpu_classes.py covers those.)"""
 import numpy as np
 import pytest
 import torch
@@ -64,7 +66,8 @@ def test_fused_equals_two_stage_area32(shape):
     w, v = shape
     say(f"fused vs two launches: 32x32 areas, 128 blocks, K=2048, I=100, shape {w}x{v}")
     phi = upload_phi(synth.round_to_f32(d["phi"]))
-    t, _, _ = shared_tables(d["images"], d["blocks"], phi, 32, 32, 0.8, parts=d["tx_parts"])
+    t, _, _ = shared_tables(d["images"], d["blocks"], phi, 32, 32, 0.8, parts=d["tx_parts"],
+                            classes=False)
     B.tune_clear()
     B.tune_import(f"2048 1024 {_bucket(len(d['blocks']))} {w} {v} 64\n")
     try:
@@ -87,7 +90,8 @@ def test_fused_border_areas_and_oracle():
     say("fused route: 8 blocks of 32x32 areas, 4 crossing the image border")
     phi_np = synth.round_to_f32(synth.dictionary(M, N, ("dct", "wht")))
     t, _, _ = shared_tables(images, blocks, upload_phi(phi_np), M, N, 0.8,
-                            parts=synth.dictionary_parts(M, N, ("dct", "wht")), ref_block=1)
+                            parts=synth.dictionary_parts(M, N, ("dct", "wht")), ref_block=1,
+                            classes=False)
     # every block's own weights differ at the border: compare the two
     # routes, which share the tables, bit for bit
     ref = _two_stage(t, images, blocks, 0.5, 100, 64)
@@ -110,7 +114,8 @@ def test_fused_equals_two_stage_area64(shape):
     w, v = shape
     say(f"fused vs two launches: 64x64 areas, 96 blocks, K=8192, I=300, shape {w}x{v}")
     phi = upload_phi(synth.round_to_f32(d["phi"]))
-    t, _, _ = shared_tables(d["images"], blocks, phi, 64, 64, 0.8, parts=d["tx_parts"])
+    t, _, _ = shared_tables(d["images"], blocks, phi, 64, 64, 0.8, parts=d["tx_parts"],
+                            classes=False)
     B.tune_clear()
     B.tune_import(f"8192 4096 {_bucket(len(blocks))} {w} {v} 64\n")
     try:

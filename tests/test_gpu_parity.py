@@ -35,13 +35,15 @@ def upload_phi(phi):
 
 
 def shared_tables(images, blocks, phi32, M, N, rho_hat, precision=B.SE_FP32, flags=0,
-                  ref_block=0, parts=()):
-    """Weights of block ``ref_block`` computed on the device, then the tables."""
+                  ref_block=0, parts=(), classes=True):
+    """Weights of block ``ref_block`` computed on the device, then the tables
+    (with buffers for parity-class tables unless ``classes`` is False)."""
     n_img, H, W = images.shape
     lost = np.stack([synth.lost_mask(H, W, blocks, i) for i in range(n_img)])
     lost_d = torch.from_numpy(lost).to(dev())
     w = B.area_weights(M, N, rho_hat, lost_d, [blocks[ref_block]])
-    t = B.weighted_gram(phi32, w[0].contiguous(), M, N, precision, flags, parts=parts)
+    t = B.weighted_gram(phi32, w[0].contiguous(), M, N, precision, flags, parts=parts,
+                        classes=classes)
     return t, w[0], lost
 
 
