@@ -184,6 +184,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (default: tune loop shape and GEMM tile on the "
                          "benchmark batch before timing)")
+    ap.add_argument("--no-classes", action="store_true",
+                    help="tables without parity-class rows (every iteration streams a whole row)")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the timing of the step captured as a HIP graph")
     ap.add_argument("--two-launch", action="store_true",
@@ -234,7 +236,8 @@ def main():
         torch.cuda.synchronize()
         g0.record(stream)
         w = B.area_weights(M, N, RHO, lost_d, blocks[:1])
-        t = B.weighted_gram(phi_d, w[0].contiguous(), M, N, parts=parts)
+        t = B.weighted_gram(phi_d, w[0].contiguous(), M, N, parts=parts,
+                            classes=not args.no_classes)
         g1.record(stream)
         torch.cuda.synchronize()
         gram_runs.append(g0.elapsed_time(g1))
@@ -309,6 +312,26 @@ def main():
                  "loop_ms": float(np.mean([e[1].elapsed_time(e[2]) for e in s_evs])),
                  "what": "se_project + se_iterate (projections written to R, then the loop)"}
 
+    # the one-launch step on tables without parity-class rows (every
+    # iteration streams a whole row), for comparison
+    full_rows = None
+    if fused and t.n_classes == 4:
+        tf = B.weighted_gram(phi_d, w[0].contiguous(), M, N, parts=parts, classes=False)
+        dblk_f = B.DeviceBlocks(tf, images_d, blocks)
+
+        def one_launch_full(ev=None, st=None):
+            if ev is not None:
+                ev[0].record(stream)
+            B.extrapolate_device(tf, images_d, dblk_f, GAMMA, ITERS, stream=st)
+            if ev is not None:
+                ev[2].record(stream)
+        f_ms, f_evs = timed(one_launch_full, args.steps)
+        full_rows = {"ms_per_step": f_ms, "blocks_per_s": nblk / (f_ms * 1e-3),
+                     "fused_ms": float(np.mean([e[0].elapsed_time(e[2]) for e in f_evs])),
+                     "what": "the one-launch step with tables without parity-class rows "
+                             "(eager): every iteration streams a whole row of K entries"}
+        del tf, dblk_f
+
     # the same step captured once into a HIP graph and replayed
     graph_info = None
     if not args.no_graph:
@@ -371,12 +394,22 @@ def main():
     note = ("requested row bytes; frac > 1 because the rows of the 16 MiB table are served by "
             "L2 and the Infinity Cache (traffic = measured HBM bytes); the limiter is the "
             "compute units' vector memory pipeline (address and data units busy 83-87%)")
+    classes = fused and t.n_classes == 4
     if fused:
-        # rows of G and the atom over the loss per iteration, the area's pixels once
-        fused_bytes_per_block = ITERS * (K_ATOMS + loss_px) * 4 + P
+        # rows of G (class rows of K/4 entries with parity classes) and the
+        # atom over the loss per iteration, the area's pixels once
+        row_len = K_ATOMS // 4 if classes else K_ATOMS
+        fused_bytes_per_block = ITERS * (row_len + loss_px) * 4 + P
         loop_gbs = fused_bytes_per_block * nblk / (loop_avg * 1e-3) / 1e9
         proj_tfs = None
-        roof = {"kernel": "k_conceal_tx (transform projections + iteration loop)",
+        if classes:
+            note = ("requested bytes (class rows of K/4 entries, the atom over the loss, the "
+                    "pixels); the 4 MiB of class rows are served by L2, so HBM carries far "
+                    "less (traffic = measured HBM bytes); the loop is bound by the latency of "
+                    "each iteration's dependent chain (selection, row load, update), with "
+                    "4096 blocks giving 4 chains per SIMD")
+        roof = {"kernel": ("k_conceal_tx (transform projections + class-row iteration loop)"
+                           if classes else "k_conceal_tx (transform projections + iteration loop)"),
                 "bound": "hbm", "achieved": loop_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": loop_gbs / HBM_PEAK_GBS,
                 "traffic": measured_traffic(args.images, "k_conceal_tx_area32_k2048_traffic.txt",
@@ -426,7 +459,9 @@ def main():
             "blocks_per_step": nblk, "K": K_ATOMS, "iters": ITERS, "area": [M, N],
             "loss": [8, 8],
             "form": ("batched, one launch per step: each block's workgroup computes its "
-                     "projections as separable transforms, then runs the loop" if fused else
+                     "projections as separable transforms, then runs the loop"
+                     + (" on parity-class rows (mirror-symmetric weights: each iteration "
+                        "updates the selected atom's class)" if classes else "") if fused else
                      "batched (project GEMM + one workgroup per block)" if args.no_parts else
                      "batched (separable transforms + one workgroup per block)"),
         },
@@ -451,6 +486,7 @@ def main():
                      "project_flops_per_block": proj_flops_per_block,
                      "project_form": "gemm" if args.no_parts else "transform"}),
         "two_launch": split,
+        "full_rows": full_rows,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -34,6 +34,12 @@
 // and eq. 20 updates only the selected atom's class -- every other entry of
 // its row of D C D is 0.  The selected position maps to its original atom
 // (for the model, the reported selection and D) through the class table.
+// With one wave per block the largest |R~| of each class is kept, per lane
+// and over the wave, across iterations: only the updated class is rescanned,
+// the class maxima are compared in scalar registers, and the winner is found
+// in the winning class (the same position the full scan finds: classes
+// occupy increasing positions, so the lowest class among equal maxima holds
+// the lowest position).
 #pragma once
 
 #include "argmax.h"
@@ -43,13 +49,23 @@ namespace sefase {
 
 constexpr int kQPL = 4;   // loss pixels per lane (the loss may hold <= 4 T pixels)
 
+// Largest |R~| of a lane's values in class C (sweeps C NJC .. C NJC + NJC - 1).
+template <int NJ, int NJC, int C>
+__device__ __forceinline__ float class_lane_max(const float (&R)[NJ][4]) {
+  float m = 0.0f;
+#pragma unroll
+  for (int j = C * NJC; j < (C + 1) * NJC; ++j)
+    m = fmaxf(m, fmaxf(fmaxf(fabsf(R[j][0]), fabsf(R[j][1])), fmaxf(fabsf(R[j][2]), fabsf(R[j][3]))));
+  return m;
+}
+
 // The iterations and the paste for block b of a workgroup of WAVES waves,
 // from R~^(0) in registers (lane t: atoms 4 (j T + t) + e).
 template <int WAVES, int VPL, bool CLS = false>
 __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (&R)[VPL / 4][4]) {
   constexpr int T = 64 * WAVES;
   constexpr int NJ = VPL / 4;
-  constexpr int NJC = NJ / 4;                  // sweeps of one class (CLS)
+  constexpr int NJC = NJ / 4 > 0 ? NJ / 4 : 1;   // sweeps of one class (CLS)
   static_assert(!CLS || NJ % 4 == 0, "the class form needs whole sweeps per class");
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -76,7 +92,76 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
   int par = 0;
   const float gamma = a.gamma;
 
+  // class maxima kept across iterations (class form, one wave): per lane,
+  // and over the wave as float bits (uniform)
+  constexpr bool INC = CLS && WAVES == 1;
+  float lmc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  uint32_t wmc[4] = {0u, 0u, 0u, 0u};
+  if constexpr (INC) {
+    lmc[0] = class_lane_max<NJ, NJC, 0>(R);
+    lmc[1] = class_lane_max<NJ, NJC, 1>(R);
+    lmc[2] = class_lane_max<NJ, NJC, 2>(R);
+    lmc[3] = class_lane_max<NJ, NJC, 3>(R);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) wmc[c] = __float_as_uint(wave_max_f32(lmc[c]));
+  }
+
   for (int it = 0; it < a.iters; ++it) {
+    int u = 0;
+    float rv = 0.0f;
+    uint64_t key = 0;                          // every score zero: atom 0, value 0
+    bool direct = WAVES == 1;
+    if constexpr (INC) {
+      // ---- the largest class maximum (lowest class first), then its holder
+      const uint32_t Mb = max(max(wmc[0], wmc[1]), max(wmc[2], wmc[3]));
+      if (Mb != 0u) {
+        const int cw = wmc[0] == Mb ? 0 : wmc[1] == Mb ? 1 : wmc[2] == Mb ? 2 : 3;
+        const float v = cw == 0 ? lmc[0] : cw == 1 ? lmc[1] : cw == 2 ? lmc[2] : lmc[3];
+        const uint64_t holders = __builtin_amdgcn_ballot_w64(__float_as_uint(v) == Mb);
+        if (__builtin_popcountll(holders) == 1) {
+          // lane L alone: its values of the class, lowest position first
+          const int L = __builtin_ctzll(holders);
+          int pos = 4 * NJC - 1;
+          uint32_t bits[4 * NJC > 0 ? 4 * NJC : 1];
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc)
+            if (cc == cw) {                    // uniform branch
+#pragma unroll
+              for (int jj = 0; jj < NJC; ++jj)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                  bits[4 * jj + e] =
+                      (uint32_t)__builtin_amdgcn_readlane(__float_as_int(R[cc * NJC + jj][e]), L);
+            }
+#pragma unroll
+          for (int i = 4 * NJC - 2; i >= 0; --i) pos = (bits[i] & 0x7FFFFFFFu) == Mb ? i : pos;
+          uint32_t vb = bits[4 * NJC - 1];
+#pragma unroll
+          for (int i = 4 * NJC - 2; i >= 0; --i) vb = i == pos ? bits[i] : vb;
+          u = 4 * ((cw * NJC + (pos >> 2)) * T + L) + (pos & 3);
+          rv = __uint_as_float(vb);
+        } else {
+          // exact ties across lanes: every lane's first maximum in the class
+          float bv = 0.0f;
+          int c = 0;
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc)
+            if (cc == cw) {
+#pragma unroll
+              for (int jj = 0; jj < NJC; ++jj)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                  if (fabsf(R[cc * NJC + jj][e]) > fabsf(bv)) {
+                    bv = R[cc * NJC + jj][e];
+                    c = 4 * (cc * NJC + jj) + e;
+                  }
+            }
+          const uint64_t mine = make_key(bv, 4 * ((c >> 2) * T + t) + (c & 3));
+          key = wave_max_key((uint32_t)(mine >> 32), (uint32_t)mine);
+          direct = false;
+        }
+      }
+    } else {
     // ---- this wave's largest |R~| and its lowest index ---------------------
     // Group maxima (4 atoms each) and the lane maximum, then the wave
     // maximum by DPP.
@@ -89,10 +174,6 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     for (int j = 1; j < NJ; ++j) lm = fmaxf(lm, gm[j]);
     const float M = wave_max_f32(lm);
     const uint64_t holders = __builtin_amdgcn_ballot_w64(lm == M);
-    int u = 0;
-    float rv = 0.0f;
-    uint64_t key = 0;                          // every score zero: atom 0, value 0
-    bool direct = WAVES == 1;
     if (M != 0.0f && __builtin_popcountll(holders) == 1) {
       // lane L alone holds the maximum: its group maxima, then the four
       // values of the first matching group, are read into scalar
@@ -138,6 +219,7 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
       key = wave_max_key((uint32_t)(mine >> 32), (uint32_t)mine);
       direct = false;
     }
+    }
     if (WAVES > 1) {
       if (lane == 0) s_key[par][wave] = key;
       __syncthreads();
@@ -154,11 +236,18 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     u = __builtin_amdgcn_readfirstlane(u);
     rv = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rv)));
     const float tc = gamma * rv;              // coefficient of the unit-norm atom
+    constexpr int NR = CLS ? NJC : NJ;
+    const float* grow = CLS ? a.Gc + (size_t)u * (T * NJ) : a.G + (size_t)u * a.ldG;
+    float4 row[NR];
+    if constexpr (CLS) {
+#pragma unroll
+      for (int j = 0; j < NR; ++j) row[j] = *reinterpret_cast<const float4*>(grow + 4 * (j * T + t));
+    }
     // the selected atom's original index and D (the class form: from the
     // class table; a scalar load that does not wait behind vector loads)
     int ou = u;
     float Du = 0.0f;
-    if (CLS) {
+    if constexpr (CLS) {
       const uint64_t cu = ((const __attribute__((address_space(4))) uint64_t*)a.cls)[u];
       ou = (int)(uint32_t)cu;
       Du = __uint_as_float((uint32_t)(cu >> 32));
@@ -175,35 +264,40 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
       for (int q = 1; q < kQPL; ++q)
         if (q < nq) pv[q] = prow[poff[q]];
     }
-    constexpr int NR = CLS ? NJC : NJ;
-    const float* grow = CLS ? a.Gc + (size_t)u * (T * NJ) : a.G + (size_t)u * a.ldG;
-    float4 row[NR];
+    if constexpr (!CLS) {
 #pragma unroll
-    for (int j = 0; j < NR; ++j) row[j] = *reinterpret_cast<const float4*>(grow + 4 * (j * T + t));
+      for (int j = 0; j < NR; ++j) row[j] = *reinterpret_cast<const float4*>(grow + 4 * (j * T + t));
+    }
     // D is read-only for the whole launch: a scalar load (constant address
     // space) that does not wait behind the row's vector loads
-    if (!CLS) Du = ((const __attribute__((address_space(4))) float*)a.D)[u];
+    if constexpr (!CLS) Du = ((const __attribute__((address_space(4))) float*)a.D)[u];
     const float c = tc * Du;                  // eq. 19
     if (t == 0) {
       if (a.sel) a.sel[(size_t)b * a.iters + it] = ou;
       if (a.coef) a.coef[(size_t)b * a.iters + it] = c;
     }
-    {                                         // eq. 9, compensated
-      const float y = fmaf(c, pv[0], -gc[0]);
-      const float s = g[0] + y;
-      gc[0] = (s - g[0]) - y;
-      g[0] = s;
-    }
-    if (nq > 1) {
+    // eq. 9, compensated (the class form applies it after eq. 20: its
+    // atom's loads wait for the class table and are not on the path to the
+    // next selection)
+    auto model_update = [&]() {
+      {
+        const float y = fmaf(c, pv[0], -gc[0]);
+        const float s = g[0] + y;
+        gc[0] = (s - g[0]) - y;
+        g[0] = s;
+      }
+      if (nq > 1) {
 #pragma unroll
-      for (int q = 1; q < kQPL; ++q)
-        if (q < nq) {
-          const float y = fmaf(c, pv[q], -gc[q]);
-          const float s = g[q] + y;
-          gc[q] = (s - g[q]) - y;
-          g[q] = s;
-        }
-    }
+        for (int q = 1; q < kQPL; ++q)
+          if (q < nq) {
+            const float y = fmaf(c, pv[q], -gc[q]);
+            const float s = g[q] + y;
+            gc[q] = (s - g[q]) - y;
+            g[q] = s;
+          }
+      }
+    };
+    if constexpr (!CLS) model_update();
 
     // ---- eq. 20 -------------------------------------------------------------
     if (CLS) {
@@ -218,6 +312,15 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
             R[cc * NJC + j][2] = fmaf(-tc, row[j].z, R[cc * NJC + j][2]);
             R[cc * NJC + j][3] = fmaf(-tc, row[j].w, R[cc * NJC + j][3]);
           }
+          if constexpr (INC) {                  // the class's new maxima
+            float m = 0.0f;
+#pragma unroll
+            for (int j = cc * NJC; j < (cc + 1) * NJC; ++j)
+              m = fmaxf(m, fmaxf(fmaxf(fabsf(R[j][0]), fabsf(R[j][1])),
+                                 fmaxf(fabsf(R[j][2]), fabsf(R[j][3]))));
+            lmc[cc] = m;
+            wmc[cc] = __float_as_uint(wave_max_f32(m));
+          }
         }
     } else {
 #pragma unroll
@@ -228,6 +331,7 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
         R[j][3] = fmaf(-tc, row[j].w, R[j][3]);
       }
     }
+    if constexpr (CLS) model_update();
   }
 
   // ---- replace the loss area by the model ----------------------------------

@@ -153,3 +153,34 @@ def test_no_class_tables_without_the_structure():
     t2, _, _ = shared_tables(d["images"], d["blocks"], upload_phi(mixed), 32, 32, 0.8,
                              parts=synth.dictionary_parts(32, 32, ("dct", "gauss"), 1024))
     assert t2.n_classes == 0
+
+
+def _bucket(n):
+    b = 0
+    while (1 << b) < n:
+        b += 1
+    return b
+
+
+def test_class_route_shapes_agree():
+    """The one-wave class loop (class maxima kept across iterations) and the
+    two-wave one (the whole row scanned every iteration) select the same
+    positions, so every output is the same bit for bit."""
+    d = synth.area32_inputs(8)
+    say("class route: loop shapes 1x32 (kept class maxima) and 2x16 (full scans)")
+    phi = upload_phi(synth.round_to_f32(d["phi"]))
+    t, _, _ = shared_tables(d["images"], d["blocks"], phi, 32, 32, 0.8, parts=d["tx_parts"])
+    assert t.n_classes == 4
+    got = []
+    for w, v in ((1, 32), (2, 16)):
+        B.tune_clear()
+        B.tune_import(f"2048 1024 {_bucket(len(d['blocks']))} {w} {v} 64\n")
+        try:
+            img = torch.from_numpy(d["images"]).to(dev())
+            sel, coef, g = B.extrapolate_batch(t, img, d["blocks"], 0.5, 100)
+            torch.cuda.synchronize()
+            got.append([x.cpu() for x in (sel, coef, g, img)])
+        finally:
+            B.tune_clear()
+    for name, x, y in zip(("sel", "coef", "g_loss", "image"), *got):
+        assert torch.equal(x, y), f"{name} differs between the loop shapes"
