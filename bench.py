@@ -767,8 +767,20 @@ def bench_area64(args):
                      "project_tflops": flops / (np.median(proj) * 1e-3) / 1e12,
                      "loop_ms": float(np.median(loop)), "gram_ms": min(gram),
                      "gram_tflops": 8192 * 8193 * 4096 / (min(gram) * 1e-3) / 1e12}
+        if parts:
+            # projections and loop in one launch (on parity-class rows when the
+            # tables have them)
+            one = _timed(lambda: B.extrapolate_device(t, img, dblk, 0.5, 300),
+                         max(2, args.steps // 4), 1)
+            out[name]["one_launch"] = {
+                "ms_per_step": float(np.median(one)),
+                "blocks_per_s": len(blocks) / (float(np.median(one)) * 1e-3),
+                "class_rows": t.n_classes == 4}
         del t
-    out["value"] = out["bf16x3"]["blocks_per_s"]
+    # the chosen form: one launch when the dictionary's parts allow it
+    best = out["bf16x3"].get("one_launch", out["bf16x3"])
+    out["value"] = best["blocks_per_s"]
+    out["ms_per_step"] = best["ms_per_step"]
     out["dtype"] = "bf16x3"
     return out
 
