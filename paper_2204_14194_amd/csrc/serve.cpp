@@ -109,12 +109,26 @@ namespace sefase {
 
 using Server = se_server;
 
+// Whether a basis set can have parity-class tables (the weight pattern's
+// symmetry is decided when its tables are built): two transform parts
+// covering the dictionary of an even-sided area, K a multiple of 1024 equal
+// to the loop's row length.
+static bool class_capable(const se_basis& b) {
+  if (b.n_parts != 2 || (b.M & 1) || (b.N & 1) || b.K % 1024 || b.K != greedy_row_len(b.K))
+    return false;
+  int lo[3], hi[3];
+  return dense_ranges(b.K, b.M * b.N, b.n_parts, b.parts, lo, hi) == 0;
+}
+
 static size_t tables_bytes(const se_basis& b) {
   const int K = b.K, P = b.M * b.N;
   const size_t ld = (size_t)greedy_row_len(K);
+  const size_t cls = class_capable(b)
+                         ? align_up((size_t)K * (K / 4) * 4, 256) + align_up((size_t)K * 8, 256)
+                         : 0;
   return align_up((size_t)K * ld * 4, 256) + align_up((size_t)K * 4, 256) +
          align_up((size_t)K * P * 4, 256) + align_up((size_t)P * 4, 256) +
-         align_up(tx_const_bytes(b.M, b.N, b.n_parts), 256) + 256;
+         align_up(tx_const_bytes(b.M, b.N, b.n_parts), 256) + cls + 256;
 }
 
 static void evict_for(Server* s, size_t need) {
@@ -195,6 +209,10 @@ static CachedTables* get_tables(Server* s, const PatternKey& key, hipStream_t st
   t.Yhi = t.Ylo = nullptr;
   t.tx = b.n_parts > 0 ? reinterpret_cast<float*>(take(tx_const_bytes(b.M, b.N, b.n_parts)))
                        : nullptr;
+  if (class_capable(b)) {   // used when the pattern turns out mirror-symmetric
+    t.Gc = reinterpret_cast<float*>(take((size_t)K * (K / 4) * 4));
+    t.cls = reinterpret_cast<int32_t*>(take((size_t)K * 8));
+  }
   // the pattern's weights: an M x N mask with the loss marked, one block at 0,0
   Carver cv(scratch);
   uint8_t* mask = cv.take<uint8_t>((size_t)P);
