@@ -119,27 +119,26 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
         const float v = cw == 0 ? lmc[0] : cw == 1 ? lmc[1] : cw == 2 ? lmc[2] : lmc[3];
         const uint64_t holders = __builtin_amdgcn_ballot_w64(__float_as_uint(v) == Mb);
         if (__builtin_popcountll(holders) == 1) {
-          // lane L alone: its values of the class, lowest position first
+          // lane L alone: every lane finds its first position holding the
+          // maximum in the class (vector selects), then L's position and
+          // value are read
           const int L = __builtin_ctzll(holders);
-          int pos = 4 * NJC - 1;
-          uint32_t bits[4 * NJC > 0 ? 4 * NJC : 1];
+          int lpos = 0;
+          uint32_t lval = 0u;
 #pragma unroll
           for (int cc = 0; cc < 4; ++cc)
             if (cc == cw) {                    // uniform branch
 #pragma unroll
-              for (int jj = 0; jj < NJC; ++jj)
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                  bits[4 * jj + e] =
-                      (uint32_t)__builtin_amdgcn_readlane(__float_as_int(R[cc * NJC + jj][e]), L);
+              for (int i = 4 * NJC - 1; i >= 0; --i) {
+                const uint32_t bi = __float_as_uint(R[cc * NJC + (i >> 2)][i & 3]);
+                const bool hit = (bi & 0x7FFFFFFFu) == Mb;
+                lpos = hit ? i : lpos;
+                lval = hit ? bi : lval;
+              }
             }
-#pragma unroll
-          for (int i = 4 * NJC - 2; i >= 0; --i) pos = (bits[i] & 0x7FFFFFFFu) == Mb ? i : pos;
-          uint32_t vb = bits[4 * NJC - 1];
-#pragma unroll
-          for (int i = 4 * NJC - 2; i >= 0; --i) vb = i == pos ? bits[i] : vb;
+          const int pos = __builtin_amdgcn_readlane(lpos, L);
           u = 4 * ((cw * NJC + (pos >> 2)) * T + L) + (pos & 3);
-          rv = __uint_as_float(vb);
+          rv = __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)lval, L));
         } else {
           // exact ties across lanes: every lane's first maximum in the class
           float bv = 0.0f;
