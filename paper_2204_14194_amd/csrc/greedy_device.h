@@ -271,9 +271,11 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     // space) that does not wait behind the row's vector loads
     if constexpr (!CLS) Du = ((const __attribute__((address_space(4))) float*)a.D)[u];
     const float c = tc * Du;                  // eq. 19
-    if (t == 0) {
-      if (a.sel) a.sel[(size_t)b * a.iters + it] = ou;
-      if (a.coef) a.coef[(size_t)b * a.iters + it] = c;
+    if (a.sel || a.coef) {                    // uniform test first: no lane mask work
+      if (t == 0) {
+        if (a.sel) a.sel[(size_t)b * a.iters + it] = ou;
+        if (a.coef) a.coef[(size_t)b * a.iters + it] = c;
+      }
     }
     // eq. 9, compensated (the class form applies it after eq. 20: its
     // atom's loads wait for the class table and are not on the path to the
