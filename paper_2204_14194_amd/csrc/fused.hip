@@ -26,7 +26,9 @@ constexpr int conceal_lds_floats() {
 // compiler keeps the projection stage in vector registers without the
 // accumulation registers it would otherwise add (four resident blocks per
 // SIMD cover a 4096-block batch at once); larger areas take what they need.
-template <int WAVES, int VPL, int MT, int NT, int NP, bool CLS>
+// VOL: areas of several frames, read as their frames stacked (M = T rows of
+// frames).
+template <int WAVES, int VPL, int MT, int NT, int NP, bool CLS, bool VOL>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(MT * NT <= 4 ? 4 : 1)))
 void k_conceal_tx(GreedyArgs a, TxArgs x, TxLayout L) {
   constexpr int T = 64 * WAVES;
@@ -44,8 +46,8 @@ void k_conceal_tx(GreedyArgs a, TxArgs x, TxLayout L) {
   floatx4 xv[MT][NT];
   if (computes) {
     TxPixels<MT, NT> P;
-    tx_load<MT, NT>(x, d, M, N, P);
-    tx_x_operands<MT, NT>(x, d, M, N, P, x.tx + L.oWf, Rs + wave * MT * NT * 256, xv);
+    tx_load<MT, NT, VOL>(x, d, M, N, P);
+    tx_x_operands<MT, NT, VOL>(x, d, M, N, P, x.tx + L.oWf, Rs + wave * MT * NT * 256, xv);
   }
   __syncthreads();   // every X operand is in registers: the LDS becomes the row
   if (computes) {
@@ -83,28 +85,30 @@ void k_conceal_tx(GreedyArgs a, TxArgs x, TxLayout L) {
   greedy_block<WAVES, VPL, CLS>(a, b, R);
 }
 
-template <int WAVES, int VPL, int MT, int NT, int NP, bool CLS>
+template <int WAVES, int VPL, int MT, int NT, int NP, bool CLS, bool VOL = false>
 static se_status launch_conceal(const GreedyArgs& a, const TxArgs& x, const TxLayout& L, int grid,
                                 hipStream_t s) {
   const size_t lds = (size_t)conceal_lds_floats<WAVES, VPL, MT, NT, NP>() * 4;
-  hipLaunchKernelGGL((k_conceal_tx<WAVES, VPL, MT, NT, NP, CLS>), dim3(grid), dim3(64 * WAVES),
-                     lds, s, a, x, L);
+  hipLaunchKernelGGL((k_conceal_tx<WAVES, VPL, MT, NT, NP, CLS, VOL>), dim3(grid),
+                     dim3(64 * WAVES), lds, s, a, x, L);
   return check_launch("conceal_tx");
 }
 
 // The instantiated combinations: two parts covering every atom of 32 x 32 or
-// 64 x 64 areas (K = 2048 or 8192), with every loop shape of that row length.
+// 64 x 64 areas (K = 2048 or 8192), with every loop shape of that row length,
+// and of 64 x 16 (K = 2048) -- also four frames of 16 x 16 stacked.  M is the
+// transformed row count (frames x rows).
 static int conceal_case(int M, int N, int n_parts) {
-  if (n_parts != 2 || M != N) return 0;
-  return M == 32 ? 2 : M == 64 ? 4 : 0;
+  if (n_parts != 2) return 0;
+  if (M == N) return M == 32 ? 2 : M == 64 ? 4 : 0;
+  return M == 64 && N == 16 ? 5 : 0;
 }
 
 bool conceal_tx_supported(const se_tables* t) {
-  if (!t || t->n_parts < 1 || !t->tx || area_frames(t->T) > 1 ||
-      conceal_case(t->M, t->N, t->n_parts) == 0)
+  if (!t || t->n_parts < 1 || !t->tx || conceal_case(tx_rows(t), t->N, t->n_parts) == 0)
     return false;
   int lo[3], hi[3];
-  return dense_ranges(t->K, t->M * t->N, t->n_parts, t->parts, lo, hi) == 0;
+  return dense_ranges(t->K, area_samples(t), t->n_parts, t->parts, lo, hi) == 0;
 }
 
 se_status conceal_tx(const se_tables* t, const GreedyArgs& a, const uint8_t* images, int H, int W,
@@ -131,16 +135,28 @@ se_status conceal_tx(const se_tables* t, const GreedyArgs& a, const uint8_t* ima
   x.tx = t->tx;
   x.first0 = t->parts[0].first;
   x.first1 = t->n_parts > 1 ? t->parts[1].first : 0;
-  x.fs = 0;   // one frame (the two-dimensional loaders)
-  const TxLayout L(t->M, t->N, t->n_parts, 0);
-  const int key = conceal_case(t->M, t->N, t->n_parts) * 10000 + waves * 100 + vpl;
+  // several frames: the loaders that stack them (rows per frame 2^fs)
+  const bool vol = area_frames(t->T) > 1;
+  x.fs = 0;
+  if (vol)
+    while ((1 << x.fs) < t->M) ++x.fs;
+  const int Mv = tx_rows(t);
+  const TxLayout L(Mv, t->N, t->n_parts, 0);
+  const int key = conceal_case(Mv, t->N, t->n_parts) * 10000 + waves * 100 + vpl;
   if (cls) {
     switch (key) {
       case 20132: return launch_conceal<1, 32, 2, 2, 2, true>(a, x, L, n_blk, s);
       case 20216: return launch_conceal<2, 16, 2, 2, 2, true>(a, x, L, n_blk, s);
       case 40432: return launch_conceal<4, 32, 4, 4, 2, true>(a, x, L, n_blk, s);
       case 40816: return launch_conceal<8, 16, 4, 4, 2, true>(a, x, L, n_blk, s);
-      default: return fail(SE_EINVAL, "no fused class loop shape %dx%d for K=%d", waves, vpl, t->K);
+      default: break;   // whole rows
+    }
+  }
+  if (vol) {
+    switch (key) {
+      case 50132: return launch_conceal<1, 32, 4, 1, 2, false, true>(a, x, L, n_blk, s);
+      case 50216: return launch_conceal<2, 16, 4, 1, 2, false, true>(a, x, L, n_blk, s);
+      default: return fail(SE_EINVAL, "no fused loop shape %dx%d for K=%d", waves, vpl, t->K);
     }
   }
   switch (key) {
@@ -149,6 +165,8 @@ se_status conceal_tx(const se_tables* t, const GreedyArgs& a, const uint8_t* ima
     case 20408: return launch_conceal<4, 8, 2, 2, 2, false>(a, x, L, n_blk, s);
     case 40432: return launch_conceal<4, 32, 4, 4, 2, false>(a, x, L, n_blk, s);
     case 40816: return launch_conceal<8, 16, 4, 4, 2, false>(a, x, L, n_blk, s);
+    case 50132: return launch_conceal<1, 32, 4, 1, 2, false>(a, x, L, n_blk, s);
+    case 50216: return launch_conceal<2, 16, 4, 1, 2, false>(a, x, L, n_blk, s);
     default: return fail(SE_EINVAL, "no fused loop shape %dx%d for K=%d", waves, vpl, t->K);
   }
 }

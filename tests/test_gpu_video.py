@@ -234,3 +234,43 @@ def test_video_part_declaration_is_verified():
     # the Walsh-Hadamard half alone is the same either way (Sylvester order
     # is a Kronecker power), so it is accepted
     B.weighted_gram(upload_phi(wrong), w, M, N, T=T, parts=[("wht", T * M * N)])
+
+
+def _two_stage_and_one_launch(t, frames, blocks, iters):
+    n = len(blocks)
+    outs = []
+    for one in (False, True):
+        img = torch.from_numpy(frames).to(dev())
+        db = B.DeviceBlocks(t, img, blocks)
+        sel = torch.full((n, iters), -7, dtype=torch.int32, device=dev())
+        coef = torch.zeros((n, iters), dtype=torch.float32, device=dev())
+        g = torch.zeros((n, 64), dtype=torch.float32, device=dev())
+        if one:
+            nb = B.extrapolate_device_ws_bytes(t, n)
+            assert nb == 0
+            B.extrapolate_device(t, img, db, 0.5, iters, None, sel, coef, g)
+        else:
+            R = torch.empty((n, t.ldR), dtype=torch.float32, device=dev())
+            ws = torch.empty(max(1, B.project_ws_bytes(t, n)), dtype=torch.uint8, device=dev())
+            B.project(t, img, db, R, ws)
+            B.iterate(t, R, img, db, 0.5, iters, sel, coef, g)
+        torch.cuda.synchronize()
+        outs.append([x.cpu() for x in (sel, coef, g, img)])
+    for name, x, y in zip(("sel", "coef", "g_loss", "frames"), *outs):
+        assert torch.equal(x, y), f"{name} differs between one launch and two"
+
+
+def test_video_one_launch_equals_two_stage():
+    """Areas of four 16 x 16 frames with transform parts take one launch
+    (the frames stacked into a 64 x 16 transform inside each block's
+    workgroup): the same bits as the projection launch and the loop launch,
+    for areas on the 16-byte grid and across the frame border."""
+    d = synth.video_inputs(1, frames=8)
+    T, M, N = d["T"], d["M"], d["N"]
+    say(f"video one launch vs two: {len(d['blocks'])} areas of {T}x{M}x{N}")
+    phi = synth.round_to_f32(d["phi"])
+    t = _tables(phi, d["frames"], d["blocks"], T, M, N, parts=d["tx_parts"])
+    _two_stage_and_one_launch(t, d["frames"], d["blocks"], 100)
+    border = [synth.Block(0, -5, -3, 4, 4, 8, 8, 2, 1), synth.Block(4, 120, 118, 4, 4, 8, 8, 2, 1),
+              synth.Block(0, 40, 7, 4, 4, 8, 8, 1, 2)]
+    _two_stage_and_one_launch(t, d["frames"], border, 60)
