@@ -175,16 +175,17 @@ typedef struct {
  *   phi_im : copied from the dictionary.
  * For a real dictionary G_im and phi_im are NULL (G_im is not written).
  * Class tables (optional; Gc and cls may be NULL): when every atom lies in
- * the two declared transform parts of a two-dimensional area with even M
- * and N, K equals se_table_ld(K) and is a multiple of 1024, and the weight
- * pattern is mirror-symmetric in both axes (w[m][n] = w[M-1-m][n] =
- * w[m][N-1-n], bit for bit), every DCT-II and Walsh-Hadamard atom is even
- * or odd about the area's centre in each axis, so C_(k,l) of eq. 16 is 0
- * whenever k and l differ in either parity: the atoms fall into four
- * classes of Kc = K/4 and eq. 20 changes only the selected atom's class.
- * se_weighted_gram then writes, in class order (class 2 pv + ph for the
- * vertical and horizontal parities; in a class the parts in the order of
- * their first atoms, each by (k1/2, k2/2)):
+ * the two declared transform parts of an area with even M and N, K equals
+ * se_table_ld(K) and is a multiple of 1024, and the weight pattern is
+ * mirror-symmetric in the rows and columns of every frame (w[m][n] =
+ * w[M-1-m][n] = w[m][N-1-n], bit for bit), every DCT-II and Walsh-Hadamard
+ * atom is even or odd about the area's centre in each of those axes, so
+ * C_(k,l) of eq. 16 is 0 whenever k and l differ in either parity: the
+ * atoms fall into four classes of Kc = K/4 and eq. 20 changes only the
+ * selected atom's class.  se_weighted_gram then writes, in class order
+ * (class 2 pv + ph for the vertical and horizontal parities; in a class the
+ * parts in the order of their first atoms, each by (k1/2, k2/2), or by
+ * (kt, k1/2, k2/2) for areas of several frames):
  *   Gc   : K x (K/4) float32, 16-byte aligned: row p holds the entries of
  *          G between the p-th atom of the class order and the atoms of its
  *          own class, in class order;

@@ -336,8 +336,8 @@ def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
         if nb_tx == 0:
             raise ValueError(f"no transform parts for a {T}x{M}x{N} area")
         t.tx = torch.empty(nb_tx // 4, dtype=torch.float32, device=dev)
-    if (classes and len(t.parts) == 2 and int(T) == 1 and phi_im is None and M % 2 == 0
-            and N % 2 == 0 and K % 1024 == 0 and ldG == K):
+    if (classes and len(t.parts) == 2 and phi_im is None and M % 2 == 0 and N % 2 == 0
+            and K % 1024 == 0 and ldG == K):
         t.Gc = torch.empty((K, K // 4), dtype=torch.float32, device=dev)
         t.cls = torch.empty((K, 2), dtype=torch.int32, device=dev)
     b = make_basis(M, N, K, phi.data_ptr(), t.parts,

@@ -376,7 +376,7 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
   if (want_classes) {
     if (hipMemsetAsync(flag + 1, 0, sizeof(int32_t), s) != hipSuccess)
       return fail(SE_EHIP, "flag clear failed");
-    launch_sym_check(w, b->M, b->N, flag + 1, s);
+    launch_sym_check(w, area_frames(b->T), b->M, b->N, flag + 1, s);
     if ((st = check_launch("sym_check"))) return st;
   }
   if ((st = verify_parts(b, flag, s, want_classes ? &asym : nullptr))) {

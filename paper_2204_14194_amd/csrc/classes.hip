@@ -14,12 +14,17 @@
 // their first atoms; in a part the atoms (k1, k2) of the class by
 // (k1 / 2, k2 / 2), row-major.  Each part contributes M N / 4 atoms to each
 // class (M, N even: k = 2 i and k = 2 i + 1 always differ in parity).
+//
+// Areas of T frames: the mirrors act on the rows and columns of every frame
+// (the time axis is left alone), so a 3-D atom (kt, k1, k2) takes the
+// parities of k1 and k2, the weights must be mirror-symmetric within every
+// frame, and a part's atoms of a class are ordered by (kt, k1 / 2, k2 / 2).
 #include "se_internal.h"
 
 namespace sefase {
 
 struct ClassLayout {
-  int M, N, K, Kc;
+  int T, M, N, K, Kc;
   int first_lo, kind_lo, first_hi, kind_hi;
 };
 
@@ -33,21 +38,25 @@ __device__ inline int parity_row(int kind, int i, int par) {
 // original atom index of position p of the class order
 __device__ inline int class_orig(const ClassLayout& L, int p) {
   const int c = p / L.Kc, r = p - c * L.Kc;
-  const int Q = L.M * L.N / 4, h = L.N / 2;
+  const int F = L.M * L.N / 4, Q = L.T * F, h = L.N / 2;
   const int q = r / Q, s = r - q * Q;
   const int kind = q ? L.kind_hi : L.kind_lo, first = q ? L.first_hi : L.first_lo;
-  const int i1 = s / h, i2 = s - i1 * h;
-  return first + parity_row(kind, i1, c >> 1) * L.N + parity_row(kind, i2, c & 1);
+  const int kt = s / F, f = s - kt * F;
+  const int i1 = f / h, i2 = f - i1 * h;
+  return first + (kt * L.M + parity_row(kind, i1, c >> 1)) * L.N + parity_row(kind, i2, c & 1);
 }
 
-// flag = 1 if the weight pattern is not mirror-symmetric in both axes (bit
-// for bit)
-__global__ void k_sym_check(const float* __restrict__ w, int M, int N, int* __restrict__ flag) {
+// flag = 1 if the weight pattern is not mirror-symmetric in the rows and
+// columns of every frame (bit for bit)
+__global__ void k_sym_check(const float* __restrict__ w, int T, int M, int N,
+                            int* __restrict__ flag) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= M * N) return;
-  const int m = p / N, n = p - m * N;
-  const uint32_t v = __float_as_uint(w[p]);
-  if (v != __float_as_uint(w[(M - 1 - m) * N + n]) || v != __float_as_uint(w[m * N + N - 1 - n]))
+  if (p >= T * M * N) return;
+  const int f = p / (M * N), q = p - f * M * N;
+  const int m = q / N, n = q - m * N;
+  const float* wf = w + (size_t)f * M * N;
+  const uint32_t v = __float_as_uint(wf[q]);
+  if (v != __float_as_uint(wf[(M - 1 - m) * N + n]) || v != __float_as_uint(wf[m * N + N - 1 - n]))
     atomicOr(flag, 1);
 }
 
@@ -70,19 +79,20 @@ __global__ __launch_bounds__(256) void k_build_classes(ClassLayout L, const floa
 // The static conditions of the class tables (the weight symmetry is
 // checked on the device).
 bool classes_possible(const se_tables* t) {
-  if (!t->Gc || !t->cls || area_frames(t->T) != 1 || t->n_parts != 2 || t->phi_im) return false;
+  if (!t->Gc || !t->cls || t->n_parts != 2 || t->phi_im) return false;
   if ((t->M & 1) || (t->N & 1) || t->K % 1024 || t->K != greedy_row_len(t->K)) return false;
   int lo[3], hi[3];
-  return dense_ranges(t->K, t->M * t->N, t->n_parts, t->parts, lo, hi) == 0;
+  return dense_ranges(t->K, area_samples(t), t->n_parts, t->parts, lo, hi) == 0;
 }
 
-void launch_sym_check(const float* w, int M, int N, int* flag, hipStream_t s) {
-  const int P = M * N;
-  hipLaunchKernelGGL(k_sym_check, dim3((P + 255) / 256), dim3(256), 0, s, w, M, N, flag);
+void launch_sym_check(const float* w, int T, int M, int N, int* flag, hipStream_t s) {
+  const int P = T * M * N;
+  hipLaunchKernelGGL(k_sym_check, dim3((P + 255) / 256), dim3(256), 0, s, w, T, M, N, flag);
 }
 
 se_status build_classes(se_tables* t, hipStream_t s) {
   ClassLayout L;
+  L.T = area_frames(t->T);
   L.M = t->M;
   L.N = t->N;
   L.K = t->K;

@@ -149,6 +149,9 @@ se_status conceal_tx(const se_tables* t, const GreedyArgs& a, const uint8_t* ima
       case 20216: return launch_conceal<2, 16, 2, 2, 2, true>(a, x, L, n_blk, s);
       case 40432: return launch_conceal<4, 32, 4, 4, 2, true>(a, x, L, n_blk, s);
       case 40816: return launch_conceal<8, 16, 4, 4, 2, true>(a, x, L, n_blk, s);
+      case 50132:
+        return vol ? launch_conceal<1, 32, 4, 1, 2, true, true>(a, x, L, n_blk, s)
+                   : launch_conceal<1, 32, 4, 1, 2, true, false>(a, x, L, n_blk, s);
       default: break;   // whole rows
     }
   }

@@ -219,8 +219,9 @@ se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s);
 // classes.hip -- parity classes of DCT / Walsh-Hadamard tables under a
 // mirror-symmetric weight pattern
 bool classes_possible(const se_tables* t);
-// flag (device) = 1 if w is not mirror-symmetric in both axes
-void launch_sym_check(const float* w, int M, int N, int* flag, hipStream_t s);
+// flag (device) = 1 if w is not mirror-symmetric in the rows and columns of
+// every frame
+void launch_sym_check(const float* w, int T, int M, int N, int* flag, hipStream_t s);
 // t->Gc and t->cls from t->G and t->D
 se_status build_classes(se_tables* t, hipStream_t s);
 

@@ -19,12 +19,13 @@ pytestmark = pytest.mark.gpu
 TOL_BF16X3 = 1e-2
 
 
-def _tables(phi32, frames, blocks, T, M, N, ref_block=0, precision=B.SE_FP32, parts=()):
+def _tables(phi32, frames, blocks, T, M, N, ref_block=0, precision=B.SE_FP32, parts=(),
+            classes=True):
     F, H, W = frames.shape
     lost = torch.from_numpy(synth.video_lost_mask(F, H, W, blocks)).to(dev())
     w = B.area_weights(M, N, 0.8, lost, [blocks[ref_block]], T=T)
     return B.weighted_gram(upload_phi(phi32), w[0].contiguous(), M, N, precision, T=T,
-                           parts=parts)
+                           parts=parts, classes=classes)
 
 
 def _batch(t, frames, blocks, iters, plain=False):
@@ -269,8 +270,56 @@ def test_video_one_launch_equals_two_stage():
     T, M, N = d["T"], d["M"], d["N"]
     say(f"video one launch vs two: {len(d['blocks'])} areas of {T}x{M}x{N}")
     phi = synth.round_to_f32(d["phi"])
-    t = _tables(phi, d["frames"], d["blocks"], T, M, N, parts=d["tx_parts"])
+    t = _tables(phi, d["frames"], d["blocks"], T, M, N, parts=d["tx_parts"], classes=False)
     _two_stage_and_one_launch(t, d["frames"], d["blocks"], 100)
     border = [synth.Block(0, -5, -3, 4, 4, 8, 8, 2, 1), synth.Block(4, 120, 118, 4, 4, 8, 8, 2, 1),
               synth.Block(0, 40, 7, 4, 4, 8, 8, 1, 2)]
     _two_stage_and_one_launch(t, d["frames"], border, 60)
+
+
+def test_video_class_tables():
+    """Areas of four frames with a centred loss in one frame: the weights are
+    mirror-symmetric in every frame's rows and columns (not in time), so the
+    3-D DCT u WHT table is block diagonal in the spatial parities; the class
+    route's one launch against the whole-row two launches and the oracle."""
+    d = synth.video_inputs(1, frames=8)
+    T, M, N = d["T"], d["M"], d["N"]
+    say(f"video class tables: {len(d['blocks'])} areas of {T}x{M}x{N}")
+    phi = synth.round_to_f32(d["phi"])
+    tc = _tables(phi, d["frames"], d["blocks"], T, M, N, parts=d["tx_parts"])
+    assert tc.n_classes == 4
+    K, Kc = 2048, 512
+    cls = tc.cls.cpu().numpy()
+    G = tc.G.cpu().numpy()[:, :K]
+    Gc = tc.Gc.cpu().numpy()
+    order = cls[:, 0]
+    assert sorted(order.tolist()) == list(range(K))
+    # the class of an atom from its own rows: spatial parities of (k1, k2)
+    rows = {"dct": synth.dct_rows(M), "wht": synth.wht_rows(M)}
+    def parity(r):
+        return 0 if np.allclose(r[::-1], r, atol=1e-12) else 1
+    cls_of = np.zeros(K, int)
+    for name, first in d["tx_parts"]:
+        for k in range(T * M * N):
+            k1, k2 = (k // N) % M, k % N
+            cls_of[first + k] = 2 * parity(rows[name][k1]) + parity(rows[name][k2])
+    for c in range(4):
+        blk = order[c * Kc:(c + 1) * Kc]
+        assert np.all(cls_of[blk] == c)
+        assert np.all(np.diff(blk[:Kc // 2]) > 0) and np.all(np.diff(blk[Kc // 2:]) > 0)
+        np.testing.assert_array_equal(Gc[c * Kc:(c + 1) * Kc], G[np.ix_(blk, blk)])
+    worst = np.abs(G[cls_of[:, None] != cls_of[None, :]]).max()
+    print(f"max |G| between classes = {worst:.3g}")
+    assert worst < 1e-6
+    sel, _, g, out = _batch(tc, d["frames"], d["blocks"], 100)
+    tf = _tables(phi, d["frames"], d["blocks"], T, M, N, parts=d["tx_parts"], classes=False)
+    self_, _, gf, _ = _batch(tf, d["frames"], d["blocks"], 100)
+    dg = np.abs(g - gf).max()
+    print(f"class vs whole rows: identical selections "
+          f"{int(np.all(sel == self_, axis=1).sum())}/{len(sel)}, max|dg|={dg:.3g}")
+    assert dg <= TOL_FP32
+    st = oracle_check_video(d["frames"], d["blocks"], phi, T, M, N, 0.8, 0.5, 100, sel, g, out,
+                            tol=TOL_FP32)
+    print(f"class route vs oracle: identical selections {st['agree']}/{st['n']}, "
+          f"max|dg|={st['worst']:.3g}")
+    assert st["worst"] <= TOL_FP32
