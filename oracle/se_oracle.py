@@ -26,6 +26,11 @@ Contents, in the paper's notation:
   * ``fase``              -- Algorithm 3: R^(0) once (eq. 12), then
                              selection by eq. 18, coefficient by eq. 19 and
                              the recursive update eq. 20
+  * ``unit_table``, ``quantise_table``, ``fase_unit`` -- Algorithm 3 in the
+                             variables D_k R_k with the unit-diagonal table
+                             D C D, and that table as 16-bit fixed-point
+                             words (Section III: the loop has no division,
+                             so fixed-point tables suit it)
   * ``conceal``           -- the whole task for a list of lost blocks of an
                              image: weights, SE (or FaSE), and the
                              replacement of the loss area by the model
@@ -48,6 +53,9 @@ Readings where the paper is silent (each is listed in the design notes):
   * pixels outside the image or inside any lost block are not support:
     their weight is 0 and their sample value is taken as 0;
   * the model is cut into the image as clip(round-half-even(g), 0, 255);
+  * fixed-point tables: signed 16-bit words with 14 fraction bits of the
+    unit-diagonal table, round to nearest (ties to even); R, D and the
+    arithmetic of the loop are not quantised;
   * in three dimensions the decay of eq. 5 takes the Euclidean distance to
     the centre of the T x M x N box, one frame counting as one pixel, and
     sample (tau, m, n) sits at index (tau*M + m)*N + n.
@@ -64,6 +72,7 @@ __all__ = [
     "area_weights", "area_signal", "se_original", "table_generation", "fase",
     "conceal", "duplicate_classes", "quantise", "operation_counts",
     "SEResult", "volume_weights", "volume_signal", "conceal_video",
+    "unit_table", "quantise_table", "fase_unit",
 ]
 
 
@@ -307,6 +316,84 @@ def fase(s: np.ndarray, w: np.ndarray, phi: np.ndarray, C: np.ndarray,
         if keep_R:
             hist.append(R.copy())
     return SEResult(sel, coef, g, best, second, energy, hist, picked)
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 3 in unit-diagonal variables, and fixed-point tables
+# ----------------------------------------------------------------------------
+def unit_table(C: np.ndarray, D: np.ndarray) -> np.ndarray:
+    """G_(k,l) = D_k C_(k,l) D_l: the table of eq. 16 scaled by eq. 17 to a
+    unit diagonal (for atoms of nonzero weighted norm).  By the
+    Cauchy-Schwarz inequality in the weighted scalar product every entry has
+    magnitude at most 1."""
+    D = np.asarray(D, dtype=np.float64)
+    return D[:, None] * np.asarray(C) * D[None, :]
+
+
+def quantise_table(G: np.ndarray, frac_bits: int = 14) -> np.ndarray:
+    """Fixed-point words of a unit-diagonal table.  Section III notes that
+    Algorithm 3 needs no division inside the loop, which suits fixed-point
+    tables, and leaves their bit depth open.  Reading: signed 16-bit words
+    with ``frac_bits`` fraction bits (value = word * 2**-frac_bits), rounded
+    to the nearest word, ties to even.  With 14 fraction bits the range
+    [-2, 2) holds every entry of a unit-diagonal table (at most 1 in
+    magnitude) and the diagonal 1 exactly; a word out of the 16-bit range
+    is an error, never a saturation."""
+    if np.iscomplexobj(G):
+        raise ValueError("fixed-point tables are stated for real dictionaries")
+    G = np.asarray(G, dtype=np.float64)
+    q = np.rint(G * 2.0 ** frac_bits)
+    if q.size and (q.max() > 32767 or q.min() < -32768):
+        raise ValueError("table entry outside the 16-bit fixed-point range")
+    return q.astype(np.int16)
+
+
+def fase_unit(s: np.ndarray, w: np.ndarray, phi: np.ndarray, G: np.ndarray,
+              D: np.ndarray, gamma: float, iters: int,
+              classes: Optional[np.ndarray] = None,
+              forced: Optional[Sequence[int]] = None) -> SEResult:
+    """Algorithm 3 written in the variables R~_k = D_k R_k with the table
+    G = D C D (unit_table), for real dictionaries:
+      u = argmax_k |R~_k|                       (eq. 18, as |R_k| D_k = |R~_k|)
+      c-hat = gamma R~_u D_u                     (eq. 19: gamma R_u D_u^2)
+      g += c-hat phi_u                           (eq. 9)
+      R~_k -= gamma R~_u G_(u,k)                 (eq. 20 times D_k)
+    With G = unit_table(C, D) this is fase() up to rounding; with the
+    dequantised words of quantise_table it is the loop run on a fixed-point
+    table (R, D and the arithmetic stay exact).  Scores are reported as in
+    fase() (|R_k|^2 D_k^2 = |R~_k|^2)."""
+    w = np.asarray(w, dtype=np.float64)
+    phi = _basis(phi)
+    if np.iscomplexobj(phi):
+        raise ValueError("fase_unit takes real dictionaries")
+    s = np.asarray(s, dtype=np.float64)
+    D = np.asarray(D, dtype=np.float64)
+    G = np.asarray(G, dtype=np.float64)
+    Rt = D * np.sum(phi * (s * w)[None, :], axis=1)         # D_k times eq. 12
+    g = np.zeros_like(s)
+    r = s.copy()
+    sel = np.zeros(iters, dtype=np.int64)
+    coef = np.zeros(iters)
+    best = np.zeros(iters)
+    second = np.zeros(iters)
+    picked = np.zeros(iters)
+    energy = np.zeros(iters + 1)
+    energy[0] = float(np.sum(w * r * r))
+    for nu in range(iters):
+        score = np.abs(Rt)
+        top = int(np.argmax(score))
+        u = top if forced is None else int(forced[nu])
+        c = gamma * Rt[u] * D[u]
+        g = g + c * phi[u]
+        r = r - c * phi[u]
+        Rt = Rt - gamma * Rt[u] * G[u]
+        sel[nu] = u
+        coef[nu] = c
+        best[nu] = score[top] ** 2
+        picked[nu] = score[u] ** 2
+        second[nu] = _second_best(score, top, classes) ** 2
+        energy[nu + 1] = float(np.sum(w * r * r))
+    return SEResult(sel, coef, g, best, second, energy, None, picked)
 
 
 # ----------------------------------------------------------------------------
