@@ -332,6 +332,40 @@ def main():
                              "(eager): every iteration streams a whole row of K entries"}
         del tf, dblk_f
 
+    # the one-launch step on the class rows as 16-bit fixed-point words
+    # (SE_ROWS_Q14), and how far the words move the result from FP32 rows
+    fixed_point = None
+    if fused and t.n_classes == 4:
+        tq = B.weighted_gram(phi_d, w[0].contiguous(), M, N, parts=parts, fixed_point=True)
+        dblk_q = B.DeviceBlocks(tq, images_d, blocks)
+
+        def one_launch_q14(ev=None, st=None):
+            if ev is not None:
+                ev[0].record(stream)
+            B.extrapolate_device(tq, images_d, dblk_q, GAMMA, ITERS, stream=st, rows_q14=True)
+            if ev is not None:
+                ev[2].record(stream)
+        q_ms, q_evs = timed(one_launch_q14, args.steps)
+        outs = []
+        for q14 in (False, True):
+            img = torch.from_numpy(d["images"]).to(dev)
+            sel_, _, g_ = B.extrapolate_batch(tq, img, blocks, GAMMA, ITERS, want_coef=False,
+                                              rows_q14=q14)
+            torch.cuda.synchronize()
+            outs.append((sel_.cpu().numpy(), g_.cpu().numpy(), img.cpu().numpy()))
+        dg = np.abs(outs[0][1] - outs[1][1])
+        fixed_point = {
+            "ms_per_step": q_ms, "blocks_per_s": nblk / (q_ms * 1e-3),
+            "fused_ms": float(np.mean([e[0].elapsed_time(e[2]) for e in q_evs])),
+            "table_bytes": int(tq.Gq.numel() * 2),
+            "same_selections_frac": float(np.all(outs[0][0] == outs[1][0], axis=1).mean()),
+            "max_abs_dg": float(dg.max()), "median_abs_dg": float(np.median(dg)),
+            "loss_pixels_changed_frac": int((outs[0][2] != outs[1][2]).sum()) / (nblk * 64),
+            "what": "the one-launch step reading the class rows as 16-bit words with 14 "
+                    "fraction bits (eager), and its model against the FP32 rows' on the same "
+                    "blocks"}
+        del tq, dblk_q
+
     # the same step captured once into a HIP graph and replayed
     graph_info = None
     if not args.no_graph:
@@ -487,6 +521,7 @@ def main():
                      "project_form": "gemm" if args.no_parts else "transform"}),
         "two_launch": split,
         "full_rows": full_rows,
+        "fixed_point_rows": fixed_point,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -754,7 +789,8 @@ def bench_area64(args):
             e0, e1 = _events(2)
             e0.record()
             w = B.area_weights(64, 64, RHO, lost_d, blocks[:1])
-            t = B.weighted_gram(phi_d, w[0].contiguous(), 64, 64, prec, parts=parts)
+            t = B.weighted_gram(phi_d, w[0].contiguous(), 64, 64, prec, parts=parts,
+                                fixed_point=True)
             e1.record()
             e1.synchronize()
             gram.append(e0.elapsed_time(e1))
@@ -784,6 +820,15 @@ def bench_area64(args):
                 "ms_per_step": float(np.median(one)),
                 "blocks_per_s": len(blocks) / (float(np.median(one)) * 1e-3),
                 "class_rows": t.n_classes == 4}
+            if t.n_classes == 4:
+                # the class rows as 16-bit fixed-point words (half the bytes)
+                q = _timed(lambda: B.extrapolate_device(t, img, dblk, 0.5, 300, rows_q14=True),
+                           max(2, args.steps // 4), 1)
+                out[name]["one_launch_q14"] = {
+                    "ms_per_step": float(np.median(q)),
+                    "blocks_per_s": len(blocks) / (float(np.median(q)) * 1e-3),
+                    "what": "the same launch reading the class rows as 16-bit words "
+                            "(SE_ROWS_Q14)"}
         del t
     # the chosen form: one launch when the dictionary's parts allow it
     best = out["bf16x3"].get("one_launch", out["bf16x3"])

@@ -194,7 +194,16 @@ typedef struct {
  * and sets n_classes = 4 (else 0, and Gc, cls are not written).  The
  * one-launch route (se_extrapolate_device and se_extrapolate_batch for
  * all-transform tables) then streams a quarter of a row per iteration;
- * selections are reported as original atom indices. */
+ * selections are reported as original atom indices.
+ * Fixed-point class rows (optional; Gq may be NULL): Section III notes
+ * that the loop of Algorithm 3 needs no division, so its tables suit
+ * fixed-point words, and leaves their bit depth open.  When Gq is non-NULL
+ * and class tables are written, se_weighted_gram also writes
+ *   Gq   : K x (K/4) int16, 16-byte aligned: Gc in signed 16-bit words with
+ *          14 fraction bits, Gq = round(Gc * 2^14) to nearest, ties to even
+ *          (|Gc| <= 1, so no word saturates and the diagonal 1 is exact);
+ * a loop called with SE_ROWS_Q14 then streams these words (a quarter of
+ * the class rows' bytes) and updates R with Gq * 2^-14 in FP32. */
 typedef struct {
   int32_t M, N, K, ldG;
   float* G;
@@ -215,14 +224,23 @@ typedef struct {
   float* Gc;             /* class tables (may be NULL, see above)          */
   int32_t* cls;
   int32_t n_classes;     /* written by se_weighted_gram: 4 or 0            */
+  int16_t* Gq;           /* fixed-point class rows (may be NULL, see above) */
 } se_tables;
 
-/* Model-generation parameters: gamma of eq. 8 (0 < gamma <= 1) and the
- * iteration count I. */
+/* Model-generation parameters: gamma of eq. 8 (0 < gamma <= 1), the
+ * iteration count I, and flags:
+ *   SE_ROWS_Q14 : the loop reads the fixed-point class rows Gq instead of
+ *                 Gc (eq. 20 with the table entries quantised as described
+ *                 for se_tables; R, D, the coefficients and the model stay
+ *                 FP32).  Accepted by se_extrapolate_batch and
+ *                 se_extrapolate_device on tables with n_classes = 4 and
+ *                 Gq written; every other call, and those calls on other
+ *                 tables, return SE_EINVAL. */
+#define SE_ROWS_Q14 1u
 typedef struct {
   float gamma;
   int32_t iters;
-  uint32_t flags; /* reserved, must be 0 */
+  uint32_t flags; /* 0 or SE_ROWS_Q14 */
 } se_params;
 
 /* ------------------------------------------------------------------------ */

@@ -20,6 +20,7 @@ SE_OK, SE_EINVAL, SE_ENOMEM, SE_EHIP, SE_EAGAIN, SE_EBUSY, SE_ENUMERIC, SE_ECANC
     0, -1, -2, -3, -4, -5, -6, -7)
 SE_FP32, SE_BF16X3 = 0, 1
 SE_DIAG_AUTO, SE_DIAG_FP64, SE_DIAG_FP32 = 0, 1, 2
+SE_ROWS_Q14 = 1   # se_params.flags: the loop reads the fixed-point class rows
 SE_PART_DCT2, SE_PART_WHT2 = 1, 2
 
 # every symbol include/se.h declares
@@ -92,7 +93,8 @@ class se_tables(C.Structure):
                 ("precision", C.c_int32), ("Yhi", C.c_void_p), ("Ylo", C.c_void_p),
                 ("n_parts", C.c_int32), ("parts", se_part * 2), ("tx", C.c_void_p),
                 ("G_im", C.c_void_p), ("phi_im", C.c_void_p), ("T", C.c_int32),
-                ("Gc", C.c_void_p), ("cls", C.c_void_p), ("n_classes", C.c_int32)]
+                ("Gc", C.c_void_p), ("cls", C.c_void_p), ("n_classes", C.c_int32),
+                ("Gq", C.c_void_p)]
 
 
 class se_params(C.Structure):
@@ -262,6 +264,7 @@ class Tables:
     Gc: Optional[torch.Tensor] = None
     cls: Optional[torch.Tensor] = None
     n_classes: int = 0
+    Gq: Optional[torch.Tensor] = None
 
     @property
     def complex(self) -> bool:
@@ -284,18 +287,20 @@ class Tables:
                          self.G_im.data_ptr() if self.G_im is not None else None,
                          self.phi_im.data_ptr() if self.phi_im is not None else None, self.T,
                          self.Gc.data_ptr() if self.Gc is not None else None,
-                         self.cls.data_ptr() if self.cls is not None else None, self.n_classes)
+                         self.cls.data_ptr() if self.cls is not None else None, self.n_classes,
+                         self.Gq.data_ptr() if self.Gq is not None else None)
 
     def nbytes(self) -> int:
         parts = [self.G, self.D, self.Y, self.sqrtw]
-        parts += [x for x in (self.Yhi, self.Ylo, self.G_im, self.Gc, self.cls) if x is not None]
+        parts += [x for x in (self.Yhi, self.Ylo, self.G_im, self.Gc, self.cls, self.Gq)
+                  if x is not None]
         return sum(t.numel() * t.element_size() for t in parts)
 
 
 def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
                   precision: int = SE_FP32, flags: int = SE_DIAG_AUTO, stream=None,
                   parts=(), phi_im: Optional[torch.Tensor] = None, T: int = 1,
-                  classes: bool = True) -> Tables:
+                  classes: bool = True, fixed_point: bool = False) -> Tables:
     """se_weighted_gram (Algorithm 2) for dictionary ``phi`` (K, T*M*N) and
     weight pattern ``w`` (T*M*N,).  ``parts``: declared transform ranges, as
     (SE_PART_*, first atom) pairs (verified by the library).  ``phi_im``: the
@@ -303,7 +308,9 @@ def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
     parts); the tables are then complex (G, G_im).  ``T``: frames per area
     (1: two-dimensional areas).  ``classes``: offer buffers for the parity
     class tables (used when the library finds the class structure; then
-    ``n_classes`` is 4)."""
+    ``n_classes`` is 4).  ``fixed_point``: also offer the buffer of the class
+    rows as 16-bit words with 14 fraction bits (``Gq``, kept only with class
+    tables), which loops called with ``rows_q14=True`` read."""
     L = lib()
     _dev_f32(phi, "phi")
     _dev_f32(w, "w")
@@ -340,6 +347,8 @@ def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
             and K % 1024 == 0 and ldG == K):
         t.Gc = torch.empty((K, K // 4), dtype=torch.float32, device=dev)
         t.cls = torch.empty((K, 2), dtype=torch.int32, device=dev)
+        if fixed_point:
+            t.Gq = torch.empty((K, K // 4), dtype=torch.int16, device=dev)
     b = make_basis(M, N, K, phi.data_ptr(), t.parts,
                    phi_im.data_ptr() if phi_im is not None else None, int(T))
     nb = L.se_weighted_gram_ws_bytes(C.byref(b), int(precision))
@@ -349,7 +358,7 @@ def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
                               _ptr(ws), nb, _stream(stream)))
     t.n_classes = int(st.n_classes)
     if t.n_classes == 0:
-        t.Gc = t.cls = None
+        t.Gc = t.cls = t.Gq = None
     return t
 
 
@@ -360,7 +369,7 @@ def extrapolate_batch_ws_bytes(t: Tables, n_blk: int) -> int:
 
 def _extrapolate(name: str, t: Tables, images: torch.Tensor, blocks: Sequence, gamma: float,
                  iters: int, want_sel: bool, want_coef: bool, want_g: bool,
-                 ws: Optional[torch.Tensor], stream, blocks_arr=None):
+                 ws: Optional[torch.Tensor], stream, blocks_arr=None, flags: int = 0):
     L = lib()
     if not (images.is_cuda and images.dtype == torch.uint8 and images.dim() == 3
             and images.is_contiguous()):
@@ -381,7 +390,7 @@ def _extrapolate(name: str, t: Tables, images: torch.Tensor, blocks: Sequence, g
     elif ws.numel() < nb:
         raise ValueError(f"workspace of {ws.numel()} bytes < {nb}")
     arr = blocks_arr if blocks_arr is not None else blocks_array(blocks)
-    prm = se_params(float(gamma), int(iters), 0)
+    prm = se_params(float(gamma), int(iters), int(flags))
     _check(getattr(L, name)(C.byref(st), _ptr(images), n_img, H, W, arr, n, prm, _ptr(sel),
                             _ptr(coef), _ptr(g), gld, _ptr(ws), ws.numel(), _stream(stream)))
     return sel, coef, g
@@ -389,12 +398,14 @@ def _extrapolate(name: str, t: Tables, images: torch.Tensor, blocks: Sequence, g
 
 def extrapolate_batch(t: Tables, images: torch.Tensor, blocks: Sequence, gamma: float,
                       iters: int, want_sel=True, want_coef=True, want_g=True, ws=None,
-                      stream=None, blocks_arr=None):
+                      stream=None, blocks_arr=None, rows_q14: bool = False):
     """se_extrapolate_batch (Algorithm 3, batched).  ``images`` is modified in
     place (each loss replaced).  Returns (sel, coef, g_loss) device tensors
-    (None where not requested)."""
+    (None where not requested).  ``rows_q14``: the loop reads the fixed-point
+    class rows (SE_ROWS_Q14)."""
     return _extrapolate("se_extrapolate_batch", t, images, blocks, gamma, iters, want_sel,
-                        want_coef, want_g, ws, stream, blocks_arr)
+                        want_coef, want_g, ws, stream, blocks_arr,
+                        SE_ROWS_Q14 if rows_q14 else 0)
 
 
 def extrapolate_plain(t: Tables, images: torch.Tensor, blocks: Sequence, gamma: float,
@@ -457,16 +468,20 @@ def extrapolate_device_ws_bytes(t: Tables, n_blk: int) -> int:
 
 
 def extrapolate_device(t: Tables, images: torch.Tensor, dblocks: DeviceBlocks, gamma: float,
-                       iters: int, ws=None, sel=None, coef=None, g_loss=None, stream=None):
+                       iters: int, ws=None, sel=None, coef=None, g_loss=None, stream=None,
+                       rows_q14: bool = False):
     """se_extrapolate_device: projections and loop for device descriptors (one
     launch when every atom lies in a transform part; ``ws`` of
-    extrapolate_device_ws_bytes bytes otherwise)."""
+    extrapolate_device_ws_bytes bytes otherwise).  ``rows_q14`` as for
+    extrapolate_batch."""
     L = lib()
     n_img, H, W = images.shape
     st = t.struct()
     gld = g_loss.shape[1] if g_loss is not None else 0
     _check(L.se_extrapolate_device(C.byref(st), _ptr(images), n_img, H, W, _ptr(dblocks.buf),
-                                   dblocks.n, se_params(float(gamma), int(iters), 0), _ptr(sel),
+                                   dblocks.n,
+                                   se_params(float(gamma), int(iters),
+                                             SE_ROWS_Q14 if rows_q14 else 0), _ptr(sel),
                                    _ptr(coef), _ptr(g_loss), gld, _ptr(ws),
                                    ws.numel() if ws is not None else 0, _stream(stream)))
 

@@ -348,6 +348,7 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
   if (b->M < 1 || b->N < 1 || b->K < 1) return fail(SE_EINVAL, "bad basis shape");
   if (prec != SE_FP32 && prec != SE_BF16X3) return fail(SE_EINVAL, "unknown precision %d", (int)prec);
   if (flags > SE_DIAG_FP32) return fail(SE_EINVAL, "unknown flags 0x%x", flags);
+  if (reinterpret_cast<uintptr_t>(t->Gq) % 16) return fail(SE_EINVAL, "Gq must be 16-byte aligned");
   t->M = b->M;
   t->N = b->N;
   t->K = b->K;
@@ -434,6 +435,7 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
     if ((st = gram_mirror(t, s))) return st;
     if (want_classes && asym == 0) {
       if ((st = build_classes(t, s))) return st;
+      if (t->Gq && (st = quantise_classes(t, s))) return st;
       t->n_classes = 4;
     }
     return SE_OK;
@@ -515,6 +517,7 @@ static GreedyArgs greedy_args(const se_tables* t, const float* R, int ldR, uint8
   ga.g_loss_ld = g_loss ? g_loss_ld : 0;
   ga.Gc = t->n_classes == 4 ? t->Gc : nullptr;
   ga.cls = t->n_classes == 4 ? reinterpret_cast<const int2*>(t->cls) : nullptr;
+  ga.Gq = (prm.flags & SE_ROWS_Q14) && t->n_classes == 4 ? t->Gq : nullptr;
   return ga;
 }
 
@@ -528,8 +531,19 @@ static se_status launch_loop(const se_tables* t, const GreedyArgs& ga, int n_blk
 static se_status check_params(se_params prm, const float* g_loss, int g_loss_ld) {
   if (!(prm.gamma > 0.0f && prm.gamma <= 1.0f)) return fail(SE_EINVAL, "gamma must lie in (0, 1]");
   if (prm.iters < 0) return fail(SE_EINVAL, "iters < 0");
-  if (prm.flags != 0) return fail(SE_EINVAL, "unknown flags 0x%x", prm.flags);
+  if (prm.flags & ~SE_ROWS_Q14) return fail(SE_EINVAL, "unknown flags 0x%x", prm.flags);
   if (g_loss && g_loss_ld < 1) return fail(SE_EINVAL, "g_loss_ld < 1");
+  return SE_OK;
+}
+
+// SE_ROWS_Q14 is honoured by the one-launch class route only (the calls
+// that take it pass `route_ok` for tables that go there)
+static se_status check_rows_q14(const se_tables* t, se_params prm, bool route_ok) {
+  if (!(prm.flags & SE_ROWS_Q14)) return SE_OK;
+  if (!route_ok || !conceal_tx_supported(t) || t->n_classes != 4)
+    return fail(SE_EINVAL, "SE_ROWS_Q14 needs the one-launch route on class tables");
+  if (!t->Gq || reinterpret_cast<uintptr_t>(t->Gq) % 16)
+    return fail(SE_EINVAL, "SE_ROWS_Q14 needs 16-byte aligned fixed-point rows Gq");
   return SE_OK;
 }
 
@@ -540,6 +554,7 @@ se_status se_iterate(const se_tables* t, const float* R, int32_t ldR, uint8_t* i
   se_status st = check_common(t, n_img, H, W, n_blk, images, dev_blocks);
   if (st) return st;
   if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
+  if ((st = check_rows_q14(t, prm, false))) return st;
   if (n_blk == 0) return SE_OK;
   if ((st = check_r(t, R, ldR))) return st;
   GreedyArgs ga = greedy_args(t, R, ldR, images, H, W, dev_blocks, n_blk, prm, sel, coef, g_loss,
@@ -565,6 +580,7 @@ se_status se_extrapolate_device(const se_tables* t, uint8_t* images, int32_t n_i
   se_status st = check_common(t, n_img, H, W, n_blk, images, dev_blocks);
   if (st) return st;
   if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
+  if ((st = check_rows_q14(t, prm, true))) return st;
   if (n_blk == 0) return SE_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int ldR = r_row_len(t);
@@ -603,6 +619,7 @@ static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, in
   if (st) return st;
   if (!images) return fail(SE_EINVAL, "images is NULL");
   if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
+  if ((st = check_rows_q14(t, prm, !plain))) return st;
   if ((st = check_blocks(t, n_img, H, W, blocks, n_blk, g_loss_ld, g_loss))) return st;
   if (plain && t->phi_im) return fail(SE_EINVAL, "the per-block form takes real dictionaries");
   if (n_blk == 0) return SE_OK;
@@ -693,6 +710,7 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* im
   se_status st;
   if ((st = check_basis_parts(b))) return st;
   if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
+  if (prm.flags) return fail(SE_EINVAL, "rows on demand take no flags");
   int max_loss = 1, iters_max = 0;
   std::vector<int> it((size_t)n_blk);
   for (int i = 0; i < n_blk; ++i) {

@@ -109,4 +109,25 @@ se_status build_classes(se_tables* t, hipStream_t s) {
   return check_launch("build_classes");
 }
 
+// Fixed-point words of the class rows: q = round(Gc 2^14), to nearest with
+// ties to even.  Scaling by a power of two is exact in FP32, so the only
+// rounding is the one to the word; unit-diagonal entries (|Gc| <= 1) never
+// leave the 16-bit range, the bound below only keeps a corrupt table finite.
+__global__ void k_quantise_rows(const float4* __restrict__ Gc, size_t n4, short4* __restrict__ Gq) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n4) return;
+  const float4 v = Gc[i];
+  auto word = [](float x) {
+    return (short)fminf(fmaxf(rintf(x * 16384.0f), -32768.0f), 32767.0f);
+  };
+  Gq[i] = make_short4(word(v.x), word(v.y), word(v.z), word(v.w));
+}
+
+se_status quantise_classes(se_tables* t, hipStream_t s) {
+  const size_t n4 = (size_t)t->K * (t->K / 4) / 4;
+  hipLaunchKernelGGL(k_quantise_rows, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<const float4*>(t->Gc), n4, reinterpret_cast<short4*>(t->Gq));
+  return check_launch("quantise_rows");
+}
+
 }  // namespace sefase

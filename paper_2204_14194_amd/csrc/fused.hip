@@ -27,8 +27,8 @@ constexpr int conceal_lds_floats() {
 // accumulation registers it would otherwise add (four resident blocks per
 // SIMD cover a 4096-block batch at once); larger areas take what they need.
 // VOL: areas of several frames, read as their frames stacked (M = T rows of
-// frames).
-template <int WAVES, int VPL, int MT, int NT, int NP, bool CLS, bool VOL>
+// frames).  Q16: the class rows as fixed-point words.
+template <int WAVES, int VPL, int MT, int NT, int NP, bool CLS, bool VOL, bool Q16>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(MT * NT <= 4 ? 4 : 1)))
 void k_conceal_tx(GreedyArgs a, TxArgs x, TxLayout L) {
   constexpr int T = 64 * WAVES;
@@ -82,14 +82,14 @@ void k_conceal_tx(GreedyArgs a, TxArgs x, TxLayout L) {
       R[j][0] = v[0]; R[j][1] = v[1]; R[j][2] = v[2]; R[j][3] = v[3];
     }
   }
-  greedy_block<WAVES, VPL, CLS>(a, b, R);
+  greedy_block<WAVES, VPL, CLS, Q16>(a, b, R);
 }
 
-template <int WAVES, int VPL, int MT, int NT, int NP, bool CLS, bool VOL = false>
+template <int WAVES, int VPL, int MT, int NT, int NP, bool CLS, bool VOL = false, bool Q16 = false>
 static se_status launch_conceal(const GreedyArgs& a, const TxArgs& x, const TxLayout& L, int grid,
                                 hipStream_t s) {
   const size_t lds = (size_t)conceal_lds_floats<WAVES, VPL, MT, NT, NP>() * 4;
-  hipLaunchKernelGGL((k_conceal_tx<WAVES, VPL, MT, NT, NP, CLS, VOL>), dim3(grid),
+  hipLaunchKernelGGL((k_conceal_tx<WAVES, VPL, MT, NT, NP, CLS, VOL, Q16>), dim3(grid),
                      dim3(64 * WAVES), lds, s, a, x, L);
   return check_launch("conceal_tx");
 }
@@ -118,6 +118,7 @@ se_status conceal_tx(const se_tables* t, const GreedyArgs& a, const uint8_t* ima
   // class tables: the class form, at the default shape when the requested
   // one does not hold whole class sweeps
   const bool cls = t->n_classes == 4 && a.Gc && a.cls;
+  if (a.Gq && !cls) return fail(SE_EINVAL, "fixed-point rows need class tables");
   if (waves <= 0 || (cls && (vpl / 4) % 4 != 0)) {
     waves = greedy_waves_for(t->K);
     vpl = greedy_row_len(t->K) / (64 * waves);
@@ -143,6 +144,20 @@ se_status conceal_tx(const se_tables* t, const GreedyArgs& a, const uint8_t* ima
   const int Mv = tx_rows(t);
   const TxLayout L(Mv, t->N, t->n_parts, 0);
   const int key = conceal_case(Mv, t->N, t->n_parts) * 10000 + waves * 100 + vpl;
+  if (cls && a.Gq) {
+    switch (key) {
+      case 20132: return launch_conceal<1, 32, 2, 2, 2, true, false, true>(a, x, L, n_blk, s);
+      case 20216: return launch_conceal<2, 16, 2, 2, 2, true, false, true>(a, x, L, n_blk, s);
+      case 40432: return launch_conceal<4, 32, 4, 4, 2, true, false, true>(a, x, L, n_blk, s);
+      case 40816: return launch_conceal<8, 16, 4, 4, 2, true, false, true>(a, x, L, n_blk, s);
+      case 50132:
+        return vol ? launch_conceal<1, 32, 4, 1, 2, true, true, true>(a, x, L, n_blk, s)
+                   : launch_conceal<1, 32, 4, 1, 2, true, false, true>(a, x, L, n_blk, s);
+      default:
+        return fail(SE_EINVAL, "no fixed-point class loop of shape %dx%d for K=%d", waves, vpl,
+                    t->K);
+    }
+  }
   if (cls) {
     switch (key) {
       case 20132: return launch_conceal<1, 32, 2, 2, 2, true>(a, x, L, n_blk, s);

@@ -40,6 +40,12 @@
 // in the winning class (the same position the full scan finds: classes
 // occupy increasing positions, so the lowest class among equal maxima holds
 // the lowest position).
+//
+// Fixed-point rows (Q16, class form): the class rows are read as 16-bit
+// words q with 14 fraction bits and eq. 20 becomes R~ -= (tc 2^-14) q.  The
+// product tc 2^-14 q equals tc (q 2^-14) exactly (both factors' scalings are
+// powers of two), so each update rounds once, as with the FP32 entries
+// q 2^-14; only the table bytes change.
 #pragma once
 
 #include "argmax.h"
@@ -61,12 +67,13 @@ __device__ __forceinline__ float class_lane_max(const float (&R)[NJ][4]) {
 
 // The iterations and the paste for block b of a workgroup of WAVES waves,
 // from R~^(0) in registers (lane t: atoms 4 (j T + t) + e).
-template <int WAVES, int VPL, bool CLS = false>
+template <int WAVES, int VPL, bool CLS = false, bool Q16 = false>
 __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (&R)[VPL / 4][4]) {
   constexpr int T = 64 * WAVES;
   constexpr int NJ = VPL / 4;
   constexpr int NJC = NJ / 4 > 0 ? NJ / 4 : 1;   // sweeps of one class (CLS)
   static_assert(!CLS || NJ % 4 == 0, "the class form needs whole sweeps per class");
+  static_assert(CLS || !Q16, "fixed-point rows are class rows");
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const DevBlock d = a.blk[b];
@@ -238,7 +245,12 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     constexpr int NR = CLS ? NJC : NJ;
     const float* grow = CLS ? a.Gc + (size_t)u * (T * NJ) : a.G + (size_t)u * a.ldG;
     float4 row[NR];
-    if constexpr (CLS) {
+    uint2 qrow[Q16 ? NR : 1];
+    if constexpr (Q16) {
+      const int16_t* g16 = a.Gq + (size_t)u * (T * NJ);
+#pragma unroll
+      for (int j = 0; j < NR; ++j) qrow[j] = *reinterpret_cast<const uint2*>(g16 + 4 * (j * T + t));
+    } else if constexpr (CLS) {
 #pragma unroll
       for (int j = 0; j < NR; ++j) row[j] = *reinterpret_cast<const float4*>(grow + 4 * (j * T + t));
     }
@@ -301,6 +313,16 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     if constexpr (!CLS) model_update();
 
     // ---- eq. 20 -------------------------------------------------------------
+    if constexpr (Q16) {                        // the words as exact FP32 integers
+#pragma unroll
+      for (int j = 0; j < NR; ++j) {
+        row[j].x = (float)(int)(int16_t)(qrow[j].x & 0xFFFFu);
+        row[j].y = (float)((int)qrow[j].x >> 16);
+        row[j].z = (float)(int)(int16_t)(qrow[j].y & 0xFFFFu);
+        row[j].w = (float)((int)qrow[j].y >> 16);
+      }
+    }
+    const float tr = Q16 ? tc * (1.0f / 16384.0f) : tc;   // eq. 20 factor per row entry
     if (CLS) {
       const int cu = u / (T * NJC * 4);         // the selected atom's class (uniform)
 #pragma unroll
@@ -308,10 +330,10 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
         if (cc == cu) {
 #pragma unroll
           for (int j = 0; j < NR; ++j) {
-            R[cc * NJC + j][0] = fmaf(-tc, row[j].x, R[cc * NJC + j][0]);
-            R[cc * NJC + j][1] = fmaf(-tc, row[j].y, R[cc * NJC + j][1]);
-            R[cc * NJC + j][2] = fmaf(-tc, row[j].z, R[cc * NJC + j][2]);
-            R[cc * NJC + j][3] = fmaf(-tc, row[j].w, R[cc * NJC + j][3]);
+            R[cc * NJC + j][0] = fmaf(-tr, row[j].x, R[cc * NJC + j][0]);
+            R[cc * NJC + j][1] = fmaf(-tr, row[j].y, R[cc * NJC + j][1]);
+            R[cc * NJC + j][2] = fmaf(-tr, row[j].z, R[cc * NJC + j][2]);
+            R[cc * NJC + j][3] = fmaf(-tr, row[j].w, R[cc * NJC + j][3]);
           }
           if constexpr (INC) {                  // the class's new maxima
             float m = 0.0f;

@@ -178,6 +178,8 @@ struct GreedyArgs {
   // (original atom index, D bits)
   const float* Gc;
   const int2* cls;
+  // fixed-point class rows (Q1.14 words of Gc); non-NULL selects them
+  const int16_t* Gq;
 };
 // ondemand.hip -- per-block weights, rows of C_b formed on demand
 struct OnDemandPlan {
@@ -224,6 +226,8 @@ bool classes_possible(const se_tables* t);
 void launch_sym_check(const float* w, int T, int M, int N, int* flag, hipStream_t s);
 // t->Gc and t->cls from t->G and t->D
 se_status build_classes(se_tables* t, hipStream_t s);
+// t->Gq = round(t->Gc 2^14) (16-bit words, 14 fraction bits)
+se_status quantise_classes(se_tables* t, hipStream_t s);
 
 // fused.hip -- projections of transform parts and the loop in one launch
 bool conceal_tx_supported(const se_tables* t);

@@ -55,20 +55,30 @@ def min_margin(res) -> float:
 
 
 def _check_block(i, s, w, phi, cls, cache, gamma, iters, sel_i, g_i, loss_idx, got, tol, delta,
-                 pasted=None):
+                 pasted=None, q14=False):
     """One block of oracle_check: returns (err, margin, agreed).  ``got``: the
-    pasted values of the loss samples selected by ``pasted`` (all if None)."""
+    pasted values of the loss samples selected by ``pasted`` (all if None).
+    ``q14``: the reference runs on the table's 16-bit fixed-point words."""
     key = w.tobytes()
     if key not in cache:
-        cache[key] = oracle.table_generation(phi, w)
-    C, D = cache[key]
-    res = oracle.fase(s, w, phi, C, D, gamma, iters, cls)
+        C, D = oracle.table_generation(phi, w)
+        Gq = None
+        if q14:
+            Gq = oracle.quantise_table(oracle.unit_table(C, D)).astype(np.float64) * 2.0 ** -14
+        cache[key] = (C, D, Gq)
+    C, D, Gq = cache[key]
+
+    def run(forced=None):
+        if q14:
+            return oracle.fase_unit(s, w, phi, Gq, D, gamma, iters, cls, forced=forced)
+        return oracle.fase(s, w, phi, C, D, gamma, iters, cls, forced=forced)
+    res = run()
     margin = min_margin(res)
     agreed = compare_selections(sel_i, res.sel, cls)
     if agreed:
         ref = res
     else:
-        ref = oracle.fase(s, w, phi, C, D, gamma, iters, cls, forced=sel_i)
+        ref = run(forced=sel_i)
         ok = np.sqrt(ref.picked) >= np.sqrt(ref.best) * (1.0 - delta)
         assert ok.all(), (f"block {i}: iteration {int(np.argmin(ok))} picked an atom "
                           f"outside the near-tie window")
@@ -87,7 +97,7 @@ def _check_block(i, s, w, phi, cls, cache, gamma, iters, sel_i, g_i, loss_idx, g
 
 
 def oracle_check(images, blocks, phi, M, N, rho_hat, gamma, iters, sel, g, out,
-                 sample=None, tol=1e-3, delta=1e-3):
+                 sample=None, tol=1e-3, delta=1e-3, q14=False):
     """Compare device results with the FP64 oracle (Algorithm 3, which the CPU
     pins tie to Algorithm 1) block by block.
 
@@ -97,7 +107,8 @@ def oracle_check(images, blocks, phi, M, N, rho_hat, gamma, iters, sel, g, out,
     re-run along the device's selections and every device pick must score
     within the relative window ``delta`` of that iteration's best score; the
     model must then agree with that run within ``tol``.  In both cases the
-    pasted pixels are the rounded model.
+    pasted pixels are the rounded model.  ``q14``: the oracle runs Algorithm 3
+    on the 16-bit fixed-point words of its own table (oracle.fase_unit).
     Returns dict(worst, margin, agree, n)."""
     n_img, H, W = images.shape
     lost = np.stack([synth.lost_mask(H, W, blocks, i) for i in range(n_img)])
@@ -114,13 +125,13 @@ def oracle_check(images, blocks, phi, M, N, rho_hat, gamma, iters, sel, g, out,
         y, x = b.y0 + b.ly, b.x0 + b.lx
         got = out[b.img, y:y + b.lh, x:x + b.lw].reshape(-1)
         err, mg, ok = _check_block(i, s, w, phi, cls, cache, gamma, iters, sel[i], g[i],
-                                   loss_idx, got, tol, delta)
+                                   loss_idx, got, tol, delta, q14=q14)
         worst, margin, agree = max(worst, err), min(margin, mg), agree + int(ok)
     return dict(worst=worst, margin=margin, agree=agree, n=len(idx))
 
 
 def oracle_check_video(frames, blocks, phi, T, M, N, rho_hat, gamma, iters, sel, g, out,
-                       sample=None, tol=1e-3, delta=1e-3):
+                       sample=None, tol=1e-3, delta=1e-3, q14=False):
     """oracle_check for areas of T consecutive frames (blocks with lt, ld;
     the model over the loss box in frames x rows x columns order).  Loss
     samples outside the frames are compared in the model only."""
@@ -143,6 +154,6 @@ def oracle_check_video(frames, blocks, phi, T, M, N, rho_hat, gamma, iters, sel,
         inside = (ff >= 0) & (ff < F) & (yy >= 0) & (yy < H) & (xx >= 0) & (xx < W)
         got = out[ff[inside], yy[inside], xx[inside]]
         err, mg, ok = _check_block(i, s, w, phi, cls, cache, gamma, iters, sel[i], g[i],
-                                   loss_idx, got, tol, delta, pasted=inside)
+                                   loss_idx, got, tol, delta, pasted=inside, q14=q14)
         worst, margin, agree = max(worst, err), min(margin, mg), agree + int(ok)
     return dict(worst=worst, margin=margin, agree=agree, n=len(idx))

@@ -35,7 +35,7 @@ def upload_phi(phi):
 
 
 def shared_tables(images, blocks, phi32, M, N, rho_hat, precision=B.SE_FP32, flags=0,
-                  ref_block=0, parts=(), classes=True):
+                  ref_block=0, parts=(), classes=True, fixed_point=False):
     """Weights of block ``ref_block`` computed on the device, then the tables
     (with buffers for parity-class tables unless ``classes`` is False)."""
     n_img, H, W = images.shape
@@ -43,7 +43,7 @@ def shared_tables(images, blocks, phi32, M, N, rho_hat, precision=B.SE_FP32, fla
     lost_d = torch.from_numpy(lost).to(dev())
     w = B.area_weights(M, N, rho_hat, lost_d, [blocks[ref_block]])
     t = B.weighted_gram(phi32, w[0].contiguous(), M, N, precision, flags, parts=parts,
-                        classes=classes)
+                        classes=classes, fixed_point=fixed_point)
     return t, w[0], lost
 
 

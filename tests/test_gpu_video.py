@@ -20,12 +20,12 @@ TOL_BF16X3 = 1e-2
 
 
 def _tables(phi32, frames, blocks, T, M, N, ref_block=0, precision=B.SE_FP32, parts=(),
-            classes=True):
+            classes=True, fixed_point=False):
     F, H, W = frames.shape
     lost = torch.from_numpy(synth.video_lost_mask(F, H, W, blocks)).to(dev())
     w = B.area_weights(M, N, 0.8, lost, [blocks[ref_block]], T=T)
     return B.weighted_gram(upload_phi(phi32), w[0].contiguous(), M, N, precision, T=T,
-                           parts=parts, classes=classes)
+                           parts=parts, classes=classes, fixed_point=fixed_point)
 
 
 def _batch(t, frames, blocks, iters, plain=False):
