@@ -19,6 +19,10 @@
 // (the time axis is left alone), so a 3-D atom (kt, k1, k2) takes the
 // parities of k1 and k2, the weights must be mirror-symmetric within every
 // frame, and a part's atoms of a class are ordered by (kt, k1 / 2, k2 / 2).
+//
+// The class rows may also be written as 16-bit fixed-point words (14
+// fraction bits), the table form Section III suggests for a loop without
+// division; the loop then streams half the bytes.
 #include "se_internal.h"
 
 namespace sefase {
