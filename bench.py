@@ -745,18 +745,21 @@ def bench_clustered(args):
         groups.append((phi, area, w, bl, it, streams[k],
                        () if args.no_parts else d["tx_parts"][area]))
 
-    def step():
+    def step(rows_bf16=False):
         cur = torch.cuda.current_stream()
         for phi, area, w, bl, it, st, parts in groups:
             st.wait_stream(cur)
             with torch.cuda.stream(st):
                 B.extrapolate_ondemand(phi, area, area, w, img, bl, 0.5, it, False, False, False,
-                                       stream=st, parts=parts)
+                                       stream=st, parts=parts, rows_bf16=rows_bf16)
         for g in groups:
             cur.wait_stream(g[5])
 
     ms = _timed(step, max(1, args.steps // 4), 1)
     med = float(np.median(ms))
+    # the dense atoms' row products from split-BF16 operands (SE_ROWS_BF16X3)
+    ms_bf = _timed(lambda: step(True), max(1, args.steps // 4), 1)
+    med_bf = float(np.median(ms_bf))
     return {"metric": "concealed blocks/s, uneven batch with per-block weights (rows on demand)",
             "value": len(blocks) / (med * 1e-3), "unit": "blocks/s", "n_gpus": 1,
             "steps": len(ms), "warmup": 1, "ms_per_step": med, "higher_is_better": True,
@@ -764,7 +767,10 @@ def bench_clustered(args):
             "config": {"workload": "8 x 1024x1024 frames, 4000 clustered/burst 8x8 and 16x16 "
                                    "losses, areas 24/32/48 (K=1152/2048/4608), I~U{100..200}, "
                                    "one dictionary group per stream"},
-            "blocks_per_area": {str(a): len(g[3]) for a, g in zip((24, 32, 48), groups)}}
+            "blocks_per_area": {str(a): len(g[3]) for a, g in zip((24, 32, 48), groups)},
+            "rows_bf16x3": {"ms_per_step": med_bf, "blocks_per_s": len(blocks) / (med_bf * 1e-3),
+                            "what": "the dense atoms' row products from split-BF16 operands "
+                                    "(SE_ROWS_BF16X3); FP32 accumulation"}}
 
 
 def bench_area64(args):

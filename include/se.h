@@ -237,10 +237,19 @@ typedef struct {
  *                 Gq written; every other call, and those calls on other
  *                 tables, return SE_EINVAL. */
 #define SE_ROWS_Q14 1u
+/*   SE_ROWS_BF16X3 : rows on demand only (se_extrapolate_ondemand): the
+ *                 per-iteration products of the dictionary's dense atoms
+ *                 (those outside declared transform parts) with w_b phi_u
+ *                 take split-BF16 operands, as SE_BF16X3 tables do (three
+ *                 BF16 matrix-core products, FP32 accumulation, the dropped
+ *                 lo*lo term below 2^-16 relative); the diagonals, the
+ *                 initial projections and the loop stay FP32.  Every other
+ *                 call returns SE_EINVAL for it. */
+#define SE_ROWS_BF16X3 2u
 typedef struct {
   float gamma;
   int32_t iters;
-  uint32_t flags; /* 0 or SE_ROWS_Q14 */
+  uint32_t flags; /* 0, SE_ROWS_Q14 or SE_ROWS_BF16X3 */
 } se_params;
 
 /* ------------------------------------------------------------------------ */
@@ -496,7 +505,9 @@ void se_tune_clear(void);
  *             left unchanged
  *   g_loss  : optional, as for se_extrapolate_batch
  *   ws      : se_extrapolate_ondemand_ws_bytes(b, n_blk, max_loss) bytes,
- *             max_loss = the largest lh*lw of the blocks
+ *             max_loss = the largest lh*lw of the blocks (the size includes
+ *             the split-BF16 copies that SE_ROWS_BF16X3 uses)
+ *   prm.flags : 0 or SE_ROWS_BF16X3
  * Errors as for se_extrapolate_batch; the loss size is not limited. */
 size_t se_extrapolate_ondemand_ws_bytes(const se_basis* b, int32_t n_blk,
                                         int32_t max_loss);

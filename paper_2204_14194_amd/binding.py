@@ -21,6 +21,7 @@ SE_OK, SE_EINVAL, SE_ENOMEM, SE_EHIP, SE_EAGAIN, SE_EBUSY, SE_ENUMERIC, SE_ECANC
 SE_FP32, SE_BF16X3 = 0, 1
 SE_DIAG_AUTO, SE_DIAG_FP64, SE_DIAG_FP32 = 0, 1, 2
 SE_ROWS_Q14 = 1   # se_params.flags: the loop reads the fixed-point class rows
+SE_ROWS_BF16X3 = 2   # se_params.flags: rows on demand from split-BF16 products
 SE_PART_DCT2, SE_PART_WHT2 = 1, 2
 
 # every symbol include/se.h declares
@@ -489,9 +490,11 @@ def extrapolate_device(t: Tables, images: torch.Tensor, dblocks: DeviceBlocks, g
 def extrapolate_ondemand(phi: torch.Tensor, M: int, N: int, w: torch.Tensor,
                          images: torch.Tensor, blocks: Sequence, gamma: float, iters,
                          want_sel=True, want_coef=True, want_g=True, ws=None, stream=None,
-                         parts=()):
+                         parts=(), rows_bf16: bool = False):
     """se_extrapolate_ondemand: per-block weights ``w`` (n_blk, M*N); ``iters``
-    an int or a per-block sequence.  Returns (sel, coef, g_loss)."""
+    an int or a per-block sequence.  ``rows_bf16``: the dense atoms' row
+    products from split-BF16 operands (SE_ROWS_BF16X3).  Returns (sel, coef,
+    g_loss)."""
     L = lib()
     _dev_f32(phi, "phi")
     _dev_f32(w, "w")
@@ -514,7 +517,7 @@ def extrapolate_ondemand(phi: torch.Tensor, M: int, N: int, w: torch.Tensor,
         ws = _workspace(nb, dev)
     elif ws.numel() < nb:
         raise ValueError(f"workspace of {ws.numel()} bytes < {nb}")
-    prm = se_params(float(gamma), int(imax), 0)
+    prm = se_params(float(gamma), int(imax), SE_ROWS_BF16X3 if rows_bf16 else 0)
     _check(L.se_extrapolate_ondemand(C.byref(bas), _ptr(w), _ptr(images), n_img, H, W,
                                      blocks_array(blocks), n, prm, per, _ptr(sel), _ptr(coef),
                                      _ptr(g), gld, _ptr(ws), ws.numel(), _stream(stream)))

@@ -531,7 +531,8 @@ static se_status launch_loop(const se_tables* t, const GreedyArgs& ga, int n_blk
 static se_status check_params(se_params prm, const float* g_loss, int g_loss_ld) {
   if (!(prm.gamma > 0.0f && prm.gamma <= 1.0f)) return fail(SE_EINVAL, "gamma must lie in (0, 1]");
   if (prm.iters < 0) return fail(SE_EINVAL, "iters < 0");
-  if (prm.flags & ~SE_ROWS_Q14) return fail(SE_EINVAL, "unknown flags 0x%x", prm.flags);
+  if (prm.flags & ~(SE_ROWS_Q14 | SE_ROWS_BF16X3))
+    return fail(SE_EINVAL, "unknown flags 0x%x", prm.flags);
   if (g_loss && g_loss_ld < 1) return fail(SE_EINVAL, "g_loss_ld < 1");
   return SE_OK;
 }
@@ -539,6 +540,8 @@ static se_status check_params(se_params prm, const float* g_loss, int g_loss_ld)
 // SE_ROWS_Q14 is honoured by the one-launch class route only (the calls
 // that take it pass `route_ok` for tables that go there)
 static se_status check_rows_q14(const se_tables* t, se_params prm, bool route_ok) {
+  if (prm.flags & SE_ROWS_BF16X3)
+    return fail(SE_EINVAL, "SE_ROWS_BF16X3 is an option of rows on demand");
   if (!(prm.flags & SE_ROWS_Q14)) return SE_OK;
   if (!route_ok || !conceal_tx_supported(t) || t->n_classes != 4)
     return fail(SE_EINVAL, "SE_ROWS_Q14 needs the one-launch route on class tables");
@@ -690,6 +693,8 @@ size_t se_extrapolate_ondemand_ws_bytes(const se_basis* b, int32_t n_blk, int32_
   cv.take<int32_t>(1);
   cv.take<float>(tx_const_bytes(b->M, b->N, b->n_parts) / 4);
   cv.take<float>(ondemand_splitk_floats(b, n_blk));
+  cv.take<uint16_t>(2 * K * P);      // split-BF16 dictionary and V rows (SE_ROWS_BF16X3)
+  cv.take<uint16_t>(2 * n * ldV);
   return cv.off + 256;
 }
 
@@ -710,7 +715,7 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* im
   se_status st;
   if ((st = check_basis_parts(b))) return st;
   if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
-  if (prm.flags) return fail(SE_EINVAL, "rows on demand take no flags");
+  if (prm.flags & SE_ROWS_Q14) return fail(SE_EINVAL, "rows on demand take no fixed-point rows");
   int max_loss = 1, iters_max = 0;
   std::vector<int> it((size_t)n_blk);
   for (int i = 0; i < n_blk; ++i) {
@@ -760,6 +765,17 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* im
   float* tx = cv.take<float>(tx_const_bytes(b->M, b->N, b->n_parts) / 4);
   pl.splitk_floats = ondemand_splitk_floats(b, n);
   pl.splitk = cv.take<float>(pl.splitk_floats);
+  pl.phi_hi = pl.phi_lo = pl.Vhi = pl.Vlo = nullptr;
+  {
+    uint16_t* ph = cv.take<uint16_t>((size_t)2 * K * P);
+    uint16_t* vh = cv.take<uint16_t>((size_t)2 * n * ldV);
+    if (prm.flags & SE_ROWS_BF16X3) {
+      pl.phi_hi = ph;
+      pl.phi_lo = ph + (size_t)K * P;
+      pl.Vhi = vh;
+      pl.Vlo = vh + (size_t)n * ldV;
+    }
+  }
   // declared transform parts: verified (one synchronisation of the stream),
   // then their table rows are formed as transforms
   if ((st = verify_parts(b, flag, s))) return st;

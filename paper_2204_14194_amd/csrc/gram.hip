@@ -3,6 +3,7 @@
 // Y[k][p] = D_k sqrt(w_p) phi_k[p] from which both the Gram matrix
 // (G = Y Y^T, computed by the GEMM in gemm.hip) and the initial projections
 // (eq. 12) are formed.
+#include "bf16.h"
 #include "se_internal.h"
 
 namespace sefase {
@@ -122,22 +123,14 @@ __global__ void k_combine_c(const float* __restrict__ S, int ldS, int K,
   G_im[(size_t)k * ldG + l] = bot[l] - top[K + l];
 }
 
-// Round-to-nearest-even float32 -> bfloat16 bits (finite inputs).
-__device__ inline uint16_t f32_to_bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
-
 __global__ void k_split_bf16(const float* __restrict__ x, size_t n, uint16_t* __restrict__ hi,
                              uint16_t* __restrict__ lo) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float v = x[i];
-  const uint16_t h = f32_to_bf16_rne(v);
+  uint16_t h, l;
+  bf16_split(x[i], h, l);
   hi[i] = h;
-  lo[i] = f32_to_bf16_rne(v - bf16_to_f32(h));
+  lo[i] = l;
 }
 
 __global__ void k_zero_cols(float* __restrict__ A, int rows, int c0, int ld) {

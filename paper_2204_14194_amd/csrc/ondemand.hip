@@ -12,6 +12,10 @@
 // and the initial projections R_b^(0) = Phi (w_b s_b) (eq. 12) are products
 // with the same dictionary.
 //
+// The dense row products may take split-BF16 operands (three BF16 matrix-core
+// products, FP32 accumulation): the dictionary split once per call, the V
+// rows split where they are written.
+//
 // Per iteration a workgroup per block applies the previous update (eq. 20,
 // in units of D_b), selects the next atom (eq. 18), records c (eq. 19),
 // updates the model over the loss (eq. 9) and writes its V row.  All state
@@ -19,6 +23,7 @@
 // decreasing order of their iteration counts, so the blocks still running at
 // iteration nu form a prefix and each launch covers only that prefix.
 #include "argmax.h"
+#include "bf16.h"
 #include "se_internal.h"
 
 namespace sefase {
@@ -79,6 +84,8 @@ struct OdArgs {
   const float* D;      // n_blk x ld
   const float* rows;   // n_blk x ld, C_b[u_prev][k] from the last product
   float* V;            // n_blk x ldV
+  uint16_t* Vhi;       // optional split copy of V (split-BF16 row products)
+  uint16_t* Vlo;
   int ld, ldV;
   const float* phi;    // K x P
   const float* w;      // original-order blocks x P
@@ -164,7 +171,20 @@ __global__ __launch_bounds__(kOdThreads) void k_od_step(OdArgs a) {
   // V row for the next product: w_b phi_u
   const float* wb = a.w + (size_t)ob * P;
   float* V = a.V + (size_t)b * a.ldV;
-  for (int p = t; p < P; p += kOdThreads) V[p] = wb[p] * prow[p];
+  if (a.Vhi) {
+    uint16_t* Vh = a.Vhi + (size_t)b * a.ldV;
+    uint16_t* Vl = a.Vlo + (size_t)b * a.ldV;
+    for (int p = t; p < P; p += kOdThreads) {
+      const float v = wb[p] * prow[p];
+      uint16_t h, l;
+      bf16_split(v, h, l);
+      V[p] = v;
+      Vh[p] = h;
+      Vl[p] = l;
+    }
+  } else {
+    for (int p = t; p < P; p += kOdThreads) V[p] = wb[p] * prow[p];
+  }
 }
 
 // paste the model into the image and (optionally) report it
@@ -242,6 +262,13 @@ se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s) {
   const bool tx = bs && bs->n_parts > 0;
   int lo[3] = {0, 0, 0}, hi[3] = {K, 0, 0};
   const int nr = tx ? dense_ranges(K, pl.M * pl.N, bs->n_parts, bs->parts, lo, hi) : 1;
+  const bool split = pl.phi_hi != nullptr && nr > 0;   // no dense atoms: nothing to split
+  if (split) {
+    launch_split_bf16(pl.phi, (size_t)K * P, pl.phi_hi, pl.phi_lo, s);
+    if ((st = check_launch("split_bf16"))) return st;
+  }
+  a.Vhi = split ? pl.Vhi : nullptr;
+  a.Vlo = split ? pl.Vlo : nullptr;
   if (tx) {   // the row products no longer write the padding columns
     hipLaunchKernelGGL(k_fill0, dim3((unsigned)(((size_t)n * pl.ld + 255) / 256)), dim3(256), 0, s,
                        pl.rows, (size_t)n * pl.ld);
@@ -258,11 +285,15 @@ se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s) {
     // rows C_b[u_b][:] for the blocks that iterate again: transforms of
     // w_b phi_u for the parts, a product with the dictionary for the rest
     if (tx && (st = rows_tx(bs, pl.tx, pl.V, pl.ldV, nxt, pl.rows, pl.ld, s))) return st;
-    for (int r = 0; r < nr; ++r)
-      if ((st = gemm_project_f32(pl.phi + (size_t)lo[r] * P, P, hi[r] - lo[r], pl.V, pl.ldV, nxt,
-                                 P, pl.rows + lo[r], pl.ld, 0, s, !tx, pl.splitk,
-                                 pl.splitk_floats)))
-        return st;
+    for (int r = 0; r < nr; ++r) {
+      st = split ? gemm_project_bf16x3(pl.phi_hi + (size_t)lo[r] * P, pl.phi_lo + (size_t)lo[r] * P,
+                                       P, hi[r] - lo[r], pl.Vhi, pl.Vlo, pl.ldV, nxt, P,
+                                       pl.rows + lo[r], pl.ld, s, !tx)
+                 : gemm_project_f32(pl.phi + (size_t)lo[r] * P, P, hi[r] - lo[r], pl.V, pl.ldV,
+                                    nxt, P, pl.rows + lo[r], pl.ld, 0, s, !tx, pl.splitk,
+                                    pl.splitk_floats);
+      if (st) return st;
+    }
   }
   hipLaunchKernelGGL(k_od_finish, dim3(n), dim3(256), 0, s, pl.blk, pl.orig, pl.g, pl.ldg,
                      pl.images, pl.H, pl.W, pl.g_loss, pl.g_loss_ld);

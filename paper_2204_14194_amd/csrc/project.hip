@@ -6,6 +6,7 @@
 //   R_k^(0) of eq. 12 in units of D_k.
 // plus the matrix-vector form of the same product for one block (the plain
 // per-block path).
+#include "bf16.h"
 #include "se_internal.h"
 
 namespace sefase {
@@ -34,12 +35,6 @@ void launch_gather(const uint8_t* images, int H, int W, const DevBlock* blk, int
                      n_blk, T, M, N, sqrtw, X, ldX);
 }
 
-__device__ inline uint16_t bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-
 __global__ void k_gather_split(const uint8_t* __restrict__ images, int H, int W,
                                const DevBlock* __restrict__ blk, int n_blk, int T, int M, int N,
                                const float* __restrict__ sqrtw, uint16_t* __restrict__ Xhi,
@@ -55,9 +50,10 @@ __global__ void k_gather_split(const uint8_t* __restrict__ images, int H, int W,
   float v = 0.0f;
   if (y >= 0 && y < H && x >= 0 && x < W)
     v = sqrtw[p] * (float)images[(size_t)(d.img + tau) * H * W + (size_t)y * W + x];
-  const uint16_t h = bf16_rne(v);
+  uint16_t h, l;
+  bf16_split(v, h, l);
   Xhi[(size_t)b * ldX + p] = h;
-  Xlo[(size_t)b * ldX + p] = bf16_rne(v - __uint_as_float((uint32_t)h << 16));
+  Xlo[(size_t)b * ldX + p] = l;
 }
 
 void launch_gather_split(const uint8_t* images, int H, int W, const DevBlock* blk, int n_blk,

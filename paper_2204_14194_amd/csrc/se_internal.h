@@ -206,6 +206,11 @@ struct OnDemandPlan {
   const float* tx;        // their A and B operands (when n_parts > 0)
   float* splitk;        // partial products of split contractions
   size_t splitk_floats;
+  // split-BF16 operands of the per-iteration dense row products (NULL: FP32)
+  uint16_t* phi_hi;     // K x P
+  uint16_t* phi_lo;
+  uint16_t* Vhi;        // n_blk x ldV
+  uint16_t* Vlo;
   float* st;            // n_blk x 2
   float* g;             // n_blk x ldg, followed by gc (n_blk x ldg)
   float* gc;

@@ -277,8 +277,8 @@ def test_rejects_bad_video_areas_on_host():
 
 def test_rejects_fixed_point_rows_on_host():
     """SE_ROWS_Q14 is taken only by the one-launch calls on class tables with
-    fixed-point rows; unknown flags, the other calls and misaligned rows are
-    refused before any device work."""
+    fixed-point rows, SE_ROWS_BF16X3 only by rows on demand; unknown flags,
+    the other calls and misaligned rows are refused before any device work."""
     L = B.lib()
     fake = C.c_void_p(0x1000)
     t = _tables_struct(K=2048, M=32, N=32)          # no parts, no class tables
@@ -289,7 +289,7 @@ def test_rejects_fixed_point_rows_on_host():
         return getattr(L, name)(C.byref(t), fake, 1, 64, 64, blk, 1, prm, None, None, None, 0,
                                 fake, 16, None)
     assert call("se_extrapolate_batch", B.se_params(0.5, 10, 0)) == B.SE_ENOMEM
-    assert call("se_extrapolate_batch", B.se_params(0.5, 10, 2)) == B.SE_EINVAL
+    assert call("se_extrapolate_batch", B.se_params(0.5, 10, 4)) == B.SE_EINVAL
     assert b"unknown flags" in L.se_last_error()
     for name in ("se_extrapolate_batch", "se_extrapolate_plain"):
         assert call(name, q14) == B.SE_EINVAL and b"SE_ROWS_Q14" in L.se_last_error()
@@ -299,7 +299,14 @@ def test_rejects_fixed_point_rows_on_host():
     bas = B.make_basis(32, 32, 2048, 0x1000)
     r = L.se_extrapolate_ondemand(C.byref(bas), fake, fake, 1, 64, 64, blk, 1, q14, None,
                                   None, None, None, 0, fake, 16, None)
-    assert r == B.SE_EINVAL and b"no flags" in L.se_last_error()
+    assert r == B.SE_EINVAL and b"no fixed-point rows" in L.se_last_error()
+    # split-BF16 rows belong to rows on demand
+    bf = B.se_params(0.5, 10, B.SE_ROWS_BF16X3)
+    assert call("se_extrapolate_batch", bf) == B.SE_EINVAL
+    assert b"rows on demand" in L.se_last_error()
+    r = L.se_extrapolate_ondemand(C.byref(bas), fake, fake, 1, 64, 64, blk, 1, bf, None,
+                                  None, None, None, 0, fake, 16, None)
+    assert r == B.SE_ENOMEM
     t.Gq = 0x1002
     assert L.se_weighted_gram(C.byref(bas), fake, 0, 0, C.byref(t), fake, 1 << 20,
                               None) == B.SE_EINVAL

@@ -337,6 +337,18 @@ def test_ondemand_clustered_losses(area, with_parts):
     transforms of w_b phi_u (Section VI) and the rest by the product with the
     dictionary."""
     say(f"on-demand clustered losses: area {area}, transform parts {with_parts}")
+    _ondemand_clustered(area, with_parts, False, TOL_FP32)
+
+
+@pytest.mark.parametrize("area", [24, 48])
+def test_ondemand_clustered_losses_bf16x3_rows(area):
+    """The same with the dense (Gaussian) atoms' row products from split-BF16
+    operands (SE_ROWS_BF16X3), held to the BF16x3 bar."""
+    say(f"on-demand clustered losses, split-BF16 rows: area {area}")
+    _ondemand_clustered(area, True, True, TOL_BF16X3)
+
+
+def _ondemand_clustered(area, with_parts, rows_bf16, tol):
     d = synth.clustered_inputs(n_img=1, blocks_per_img=500)
     blocks = [b for b in d["blocks"] if b.ly * 2 + b.lh == area]
     iters = [int(v) for v, b in zip(d["iters"], d["blocks"]) if b.ly * 2 + b.lh == area]
@@ -347,7 +359,8 @@ def test_ondemand_clustered_losses(area, with_parts):
     w = B.area_weights(area, area, 0.8, torch.from_numpy(lost).to(dev()), blocks)
     img_d = torch.from_numpy(img).to(dev())
     sel, coef, g = B.extrapolate_ondemand(upload_phi(phi), area, area, w, img_d, blocks, 0.5,
-                                          iters, parts=d["tx_parts"][area] if with_parts else ())
+                                          iters, parts=d["tx_parts"][area] if with_parts else (),
+                                          rows_bf16=rows_bf16)
     torch.cuda.synchronize()
     sel, g, out = sel.cpu().numpy(), g.cpu().numpy(), img_d.cpu().numpy()
     rng = np.random.default_rng(area)
@@ -370,10 +383,10 @@ def test_ondemand_clustered_losses(area, with_parts):
         gref = res.g.reshape(area, area)[b.ly:b.ly + b.lh, b.lx:b.lx + b.lw].reshape(-1)
         err = np.abs(g[i, :n] - gref).max()
         worst = max(worst, err)
-        assert err <= TOL_FP32, f"block {i}: {err}"
+        assert err <= tol, f"block {i}: {err}"
         y, x = b.y0 + b.ly, b.x0 + b.lx
         got = out[0, y:y + b.lh, x:x + b.lw].reshape(-1)
-        near = np.abs(np.abs(gref - np.floor(gref)) - 0.5) < TOL_FP32
+        near = np.abs(np.abs(gref - np.floor(gref)) - 0.5) < tol
         assert ((got == np.clip(np.rint(gref), 0, 255)) | near).all()
     print(f"on-demand area {area}: {len(blocks)} blocks, identical selections "
           f"{agree}/{len(sample)}, max|dg|={worst:.3g}")
