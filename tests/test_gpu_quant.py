@@ -198,3 +198,39 @@ def test_fixed_point_area64():
     f = _run(_dequantised_twin(t), d["images"], d["blocks"], 300, False, n=64)
     for name, x, y in zip(("sel", "coef", "g_loss", "image"), q, f):
         assert torch.equal(x, y), f"{name} differs"
+
+
+def test_fixed_point_edge_cases():
+    """An empty batch, zero iterations (the model is 0 and is pasted), and
+    areas across the image border next to areas on the 16-byte grid: the
+    fixed-point route equals the FP32 route on the dequantised rows bit for
+    bit; tables without fixed-point words refuse the flag."""
+    M = N = 32
+    H, W = 3 * M + 8, 3 * N + 16
+    images = np.stack([synth.synth_image(H, W, seed=40 + s) for s in range(2)])
+    blocks = [synth.Block(i, y, x, 12, 12, 8, 8)
+              for i in range(2) for (y, x) in ((-12, -12), (0, 16), (40, 48), (H - 20, W - 20))]
+    say("fixed-point route: empty batch, I=0, 8 areas of which 4 cross the border")
+    phi = upload_phi(synth.round_to_f32(synth.dictionary(M, N, ("dct", "wht"))))
+    parts = synth.dictionary_parts(M, N, ("dct", "wht"))
+    t, _, _ = shared_tables(images, blocks, phi, M, N, 0.8, parts=parts, ref_block=1,
+                            fixed_point=True)
+    assert t.n_classes == 4
+    twin = _dequantised_twin(t)
+    img = torch.from_numpy(images).to(dev())
+    sel, coef, g = B.extrapolate_batch(t, img, [], 0.5, 100, rows_q14=True)
+    torch.cuda.synchronize()
+    assert sel.numel() == 0 and torch.equal(img.cpu(), torch.from_numpy(images))
+    for iters in (0, 100):
+        q = _run(t, images, blocks, iters, True)
+        f = _run(twin, images, blocks, iters, False)
+        for name, x, y in zip(("sel", "coef", "g_loss", "image"), q, f):
+            assert torch.equal(x, y), f"{name} differs at I={iters}"
+        if iters == 0:
+            assert (q[2] == 0).all()
+    # class tables without words: the flag is refused
+    t2, _, _ = shared_tables(images, blocks, phi, M, N, 0.8, parts=parts, ref_block=1)
+    assert t2.n_classes == 4 and t2.Gq is None
+    with pytest.raises(RuntimeError, match="SE_ROWS_Q14"):
+        B.extrapolate_batch(t2, torch.from_numpy(images).to(dev()), blocks, 0.5, 10,
+                            rows_q14=True)
