@@ -537,9 +537,10 @@ static se_status check_params(se_params prm, const float* g_loss, int g_loss_ld)
   return SE_OK;
 }
 
-// SE_ROWS_Q14 is honoured by the one-launch class route only (the calls
-// that take it pass `route_ok` for tables that go there)
-static se_status check_rows_q14(const se_tables* t, se_params prm, bool route_ok) {
+// The flags of the table routes: SE_ROWS_Q14 is honoured by the one-launch
+// class route only (the calls that take it pass `route_ok` for tables that
+// go there); SE_ROWS_BF16X3 belongs to rows on demand.
+static se_status check_route_flags(const se_tables* t, se_params prm, bool route_ok) {
   if (prm.flags & SE_ROWS_BF16X3)
     return fail(SE_EINVAL, "SE_ROWS_BF16X3 is an option of rows on demand");
   if (!(prm.flags & SE_ROWS_Q14)) return SE_OK;
@@ -557,7 +558,7 @@ se_status se_iterate(const se_tables* t, const float* R, int32_t ldR, uint8_t* i
   se_status st = check_common(t, n_img, H, W, n_blk, images, dev_blocks);
   if (st) return st;
   if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
-  if ((st = check_rows_q14(t, prm, false))) return st;
+  if ((st = check_route_flags(t, prm, false))) return st;
   if (n_blk == 0) return SE_OK;
   if ((st = check_r(t, R, ldR))) return st;
   GreedyArgs ga = greedy_args(t, R, ldR, images, H, W, dev_blocks, n_blk, prm, sel, coef, g_loss,
@@ -583,7 +584,7 @@ se_status se_extrapolate_device(const se_tables* t, uint8_t* images, int32_t n_i
   se_status st = check_common(t, n_img, H, W, n_blk, images, dev_blocks);
   if (st) return st;
   if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
-  if ((st = check_rows_q14(t, prm, true))) return st;
+  if ((st = check_route_flags(t, prm, true))) return st;
   if (n_blk == 0) return SE_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int ldR = r_row_len(t);
@@ -622,7 +623,7 @@ static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, in
   if (st) return st;
   if (!images) return fail(SE_EINVAL, "images is NULL");
   if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
-  if ((st = check_rows_q14(t, prm, !plain))) return st;
+  if ((st = check_route_flags(t, prm, !plain))) return st;
   if ((st = check_blocks(t, n_img, H, W, blocks, n_blk, g_loss_ld, g_loss))) return st;
   if (plain && t->phi_im) return fail(SE_EINVAL, "the per-block form takes real dictionaries");
   if (n_blk == 0) return SE_OK;
