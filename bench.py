@@ -674,7 +674,7 @@ def bench_video(args):
         e0, e1 = _events(2)
         e0.record()
         t = B.weighted_gram(phi, w[0].contiguous(), Mv, Nv, T=T,
-                            parts=() if args.no_parts else d["tx_parts"])
+                            parts=() if args.no_parts else d["tx_parts"], fixed_point=True)
         e1.record()
         e1.synchronize()
         gram.append(e0.elapsed_time(e1))
@@ -695,6 +695,14 @@ def bench_video(args):
     ms = (_timed(lambda: B.extrapolate_device(t, img, db, GAMMA, ITERS), args.steps, args.warmup)
           if one else two_ms)
     med = float(np.median(ms))
+    # the same launch on the class rows as 16-bit fixed-point words
+    q14 = None
+    if one and t.n_classes == 4:
+        q = _timed(lambda: B.extrapolate_device(t, img, db, GAMMA, ITERS, rows_q14=True),
+                   args.steps, args.warmup)
+        q14 = {"ms_per_step": float(np.median(q)),
+               "blocks_per_s": n / (float(np.median(q)) * 1e-3),
+               "what": "one launch reading the class rows as 16-bit words (SE_ROWS_Q14)"}
     loop_ms, proj_ms = float(np.median(loop)), float(np.median(proj))
     P = T * Mv * Nv
     # per iteration a row of G and the atom over the loss; R^(0) once
@@ -716,6 +724,7 @@ def bench_video(args):
             "latency_ms": {"p50": percentile(ms, 50), "p99": percentile(ms, 99)},
             "two_launch": {"ms_per_step": float(np.median(two_ms)),
                            "blocks_per_s": n / (float(np.median(two_ms)) * 1e-3)},
+            "fixed_point_rows": q14,
             "kernels": {"project_ms": proj_ms,
                         "project_tflops": proj_flops / (proj_ms * 1e-3) / 1e12,
                         "loop_ms": loop_ms,
