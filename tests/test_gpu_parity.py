@@ -221,6 +221,37 @@ def test_area32_bench_scale_sampled():
         np.testing.assert_array_equal(out[b.img, y:y + 8, x:x + 8], q)
 
 
+def test_area32_bench_scale_timed_route():
+    """The route the benchmark times: the dictionary's DCT-II and WHT halves
+    declared as transform parts, class tables, one se_extrapolate_device
+    launch for 4096 blocks (256 images x 16), sampled against the oracle;
+    every block's paste is its rounded model."""
+    d = synth.area32_inputs(256)
+    say("benchmark route: 4096 blocks, one launch on parity-class rows, sampled oracle check")
+    phi = synth.round_to_f32(d["phi"])
+    t, _, _ = shared_tables(d["images"], d["blocks"], upload_phi(phi), 32, 32, 0.8,
+                            parts=d["tx_parts"])
+    assert t.n_classes == 4
+    n = len(d["blocks"])
+    img = torch.from_numpy(d["images"]).to(dev())
+    db = B.DeviceBlocks(t, img, d["blocks"])
+    assert B.extrapolate_device_ws_bytes(t, n) == 0
+    sel = torch.zeros((n, 100), dtype=torch.int32, device=dev())
+    coef = torch.zeros((n, 100), dtype=torch.float32, device=dev())
+    g = torch.zeros((n, 64), dtype=torch.float32, device=dev())
+    B.extrapolate_device(t, img, db, 0.5, 100, None, sel, coef, g)
+    torch.cuda.synchronize()
+    sel, coef, g, out = (x.cpu().numpy() for x in (sel, coef, g, img))
+    sample = np.random.default_rng(1).choice(n, 24, replace=False)
+    worst, _ = check_against_oracle(d["images"], d["blocks"], phi, 32, 32, 0.8, 0.5, 100, sel,
+                                    coef, g, out, sample=sample)
+    print(f"benchmark route vs oracle on 24 sampled blocks: max|dg|={worst:.3g}")
+    for i, b in enumerate(d["blocks"]):
+        y, x = b.y0 + b.ly, b.x0 + b.lx
+        q = np.clip(np.rint(g[i, :64]), 0, 255).reshape(8, 8)
+        np.testing.assert_array_equal(out[b.img, y:y + 8, x:x + 8], q)
+
+
 @pytest.mark.parametrize("M,N,K,nimg", [(5, 7, 37, 1), (32, 32, 2048, 19), (20, 20, 700, 3)])
 def test_project_matches_oracle(M, N, K, nimg):
     """se_project alone: R[b][k] = D_k sum_p phi_k w s_b (eq. 12), padded
