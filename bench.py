@@ -522,10 +522,21 @@ def main():
         "two_launch": split,
         "full_rows": full_rows,
         "fixed_point_rows": fixed_point,
-        "roofline": roof,
+        "roofline": _with_traffic_rate(roof),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def _with_traffic_rate(roof):
+    """The measured HBM bytes per launch as a rate over the same launch time,
+    and its fraction of the HBM peak (how far HBM itself is from its limit,
+    next to `frac`, which counts the requested bytes)."""
+    if roof and roof.get("traffic") and roof.get("avg_ms"):
+        rate = roof["traffic"] / (roof["avg_ms"] * 1e-3) / 1e9
+        roof["traffic_gbs"] = rate
+        roof["traffic_frac"] = rate / HBM_PEAK_GBS
+    return roof
 
 
 # ---------------------------------------------------------------------------
