@@ -118,6 +118,7 @@ __global__ __launch_bounds__(kOdThreads) void k_od_step(OdArgs a) {
   const int nj = a.ld / (4 * kOdThreads);
   for (int j = 0; j < nj; ++j) {
     const int k0 = 4 * (j * kOdThreads + t);
+    if (k0 >= K) break;   // the padding (always 0) is neither updated nor a candidate
     float4 r = *reinterpret_cast<const float4*>(R + k0);
     if (upd) {
       const float4 d = *reinterpret_cast<const float4*>(D + k0);
