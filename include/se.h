@@ -567,7 +567,8 @@ typedef struct {
   int32_t H, W;
   const se_loss* losses;     /* host, copied during submit                    */
   int32_t n_losses;
-  se_params prm;             /* gamma and iteration count for every block     */
+  se_params prm;             /* gamma and iteration count for every block;
+                                flags must be 0                                  */
 } se_request;
 
 typedef struct {
