@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <numeric>
+#include <unordered_map>
 #include <vector>
 
 #include "se_internal.h"
@@ -253,6 +254,85 @@ static se_status project_into(const se_tables* t, const uint8_t* images, int H, 
   return SE_OK;
 }
 
+// Each block writes its loss into the images in place, so no pixel may lie
+// in two losses.  The losses (clipped to the frames, which is all a block
+// writes) are bucketed by the 32 x 32 cells of each frame they touch, and
+// only losses that share a cell are compared: linear in the number of blocks.
+// The buckets live in an open-addressing table of the calling thread, at
+// most half full and reused across calls (a generation stamp marks the live
+// slots, so nothing is cleared per call).
+static se_status check_loss_overlap(const se_block* blocks, int n_blk, int H, int W) {
+  struct Box {
+    int f0, f1, y0, y1, x0, x1;   // inclusive; y1 < y0 when wholly outside
+  };
+  struct Slot {
+    uint64_t key;
+    uint32_t gen;
+    int head;                     // newest entry of the cell
+  };
+  struct Entry {
+    int box, next;
+  };
+  thread_local std::vector<Slot> tl_table;
+  thread_local std::vector<Box> tl_box;
+  thread_local std::vector<Entry> tl_entries;
+  thread_local uint32_t tl_gen = 0;
+  if (n_blk < 2) return SE_OK;
+  // one thread-local lookup each (every access to a thread_local of a
+  // shared library is a call)
+  std::vector<Slot>& table = tl_table;
+  std::vector<Box>& box = tl_box;
+  std::vector<Entry>& entries = tl_entries;
+  uint32_t& gen_ref = tl_gen;
+  box.resize((size_t)n_blk);
+  size_t n_cells = 0;
+  for (int i = 0; i < n_blk; ++i) {
+    const se_block& b = blocks[i];
+    const int ld = b.ld < 1 ? 1 : b.ld;
+    Box& q = box[(size_t)i];
+    q = Box{b.img + b.lt, b.img + b.lt + ld - 1, std::max(b.y0 + b.ly, 0),
+            std::min(b.y0 + b.ly + b.lh, H) - 1, std::max(b.x0 + b.lx, 0),
+            std::min(b.x0 + b.lx + b.lw, W) - 1};
+    if (q.y1 >= q.y0 && q.x1 >= q.x0)
+      n_cells += (size_t)ld * ((q.y1 >> 5) - (q.y0 >> 5) + 1) * ((q.x1 >> 5) - (q.x0 >> 5) + 1);
+  }
+  size_t cap = 1024;
+  while (cap < 2 * n_cells) cap <<= 1;
+  if (table.size() < cap || ++gen_ref == 0) {
+    table.assign(std::max(cap, table.size()), Slot{0, 0, -1});
+    gen_ref = 1;
+  }
+  const uint32_t gen = gen_ref;
+  const size_t mask = table.size() - 1;
+  int shift = 64;                 // Fibonacci hashing: the product's top bits
+  for (size_t c = table.size(); c > 1; c >>= 1) --shift;
+  entries.clear();
+  for (int i = 0; i < n_blk; ++i) {
+    const Box& q = box[(size_t)i];
+    if (q.y1 < q.y0 || q.x1 < q.x0) continue;
+    for (int f = q.f0; f <= q.f1; ++f)
+      for (int cy = q.y0 >> 5; cy <= q.y1 >> 5; ++cy)
+        for (int cx = q.x0 >> 5; cx <= q.x1 >> 5; ++cx) {
+          const uint64_t key = ((uint64_t)(uint32_t)f << 40) | ((uint64_t)(uint32_t)cy << 20) |
+                               (uint64_t)(uint32_t)cx;
+          size_t h = (size_t)((key * 0x9E3779B97F4A7C15ull) >> shift);
+          while (table[h].gen == gen && table[h].key != key) h = (h + 1) & mask;
+          Slot& sl = table[h];
+          if (sl.gen != gen) sl = Slot{key, gen, -1};
+          for (int e = sl.head; e >= 0; e = entries[(size_t)e].next) {
+            const int j = entries[(size_t)e].box;
+            const Box& o = box[(size_t)j];
+            if (o.f0 <= q.f1 && q.f0 <= o.f1 && o.y0 <= q.y1 && q.y0 <= o.y1 && o.x0 <= q.x1 &&
+                q.x0 <= o.x1)
+              return fail(SE_EINVAL, "blocks %d and %d: their losses overlap", j, i);
+          }
+          entries.push_back(Entry{i, sl.head});
+          sl.head = (int)entries.size() - 1;
+        }
+  }
+  return SE_OK;
+}
+
 static se_status check_blocks(const se_tables* t, int n_img, int H, int W, const se_block* blocks,
                               int n_blk, int g_loss_ld, const float* g_loss) {
   if (n_blk < 0) return fail(SE_EINVAL, "n_blk < 0");
@@ -274,7 +354,7 @@ static se_status check_blocks(const se_tables* t, int n_img, int H, int W, const
     if (g_loss && n > g_loss_ld)
       return fail(SE_EINVAL, "block %d: g_loss_ld=%d < loss size %lld", i, g_loss_ld, n);
   }
-  return SE_OK;
+  return check_loss_overlap(blocks, n_blk, H, W);
 }
 
 }  // namespace sefase
@@ -730,6 +810,7 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* im
     if (it[(size_t)i] < 0) return fail(SE_EINVAL, "block %d: negative iteration count", i);
     iters_max = std::max(iters_max, it[(size_t)i]);
   }
+  if ((st = check_loss_overlap(blocks, n_blk, H, W))) return st;
   if (n_blk == 0) return SE_OK;
   const size_t need = se_extrapolate_ondemand_ws_bytes(b, n_blk, max_loss);
   if (!ws || ws_bytes < need) return fail(SE_ENOMEM, "workspace too small: need %zu bytes", need);

@@ -311,3 +311,38 @@ def test_rejects_fixed_point_rows_on_host():
     assert L.se_weighted_gram(C.byref(bas), fake, 0, 0, C.byref(t), fake, 1 << 20,
                               None) == B.SE_EINVAL
     assert b"Gq" in L.se_last_error()
+
+
+def test_rejects_overlapping_losses_on_host():
+    """Each block writes its loss in place: losses sharing a pixel are
+    refused; adjacent losses, losses in different images and losses that
+    meet only outside the image are accepted (checked up to the workspace
+    test, SE_ENOMEM, before any device work)."""
+    L = B.lib()
+    fake = C.c_void_p(0x1000)
+    prm = B.se_params(0.5, 10, 0)
+    t = _tables_struct(K=2048, M=32, N=32)
+
+    def batch(pairs, n_img=2, H=100, W=100):
+        blk = (B.se_block * len(pairs))(*[B.se_block(*p) for p in pairs])
+        return L.se_extrapolate_batch(C.byref(t), fake, n_img, H, W, blk, len(pairs), prm, None,
+                                      None, None, 0, fake, 16, None)
+    # (img, y0, x0, ly, lx, lh, lw)
+    a = (0, 10, 10, 12, 12, 8, 8)                     # loss rows 22..29, cols 22..29
+    assert batch([a, (0, 10, 17, 12, 12, 8, 8)]) == B.SE_EINVAL   # shares column 29
+    assert b"overlap" in L.se_last_error()
+    assert batch([a, (0, 10, 18, 12, 12, 8, 8)]) == B.SE_ENOMEM   # adjacent
+    assert batch([a, (1, 10, 10, 12, 12, 8, 8)]) == B.SE_ENOMEM   # another image
+    # losses that meet only above the image (rows < 0) write nothing there
+    assert batch([(0, -20, 0, 12, 12, 8, 8), (0, -20, 4, 12, 12, 8, 8)]) == B.SE_ENOMEM
+    assert batch([(0, -16, 0, 12, 12, 8, 8), (0, -16, 4, 12, 12, 8, 8)]) == B.SE_EINVAL
+    # many disjoint losses across cell borders, one duplicate at the end
+    grid = [(0, y, x, 12, 12, 8, 8) for y in range(-12, 80, 8) for x in range(-12, 80, 8)]
+    assert batch(grid) == B.SE_ENOMEM
+    assert batch(grid + [grid[57]]) == B.SE_EINVAL
+    # rows on demand check the same
+    bas = B.make_basis(32, 32, 2048, 0x1000)
+    blk = (B.se_block * 2)(B.se_block(*a), B.se_block(0, 10, 17, 12, 12, 8, 8))
+    r = L.se_extrapolate_ondemand(C.byref(bas), fake, fake, 2, 100, 100, blk, 2, prm, None,
+                                  None, None, None, 0, fake, 16, None)
+    assert r == B.SE_EINVAL and b"overlap" in L.se_last_error()
