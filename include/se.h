@@ -355,7 +355,7 @@ se_status se_weighted_gram(const se_basis* b, const float* w,
  *             workgroup size of the loop for K: 1 for K <= 2048, 2 for
  *             K <= 4096, 4 for K <= 8192, 8 for K <= 16384, 16 above; so 256
  *             pixels are always accepted); losses of different blocks must
- *             not overlap
+ *             not share a pixel inside the frames (SE_EINVAL otherwise)
  *   sel     : optional device int32 n_blk x iters, selected atom per
  *             iteration (NULL to skip)
  *   coef    : optional device float32 n_blk x iters, coefficient c per
