@@ -445,6 +445,37 @@ se_status se_extrapolate_plain(const se_tables* t, uint8_t* images,
                                float* g_loss, int32_t g_loss_ld, void* ws,
                                size_t ws_bytes, void* stream);
 
+/* se_extrapolate_batch without a workspace argument, for callers that
+ * cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.  Same contract, route
+ * and results (bit for bit) as se_extrapolate_batch; the scratch memory is
+ * a static device array of the library, SE_STATIC_SCRATCH_BYTES bytes on
+ * every GPU the library's code is loaded on, held until the process ends.
+ * Its device address is looked up on the first call on each device (the
+ * device of `stream`; the current device for the null stream); the call
+ * itself allocates no device memory and calls no allocating routine.
+ *   Scratch needed: 256-byte aligned pieces of n_blk * 40 bytes of
+ *   descriptors and, unless every atom lies in the two declared transform
+ *   parts of a 32 x 32, 64 x 64 or 64 x 16 area (the one-launch route),
+ *   n_blk rows of R (se_table_ld(K) floats, twice that for a complex
+ *   dictionary) and the projection workspace (n_blk * M*N floats, plus the
+ *   partial products of a split contraction for small batches).  A batch
+ *   that needs more than SE_STATIC_SCRATCH_BYTES returns SE_ENOMEM and
+ *   launches nothing.
+ *   Sharing: every call on one GPU uses that GPU's one array, and nothing
+ *   in it has to start at zero (each call writes every byte it reads).
+ *   Calls that overlap in time on one GPU (on different streams or from
+ *   different threads) race on the array: serialise them, e.g. on one
+ *   stream.
+ * Other arguments and errors as for se_extrapolate_batch. */
+#define SE_STATIC_SCRATCH_BYTES ((size_t)16 << 20)
+se_status se_extrapolate_batch_static(const se_tables* t, uint8_t* images,
+                                      int32_t n_img, int32_t H, int32_t W,
+                                      const se_block* blocks, int32_t n_blk,
+                                      se_params prm, int32_t* sel, float* coef,
+                                      float* g_loss, int32_t g_loss_ld,
+                                      void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Autotuning of the batched path                                           */
 /* ------------------------------------------------------------------------ */

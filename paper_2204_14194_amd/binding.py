@@ -33,7 +33,11 @@ EXPORTED = (
     "se_project", "se_iterate", "se_extrapolate_device_ws_bytes", "se_extrapolate_device",
     "se_table_ld", "se_tables_tx_bytes",
     "se_extrapolate_ondemand_ws_bytes", "se_extrapolate_ondemand",
+    "se_extrapolate_batch_static",
 )
+
+# bytes of the library's static scratch (se_extrapolate_batch_static)
+SE_STATIC_SCRATCH_BYTES = 16 << 20
 
 
 class SEError(RuntimeError):
@@ -140,6 +144,9 @@ def lib():
         f.restype = i32
         f.argtypes = [C.POINTER(se_tables), vp, i32, i32, i32, vp, i32, se_params, vp, vp, vp,
                       i32, vp, sz, vp]
+    L.se_extrapolate_batch_static.restype = i32
+    L.se_extrapolate_batch_static.argtypes = [C.POINTER(se_tables), vp, i32, i32, i32, vp, i32,
+                                              se_params, vp, vp, vp, i32, vp]
     L.se_blocks_upload.restype = i32
     L.se_blocks_upload.argtypes = [C.POINTER(se_tables), i32, i32, i32, vp, i32, vp,
                                    C.POINTER(C.c_int32), vp]
@@ -407,6 +414,32 @@ def extrapolate_batch(t: Tables, images: torch.Tensor, blocks: Sequence, gamma: 
     return _extrapolate("se_extrapolate_batch", t, images, blocks, gamma, iters, want_sel,
                         want_coef, want_g, ws, stream, blocks_arr,
                         SE_ROWS_Q14 if rows_q14 else 0)
+
+
+def extrapolate_batch_static(t: Tables, images: torch.Tensor, blocks: Sequence, gamma: float,
+                             iters: int, want_sel=True, want_coef=True, want_g=True,
+                             stream=None, blocks_arr=None, rows_q14: bool = False):
+    """se_extrapolate_batch_static: se_extrapolate_batch with the library's
+    static scratch as workspace (no workspace is allocated; the output
+    tensors requested here are).  Results as extrapolate_batch."""
+    L = lib()
+    if not (images.is_cuda and images.dtype == torch.uint8 and images.dim() == 3
+            and images.is_contiguous()):
+        raise ValueError("images must be a contiguous (n_img, H, W) uint8 CUDA tensor")
+    n_img, H, W = images.shape
+    n = len(blocks)
+    dev = images.device
+    sel = torch.empty((n, iters), dtype=torch.int32, device=dev) if want_sel else None
+    coef = (torch.empty((n, iters * (2 if t.complex else 1)), dtype=torch.float32, device=dev)
+            if want_coef else None)
+    gld = max([loss_size(b) for b in blocks] + [1])
+    g = torch.zeros((n, gld), dtype=torch.float32, device=dev) if want_g else None
+    st = t.struct()
+    arr = blocks_arr if blocks_arr is not None else blocks_array(blocks)
+    prm = se_params(float(gamma), int(iters), SE_ROWS_Q14 if rows_q14 else 0)
+    _check(L.se_extrapolate_batch_static(C.byref(st), _ptr(images), n_img, H, W, arr, n, prm,
+                                         _ptr(sel), _ptr(coef), _ptr(g), gld, _stream(stream)))
+    return sel, coef, g
 
 
 def extrapolate_plain(t: Tables, images: torch.Tensor, blocks: Sequence, gamma: float,

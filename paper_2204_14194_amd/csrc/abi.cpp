@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <numeric>
 #include <unordered_map>
 #include <vector>
@@ -44,6 +45,66 @@ static se_status upload_blocks(const se_block* blocks, int n_blk, DevBlock* dst,
   const hipError_t e = hipMemcpyAsync(dst, tmp.data(), tmp.size() * sizeof(DevBlock),
                                       hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return fail(SE_EHIP, "block upload: %s", hipGetErrorString(e));
+  return SE_OK;
+}
+
+// Descriptors as the caller wrote them, normalised on the device the way
+// upload_blocks writes them (tag cleared, ld = 0 read as 1): the upload of
+// the allocation-free entry point needs no host staging buffer.
+__global__ void k_normalize_blocks(se_block* b, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  se_block v = b[i];
+  v.geom = 0;
+  v.ld = v.ld < 1 ? 1 : v.ld;
+  b[i] = v;
+}
+
+static se_status upload_blocks_raw(const se_block* blocks, int n_blk, DevBlock* dst,
+                                   hipStream_t s) {
+  // pageable source: the call returns once the data has been staged
+  const hipError_t e = hipMemcpyAsync(dst, blocks, (size_t)n_blk * sizeof(se_block),
+                                      hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return fail(SE_EHIP, "block upload: %s", hipGetErrorString(e));
+  hipLaunchKernelGGL(k_normalize_blocks, dim3((n_blk + 255) / 256), dim3(256), 0, s, dst, n_blk);
+  return check_launch("normalize_blocks");
+}
+
+// ---------------------------------------------------------------------------
+// Workspace of the allocation-free entry point: a static device array, one
+// copy per GPU (each device that loads the library's code object holds it
+// until the process ends).  In host code `scratch` names a host-side stand-in
+// only; kernels and copies get the device address that hipGetSymbolAddress
+// returns, looked up once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[SE_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxDevices];
+
+// Device address of `scratch` on the device `stream` belongs to (the current
+// device for the null stream).
+static se_status static_scratch(hipStream_t s, void** out) {
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return fail(SE_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+  int dev = cur;
+  if (s && (e = hipStreamGetDevice(s, &dev)) != hipSuccess)
+    return fail(SE_EHIP, "hipStreamGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SE_EINVAL, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    if (dev != cur && (e = hipSetDevice(dev)) != hipSuccess)
+      return fail(SE_EHIP, "hipSetDevice(%d): %s", dev, hipGetErrorString(e));
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (dev != cur) hipSetDevice(cur);
+    if (e != hipSuccess || !p)
+      return fail(SE_EHIP, "device address of the static scratch on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
   return SE_OK;
 }
 
@@ -694,10 +755,27 @@ size_t se_extrapolate_batch_ws_bytes(const se_tables* t, int32_t n_blk) {
   return cv.off + 256;
 }
 
+// Workspace one batched call actually uses on its route: the descriptors,
+// and R with the projection workspace unless the projections stay in the
+// loop's workgroups.
+static size_t batch_route_ws(const se_tables* t, int n_blk) {
+  Carver cv(nullptr);
+  cv.take<se_block>((size_t)n_blk);
+  if (!conceal_tx_supported(t)) {
+    cv.take<float>((size_t)n_blk * r_row_len(t));
+    cv.take<char>(project_ws(t, n_blk));
+  }
+  return cv.off;
+}
+
+// The batched and per-block calls.  use_static: the workspace is the static
+// scratch of this device (ws ignored), sized for the route taken, and the
+// descriptors are uploaded without a host staging buffer.
 static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, int32_t n_img,
                              int32_t H, int32_t W, const se_block* blocks, int32_t n_blk,
                              se_params prm, int32_t* sel, float* coef, float* g_loss,
-                             int32_t g_loss_ld, void* ws, size_t ws_bytes, void* stream) {
+                             int32_t g_loss_ld, void* ws, size_t ws_bytes, void* stream,
+                             bool use_static = false) {
   g_err[0] = 0;
   se_status st = check_tables(t);
   if (st) return st;
@@ -707,15 +785,26 @@ static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, in
   if ((st = check_blocks(t, n_img, H, W, blocks, n_blk, g_loss_ld, g_loss))) return st;
   if (plain && t->phi_im) return fail(SE_EINVAL, "the per-block form takes real dictionaries");
   if (n_blk == 0) return SE_OK;
-  const size_t need = se_extrapolate_batch_ws_bytes(t, n_blk);
-  if (!ws || ws_bytes < need) return fail(SE_ENOMEM, "workspace too small: need %zu bytes", need);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (use_static) {
+    const size_t need = batch_route_ws(t, n_blk);
+    if (need > SE_STATIC_SCRATCH_BYTES)
+      return fail(SE_ENOMEM, "the batch needs %zu bytes of scratch; the static scratch holds %zu",
+                  need, (size_t)SE_STATIC_SCRATCH_BYTES);
+    if ((st = static_scratch(s, &ws))) return st;
+    ws_bytes = SE_STATIC_SCRATCH_BYTES;
+  } else {
+    const size_t need = se_extrapolate_batch_ws_bytes(t, n_blk);
+    if (!ws || ws_bytes < need) return fail(SE_ENOMEM, "workspace too small: need %zu bytes", need);
+  }
   const int P = area_samples(t), ldR = r_row_len(t);
   Carver cv(ws);
   se_block* dblk = cv.take<se_block>((size_t)n_blk);
   float* R = cv.take<float>((size_t)n_blk * ldR);
   char* pws = cv.take<char>(project_ws(t, n_blk));
-  if ((st = upload_blocks(blocks, n_blk, dblk, s))) return st;
+  if ((st = use_static ? upload_blocks_raw(blocks, n_blk, dblk, s)
+                       : upload_blocks(blocks, n_blk, dblk, s)))
+    return st;
   GreedyArgs ga = greedy_args(t, R, ldR, images, H, W, dblk, n_blk, prm, sel, coef, g_loss,
                               g_loss_ld);
   if (!plain) {
@@ -900,6 +989,14 @@ se_status se_extrapolate_batch(const se_tables* t, uint8_t* images, int32_t n_im
                                void* ws, size_t ws_bytes, void* stream) {
   return extrapolate(false, t, images, n_img, H, W, blocks, n_blk, prm, sel, coef, g_loss,
                      g_loss_ld, ws, ws_bytes, stream);
+}
+
+se_status se_extrapolate_batch_static(const se_tables* t, uint8_t* images, int32_t n_img,
+                                      int32_t H, int32_t W, const se_block* blocks,
+                                      int32_t n_blk, se_params prm, int32_t* sel, float* coef,
+                                      float* g_loss, int32_t g_loss_ld, void* stream) {
+  return extrapolate(false, t, images, n_img, H, W, blocks, n_blk, prm, sel, coef, g_loss,
+                     g_loss_ld, nullptr, 0, stream, true);
 }
 
 se_status se_extrapolate_plain(const se_tables* t, uint8_t* images, int32_t n_img, int32_t H,
