@@ -41,6 +41,20 @@
  *   * Scratch memory ("ws") is device memory supplied by the caller; the
  *     matching *_ws_bytes() call gives the size needed.  No call allocates
  *     device memory.
+ *   * Blocks with nothing to extrapolate from: when every atom has a zero
+ *     weighted norm over a block's area (eq. 17 is undefined for all of
+ *     them), no atom can be selected.  Such a block reports sel = -1 in
+ *     every iteration, coefficients and model 0, and its loss is left as it
+ *     is; the other blocks of the call are concealed as usual.  Blocks whose
+ *     area holds no available sample by their geometry (the area wholly
+ *     outside the frames, or the loss covering every sample of the area
+ *     inside them) are found on the host: the concealment calls (and
+ *     se_blocks_upload) then return SE_ENUMERIC after launching everything
+ *     else, with the outputs written.  Blocks found only on the device
+ *     (every D_k = 0 for their weights, e.g. an area covered by other
+ *     losses) are reported through sel = -1 alone, since the calls do not
+ *     wait for the device; the server reports both kinds in the request's
+ *     status.
  */
 #ifndef SEFASE_SE_H
 #define SEFASE_SE_H
@@ -59,7 +73,7 @@ typedef int32_t se_status;
 #define SE_EHIP (-3)      /* a HIP runtime call or kernel launch failed    */
 #define SE_EAGAIN (-4)    /* result not ready yet (serving)                */
 #define SE_EBUSY (-5)     /* queue full (serving)                          */
-#define SE_ENUMERIC (-6)  /* numerically degenerate input                  */
+#define SE_ENUMERIC (-6)  /* blocks with nothing to extrapolate from      */
 #define SE_ECANCELED (-7) /* request cancelled / server shut down         */
 
 typedef enum { SE_FP32 = 0, SE_BF16X3 = 1 } se_precision;
@@ -342,7 +356,9 @@ se_status se_weighted_gram(const se_basis* b, const float* w,
  *   R^(0) = initial weighted projections (eq. 12), for all blocks at once as
  *           one matrix product on the matrix cores;
  *   I times: u = argmax_k |R_k| D_k (eq. 18; exact ties go to the lowest
- *           k), c = gamma R_u D_u^2 (eq. 19), g += c phi_u over the loss
+ *           k, also on the class route, where positions do not follow the
+ *           atom order across classes), c = gamma R_u D_u^2 (eq. 19),
+ *           g += c phi_u over the loss
  *           (eq. 9), R_k -= c C_(k,u) for all k (eq. 20);
  *   the loss rectangle of `images` is replaced by clip(rint(g), 0, 255)
  *           (round half to even).
@@ -366,7 +382,9 @@ se_status se_weighted_gram(const se_basis* b, const float* w,
  *             loss over several frames) (NULL to skip)
  *   ws      : device scratch of se_extrapolate_batch_ws_bytes() bytes
  * Errors: SE_EINVAL for bad descriptors or parameters (nothing launched),
- * SE_ENOMEM for ws too small, SE_EHIP for launch failures. */
+ * SE_ENOMEM for ws too small, SE_EHIP for launch failures, SE_ENUMERIC
+ * (everything launched, outputs written) when some blocks have no available
+ * sample (see the conventions above). */
 size_t se_extrapolate_batch_ws_bytes(const se_tables* t, int32_t n_blk);
 se_status se_extrapolate_batch(const se_tables* t, uint8_t* images,
                                int32_t n_img, int32_t H, int32_t W,

@@ -23,6 +23,9 @@ Contents, in the paper's notation:
                              atom (eq. 3), selects by eq. 7, estimates the
                              coefficient by eq. 8, updates by eq. 9-10
   * ``table_generation``  -- Algorithm 2: C (eq. 16) and D (eq. 17)
+  * ``TableColumns``      -- the same entries of C, formed per column when
+                             Algorithm 3 reads them (blocks with their own
+                             weighting functions)
   * ``fase``              -- Algorithm 3: R^(0) once (eq. 12), then
                              selection by eq. 18, coefficient by eq. 19 and
                              the recursive update eq. 20
@@ -72,7 +75,7 @@ __all__ = [
     "area_weights", "area_signal", "se_original", "table_generation", "fase",
     "conceal", "duplicate_classes", "quantise", "operation_counts",
     "SEResult", "volume_weights", "volume_signal", "conceal_video",
-    "unit_table", "quantise_table", "fase_unit",
+    "unit_table", "quantise_table", "fase_unit", "TableColumns",
 ]
 
 
@@ -269,6 +272,36 @@ def table_generation(phi: np.ndarray, w: np.ndarray):
     pos = diag > 0.0
     D[pos] = 1.0 / np.sqrt(diag[pos])
     return C, D
+
+
+class TableColumns:
+    """The table of eq. 16 for one weight pattern, formed column by column
+    when Algorithm 3 first reads a column: C[:, u] = sum phi_k^* w phi_u for
+    every k (the same entries as table_generation), and D (eq. 17) from the
+    diagonal sum phi_k^* w phi_k.  Algorithm 3 reads only the columns of the
+    atoms it selects, so for blocks that each have their own weighting
+    function (the tables then "have to be adapted", Section III) this costs
+    the selected columns instead of the whole table.  Only ``C[:, u]`` is
+    supported."""
+
+    def __init__(self, phi: np.ndarray, w: np.ndarray):
+        self.phi = _basis(phi)
+        self.w = np.asarray(w, dtype=np.float64)
+        self.cols: Dict[int, np.ndarray] = {}
+        self.phiw = _conj(self.phi) * self.w[None, :]        # phi_k^* w, every k
+        diag = np.sum(_abs2(self.phi) * self.w[None, :], axis=1)
+        self.D = np.zeros_like(diag)
+        pos = diag > 0.0
+        self.D[pos] = 1.0 / np.sqrt(diag[pos])
+
+    def __getitem__(self, key):
+        rows, u = key
+        if rows != slice(None):
+            raise IndexError("TableColumns supports C[:, u] only")
+        u = int(u)
+        if u not in self.cols:
+            self.cols[u] = self.phiw @ self.phi[u]
+        return self.cols[u]
 
 
 # ----------------------------------------------------------------------------

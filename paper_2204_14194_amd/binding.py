@@ -177,6 +177,25 @@ def _check(code: int):
         raise SEError(code, lib().se_last_error().decode())
 
 
+class SENumericError(SEError):
+    """SE_ENUMERIC from a concealment call: the call finished every other
+    block, but some blocks had no available sample in their area (they
+    report sel = -1 and keep their loss).  ``results`` holds the outputs the
+    call would have returned."""
+
+    def __init__(self, code: int, msg: str, results):
+        super().__init__(code, msg)
+        self.results = results
+
+
+def _check_results(code: int, results):
+    """_check for concealment calls: their outputs travel with SE_ENUMERIC."""
+    if code == SE_ENUMERIC:
+        raise SENumericError(code, lib().se_last_error().decode(), results)
+    _check(code)
+    return results
+
+
 def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else C.c_void_p(t.data_ptr())
 
@@ -399,9 +418,9 @@ def _extrapolate(name: str, t: Tables, images: torch.Tensor, blocks: Sequence, g
         raise ValueError(f"workspace of {ws.numel()} bytes < {nb}")
     arr = blocks_arr if blocks_arr is not None else blocks_array(blocks)
     prm = se_params(float(gamma), int(iters), int(flags))
-    _check(getattr(L, name)(C.byref(st), _ptr(images), n_img, H, W, arr, n, prm, _ptr(sel),
-                            _ptr(coef), _ptr(g), gld, _ptr(ws), ws.numel(), _stream(stream)))
-    return sel, coef, g
+    return _check_results(getattr(L, name)(C.byref(st), _ptr(images), n_img, H, W, arr, n, prm,
+                                           _ptr(sel), _ptr(coef), _ptr(g), gld, _ptr(ws),
+                                           ws.numel(), _stream(stream)), (sel, coef, g))
 
 
 def extrapolate_batch(t: Tables, images: torch.Tensor, blocks: Sequence, gamma: float,
@@ -437,9 +456,10 @@ def extrapolate_batch_static(t: Tables, images: torch.Tensor, blocks: Sequence, 
     st = t.struct()
     arr = blocks_arr if blocks_arr is not None else blocks_array(blocks)
     prm = se_params(float(gamma), int(iters), SE_ROWS_Q14 if rows_q14 else 0)
-    _check(L.se_extrapolate_batch_static(C.byref(st), _ptr(images), n_img, H, W, arr, n, prm,
-                                         _ptr(sel), _ptr(coef), _ptr(g), gld, _stream(stream)))
-    return sel, coef, g
+    return _check_results(L.se_extrapolate_batch_static(C.byref(st), _ptr(images), n_img, H, W,
+                                                        arr, n, prm, _ptr(sel), _ptr(coef),
+                                                        _ptr(g), gld, _stream(stream)),
+                          (sel, coef, g))
 
 
 def extrapolate_plain(t: Tables, images: torch.Tensor, blocks: Sequence, gamma: float,
@@ -464,8 +484,13 @@ class DeviceBlocks:
                                device=images.device)
         mx = C.c_int32(0)
         st = t.struct()
-        _check(L.se_blocks_upload(C.byref(st), n_img, H, W, blocks_array(blocks), self.n,
-                                  _ptr(self.buf), C.byref(mx), _stream(stream)))
+        code = L.se_blocks_upload(C.byref(st), n_img, H, W, blocks_array(blocks), self.n,
+                                  _ptr(self.buf), C.byref(mx), _stream(stream))
+        # SE_ENUMERIC: uploaded, with the blocks that have no available sample
+        # marked (the loop reports sel = -1 for them)
+        self.degenerate = code == SE_ENUMERIC
+        if not self.degenerate:
+            _check(code)
         self.max_loss = int(mx.value)
 
 
@@ -551,10 +576,11 @@ def extrapolate_ondemand(phi: torch.Tensor, M: int, N: int, w: torch.Tensor,
     elif ws.numel() < nb:
         raise ValueError(f"workspace of {ws.numel()} bytes < {nb}")
     prm = se_params(float(gamma), int(imax), SE_ROWS_BF16X3 if rows_bf16 else 0)
-    _check(L.se_extrapolate_ondemand(C.byref(bas), _ptr(w), _ptr(images), n_img, H, W,
-                                     blocks_array(blocks), n, prm, per, _ptr(sel), _ptr(coef),
-                                     _ptr(g), gld, _ptr(ws), ws.numel(), _stream(stream)))
-    return sel, coef, g
+    return _check_results(L.se_extrapolate_ondemand(C.byref(bas), _ptr(w), _ptr(images), n_img,
+                                                    H, W, blocks_array(blocks), n, prm, per,
+                                                    _ptr(sel), _ptr(coef), _ptr(g), gld,
+                                                    _ptr(ws), ws.numel(), _stream(stream)),
+                          (sel, coef, g))
 
 
 # ---------------------------------------------------------------------------

@@ -33,14 +33,28 @@ se_status check_launch(const char* what) {
 
 static inline int round4(int v) { return (v + 3) & ~3; }
 
-static se_status upload_blocks(const se_block* blocks, int n_blk, DevBlock* dst,
-                               hipStream_t s) {
+// Frames and area shape the descriptors are checked against when they are
+// uploaded for a loop (blocks without an available sample are marked).
+struct AreaShape {
+  int H, W, T, M, N;
+};
+
+// Copies n_blk descriptors to the device (ld = 0 read as 1); with `shape`,
+// marks the blocks that have no available sample (kBlockNoSupport) and
+// counts them into *n_deg.
+static se_status upload_blocks(const se_block* blocks, int n_blk, DevBlock* dst, hipStream_t s,
+                               const AreaShape* shape = nullptr, int* n_deg = nullptr) {
   std::vector<DevBlock> tmp((size_t)n_blk);
+  int deg = 0;
   for (int i = 0; i < n_blk; ++i) {
     const se_block& b = blocks[i];
-    tmp[(size_t)i] = DevBlock{b.img, b.y0, b.x0, b.ly, b.lx, b.lh, b.lw, 0, b.lt,
-                              b.ld < 1 ? 1 : b.ld};
+    const bool none = shape && block_without_support(b, shape->H, shape->W, shape->T, shape->M,
+                                                     shape->N);
+    deg += none;
+    tmp[(size_t)i] = DevBlock{b.img, b.y0, b.x0, b.ly, b.lx, b.lh, b.lw,
+                              none ? kBlockNoSupport : 0, b.lt, b.ld < 1 ? 1 : b.ld};
   }
+  if (n_deg) *n_deg = deg;
   // pageable source: the call returns once the data has been staged
   const hipError_t e = hipMemcpyAsync(dst, tmp.data(), tmp.size() * sizeof(DevBlock),
                                       hipMemcpyHostToDevice, s);
@@ -49,25 +63,42 @@ static se_status upload_blocks(const se_block* blocks, int n_blk, DevBlock* dst,
 }
 
 // Descriptors as the caller wrote them, normalised on the device the way
-// upload_blocks writes them (tag cleared, ld = 0 read as 1): the upload of
-// the allocation-free entry point needs no host staging buffer.
-__global__ void k_normalize_blocks(se_block* b, int n) {
+// upload_blocks writes them (ld = 0 read as 1, the blocks without an
+// available sample marked): the upload of the allocation-free entry point
+// needs no host staging buffer.
+__global__ void k_normalize_blocks(se_block* b, int n, AreaShape sh) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   se_block v = b[i];
-  v.geom = 0;
+  v.geom = block_without_support(v, sh.H, sh.W, sh.T, sh.M, sh.N) ? kBlockNoSupport : 0;
   v.ld = v.ld < 1 ? 1 : v.ld;
   b[i] = v;
 }
 
 static se_status upload_blocks_raw(const se_block* blocks, int n_blk, DevBlock* dst,
-                                   hipStream_t s) {
+                                   hipStream_t s, const AreaShape& shape) {
   // pageable source: the call returns once the data has been staged
   const hipError_t e = hipMemcpyAsync(dst, blocks, (size_t)n_blk * sizeof(se_block),
                                       hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return fail(SE_EHIP, "block upload: %s", hipGetErrorString(e));
-  hipLaunchKernelGGL(k_normalize_blocks, dim3((n_blk + 255) / 256), dim3(256), 0, s, dst, n_blk);
+  hipLaunchKernelGGL(k_normalize_blocks, dim3((n_blk + 255) / 256), dim3(256), 0, s, dst, n_blk,
+                     shape);
   return check_launch("normalize_blocks");
+}
+
+// The count of blocks without an available sample (host side).
+static int count_without_support(const se_block* blocks, int n_blk, const AreaShape& sh) {
+  int n = 0;
+  for (int i = 0; i < n_blk; ++i) n += block_without_support(blocks[i], sh.H, sh.W, sh.T, sh.M, sh.N);
+  return n;
+}
+
+// SE_ENUMERIC for a call that finished its other blocks but found n_deg
+// blocks with nothing to extrapolate from.
+static se_status degenerate_status(int n_deg) {
+  if (n_deg == 0) return SE_OK;
+  return fail(SE_ENUMERIC, "%d block(s) have no available sample in their area: sel = -1, loss "
+              "left unchanged", n_deg);
 }
 
 // ---------------------------------------------------------------------------
@@ -599,7 +630,12 @@ se_status se_blocks_upload(const se_tables* t, int32_t n_img, int32_t H, int32_t
   if (max_loss) *max_loss = mx;
   if (n_blk == 0) return SE_OK;
   if (!dev_blocks) return fail(SE_EINVAL, "dev_blocks is NULL");
-  return upload_blocks(blocks, n_blk, dev_blocks, static_cast<hipStream_t>(stream));
+  const AreaShape sh{H, W, area_frames(t->T), t->M, t->N};
+  int n_deg = 0;
+  if ((st = upload_blocks(blocks, n_blk, dev_blocks, static_cast<hipStream_t>(stream), &sh,
+                          &n_deg)))
+    return st;
+  return degenerate_status(n_deg);
 }
 
 size_t se_project_ws_bytes(const se_tables* t, int32_t n_blk) {
@@ -659,6 +695,8 @@ static GreedyArgs greedy_args(const se_tables* t, const float* R, int ldR, uint8
   ga.Gc = t->n_classes == 4 ? t->Gc : nullptr;
   ga.cls = t->n_classes == 4 ? reinterpret_cast<const int2*>(t->cls) : nullptr;
   ga.Gq = (prm.flags & SE_ROWS_Q14) && t->n_classes == 4 ? t->Gq : nullptr;
+  ga.cl = t->n_classes == 4 ? class_layout(t) : ClassLayout{};
+  ga.n_degenerate = nullptr;
   return ga;
 }
 
@@ -768,6 +806,11 @@ static size_t batch_route_ws(const se_tables* t, int n_blk) {
   return cv.off;
 }
 
+static se_status extrapolate_uploaded(bool plain, const se_tables* t, uint8_t* images, int H,
+                                      int W, se_block* dblk, float* R, char* pws, int n_blk,
+                                      se_params prm, int32_t* sel, float* coef, float* g_loss,
+                                      int32_t g_loss_ld, hipStream_t s);
+
 // The batched and per-block calls.  use_static: the workspace is the static
 // scratch of this device (ws ignored), sized for the route taken, and the
 // descriptors are uploaded without a host staging buffer.
@@ -785,6 +828,10 @@ static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, in
   if ((st = check_blocks(t, n_img, H, W, blocks, n_blk, g_loss_ld, g_loss))) return st;
   if (plain && t->phi_im) return fail(SE_EINVAL, "the per-block form takes real dictionaries");
   if (n_blk == 0) return SE_OK;
+  const AreaShape sh{H, W, area_frames(t->T), t->M, t->N};
+  const int n_deg = count_without_support(blocks, n_blk, sh);
+  // nothing to compute and nothing to report on the device
+  if (n_deg == n_blk && !sel && !coef && !g_loss) return degenerate_status(n_deg);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (use_static) {
     const size_t need = batch_route_ws(t, n_blk);
@@ -797,14 +844,27 @@ static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, in
     const size_t need = se_extrapolate_batch_ws_bytes(t, n_blk);
     if (!ws || ws_bytes < need) return fail(SE_ENOMEM, "workspace too small: need %zu bytes", need);
   }
-  const int P = area_samples(t), ldR = r_row_len(t);
+  const int ldR = r_row_len(t);
   Carver cv(ws);
   se_block* dblk = cv.take<se_block>((size_t)n_blk);
   float* R = cv.take<float>((size_t)n_blk * ldR);
   char* pws = cv.take<char>(project_ws(t, n_blk));
-  if ((st = use_static ? upload_blocks_raw(blocks, n_blk, dblk, s)
-                       : upload_blocks(blocks, n_blk, dblk, s)))
+  if ((st = use_static ? upload_blocks_raw(blocks, n_blk, dblk, s, sh)
+                       : upload_blocks(blocks, n_blk, dblk, s, &sh)))
     return st;
+  if ((st = extrapolate_uploaded(plain, t, images, H, W, dblk, R, pws, n_blk, prm, sel, coef,
+                                 g_loss, g_loss_ld, s)))
+    return st;
+  return degenerate_status(n_deg);
+}
+
+// The launches of extrapolate() once the descriptors are on the device.
+static se_status extrapolate_uploaded(bool plain, const se_tables* t, uint8_t* images, int H,
+                                      int W, se_block* dblk, float* R, char* pws, int n_blk,
+                                      se_params prm, int32_t* sel, float* coef, float* g_loss,
+                                      int32_t g_loss_ld, hipStream_t s) {
+  se_status st;
+  const int P = area_samples(t), ldR = r_row_len(t);
   GreedyArgs ga = greedy_args(t, R, ldR, images, H, W, dblk, n_blk, prm, sel, coef, g_loss,
                               g_loss_ld);
   if (!plain) {
@@ -861,6 +921,7 @@ size_t se_extrapolate_ondemand_ws_bytes(const se_basis* b, int32_t n_blk, int32_
   cv.take<float>(2 * n);
   cv.take<float>(2 * n * (size_t)(max_loss > 0 ? max_loss : 1));
   cv.take<int32_t>(1);
+  cv.take<int32_t>(n);
   cv.take<float>(tx_const_bytes(b->M, b->N, b->n_parts) / 4);
   cv.take<float>(ondemand_splitk_floats(b, n_blk));
   cv.take<uint16_t>(2 * K * P);      // split-BF16 dictionary and V rows (SE_ROWS_BF16X3)
@@ -909,8 +970,18 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* im
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),
                    [&](int32_t x, int32_t y) { return it[(size_t)x] > it[(size_t)y]; });
+  // device copies: the caller's tag replaced by the mark of blocks without an
+  // available sample
+  int n_deg = 0;
   std::vector<se_block> sorted((size_t)n_blk);
-  for (int i = 0; i < n_blk; ++i) sorted[(size_t)i] = blocks[order[(size_t)i]];
+  for (int i = 0; i < n_blk; ++i) {
+    se_block v = blocks[order[(size_t)i]];
+    const bool none = block_without_support(v, H, W, 1, b->M, b->N);
+    n_deg += none;
+    v.geom = none ? kBlockNoSupport : 0;
+    v.ld = 1;
+    sorted[(size_t)i] = v;
+  }
   std::vector<int> active((size_t)std::max(iters_max, 1), 0);
   for (int nu = 0; nu < iters_max; ++nu) {
     int c = 0;
@@ -933,6 +1004,8 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* im
   pl.g = cv.take<float>((size_t)2 * n * max_loss);
   pl.gc = pl.g + (size_t)n * max_loss;
   int32_t* flag = cv.take<int32_t>(1);
+  pl.deg = cv.take<int32_t>((size_t)n);
+  pl.n_degenerate = nullptr;
   float* tx = cv.take<float>(tx_const_bytes(b->M, b->N, b->n_parts) / 4);
   pl.splitk_floats = ondemand_splitk_floats(b, n);
   pl.splitk = cv.take<float>(pl.splitk_floats);
@@ -980,7 +1053,8 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* im
   pl.coef = coef;
   pl.g_loss = g_loss;
   pl.g_loss_ld = g_loss ? g_loss_ld : 0;
-  return ondemand_run(pl, s);
+  if ((st = ondemand_run(pl, s))) return st;
+  return degenerate_status(n_deg);
 }
 
 se_status se_extrapolate_batch(const se_tables* t, uint8_t* images, int32_t n_img, int32_t H,

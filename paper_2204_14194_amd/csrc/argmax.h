@@ -87,4 +87,24 @@ __device__ __forceinline__ void decode_key(uint64_t key, int K, int& u, float& r
   }
 }
 
+// Keys of the class form of the loop, whose positions follow the atom order
+// inside a class but not across classes: an exact tie is decided on the
+// original atom index, and the position travels in the low bits,
+//     |R| bits << 32  |  (0xFFFF - atom) << 16  |  sign << 15  |  position
+// (positions below 2^15).
+__device__ __forceinline__ uint64_t make_class_key(uint32_t vbits, int atom, int pos) {
+  return ((uint64_t)(vbits & 0x7FFFFFFFu) << 32) | ((uint32_t)(0xFFFF - atom) << 16) |
+         ((vbits >> 31) << 15) | (uint32_t)pos;
+}
+
+__device__ __forceinline__ void decode_class_key(uint64_t key, int& pos, float& rv) {
+  const uint32_t khi = (uint32_t)(key >> 32), klo = (uint32_t)key;
+  pos = (int)(klo & 0x7FFFu);
+  rv = __uint_as_float(khi | ((klo & 0x8000u) << 16));
+  if (khi == 0u) {
+    pos = 0;
+    rv = 0.0f;
+  }
+}
+
 }  // namespace sefase

@@ -27,29 +27,6 @@
 
 namespace sefase {
 
-struct ClassLayout {
-  int T, M, N, K, Kc;
-  int first_lo, kind_lo, first_hi, kind_hi;
-};
-
-// the row (2 i or 2 i + 1) of a 1-D transform of `kind` with parity `par`
-__device__ inline int parity_row(int kind, int i, int par) {
-  const int even = 2 * i;
-  const int p_even = kind == SE_PART_WHT2 ? (__popc(even) & 1) : 0;
-  return even + (p_even ^ par);
-}
-
-// original atom index of position p of the class order
-__device__ inline int class_orig(const ClassLayout& L, int p) {
-  const int c = p / L.Kc, r = p - c * L.Kc;
-  const int F = L.M * L.N / 4, Q = L.T * F, h = L.N / 2;
-  const int q = r / Q, s = r - q * Q;
-  const int kind = q ? L.kind_hi : L.kind_lo, first = q ? L.first_hi : L.first_lo;
-  const int kt = s / F, f = s - kt * F;
-  const int i1 = f / h, i2 = f - i1 * h;
-  return first + (kt * L.M + parity_row(kind, i1, c >> 1)) * L.N + parity_row(kind, i2, c & 1);
-}
-
 // flag = 1 if the weight pattern is not mirror-symmetric in the rows and
 // columns of every frame (bit for bit)
 __global__ void k_sym_check(const float* __restrict__ w, int T, int M, int N,
@@ -94,7 +71,7 @@ void launch_sym_check(const float* w, int T, int M, int N, int* flag, hipStream_
   hipLaunchKernelGGL(k_sym_check, dim3((P + 255) / 256), dim3(256), 0, s, w, T, M, N, flag);
 }
 
-se_status build_classes(se_tables* t, hipStream_t s) {
+ClassLayout class_layout(const se_tables* t) {
   ClassLayout L;
   L.T = area_frames(t->T);
   L.M = t->M;
@@ -108,6 +85,11 @@ se_status build_classes(se_tables* t, hipStream_t s) {
   L.kind_lo = lo.kind;
   L.first_hi = hi.first;
   L.kind_hi = hi.kind;
+  return L;
+}
+
+se_status build_classes(se_tables* t, hipStream_t s) {
+  const ClassLayout L = class_layout(t);
   hipLaunchKernelGGL(k_build_classes, dim3(t->K), dim3(256), 0, s, L, t->G, t->ldG, t->D, t->Gc,
                      L.Kc, reinterpret_cast<int2*>(t->cls));
   return check_launch("build_classes");

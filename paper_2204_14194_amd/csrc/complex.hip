@@ -62,6 +62,34 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy_c(GreedyArgs a, CplxArgs 
     gc[q] = 0.0f;
   }
 
+  // a block with nothing to extrapolate from (no available sample, or every
+  // atom of zero weighted norm): sel = -1, coefficients and model 0, the loss
+  // left as it is (as in the real loop)
+  {
+    bool deg = (d.geom & kBlockNoSupport) != 0;
+    if (!deg) {
+      bool nz = false;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) nz = nz || Rr[j][e] != 0.0f || Ri[j][e] != 0.0f;
+      if (!any_in_workgroup<WAVES>(nz)) {
+        bool dnz = false;
+        for (int j = 0; j < NJ; ++j)
+          for (int e = 0; e < 4; ++e) {
+            const int k = 4 * (j * T + t) + e;
+            if (k < K) dnz = dnz || a.D[k] != 0.0f;
+          }
+        deg = !any_in_workgroup<WAVES>(dnz);
+      }
+    }
+    if (deg) {
+      degenerate_outputs(a.sel, a.coef, 2, a.g_loss, a.g_loss_ld, a.iters, nloss, b, t, T,
+                         a.n_degenerate);
+      return;
+    }
+  }
+
   __shared__ uint64_t s_key[2][WAVES];
   __shared__ float s_val[2][WAVES][2];
   int par = 0;

@@ -37,9 +37,12 @@
 // With one wave per block the largest |R~| of each class is kept, per lane
 // and over the wave, across iterations: only the updated class is rescanned,
 // the class maxima are compared in scalar registers, and the winner is found
-// in the winning class (the same position the full scan finds: classes
-// occupy increasing positions, so the lowest class among equal maxima holds
-// the lowest position).
+// in the winning class.  Inside a class positions follow the atom order, so
+// the lowest position holding the maximum is its lowest atom; across classes
+// they do not, so an exact tie between classes (or any tie the position
+// order cannot settle: several lanes, several groups of one lane, several
+// waves) is decided by class_tie_key on the original atom indices, as eq. 18
+// with ties to the lowest index requires.
 //
 // Fixed-point rows (Q16, class form): the class rows are read as 16-bit
 // words q with 14 fraction bits and eq. 20 becomes R~ -= (tc 2^-14) q.  The
@@ -63,6 +66,56 @@ __device__ __forceinline__ float class_lane_max(const float (&R)[NJ][4]) {
   for (int j = C * NJC; j < (C + 1) * NJC; ++j)
     m = fmaxf(m, fmaxf(fmaxf(fabsf(R[j][0]), fabsf(R[j][1])), fmaxf(fabsf(R[j][2]), fabsf(R[j][3]))));
   return m;
+}
+
+// Class form: the classes (bit c) of the sweeps set in a mask of sweeps
+// (class c holds the sweeps c NJC .. c NJC + NJC - 1).
+template <int NJ, int NJC>
+__device__ __forceinline__ uint32_t class_mask(uint32_t sweeps) {
+  constexpr uint32_t one = (NJC >= 32) ? 0xFFFFFFFFu : ((1u << NJC) - 1u);
+  uint32_t m = 0u;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) m |= (uint32_t)((sweeps & (one << (c * NJC))) != 0u) << c;
+  return m;
+}
+template <int NJ, int NJC>
+__device__ __forceinline__ int classes_hit(uint32_t sweeps) {
+  return __builtin_popcount(class_mask<NJ, NJC>(sweeps));
+}
+
+// Exact ties of the class form: every lane's positions whose |R~| bits equal
+// Mb, keyed by their original atom index (class_orig), reduced over the wave
+// (eq. 18 with ties to the lowest atom index).  Rare: only bit-identical
+// scores take this path, so the positions are visited in a rolled loop.
+template <int NJ, int T>
+__device__ __forceinline__ uint64_t class_tie_key(const float (&R)[NJ][4], uint32_t Mb,
+                                                  const ClassLayout& cl, int t) {
+  static_assert(NJ * 4 <= 32, "one mask bit per value of a lane");
+  uint32_t mask = 0u;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      mask |= ((__float_as_uint(R[j][e]) & 0x7FFFFFFFu) == Mb ? 1u : 0u) << (4 * j + e);
+  int best = -1, bo = 0x7FFFFFFF;
+  for (uint32_t m = mask; m; m &= m - 1) {
+    const int bit = __builtin_ctz(m);
+    const int o = class_orig(cl, 4 * ((bit >> 2) * T + t) + (bit & 3));
+    if (o < bo) {
+      bo = o;
+      best = bit;
+    }
+  }
+  uint64_t mine = 0;
+  if (best >= 0) {
+    uint32_t vb = 0u;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) vb = 4 * j + e == best ? __float_as_uint(R[j][e]) : vb;
+    mine = make_class_key(vb, bo, 4 * ((best >> 2) * T + t) + (best & 3));
+  }
+  return wave_max_key((uint32_t)(mine >> 32), (uint32_t)mine);
 }
 
 // The iterations and the paste for block b of a workgroup of WAVES waves,
@@ -95,7 +148,38 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     gc[q] = 0.0f;
   }
 
+  // ---- a block with nothing to extrapolate from -----------------------------
+  // No available sample (marked by the host), or every atom of zero weighted
+  // norm (then every D_k and every R~_k is 0): eq. 17 is undefined for all
+  // atoms, no atom can be selected, and the block reports sel = -1 with its
+  // loss left as it is.  D is read only when every R~ is 0.
+  {
+    bool deg = (d.geom & kBlockNoSupport) != 0;
+    if (!deg) {
+      float m = 0.0f;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) m = fmaxf(m, fabsf(R[j][e]));
+      if (!any_in_workgroup<WAVES>(m != 0.0f)) {
+        bool dnz = false;
+        for (int j = 0; j < NJ; ++j)
+          for (int e = 0; e < 4; ++e) {
+            const int k = 4 * (j * T + t) + e;
+            if (k < K) dnz = dnz || (CLS ? __int_as_float(a.cls[k].y) : a.D[k]) != 0.0f;
+          }
+        deg = !any_in_workgroup<WAVES>(dnz);
+      }
+    }
+    if (deg) {
+      degenerate_outputs(a.sel, a.coef, 1, a.g_loss, a.g_loss_ld, a.iters, nloss, b, t, T,
+                         a.n_degenerate);
+      return;
+    }
+  }
+
   __shared__ uint64_t s_key[2][WAVES];
+  __shared__ uint64_t s_tie[WAVES];
   int par = 0;
   const float gamma = a.gamma;
 
@@ -118,14 +202,16 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     float rv = 0.0f;
     uint64_t key = 0;                          // every score zero: atom 0, value 0
     bool direct = WAVES == 1;
+    bool class_key = false;                    // key from class_tie_key
     if constexpr (INC) {
-      // ---- the largest class maximum (lowest class first), then its holder
+      // ---- the largest class maximum, then its holder
       const uint32_t Mb = max(max(wmc[0], wmc[1]), max(wmc[2], wmc[3]));
       if (Mb != 0u) {
         const int cw = wmc[0] == Mb ? 0 : wmc[1] == Mb ? 1 : wmc[2] == Mb ? 2 : 3;
         const float v = cw == 0 ? lmc[0] : cw == 1 ? lmc[1] : cw == 2 ? lmc[2] : lmc[3];
         const uint64_t holders = __builtin_amdgcn_ballot_w64(__float_as_uint(v) == Mb);
-        if (__builtin_popcountll(holders) == 1) {
+        const int nclass = (wmc[0] == Mb) + (wmc[1] == Mb) + (wmc[2] == Mb) + (wmc[3] == Mb);
+        if (nclass == 1 && __builtin_popcountll(holders) == 1) {
           // lane L alone: every lane finds its first position holding the
           // maximum in the class (vector selects), then L's position and
           // value are read
@@ -147,24 +233,10 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
           u = 4 * ((cw * NJC + (pos >> 2)) * T + L) + (pos & 3);
           rv = __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)lval, L));
         } else {
-          // exact ties across lanes: every lane's first maximum in the class
-          float bv = 0.0f;
-          int c = 0;
-#pragma unroll
-          for (int cc = 0; cc < 4; ++cc)
-            if (cc == cw) {
-#pragma unroll
-              for (int jj = 0; jj < NJC; ++jj)
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                  if (fabsf(R[cc * NJC + jj][e]) > fabsf(bv)) {
-                    bv = R[cc * NJC + jj][e];
-                    c = 4 * (cc * NJC + jj) + e;
-                  }
-            }
-          const uint64_t mine = make_key(bv, 4 * ((c >> 2) * T + t) + (c & 3));
-          key = wave_max_key((uint32_t)(mine >> 32), (uint32_t)mine);
+          // exact ties across lanes or between classes: the lowest atom index
+          key = class_tie_key<NJ, T>(R, Mb, a.cl, t);
           direct = false;
+          class_key = true;
         }
       }
     } else {
@@ -187,9 +259,13 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
       const int L = __builtin_ctzll(holders);
       const uint32_t Mb = __float_as_uint(M);
       int gsel = NJ - 1;
+      uint32_t hits = 0u;                      // the holder's groups at the maximum (class form)
 #pragma unroll
-      for (int j = NJ - 2; j >= 0; --j)
-        gsel = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(gm[j]), L) == Mb ? j : gsel;
+      for (int j = NJ - 1; j >= 0; --j) {
+        const bool hit = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(gm[j]), L) == Mb;
+        if (j < NJ - 1) gsel = hit ? j : gsel;
+        if (CLS) hits |= (uint32_t)hit << j;
+      }
       uint32_t r[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
@@ -208,7 +284,9 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
         u = 0;
         rv = 0.0f;
       }
-      if (WAVES > 1) key = make_key(rv, u);
+      // class form: groups of one lane may lie in different classes; groups
+      // at the maximum in two classes mark the key for the atom-index rule
+      if (WAVES > 1) key = make_key(rv, u) | (uint64_t)(CLS && classes_hit<NJ, NJC>(hits) > 1);
     } else if (M != 0.0f) {
       // exact ties across lanes: every lane's first maximum as a key
       float bv = 0.0f;
@@ -223,6 +301,21 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
           }
       const uint64_t mine = make_key(bv, 4 * ((c >> 2) * T + t) + (c & 3));
       key = wave_max_key((uint32_t)(mine >> 32), (uint32_t)mine);
+      if constexpr (CLS) {
+        // holders in two classes mark the key for the atom-index rule
+        const uint32_t Mb = __float_as_uint(M);
+        uint32_t lh = 0u;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            lh |= (uint32_t)((__float_as_uint(R[j][e]) & 0x7FFFFFFFu) == Mb) << j;
+        const uint32_t cm = class_mask<NJ, NJC>(lh);
+        int ncls = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) ncls += __builtin_amdgcn_ballot_w64((cm >> k) & 1u) != 0;
+        key |= (uint64_t)(ncls > 1);
+      }
       direct = false;
     }
     }
@@ -235,10 +328,44 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
         const uint64_t o = s_key[par][w];
         key = o > key ? o : key;
       }
+      if constexpr (CLS) {
+        // exact ties between waves, or marked inside the winning wave, are
+        // decided on the atom index (positions do not follow it across
+        // classes): every wave keys its candidates at the maximum again
+        const uint32_t kh = (uint32_t)(key >> 32);
+        uint32_t cm = 0u;                      // classes of the waves' winners at the maximum
+        bool marked = false;                   // a wave at the maximum holds it in two classes
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+          const uint64_t o = s_key[par][w];
+          if ((uint32_t)(o >> 32) == kh) {
+            const int ow = 0xFFFF - (int)((uint32_t)o >> 16);
+            cm |= 1u << (ow / a.cl.Kc);
+            marked = marked || (o & 1u);
+          }
+        }
+        if (kh != 0u && (marked || __builtin_popcount(cm) > 1)) {
+          const uint64_t k2 = class_tie_key<NJ, T>(R, kh, a.cl, t);
+          if (lane == 0) s_tie[wave] = k2;
+          __syncthreads();
+          key = s_tie[0];
+#pragma unroll
+          for (int w = 1; w < WAVES; ++w) {
+            const uint64_t o = s_tie[w];
+            key = o > key ? o : key;
+          }
+          class_key = true;
+        }
+      }
       par ^= 1;
     }
     // ---- the winner (wave-uniform, kept in scalar registers) ----------------
-    if (!direct) decode_key(key, K, u, rv);
+    if (!direct) {
+      if (CLS && class_key)
+        decode_class_key(key, u, rv);
+      else
+        decode_key(key, K, u, rv);
+    }
     u = __builtin_amdgcn_readfirstlane(u);
     rv = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rv)));
     const float tc = gamma * rv;              // coefficient of the unit-norm atom

@@ -100,6 +100,8 @@ struct OdArgs {
   float gamma;
   int32_t* sel;        // optional, caller order, stride iters_max
   float* coef;         // optional
+  int32_t* deg;        // n_blk: 1 for a block with nothing to extrapolate from
+  int32_t* n_degenerate;   // optional device counter of such blocks
 };
 
 __global__ __launch_bounds__(kOdThreads) void k_od_step(OdArgs a) {
@@ -110,6 +112,31 @@ __global__ __launch_bounds__(kOdThreads) void k_od_step(OdArgs a) {
   const float* D = a.D + (size_t)b * a.ld;
   const float* rows = a.rows + (size_t)b * a.ld;
   const bool upd = a.nu > 0;
+  const int ob = a.orig[b];
+  // a block with nothing to extrapolate from (no available sample, marked by
+  // the host, or every atom of zero weighted norm: D_b = 0 and R~ = 0
+  // everywhere) reports sel = -1 and a zero coefficient in every iteration
+  if (a.nu == 0) {
+    bool deg = (a.blk[b].geom & kBlockNoSupport) != 0;
+    if (!deg) {
+      bool nz = false;
+      for (int k = t; k < K; k += kOdThreads) nz = nz || R[k] != 0.0f || D[k] != 0.0f;
+      deg = !any_in_workgroup<kOdThreads / 64>(nz);
+    }
+    if (t == 0) {
+      a.deg[b] = deg;
+      if (deg && a.n_degenerate) atomicAdd(a.n_degenerate, 1);
+    }
+    if (deg) {
+      if (t == 0 && a.sel) a.sel[(size_t)ob * a.iters_max] = -1;
+      if (t == 0 && a.coef) a.coef[(size_t)ob * a.iters_max] = 0.0f;
+      return;
+    }
+  } else if (a.deg[b]) {
+    if (t == 0 && a.sel) a.sel[(size_t)ob * a.iters_max + a.nu] = -1;
+    if (t == 0 && a.coef) a.coef[(size_t)ob * a.iters_max + a.nu] = 0.0f;
+    return;
+  }
   float sc = 0.0f;
   if (upd) sc = a.st[2 * b] * a.st[2 * b + 1];   // gamma R~_u D_u: the eq. 20 factor
   // update with the previous row, then find this lane's first strict maximum
@@ -148,7 +175,6 @@ __global__ __launch_bounds__(kOdThreads) void k_od_step(OdArgs a) {
   const float Du = D[u];
   const float tc = a.gamma * rv;          // coefficient of the unit-norm atom
   const float c = tc * Du;                // eq. 19
-  const int ob = a.orig[b];
   if (t == 0) {
     a.st[2 * b] = tc;
     a.st[2 * b + 1] = Du;
@@ -191,14 +217,17 @@ __global__ __launch_bounds__(kOdThreads) void k_od_step(OdArgs a) {
 // paste the model into the image and (optionally) report it
 __global__ void k_od_finish(const DevBlock* __restrict__ blk, const int32_t* __restrict__ orig,
                             const float* __restrict__ g, int ldg, uint8_t* __restrict__ images,
-                            int H, int W, float* __restrict__ g_loss, int g_loss_ld) {
+                            int H, int W, float* __restrict__ g_loss, int g_loss_ld,
+                            const int32_t* __restrict__ deg) {
   const int b = blockIdx.x;
   const DevBlock d = blk[b];
   const int nloss = d.lh * d.lw;
   const int ob = orig[b];
+  const bool none = deg[b] != 0;           // no model: the loss is left as it is
   for (int q = threadIdx.x; q < nloss; q += blockDim.x) {
-    const float v = g[(size_t)b * ldg + q];
+    const float v = none ? 0.0f : g[(size_t)b * ldg + q];
     if (g_loss && q < g_loss_ld) g_loss[(size_t)ob * g_loss_ld + q] = v;
+    if (none) continue;
     const int my = q / d.lw, mx = q - my * d.lw;
     const int y = d.y0 + d.ly + my, x = d.x0 + d.lx + mx;
     if (y >= 0 && y < H && x >= 0 && x < W)
@@ -257,6 +286,8 @@ se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s) {
   a.gamma = pl.gamma;
   a.sel = pl.sel;
   a.coef = pl.coef;
+  a.deg = pl.deg;
+  a.n_degenerate = pl.n_degenerate;
   // atoms whose rows come from the dictionary product (all of them without
   // transform parts)
   const se_basis* bs = pl.basis;
@@ -297,7 +328,7 @@ se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s) {
     }
   }
   hipLaunchKernelGGL(k_od_finish, dim3(n), dim3(256), 0, s, pl.blk, pl.orig, pl.g, pl.ldg,
-                     pl.images, pl.H, pl.W, pl.g_loss, pl.g_loss_ld);
+                     pl.images, pl.H, pl.W, pl.g_loss, pl.g_loss_ld, pl.deg);
   return check_launch("od_finish");
 }
 

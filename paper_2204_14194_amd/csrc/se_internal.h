@@ -40,6 +40,25 @@ using DevBlock = se_block;
 
 // frames per area of a dictionary or table set (0 is read as 1)
 inline int area_frames(int T) { return T < 1 ? 1 : T; }
+
+// DevBlock.geom of the device copy: flags set when the descriptors are
+// uploaded (the caller's tag is not kept).
+constexpr int kBlockNoSupport = 1;   // no available sample in the area
+
+// A block whose area holds no available sample: the area lies wholly outside
+// the frames' H x W, or its loss box covers every frame of the area and
+// every one of its samples inside H x W.  Eq. 17 is then undefined for every
+// atom (every weighted norm is 0), so nothing can be extrapolated.
+__host__ __device__ inline bool block_without_support(const se_block& b, int H, int W, int T,
+                                                      int M, int N) {
+  const int y0 = b.y0 > 0 ? b.y0 : 0, y1 = b.y0 + M < H ? b.y0 + M : H;
+  const int x0 = b.x0 > 0 ? b.x0 : 0, x1 = b.x0 + N < W ? b.x0 + N : W;
+  if (y1 <= y0 || x1 <= x0) return true;
+  const int ld = b.ld < 1 ? 1 : b.ld;
+  if (b.lt > 0 || b.lt + ld < T) return false;
+  return b.y0 + b.ly <= y0 && b.y0 + b.ly + b.lh >= y1 && b.x0 + b.lx <= x0 &&
+         b.x0 + b.lx + b.lw >= x1;
+}
 // samples per area of a table set: T M N
 inline int area_samples(const se_tables* t) { return area_frames(t->T) * t->M * t->N; }
 // rows of the area as transformed: the T frames of M rows stacked (T M)
@@ -57,6 +76,58 @@ __device__ __forceinline__ LossSample loss_sample(const DevBlock& d, int i, int 
   const int my = r / d.lw, mx = r - my * d.lw;
   return LossSample{((d.lt + mt) * M + d.ly + my) * N + d.lx + mx, d.img + d.lt + mt,
                     d.y0 + d.ly + my, d.x0 + d.lx + mx};
+}
+
+// Class order of parity-class tables (classes.hip writes them): class
+// c = 2 pv + ph in blocks of Kc = K / 4 positions; in a class the two parts
+// in the order of their first atoms; in a part the atoms (kt, k1, k2) of the
+// class by (kt, k1 / 2, k2 / 2), row-major.
+struct ClassLayout {
+  int T, M, N, K, Kc;
+  int first_lo, kind_lo, first_hi, kind_hi;
+};
+
+// the row (2 i or 2 i + 1) of a 1-D transform of `kind` with parity `par`
+// (a Walsh-Hadamard row k in natural order has the parity of popcount(k))
+__device__ inline int parity_row(int kind, int i, int par) {
+  const int even = 2 * i;
+  const int p_even = kind == SE_PART_WHT2 ? (__popc(even) & 1) : 0;
+  return even + (p_even ^ par);
+}
+
+// original atom index of position p of the class order (increasing with p
+// inside each class, not across classes)
+__device__ inline int class_orig(const ClassLayout& L, int p) {
+  const int c = p / L.Kc, r = p - c * L.Kc;
+  const int F = L.M * L.N / 4, Q = L.T * F, h = L.N / 2;
+  const int q = r / Q, s = r - q * Q;
+  const int kind = q ? L.kind_hi : L.kind_lo, first = q ? L.first_hi : L.first_lo;
+  const int kt = s / F, f = s - kt * F;
+  const int i1 = f / h, i2 = f - i1 * h;
+  return first + (kt * L.M + parity_row(kind, i1, c >> 1)) * L.N + parity_row(kind, i2, c & 1);
+}
+
+// Predicate over a workgroup of WAVES waves (uniform result).
+template <int WAVES>
+__device__ __forceinline__ bool any_in_workgroup(bool p) {
+  if constexpr (WAVES == 1) return __builtin_amdgcn_ballot_w64(p) != 0;
+  else return __syncthreads_or(p) != 0;
+}
+
+// The outputs of a block with nothing to extrapolate from: every selection
+// -1, every coefficient and model value 0; its loss is not touched.  T
+// threads of the workgroup, thread t.
+__device__ inline void degenerate_outputs(int32_t* sel, float* coef, int n_coef, float* g_loss,
+                                          int g_loss_ld, int iters, int nloss, int b, int t,
+                                          int T, int32_t* counter) {
+  for (int i = t; i < iters; i += T)
+    if (sel) sel[(size_t)b * iters + i] = -1;
+  for (int i = t; i < n_coef * iters; i += T)
+    if (coef) coef[(size_t)b * n_coef * iters + i] = 0.0f;
+  const int ng = nloss < g_loss_ld ? nloss : g_loss_ld;
+  for (int i = t; i < ng; i += T)
+    if (g_loss) g_loss[(size_t)b * g_loss_ld + i] = 0.0f;
+  if (counter && t == 0) atomicAdd(counter, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -180,6 +251,10 @@ struct GreedyArgs {
   const int2* cls;
   // fixed-point class rows (Q1.14 words of Gc); non-NULL selects them
   const int16_t* Gq;
+  // the class order (exact ties between classes are decided by atom index)
+  ClassLayout cl;
+  // optional device counter of blocks with nothing to extrapolate from
+  int32_t* n_degenerate;
 };
 // ondemand.hip -- per-block weights, rows of C_b formed on demand
 struct OnDemandPlan {
@@ -220,6 +295,8 @@ struct OnDemandPlan {
   float* coef;
   float* g_loss;
   int g_loss_ld;
+  int32_t* deg;           // n_blk workspace: blocks with nothing to extrapolate from
+  int32_t* n_degenerate;  // optional device counter of those blocks
 };
 se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s);
 
@@ -229,6 +306,8 @@ bool classes_possible(const se_tables* t);
 // flag (device) = 1 if w is not mirror-symmetric in the rows and columns of
 // every frame
 void launch_sym_check(const float* w, int T, int M, int N, int* flag, hipStream_t s);
+// the class order of t's class tables
+ClassLayout class_layout(const se_tables* t);
 // t->Gc and t->cls from t->G and t->D
 se_status build_classes(se_tables* t, hipStream_t s);
 // t->Gq = round(t->Gc 2^14) (16-bit words, 14 fraction bits)

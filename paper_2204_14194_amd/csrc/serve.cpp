@@ -64,6 +64,7 @@ struct Req {
   se_params prm{};
   int slot = -1;
   int state = 0;   // 0 queued, 1 admitted, 2 launched, 3 done
+  int n_degenerate = 0;   // blocks with no available sample in their area
   se_result res{};
 };
 
@@ -283,6 +284,27 @@ static void group_request(Server* s, Req* r, Grouped& g) {
             }
           }
     }
+    // no available sample: the losses (disjoint) cover every in-frame
+    // sample of the area; such a block reports sel = -1, keeps its loss, and
+    // the request ends with SE_ENUMERIC
+    {
+      const int y0 = std::max(blk.y0, 0), y1 = std::min(blk.y0 + b.M, H);
+      const int x0 = std::max(blk.x0, 0), x1 = std::min(blk.x0 + b.N, W);
+      long long covered = 0;
+      std::vector<int> seen;
+      for (int cy = y0 / cs; cy <= (y1 - 1) / cs; ++cy)
+        for (int cx = x0 / cs; cx <= (x1 - 1) / cs; ++cx)
+          for (int j : cell[(size_t)cy * gw + cx]) seen.push_back(j);
+      std::sort(seen.begin(), seen.end());
+      seen.erase(std::unique(seen.begin(), seen.end()), seen.end());
+      for (int j : seen) {
+        const se_loss& o = L[j];
+        const int h = std::min(o.y + o.h, y1) - std::max(o.y, y0);
+        const int w = std::min(o.x + o.w, x1) - std::max(o.x, x0);
+        if (h > 0 && w > 0) covered += (long long)h * w;
+      }
+      if (covered >= (long long)(y1 - y0) * (x1 - x0)) r->n_degenerate++;
+    }
     if (iso) {
       g.iso[{PatternKey{l.basis, ly, lx, l.h, l.w}, r->prm.gamma, r->prm.iters}].push_back(blk);
       ++n_iso;
@@ -389,7 +411,7 @@ static se_status launch_batch(Server* s, std::vector<Req*>& reqs, Batch& bt) {
     rc = se_extrapolate_batch(&ct->t, s->slot_frames, nslot, H, W, blocks.data(),
                               (int)blocks.size(), prm, nullptr, nullptr, nullptr, 0, work,
                               work_bytes, st);
-    if (rc) return rc;
+    if (rc && rc != SE_ENUMERIC) return rc;   // blocks without support: per request below
   }
   // blocks with their own weights: per-block weights, then on-demand rows
   for (auto& e : g.own) {
@@ -408,7 +430,7 @@ static se_status launch_batch(Server* s, std::vector<Req*>& reqs, Batch& bt) {
     rc = se_extrapolate_ondemand(&b, w, s->slot_frames, nslot, H, W, blocks.data(), n, prm,
                                  e.second.second.data(), nullptr, nullptr, nullptr, 0, ows,
                                  ows_bytes, st);
-    if (rc) return rc;
+    if (rc && rc != SE_ENUMERIC) return rc;
   }
   for (Req* r : reqs) {
     if (hipMemcpyAsync(r->frame, s->slot_frames + (size_t)r->slot * fb, fb,
@@ -427,7 +449,7 @@ static void finish_batch(Server* s, Batch& bt) {
   const uint64_t t = now_ns();
   std::lock_guard<std::mutex> lk(s->mu);
   for (Req* r : bt.reqs) {
-    r->res.status = bt.status;
+    r->res.status = bt.status != SE_OK ? bt.status : r->n_degenerate ? SE_ENUMERIC : SE_OK;
     r->res.t_done_ns = t;
     r->state = 3;
     s->free_slots.push_back(r->slot);

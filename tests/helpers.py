@@ -54,19 +54,142 @@ def min_margin(res) -> float:
     return float(np.min(m))
 
 
-def _check_block(i, s, w, phi, cls, cache, gamma, iters, sel_i, g_i, loss_idx, got, tol, delta,
-                 pasted=None, q14=False):
-    """One block of oracle_check: returns (err, margin, agreed).  ``got``: the
-    pasted values of the loss samples selected by ``pasted`` (all if None).
-    ``q14``: the reference runs on the table's 16-bit fixed-point words."""
+# ---------------------------------------------------------------------------
+# The window within which FP32 rounding may reorder atoms
+# ---------------------------------------------------------------------------
+# The device runs Algorithm 3 in the unit-diagonal variables R~_k = D_k R_k
+# with the table G = D C D (|G_kl| <= 1).  Against the exact values along the
+# same selections its R~ differs by at most E(nu) at the start of iteration
+# nu, where (first order in the unit roundoff u = 2^-24)
+#   E(0)    = eps0: error of the initial projections (eq. 12); a scalar
+#             product over the area of unit-norm rows Y_k with x = sqrt(w) s
+#             rounds at most n_sum times, each error at most u |Y_k| . |x|,
+#             so eps0 = n_sum u ||x|| (Cauchy-Schwarz); split-BF16 operands
+#             add their own representation error, 3 * 2^-16 ||x||;
+#   E(nu+1) = E(nu) + u (s_nu + gamma p_nu) + gamma p_nu eps_G[u_nu]
+#             the fused multiply-add of eq. 20 rounds each R~_k once, to at
+#             most s_nu + gamma p_nu in magnitude (s_nu = max |R~|, p_nu =
+#             |R~_u| of the atom taken), and the row of G it reads is off by
+#             at most eps_G[u] per entry.
+# Errors carried into the coefficient gamma R~_u are not amplified by the
+# later updates in the span of the rows: there eq. 20 applies I - gamma Y_u
+# Y_u^T, which has norm at most 1 for 0 < gamma <= 1.  The bound is checked
+# against the device's own coefficients wherever they are compared (the
+# measured error of R~_u at each iteration must stay below E).
+# Two atoms whose exact scores differ by more than 2 E(nu) are therefore never
+# swapped by the device; a selection that differs from the oracle's must come
+# from a pair closer than that.
+U32 = 2.0 ** -24
+
+
+def fp32_sum_roundings(P: int, rows: int, N: int) -> int:
+    """Roundings along the longest path of one FP32 scalar product over P
+    samples as the library forms it (matrix-core GEMMs sum stages of 32
+    samples into fresh accumulators and add each stage to the running sum;
+    separable transforms sum `rows` then N terms), plus the roundings of
+    the scaled operands D sqrt(w) phi and sqrt(w) s."""
+    return max(rows + N, 32 + -(-P // 32)) + 4
+
+
+def error_bound(res, gamma: float, eps0: float, eps_G, cplx: bool = False) -> np.ndarray:
+    """E(nu) for nu = 0 .. I-1 along the selections of ``res`` (a free or a
+    forced oracle run): see the derivation above.  ``eps_G``: a scalar or a
+    per-atom array (the error of that atom's row of G).  A complex R~ rounds
+    its real and imaginary parts separately (twice the increment)."""
+    s = np.sqrt(res.best)
+    p = np.sqrt(res.picked)
+    eg = eps_G[res.sel] if np.ndim(eps_G) else float(eps_G)
+    inc = U32 * (s + gamma * p) + gamma * p * eg
+    if cplx:
+        inc = 2.0 * inc
+    return eps0 + np.concatenate([[0.0], np.cumsum(inc)[:-1]])
+
+
+class Arith:
+    """What the device computed in, for the window: the projections'
+    precision and the error of each table row (measured from the device's
+    table where one exists, else the FP32 bound of fp32_sum_roundings)."""
+
+    def __init__(self, proj_bf16x3: bool = False, eps_G=None, eps_D=None, cplx: bool = False):
+        self.proj_bf16x3 = proj_bf16x3
+        self.eps_G = eps_G
+        self.eps_D = eps_D
+        self.cplx = cplx
+
+
+def table_errors(t, C, D):
+    """Per-atom error of the device's unit-diagonal table rows and of its D
+    against the oracle's tables C, D (eq. 16, 17) of the same pattern.  For
+    fixed-point class rows use quant_table_errors."""
+    K = t.K
+    Gd = t.G.cpu().numpy()[:, :K].astype(np.float64)
+    if t.G_im is not None:
+        Gd = Gd + 1j * t.G_im.cpu().numpy()[:, :K].astype(np.float64)
+    Gref = D[:, None] * C * D[None, :]
+    eps_G = np.abs(Gd - Gref).max(axis=1)
+    eps_D = np.abs(t.D.cpu().numpy().astype(np.float64) - D)
+    return eps_G, eps_D
+
+
+def quant_table_errors(t, C, D):
+    """Per-atom error of the device's fixed-point class rows against the
+    oracle's own words of the same pattern (the reference of the fixed-point
+    route): row p of Gq holds the words of atom cls[p] against the atoms of
+    its class, in class order."""
+    K = t.K
+    Kc = K // 4
+    Gq = t.Gq.cpu().numpy().astype(np.int64)
+    orig = t.cls.cpu().numpy()[:, 0].astype(np.int64)
+    ref = oracle.quantise_table(oracle.unit_table(C, D)).astype(np.int64)
+    eps_G = np.zeros(K)
+    for c in range(4):
+        pos = np.arange(c * Kc, (c + 1) * Kc)
+        a = orig[pos]
+        diff = np.abs(Gq[pos] - ref[np.ix_(a, a)]).max(axis=1)
+        eps_G[a] = diff * 2.0 ** -14
+    eps_D = np.abs(t.D.cpu().numpy().astype(np.float64) - D)
+    return eps_G, eps_D
+
+
+def default_arith(tables, phi, P) -> Arith:
+    """Split-BF16 projections when the tables are SE_BF16X3 and some atoms
+    lie outside the declared transform parts (those take the GEMM)."""
+    dense = tables is not None and tables.K > len(tables.parts) * P
+    return Arith(proj_bf16x3=tables is not None and tables.precision == 1 and dense,
+                 cplx=np.iscomplexobj(phi))
+
+
+def _eps0(arith: Arith, s, w, P, rows, N):
+    x = np.linalg.norm(np.sqrt(w) * np.abs(s))
+    e = fp32_sum_roundings(P, rows, N) * U32 * x
+    if arith.proj_bf16x3:
+        e += 3.0 * 2.0 ** -16 * x
+    return e
+
+
+def _check_block(i, s, w, phi, cls, cache, gamma, iters, sel_i, g_i, loss_idx, got, tol,
+                 arith, shape, pasted=None, q14=False, coef_i=None, tables=None):
+    """One block of oracle_check: returns a dict (err, margin, agreed,
+    divergence info, bound use).  ``got``: the pasted values of the loss
+    samples selected by ``pasted`` (all if None).  ``q14``: the reference
+    runs on the table's 16-bit fixed-point words."""
     key = w.tobytes()
     if key not in cache:
-        C, D = oracle.table_generation(phi, w)
+        if tables is None and not q14:
+            C = oracle.TableColumns(phi, w)     # only the columns the loop reads
+            D = C.D
+        else:
+            C, D = oracle.table_generation(phi, w)
         Gq = None
         if q14:
             Gq = oracle.quantise_table(oracle.unit_table(C, D)).astype(np.float64) * 2.0 ** -14
-        cache[key] = (C, D, Gq)
-    C, D, Gq = cache[key]
+        eps_G, eps_D = arith.eps_G, arith.eps_D
+        if tables is not None:
+            eps_G, eps_D = (quant_table_errors if q14 else table_errors)(tables, C, D)
+        if eps_G is None:
+            eps_G = fp32_sum_roundings(*shape) * U32
+        cache[key] = (C, D, Gq, eps_G, eps_D)
+    C, D, Gq, eps_G, eps_D = cache[key]
 
     def run(forced=None):
         if q14:
@@ -74,48 +197,109 @@ def _check_block(i, s, w, phi, cls, cache, gamma, iters, sel_i, g_i, loss_idx, g
         return oracle.fase(s, w, phi, C, D, gamma, iters, cls, forced=forced)
     res = run()
     margin = min_margin(res)
+    eps0 = _eps0(arith, s, w, *shape)
     agreed = compare_selections(sel_i, res.sel, cls)
+    info = dict(err=0.0, margin=margin, agreed=agreed, first=None, gap=None, window=None,
+                dg_free=None, bound_use=None)
     if agreed:
         ref = res
     else:
+        first = int(np.nonzero(cls[np.asarray(sel_i)] != cls[res.sel])[0][0])
         ref = run(forced=sel_i)
-        ok = np.sqrt(ref.picked) >= np.sqrt(ref.best) * (1.0 - delta)
-        assert ok.all(), (f"block {i}: iteration {int(np.argmin(ok))} picked an atom "
-                          f"outside the near-tie window")
+        E = error_bound(ref, gamma, eps0, eps_G, arith.cplx)
+        sb, sp = np.sqrt(ref.best), np.sqrt(ref.picked)
+        ok = sb - sp <= 2.0 * E
+        bad = int(np.argmin(ok))
+        assert ok.all(), (f"block {i}: iteration {bad} took an atom {(sb - sp)[bad]:.3g} below "
+                          f"the best score {sb[bad]:.6g}, outside the derived window "
+                          f"2E = {2 * E[bad]:.3g}")
+        # the oracle's own run, not the one along the device's picks
+        gfree = np.real(res.g)[loss_idx]
+        info.update(first=first, gap=float((sb[first] - sp[first]) / sb[first]),
+                    window=float(2 * E[first] / sb[first]),
+                    dg_free=float(np.abs(g_i[:len(loss_idx)].astype(np.float64) - gfree).max()))
+    E = error_bound(ref, gamma, eps0, eps_G, arith.cplx)
+    if coef_i is not None and eps_D is not None and not arith.cplx:
+        # the bound against the device's coefficients gamma R~_u D_u: the
+        # measured error of R~_u must stay inside E (D's own error and the
+        # product's rounding accounted for)
+        u = ref.sel
+        Rt = np.sqrt(ref.picked)
+        cdev = np.asarray(coef_i[:iters], dtype=np.float64)
+        allowed = gamma * (D[u] * E + Rt * eps_D[u]) + 2 * U32 * np.abs(ref.coef) + 1e-30
+        use = np.abs(cdev - ref.coef) / allowed
+        info["bound_use"] = float(use.max())
+        assert use.max() <= 1.0, (f"block {i}: coefficient of iteration {int(np.argmax(use))} "
+                                  f"off by {use.max():.3g} times the derived bound")
     # the model's real part replaces the loss (a complex dictionary gives a
     # complex model)
     gref = np.real(ref.g)[loss_idx]
     n = len(loss_idx)
     err = float(np.abs(g_i[:n].astype(np.float64) - gref).max())
     assert err <= tol, f"block {i}: max |g - g_oracle| = {err}"
+    info["err"] = err
     if pasted is not None:
         gref = gref[pasted]
     q_ref = np.clip(np.rint(gref), 0, 255)
     near = np.abs(np.abs(gref - np.floor(gref)) - 0.5) < tol
     assert ((got.astype(np.float64) == q_ref) | near).all(), f"block {i}: pasted pixels differ"
-    return err, margin, agreed
+    return info
+
+
+def _summary(infos, idx):
+    div = [(i, f) for i, f in zip(idx, infos) if not f["agreed"]]
+    uses = [f["bound_use"] for f in infos if f["bound_use"] is not None]
+    return dict(worst=max([f["err"] for f in infos] + [0.0]),
+                margin=min([f["margin"] for f in infos] + [np.inf]),
+                agree=sum(f["agreed"] for f in infos), n=len(infos),
+                divergences=[dict(block=int(i), first=f["first"], gap=f["gap"],
+                                  window=f["window"], dg_free=f["dg_free"]) for i, f in div],
+                bound_use=max(uses) if uses else None)
+
+
+def describe(st) -> str:
+    """One line for a test log: agreement, errors, margins and divergences."""
+    txt = (f"identical selections {st['agree']}/{st['n']}, max|dg|={st['worst']:.3g}, "
+           f"min tie margin={st['margin']:.3g}")
+    if st["bound_use"] is not None:
+        txt += f", coefficient error <= {st['bound_use']:.2g} of the bound"
+    for d in st["divergences"]:
+        txt += (f"; block {d['block']} leaves the oracle's path at iteration {d['first']} "
+                f"(oracle gap {d['gap']:.2g} < window {d['window']:.2g}, "
+                f"|g - g_oracle free run| = {d['dg_free']:.3g})")
+    return txt
 
 
 def oracle_check(images, blocks, phi, M, N, rho_hat, gamma, iters, sel, g, out,
-                 sample=None, tol=1e-3, delta=1e-3, q14=False):
+                 sample=None, tol=1e-3, q14=False, coef=None, tables=None, arith=None,
+                 lost=None):
     """Compare device results with the FP64 oracle (Algorithm 3, which the CPU
     pins tie to Algorithm 1) block by block.
 
     Where the device's selections equal the oracle's (modulo classes of
     parallel atoms) the model over the loss must agree within ``tol``.  Where
     they differ, the difference must come from a near-tie: the oracle is
-    re-run along the device's selections and every device pick must score
-    within the relative window ``delta`` of that iteration's best score; the
-    model must then agree with that run within ``tol``.  In both cases the
-    pasted pixels are the rounded model.  ``q14``: the oracle runs Algorithm 3
-    on the 16-bit fixed-point words of its own table (oracle.fase_unit).
-    Returns dict(worst, margin, agree, n)."""
+    re-run along the device's selections, and at every iteration the atom
+    the device took must score within the derived window 2 E(nu) of that
+    iteration's best (error_bound); the model must then agree with that run
+    within ``tol``, and its distance to the oracle's own run is reported.  In
+    both cases the pasted pixels are the rounded model.  ``tables``: the
+    device tables the blocks used (their measured row errors enter E; with
+    ``coef`` the device's coefficients are held to the bound as well).
+    ``q14``: the oracle runs Algorithm 3 on the 16-bit fixed-point words of
+    its own table (oracle.fase_unit).  ``arith``: an Arith for routes
+    without device tables.  ``iters``: one count, or one per block.
+    ``lost``: the lost mask of the images when it holds more losses than
+    ``blocks`` (default: exactly the losses of ``blocks``).  Returns
+    dict(worst, margin, agree, n, divergences, bound_use)."""
     n_img, H, W = images.shape
-    lost = np.stack([synth.lost_mask(H, W, blocks, i) for i in range(n_img)])
+    if lost is None:
+        lost = np.stack([synth.lost_mask(H, W, blocks, i) for i in range(n_img)])
     cls = classes_of(phi)
     idx = list(range(len(blocks))) if sample is None else [int(i) for i in sample]
+    arith = arith or default_arith(tables, phi, M * N)
     cache = {}
-    worst, margin, agree = 0.0, np.inf, 0
+    infos = []
     for i in idx:
         b = blocks[i]
         s, sup = oracle.area_signal(images[b.img], lost[b.img], b.y0, b.x0, M, N)
@@ -124,14 +308,15 @@ def oracle_check(images, blocks, phi, M, N, rho_hat, gamma, iters, sel, g, out,
                     + np.arange(N)[None, b.lx:b.lx + b.lw]).reshape(-1)
         y, x = b.y0 + b.ly, b.x0 + b.lx
         got = out[b.img, y:y + b.lh, x:x + b.lw].reshape(-1)
-        err, mg, ok = _check_block(i, s, w, phi, cls, cache, gamma, iters, sel[i], g[i],
-                                   loss_idx, got, tol, delta, q14=q14)
-        worst, margin, agree = max(worst, err), min(margin, mg), agree + int(ok)
-    return dict(worst=worst, margin=margin, agree=agree, n=len(idx))
+        I = int(iters) if np.ndim(iters) == 0 else int(iters[i])
+        infos.append(_check_block(i, s, w, phi, cls, cache, gamma, I, sel[i][:I], g[i],
+                                  loss_idx, got, tol, arith, (M * N, M, N), q14=q14,
+                                  coef_i=None if coef is None else coef[i], tables=tables))
+    return _summary(infos, idx)
 
 
 def oracle_check_video(frames, blocks, phi, T, M, N, rho_hat, gamma, iters, sel, g, out,
-                       sample=None, tol=1e-3, delta=1e-3, q14=False):
+                       sample=None, tol=1e-3, q14=False, coef=None, tables=None, arith=None):
     """oracle_check for areas of T consecutive frames (blocks with lt, ld;
     the model over the loss box in frames x rows x columns order).  Loss
     samples outside the frames are compared in the model only."""
@@ -139,8 +324,9 @@ def oracle_check_video(frames, blocks, phi, T, M, N, rho_hat, gamma, iters, sel,
     lost = synth.video_lost_mask(F, H, W, blocks)
     cls = classes_of(phi)
     idx = list(range(len(blocks))) if sample is None else [int(i) for i in sample]
+    arith = arith or default_arith(tables, phi, T * M * N)
     cache = {}
-    worst, margin, agree = 0.0, np.inf, 0
+    infos = []
     for i in idx:
         b = blocks[i]
         s, sup = oracle.volume_signal(frames, lost, b.img, b.y0, b.x0, T, M, N)
@@ -153,7 +339,8 @@ def oracle_check_video(frames, blocks, phi, T, M, N, rho_hat, gamma, iters, sel,
         xx = (b.x0 + nn).reshape(-1)
         inside = (ff >= 0) & (ff < F) & (yy >= 0) & (yy < H) & (xx >= 0) & (xx < W)
         got = out[ff[inside], yy[inside], xx[inside]]
-        err, mg, ok = _check_block(i, s, w, phi, cls, cache, gamma, iters, sel[i], g[i],
-                                   loss_idx, got, tol, delta, pasted=inside, q14=q14)
-        worst, margin, agree = max(worst, err), min(margin, mg), agree + int(ok)
-    return dict(worst=worst, margin=margin, agree=agree, n=len(idx))
+        infos.append(_check_block(i, s, w, phi, cls, cache, gamma, iters, sel[i], g[i],
+                                  loss_idx, got, tol, arith, (T * M * N, T * M, N),
+                                  pasted=inside, q14=q14,
+                                  coef_i=None if coef is None else coef[i], tables=tables))
+    return _summary(infos, idx)

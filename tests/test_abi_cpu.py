@@ -346,3 +346,32 @@ def test_rejects_overlapping_losses_on_host():
     r = L.se_extrapolate_ondemand(C.byref(bas), fake, fake, 2, 100, 100, blk, 2, prm, None,
                                   None, None, None, 0, fake, 16, None)
     assert r == B.SE_EINVAL and b"overlap" in L.se_last_error()
+
+
+def test_blocks_without_support_are_reported_on_host():
+    """Blocks whose area holds no available sample (eq. 17 undefined for every
+    atom): an area wholly outside the image, and a loss covering every
+    in-image sample of its area.  The host finds them before any launch; with
+    every block such and no output requested there is nothing to compute and
+    the call returns SE_ENUMERIC without touching a device."""
+    L = B.lib()
+    t = _tables_struct(K=64, M=8, N=8)
+    fake = C.c_void_p(0x1000)
+    prm = B.se_params(0.5, 10, 0)
+    blk = (B.se_block * 3)(B.se_block(0, 40, 0, 2, 2, 4, 4, 0),    # area below the image
+                           B.se_block(0, -8, -8, 2, 2, 4, 4, 0),   # above and left of it
+                           B.se_block(0, -4, -4, 4, 4, 4, 4, 0))   # loss = the in-image quarter
+    r = L.se_extrapolate_batch(C.byref(t), fake, 1, 32, 32, blk, 3, prm, None, None, None, 0,
+                               fake, 1 << 20, None)
+    assert r == B.SE_ENUMERIC
+    assert b"3 block(s) have no available sample" in L.se_last_error()
+    r = L.se_extrapolate_batch_static(C.byref(t), fake, 1, 32, 32, blk, 3, prm, None, None,
+                                      None, 0, None)
+    assert r == B.SE_ENUMERIC
+    # one sample of the last area left outside its loss: not such a block
+    # (the call would then launch, which needs a device: only the message of
+    # the first two is checked through a call with two blocks)
+    r = L.se_extrapolate_batch(C.byref(t), fake, 1, 32, 32, blk, 2, prm, None, None, None, 0,
+                               fake, 1 << 20, None)
+    assert r == B.SE_ENUMERIC
+    assert b"2 block(s)" in L.se_last_error()

@@ -7,10 +7,11 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 from paper_2204_14194_amd import binding as B
 from paper_2204_14194_amd import synth
 
-from helpers import oracle_check
+from helpers import describe, oracle_check
 from test_gpu_parity import TOL_FP32, dev, say, shared_tables, upload_phi
 
 pytestmark = pytest.mark.gpu
@@ -87,9 +88,9 @@ def test_class_route_matches_full_rows_and_oracle():
     assert dg <= TOL_FP32
     sel, coef, g, img = out["class"]
     st = oracle_check(d["images"], d["blocks"], phi_np, 32, 32, 0.8, 0.5, 100, sel, g, img,
-                      tol=TOL_FP32)
-    print(f"class route vs oracle: identical selections {st['agree']}/{st['n']}, "
-          f"max|dg|={st['worst']:.3g}")
+                      tol=TOL_FP32, coef=coef, tables=tc)
+    print(f"class route vs oracle: {describe(st)}")
+    assert st["agree"] == st["n"]
     assert st["worst"] <= TOL_FP32
 
 
@@ -184,3 +185,43 @@ def test_class_route_shapes_agree():
             B.tune_clear()
     for name, x, y in zip(("sel", "coef", "g_loss", "image"), *got):
         assert torch.equal(x, y), f"{name} differs between the loop shapes"
+
+
+@pytest.mark.parametrize("M,N", [(64, 16), (64, 64)])
+def test_class_route_exact_tie_between_classes(M, N):
+    """An exact tie between atoms of two parity classes must go to the lower
+    atom index (eq. 18 with ties to the lowest k), although the class order
+    puts the other atom first.  Walsh-Hadamard atoms (1, 3) (class 2) and
+    (3, 1) (class 1) of a 64 x 16 area (one wave per block) and of a 64 x 64
+    area (four waves): with 0/1 weights and a signal built from the two
+    atoms, every product and sum of the projections and of their table rows
+    is a dyadic number computed exactly on both sides, so the scores are
+    bit-identical on the device as in the oracle."""
+    say(f"class route, exact tie between classes: {M}x{N} area, WHT atoms (1,3) and (3,1)")
+    phi = synth.round_to_f32(synth.dictionary(M, N, ("dct", "wht")))
+    P = M * N
+    a, b = P + 1 * N + 3, P + 3 * N + 1            # classes 2 and 1 (lower position: b)
+    sup = np.ones((M, N), bool)
+    ly, lx = M // 2 - 8, N // 2 - 4
+    sup[ly:ly + 16, lx:lx + 8] = False
+    w = sup.reshape(-1).astype(np.float64)
+    va, vb = np.sign(phi[a]), np.sign(phi[b])
+    s = (96 + 40 * (va + vb)) * w
+    img = s.reshape(1, M, N).astype(np.uint8)
+    t = B.weighted_gram(upload_phi(phi), torch.from_numpy(w.astype(np.float32)).to(dev()), M, N,
+                        parts=synth.dictionary_parts(M, N, ("dct", "wht")))
+    assert t.n_classes == 4
+    blk = [synth.Block(0, 0, 0, ly, lx, 16, 8)]
+    img_d = torch.from_numpy(img).to(dev())
+    sel, coef, g = B.extrapolate_batch(t, img_d, blk, 0.5, 8)
+    torch.cuda.synchronize()
+    sel = sel.cpu().numpy()[0]
+    phi64 = phi.astype(np.float64)
+    C, D = oracle.table_generation(phi64, w)
+    res = oracle.fase(s, w, phi64, C, D, 0.5, 8, oracle.duplicate_classes(phi64))
+    ties = np.nonzero(res.second == res.best)[0]
+    print(f"device {sel.tolist()}, oracle {res.sel.tolist()}, exact ties at {ties.tolist()}")
+    assert res.sel[2] == a and res.best[2] == res.second[2]    # the tie the test is built on
+    np.testing.assert_array_equal(sel, res.sel)
+    gref = res.g.reshape(M, N)[ly:ly + 16, lx:lx + 8].reshape(-1)
+    assert np.abs(g.cpu().numpy()[0, :128] - gref).max() <= TOL_FP32

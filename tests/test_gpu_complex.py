@@ -10,7 +10,7 @@ import oracle
 from paper_2204_14194_amd import binding as B
 from paper_2204_14194_amd import synth
 
-from helpers import oracle_check
+from helpers import describe, oracle_check
 from test_gpu_parity import TOL_FP32, dev, say, upload_phi
 
 pytestmark = pytest.mark.gpu
@@ -102,9 +102,8 @@ def test_complex_batch_parity(parts, n_img):
     sel, coef, g, out = _batch(t, d["images"], d["blocks"], 100)
     assert coef.shape[1] == 200
     st = oracle_check(d["images"], d["blocks"], phi, 32, 32, 0.8, 0.5, 100, sel, g, out,
-                      tol=TOL_FP32)
-    print(f"identical selections {st['agree']}/{st['n']}, max|dg|={st['worst']:.3g}, "
-          f"min margin {st['margin']:.2g}")
+                      tol=TOL_FP32, tables=t)
+    print(describe(st))
     assert st["worst"] <= TOL_FP32
 
 

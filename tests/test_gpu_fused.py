@@ -104,7 +104,7 @@ def test_fused_border_areas_and_oracle():
     sel, coef, g, out = (x.numpy() for x in got)
     check_against_oracle(images, [blocks[i] for i in inner], phi_np.astype(np.float64), M, N,
                          0.8, 0.5, 100, sel[inner], coef[inner], g[inner], out,
-                         tol=TOL_FP32)
+                         tol=TOL_FP32, tables=t)
 
 
 @pytest.mark.parametrize("shape", [(4, 32), (8, 16)])

@@ -13,7 +13,7 @@ import oracle
 from paper_2204_14194_amd import binding as B
 from paper_2204_14194_amd import synth
 
-from helpers import oracle_check, oracle_check_video
+from helpers import describe, oracle_check, oracle_check_video
 from test_gpu_classes import expected_class_order, _bucket
 from test_gpu_parity import dev, say, shared_tables, upload_phi
 from test_gpu_video import _tables as video_tables
@@ -90,9 +90,8 @@ def test_fixed_point_route_matches_oracle():
                             parts=d["tx_parts"], fixed_point=True)
     sel, coef, g, img = [x.numpy() for x in _run(t, d["images"], d["blocks"], 100, True)]
     st = oracle_check(d["images"], d["blocks"], phi32, 32, 32, 0.8, 0.5, 100, sel, g, img,
-                      tol=TOL_Q14, q14=True)
-    print(f"fixed-point route vs oracle on words: identical selections {st['agree']}/{st['n']}, "
-          f"max|dg|={st['worst']:.3g}")
+                      tol=TOL_Q14, q14=True, coef=coef, tables=t)
+    print(f"fixed-point route vs oracle on words: {describe(st)}")
     assert st["worst"] <= TOL_Q14
     # context: how far the words move the model from the FP32 rows
     _, _, gf, _ = [x.numpy() for x in _run(t, d["images"], d["blocks"], 100, False)]
@@ -180,9 +179,8 @@ def test_fixed_point_video_areas():
     sel, _, g, out = [x.numpy() for x in q]
     sample = np.random.default_rng(1).choice(len(d["blocks"]), 24, replace=False)
     st = oracle_check_video(d["frames"], d["blocks"], phi, T, M, N, 0.8, 0.5, 100, sel, g, out,
-                            sample=sample, tol=TOL_Q14, q14=True)
-    print(f"video fixed-point route vs oracle on words: identical selections "
-          f"{st['agree']}/{st['n']}, max|dg|={st['worst']:.3g}")
+                            sample=sample, tol=TOL_Q14, q14=True, tables=t)
+    print(f"video fixed-point route vs oracle on words: {describe(st)}")
     assert st["worst"] <= TOL_Q14
 
 

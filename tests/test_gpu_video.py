@@ -11,7 +11,7 @@ import oracle
 from paper_2204_14194_amd import binding as B
 from paper_2204_14194_amd import synth
 
-from helpers import oracle_check_video
+from helpers import describe, oracle_check_video
 from test_gpu_parity import TOL_FP32, dev, say, upload_phi
 
 pytestmark = pytest.mark.gpu
@@ -86,9 +86,8 @@ def test_video_batch_parity():
     t = _tables(phi, d["frames"], d["blocks"], T, M, N)
     sel, coef, g, out = _batch(t, d["frames"], d["blocks"], 100)
     st = oracle_check_video(d["frames"], d["blocks"], phi, T, M, N, 0.8, 0.5, 100, sel, g, out,
-                            tol=TOL_FP32)
-    print(f"identical selections {st['agree']}/{st['n']}, max|dg|={st['worst']:.3g}, "
-          f"min margin {st['margin']:.2g}")
+                            tol=TOL_FP32, coef=coef, tables=t)
+    print(describe(st))
     assert st["worst"] <= TOL_FP32
     # frames without losses are untouched
     lost = synth.video_lost_mask(*d["frames"].shape, d["blocks"])
@@ -136,8 +135,8 @@ def test_video_routes_agree():
     tb = _tables(phi, d["frames"], blocks, T, M, N, precision=B.SE_BF16X3)
     selb, _, gb, outb = _batch(tb, d["frames"], blocks, 60)
     st = oracle_check_video(d["frames"], blocks, phi, T, M, N, 0.8, 0.5, 60, selb, gb, outb,
-                            sample=range(0, n, 6), tol=TOL_BF16X3)
-    print(f"bf16x3: identical selections {st['agree']}/{st['n']}, max|dg|={st['worst']:.3g}")
+                            sample=range(0, n, 6), tol=TOL_BF16X3, tables=tb)
+    print(f"bf16x3: {describe(st)}")
 
 
 def test_video_loss_boxes_and_border_areas():
@@ -169,7 +168,7 @@ def test_video_loss_boxes_and_border_areas():
     g_all = np.stack([np.pad(x, (0, gl - len(x))) for x in gs])
     st = oracle_check_video(frames, blocks, phi, T, M, N, 0.8, 0.5, 40, np.stack(sels), g_all,
                             out, tol=TOL_FP32)
-    print(f"identical selections {st['agree']}/{st['n']}, max|dg|={st['worst']:.3g}")
+    print(describe(st))
     assert st["worst"] <= TOL_FP32
     # samples outside every loss are untouched
     keep = synth.video_lost_mask(F, H, W, blocks) == 0
@@ -214,8 +213,8 @@ def test_video_transform_parts(precision):
     tol = TOL_FP32 if precision == B.SE_FP32 else TOL_BF16X3
     sample = None if precision == B.SE_FP32 else range(0, n, 8)
     st = oracle_check_video(d["frames"], blocks, phi, T, M, N, 0.8, 0.5, 100, sel, g, out,
-                            sample=sample, tol=tol)
-    print(f"identical selections {st['agree']}/{st['n']}, max|dg|={st['worst']:.3g}")
+                            sample=sample, tol=tol, tables=tp)
+    print(describe(st))
     assert st["worst"] <= tol
 
 
@@ -319,7 +318,6 @@ def test_video_class_tables():
           f"{int(np.all(sel == self_, axis=1).sum())}/{len(sel)}, max|dg|={dg:.3g}")
     assert dg <= TOL_FP32
     st = oracle_check_video(d["frames"], d["blocks"], phi, T, M, N, 0.8, 0.5, 100, sel, g, out,
-                            tol=TOL_FP32)
-    print(f"class route vs oracle: identical selections {st['agree']}/{st['n']}, "
-          f"max|dg|={st['worst']:.3g}")
+                            tol=TOL_FP32, tables=tc)
+    print(f"class route vs oracle: {describe(st)}")
     assert st["worst"] <= TOL_FP32

@@ -323,6 +323,34 @@ def test_table_properties_and_bruteforce_entries():
         assert C[k, l] == pytest.approx(ref, rel=1e-12)
 
 
+@pytest.mark.parametrize("cplx", [False, True])
+def test_table_columns_on_demand(cplx):
+    """Columns of C formed when Algorithm 3 reads them: brute-force entries
+    of eq. 16 (with the conjugated atom), D of eq. 17 from the brute-force
+    diagonal, and Algorithm 3 run on them equal to Algorithm 1 (which uses
+    no table) in selections, coefficients and model."""
+    if cplx:
+        phi, s, w = _complex_case(5, 6, 40, seed=61)
+    else:
+        phi, s, w = _rng_case(5, 6, 40, seed=61, loss=(1, 2, 2, 2))
+    P = 30
+    tc = oracle.TableColumns(phi, w)
+    for k, l in [(0, 0), (3, 17), (29, 1), (39, 39)]:
+        ref = sum(np.conj(phi[k, i]) * w[i] * phi[l, i] for i in range(P))
+        assert tc[:, l][k] == pytest.approx(ref, rel=1e-12, abs=1e-12)
+    diag = np.array([sum(abs(phi[k, i]) ** 2 * w[i] for i in range(P)) for k in range(40)])
+    np.testing.assert_allclose(tc.D, 1.0 / np.sqrt(diag), rtol=1e-12)
+    with pytest.raises(IndexError):
+        tc[0, 1]
+    a = oracle.se_original(s, w, phi, 0.5, 25)
+    tc = oracle.TableColumns(phi, w)
+    f = oracle.fase(s, w, phi, tc, tc.D, 0.5, 25)
+    np.testing.assert_array_equal(a.sel, f.sel)
+    np.testing.assert_allclose(f.coef, a.coef, rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(f.g, a.g, atol=1e-8)
+    assert len(tc.cols) == len(set(f.sel)) < 40      # only the selected columns were formed
+
+
 def test_degenerate_atom_never_selected():
     phi, s, w = _rng_case(6, 6, 20, seed=14)
     spike = np.zeros(36)
