@@ -130,10 +130,10 @@ def cpu_baseline(n_blocks: int):
 
 
 # ---------------------------------------------------------------------------
-def measured_traffic(images: int, profile: str, sources):
-    """HBM bytes per launch of a kernel from a committed rocprofv3 counter
-    summary, or None when one of the kernel's source files changed since the
-    counters were taken (or the workload differs from the one profiled)."""
+def _profile_values(images: int, profile: str, sources):
+    """The machine-read lines of a committed rocprofv3 summary, or None when
+    one of the kernel's source files changed since the counters were taken
+    (or the workload differs from the one profiled)."""
     import hashlib
     if images != 256:
         return None
@@ -154,7 +154,32 @@ def measured_traffic(images: int, profile: str, sources):
         return None
     if hashlib.sha256(src).hexdigest() != kv.get("kernel_source_sha256"):
         return None
-    return int(float(kv["traffic_bytes_per_launch"]))
+    return kv
+
+
+def measured_traffic(images: int, profile: str, sources):
+    """HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE) from a
+    committed counter summary, or None (see _profile_values)."""
+    kv = _profile_values(images, profile, sources)
+    return None if kv is None else int(float(kv["traffic_bytes_per_launch"]))
+
+
+def issue_rates(images: int, profile: str, sources):
+    """Issue rates of a kernel's instruction pipes from committed counters:
+    VALU = SQ_INSTS_VALU x 4 cycles (a wave64 instruction occupies a 16-lane
+    SIMD for 4 cycles) / (SIMDs x cycles per XCD), SALU = SQ_INSTS_SALU / (CUs
+    x cycles per XCD) (one scalar unit per CU), with cycles per XCD =
+    GRBM_GUI_ACTIVE / 8 XCDs; and the fraction of each wave's cycles spent in
+    s_waitcnt (SQ_WAIT_ANY / SQ_WAVE_CYCLES).  None when the kernel changed
+    since the counters were taken."""
+    kv = _profile_values(images, profile, sources)
+    if kv is None or "valu_insts" not in kv:
+        return None
+    cyc = float(kv["grbm_gui_active"]) / 8.0
+    return {"valu_issue_frac": float(kv["valu_insts"]) * 4.0 / (1024 * cyc),
+            "salu_issue_frac": float(kv["salu_insts"]) / (256 * cyc),
+            "wait_frac": float(kv["wait_any"]) / float(kv["wave_cycles"]),
+            "from": "profiles/" + profile}
 
 
 LOOP_SOURCES = ("greedy.hip", "greedy_device.h", "argmax.h")
@@ -181,6 +206,9 @@ def main():
                     help="area32 (default) is the headline line; the others measure the "
                          "secondary workloads")
     ap.add_argument("--frames", type=int, default=120, help="serving: frames per arrival rate")
+    ap.add_argument("--precision-blocks", type=int, default=16,
+                    help="area64: blocks of the seeded sample the precision report compares "
+                         "with the FP64 oracle")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (default: tune loop shape and GEMM tile on the "
                          "benchmark batch before timing)")
@@ -419,15 +447,18 @@ def main():
     P = M * N
     loss_px = 64
     loop_bytes_per_block = ITERS * (K_ATOMS + loss_px) * 4 + K_ATOMS * 4
+    # the work the method itself must move per block (a row of the table per
+    # iteration, R and D once): I K 4 + 2 K 4 bytes
+    alg_bytes_per_block = ITERS * K_ATOMS * 4 + 2 * K_ATOMS * 4
     # GEMM: 2 K P per block; transforms: two separable products per part,
     # 2 P (M + N) flops each
     proj_flops_per_block = (2.0 * K_ATOMS * P if args.no_parts
                             else 2.0 * len(parts) * P * (M + N))
     loop_avg = float(np.mean(loop_ms))
     proj_avg = float(np.mean(proj_ms))
-    note = ("requested row bytes; frac > 1 because the rows of the 16 MiB table are served by "
-            "L2 and the Infinity Cache (traffic = measured HBM bytes); the limiter is the "
-            "compute units' vector memory pipeline (address and data units busy 83-87%)")
+    note = ("whole rows of the 16 MiB table, served by L2 and the Infinity Cache; the "
+            "limiter is the compute units' vector memory pipeline (address and data units "
+            "busy 83-87%)")
     classes = fused and t.n_classes == 4
     if fused:
         # rows of G (class rows of K/4 entries with parity classes) and the
@@ -437,29 +468,26 @@ def main():
         loop_gbs = fused_bytes_per_block * nblk / (loop_avg * 1e-3) / 1e9
         proj_tfs = None
         if classes:
-            note = ("requested bytes (class rows of K/4 entries, the atom over the loss, the "
-                    "pixels); the 4 MiB of class rows are served by L2, so HBM carries far "
-                    "less (traffic = measured HBM bytes); the loop is bound by the latency of "
-                    "each iteration's dependent chain (selection, row load, update), with "
-                    "4096 blocks giving 4 chains per SIMD")
-        roof = {"kernel": ("k_conceal_tx (transform projections + class-row iteration loop)"
-                           if classes else "k_conceal_tx (transform projections + iteration loop)"),
-                "bound": "hbm", "achieved": loop_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": loop_gbs / HBM_PEAK_GBS,
-                "traffic": measured_traffic(args.images, "k_conceal_tx_area32_k2048_traffic.txt",
-                                            FUSED_SOURCES),
-                "bytes_per_launch": fused_bytes_per_block * nblk, "avg_ms": loop_avg,
-                "note": note}
+            note = ("the 4 MiB of class rows (K/4 entries per row) are served by L2; the loop "
+                    "is bound by the latency of each iteration's dependent chain (selection, "
+                    "row load, update, wave maximum), with 4096 blocks giving 4 chains per "
+                    "SIMD")
+        roof = _latency_roof(
+            "k_conceal_tx (transform projections + " +
+            ("class-row iteration loop)" if classes else "iteration loop)"),
+            measured_traffic(args.images, "k_conceal_tx_area32_k2048_traffic.txt",
+                             FUSED_SOURCES),
+            loop_avg, alg_bytes_per_block * nblk, fused_bytes_per_block * nblk,
+            issue_rates(args.images, "k_conceal_tx_area32_k2048_counters.txt", FUSED_SOURCES),
+            note)
     else:
         loop_gbs = loop_bytes_per_block * nblk / (loop_avg * 1e-3) / 1e9
         proj_tfs = proj_flops_per_block * nblk / (proj_avg * 1e-3) / 1e12
         if loop_avg >= proj_avg:
-            roof = {"kernel": "k_greedy (iteration loop)", "bound": "hbm", "achieved": loop_gbs,
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": loop_gbs / HBM_PEAK_GBS,
-                    "traffic": measured_traffic(args.images, "k_greedy_area32_k2048_traffic.txt",
-                                                LOOP_SOURCES),
-                    "bytes_per_launch": loop_bytes_per_block * nblk, "avg_ms": loop_avg,
-                    "note": note}
+            roof = _latency_roof(
+                "k_greedy (iteration loop)",
+                measured_traffic(args.images, "k_greedy_area32_k2048_traffic.txt", LOOP_SOURCES),
+                loop_avg, alg_bytes_per_block * nblk, loop_bytes_per_block * nblk, None, note)
         elif not args.no_parts:
             proj_bytes = nblk * (ldR * 4 + P)      # R written, the area's pixels read
             roof = {"kernel": "k_project_tx (initial projections)", "bound": "hbm",
@@ -522,21 +550,36 @@ def main():
         "two_launch": split,
         "full_rows": full_rows,
         "fixed_point_rows": fixed_point,
-        "roofline": _with_traffic_rate(roof),
+        "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
 
-def _with_traffic_rate(roof):
-    """The measured HBM bytes per launch as a rate over the same launch time,
-    and its fraction of the HBM peak (how far HBM itself is from its limit,
-    next to `frac`, which counts the requested bytes)."""
-    if roof and roof.get("traffic") and roof.get("avg_ms"):
-        rate = roof["traffic"] / (roof["avg_ms"] * 1e-3) / 1e9
-        roof["traffic_gbs"] = rate
-        roof["traffic_frac"] = rate / HBM_PEAK_GBS
-    return roof
+def _latency_roof(kernel, traffic, avg_ms, alg_bytes, req_bytes, issue, note):
+    """Roofline object of a loop kernel whose rows come from the caches.
+    HBM is its only off-chip bound: `achieved` is the measured HBM bytes per
+    launch (calibrated counters, `traffic`) over the launch time, `frac` that
+    rate over the HBM peak (None when the counters are stale).  The method's
+    own bytes (a table row per iteration, section 8(d)) and the bytes the
+    loop requests from the caches are reported beside it: both exceed what
+    HBM could deliver in the launch time, because the rows are served on
+    chip, so the limit is the latency of each iteration's dependent chain
+    (selection, row load, update, wave maximum), for which the issue rates of
+    the instruction pipes (from the committed counters) are the evidence."""
+    t = avg_ms * 1e-3
+    hbm = traffic / t / 1e9 if traffic else None
+    return {"kernel": kernel, "bound": "latency", "achieved": hbm, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": None if hbm is None else hbm / HBM_PEAK_GBS,
+            "traffic": traffic, "avg_ms": avg_ms,
+            "algorithmic": {"bytes_per_launch": alg_bytes, "gbs": alg_bytes / t / 1e9,
+                            "over_hbm_peak": alg_bytes / t / 1e9 / HBM_PEAK_GBS,
+                            "what": "I*K*4 + 2*K*4 bytes per block (a table row per iteration, "
+                                    "R and D once); served by L2 and the Infinity Cache"},
+            "requested": {"bytes_per_launch": req_bytes, "gbs": req_bytes / t / 1e9,
+                          "what": "bytes the loop loads (class rows of K/4 entries or whole "
+                                  "rows, the atom over the loss, the pixels)"},
+            "issue": issue, "note": note}
 
 
 # ---------------------------------------------------------------------------
@@ -793,74 +836,172 @@ def bench_clustered(args):
                                     "(SE_ROWS_BF16X3); FP32 accumulation"}}
 
 
+def cpu_baseline_area64(d, sample, iters):
+    """The oracle leg of the 64x64 line: Algorithm 2 once for the shared
+    weight pattern, then Algorithm 3 (FP64, NumPy) on the sampled blocks, on
+    the host (timed: the CPU baseline of this workload), and its results as
+    the reference of the precision report.  Runs before the GPU work."""
+    import oracle
+    blocks = d["blocks"]
+    phi = synth.round_to_f32(d["phi"])
+    lost = synth.lost_mask(2048, 2048, blocks)
+    cls = oracle.duplicate_classes(phi)
+    b0 = blocks[0]
+    _, sup0 = oracle.area_signal(d["images"][0], lost, b0.y0, b0.x0, 64, 64)
+    w = oracle.area_weights(64, 64, RHO, sup0)
+    t0 = time.perf_counter()
+    C, D = oracle.table_generation(phi, w)
+    tables_s = time.perf_counter() - t0
+    ref = []
+    t0 = time.perf_counter()
+    for i in sample:
+        b = blocks[i]
+        s_, _ = oracle.area_signal(d["images"][0], lost, b.y0, b.x0, 64, 64)
+        res = oracle.fase(s_, w, phi, C, D, GAMMA, iters, cls)
+        g = res.g.reshape(64, 64)[b.ly:b.ly + b.lh, b.lx:b.lx + b.lw].reshape(-1)
+        best, second = np.sqrt(res.best), np.sqrt(res.second)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            margin = float(np.min(np.where(best > 0, (best - second) / best, np.inf)))
+        ref.append((res.sel, g, margin))
+    per_block = (time.perf_counter() - t0) / len(sample)
+    return {"ref": ref, "cls": cls,
+            "baseline": {"value": 1.0 / per_block, "unit": "blocks/s", "cores": 1,
+                         "kind": "oracle", "tables_s": tables_s,
+                         "sample": f"{len(sample)} seeded blocks, Algorithm 3 (FP64 NumPy) after "
+                                   f"Algorithm 2 once for the shared pattern (tables_s)"}}
+
+
+def _precision_report(oracle_leg, sample, sel, g):
+    """Selected-index agreement, the oracle's smallest tie margin and the
+    largest |g - g_oracle| over the loss (0..255 scale) on the sampled
+    blocks, against the FP64 oracle (selections compared modulo parallel
+    atoms)."""
+    cls = oracle_leg["cls"]
+    same, first_div, dg, dg_same, margin = 0, [], 0.0, 0.0, np.inf
+    for i, (rsel, rg, m) in zip(sample, oracle_leg["ref"]):
+        eq = cls[sel[i]] == cls[rsel]
+        err = float(np.abs(g[i, :len(rg)].astype(np.float64) - rg).max())
+        dg = max(dg, err)
+        margin = min(margin, m)
+        if eq.all():
+            same += 1
+            dg_same = max(dg_same, err)
+        else:
+            first_div.append(int(np.argmin(eq)))
+    return {"blocks": len(sample), "identical_selections": same,
+            "iterations_identical_frac": float(np.mean(
+                [np.mean(cls[sel[i]] == cls[r[0]]) for i, r in zip(sample, oracle_leg["ref"])])),
+            "first_divergence_iterations": first_div,
+            "min_tie_margin": margin, "max_abs_dg": dg, "max_abs_dg_identical": dg_same}
+
+
 def bench_area64(args):
     """Precision: 1024 blocks of one geometry, 64x64 areas, K = 8192 (DCT u
-    WHT 64^2), I = 300; FP32 vs split-BF16 tables and projections."""
+    WHT 64^2), I = 300.  FP32 against split-BF16 tables and projections on
+    the dense route (no declared parts: every product on the matrix cores, so
+    BF16x3 changes the arithmetic), each with a precision report against the
+    FP64 oracle on a seeded sample; then the chosen form, the dictionary's
+    halves declared as transform parts (tables and projections are FP32
+    transforms in either precision) and one launch per step on parity-class
+    rows."""
+    iters = 300
+    d = synth.area64_inputs(1)
+    blocks = d["blocks"]
+    sample = sorted(np.random.default_rng(64).choice(len(blocks), args.precision_blocks,
+                                                     replace=False).tolist())
+    leg = None if args.no_cpu else cpu_baseline_area64(d, sample, iters)
     import torch
     from paper_2204_14194_amd import binding as B
     dev = torch.device("cuda:0")
-    d = synth.area64_inputs(1)
-    blocks = d["blocks"]
-    out = {"metric": "concealed blocks/s, 64x64 areas, K=8192, I=300 (FP32 vs BF16x3)",
-           "unit": "blocks/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+    out = {"metric": "concealed blocks/s, 64x64 areas, K=8192, I=300", "unit": "blocks/s",
+           "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
            "config": {"workload": "2048x2048 image, 1024 64x64 areas with 16x16 losses, "
-                                  "K=8192, I=300"}}
-    parts = () if args.no_parts else d["tx_parts"]
+                                  "K=8192 (2-D DCT-II 64x64 u 2-D WHT 64x64), rho_hat=0.8, "
+                                  "gamma=0.5, I=300"}}
     phi_d = torch.from_numpy(d["phi"].astype(np.float32)).to(dev)
     lost = synth.lost_mask(2048, 2048, blocks)[None]
     lost_d = torch.from_numpy(lost).to(dev)
-    for name, prec in (("fp32", B.SE_FP32), ("bf16x3", B.SE_BF16X3)):
-        gram = []
+    K, P, n = 8192, 4096, len(blocks)
+
+    def tables(prec, parts):
+        runs = []
         for _ in range(3):   # weights + Algorithm 2 (inputs already on the device)
             e0, e1 = _events(2)
             e0.record()
             w = B.area_weights(64, 64, RHO, lost_d, blocks[:1])
             t = B.weighted_gram(phi_d, w[0].contiguous(), 64, 64, prec, parts=parts,
-                                fixed_point=True)
+                                fixed_point=bool(parts))
             e1.record()
             e1.synchronize()
-            gram.append(e0.elapsed_time(e1))
+            runs.append(e0.elapsed_time(e1))
+        return t, min(runs)
+
+    # ---- the dense route: FP32 vs split-BF16 products ------------------------
+    out["dense"] = {}
+    for name, prec in (("fp32", B.SE_FP32), ("bf16x3", B.SE_BF16X3)):
+        t, gram_ms = tables(prec, ())
         img = torch.from_numpy(d["images"]).to(dev)
         dblk = B.DeviceBlocks(t, img, blocks)
-        R = torch.empty((len(blocks), B.table_ld(8192)), dtype=torch.float32, device=dev)
-        ws = torch.empty(max(1, B.project_ws_bytes(t, len(blocks))), dtype=torch.uint8,
-                         device=dev)
+        R = torch.empty((n, B.table_ld(K)), dtype=torch.float32, device=dev)
+        ws = torch.empty(max(1, B.project_ws_bytes(t, n)), dtype=torch.uint8, device=dev)
         proj = _timed(lambda: B.project(t, img, dblk, R, ws), args.steps, args.warmup)
-        loop = _timed(lambda: B.iterate(t, R, img, dblk, 0.5, 300), max(2, args.steps // 4), 1)
+        loop = _timed(lambda: B.iterate(t, R, img, dblk, GAMMA, iters), max(2, args.steps // 4), 1)
         step = float(np.median(proj)) + float(np.median(loop))
-        # projection work: the GEMM against all atoms, or two separable
-        # products per declared part
-        flops = (2.0 * 8192 * 4096 if not parts else 2.0 * len(parts) * 4096 * 128) * len(blocks)
-        out[name] = {"blocks_per_s": len(blocks) / (step * 1e-3), "ms_per_step": step,
-                     "project_ms": float(np.median(proj)),
-                     "project_form": "transform" if parts else "gemm",
-                     "project_tflops": flops / (np.median(proj) * 1e-3) / 1e12,
-                     "loop_ms": float(np.median(loop)), "gram_ms": min(gram),
-                     "gram_tflops": 8192 * 8193 * 4096 / (min(gram) * 1e-3) / 1e12}
-        if parts:
-            # projections and loop in one launch (on parity-class rows when the
-            # tables have them)
-            one = _timed(lambda: B.extrapolate_device(t, img, dblk, 0.5, 300),
-                         max(2, args.steps // 4), 1)
-            out[name]["one_launch"] = {
-                "ms_per_step": float(np.median(one)),
-                "blocks_per_s": len(blocks) / (float(np.median(one)) * 1e-3),
-                "class_rows": t.n_classes == 4}
-            if t.n_classes == 4:
-                # the class rows as 16-bit fixed-point words (half the bytes)
-                q = _timed(lambda: B.extrapolate_device(t, img, dblk, 0.5, 300, rows_q14=True),
-                           max(2, args.steps // 4), 1)
-                out[name]["one_launch_q14"] = {
-                    "ms_per_step": float(np.median(q)),
-                    "blocks_per_s": len(blocks) / (float(np.median(q)) * 1e-3),
-                    "what": "the same launch reading the class rows as 16-bit words "
-                            "(SE_ROWS_Q14)"}
-        del t
-    # the chosen form: one launch when the dictionary's parts allow it
-    best = out["bf16x3"].get("one_launch", out["bf16x3"])
-    out["value"] = best["blocks_per_s"]
-    out["ms_per_step"] = best["ms_per_step"]
-    out["dtype"] = "bf16x3"
+        # Algorithm 2: K (K + 1) P flops for the lower half (one product per
+        # pair, mirrored); eq. 12: 2 K P flops per block; BF16x3 issues three
+        # BF16 products for each
+        gram_flops, proj_flops = K * (K + 1) * P, 2.0 * K * P * n
+        mult = 3 if prec == B.SE_BF16X3 else 1
+        e = {"dtype": "bf16x3" if prec == B.SE_BF16X3 else "f32",
+             "blocks_per_s": n / (step * 1e-3), "ms_per_step": step,
+             "project_ms": float(np.median(proj)),
+             "project_tflops": proj_flops / (np.median(proj) * 1e-3) / 1e12,
+             "loop_ms": float(np.median(loop)), "gram_ms": gram_ms,
+             "gram_tflops": gram_flops / (gram_ms * 1e-3) / 1e12,
+             "mfma_issued_tflops": {"project": mult * proj_flops / (np.median(proj) * 1e-3) / 1e12,
+                                    "gram": mult * gram_flops / (gram_ms * 1e-3) / 1e12},
+             "what": "tables, projections and loop without declared parts (two launches)"}
+        if leg is not None:
+            img2 = torch.from_numpy(d["images"]).to(dev)
+            sel, _, g = B.extrapolate_batch(t, img2, blocks, GAMMA, iters, want_coef=False)
+            torch.cuda.synchronize()
+            e["precision"] = _precision_report(leg, sample, sel.cpu().numpy(), g.cpu().numpy())
+        out["dense"][name] = e
+        del t, R, ws
+
+    # ---- the chosen form: transform parts, one launch on class rows ----------
+    parts = d["tx_parts"]
+    t, gram_ms = tables(B.SE_FP32, parts)
+    img = torch.from_numpy(d["images"]).to(dev)
+    dblk = B.DeviceBlocks(t, img, blocks)
+    one = _timed(lambda: B.extrapolate_device(t, img, dblk, GAMMA, iters),
+                 max(2, args.steps // 4), 1)
+    # table rows of the part atoms as transforms of w phi_k: K atoms x two
+    # parts x two separable products of 2 P (M + N) flops
+    tx_flops = K * len(parts) * 2.0 * P * (64 + 64)
+    chosen = {"dtype": "f32", "ms_per_step": float(np.median(one)),
+              "blocks_per_s": n / (float(np.median(one)) * 1e-3), "class_rows": t.n_classes == 4,
+              "gram_ms": gram_ms, "gram_transform_tflops": tx_flops / (gram_ms * 1e-3) / 1e12,
+              "what": "the dictionary's DCT and WHT halves declared as transform parts: "
+                      "tables and projections are FP32 transforms in either precision; one "
+                      "launch per step on parity-class rows"}
+    if t.n_classes == 4:
+        q = _timed(lambda: B.extrapolate_device(t, img, dblk, GAMMA, iters, rows_q14=True),
+                   max(2, args.steps // 4), 1)
+        chosen["one_launch_q14"] = {
+            "ms_per_step": float(np.median(q)),
+            "blocks_per_s": n / (float(np.median(q)) * 1e-3),
+            "what": "the same launch reading the class rows as 16-bit words (SE_ROWS_Q14)"}
+    if leg is not None:
+        img2 = torch.from_numpy(d["images"]).to(dev)
+        sel, _, g = B.extrapolate_batch(t, img2, blocks, GAMMA, iters, want_coef=False)
+        torch.cuda.synchronize()
+        chosen["precision"] = _precision_report(leg, sample, sel.cpu().numpy(), g.cpu().numpy())
+    out["chosen"] = chosen
+    out["value"] = chosen["blocks_per_s"]
+    out["ms_per_step"] = chosen["ms_per_step"]
+    out["dtype"] = "f32"
+    out["cpu_baseline"] = None if leg is None else leg["baseline"]
     return out
 
 

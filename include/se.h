@@ -260,10 +260,21 @@ typedef struct {
  *                 initial projections and the loop stay FP32.  Every other
  *                 call returns SE_EINVAL for it. */
 #define SE_ROWS_BF16X3 2u
+/*   SE_INVARIANT : every matrix product of the call (the initial projections
+ *                 of eq. 12 and, on demand, the diagonals and table rows)
+ *                 runs in one pass over its contraction, whatever the number
+ *                 of blocks.  Without it a call with few blocks splits the
+ *                 contraction over slices to fill the GPU, which changes the
+ *                 order of the FP32 sums; with it each block's result is the
+ *                 same whichever other blocks share the call (the server
+ *                 sets it for the batches it forms from several requests).
+ *                 Accepted by every call that takes se_params. */
+#define SE_INVARIANT 4u
 typedef struct {
   float gamma;
   int32_t iters;
-  uint32_t flags; /* 0, SE_ROWS_Q14 or SE_ROWS_BF16X3 */
+  uint32_t flags; /* 0, or SE_ROWS_Q14 or SE_ROWS_BF16X3, each with or
+                     without SE_INVARIANT */
 } se_params;
 
 /* ------------------------------------------------------------------------ */

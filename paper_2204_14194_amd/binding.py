@@ -22,6 +22,7 @@ SE_FP32, SE_BF16X3 = 0, 1
 SE_DIAG_AUTO, SE_DIAG_FP64, SE_DIAG_FP32 = 0, 1, 2
 SE_ROWS_Q14 = 1   # se_params.flags: the loop reads the fixed-point class rows
 SE_ROWS_BF16X3 = 2   # se_params.flags: rows on demand from split-BF16 products
+SE_INVARIANT = 4     # se_params.flags: products in one pass, independent of the batch
 SE_PART_DCT2, SE_PART_WHT2 = 1, 2
 
 # every symbol include/se.h declares
@@ -425,14 +426,15 @@ def _extrapolate(name: str, t: Tables, images: torch.Tensor, blocks: Sequence, g
 
 def extrapolate_batch(t: Tables, images: torch.Tensor, blocks: Sequence, gamma: float,
                       iters: int, want_sel=True, want_coef=True, want_g=True, ws=None,
-                      stream=None, blocks_arr=None, rows_q14: bool = False):
+                      stream=None, blocks_arr=None, rows_q14: bool = False,
+                      invariant: bool = False):
     """se_extrapolate_batch (Algorithm 3, batched).  ``images`` is modified in
     place (each loss replaced).  Returns (sel, coef, g_loss) device tensors
     (None where not requested).  ``rows_q14``: the loop reads the fixed-point
-    class rows (SE_ROWS_Q14)."""
+    class rows (SE_ROWS_Q14); ``invariant``: SE_INVARIANT."""
     return _extrapolate("se_extrapolate_batch", t, images, blocks, gamma, iters, want_sel,
                         want_coef, want_g, ws, stream, blocks_arr,
-                        SE_ROWS_Q14 if rows_q14 else 0)
+                        (SE_ROWS_Q14 if rows_q14 else 0) | (SE_INVARIANT if invariant else 0))
 
 
 def extrapolate_batch_static(t: Tables, images: torch.Tensor, blocks: Sequence, gamma: float,
@@ -548,11 +550,11 @@ def extrapolate_device(t: Tables, images: torch.Tensor, dblocks: DeviceBlocks, g
 def extrapolate_ondemand(phi: torch.Tensor, M: int, N: int, w: torch.Tensor,
                          images: torch.Tensor, blocks: Sequence, gamma: float, iters,
                          want_sel=True, want_coef=True, want_g=True, ws=None, stream=None,
-                         parts=(), rows_bf16: bool = False):
+                         parts=(), rows_bf16: bool = False, invariant: bool = False):
     """se_extrapolate_ondemand: per-block weights ``w`` (n_blk, M*N); ``iters``
     an int or a per-block sequence.  ``rows_bf16``: the dense atoms' row
-    products from split-BF16 operands (SE_ROWS_BF16X3).  Returns (sel, coef,
-    g_loss)."""
+    products from split-BF16 operands (SE_ROWS_BF16X3); ``invariant``:
+    SE_INVARIANT.  Returns (sel, coef, g_loss)."""
     L = lib()
     _dev_f32(phi, "phi")
     _dev_f32(w, "w")
@@ -575,7 +577,8 @@ def extrapolate_ondemand(phi: torch.Tensor, M: int, N: int, w: torch.Tensor,
         ws = _workspace(nb, dev)
     elif ws.numel() < nb:
         raise ValueError(f"workspace of {ws.numel()} bytes < {nb}")
-    prm = se_params(float(gamma), int(imax), SE_ROWS_BF16X3 if rows_bf16 else 0)
+    prm = se_params(float(gamma), int(imax), (SE_ROWS_BF16X3 if rows_bf16 else 0) |
+                    (SE_INVARIANT if invariant else 0))
     return _check_results(L.se_extrapolate_ondemand(C.byref(bas), _ptr(w), _ptr(images), n_img,
                                                     H, W, blocks_array(blocks), n, prm, per,
                                                     _ptr(sel), _ptr(coef), _ptr(g), gld,

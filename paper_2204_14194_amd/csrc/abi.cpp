@@ -293,7 +293,7 @@ static se_status verify_parts(const se_basis* b, int32_t* flag, hipStream_t s,
 // the transform parts as separable transforms.  ws holds project_ws().
 static se_status project_into(const se_tables* t, const uint8_t* images, int H, int W,
                               const se_block* dblk, int n_blk, float* R, int ldR, void* ws,
-                              hipStream_t s) {
+                              hipStream_t s, bool invariant = false) {
   se_status st;
   const int P = area_samples(t);
   int lo[3] = {0, 0, 0}, hi[3] = {t->K, 0, 0};
@@ -322,8 +322,11 @@ static se_status project_into(const se_tables* t, const uint8_t* images, int H, 
   }
   const int ldX = round4(P);
   float* X = cv.take<float>((size_t)n_blk * ldX);
-  const size_t split_floats = project_splitk_floats(t, n_blk);
-  float* split = cv.take<float>(split_floats);
+  // invariant: one pass over the contraction whatever the batch size (a
+  // split into slices depends on the number of blocks and changes the
+  // rounding)
+  const size_t split_floats = invariant ? 0 : project_splitk_floats(t, n_blk);
+  float* split = cv.take<float>(project_splitk_floats(t, n_blk));
   launch_gather(images, H, W, dblk, n_blk, area_frames(t->T), t->M, t->N, t->sqrtw, X, ldX, s);
   if ((st = check_launch("gather"))) return st;
   if (t->phi_im) {
@@ -710,7 +713,7 @@ static se_status launch_loop(const se_tables* t, const GreedyArgs& ga, int n_blk
 static se_status check_params(se_params prm, const float* g_loss, int g_loss_ld) {
   if (!(prm.gamma > 0.0f && prm.gamma <= 1.0f)) return fail(SE_EINVAL, "gamma must lie in (0, 1]");
   if (prm.iters < 0) return fail(SE_EINVAL, "iters < 0");
-  if (prm.flags & ~(SE_ROWS_Q14 | SE_ROWS_BF16X3))
+  if (prm.flags & ~(SE_ROWS_Q14 | SE_ROWS_BF16X3 | SE_INVARIANT))
     return fail(SE_EINVAL, "unknown flags 0x%x", prm.flags);
   if (g_loss && g_loss_ld < 1) return fail(SE_EINVAL, "g_loss_ld < 1");
   return SE_OK;
@@ -778,7 +781,9 @@ se_status se_extrapolate_device(const se_tables* t, uint8_t* images, int32_t n_i
   Carver cv(ws);
   float* R = cv.take<float>((size_t)n_blk * ldR);
   char* pws = cv.take<char>(project_ws(t, n_blk));
-  if ((st = project_into(t, images, H, W, dev_blocks, n_blk, R, ldR, pws, s))) return st;
+  if ((st = project_into(t, images, H, W, dev_blocks, n_blk, R, ldR, pws, s,
+                        (prm.flags & SE_INVARIANT) != 0)))
+    return st;
   const GreedyArgs ga = greedy_args(t, R, ldR, images, H, W, dev_blocks, n_blk, prm, sel, coef,
                                     g_loss, g_loss_ld);
   return launch_loop(t, ga, n_blk, s, tc);
@@ -809,7 +814,7 @@ static size_t batch_route_ws(const se_tables* t, int n_blk) {
 static se_status extrapolate_uploaded(bool plain, const se_tables* t, uint8_t* images, int H,
                                       int W, se_block* dblk, float* R, char* pws, int n_blk,
                                       se_params prm, int32_t* sel, float* coef, float* g_loss,
-                                      int32_t g_loss_ld, hipStream_t s);
+                                      int32_t g_loss_ld, hipStream_t s, bool invariant);
 
 // The batched and per-block calls.  use_static: the workspace is the static
 // scratch of this device (ws ignored), sized for the route taken, and the
@@ -853,7 +858,7 @@ static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, in
                        : upload_blocks(blocks, n_blk, dblk, s, &sh)))
     return st;
   if ((st = extrapolate_uploaded(plain, t, images, H, W, dblk, R, pws, n_blk, prm, sel, coef,
-                                 g_loss, g_loss_ld, s)))
+                                 g_loss, g_loss_ld, s, (prm.flags & SE_INVARIANT) != 0)))
     return st;
   return degenerate_status(n_deg);
 }
@@ -862,7 +867,7 @@ static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, in
 static se_status extrapolate_uploaded(bool plain, const se_tables* t, uint8_t* images, int H,
                                       int W, se_block* dblk, float* R, char* pws, int n_blk,
                                       se_params prm, int32_t* sel, float* coef, float* g_loss,
-                                      int32_t g_loss_ld, hipStream_t s) {
+                                      int32_t g_loss_ld, hipStream_t s, bool invariant) {
   se_status st;
   const int P = area_samples(t), ldR = r_row_len(t);
   GreedyArgs ga = greedy_args(t, R, ldR, images, H, W, dblk, n_blk, prm, sel, coef, g_loss,
@@ -871,7 +876,7 @@ static se_status extrapolate_uploaded(bool plain, const se_tables* t, uint8_t* i
     const TuneChoice tc = tune_lookup(t->K, P, n_blk);
     if (conceal_tx_supported(t))   // projections inside the loop's workgroups
       return conceal_tx(t, ga, images, H, W, n_blk, s, tc.loop_waves, tc.loop_vpl);
-    if ((st = project_into(t, images, H, W, dblk, n_blk, R, ldR, pws, s))) return st;
+    if ((st = project_into(t, images, H, W, dblk, n_blk, R, ldR, pws, s, invariant))) return st;
     return launch_loop(t, ga, n_blk, s, tc);
   }
   // one block at a time: gather, matrix-vector product (FP32), single-workgroup loop
@@ -929,12 +934,14 @@ size_t se_extrapolate_ondemand_ws_bytes(const se_basis* b, int32_t n_blk, int32_
   return cv.off + 256;
 }
 
-se_status se_extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* images,
-                                  int32_t n_img, int32_t H, int32_t W, const se_block* blocks,
-                                  int32_t n_blk, se_params prm, const int32_t* iters,
-                                  int32_t* sel, float* coef, float* g_loss, int32_t g_loss_ld,
-                                  void* ws, size_t ws_bytes, void* stream) {
+static se_status extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* images,
+                                      int32_t n_img, int32_t H, int32_t W,
+                                      const se_block* blocks, int32_t n_blk, se_params prm,
+                                      const int32_t* iters, int32_t* sel, float* coef,
+                                      float* g_loss, int32_t g_loss_ld, void* ws,
+                                      size_t ws_bytes, void* stream) {
   g_err[0] = 0;
+  const bool invariant = (prm.flags & SE_INVARIANT) != 0;
   if (b && b->phi_im) return fail(SE_EINVAL, "rows on demand take real dictionaries");
   if (b && b->T > 1) return fail(SE_EINVAL, "rows on demand take two-dimensional areas");
   if (!b || !b->phi || !w || !images) return fail(SE_EINVAL, "NULL argument");
@@ -1007,8 +1014,10 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* im
   pl.deg = cv.take<int32_t>((size_t)n);
   pl.n_degenerate = nullptr;
   float* tx = cv.take<float>(tx_const_bytes(b->M, b->N, b->n_parts) / 4);
-  pl.splitk_floats = ondemand_splitk_floats(b, n);
-  pl.splitk = cv.take<float>(pl.splitk_floats);
+  pl.splitk = cv.take<float>(ondemand_splitk_floats(b, n));
+  // invariant: every product in one pass over its contraction (the split
+  // depends on how many blocks iterate, which would change the rounding)
+  pl.splitk_floats = invariant ? 0 : ondemand_splitk_floats(b, n);
   pl.phi_hi = pl.phi_lo = pl.Vhi = pl.Vlo = nullptr;
   {
     uint16_t* ph = cv.take<uint16_t>((size_t)2 * K * P);
@@ -1057,6 +1066,15 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* im
   return degenerate_status(n_deg);
 }
 
+se_status se_extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* images,
+                                  int32_t n_img, int32_t H, int32_t W, const se_block* blocks,
+                                  int32_t n_blk, se_params prm, const int32_t* iters,
+                                  int32_t* sel, float* coef, float* g_loss, int32_t g_loss_ld,
+                                  void* ws, size_t ws_bytes, void* stream) {
+  return extrapolate_ondemand(b, w, images, n_img, H, W, blocks, n_blk, prm, iters, sel, coef,
+                              g_loss, g_loss_ld, ws, ws_bytes, stream);
+}
+
 se_status se_extrapolate_batch(const se_tables* t, uint8_t* images, int32_t n_img, int32_t H,
                                int32_t W, const se_block* blocks, int32_t n_blk, se_params prm,
                                int32_t* sel, float* coef, float* g_loss, int32_t g_loss_ld,
@@ -1082,3 +1100,4 @@ se_status se_extrapolate_plain(const se_tables* t, uint8_t* images, int32_t n_im
 }
 
 }  // extern "C"
+

@@ -68,6 +68,36 @@ __device__ __forceinline__ float class_lane_max(const float (&R)[NJ][4]) {
   return m;
 }
 
+// Class form, one wave per block: the winner of class C, found when the
+// class changes (once at the start, then after each update of the class):
+// the class's largest |R~| over the wave (wm, float bits), whether one lane
+// alone holds it (one), and, if so, its position in the class order and its
+// signed value.  The holding lane's lowest position at the maximum is that
+// lane's lowest atom of the class (positions follow the atom order inside a
+// class).
+template <int NJ, int NJC, int C, int T>
+__device__ __forceinline__ void class_winner(const float (&R)[NJ][4], int t, float& lm,
+                                             uint32_t& wm, bool& one, int& pos, float& val) {
+  const float m = class_lane_max<NJ, NJC, C>(R);
+  int p = 4 * NJC - 1;
+  float v = R[C * NJC + NJC - 1][3];
+#pragma unroll
+  for (int i = 4 * NJC - 2; i >= 0; --i) {
+    const float x = R[C * NJC + (i >> 2)][i & 3];
+    const bool hit = fabsf(x) == m;
+    p = hit ? i : p;
+    v = hit ? x : v;
+  }
+  lm = m;
+  wm = __float_as_uint(wave_max_f32(m));
+  const uint64_t holders = __builtin_amdgcn_ballot_w64(__float_as_uint(m) == wm);
+  one = __builtin_popcountll(holders) == 1;
+  const int L = (int)__builtin_ctzll(holders);
+  const int pl = __builtin_amdgcn_readlane(p, L);
+  pos = 4 * ((C * NJC + (pl >> 2)) * T + L) + (pl & 3);
+  val = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), L));
+}
+
 // Class form: the classes (bit c) of the sweeps set in a mask of sweeps
 // (class c holds the sweeps c NJC .. c NJC + NJC - 1).
 template <int NJ, int NJC>
@@ -77,10 +107,6 @@ __device__ __forceinline__ uint32_t class_mask(uint32_t sweeps) {
 #pragma unroll
   for (int c = 0; c < 4; ++c) m |= (uint32_t)((sweeps & (one << (c * NJC))) != 0u) << c;
   return m;
-}
-template <int NJ, int NJC>
-__device__ __forceinline__ int classes_hit(uint32_t sweeps) {
-  return __builtin_popcount(class_mask<NJ, NJC>(sweeps));
 }
 
 // Exact ties of the class form: every lane's positions whose |R~| bits equal
@@ -183,18 +209,20 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
   int par = 0;
   const float gamma = a.gamma;
 
-  // class maxima kept across iterations (class form, one wave): per lane,
-  // and over the wave as float bits (uniform)
+  // each class's winner kept across iterations (class form, one wave): the
+  // lane maxima, and, uniform, the wave maximum (float bits), whether one
+  // lane alone holds it, its position and signed value
   constexpr bool INC = CLS && WAVES == 1;
   float lmc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
   uint32_t wmc[4] = {0u, 0u, 0u, 0u};
+  bool c_one[4] = {false, false, false, false};
+  int c_pos[4] = {0, 0, 0, 0};
+  float c_val[4] = {0.0f, 0.0f, 0.0f, 0.0f};
   if constexpr (INC) {
-    lmc[0] = class_lane_max<NJ, NJC, 0>(R);
-    lmc[1] = class_lane_max<NJ, NJC, 1>(R);
-    lmc[2] = class_lane_max<NJ, NJC, 2>(R);
-    lmc[3] = class_lane_max<NJ, NJC, 3>(R);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) wmc[c] = __float_as_uint(wave_max_f32(lmc[c]));
+    class_winner<NJ, NJC, 0, T>(R, t, lmc[0], wmc[0], c_one[0], c_pos[0], c_val[0]);
+    class_winner<NJ, NJC, 1, T>(R, t, lmc[1], wmc[1], c_one[1], c_pos[1], c_val[1]);
+    class_winner<NJ, NJC, 2, T>(R, t, lmc[2], wmc[2], c_one[2], c_pos[2], c_val[2]);
+    class_winner<NJ, NJC, 3, T>(R, t, lmc[3], wmc[3], c_one[3], c_pos[3], c_val[3]);
   }
 
   for (int it = 0; it < a.iters; ++it) {
@@ -204,34 +232,17 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     bool direct = WAVES == 1;
     bool class_key = false;                    // key from class_tie_key
     if constexpr (INC) {
-      // ---- the largest class maximum, then its holder
+      // ---- the largest class maximum: its class's winner, unless it ties
+      // (between classes, or between lanes of the class)
       const uint32_t Mb = max(max(wmc[0], wmc[1]), max(wmc[2], wmc[3]));
       if (Mb != 0u) {
-        const int cw = wmc[0] == Mb ? 0 : wmc[1] == Mb ? 1 : wmc[2] == Mb ? 2 : 3;
-        const float v = cw == 0 ? lmc[0] : cw == 1 ? lmc[1] : cw == 2 ? lmc[2] : lmc[3];
-        const uint64_t holders = __builtin_amdgcn_ballot_w64(__float_as_uint(v) == Mb);
-        const int nclass = (wmc[0] == Mb) + (wmc[1] == Mb) + (wmc[2] == Mb) + (wmc[3] == Mb);
-        if (nclass == 1 && __builtin_popcountll(holders) == 1) {
-          // lane L alone: every lane finds its first position holding the
-          // maximum in the class (vector selects), then L's position and
-          // value are read
-          const int L = __builtin_ctzll(holders);
-          int lpos = 0;
-          uint32_t lval = 0u;
-#pragma unroll
-          for (int cc = 0; cc < 4; ++cc)
-            if (cc == cw) {                    // uniform branch
-#pragma unroll
-              for (int i = 4 * NJC - 1; i >= 0; --i) {
-                const uint32_t bi = __float_as_uint(R[cc * NJC + (i >> 2)][i & 3]);
-                const bool hit = (bi & 0x7FFFFFFFu) == Mb;
-                lpos = hit ? i : lpos;
-                lval = hit ? bi : lval;
-              }
-            }
-          const int pos = __builtin_amdgcn_readlane(lpos, L);
-          u = 4 * ((cw * NJC + (pos >> 2)) * T + L) + (pos & 3);
-          rv = __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)lval, L));
+        const uint32_t at = (wmc[0] == Mb ? 1u : 0u) | (wmc[1] == Mb ? 2u : 0u) |
+                            (wmc[2] == Mb ? 4u : 0u) | (wmc[3] == Mb ? 8u : 0u);
+        const int cw = (int)__builtin_ctz(at);
+        const bool one = cw == 0 ? c_one[0] : cw == 1 ? c_one[1] : cw == 2 ? c_one[2] : c_one[3];
+        if ((at & (at - 1u)) == 0u && one) {
+          u = cw == 0 ? c_pos[0] : cw == 1 ? c_pos[1] : cw == 2 ? c_pos[2] : c_pos[3];
+          rv = cw == 0 ? c_val[0] : cw == 1 ? c_val[1] : cw == 2 ? c_val[2] : c_val[3];
         } else {
           // exact ties across lanes or between classes: the lowest atom index
           key = class_tie_key<NJ, T>(R, Mb, a.cl, t);
@@ -284,9 +295,15 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
         u = 0;
         rv = 0.0f;
       }
-      // class form: groups of one lane may lie in different classes; groups
-      // at the maximum in two classes mark the key for the atom-index rule
-      if (WAVES > 1) key = make_key(rv, u) | (uint64_t)(CLS && classes_hit<NJ, NJC>(hits) > 1);
+      // class form: groups of one lane may lie in different classes; a group
+      // at the maximum outside the first one's class marks the key for the
+      // atom-index rule
+      bool mark = false;
+      if constexpr (CLS) {
+        constexpr uint32_t one = (NJC >= 32) ? 0xFFFFFFFFu : ((1u << NJC) - 1u);
+        mark = (hits & ~(one << ((gsel / NJC) * NJC))) != 0u;
+      }
+      if (WAVES > 1) key = make_key(rv, u) | (uint64_t)mark;
     } else if (M != 0.0f) {
       // exact ties across lanes: every lane's first maximum as a key
       float bv = 0.0f;
@@ -333,18 +350,29 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
         // decided on the atom index (positions do not follow it across
         // classes): every wave keys its candidates at the maximum again
         const uint32_t kh = (uint32_t)(key >> 32);
-        uint32_t cm = 0u;                      // classes of the waves' winners at the maximum
-        bool marked = false;                   // a wave at the maximum holds it in two classes
+        int nmax = 0;                          // waves whose winner is at the maximum
+        bool marked = false;                   // one of them holds it in two classes
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) {
           const uint64_t o = s_key[par][w];
-          if ((uint32_t)(o >> 32) == kh) {
-            const int ow = 0xFFFF - (int)((uint32_t)o >> 16);
-            cm |= 1u << (ow / a.cl.Kc);
-            marked = marked || (o & 1u);
+          const bool at = (uint32_t)(o >> 32) == kh;
+          nmax += at;
+          marked = marked || (at && (o & 1u));
+        }
+        bool slow = kh != 0u && marked;
+        if (kh != 0u && nmax > 1 && !slow) {   // rare: winners of several waves tie
+          int c0 = -1;
+#pragma unroll
+          for (int w = 0; w < WAVES; ++w) {
+            const uint64_t o = s_key[par][w];
+            if ((uint32_t)(o >> 32) == kh) {
+              const int c = (0xFFFF - (int)((uint32_t)o >> 16)) / a.cl.Kc;
+              slow = slow || (c0 >= 0 && c != c0);
+              c0 = c;
+            }
           }
         }
-        if (kh != 0u && (marked || __builtin_popcount(cm) > 1)) {
+        if (slow) {
           const uint64_t k2 = class_tie_key<NJ, T>(R, kh, a.cl, t);
           if (lane == 0) s_tie[wave] = k2;
           __syncthreads();
@@ -462,14 +490,13 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
             R[cc * NJC + j][2] = fmaf(-tr, row[j].z, R[cc * NJC + j][2]);
             R[cc * NJC + j][3] = fmaf(-tr, row[j].w, R[cc * NJC + j][3]);
           }
-          if constexpr (INC) {                  // the class's new maxima
-            float m = 0.0f;
-#pragma unroll
-            for (int j = cc * NJC; j < (cc + 1) * NJC; ++j)
-              m = fmaxf(m, fmaxf(fmaxf(fabsf(R[j][0]), fabsf(R[j][1])),
-                                 fmaxf(fabsf(R[j][2]), fabsf(R[j][3]))));
-            lmc[cc] = m;
-            wmc[cc] = __float_as_uint(wave_max_f32(m));
+          if constexpr (INC) {                  // the class's new winner
+            switch (cc) {
+              case 0: class_winner<NJ, NJC, 0, T>(R, t, lmc[0], wmc[0], c_one[0], c_pos[0], c_val[0]); break;
+              case 1: class_winner<NJ, NJC, 1, T>(R, t, lmc[1], wmc[1], c_one[1], c_pos[1], c_val[1]); break;
+              case 2: class_winner<NJ, NJC, 2, T>(R, t, lmc[2], wmc[2], c_one[2], c_pos[2], c_val[2]); break;
+              default: class_winner<NJ, NJC, 3, T>(R, t, lmc[3], wmc[3], c_one[3], c_pos[3], c_val[3]); break;
+            }
           }
         }
     } else {

@@ -396,7 +396,9 @@ static se_status launch_batch(Server* s, std::vector<Req*>& reqs, Batch& bt) {
   // isolated blocks: cached tables of their pattern, one batched call each
   for (auto& e : g.iso) {
     const PatternKey& key = std::get<0>(e.first);
-    const se_params prm{std::get<1>(e.first), std::get<2>(e.first), 0};
+    // SE_INVARIANT: a batch mixes requests, and each request's result must
+    // not depend on which others share it
+    const se_params prm{std::get<1>(e.first), std::get<2>(e.first), SE_INVARIANT};
     CachedTables* ct = get_tables(s, key, st, work, work_bytes);
     std::vector<se_block>& blocks = e.second;
     if (!ct) {   // the budget cannot hold the tables: take the on-demand path
@@ -426,7 +428,7 @@ static se_status launch_batch(Server* s, std::vector<Req*>& reqs, Batch& bt) {
     rc = se_area_weights(b.M, b.N, s->cfg.rho_hat, s->slot_lost, nslot, H, W, blocks.data(), n,
                          w, aws, se_area_weights_ws_bytes(n), st);
     if (rc) return rc;
-    const se_params prm{e.first.second, 0, 0};
+    const se_params prm{e.first.second, 0, SE_INVARIANT};
     rc = se_extrapolate_ondemand(&b, w, s->slot_frames, nslot, H, W, blocks.data(), n, prm,
                                  e.second.second.data(), nullptr, nullptr, nullptr, 0, ows,
                                  ows_bytes, st);

@@ -289,8 +289,10 @@ def test_rejects_fixed_point_rows_on_host():
         return getattr(L, name)(C.byref(t), fake, 1, 64, 64, blk, 1, prm, None, None, None, 0,
                                 fake, 16, None)
     assert call("se_extrapolate_batch", B.se_params(0.5, 10, 0)) == B.SE_ENOMEM
-    assert call("se_extrapolate_batch", B.se_params(0.5, 10, 4)) == B.SE_EINVAL
+    assert call("se_extrapolate_batch", B.se_params(0.5, 10, 8)) == B.SE_EINVAL
     assert b"unknown flags" in L.se_last_error()
+    # SE_INVARIANT is accepted by every call (here it reaches the workspace check)
+    assert call("se_extrapolate_batch", B.se_params(0.5, 10, B.SE_INVARIANT)) == B.SE_ENOMEM
     for name in ("se_extrapolate_batch", "se_extrapolate_plain"):
         assert call(name, q14) == B.SE_EINVAL and b"SE_ROWS_Q14" in L.se_last_error()
     r = L.se_iterate(C.byref(t), fake, t.ldG, fake, 1, 64, 64, fake, 1, q14, None, None, None,

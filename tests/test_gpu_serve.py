@@ -174,3 +174,87 @@ def test_serve_queue_limit_and_errors():
     with pytest.raises(B.SEError):
         srv.poll(123456789)
     srv.close()
+
+
+def test_serve_full_hd_frames():
+    """The serving workload's frame size: 1920x1080 frames with 8x8 and 16x16
+    losses covering 5% of the frame (areas 32, 48, 64).  Each of two frames
+    is the same alone and among others, bit for bit.  The served frame equals,
+    bit for bit, the direct library calls on its blocks with SE_INVARIANT
+    (the blocks of an isolated pattern with that pattern's tables, the others
+    with rows on demand), and those calls' selections and models are held to
+    the FP64 oracle on 16 sampled blocks per dictionary (half of each kind
+    where the frame has them), with the window derived from the arithmetic."""
+    from helpers import describe, oracle_check
+    FH, FW = 1080, 1920
+    say("serve: 1920x1080 frames, 5% lost, 3 dictionaries, I=100")
+    bs = bases()
+    dev_bases = to_dev(bs, True)
+    srv = B.Server(dev_bases, FH, FW, max_slots=3, max_queue=8, n_streams=3,
+                   hbm_budget_bytes=6 << 30)
+    imgs = [synth.synth_image(FH, FW, seed=70 + i) for i in range(3)]
+    losses = [synth.frame_losses(FH, FW, 0.05, 80 + i) for i in range(3)]
+    frames = [torch.from_numpy(im.copy()).cuda() for im in imgs]
+    tickets = [srv.submit(f, L, 0.5, 100) for f, L in zip(frames, losses)]
+    for t in tickets:
+        assert srv.wait(t).status == 0
+    outs = [f.cpu().numpy() for f in frames]
+    for i in (0, 2):
+        f = torch.from_numpy(imgs[i].copy()).cuda()
+        assert srv.wait(srv.submit(f, losses[i], 0.5, 100)).status == 0
+        np.testing.assert_array_equal(f.cpu().numpy(), outs[i])
+    srv.close()
+    # frame 0: the direct calls on its blocks, then the oracle
+    img, out, L = imgs[0], outs[0], losses[0]
+    blocks = [(synth.Block(0, y - (bs[k][1] - h) // 2, x - (bs[k][2] - w) // 2,
+                           (bs[k][1] - h) // 2, (bs[k][2] - w) // 2, h, w), k)
+              for (y, x, h, w, k) in L]
+    lost = synth.lost_mask(FH, FW, [b for b, _ in blocks])
+    lost_d = torch.from_numpy(lost[None]).cuda()
+    rng = np.random.default_rng(5)
+    for k in range(len(bs)):
+        phi, M, N = bs[k]
+        phi_d, _, _, parts = dev_bases[k]
+        mine = [b for b, kk in blocks if kk == k]
+        inside = [b.y0 >= 0 and b.x0 >= 0 and b.y0 + M <= FH and b.x0 + N <= FW and
+                  lost[b.y0:b.y0 + M, b.x0:b.x0 + N].sum() == b.lh * b.lw for b in mine]
+        iso = [b for b, f in zip(mine, inside) if f]
+        own = [b for b, f in zip(mine, inside) if not f]
+        checked = 0
+        if iso:
+            w = B.area_weights(M, N, 0.8, lost_d, iso[:1])
+            t = B.weighted_gram(phi_d, w[0].contiguous(), M, N, parts=parts)
+            img_d = torch.from_numpy(img[None].copy()).cuda()
+            sel, coef, g = B.extrapolate_batch(t, img_d, iso, 0.5, 100, invariant=True)
+            torch.cuda.synchronize()
+            sel, coef, g, o = (x.cpu().numpy() for x in (sel, coef, g, img_d))
+            for b in iso:
+                y, x = b.y0 + b.ly, b.x0 + b.lx
+                np.testing.assert_array_equal(out[y:y + b.lh, x:x + b.lw],
+                                              o[0, y:y + b.lh, x:x + b.lw])
+            n = min(len(iso), 16 if not own else 8)
+            sample = sorted(rng.choice(len(iso), n, replace=False))
+            st = oracle_check(img[None], iso, phi, M, N, 0.8, 0.5, 100, sel, g, o, sample=sample,
+                              tol=1e-3, coef=coef, tables=t, lost=lost[None])
+            print(f"dictionary {k} ({M}x{N}), isolated pattern: {len(iso)} blocks, "
+                  f"{describe(st)}")
+            checked += n
+            del t
+        if own:
+            w = B.area_weights(M, N, 0.8, lost_d, own)
+            img_d = torch.from_numpy(img[None].copy()).cuda()
+            sel, coef, g = B.extrapolate_ondemand(phi_d, M, N, w, img_d, own, 0.5, 100,
+                                                  parts=parts, invariant=True)
+            torch.cuda.synchronize()
+            sel, coef, g, o = (x.cpu().numpy() for x in (sel, coef, g, img_d))
+            for b in own:
+                y, x = b.y0 + b.ly, b.x0 + b.lx
+                np.testing.assert_array_equal(out[y:y + b.lh, x:x + b.lw],
+                                              o[0, y:y + b.lh, x:x + b.lw])
+            n = min(len(own), 16 - checked)
+            sample = sorted(rng.choice(len(own), n, replace=False))
+            st = oracle_check(img[None], own, phi, M, N, 0.8, 0.5, 100, sel, g, o, sample=sample,
+                              tol=1e-3, lost=lost[None])
+            print(f"dictionary {k} ({M}x{N}), own weights: {len(own)} blocks, {describe(st)}")
+            checked += n
+        assert checked >= 16
