@@ -786,9 +786,33 @@ def bench_video(args):
                         "loop_bytes_per_block": bytes_per_block, "gram_ms": min(gram)}}
 
 
+def _row_requests(sel, iters, cached):
+    """Table rows formed on demand for one group: per block, the iterations
+    before its last whose selected atom needs a new row (every one without a
+    row cache; with every row cached, only atoms new to the block)."""
+    n = 0
+    for b, it in enumerate(iters):
+        seq = sel[b, :it]
+        if it < 2 or seq[0] < 0:
+            continue
+        if cached:
+            seen = set()
+            for u in seq[:it - 1]:
+                if int(u) not in seen:
+                    seen.add(int(u))
+                    n += 1
+        else:
+            n += it - 1
+    return n
+
+
 def bench_clustered(args):
     """Uneven batch: 8 1024x1024 frames with clustered/burst losses, 4000
-    blocks, areas 24/32/48, per-block weights (rows on demand), I ~ U{100..200}."""
+    blocks, areas 24/32/48, per-block weights (rows on demand), I ~ U{100..200}.
+    Routes: the one call per area group (se_extrapolate_ondemand: part
+    verification, phi squared and the descriptor upload in every call), and
+    prepared dictionaries + plans whose runs cache each block's table rows,
+    eager and as one captured HIP graph of the three groups on three streams."""
     import torch
     from paper_2204_14194_amd import binding as B
     dev = torch.device("cuda:0")
@@ -805,35 +829,121 @@ def bench_clustered(args):
         it = [int(iters[i]) for i in idx]
         phi = torch.from_numpy(d["dicts"][area].astype(np.float32)).to(dev)
         w = B.area_weights(area, area, RHO, lost_d, bl)
-        groups.append((phi, area, w, bl, it, streams[k],
-                       () if args.no_parts else d["tx_parts"][area]))
+        groups.append(dict(area=area, phi=phi, w=w, blocks=bl, iters=it, stream=streams[k],
+                           parts=() if args.no_parts else d["tx_parts"][area]))
+    n_blk = len(blocks)
+    steps = max(2, args.steps // 4)
 
-    def step(rows_bf16=False):
+    def call_step(rows_bf16=False):
         cur = torch.cuda.current_stream()
-        for phi, area, w, bl, it, st, parts in groups:
+        for g in groups:
+            st = g["stream"]
             st.wait_stream(cur)
             with torch.cuda.stream(st):
-                B.extrapolate_ondemand(phi, area, area, w, img, bl, 0.5, it, False, False, False,
-                                       stream=st, parts=parts, rows_bf16=rows_bf16)
+                B.extrapolate_ondemand(g["phi"], g["area"], g["area"], g["w"], img, g["blocks"],
+                                       0.5, g["iters"], False, False, False, stream=st,
+                                       parts=g["parts"], rows_bf16=rows_bf16)
         for g in groups:
-            cur.wait_stream(g[5])
+            cur.wait_stream(g["stream"])
 
-    ms = _timed(step, max(1, args.steps // 4), 1)
-    med = float(np.median(ms))
-    # the dense atoms' row products from split-BF16 operands (SE_ROWS_BF16X3)
-    ms_bf = _timed(lambda: step(True), max(1, args.steps // 4), 1)
-    med_bf = float(np.median(ms_bf))
+    call_ms = float(np.median(_timed(call_step, steps, 1)))
+    call_bf_ms = float(np.median(_timed(lambda: call_step(True), steps, 1)))
+
+    def make_plans(rows_bf16, slots):
+        plans = []
+        for g in groups:
+            dd = B.OnDemandDict(g["phi"], g["area"], g["area"], parts=g["parts"],
+                                rows_bf16=rows_bf16)
+            plans.append((dd, B.OnDemandPlan(dd, img, g["blocks"], 0.5, g["iters"],
+                                             row_slots=slots, rows_bf16=rows_bf16)))
+        return plans
+
+    def plan_step(plans, outs=None):
+        cur = torch.cuda.current_stream()
+        for k, (g, (_, pl)) in enumerate(zip(groups, plans)):
+            st = g["stream"]
+            st.wait_stream(cur)
+            o = outs[k] if outs else (None, None, None)
+            try:
+                pl.run(g["w"], img, *o, stream=st)
+            except B.SENumericError:
+                pass
+        for g in groups:
+            cur.wait_stream(g["stream"])
+
+    def route(rows_bf16, slots, want_counts=False):
+        plans = make_plans(rows_bf16, slots)
+        res = {}
+        if want_counts:   # selections of one eager run give the rows formed
+            outs = [pl.outputs(dev, True, False, False) for _, pl in plans]
+            plan_step(plans, outs)
+            torch.cuda.synchronize()
+            res["sel"] = [o[0].cpu().numpy() for o in outs]
+        res["eager_ms"] = float(np.median(_timed(lambda: plan_step(plans), steps, 1)))
+        if not args.no_graph:
+            main = torch.cuda.Stream()
+            main.wait_stream(torch.cuda.current_stream())
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=main):
+                plan_step(plans)
+            res["graph_ms"] = float(np.median(_timed(graph.replay, steps, 1)))
+            del graph
+        for dd, pl in plans:
+            pl.close()
+            dd.close()
+        torch.cuda.empty_cache()
+        return res
+
+    cached = route(False, None, want_counts=True)
+    uncached = route(False, 0)
+    cached_bf = route(True, None)
+    # the dense row products (plus the diagonal and projection products of
+    # every block) in FP32 matrix-core flops per batch
+    flops = 0.0
+    rows_formed = {}
+    for g, sel in zip(groups, cached["sel"]):
+        A = g["area"] * g["area"]
+        K = g["phi"].shape[0]
+        kd = K - sum(A for _ in g["parts"])
+        req = _row_requests(sel, g["iters"], True)
+        rows_formed[str(g["area"])] = {"cached": req,
+                                       "every_use": _row_requests(sel, g["iters"], False)}
+        flops += 2.0 * kd * A * req + 2 * 2.0 * K * A * len(g["blocks"])
+    best = cached.get("graph_ms", cached["eager_ms"])
+    prof = _profile_values(256, "ondemand_clustered_kernel_stats.txt",
+                           ["gemm.hip", "ondemand.hip", "transform.hip", "abi.cpp"])
+    gemm = {"flops_per_batch": flops, "peak_tflops": 157.3,
+            "what": "FP32 matrix-core flops of the dense row products (rows formed, from the "
+                    "selections of one run, x 2 x dense atoms x M*N) and the per-block diagonal "
+                    "and projection products, per batch; k_gemm_nt_f32 time from the committed "
+                    "kernel statistics of the same sources"}
+    if prof is not None and "gemm_f32_ms_per_batch" in prof:
+        gms = float(prof["gemm_f32_ms_per_batch"])
+        gemm.update({"kernel_ms_per_batch": gms, "tflops": flops / (gms * 1e-3) / 1e12,
+                     "frac": flops / (gms * 1e-3) / 1e12 / 157.3})
+    else:
+        gemm.update({"kernel_ms_per_batch": None, "tflops": None, "frac": None})
     return {"metric": "concealed blocks/s, uneven batch with per-block weights (rows on demand)",
-            "value": len(blocks) / (med * 1e-3), "unit": "blocks/s", "n_gpus": 1,
-            "steps": len(ms), "warmup": 1, "ms_per_step": med, "higher_is_better": True,
+            "value": n_blk / (best * 1e-3), "unit": "blocks/s", "n_gpus": 1,
+            "steps": steps, "warmup": 1, "ms_per_step": best, "higher_is_better": True,
             "dtype": "f32", "data": "synthetic",
             "config": {"workload": "8 x 1024x1024 frames, 4000 clustered/burst 8x8 and 16x16 "
                                    "losses, areas 24/32/48 (K=1152/2048/4608), I~U{100..200}, "
-                                   "one dictionary group per stream"},
-            "blocks_per_area": {str(a): len(g[3]) for a, g in zip((24, 32, 48), groups)},
-            "rows_bf16x3": {"ms_per_step": med_bf, "blocks_per_s": len(blocks) / (med_bf * 1e-3),
-                            "what": "the dense atoms' row products from split-BF16 operands "
-                                    "(SE_ROWS_BF16X3); FP32 accumulation"}}
+                                   "one dictionary group per stream",
+                       "route": "prepared dictionaries + plans, every table row cached per "
+                                "block, the three groups as one captured HIP graph"
+                                if "graph_ms" in cached else
+                                "prepared dictionaries + plans, every table row cached, eager"},
+            "blocks_per_area": {str(g["area"]): len(g["blocks"]) for g in groups},
+            "rows_formed": rows_formed,
+            "routes_ms": {"call_fp32": call_ms, "call_bf16x3_rows": call_bf_ms,
+                          "plan_cached_eager": cached["eager_ms"],
+                          "plan_cached_graph": cached.get("graph_ms"),
+                          "plan_uncached_eager": uncached["eager_ms"],
+                          "plan_uncached_graph": uncached.get("graph_ms"),
+                          "plan_cached_bf16x3_rows_eager": cached_bf["eager_ms"],
+                          "plan_cached_bf16x3_rows_graph": cached_bf.get("graph_ms")},
+            "row_gemm": gemm}
 
 
 def cpu_baseline_area64(d, sample, iters):
@@ -930,7 +1040,7 @@ def bench_area64(args):
             e0.record()
             w = B.area_weights(64, 64, RHO, lost_d, blocks[:1])
             t = B.weighted_gram(phi_d, w[0].contiguous(), 64, 64, prec, parts=parts,
-                                fixed_point=bool(parts))
+                                fixed_point=bool(parts), fixed_point_rows=not parts)
             e1.record()
             e1.synchronize()
             runs.append(e0.elapsed_time(e1))
@@ -966,6 +1076,24 @@ def bench_area64(args):
             sel, _, g = B.extrapolate_batch(t, img2, blocks, GAMMA, iters, want_coef=False)
             torch.cuda.synchronize()
             e["precision"] = _precision_report(leg, sample, sel.cpu().numpy(), g.cpu().numpy())
+        # the same loop reading whole rows as 16-bit words (SE_ROWS_Q14):
+        # half the bytes of each streamed row
+        loop_q = _timed(lambda: B.iterate(t, R, img, dblk, GAMMA, iters, rows_q14=True),
+                        max(2, args.steps // 4), 1)
+        step_q = float(np.median(proj)) + float(np.median(loop_q))
+        q = {"loop_ms": float(np.median(loop_q)), "ms_per_step": step_q,
+             "blocks_per_s": n / (step_q * 1e-3),
+             "faster_than_fp32_rows": bool(step_q < step),
+             "what": "the loop over whole rows reading G as 16-bit words with 14 fraction "
+                     "bits (SE_ROWS_Q14, Gq_rows); projections as above"}
+        if leg is not None:
+            img2 = torch.from_numpy(d["images"]).to(dev)
+            sel, _, g = B.extrapolate_batch(t, img2, blocks, GAMMA, iters, want_coef=False,
+                                            rows_q14=True)
+            torch.cuda.synchronize()
+            q["precision"] = _precision_report(leg, sample, sel.cpu().numpy(), g.cpu().numpy())
+            q["precision"]["reference"] = "the FP64 oracle on FP64 tables (not on the words)"
+        e["rows_q14"] = q
         out["dense"][name] = e
         del t, R, ws
 

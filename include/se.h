@@ -217,7 +217,15 @@ typedef struct {
  *          14 fraction bits, Gq = round(Gc * 2^14) to nearest, ties to even
  *          (|Gc| <= 1, so no word saturates and the diagonal 1 is exact);
  * a loop called with SE_ROWS_Q14 then streams these words (a quarter of
- * the class rows' bytes) and updates R with Gq * 2^-14 in FP32. */
+ * the class rows' bytes) and updates R with Gq * 2^-14 in FP32.
+ * Fixed-point whole rows (optional; Gq_rows may be NULL): for a real
+ * dictionary, when Gq_rows is non-NULL se_weighted_gram also writes
+ *   Gq_rows : K x ldG int16, 16-byte aligned: G in the same words,
+ *          round(G * 2^14) to nearest, ties to even (|G| <= 1; columns K ..
+ *          ldG-1 hold 0);
+ * the loop over whole rows (the route of tables without the one-launch
+ * form, se_iterate and se_extrapolate_plain) called with SE_ROWS_Q14 then
+ * streams these words (half the bytes of a row of G). */
 typedef struct {
   int32_t M, N, K, ldG;
   float* G;
@@ -239,17 +247,22 @@ typedef struct {
   int32_t* cls;
   int32_t n_classes;     /* written by se_weighted_gram: 4 or 0            */
   int16_t* Gq;           /* fixed-point class rows (may be NULL, see above) */
+  int16_t* Gq_rows;      /* fixed-point whole rows (may be NULL, see above) */
 } se_tables;
 
 /* Model-generation parameters: gamma of eq. 8 (0 < gamma <= 1), the
  * iteration count I, and flags:
- *   SE_ROWS_Q14 : the loop reads the fixed-point class rows Gq instead of
- *                 Gc (eq. 20 with the table entries quantised as described
+ *   SE_ROWS_Q14 : the loop reads fixed-point words instead of FP32 table
+ *                 entries (eq. 20 with the entries quantised as described
  *                 for se_tables; R, D, the coefficients and the model stay
- *                 FP32).  Accepted by se_extrapolate_batch and
- *                 se_extrapolate_device on tables with n_classes = 4 and
- *                 Gq written; every other call, and those calls on other
- *                 tables, return SE_EINVAL. */
+ *                 FP32): the class rows Gq on the one-launch route
+ *                 (se_extrapolate_batch and se_extrapolate_device on tables
+ *                 with n_classes = 4 and Gq written), the whole rows
+ *                 Gq_rows on the loop over whole rows (those calls on
+ *                 tables without the one-launch form, se_iterate and
+ *                 se_extrapolate_plain, on real tables with Gq_rows
+ *                 written).  Every other case, and rows on demand, return
+ *                 SE_EINVAL. */
 #define SE_ROWS_Q14 1u
 /*   SE_ROWS_BF16X3 : rows on demand only (se_extrapolate_ondemand): the
  *                 per-iteration products of the dictionary's dense atoms
@@ -528,7 +541,9 @@ se_status se_autotune_batch(const se_tables* t, uint8_t* images, int32_t n_img,
                             int32_t n_blk, se_params prm, float* R,
                             int32_t ldR, void* ws, size_t ws_bytes,
                             int32_t reps, void* stream, se_tune_result* out);
-/* The records as text, one "K MN bucket waves vpl tile" line per entry;
+/* The records as text, one "K MN bucket waves vpl tile" line per entry of
+ * the batched path and one "rows Kd MN bucket tile split" line per entry of
+ * se_autotune_ondemand;
  * returns the length (without the terminating 0) and writes at most cap-1
  * characters plus a terminating 0 into buf (may be NULL). */
 int32_t se_tune_export(char* buf, int32_t cap);
@@ -579,6 +594,91 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w,
                                   float* coef, float* g_loss,
                                   int32_t g_loss_ld, void* ws, size_t ws_bytes,
                                   void* stream);
+
+/* The same computation split into a preparation per dictionary, a plan per
+ * batch and runs of a plan, for callers that conceal many batches with one
+ * dictionary, or capture the work in a HIP graph.
+ *
+ * Prepared dictionary (se_ondemand_prepare): the declared transform parts
+ * are verified against phi once, here (the call synchronises `stream`),
+ * and phi squared (the per-block diagonals C_b[k][k] of eq. 16 are its
+ * products with w_b), the transform operands and, with SE_ROWS_BF16X3 in
+ * flags, the split-BF16 dictionary are formed and kept on the device,
+ * allocated by the library (freed by se_ondemand_release).  The dictionary
+ * keeps a copy of *b and reads phi through it: phi must stay valid and
+ * unchanged while the dictionary is used.  Errors: SE_EINVAL as for
+ * se_extrapolate_ondemand's basis checks or an unknown flag (only
+ * SE_ROWS_BF16X3 is known), SE_ENOMEM if the device memory cannot be
+ * allocated, SE_EHIP; nothing is returned in *out then.
+ *
+ * Plan (se_ondemand_plan_create): the block checks, the order of the
+ * blocks by decreasing iteration count and the device copies of their
+ * descriptors (copied here, then the call synchronises `stream`), for
+ * images of n_img x H x W.  The plan keeps pointers into `ws` and the
+ * dictionary: both must outlive it.  prm.flags: 0, SE_ROWS_BF16X3 (the
+ * dictionary must have been prepared with it) and SE_INVARIANT, as for
+ * se_extrapolate_ondemand.
+ *   row_slots : table rows cached per block.  A block that selects an atom
+ *             whose row it has cached reuses that row (eq. 16's row of an
+ *             atom depends only on the block's weights), so only the rows
+ *             of atoms new to a block are formed; the first row_slots
+ *             distinct atoms of a block are cached and later new ones are
+ *             formed on every selection.  0 forms every row on use, as
+ *             se_extrapolate_ondemand does; the largest iteration count
+ *             caches every row (values above it, or above K, act as it).
+ *             Results do not depend on row_slots: a cached row holds the
+ *             values the product would form again.
+ *   ws      : device, se_ondemand_plan_ws_bytes(d, n_blk, max_loss,
+ *             row_slots) bytes (max_loss as for se_extrapolate_ondemand);
+ *             the cache takes n_blk * (row_slots + 1) rows of K rounded
+ *             up to a multiple of 1024 floats, and with row_slots > 0 a
+ *             map of n_blk * K int32.
+ * se_ondemand_plan_info returns the plan's block count (-1 for NULL) and
+ * writes, where not NULL, its largest iteration count (the stride of sel
+ * and coef), largest loss (the least g_loss_ld) and rows cached per block.
+ *
+ * Run (se_ondemand_run): conceals the plan's blocks, with results as
+ * se_extrapolate_ondemand's for the same blocks, weights w, images,
+ * prm and iteration counts (outputs as described there).  A run only
+ * launches kernels on `stream`, with launch shapes fixed by the plan: no
+ * copy, no memory fill through the runtime, no allocation, no
+ * synchronisation, so it can be captured in a HIP graph and replayed (each
+ * replay recomputes everything from w and the images).  Runs of one plan
+ * share its workspace: runs that overlap in time (on different streams)
+ * race; serialise them.  Returns SE_ENUMERIC, after completing the work,
+ * if some blocks have no available sample, as se_extrapolate_ondemand.
+ *
+ * se_autotune_ondemand times the row products' tile (64 or 128) and split
+ * of the contraction (1, 2, 4 or 8 slices, or the automatic rule) on runs
+ * of the plan (`reps` each after a warm-up, synchronising `stream`;
+ * images are rewritten with the same values, sel/coef/g_loss not written),
+ * records the fastest per (dense atoms, M*N, block-count bucket) for
+ * later plans, and sets it in this plan.  A split other than none changes
+ * the order of the FP32 sums (results stay within the FP32 rounding of the
+ * products); SE_INVARIANT plans never split.  SE_EINVAL if the plan has
+ * no dense atoms (every row a transform) or no blocks. */
+typedef struct se_od_dict se_od_dict;
+typedef struct se_od_plan se_od_plan;
+se_status se_ondemand_prepare(const se_basis* b, uint32_t flags, se_od_dict** out,
+                              void* stream);
+void se_ondemand_release(se_od_dict* d);
+size_t se_ondemand_plan_ws_bytes(const se_od_dict* d, int32_t n_blk, int32_t max_loss,
+                                 int32_t row_slots);
+se_status se_ondemand_plan_create(const se_od_dict* d, int32_t n_img, int32_t H, int32_t W,
+                                  const se_block* blocks, int32_t n_blk, se_params prm,
+                                  const int32_t* iters, int32_t row_slots, void* ws,
+                                  size_t ws_bytes, void* stream, se_od_plan** out);
+int32_t se_ondemand_plan_info(const se_od_plan* p, int32_t* iters_max, int32_t* max_loss,
+                              int32_t* row_slots);
+se_status se_ondemand_run(const se_od_plan* p, const float* w, uint8_t* images, int32_t* sel,
+                          float* coef, float* g_loss, int32_t g_loss_ld, void* stream);
+void se_ondemand_plan_release(se_od_plan* p);
+typedef struct {
+  int32_t row_tile, row_split;  /* 0 / -1: the automatic rules */
+  float run_ms;                 /* best measured run time */
+} se_tune_rows_result;
+se_status se_autotune_ondemand(se_od_plan* p, const float* w, uint8_t* images, int32_t reps,
+                               void* stream, se_tune_rows_result* out);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of concealment requests                      */

@@ -100,7 +100,7 @@ class se_tables(C.Structure):
                 ("n_parts", C.c_int32), ("parts", se_part * 2), ("tx", C.c_void_p),
                 ("G_im", C.c_void_p), ("phi_im", C.c_void_p), ("T", C.c_int32),
                 ("Gc", C.c_void_p), ("cls", C.c_void_p), ("n_classes", C.c_int32),
-                ("Gq", C.c_void_p)]
+                ("Gq", C.c_void_p), ("Gq_rows", C.c_void_p)]
 
 
 class se_params(C.Structure):
@@ -169,6 +169,23 @@ def lib():
     L.se_extrapolate_ondemand.restype = i32
     L.se_extrapolate_ondemand.argtypes = [C.POINTER(se_basis), vp, vp, i32, i32, i32, vp, i32,
                                           se_params, vp, vp, vp, vp, i32, vp, sz, vp]
+    L.se_ondemand_prepare.restype = i32
+    L.se_ondemand_prepare.argtypes = [C.POINTER(se_basis), C.c_uint32, C.POINTER(vp), vp]
+    L.se_ondemand_release.restype = None
+    L.se_ondemand_release.argtypes = [vp]
+    L.se_ondemand_plan_ws_bytes.restype = sz
+    L.se_ondemand_plan_ws_bytes.argtypes = [vp, i32, i32, i32]
+    L.se_ondemand_plan_create.restype = i32
+    L.se_ondemand_plan_create.argtypes = [vp, i32, i32, i32, vp, i32, se_params, vp, i32, vp, sz,
+                                          vp, C.POINTER(vp)]
+    L.se_ondemand_plan_info.restype = i32
+    L.se_ondemand_plan_info.argtypes = [vp, vp, vp, vp]
+    L.se_ondemand_run.restype = i32
+    L.se_ondemand_run.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp]
+    L.se_ondemand_plan_release.restype = None
+    L.se_ondemand_plan_release.argtypes = [vp]
+    L.se_autotune_ondemand.restype = i32
+    L.se_autotune_ondemand.argtypes = [vp, vp, vp, i32, vp, vp]
     _lib = L
     return L
 
@@ -293,6 +310,7 @@ class Tables:
     cls: Optional[torch.Tensor] = None
     n_classes: int = 0
     Gq: Optional[torch.Tensor] = None
+    Gq_rows: Optional[torch.Tensor] = None
 
     @property
     def complex(self) -> bool:
@@ -316,19 +334,21 @@ class Tables:
                          self.phi_im.data_ptr() if self.phi_im is not None else None, self.T,
                          self.Gc.data_ptr() if self.Gc is not None else None,
                          self.cls.data_ptr() if self.cls is not None else None, self.n_classes,
-                         self.Gq.data_ptr() if self.Gq is not None else None)
+                         self.Gq.data_ptr() if self.Gq is not None else None,
+                         self.Gq_rows.data_ptr() if self.Gq_rows is not None else None)
 
     def nbytes(self) -> int:
         parts = [self.G, self.D, self.Y, self.sqrtw]
-        parts += [x for x in (self.Yhi, self.Ylo, self.G_im, self.Gc, self.cls, self.Gq)
-                  if x is not None]
+        parts += [x for x in (self.Yhi, self.Ylo, self.G_im, self.Gc, self.cls, self.Gq,
+                              self.Gq_rows) if x is not None]
         return sum(t.numel() * t.element_size() for t in parts)
 
 
 def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
                   precision: int = SE_FP32, flags: int = SE_DIAG_AUTO, stream=None,
                   parts=(), phi_im: Optional[torch.Tensor] = None, T: int = 1,
-                  classes: bool = True, fixed_point: bool = False) -> Tables:
+                  classes: bool = True, fixed_point: bool = False,
+                  fixed_point_rows: bool = False) -> Tables:
     """se_weighted_gram (Algorithm 2) for dictionary ``phi`` (K, T*M*N) and
     weight pattern ``w`` (T*M*N,).  ``parts``: declared transform ranges, as
     (SE_PART_*, first atom) pairs (verified by the library).  ``phi_im``: the
@@ -338,7 +358,10 @@ def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
     class tables (used when the library finds the class structure; then
     ``n_classes`` is 4).  ``fixed_point``: also offer the buffer of the class
     rows as 16-bit words with 14 fraction bits (``Gq``, kept only with class
-    tables), which loops called with ``rows_q14=True`` read."""
+    tables), which loops called with ``rows_q14=True`` read.
+    ``fixed_point_rows``: also write every whole row of G in those words
+    (``Gq_rows``, real dictionaries), which the loop over whole rows reads
+    when called with ``rows_q14=True``."""
     L = lib()
     _dev_f32(phi, "phi")
     _dev_f32(w, "w")
@@ -377,6 +400,8 @@ def weighted_gram(phi: torch.Tensor, w: torch.Tensor, M: int, N: int,
         t.cls = torch.empty((K, 2), dtype=torch.int32, device=dev)
         if fixed_point:
             t.Gq = torch.empty((K, K // 4), dtype=torch.int16, device=dev)
+    if fixed_point_rows and phi_im is None:
+        t.Gq_rows = torch.empty((K, ldG), dtype=torch.int16, device=dev)
     b = make_basis(M, N, K, phi.data_ptr(), t.parts,
                    phi_im.data_ptr() if phi_im is not None else None, int(T))
     nb = L.se_weighted_gram_ws_bytes(C.byref(b), int(precision))
@@ -430,8 +455,9 @@ def extrapolate_batch(t: Tables, images: torch.Tensor, blocks: Sequence, gamma: 
                       invariant: bool = False):
     """se_extrapolate_batch (Algorithm 3, batched).  ``images`` is modified in
     place (each loss replaced).  Returns (sel, coef, g_loss) device tensors
-    (None where not requested).  ``rows_q14``: the loop reads the fixed-point
-    class rows (SE_ROWS_Q14); ``invariant``: SE_INVARIANT."""
+    (None where not requested).  ``rows_q14``: the loop reads fixed-point
+    words (SE_ROWS_Q14: the class rows on the one-launch route, the whole
+    rows Gq_rows on the loop over whole rows); ``invariant``: SE_INVARIANT."""
     return _extrapolate("se_extrapolate_batch", t, images, blocks, gamma, iters, want_sel,
                         want_coef, want_g, ws, stream, blocks_arr,
                         (SE_ROWS_Q14 if rows_q14 else 0) | (SE_INVARIANT if invariant else 0))
@@ -466,10 +492,12 @@ def extrapolate_batch_static(t: Tables, images: torch.Tensor, blocks: Sequence, 
 
 def extrapolate_plain(t: Tables, images: torch.Tensor, blocks: Sequence, gamma: float,
                       iters: int, want_sel=True, want_coef=True, want_g=True, ws=None,
-                      stream=None, blocks_arr=None):
-    """se_extrapolate_plain: same results, one block at a time."""
+                      stream=None, blocks_arr=None, rows_q14: bool = False):
+    """se_extrapolate_plain: same results, one block at a time.  ``rows_q14``:
+    the loop reads the whole-row words Gq_rows (SE_ROWS_Q14)."""
     return _extrapolate("se_extrapolate_plain", t, images, blocks, gamma, iters, want_sel,
-                        want_coef, want_g, ws, stream, blocks_arr)
+                        want_coef, want_g, ws, stream, blocks_arr,
+                        flags=SE_ROWS_Q14 if rows_q14 else 0)
 
 
 # ---------------------------------------------------------------------------
@@ -512,15 +540,18 @@ def project_ws_bytes(t: Tables, n_blk: int) -> int:
 
 
 def iterate(t: Tables, R: torch.Tensor, images: torch.Tensor, dblocks: DeviceBlocks,
-            gamma: float, iters: int, sel=None, coef=None, g_loss=None, stream=None):
-    """se_iterate: the iteration loop and the paste, from R."""
+            gamma: float, iters: int, sel=None, coef=None, g_loss=None, stream=None,
+            rows_q14: bool = False):
+    """se_iterate: the iteration loop and the paste, from R.  ``rows_q14``:
+    the loop reads the whole-row words Gq_rows (SE_ROWS_Q14)."""
     L = lib()
     n_img, H, W = images.shape
     st = t.struct()
     gld = g_loss.shape[1] if g_loss is not None else 0
+    prm = se_params(float(gamma), int(iters), SE_ROWS_Q14 if rows_q14 else 0)
     _check(L.se_iterate(C.byref(st), _ptr(R), R.shape[1], _ptr(images), n_img, H, W,
-                        _ptr(dblocks.buf), dblocks.n, se_params(float(gamma), int(iters), 0),
-                        _ptr(sel), _ptr(coef), _ptr(g_loss), gld, _stream(stream)))
+                        _ptr(dblocks.buf), dblocks.n, prm, _ptr(sel), _ptr(coef), _ptr(g_loss),
+                        gld, _stream(stream)))
 
 
 def extrapolate_device_ws_bytes(t: Tables, n_blk: int) -> int:
@@ -586,6 +617,106 @@ def extrapolate_ondemand(phi: torch.Tensor, M: int, N: int, w: torch.Tensor,
                           (sel, coef, g))
 
 
+class se_tune_rows_result(C.Structure):
+    _fields_ = [("row_tile", C.c_int32), ("row_split", C.c_int32), ("run_ms", C.c_float)]
+
+
+class OnDemandDict:
+    """se_ondemand_prepare: a dictionary prepared once for rows on demand
+    (parts verified, phi squared and, with ``rows_bf16``, the split copy kept
+    on the device).  ``phi`` is kept referenced while the object lives."""
+
+    def __init__(self, phi: torch.Tensor, M: int, N: int, parts=(), rows_bf16: bool = False,
+                 stream=None):
+        L = lib()
+        _dev_f32(phi, "phi")
+        self.phi, self.M, self.N, self.K = phi, M, N, phi.shape[0]
+        self.rows_bf16 = rows_bf16
+        self._bas = make_basis(M, N, self.K, phi.data_ptr(), parts)
+        h = C.c_void_p()
+        _check(L.se_ondemand_prepare(C.byref(self._bas), SE_ROWS_BF16X3 if rows_bf16 else 0,
+                                     C.byref(h), _stream(stream)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().se_ondemand_release(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class OnDemandPlan:
+    """se_ondemand_plan_create: the blocks of one batch ordered, checked and
+    uploaded once, with their own workspace (``row_slots`` cached table rows
+    per block; None caches every row).  ``run`` launches kernels only and
+    may be captured in a graph."""
+
+    def __init__(self, d: OnDemandDict, images: torch.Tensor, blocks: Sequence, gamma: float,
+                 iters, row_slots=None, rows_bf16: bool = False, invariant: bool = False,
+                 stream=None):
+        L = lib()
+        self.d = d
+        n_img, H, W = images.shape
+        n = len(blocks)
+        self.n = n
+        if isinstance(iters, int):
+            per, imax = None, iters
+        else:
+            per = (C.c_int32 * max(n, 1))(*[int(v) for v in iters])
+            imax = max([int(v) for v in iters] + [0])
+        self.gld = max([loss_size(b) for b in blocks] + [1])
+        slots = imax if row_slots is None else int(row_slots)
+        nb = L.se_ondemand_plan_ws_bytes(d.handle, n, self.gld, slots)
+        self.ws = _workspace(nb, images.device)
+        prm = se_params(float(gamma), int(imax), (SE_ROWS_BF16X3 if rows_bf16 else 0) |
+                        (SE_INVARIANT if invariant else 0))
+        h = C.c_void_p()
+        _check(L.se_ondemand_plan_create(d.handle, n_img, H, W, blocks_array(blocks), n, prm, per,
+                                         slots, _ptr(self.ws), self.ws.numel(), _stream(stream),
+                                         C.byref(h)))
+        self.handle = h
+        im, ml, rs = C.c_int32(), C.c_int32(), C.c_int32()
+        L.se_ondemand_plan_info(h, C.byref(im), C.byref(ml), C.byref(rs))
+        self.iters_max, self.max_loss, self.row_slots = im.value, ml.value, rs.value
+
+    def outputs(self, device, want_sel=True, want_coef=True, want_g=True):
+        n, im = self.n, self.iters_max
+        sel = torch.empty((n, im), dtype=torch.int32, device=device) if want_sel else None
+        coef = torch.empty((n, im), dtype=torch.float32, device=device) if want_coef else None
+        g = torch.zeros((n, self.gld), dtype=torch.float32, device=device) if want_g else None
+        return sel, coef, g
+
+    def run(self, w: torch.Tensor, images: torch.Tensor, sel=None, coef=None, g=None,
+            stream=None):
+        """se_ondemand_run into the given outputs (None: not written)."""
+        _dev_f32(w, "w")
+        return _check_results(lib().se_ondemand_run(self.handle, _ptr(w), _ptr(images), _ptr(sel),
+                                                    _ptr(coef), _ptr(g), self.gld,
+                                                    _stream(stream)), (sel, coef, g))
+
+    def autotune(self, w: torch.Tensor, images: torch.Tensor, reps: int = 2, stream=None):
+        out = se_tune_rows_result()
+        _check(lib().se_autotune_ondemand(self.handle, _ptr(w), _ptr(images), int(reps),
+                                          _stream(stream), C.byref(out)))
+        return out.row_tile, out.row_split, out.run_ms
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().se_ondemand_plan_release(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # ---------------------------------------------------------------------------
 # serving
 # ---------------------------------------------------------------------------
@@ -640,8 +771,12 @@ def _serve_lib():
 
 SERVE_EXPORTED = ("se_serve_create", "se_serve_submit", "se_serve_poll", "se_serve_wait",
                   "se_serve_stats_get", "se_serve_destroy")
-TUNE_EXPORTED = ("se_autotune_batch", "se_tune_export", "se_tune_import", "se_tune_clear")
-EXPORTED = EXPORTED + SERVE_EXPORTED + TUNE_EXPORTED
+TUNE_EXPORTED = ("se_autotune_batch", "se_tune_export", "se_tune_import", "se_tune_clear",
+                 "se_autotune_ondemand")
+PLAN_EXPORTED = ("se_ondemand_prepare", "se_ondemand_release", "se_ondemand_plan_ws_bytes",
+                 "se_ondemand_plan_create", "se_ondemand_plan_info", "se_ondemand_run",
+                 "se_ondemand_plan_release")
+EXPORTED = EXPORTED + SERVE_EXPORTED + TUNE_EXPORTED + PLAN_EXPORTED
 
 
 class Server:

@@ -524,6 +524,8 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
   if (prec != SE_FP32 && prec != SE_BF16X3) return fail(SE_EINVAL, "unknown precision %d", (int)prec);
   if (flags > SE_DIAG_FP32) return fail(SE_EINVAL, "unknown flags 0x%x", flags);
   if (reinterpret_cast<uintptr_t>(t->Gq) % 16) return fail(SE_EINVAL, "Gq must be 16-byte aligned");
+  if (reinterpret_cast<uintptr_t>(t->Gq_rows) % 16)
+    return fail(SE_EINVAL, "Gq_rows must be 16-byte aligned");
   t->M = b->M;
   t->N = b->N;
   t->K = b->K;
@@ -613,10 +615,14 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
       if (t->Gq && (st = quantise_classes(t, s))) return st;
       t->n_classes = 4;
     }
-    return SE_OK;
+  } else {
+    st = prec == SE_FP32 ? gemm_syrk_f32(t->Y, P, K, P, t->G, t->ldG, s)
+                         : gemm_syrk_bf16x3(t->Yhi, t->Ylo, P, K, P, t->G, t->ldG, s);
+    if (st) return st;
   }
-  if (prec == SE_FP32) return gemm_syrk_f32(t->Y, P, K, P, t->G, t->ldG, s);
-  return gemm_syrk_bf16x3(t->Yhi, t->Ylo, P, K, P, t->G, t->ldG, s);
+  // fixed-point words of every whole row (real tables)
+  if (t->Gq_rows && (st = quantise_rows(t, s))) return st;
+  return SE_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -698,6 +704,7 @@ static GreedyArgs greedy_args(const se_tables* t, const float* R, int ldR, uint8
   ga.Gc = t->n_classes == 4 ? t->Gc : nullptr;
   ga.cls = t->n_classes == 4 ? reinterpret_cast<const int2*>(t->cls) : nullptr;
   ga.Gq = (prm.flags & SE_ROWS_Q14) && t->n_classes == 4 ? t->Gq : nullptr;
+  ga.Gqr = (prm.flags & SE_ROWS_Q14) && !t->phi_im ? t->Gq_rows : nullptr;
   ga.cl = t->n_classes == 4 ? class_layout(t) : ClassLayout{};
   ga.n_degenerate = nullptr;
   return ga;
@@ -719,17 +726,25 @@ static se_status check_params(se_params prm, const float* g_loss, int g_loss_ld)
   return SE_OK;
 }
 
-// The flags of the table routes: SE_ROWS_Q14 is honoured by the one-launch
-// class route only (the calls that take it pass `route_ok` for tables that
-// go there); SE_ROWS_BF16X3 belongs to rows on demand.
-static se_status check_route_flags(const se_tables* t, se_params prm, bool route_ok) {
+// The flags of the table routes: SE_ROWS_Q14 reads the class words Gq on the
+// one-launch route (one_launch: the call takes it for these tables) and the
+// whole-row words Gq_rows on the loop over whole rows; SE_ROWS_BF16X3
+// belongs to rows on demand.
+static se_status check_route_flags(const se_tables* t, se_params prm, bool one_launch) {
   if (prm.flags & SE_ROWS_BF16X3)
     return fail(SE_EINVAL, "SE_ROWS_BF16X3 is an option of rows on demand");
   if (!(prm.flags & SE_ROWS_Q14)) return SE_OK;
-  if (!route_ok || !conceal_tx_supported(t) || t->n_classes != 4)
-    return fail(SE_EINVAL, "SE_ROWS_Q14 needs the one-launch route on class tables");
-  if (!t->Gq || reinterpret_cast<uintptr_t>(t->Gq) % 16)
-    return fail(SE_EINVAL, "SE_ROWS_Q14 needs 16-byte aligned fixed-point rows Gq");
+  if (one_launch) {
+    if (t->n_classes != 4)
+      return fail(SE_EINVAL, "SE_ROWS_Q14 on the one-launch route needs class tables");
+    if (!t->Gq || reinterpret_cast<uintptr_t>(t->Gq) % 16)
+      return fail(SE_EINVAL, "SE_ROWS_Q14 needs 16-byte aligned fixed-point rows Gq");
+    return SE_OK;
+  }
+  if (t->phi_im) return fail(SE_EINVAL, "SE_ROWS_Q14 takes real tables");
+  if (!t->Gq_rows || reinterpret_cast<uintptr_t>(t->Gq_rows) % 16)
+    return fail(SE_EINVAL,
+                "SE_ROWS_Q14 on the loop over whole rows needs 16-byte aligned words Gq_rows");
   return SE_OK;
 }
 
@@ -766,7 +781,7 @@ se_status se_extrapolate_device(const se_tables* t, uint8_t* images, int32_t n_i
   se_status st = check_common(t, n_img, H, W, n_blk, images, dev_blocks);
   if (st) return st;
   if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
-  if ((st = check_route_flags(t, prm, true))) return st;
+  if ((st = check_route_flags(t, prm, conceal_tx_supported(t)))) return st;
   if (n_blk == 0) return SE_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int ldR = r_row_len(t);
@@ -829,7 +844,7 @@ static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, in
   if (st) return st;
   if (!images) return fail(SE_EINVAL, "images is NULL");
   if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
-  if ((st = check_route_flags(t, prm, !plain))) return st;
+  if ((st = check_route_flags(t, prm, !plain && conceal_tx_supported(t)))) return st;
   if ((st = check_blocks(t, n_img, H, W, blocks, n_blk, g_loss_ld, g_loss))) return st;
   if (plain && t->phi_im) return fail(SE_EINVAL, "the per-block form takes real dictionaries");
   if (n_blk == 0) return SE_OK;
@@ -898,39 +913,181 @@ static inline int round1024(int v) { return (v + 1023) & ~1023; }
 
 // workspace for the split products of the on-demand path: the per-block
 // diagonal and projections (every atom, padded rows) and the per-iteration
-// rows (the dense ranges when transform parts are declared)
-static size_t ondemand_splitk_floats(const se_basis* b, int n_blk) {
+// rows (the dense ranges when transform parts are declared); with `tuned`,
+// room for any split the tuner may choose (up to 8 slices)
+static size_t ondemand_splitk_floats(const se_basis* b, int n_blk, bool tuned = false) {
   const int P = b->M * b->N, ld = round1024(b->K);
   size_t f = gemm_splitk_floats(ld, n_blk, P);
-  if (b->n_parts > 0 && b->n_parts <= 2) {
-    int lo[3], hi[3];
-    const int nr = dense_ranges(b->K, P, b->n_parts, b->parts, lo, hi);
-    for (int r = 0; r < nr; ++r) f = std::max(f, gemm_splitk_floats(hi[r] - lo[r], n_blk, P));
+  int lo[3] = {0, 0, 0}, hi[3] = {b->K, 0, 0};
+  const int nr = b->n_parts > 0 && b->n_parts <= 2
+                     ? dense_ranges(b->K, P, b->n_parts, b->parts, lo, hi)
+                     : 1;
+  for (int r = 0; r < nr; ++r) {
+    f = std::max(f, gemm_rows_splitk_floats(hi[r] - lo[r], n_blk, P, -1));
+    if (tuned) f = std::max(f, gemm_rows_splitk_floats(hi[r] - lo[r], n_blk, P, 8));
   }
   return f;
 }
 
-size_t se_extrapolate_ondemand_ws_bytes(const se_basis* b, int32_t n_blk, int32_t max_loss) {
-  if (!b || b->K < 1 || b->M < 1 || b->N < 1 || n_blk < 0 || max_loss < 0) return 0;
+// The basis checks of rows on demand.
+static se_status check_od_basis(const se_basis* b) {
+  if (b && b->phi_im) return fail(SE_EINVAL, "rows on demand take real dictionaries");
+  if (b && b->T > 1) return fail(SE_EINVAL, "rows on demand take two-dimensional areas");
+  if (!b || !b->phi) return fail(SE_EINVAL, "NULL argument");
+  if (b->M < 1 || b->N < 1 || b->K < 1) return fail(SE_EINVAL, "bad basis shape");
+  if (b->K > 32768) return fail(SE_EINVAL, "K=%d exceeds 32768", b->K);
+  if ((long long)b->M * b->N > (1 << 24)) return fail(SE_EINVAL, "area too large");
+  return check_basis_parts(b);
+}
+
+// Workspace of a batch on demand, carved in one order for the size query
+// (base NULL) and the call.  own_dict: the dictionary's own pieces (phi
+// squared, transform operands, split copy, verification flag) live in the
+// workspace too (se_extrapolate_ondemand); a prepared dictionary holds them.
+struct OdCarve {
+  se_block* dblk = nullptr;
+  int32_t* dorig = nullptr;
+  int32_t* flag = nullptr;
+  float* tx = nullptr;
+  uint16_t* phi_split = nullptr;
+};
+static void carve_ondemand(Carver& cv, const se_basis* b, int n_blk, int max_loss, int slots,
+                           bool own_dict, bool bf16, bool tuned, OnDemandPlan& pl, OdCarve& oc) {
   const size_t K = (size_t)b->K, P = (size_t)b->M * b->N, n = (size_t)n_blk;
   const size_t ld = (size_t)round1024(b->K), ldV = (size_t)round4((int)P);
+  const size_t ml = (size_t)(max_loss > 0 ? max_loss : 1);
+  oc.dblk = cv.take<se_block>(n);
+  oc.dorig = cv.take<int32_t>(n);
+  if (own_dict) pl.phi2 = cv.take<float>(K * P);
+  pl.X = cv.take<float>(n * ldV);
+  pl.V = cv.take<float>(n * ldV);
+  pl.R = cv.take<float>(n * ld);
+  pl.D = cv.take<float>(n * ld);
+  pl.rows = cv.take<float>(n * (size_t)(slots + 1) * ld);
+  pl.st = cv.take<float>(2 * n);
+  pl.g = cv.take<float>(2 * n * ml);
+  pl.gc = pl.g ? pl.g + n * ml : nullptr;
+  if (own_dict) oc.flag = cv.take<int32_t>(2);
+  pl.ibuf = cv.take<int32_t>(4 + 2 * n + (slots > 0 ? n * K : 0));
+  pl.deg = pl.ibuf ? pl.ibuf + 4 + n : nullptr;
+  pl.cur = cv.take<int32_t>(n);
+  pl.cmap = cv.take<int32_t>(n);
+  if (own_dict) oc.tx = cv.take<float>(tx_const_bytes(b->M, b->N, b->n_parts) / 4);
+  pl.splitk_floats = ondemand_splitk_floats(b, n_blk, tuned);
+  pl.splitk = cv.take<float>(pl.splitk_floats);
+  if (own_dict) oc.phi_split = cv.take<uint16_t>(2 * K * P);
+  pl.Vhi = pl.Vlo = nullptr;
+  if (own_dict || bf16) {
+    uint16_t* vh = cv.take<uint16_t>(2 * n * ldV);
+    pl.Vhi = vh;
+    pl.Vlo = vh ? vh + n * ldV : nullptr;
+  }
+}
+
+// Host part of a batch on demand: checks of the blocks, their order by
+// decreasing iteration count (the blocks iterating at nu form a prefix),
+// the device copies of the descriptors (blocks without an available sample
+// marked) and the number of blocks still iterating at each nu.
+struct OdBatch {
+  int max_loss = 1, iters_max = 0, n_deg = 0;
+  std::vector<int> it, active;
+  std::vector<int32_t> order;
+  std::vector<se_block> sorted;
+};
+static se_status plan_ondemand_batch(const se_basis* b, int n_img, int H, int W,
+                                     const se_block* blocks, int n_blk, se_params prm,
+                                     const int32_t* iters, OdBatch& ob) {
+  if (n_img < 1 || H < 1 || W < 1) return fail(SE_EINVAL, "bad image batch");
+  if (n_blk < 0 || (n_blk > 0 && !blocks)) return fail(SE_EINVAL, "bad block list");
+  ob.it.assign((size_t)n_blk, 0);
+  for (int i = 0; i < n_blk; ++i) {
+    const se_block& bl = blocks[i];
+    if (bl.img < 0 || bl.img >= n_img) return fail(SE_EINVAL, "block %d: img out of range", i);
+    if (bl.lh < 1 || bl.lw < 1 || bl.ly < 0 || bl.lx < 0 || bl.ly + bl.lh > b->M ||
+        bl.lx + bl.lw > b->N || bl.lt != 0 || bl.ld > 1)
+      return fail(SE_EINVAL, "block %d: loss rectangle not inside the %dx%d area", i, b->M, b->N);
+    ob.max_loss = std::max(ob.max_loss, bl.lh * bl.lw);
+    ob.it[(size_t)i] = iters ? iters[i] : prm.iters;
+    if (ob.it[(size_t)i] < 0) return fail(SE_EINVAL, "block %d: negative iteration count", i);
+    ob.iters_max = std::max(ob.iters_max, ob.it[(size_t)i]);
+  }
+  se_status st;
+  if ((st = check_loss_overlap(blocks, n_blk, H, W))) return st;
+  ob.order.resize((size_t)n_blk);
+  std::iota(ob.order.begin(), ob.order.end(), 0);
+  std::stable_sort(ob.order.begin(), ob.order.end(), [&](int32_t x, int32_t y) {
+    return ob.it[(size_t)x] > ob.it[(size_t)y];
+  });
+  ob.sorted.resize((size_t)n_blk);
+  for (int i = 0; i < n_blk; ++i) {
+    se_block v = blocks[ob.order[(size_t)i]];
+    const bool none = block_without_support(v, H, W, 1, b->M, b->N);
+    ob.n_deg += none;
+    v.geom = none ? kBlockNoSupport : 0;
+    v.ld = 1;
+    ob.sorted[(size_t)i] = v;
+  }
+  ob.active.assign((size_t)std::max(ob.iters_max, 1), 0);
+  for (int nu = 0; nu < ob.iters_max; ++nu) {
+    int c = 0;
+    while (c < n_blk && ob.it[(size_t)ob.order[(size_t)c]] > nu) ++c;
+    ob.active[(size_t)nu] = c;
+  }
+  return SE_OK;
+}
+
+static se_status upload_ondemand_batch(const OdBatch& ob, const OdCarve& oc, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(oc.dblk, ob.sorted.data(), ob.sorted.size() * sizeof(se_block),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(oc.dorig, ob.order.data(), ob.order.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return fail(SE_EHIP, "descriptor upload: %s", hipGetErrorString(e));
+  return SE_OK;
+}
+
+// The row products' tile and split per dense range (tuner records, else the
+// automatic rules; one pass when invariant).
+static void ondemand_row_shapes(const se_basis* b, int n_blk, bool invariant, OnDemandPlan& pl) {
+  const int P = b->M * b->N;
+  int lo[3] = {0, 0, 0}, hi[3] = {b->K, 0, 0};
+  const int nr = b->n_parts > 0 ? dense_ranges(b->K, P, b->n_parts, b->parts, lo, hi) : 1;
+  for (int r = 0; r < 3; ++r) {
+    pl.row_tile[r] = 0;
+    pl.row_split[r] = invariant ? 1 : -1;
+    if (r < nr) {
+      const RowTune rt = tune_lookup_rows(hi[r] - lo[r], P, n_blk);
+      pl.row_tile[r] = rt.tile;
+      if (!invariant) pl.row_split[r] = rt.split;
+    }
+  }
+}
+
+static void fill_ondemand_plan(const se_basis* b, const OdBatch& ob, const OdCarve& oc,
+                               se_params prm, OnDemandPlan& pl) {
+  pl.K = b->K;
+  pl.M = b->M;
+  pl.N = b->N;
+  pl.n_blk = (int)ob.sorted.size();
+  pl.phi = b->phi;
+  pl.blk = oc.dblk;
+  pl.orig = oc.dorig;
+  pl.active = ob.active.data();
+  pl.iters_max = ob.iters_max;
+  pl.gamma = prm.gamma;
+  pl.ldV = round4(b->M * b->N);
+  pl.ld = round1024(b->K);
+  pl.ldg = ob.max_loss;
+  pl.n_degenerate = nullptr;
+  pl.basis = b;
+}
+
+size_t se_extrapolate_ondemand_ws_bytes(const se_basis* b, int32_t n_blk, int32_t max_loss) {
+  if (!b || b->K < 1 || b->M < 1 || b->N < 1 || n_blk < 0 || max_loss < 0) return 0;
   Carver cv(nullptr);
-  cv.take<se_block>(n);
-  cv.take<int32_t>(n);
-  cv.take<float>(K * P);
-  cv.take<float>(n * ldV);
-  cv.take<float>(n * ldV);
-  cv.take<float>(n * ld);
-  cv.take<float>(n * ld);
-  cv.take<float>(n * ld);
-  cv.take<float>(2 * n);
-  cv.take<float>(2 * n * (size_t)(max_loss > 0 ? max_loss : 1));
-  cv.take<int32_t>(1);
-  cv.take<int32_t>(n);
-  cv.take<float>(tx_const_bytes(b->M, b->N, b->n_parts) / 4);
-  cv.take<float>(ondemand_splitk_floats(b, n_blk));
-  cv.take<uint16_t>(2 * K * P);      // split-BF16 dictionary and V rows (SE_ROWS_BF16X3)
-  cv.take<uint16_t>(2 * n * ldV);
+  OnDemandPlan pl{};
+  OdCarve oc;
+  carve_ondemand(cv, b, n_blk, max_loss, 0, true, true, false, pl, oc);
   return cv.off + 256;
 }
 
@@ -942,128 +1099,55 @@ static se_status extrapolate_ondemand(const se_basis* b, const float* w, uint8_t
                                       size_t ws_bytes, void* stream) {
   g_err[0] = 0;
   const bool invariant = (prm.flags & SE_INVARIANT) != 0;
-  if (b && b->phi_im) return fail(SE_EINVAL, "rows on demand take real dictionaries");
-  if (b && b->T > 1) return fail(SE_EINVAL, "rows on demand take two-dimensional areas");
-  if (!b || !b->phi || !w || !images) return fail(SE_EINVAL, "NULL argument");
-  if (b->M < 1 || b->N < 1 || b->K < 1) return fail(SE_EINVAL, "bad basis shape");
-  if (b->K > 32768) return fail(SE_EINVAL, "K=%d exceeds 32768", b->K);
-  if ((long long)b->M * b->N > (1 << 24)) return fail(SE_EINVAL, "area too large");
-  if (n_img < 1 || H < 1 || W < 1) return fail(SE_EINVAL, "bad image batch");
-  if (n_blk < 0 || (n_blk > 0 && !blocks)) return fail(SE_EINVAL, "bad block list");
   se_status st;
-  if ((st = check_basis_parts(b))) return st;
+  if ((st = check_od_basis(b))) return st;
+  if (!w || !images) return fail(SE_EINVAL, "NULL argument");
   if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
   if (prm.flags & SE_ROWS_Q14) return fail(SE_EINVAL, "rows on demand take no fixed-point rows");
-  int max_loss = 1, iters_max = 0;
-  std::vector<int> it((size_t)n_blk);
-  for (int i = 0; i < n_blk; ++i) {
-    const se_block& bl = blocks[i];
-    if (bl.img < 0 || bl.img >= n_img) return fail(SE_EINVAL, "block %d: img out of range", i);
-    if (bl.lh < 1 || bl.lw < 1 || bl.ly < 0 || bl.lx < 0 || bl.ly + bl.lh > b->M ||
-        bl.lx + bl.lw > b->N || bl.lt != 0 || bl.ld > 1)
-      return fail(SE_EINVAL, "block %d: loss rectangle not inside the %dx%d area", i, b->M, b->N);
-    max_loss = std::max(max_loss, bl.lh * bl.lw);
-    it[(size_t)i] = iters ? iters[i] : prm.iters;
-    if (it[(size_t)i] < 0) return fail(SE_EINVAL, "block %d: negative iteration count", i);
-    iters_max = std::max(iters_max, it[(size_t)i]);
-  }
-  if ((st = check_loss_overlap(blocks, n_blk, H, W))) return st;
+  OdBatch ob;
+  if ((st = plan_ondemand_batch(b, n_img, H, W, blocks, n_blk, prm, iters, ob))) return st;
   if (n_blk == 0) return SE_OK;
-  const size_t need = se_extrapolate_ondemand_ws_bytes(b, n_blk, max_loss);
+  const size_t need = se_extrapolate_ondemand_ws_bytes(b, n_blk, ob.max_loss);
   if (!ws || ws_bytes < need) return fail(SE_ENOMEM, "workspace too small: need %zu bytes", need);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  // decreasing iteration counts: the blocks still iterating form a prefix
-  std::vector<int32_t> order((size_t)n_blk);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int32_t x, int32_t y) { return it[(size_t)x] > it[(size_t)y]; });
-  // device copies: the caller's tag replaced by the mark of blocks without an
-  // available sample
-  int n_deg = 0;
-  std::vector<se_block> sorted((size_t)n_blk);
-  for (int i = 0; i < n_blk; ++i) {
-    se_block v = blocks[order[(size_t)i]];
-    const bool none = block_without_support(v, H, W, 1, b->M, b->N);
-    n_deg += none;
-    v.geom = none ? kBlockNoSupport : 0;
-    v.ld = 1;
-    sorted[(size_t)i] = v;
-  }
-  std::vector<int> active((size_t)std::max(iters_max, 1), 0);
-  for (int nu = 0; nu < iters_max; ++nu) {
-    int c = 0;
-    while (c < n_blk && it[(size_t)order[(size_t)c]] > nu) ++c;
-    active[(size_t)nu] = c;
-  }
-  const int K = b->K, P = b->M * b->N, n = n_blk;
-  const int ld = round1024(K), ldV = round4(P);
   Carver cv(ws);
-  OnDemandPlan pl;
-  se_block* dblk = cv.take<se_block>((size_t)n);
-  int32_t* dorig = cv.take<int32_t>((size_t)n);
-  pl.phi2 = cv.take<float>((size_t)K * P);
-  pl.X = cv.take<float>((size_t)n * ldV);
-  pl.V = cv.take<float>((size_t)n * ldV);
-  pl.R = cv.take<float>((size_t)n * ld);
-  pl.D = cv.take<float>((size_t)n * ld);
-  pl.rows = cv.take<float>((size_t)n * ld);
-  pl.st = cv.take<float>((size_t)2 * n);
-  pl.g = cv.take<float>((size_t)2 * n * max_loss);
-  pl.gc = pl.g + (size_t)n * max_loss;
-  int32_t* flag = cv.take<int32_t>(1);
-  pl.deg = cv.take<int32_t>((size_t)n);
-  pl.n_degenerate = nullptr;
-  float* tx = cv.take<float>(tx_const_bytes(b->M, b->N, b->n_parts) / 4);
-  pl.splitk = cv.take<float>(ondemand_splitk_floats(b, n));
+  OnDemandPlan pl{};
+  OdCarve oc;
+  carve_ondemand(cv, b, n_blk, ob.max_loss, 0, true, true, false, pl, oc);
+  fill_ondemand_plan(b, ob, oc, prm, pl);
+  pl.slots = 0;
+  pl.phi2_ready = false;
+  pl.split_ready = false;
   // invariant: every product in one pass over its contraction (the split
   // depends on how many blocks iterate, which would change the rounding)
-  pl.splitk_floats = invariant ? 0 : ondemand_splitk_floats(b, n);
-  pl.phi_hi = pl.phi_lo = pl.Vhi = pl.Vlo = nullptr;
-  {
-    uint16_t* ph = cv.take<uint16_t>((size_t)2 * K * P);
-    uint16_t* vh = cv.take<uint16_t>((size_t)2 * n * ldV);
-    if (prm.flags & SE_ROWS_BF16X3) {
-      pl.phi_hi = ph;
-      pl.phi_lo = ph + (size_t)K * P;
-      pl.Vhi = vh;
-      pl.Vlo = vh + (size_t)n * ldV;
-    }
+  if (invariant) pl.splitk_floats = 0;
+  for (int r = 0; r < 3; ++r) {   // automatic shapes (the tuner's records are for plans)
+    pl.row_tile[r] = 0;
+    pl.row_split[r] = invariant ? 1 : -1;
+  }
+  if (prm.flags & SE_ROWS_BF16X3) {
+    pl.phi_hi = oc.phi_split;
+    pl.phi_lo = oc.phi_split + (size_t)b->K * b->M * b->N;
+  } else {
+    pl.phi_hi = pl.phi_lo = nullptr;
+    pl.Vhi = pl.Vlo = nullptr;
   }
   // declared transform parts: verified (one synchronisation of the stream),
   // then their table rows are formed as transforms
-  if ((st = verify_parts(b, flag, s))) return st;
-  if (b->n_parts > 0 && (st = build_tx_basis(b, tx, s))) return st;
-  pl.basis = b;
-  pl.tx = tx;
-  hipError_t e = hipMemcpyAsync(dblk, sorted.data(), sorted.size() * sizeof(se_block),
-                                hipMemcpyHostToDevice, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(dorig, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                       s);
-  if (e != hipSuccess) return fail(SE_EHIP, "descriptor upload: %s", hipGetErrorString(e));
-  pl.K = K;
-  pl.M = b->M;
-  pl.N = b->N;
-  pl.n_blk = n;
-  pl.phi = b->phi;
+  if ((st = verify_parts(b, oc.flag, s))) return st;
+  if (b->n_parts > 0 && (st = build_tx_basis(b, oc.tx, s))) return st;
+  pl.tx = oc.tx;
+  if ((st = upload_ondemand_batch(ob, oc, s))) return st;
   pl.w = w;
   pl.images = images;
   pl.H = H;
   pl.W = W;
-  pl.blk = dblk;
-  pl.orig = dorig;
-  pl.active = active.data();
-  pl.iters_max = iters_max;
-  pl.gamma = prm.gamma;
-  pl.ldV = ldV;
-  pl.ld = ld;
-  pl.ldg = max_loss;
   pl.sel = sel;
   pl.coef = coef;
   pl.g_loss = g_loss;
   pl.g_loss_ld = g_loss ? g_loss_ld : 0;
   if ((st = ondemand_run(pl, s))) return st;
-  return degenerate_status(n_deg);
+  return degenerate_status(ob.n_deg);
 }
 
 se_status se_extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* images,
@@ -1073,6 +1157,213 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w, uint8_t* im
                                   void* ws, size_t ws_bytes, void* stream) {
   return extrapolate_ondemand(b, w, images, n_img, H, W, blocks, n_blk, prm, iters, sel, coef,
                               g_loss, g_loss_ld, ws, ws_bytes, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Prepared dictionaries and plans of rows on demand.
+
+}  // extern "C"
+
+struct se_od_dict {
+  se_basis b{};
+  uint32_t flags = 0;
+  float* phi2 = nullptr;       // K x P, phi squared
+  float* tx = nullptr;         // transform operands (declared parts)
+  uint16_t* phi_hi = nullptr;  // split-BF16 dictionary (SE_ROWS_BF16X3)
+  uint16_t* phi_lo = nullptr;
+};
+
+struct se_od_plan {
+  const se_od_dict* d = nullptr;
+  OdBatch ob;
+  se_params prm{};
+  int n_img = 0, H = 0, W = 0, slots = 0;
+  OnDemandPlan pl{};
+};
+
+extern "C" {
+
+void se_ondemand_release(se_od_dict* d) {
+  if (!d) return;
+  if (d->phi2) (void)hipFree(d->phi2);
+  if (d->tx) (void)hipFree(d->tx);
+  if (d->phi_hi) (void)hipFree(d->phi_hi);
+  delete d;
+}
+
+se_status se_ondemand_prepare(const se_basis* b, uint32_t flags, se_od_dict** out,
+                              void* stream) {
+  g_err[0] = 0;
+  if (!out) return fail(SE_EINVAL, "NULL argument");
+  *out = nullptr;
+  se_status st;
+  if ((st = check_od_basis(b))) return st;
+  if (flags & ~SE_ROWS_BF16X3) return fail(SE_EINVAL, "unknown flags 0x%x", flags);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  se_od_dict* d = new se_od_dict;
+  d->b = *b;
+  d->flags = flags;
+  const size_t KP = (size_t)b->K * b->M * b->N;
+  int32_t* flag = nullptr;
+  auto bail = [&](se_status code) {
+    if (flag) (void)hipFree(flag);
+    se_ondemand_release(d);
+    return code;
+  };
+  if (hipMalloc(reinterpret_cast<void**>(&d->phi2), KP * sizeof(float)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&flag), 2 * sizeof(int32_t)) != hipSuccess)
+    return bail(fail(SE_ENOMEM, "device allocation of %zu bytes failed", KP * sizeof(float)));
+  if (b->n_parts > 0 &&
+      hipMalloc(reinterpret_cast<void**>(&d->tx), tx_const_bytes(b->M, b->N, b->n_parts)) !=
+          hipSuccess)
+    return bail(fail(SE_ENOMEM, "device allocation of the transform operands failed"));
+  if ((flags & SE_ROWS_BF16X3) &&
+      hipMalloc(reinterpret_cast<void**>(&d->phi_hi), 2 * KP * sizeof(uint16_t)) != hipSuccess)
+    return bail(fail(SE_ENOMEM, "device allocation of the split dictionary failed"));
+  if (d->phi_hi) d->phi_lo = d->phi_hi + KP;
+  launch_square(b->phi, KP, d->phi2, s);
+  if ((st = check_launch("square"))) return bail(st);
+  if (d->phi_hi) {
+    launch_split_bf16(b->phi, KP, d->phi_hi, d->phi_lo, s);
+    if ((st = check_launch("split_bf16"))) return bail(st);
+  }
+  if (b->n_parts > 0 && (st = build_tx_basis(b, d->tx, s))) return bail(st);
+  if ((st = verify_parts(b, flag, s))) return bail(st);   // synchronises the stream
+  if (hipStreamSynchronize(s) != hipSuccess)
+    return bail(fail(SE_EHIP, "prepare: %s", hipGetErrorString(hipGetLastError())));
+  (void)hipFree(flag);
+  *out = d;
+  return SE_OK;
+}
+
+size_t se_ondemand_plan_ws_bytes(const se_od_dict* d, int32_t n_blk, int32_t max_loss,
+                                 int32_t row_slots) {
+  if (!d || n_blk < 0 || max_loss < 0 || row_slots < 0) return 0;
+  Carver cv(nullptr);
+  OnDemandPlan pl{};
+  OdCarve oc;
+  carve_ondemand(cv, &d->b, n_blk, max_loss, std::min(row_slots, d->b.K), false,
+                 (d->flags & SE_ROWS_BF16X3) != 0, true, pl, oc);
+  return cv.off + 256;
+}
+
+se_status se_ondemand_plan_create(const se_od_dict* d, int32_t n_img, int32_t H, int32_t W,
+                                  const se_block* blocks, int32_t n_blk, se_params prm,
+                                  const int32_t* iters, int32_t row_slots, void* ws,
+                                  size_t ws_bytes, void* stream, se_od_plan** out) {
+  g_err[0] = 0;
+  if (!out || !d) return fail(SE_EINVAL, "NULL argument");
+  *out = nullptr;
+  se_status st;
+  if ((st = check_params(prm, nullptr, 0))) return st;
+  if (prm.flags & SE_ROWS_Q14) return fail(SE_EINVAL, "rows on demand take no fixed-point rows");
+  if ((prm.flags & SE_ROWS_BF16X3) && !(d->flags & SE_ROWS_BF16X3))
+    return fail(SE_EINVAL, "SE_ROWS_BF16X3 needs a dictionary prepared with it");
+  if (row_slots < 0) return fail(SE_EINVAL, "row_slots < 0");
+  se_od_plan* p = new se_od_plan;
+  if ((st = plan_ondemand_batch(&d->b, n_img, H, W, blocks, n_blk, prm, iters, p->ob))) {
+    delete p;
+    return st;
+  }
+  // rows a block can use: one per iteration at most
+  p->slots = std::min(row_slots, std::min(p->ob.iters_max, d->b.K));
+  const size_t need = se_ondemand_plan_ws_bytes(d, n_blk, p->ob.max_loss, p->slots);
+  if (n_blk > 0 && (!ws || ws_bytes < need)) {
+    delete p;
+    return fail(SE_ENOMEM, "workspace too small: need %zu bytes", need);
+  }
+  p->d = d;
+  p->prm = prm;
+  p->n_img = n_img;
+  p->H = H;
+  p->W = W;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n_blk > 0) {
+    Carver cv(ws);
+    OdCarve oc;
+    const bool bf16 = (prm.flags & SE_ROWS_BF16X3) != 0;
+    carve_ondemand(cv, &d->b, n_blk, p->ob.max_loss, p->slots, false,
+                   (d->flags & SE_ROWS_BF16X3) != 0, true, p->pl, oc);
+    fill_ondemand_plan(&d->b, p->ob, oc, prm, p->pl);
+    p->pl.basis = &d->b;
+    p->pl.slots = p->slots;
+    p->pl.phi2 = d->phi2;
+    p->pl.phi2_ready = true;
+    p->pl.tx = d->tx;
+    p->pl.phi_hi = bf16 ? d->phi_hi : nullptr;
+    p->pl.phi_lo = bf16 ? d->phi_lo : nullptr;
+    p->pl.split_ready = true;
+    if (!bf16) p->pl.Vhi = p->pl.Vlo = nullptr;
+    const bool invariant = (prm.flags & SE_INVARIANT) != 0;
+    if (invariant) p->pl.splitk_floats = 0;
+    ondemand_row_shapes(&d->b, n_blk, invariant, p->pl);
+    // the descriptors, copied once (the run reads them from the device)
+    if ((st = upload_ondemand_batch(p->ob, oc, s)) ||
+        (hipStreamSynchronize(s) != hipSuccess &&
+         (st = fail(SE_EHIP, "plan: %s", hipGetErrorString(hipGetLastError()))))) {
+      delete p;
+      return st;
+    }
+  }
+  *out = p;
+  return SE_OK;
+}
+
+void se_ondemand_plan_release(se_od_plan* p) { delete p; }
+
+}  // extern "C"
+
+namespace sefase {
+// (for the tuner) the plan's dense ranges: their sizes and the pixels per atom
+int ondemand_plan_dense(const se_od_plan* p, int kd[3], int* P) {
+  const se_basis& b = p->d->b;
+  int lo[3] = {0, 0, 0}, hi[3] = {b.K, 0, 0};
+  const int nr = b.n_parts > 0 ? dense_ranges(b.K, b.M * b.N, b.n_parts, b.parts, lo, hi) : 1;
+  for (int r = 0; kd && r < nr; ++r) kd[r] = hi[r] - lo[r];
+  if (P) *P = b.M * b.N;
+  return nr;
+}
+int ondemand_plan_blocks(const se_od_plan* p) { return (int)p->ob.sorted.size(); }
+void ondemand_plan_set_rows(se_od_plan* p, int tile, int split) {
+  const bool invariant = (p->prm.flags & SE_INVARIANT) != 0;
+  for (int r = 0; r < 3; ++r) {
+    p->pl.row_tile[r] = tile;
+    p->pl.row_split[r] = invariant ? 1 : split;
+  }
+}
+}  // namespace sefase
+
+extern "C" {
+
+int32_t se_ondemand_plan_info(const se_od_plan* p, int32_t* iters_max, int32_t* max_loss,
+                              int32_t* row_slots) {
+  if (!p) return -1;
+  if (iters_max) *iters_max = p->ob.iters_max;
+  if (max_loss) *max_loss = p->ob.max_loss;
+  if (row_slots) *row_slots = p->slots;
+  return (int32_t)p->ob.sorted.size();
+}
+
+se_status se_ondemand_run(const se_od_plan* p, const float* w, uint8_t* images, int32_t* sel,
+                          float* coef, float* g_loss, int32_t g_loss_ld, void* stream) {
+  g_err[0] = 0;
+  if (!p || !w || !images) return fail(SE_EINVAL, "NULL argument");
+  se_status st;
+  if ((st = check_params(p->prm, g_loss, g_loss_ld))) return st;
+  if (g_loss && g_loss_ld < p->ob.max_loss)
+    return fail(SE_EINVAL, "g_loss_ld=%d < loss size %d", g_loss_ld, p->ob.max_loss);
+  if (p->ob.sorted.empty()) return SE_OK;
+  OnDemandPlan pl = p->pl;
+  pl.w = w;
+  pl.images = images;
+  pl.H = p->H;
+  pl.W = p->W;
+  pl.sel = sel;
+  pl.coef = coef;
+  pl.g_loss = g_loss;
+  pl.g_loss_ld = g_loss ? g_loss_ld : 0;
+  if ((st = ondemand_run(pl, static_cast<hipStream_t>(stream)))) return st;
+  return degenerate_status(p->ob.n_deg);
 }
 
 se_status se_extrapolate_batch(const se_tables* t, uint8_t* images, int32_t n_img, int32_t H,

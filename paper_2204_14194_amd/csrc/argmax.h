@@ -44,6 +44,21 @@ __device__ __forceinline__ uint64_t wave_max_key(uint32_t hi, uint32_t lo) {
   return ((uint64_t)h << 32) | l;
 }
 
+// Maximum 64-bit key over each aligned group of G lanes (G a power of two up
+// to 16), returned wave-uniform: every group must hold the same G keys (as
+// when lane i holds item i mod G), so each group's maximum is the maximum.
+template <int G>
+__device__ __forceinline__ uint64_t group_max_key(uint32_t hi, uint32_t lo) {
+  static_assert(G >= 1 && G <= 16 && (G & (G - 1)) == 0, "groups within a row of 16 lanes");
+  if constexpr (G >= 2) key_step<kQuadXor1, 0xF>(hi, lo);
+  if constexpr (G >= 4) key_step<kQuadXor2, 0xF>(hi, lo);
+  if constexpr (G >= 8) key_step<kRowHalfMirror, 0xF>(hi, lo);
+  if constexpr (G >= 16) key_step<kRowMirror, 0xF>(hi, lo);
+  const uint32_t h = (uint32_t)__builtin_amdgcn_readfirstlane((int)hi);
+  const uint32_t l = (uint32_t)__builtin_amdgcn_readfirstlane((int)lo);
+  return ((uint64_t)h << 32) | l;
+}
+
 __device__ __forceinline__ uint64_t make_key(float v, int idx) {
   const uint32_t bits = __float_as_uint(v);
   const uint32_t hi = bits & 0x7FFFFFFFu;

@@ -116,4 +116,12 @@ se_status quantise_classes(se_tables* t, hipStream_t s) {
   return check_launch("quantise_rows");
 }
 
+se_status quantise_rows(se_tables* t, hipStream_t s) {
+  const size_t n4 = (size_t)t->K * t->ldG / 4;
+  hipLaunchKernelGGL(k_quantise_rows, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<const float4*>(t->G), n4,
+                     reinterpret_cast<short4*>(t->Gq_rows));
+  return check_launch("quantise_rows");
+}
+
 }  // namespace sefase

@@ -96,7 +96,9 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f32(const float* __restrict__ A
                                                      const float* __restrict__ B, int ldb,
                                                      float* __restrict__ C, int ldc, int Ma, int Nb,
                                                      int Mst, int Nst, int P, int tiles_n,
-                                                     int ntiles, int kchunk, size_t cstride) {
+                                                     int ntiles, int kchunk, size_t cstride,
+                                                     const int32_t* __restrict__ nb_dev,
+                                                     const int32_t* __restrict__ cmap) {
   constexpr int SI = BM / 32, SJ = BN / 32;   // 16x16 MFMA tiles per wave
   // split contraction: slice z covers p in [z kchunk, (z + 1) kchunk) and
   // writes its partial S to C + z cstride
@@ -123,6 +125,12 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f32(const float* __restrict__ A
     bj = tile - bi * tiles_n;
   }
   const int m0 = bi * BM, n0 = bj * BN;
+  // rows formed on demand (transposed store): the valid blocks are counted
+  // on the device, and tiles past the count have nothing to do
+  if (MODE == kStoreTransposed && nb_dev) {
+    Nb = min(Nb, *nb_dev);
+    if (n0 >= Nb) return;                     // uniform over the workgroup
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int lr = lane & 15, lq = lane >> 4;
@@ -219,7 +227,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f32(const float* __restrict__ A
           v.y = r0 + 1 < Ma ? acc[i][j][1] : 0.0f;
           v.z = r0 + 2 < Ma ? acc[i][j][2] : 0.0f;
           v.w = r0 + 3 < Ma ? acc[i][j][3] : 0.0f;
-          float* dst = C + (size_t)c * ldc + r0;
+          float* dst = C + (size_t)(cmap ? cmap[c] : c) * ldc + r0;
           if (VEC && r0 + 3 < Mst) {
             *reinterpret_cast<float4*>(dst) = v;
           } else {
@@ -268,12 +276,14 @@ template <bool VEC>
 __global__ __launch_bounds__(256) void k_splitk_sum(const float* __restrict__ W, int ldw,
                                                     size_t wstride, int S,
                                                     float* __restrict__ C, int ldc, int rows,
-                                                    int cols) {
+                                                    int cols, const int32_t* __restrict__ nb_dev,
+                                                    const int32_t* __restrict__ cmap) {
   const int c = blockIdx.y;
   const int r = 4 * (blockIdx.x * blockDim.x + threadIdx.x);
+  if (nb_dev) rows = min(rows, *nb_dev);
   if (c >= rows || r >= cols) return;
   const float* w = W + (size_t)c * ldw + r;
-  float* dst = C + (size_t)c * ldc + r;
+  float* dst = C + (size_t)(cmap ? cmap[c] : c) * ldc + r;
   if (VEC && r + 3 < cols) {
     float4 v = *reinterpret_cast<const float4*>(w);
     for (int z = 1; z < S; ++z) {
@@ -323,7 +333,8 @@ size_t gemm_splitk_floats(int Mst, int Nst_max, int P) {
 template <int BM, int BN, int MODE>
 static se_status launch_f32(const float* A, int lda, const float* B, int ldb, float* C, int ldc,
                             int Ma, int Nb, int Mst, int Nst, int P, bool vec, hipStream_t s,
-                            int S = 1, int kchunk = 0, size_t cstride = 0) {
+                            int S = 1, int kchunk = 0, size_t cstride = 0,
+                            const int32_t* nb_dev = nullptr, const int32_t* cmap = nullptr) {
   int ntiles, tiles_n;
   if (MODE == kStoreSymmetric) {
     const int nb = (Ma + BM - 1) / BM;
@@ -337,17 +348,31 @@ static se_status launch_f32(const float* A, int lda, const float* B, int ldb, fl
   if (S <= 1) kchunk = P;
   if (vec)
     hipLaunchKernelGGL((k_gemm_nt_f32<BM, BN, true, MODE>), dim3(ntiles, S), dim3(256), 0, s, A,
-                       lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, tiles_n, ntiles, kchunk, cstride);
+                       lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, tiles_n, ntiles, kchunk, cstride, nb_dev,
+                       cmap);
   else
     hipLaunchKernelGGL((k_gemm_nt_f32<BM, BN, false, MODE>), dim3(ntiles, S), dim3(256), 0, s, A,
-                       lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, tiles_n, ntiles, kchunk, cstride);
+                       lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, tiles_n, ntiles, kchunk, cstride, nb_dev,
+                       cmap);
   return check_launch("gemm_nt_f32");
 }
 
+// Rows formed on demand: the valid block count read on the device (nb_dev)
+// and each output row placed at its own destination row (cmap).
+struct RowMap {
+  const int32_t* nb_dev = nullptr;
+  const int32_t* cmap = nullptr;
+};
+
+// tile: 0 = automatic, 64 or 128.  split: -1 = automatic (slices when the
+// tiles alone leave the chip idle and the workspace holds the partials),
+// 0 or 1 = none, S = S slices (64-wide tiles only; falls back to none when
+// the workspace is too small).
 template <int MODE>
 static se_status dispatch_f32(const float* A, int lda, const float* B, int ldb, float* C, int ldc,
                               int Ma, int Nb, int Mst, int Nst, int P, int tile, hipStream_t s,
-                              float* ws = nullptr, size_t ws_floats = 0) {
+                              float* ws = nullptr, size_t ws_floats = 0, int split = -1,
+                              RowMap map = RowMap{}) {
   const bool vec = (lda % 4 == 0) && (ldb % 4 == 0) && (ldc % 4 == 0) &&
                    ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B) |
                      reinterpret_cast<uintptr_t>(C)) % 16 == 0);
@@ -363,27 +388,30 @@ static se_status dispatch_f32(const float* A, int lda, const float* B, int ldb, 
     tile = big >= 512 ? 128 : 64;
   }
   if (tile == 128)
-    return launch_f32<128, 128, MODE>(A, lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, vec, s);
-  if (MODE == kStoreTransposed && ws && vec && Mst > 0 && Nst > 0) {
+    return launch_f32<128, 128, MODE>(A, lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, vec, s, 1, 0,
+                                      0, map.nb_dev, map.cmap);
+  if (MODE == kStoreTransposed && ws && vec && Mst > 0 && Nst > 0 && split != 0 && split != 1) {
     // few tiles: split the contraction over slices that write partial
     // products to the workspace, then sum them in slice order
-    const int S = splitk_slices(Mst, Nst, P);
+    const int nk = (P + kBK - 1) / kBK;
+    const int S = split < 0 ? splitk_slices(Mst, Nst, P) : std::min(split, nk);
     const int ldw = ldw_of(Mst);
     const size_t wstride = (size_t)Nst * ldw;
     if (S > 1 && (size_t)S * wstride <= ws_floats &&
         reinterpret_cast<uintptr_t>(ws) % 16 == 0) {
-      const int nk = (P + kBK - 1) / kBK;
       const int kchunk = ((nk + S - 1) / S) * kBK;
+      const int Sr = (nk + kchunk / kBK - 1) / (kchunk / kBK);   // slices that hold stages
       se_status st = launch_f32<64, 64, MODE>(A, lda, B, ldb, ws, ldw, Ma, Nb, Mst, Nst, P, true,
-                                              s, S, kchunk, wstride);
+                                              s, Sr, kchunk, wstride, map.nb_dev, nullptr);
       if (st) return st;
       const dim3 grid((unsigned)((Mst + 1023) / 1024), (unsigned)Nst);
-      hipLaunchKernelGGL(k_splitk_sum<true>, grid, dim3(256), 0, s, ws, ldw, wstride, S, C, ldc,
-                         Nst, Mst);
+      hipLaunchKernelGGL(k_splitk_sum<true>, grid, dim3(256), 0, s, ws, ldw, wstride, Sr, C, ldc,
+                         Nst, Mst, map.nb_dev, map.cmap);
       return check_launch("splitk_sum");
     }
   }
-  return launch_f32<64, 64, MODE>(A, lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, vec, s);
+  return launch_f32<64, 64, MODE>(A, lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, vec, s, 1, 0, 0,
+                                  map.nb_dev, map.cmap);
 }
 
 se_status gemm_syrk_f32(const float* Y, int ldy, int K, int P, float* G, int ldg, hipStream_t s) {
@@ -396,6 +424,22 @@ se_status gemm_project_f32(const float* Y, int ldy, int K, const float* X, int l
   // S = Y X^T (atoms x blocks), stored transposed: R[b][k]; atoms K .. ldr-1 as 0
   return dispatch_f32<kStoreTransposed>(Y, ldy, X, ldx, R, ldr, K, n_blk, pad ? ldr : K, n_blk, P,
                                         tile, s, ws, ws_floats);
+}
+
+size_t gemm_rows_splitk_floats(int K, int n_max, int P, int split) {
+  if (split == 0 || split == 1) return 0;
+  if (split < 0) return gemm_splitk_floats(K, n_max, P);
+  return (size_t)split * n_max * ldw_of(K);
+}
+
+se_status gemm_rows_f32(const float* Y, int ldy, int K, const float* X, int ldx, int n_max,
+                        const int32_t* n_dev, const int32_t* cmap, int P, float* rows, int ldr,
+                        int tile, int split, hipStream_t s, float* ws, size_t ws_floats) {
+  RowMap map;
+  map.nb_dev = n_dev;
+  map.cmap = cmap;
+  return dispatch_f32<kStoreTransposed>(Y, ldy, X, ldx, rows, ldr, K, n_max, K, n_max, P, tile, s,
+                                        ws, ws_floats, split, map);
 }
 
 }  // namespace sefase

@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt_bf16x3(
     const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo, int lda,
     const uint16_t* __restrict__ Bhi, const uint16_t* __restrict__ Blo, int ldb,
     float* __restrict__ C, int ldc, int Ma, int Nb, int Mst, int Nst, int P, int tiles_n,
-    int ntiles) {
+    int ntiles, const int32_t* __restrict__ nb_dev, const int32_t* __restrict__ cmap) {
   constexpr int SI = BM / 32, SJ = BN / 32;
   __shared__ __attribute__((aligned(16))) uint16_t Ash[2][BM][hBK + hPad];
   __shared__ __attribute__((aligned(16))) uint16_t Asl[2][BM][hBK + hPad];
@@ -108,6 +108,11 @@ __global__ __launch_bounds__(256) void k_gemm_nt_bf16x3(
     bj = tile - bi * tiles_n;
   }
   const int m0 = bi * BM, n0 = bj * BN;
+  // rows formed on demand: block count on the device, mapped destinations
+  if (MODE == hStoreTransposed && nb_dev) {
+    Nb = min(Nb, *nb_dev);
+    if (n0 >= Nb) return;                     // uniform over the workgroup
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int lr = lane & 15, lq = lane >> 4;
@@ -200,7 +205,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt_bf16x3(
           v.y = r0 + 1 < Ma ? acc[i][j][1] : 0.0f;
           v.z = r0 + 2 < Ma ? acc[i][j][2] : 0.0f;
           v.w = r0 + 3 < Ma ? acc[i][j][3] : 0.0f;
-          float* dst = C + (size_t)c * ldc + r0;
+          float* dst = C + (size_t)(cmap ? cmap[c] : c) * ldc + r0;
           if ((ldc & 3) == 0 && (reinterpret_cast<uintptr_t>(C) & 15) == 0 && r0 + 3 < Mst) {
             *reinterpret_cast<float4*>(dst) = v;
           } else {
@@ -229,7 +234,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt_bf16x3(
         if (MODE == hStoreSymmetric && bi != bj && c < Nb) {
           // off-diagonal tile: rows r0..r0+3 of column c are one row segment of
           // the mirrored tile
-          float* dst = C + (size_t)c * ldc + r0;
+          float* dst = C + (size_t)(cmap ? cmap[c] : c) * ldc + r0;
           if ((ldc & 3) == 0 && r0 + 3 < Ma) {
             *reinterpret_cast<float4*>(dst) =
                 make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
@@ -246,7 +251,8 @@ __global__ __launch_bounds__(256) void k_gemm_nt_bf16x3(
 template <int BM, int MODE>
 static se_status launch_h(const uint16_t* Ahi, const uint16_t* Alo, int lda, const uint16_t* Bhi,
                           const uint16_t* Blo, int ldb, float* C, int ldc, int Ma, int Nb,
-                          int Mst, int Nst, int P, bool vec, hipStream_t s) {
+                          int Mst, int Nst, int P, bool vec, hipStream_t s,
+                          const int32_t* nb_dev = nullptr, const int32_t* cmap = nullptr) {
   int ntiles, tiles_n;
   if (MODE == hStoreSymmetric) {
     const int nb = (Ma + BM - 1) / BM;
@@ -259,17 +265,20 @@ static se_status launch_h(const uint16_t* Ahi, const uint16_t* Alo, int lda, con
   if (ntiles <= 0 || P <= 0) return SE_OK;
   if (vec)
     hipLaunchKernelGGL((k_gemm_nt_bf16x3<BM, BM, true, MODE>), dim3(ntiles), dim3(256), 0, s, Ahi,
-                       Alo, lda, Bhi, Blo, ldb, C, ldc, Ma, Nb, Mst, Nst, P, tiles_n, ntiles);
+                       Alo, lda, Bhi, Blo, ldb, C, ldc, Ma, Nb, Mst, Nst, P, tiles_n, ntiles, nb_dev,
+                       cmap);
   else
     hipLaunchKernelGGL((k_gemm_nt_bf16x3<BM, BM, false, MODE>), dim3(ntiles), dim3(256), 0, s,
-                       Ahi, Alo, lda, Bhi, Blo, ldb, C, ldc, Ma, Nb, Mst, Nst, P, tiles_n, ntiles);
+                       Ahi, Alo, lda, Bhi, Blo, ldb, C, ldc, Ma, Nb, Mst, Nst, P, tiles_n, ntiles, nb_dev,
+                       cmap);
   return check_launch("gemm_nt_bf16x3");
 }
 
 template <int MODE>
 static se_status dispatch_h(const uint16_t* Ahi, const uint16_t* Alo, int lda, const uint16_t* Bhi,
                             const uint16_t* Blo, int ldb, float* C, int ldc, int Ma, int Nb,
-                            int Mst, int Nst, int P, hipStream_t s) {
+                            int Mst, int Nst, int P, hipStream_t s, int tile = 0,
+                            const int32_t* nb_dev = nullptr, const int32_t* cmap = nullptr) {
   const uintptr_t al = reinterpret_cast<uintptr_t>(Ahi) | reinterpret_cast<uintptr_t>(Alo) |
                        reinterpret_cast<uintptr_t>(Bhi) | reinterpret_cast<uintptr_t>(Blo);
   const bool vec = (lda % 8 == 0) && (ldb % 8 == 0) && (al % 16 == 0);
@@ -280,9 +289,12 @@ static se_status dispatch_h(const uint16_t* Ahi, const uint16_t* Alo, int lda, c
   } else {
     big = (long long)((Mst + 127) / 128) * ((Nst + 127) / 128);
   }
-  if (big >= 512)
-    return launch_h<128, MODE>(Ahi, Alo, lda, Bhi, Blo, ldb, C, ldc, Ma, Nb, Mst, Nst, P, vec, s);
-  return launch_h<64, MODE>(Ahi, Alo, lda, Bhi, Blo, ldb, C, ldc, Ma, Nb, Mst, Nst, P, vec, s);
+  if (tile <= 0) tile = big >= 512 ? 128 : 64;
+  if (tile == 128)
+    return launch_h<128, MODE>(Ahi, Alo, lda, Bhi, Blo, ldb, C, ldc, Ma, Nb, Mst, Nst, P, vec, s,
+                               nb_dev, cmap);
+  return launch_h<64, MODE>(Ahi, Alo, lda, Bhi, Blo, ldb, C, ldc, Ma, Nb, Mst, Nst, P, vec, s,
+                            nb_dev, cmap);
 }
 
 se_status gemm_syrk_bf16x3(const uint16_t* Yhi, const uint16_t* Ylo, int ldy, int K, int P,
@@ -295,6 +307,14 @@ se_status gemm_project_bf16x3(const uint16_t* Yhi, const uint16_t* Ylo, int ldy,
                               float* R, int ldr, hipStream_t s, bool pad) {
   return dispatch_h<hStoreTransposed>(Yhi, Ylo, ldy, Xhi, Xlo, ldx, R, ldr, K, n_blk,
                                       pad ? ldr : K, n_blk, P, s);
+}
+
+se_status gemm_rows_bf16x3(const uint16_t* Yhi, const uint16_t* Ylo, int ldy, int K,
+                           const uint16_t* Xhi, const uint16_t* Xlo, int ldx, int n_max,
+                           const int32_t* n_dev, const int32_t* cmap, int P, float* rows, int ldr,
+                           int tile, hipStream_t s) {
+  return dispatch_h<hStoreTransposed>(Yhi, Ylo, ldy, Xhi, Xlo, ldx, rows, ldr, K, n_max, K, n_max,
+                                      P, s, tile, n_dev, cmap);
 }
 
 }  // namespace sefase

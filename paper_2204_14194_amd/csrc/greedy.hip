@@ -6,8 +6,9 @@
 namespace sefase {
 
 // ONE: the launch conceals the single block a.blk0 (plain per-block form); a
-// separate instantiation so profiles keep the two forms apart.
-template <int WAVES, int VPL, bool ONE>
+// separate instantiation so profiles keep the two forms apart.  Q16: the
+// rows are the fixed-point words a.Gqr.
+template <int WAVES, int VPL, bool ONE, bool Q16>
 __global__ __launch_bounds__(64 * WAVES) void k_greedy(GreedyArgs a) {
   constexpr int T = 64 * WAVES;
   constexpr int NJ = VPL / 4;
@@ -20,7 +21,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_greedy(GreedyArgs a) {
     const float4 v = *reinterpret_cast<const float4*>(src + 4 * (j * T + t));
     R[j][0] = v.x; R[j][1] = v.y; R[j][2] = v.z; R[j][3] = v.w;
   }
-  greedy_block<WAVES, VPL>(a, ONE ? a.blk0 : (int)blockIdx.x, R);
+  greedy_block<WAVES, VPL, false, Q16>(a, ONE ? a.blk0 : (int)blockIdx.x, R);
 }
 
 // Workgroup shapes: (waves, values per lane).  The capacity 64 * waves * vpl
@@ -70,10 +71,17 @@ int greedy_shapes_for(int K, int* waves, int* vpl, int cap) {
 
 template <int W, int V>
 static void launch_shape(const GreedyArgs& a, int grid, hipStream_t s) {
-  if (grid == 1 && a.blk0 >= 0)
-    hipLaunchKernelGGL((k_greedy<W, V, true>), dim3(1), dim3(64 * W), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_greedy<W, V, false>), dim3(grid), dim3(64 * W), 0, s, a);
+  const bool q = a.Gqr != nullptr;
+  if (grid == 1 && a.blk0 >= 0) {
+    if (q)
+      hipLaunchKernelGGL((k_greedy<W, V, true, true>), dim3(1), dim3(64 * W), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_greedy<W, V, true, false>), dim3(1), dim3(64 * W), 0, s, a);
+  } else if (q) {
+    hipLaunchKernelGGL((k_greedy<W, V, false, true>), dim3(grid), dim3(64 * W), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_greedy<W, V, false, false>), dim3(grid), dim3(64 * W), 0, s, a);
+  }
 }
 
 se_status launch_greedy(const GreedyArgs& a, int grid, hipStream_t s, int waves, int vpl) {

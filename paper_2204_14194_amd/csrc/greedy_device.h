@@ -44,8 +44,9 @@
 // waves) is decided by class_tie_key on the original atom indices, as eq. 18
 // with ties to the lowest index requires.
 //
-// Fixed-point rows (Q16, class form): the class rows are read as 16-bit
-// words q with 14 fraction bits and eq. 20 becomes R~ -= (tc 2^-14) q.  The
+// Fixed-point rows (Q16): the rows (class rows in the class form, else whole
+// rows of ldG words) are read as 16-bit words q with 14 fraction bits and
+// eq. 20 becomes R~ -= (tc 2^-14) q.  The
 // product tc 2^-14 q equals tc (q 2^-14) exactly (both factors' scalings are
 // powers of two), so each update rounds once, as with the FP32 entries
 // q 2^-14; only the table bytes change.
@@ -117,12 +118,14 @@ template <int NJ, int T>
 __device__ __forceinline__ uint64_t class_tie_key(const float (&R)[NJ][4], uint32_t Mb,
                                                   const ClassLayout& cl, int t) {
   static_assert(NJ * 4 <= 32, "one mask bit per value of a lane");
+  // (float compares with the |.| operand modifier: no operand of the mask
+  // is formed ahead of the rare branch that calls this)
+  const float Mf = __uint_as_float(Mb);
   uint32_t mask = 0u;
 #pragma unroll
   for (int j = 0; j < NJ; ++j)
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-      mask |= ((__float_as_uint(R[j][e]) & 0x7FFFFFFFu) == Mb ? 1u : 0u) << (4 * j + e);
+    for (int e = 0; e < 4; ++e) mask |= (fabsf(R[j][e]) == Mf ? 1u : 0u) << (4 * j + e);
   int best = -1, bo = 0x7FFFFFFF;
   for (uint32_t m = mask; m; m &= m - 1) {
     const int bit = __builtin_ctz(m);
@@ -152,7 +155,6 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
   constexpr int NJ = VPL / 4;
   constexpr int NJC = NJ / 4 > 0 ? NJ / 4 : 1;   // sweeps of one class (CLS)
   static_assert(!CLS || NJ % 4 == 0, "the class form needs whole sweeps per class");
-  static_assert(CLS || !Q16, "fixed-point rows are class rows");
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const DevBlock d = a.blk[b];
@@ -258,9 +260,27 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
 #pragma unroll
     for (int j = 0; j < NJ; ++j)
       gm[j] = fmaxf(fmaxf(fabsf(R[j][0]), fabsf(R[j][1])), fmaxf(fabsf(R[j][2]), fabsf(R[j][3])));
-    float lm = gm[0];
+    float lm;
+    bool two = false;   // class form: the lane's maximum lies in two classes
+    if constexpr (CLS) {
+      // class maxima, their largest, and their second largest (the larger
+      // of the smaller of each pair and the smaller pair maximum): equal to
+      // the largest exactly when two classes share it
+      float cm[4];
 #pragma unroll
-    for (int j = 1; j < NJ; ++j) lm = fmaxf(lm, gm[j]);
+      for (int c = 0; c < 4; ++c) {
+        cm[c] = gm[c * NJC];
+#pragma unroll
+        for (int j = 1; j < NJC; ++j) cm[c] = fmaxf(cm[c], gm[c * NJC + j]);
+      }
+      const float m01 = fmaxf(cm[0], cm[1]), m23 = fmaxf(cm[2], cm[3]);
+      lm = fmaxf(m01, m23);
+      two = fmaxf(fmaxf(fminf(m01, m23), fminf(cm[0], cm[1])), fminf(cm[2], cm[3])) == lm;
+    } else {
+      lm = gm[0];
+#pragma unroll
+      for (int j = 1; j < NJ; ++j) lm = fmaxf(lm, gm[j]);
+    }
     const float M = wave_max_f32(lm);
     const uint64_t holders = __builtin_amdgcn_ballot_w64(lm == M);
     if (M != 0.0f && __builtin_popcountll(holders) == 1) {
@@ -270,13 +290,14 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
       const int L = __builtin_ctzll(holders);
       const uint32_t Mb = __float_as_uint(M);
       int gsel = NJ - 1;
-      uint32_t hits = 0u;                      // the holder's groups at the maximum (class form)
+      bool mark = false;
 #pragma unroll
-      for (int j = NJ - 1; j >= 0; --j) {
-        const bool hit = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(gm[j]), L) == Mb;
-        if (j < NJ - 1) gsel = hit ? j : gsel;
-        if (CLS) hits |= (uint32_t)hit << j;
-      }
+      for (int j = NJ - 2; j >= 0; --j)
+        gsel = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(gm[j]), L) == Mb ? j : gsel;
+      // class form: a group at the maximum in another class of the lane
+      // marks the key for the atom-index rule (positions do not follow the
+      // atom order across classes)
+      if constexpr (CLS) mark = ((__builtin_amdgcn_ballot_w64(two) >> L) & 1ull) != 0ull;
       uint32_t r[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
@@ -295,14 +316,6 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
         u = 0;
         rv = 0.0f;
       }
-      // class form: groups of one lane may lie in different classes; a group
-      // at the maximum outside the first one's class marks the key for the
-      // atom-index rule
-      bool mark = false;
-      if constexpr (CLS) {
-        constexpr uint32_t one = (NJC >= 32) ? 0xFFFFFFFFu : ((1u << NJC) - 1u);
-        mark = (hits & ~(one << ((gsel / NJC) * NJC))) != 0u;
-      }
       if (WAVES > 1) key = make_key(rv, u) | (uint64_t)mark;
     } else if (M != 0.0f) {
       // exact ties across lanes: every lane's first maximum as a key
@@ -320,13 +333,11 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
       key = wave_max_key((uint32_t)(mine >> 32), (uint32_t)mine);
       if constexpr (CLS) {
         // holders in two classes mark the key for the atom-index rule
-        const uint32_t Mb = __float_as_uint(M);
         uint32_t lh = 0u;
 #pragma unroll
         for (int j = 0; j < NJ; ++j)
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            lh |= (uint32_t)((__float_as_uint(R[j][e]) & 0x7FFFFFFFu) == Mb) << j;
+          for (int e = 0; e < 4; ++e) lh |= (uint32_t)(fabsf(R[j][e]) == M) << j;
         const uint32_t cm = class_mask<NJ, NJC>(lh);
         int ncls = 0;
 #pragma unroll
@@ -339,49 +350,24 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     if (WAVES > 1) {
       if (lane == 0) s_key[par][wave] = key;
       __syncthreads();
-      key = s_key[par][0];
-#pragma unroll
-      for (int w = 1; w < WAVES; ++w) {
-        const uint64_t o = s_key[par][w];
-        key = o > key ? o : key;
-      }
+      // every group of WAVES lanes reads the waves' keys (lane i: wave
+      // i mod WAVES) and reduces them by DPP; the largest key holds the
+      // largest |R~| and, among waves tied on it, the lowest position
+      const uint64_t o = s_key[par][lane & (WAVES - 1)];
+      const uint32_t ohi = (uint32_t)(o >> 32);
+      key = group_max_key<WAVES>(ohi, (uint32_t)o);
       if constexpr (CLS) {
-        // exact ties between waves, or marked inside the winning wave, are
-        // decided on the atom index (positions do not follow it across
-        // classes): every wave keys its candidates at the maximum again
+        // class form, rare: several waves at the maximum, or a winner marked
+        // for holding it in two classes -- positions do not follow the atom
+        // order across classes, so the atom-index rule decides
         const uint32_t kh = (uint32_t)(key >> 32);
-        int nmax = 0;                          // waves whose winner is at the maximum
-        bool marked = false;                   // one of them holds it in two classes
-#pragma unroll
-        for (int w = 0; w < WAVES; ++w) {
-          const uint64_t o = s_key[par][w];
-          const bool at = (uint32_t)(o >> 32) == kh;
-          nmax += at;
-          marked = marked || (at && (o & 1u));
-        }
-        bool slow = kh != 0u && marked;
-        if (kh != 0u && nmax > 1 && !slow) {   // rare: winners of several waves tie
-          int c0 = -1;
-#pragma unroll
-          for (int w = 0; w < WAVES; ++w) {
-            const uint64_t o = s_key[par][w];
-            if ((uint32_t)(o >> 32) == kh) {
-              const int c = (0xFFFF - (int)((uint32_t)o >> 16)) / a.cl.Kc;
-              slow = slow || (c0 >= 0 && c != c0);
-              c0 = c;
-            }
-          }
-        }
-        if (slow) {
+        const uint64_t at = __builtin_amdgcn_ballot_w64(ohi == kh) & ((1ull << WAVES) - 1ull);
+        if (kh != 0u && ((at & (at - 1ull)) != 0ull || (key & 1ull) != 0ull)) {
           const uint64_t k2 = class_tie_key<NJ, T>(R, kh, a.cl, t);
           if (lane == 0) s_tie[wave] = k2;
           __syncthreads();
-          key = s_tie[0];
-#pragma unroll
-          for (int w = 1; w < WAVES; ++w) {
-            const uint64_t o = s_tie[w];
-            key = o > key ? o : key;
-          }
+          const uint64_t o2 = s_tie[lane & (WAVES - 1)];
+          key = group_max_key<WAVES>((uint32_t)(o2 >> 32), (uint32_t)o2);
           class_key = true;
         }
       }
@@ -402,7 +388,7 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     float4 row[NR];
     uint2 qrow[Q16 ? NR : 1];
     if constexpr (Q16) {
-      const int16_t* g16 = a.Gq + (size_t)u * (T * NJ);
+      const int16_t* g16 = CLS ? a.Gq + (size_t)u * (T * NJ) : a.Gqr + (size_t)u * a.ldG;
 #pragma unroll
       for (int j = 0; j < NR; ++j) qrow[j] = *reinterpret_cast<const uint2*>(g16 + 4 * (j * T + t));
     } else if constexpr (CLS) {
@@ -430,7 +416,7 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
       for (int q = 1; q < kQPL; ++q)
         if (q < nq) pv[q] = prow[poff[q]];
     }
-    if constexpr (!CLS) {
+    if constexpr (!CLS && !Q16) {
 #pragma unroll
       for (int j = 0; j < NR; ++j) row[j] = *reinterpret_cast<const float4*>(grow + 4 * (j * T + t));
     }
@@ -502,10 +488,10 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     } else {
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
-        R[j][0] = fmaf(-tc, row[j].x, R[j][0]);
-        R[j][1] = fmaf(-tc, row[j].y, R[j][1]);
-        R[j][2] = fmaf(-tc, row[j].z, R[j][2]);
-        R[j][3] = fmaf(-tc, row[j].w, R[j][3]);
+        R[j][0] = fmaf(-tr, row[j].x, R[j][0]);
+        R[j][1] = fmaf(-tr, row[j].y, R[j][1]);
+        R[j][2] = fmaf(-tr, row[j].z, R[j][2]);
+        R[j][3] = fmaf(-tr, row[j].w, R[j][3]);
       }
     }
     if constexpr (CLS) model_update();

@@ -82,8 +82,15 @@ __global__ void k_od_init(float* __restrict__ Dd, float* __restrict__ R, int n_b
 struct OdArgs {
   float* R;            // n_blk x ld, R~ = D_b R (units of D_b)
   const float* D;      // n_blk x ld
-  const float* rows;   // n_blk x ld, C_b[u_prev][k] from the last product
-  float* V;            // n_blk x ldV
+  const float* rows;   // n_blk x (slots + 1) rows of ld: the row cache
+  int slots;           // cached rows per block; row `slots` is recomputed on every use
+  int32_t* slot_of;    // n_blk x K: 1 + cache row of atom k's row, 0 if none (NULL: slots 0)
+  int32_t* nslot;      // n_blk: cache rows in use
+  int32_t* cur;        // n_blk: cache row of the last selection's row
+  int32_t* cnt;        // 2: rows requested in this iteration (by parity)
+  int32_t* cmap;       // requested row i -> its row in the cache
+  int nxt;             // blocks that iterate again (a prefix)
+  float* V;            // rows requested in this iteration: w_b phi_u (compact)
   uint16_t* Vhi;       // optional split copy of V (split-BF16 row products)
   uint16_t* Vlo;
   int ld, ldV;
@@ -110,9 +117,11 @@ __global__ __launch_bounds__(kOdThreads) void k_od_step(OdArgs a) {
   const int K = a.K, P = a.M * a.N;
   float* R = a.R + (size_t)b * a.ld;
   const float* D = a.D + (size_t)b * a.ld;
-  const float* rows = a.rows + (size_t)b * a.ld;
   const bool upd = a.nu > 0;
   const int ob = a.orig[b];
+  // the request counter of the next iteration starts at 0 (the products of
+  // the previous iteration, its last readers, have completed)
+  if (b == 0 && t == 0) a.cnt[(a.nu + 1) & 1] = 0;
   // a block with nothing to extrapolate from (no available sample, marked by
   // the host, or every atom of zero weighted norm: D_b = 0 and R~ = 0
   // everywhere) reports sel = -1 and a zero coefficient in every iteration
@@ -139,6 +148,8 @@ __global__ __launch_bounds__(kOdThreads) void k_od_step(OdArgs a) {
   }
   float sc = 0.0f;
   if (upd) sc = a.st[2 * b] * a.st[2 * b + 1];   // gamma R~_u D_u: the eq. 20 factor
+  // the row C_b[u_prev][:] (cached, or formed after the previous launch)
+  const float* rows = a.rows + ((size_t)b * (a.slots + 1) + (upd ? a.cur[b] : 0)) * a.ld;
   // update with the previous row, then find this lane's first strict maximum
   float bv = 0.0f;
   int bi = 0x7fffffff;
@@ -149,7 +160,12 @@ __global__ __launch_bounds__(kOdThreads) void k_od_step(OdArgs a) {
     float4 r = *reinterpret_cast<const float4*>(R + k0);
     if (upd) {
       const float4 d = *reinterpret_cast<const float4*>(D + k0);
-      const float4 c = *reinterpret_cast<const float4*>(rows + k0);
+      float4 c = *reinterpret_cast<const float4*>(rows + k0);
+      if (k0 + 4 > K) {   // row entries past K are never written
+        c.y = k0 + 1 < K ? c.y : 0.0f;
+        c.z = k0 + 2 < K ? c.z : 0.0f;
+        c.w = 0.0f;
+      }
       r.x = fmaf(-sc * d.x, c.x, r.x);
       r.y = fmaf(-sc * d.y, c.y, r.y);
       r.z = fmaf(-sc * d.z, c.z, r.z);
@@ -195,12 +211,36 @@ __global__ __launch_bounds__(kOdThreads) void k_od_step(OdArgs a) {
     *cp = (s - *gp) - y;
     *gp = s;
   }
-  // V row for the next product: w_b phi_u
+  // the row C_b[u][:] for the next iteration: a cached row, or a request
+  // (w_b phi_u as a compact row of V) for the products after this launch
+  if (b >= a.nxt) return;
+  __shared__ int s_req;
+  if (t == 0) {
+    int32_t* so = a.slot_of ? a.slot_of + (size_t)b * K + u : nullptr;
+    const int have = so ? *so : 0;
+    int row = a.slots;                     // the row recomputed on every use
+    int req = -1;
+    if (have > 0) {
+      row = have - 1;
+    } else {
+      if (so && a.nslot[b] < a.slots) {
+        row = a.nslot[b]++;
+        *so = row + 1;
+      }
+      req = atomicAdd(a.cnt + (a.nu & 1), 1);
+      a.cmap[req] = b * (a.slots + 1) + row;
+    }
+    a.cur[b] = row;
+    s_req = req;
+  }
+  __syncthreads();
+  const int req = s_req;
+  if (req < 0) return;
   const float* wb = a.w + (size_t)ob * P;
-  float* V = a.V + (size_t)b * a.ldV;
+  float* V = a.V + (size_t)req * a.ldV;
   if (a.Vhi) {
-    uint16_t* Vh = a.Vhi + (size_t)b * a.ldV;
-    uint16_t* Vl = a.Vlo + (size_t)b * a.ldV;
+    uint16_t* Vh = a.Vhi + (size_t)req * a.ldV;
+    uint16_t* Vl = a.Vlo + (size_t)req * a.ldV;
     for (int p = t; p < P; p += kOdThreads) {
       const float v = wb[p] * prow[p];
       uint16_t h, l;
@@ -237,17 +277,35 @@ __global__ void k_od_finish(const DevBlock* __restrict__ blk, const int32_t* __r
 }
 
 // ---------------------------------------------------------------------------
+__global__ void k_fill0_i32(int32_t* __restrict__ a, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0;
+}
+
+void launch_square(const float* phi, size_t n, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_square, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, phi, n, out);
+}
+
+// Only kernel launches, whose shapes depend on the plan alone (no copy, no
+// fill through the runtime, no synchronisation): a run can be captured in a
+// graph and replayed.
 se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s) {
   se_status st;
   const int K = pl.K, P = pl.M * pl.N, n = pl.n_blk;
-  // model accumulators start at 0 (g and gc are adjacent)
+  // model accumulators start at 0 (g and gc are adjacent); request counters,
+  // rows in use and the atom -> cached row map too
   hipLaunchKernelGGL(k_fill0, dim3((unsigned)(((size_t)2 * n * pl.ldg + 255) / 256)), dim3(256), 0,
                      s, pl.g, (size_t)2 * n * pl.ldg);
   if ((st = check_launch("fill0"))) return st;
-  // dictionary squared (for the per-block diagonal)
-  hipLaunchKernelGGL(k_square, dim3((unsigned)(((size_t)K * P + 255) / 256)), dim3(256), 0, s,
-                     pl.phi, (size_t)K * P, pl.phi2);
-  if ((st = check_launch("square"))) return st;
+  const size_t ni = 4 + 2 * (size_t)n + (pl.slots > 0 ? (size_t)n * K : 0);
+  hipLaunchKernelGGL(k_fill0_i32, dim3((unsigned)((ni + 255) / 256)), dim3(256), 0, s, pl.ibuf, ni);
+  if ((st = check_launch("fill0_i32"))) return st;
+  // dictionary squared (for the per-block diagonal), unless prepared
+  if (!pl.phi2_ready) {
+    hipLaunchKernelGGL(k_square, dim3((unsigned)(((size_t)K * P + 255) / 256)), dim3(256), 0, s,
+                       pl.phi, (size_t)K * P, pl.phi2);
+    if ((st = check_launch("square"))) return st;
+  }
   // weighted signal and weights as row blocks of the products
   hipLaunchKernelGGL(k_od_gather, dim3((P + 255) / 256, n), dim3(256), 0, s, pl.images, pl.H,
                      pl.W, pl.blk, n, pl.M, pl.N, pl.w, pl.orig, pl.X, pl.ldV);
@@ -268,6 +326,12 @@ se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s) {
   a.R = pl.R;
   a.D = pl.D;
   a.rows = pl.rows;
+  a.slots = pl.slots;
+  a.cnt = pl.ibuf;
+  a.nslot = pl.ibuf + 4;
+  a.slot_of = pl.slots > 0 ? pl.ibuf + 4 + 2 * (size_t)n : nullptr;
+  a.cur = pl.cur;
+  a.cmap = pl.cmap;
   a.V = pl.V;
   a.ld = pl.ld;
   a.ldV = pl.ldV;
@@ -295,35 +359,37 @@ se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s) {
   int lo[3] = {0, 0, 0}, hi[3] = {K, 0, 0};
   const int nr = tx ? dense_ranges(K, pl.M * pl.N, bs->n_parts, bs->parts, lo, hi) : 1;
   const bool split = pl.phi_hi != nullptr && nr > 0;   // no dense atoms: nothing to split
-  if (split) {
+  if (split && !pl.split_ready) {
     launch_split_bf16(pl.phi, (size_t)K * P, pl.phi_hi, pl.phi_lo, s);
     if ((st = check_launch("split_bf16"))) return st;
   }
   a.Vhi = split ? pl.Vhi : nullptr;
   a.Vlo = split ? pl.Vlo : nullptr;
-  if (tx) {   // the row products no longer write the padding columns
-    hipLaunchKernelGGL(k_fill0, dim3((unsigned)(((size_t)n * pl.ld + 255) / 256)), dim3(256), 0, s,
-                       pl.rows, (size_t)n * pl.ld);
-    if ((st = check_launch("fill0"))) return st;
-  }
+  const size_t rows_ld = (size_t)pl.ld;
   for (int nu = 0; nu < pl.iters_max; ++nu) {
     const int act = pl.active[nu];        // blocks still iterating at nu (a prefix)
     if (act <= 0) break;
+    const int nxt = nu + 1 < pl.iters_max ? pl.active[nu + 1] : 0;
     a.nu = nu;
+    a.nxt = nxt;
     hipLaunchKernelGGL(k_od_step, dim3(act), dim3(kOdThreads), 0, s, a);
     if ((st = check_launch("od_step"))) return st;
-    const int nxt = nu + 1 < pl.iters_max ? pl.active[nu + 1] : 0;
     if (nxt <= 0) continue;
-    // rows C_b[u_b][:] for the blocks that iterate again: transforms of
-    // w_b phi_u for the parts, a product with the dictionary for the rest
-    if (tx && (st = rows_tx(bs, pl.tx, pl.V, pl.ldV, nxt, pl.rows, pl.ld, s))) return st;
+    // rows C_b[u_b][:] requested by the blocks that iterate again (at most
+    // nxt, counted on the device): transforms of w_b phi_u for the parts, a
+    // product with the dictionary for the rest, each written to its row of
+    // the cache
+    const int32_t* cnt = pl.ibuf + (nu & 1);
+    if (tx && (st = rows_tx(bs, pl.tx, pl.V, pl.ldV, nxt, pl.rows, (int)rows_ld, s, cnt,
+                            pl.cmap)))
+      return st;
     for (int r = 0; r < nr; ++r) {
-      st = split ? gemm_project_bf16x3(pl.phi_hi + (size_t)lo[r] * P, pl.phi_lo + (size_t)lo[r] * P,
-                                       P, hi[r] - lo[r], pl.Vhi, pl.Vlo, pl.ldV, nxt, P,
-                                       pl.rows + lo[r], pl.ld, s, !tx)
-                 : gemm_project_f32(pl.phi + (size_t)lo[r] * P, P, hi[r] - lo[r], pl.V, pl.ldV,
-                                    nxt, P, pl.rows + lo[r], pl.ld, 0, s, !tx, pl.splitk,
-                                    pl.splitk_floats);
+      st = split ? gemm_rows_bf16x3(pl.phi_hi + (size_t)lo[r] * P, pl.phi_lo + (size_t)lo[r] * P,
+                                    P, hi[r] - lo[r], pl.Vhi, pl.Vlo, pl.ldV, nxt, cnt, pl.cmap, P,
+                                    pl.rows + lo[r], (int)rows_ld, pl.row_tile[r], s)
+                 : gemm_rows_f32(pl.phi + (size_t)lo[r] * P, P, hi[r] - lo[r], pl.V, pl.ldV, nxt,
+                                 cnt, pl.cmap, P, pl.rows + lo[r], (int)rows_ld, pl.row_tile[r],
+                                 pl.row_split[r], s, pl.splitk, pl.splitk_floats);
       if (st) return st;
     }
   }

@@ -177,12 +177,25 @@ se_status gemm_project_f32(const float* Y, int ldy, int K, const float* X, int l
 // product with Mst stored atoms, up to Nst_max blocks and P pixels; 0 when it
 // never splits.  Without it (or with less) the product runs unsplit.
 size_t gemm_splitk_floats(int Mst, int Nst_max, int P);
+// Rows formed on demand: rows[cmap[i]][k] = sum_p X[i][p] Y[k][p] for k < K
+// and i < min(n_max, *n_dev) (n_dev on the device, read by the kernels, so
+// the launch shape depends on n_max only); columns from K on are left alone.
+// tile: 0 = automatic, 64 or 128; split: -1 automatic, 0/1 none, S slices of
+// the contraction (partials in ws, gemm_rows_splitk_floats of it).
+se_status gemm_rows_f32(const float* Y, int ldy, int K, const float* X, int ldx, int n_max,
+                        const int32_t* n_dev, const int32_t* cmap, int P, float* rows, int ldr,
+                        int tile, int split, hipStream_t s, float* ws, size_t ws_floats);
+size_t gemm_rows_splitk_floats(int K, int n_max, int P, int split);
 // gemm_bf16x3.hip -- the same two products from split-bf16 operands
 se_status gemm_syrk_bf16x3(const uint16_t* Yhi, const uint16_t* Ylo, int ldy, int K, int P,
                            float* G, int ldg, hipStream_t s);
 se_status gemm_project_bf16x3(const uint16_t* Yhi, const uint16_t* Ylo, int ldy, int K,
                               const uint16_t* Xhi, const uint16_t* Xlo, int ldx, int n_blk, int P,
                               float* R, int ldr, hipStream_t s, bool pad = true);
+se_status gemm_rows_bf16x3(const uint16_t* Yhi, const uint16_t* Ylo, int ldy, int K,
+                           const uint16_t* Xhi, const uint16_t* Xlo, int ldx, int n_max,
+                           const int32_t* n_dev, const int32_t* cmap, int P, float* rows, int ldr,
+                           int tile, hipStream_t s);
 
 // project.hip -- X[b][p] = sqrt(w_p) s_b[p] and the per-block GEMV
 void launch_gather(const uint8_t* images, int H, int W, const DevBlock* blk,
@@ -215,8 +228,11 @@ se_status gram_mirror(const se_tables* t, hipStream_t s);
 // the A and B operands alone (for unscaled transforms) into tx
 se_status build_tx_basis(const se_basis* b, float* tx, hipStream_t s);
 // rows[b][first + k] = transform k of V[b] (M x N), for the parts of b
+// (n_dev, out_row: optional, the row count on the device, at most n_blk, and
+// the destination row of each V row)
 se_status rows_tx(const se_basis* b, const float* tx, const float* V, int ldV, int n_blk,
-                  float* rows, int ld, hipStream_t s);
+                  float* rows, int ld, hipStream_t s, const int32_t* n_dev = nullptr,
+                  const int32_t* out_row = nullptr);
 // abi.cpp -- the host-side checks of a basis' part declaration; the atom
 // ranges outside the parts
 se_status check_basis_parts(const se_basis* b);
@@ -250,7 +266,8 @@ struct GreedyArgs {
   const float* Gc;
   const int2* cls;
   // fixed-point class rows (Q1.14 words of Gc); non-NULL selects them
-  const int16_t* Gq;
+  const int16_t* Gq;   // fixed-point class rows (class form), or NULL
+  const int16_t* Gqr;  // fixed-point whole rows, ldG words each (whole-row form), or NULL
   // the class order (exact ties between classes are decided by atom index)
   ClassLayout cl;
   // optional device counter of blocks with nothing to extrapolate from
@@ -269,14 +286,21 @@ struct OnDemandPlan {
   int iters_max;
   float gamma;
   // device workspace
-  float* phi2;          // K x P
+  float* phi2;          // K x P (phi squared)
+  bool phi2_ready;      // phi2 already holds it (a prepared dictionary)
   float* X;             // n_blk x ldV
-  float* V;             // n_blk x ldV
+  float* V;             // n_blk x ldV (compact rows of the requested table rows)
   int ldV;
   float* R;             // n_blk x ld
   float* D;             // n_blk x ld
-  float* rows;          // n_blk x ld
+  float* rows;          // n_blk x (slots + 1) x ld: the cache of table rows
+  int slots;            // cached rows per block (row `slots` of a block: not cached)
+  int32_t* ibuf;        // 4 + 2 n_blk (+ n_blk K when slots > 0) ints cleared per run:
+                        // the request counters, rows in use, deg, the atom -> row map
+  int32_t* cur;         // n_blk
+  int32_t* cmap;        // n_blk
   int ld;               // multiple of 1024
+  int row_tile[3], row_split[3];   // per dense range of the row products
   const se_basis* basis;  // transform parts (rows formed as transforms)
   const float* tx;        // their A and B operands (when n_parts > 0)
   float* splitk;        // partial products of split contractions
@@ -284,6 +308,7 @@ struct OnDemandPlan {
   // split-BF16 operands of the per-iteration dense row products (NULL: FP32)
   uint16_t* phi_hi;     // K x P
   uint16_t* phi_lo;
+  bool split_ready;     // phi_hi / phi_lo already hold the split dictionary
   uint16_t* Vhi;        // n_blk x ldV
   uint16_t* Vlo;
   float* st;            // n_blk x 2
@@ -295,10 +320,12 @@ struct OnDemandPlan {
   float* coef;
   float* g_loss;
   int g_loss_ld;
-  int32_t* deg;           // n_blk workspace: blocks with nothing to extrapolate from
+  int32_t* deg;           // n_blk (inside ibuf): blocks with nothing to extrapolate from
   int32_t* n_degenerate;  // optional device counter of those blocks
 };
 se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s);
+// out = phi squared, elementwise (n floats)
+void launch_square(const float* phi, size_t n, float* out, hipStream_t s);
 
 // classes.hip -- parity classes of DCT / Walsh-Hadamard tables under a
 // mirror-symmetric weight pattern
@@ -312,6 +339,8 @@ ClassLayout class_layout(const se_tables* t);
 se_status build_classes(se_tables* t, hipStream_t s);
 // t->Gq = round(t->Gc 2^14) (16-bit words, 14 fraction bits)
 se_status quantise_classes(se_tables* t, hipStream_t s);
+// t->Gq_rows = round(t->G 2^14), every row of ldG entries
+se_status quantise_rows(se_tables* t, hipStream_t s);
 
 // fused.hip -- projections of transform parts and the loop in one launch
 bool conceal_tx_supported(const se_tables* t);
@@ -338,5 +367,15 @@ struct TuneChoice {
   int loop_waves = 0, loop_vpl = 0, proj_tile = 0;
 };
 TuneChoice tune_lookup(int K, int P, int n_blk);
+// rows on demand: the row products' tile (0 automatic, 64, 128) and split
+// (-1 automatic, 1 none, 2/4/8 slices) for Kd dense atoms of P pixels
+struct RowTune {
+  int tile = 0, split = -1;
+};
+RowTune tune_lookup_rows(int Kd, int P, int n_blk);
+// plans of rows on demand, for the tuner (abi.cpp)
+int ondemand_plan_dense(const se_od_plan* p, int kd[3], int* P);
+int ondemand_plan_blocks(const se_od_plan* p);
+void ondemand_plan_set_rows(se_od_plan* p, int tile, int split);
 
 }  // namespace sefase

@@ -225,6 +225,8 @@ struct TxRowsArgs {
   int first0, first1;
   float* rows;
   int ld;
+  const int32_t* n_dev;   // optional: rows to form counted on the device (<= n_blk)
+  const int32_t* out_row; // optional: destination row of V row i
 };
 
 template <int MT, int NT, int NP>
@@ -240,7 +242,8 @@ __global__ __launch_bounds__((tx_max_threads<MT, NT>())) void k_rows_tx(TxRowsAr
   const int l = threadIdx.x & 63, wave = threadIdx.x >> 6, W = blockDim.x >> 6;
   const int lr = l & 15, lc = 4 * (l >> 4);
   const bool vec = (N & 3) == 0;
-  for (int b = blockIdx.x * W + wave; b < a.n_blk; b += gridDim.x * W) {
+  const int nb = a.n_dev ? min(a.n_blk, *a.n_dev) : a.n_blk;
+  for (int b = blockIdx.x * W + wave; b < nb; b += gridDim.x * W) {
     const float* Vb = a.V + (size_t)b * a.ldV;
     // every load at clamped (valid) coordinates and issued before the
     // first use; entries outside the area are zeroed afterwards
@@ -272,7 +275,7 @@ __global__ __launch_bounds__((tx_max_threads<MT, NT>())) void k_rows_tx(TxRowsAr
         }
 #pragma unroll 1
     for (int q = 0; q < NP; ++q) {
-      float* Rq = a.rows + (size_t)b * a.ld + (q ? a.first1 : a.first0);
+      float* Rq = a.rows + (size_t)(a.out_row ? a.out_row[b] : b) * a.ld + (q ? a.first1 : a.first0);
       tx_part<MT, NT, false>(sm + L.oAf + q * MT * MT * 256, sm + L.oBtf + q * NT * NT * 256,
                              nullptr, xv, M, N,
                              [&](int k1, int k2, float v) { Rq[k1 * N + k2] = v; });
@@ -599,7 +602,8 @@ static se_status launch_rows_np(const TxRowsArgs& a, const TxLayout& L, int grid
 }
 
 se_status rows_tx(const se_basis* b, const float* tx, const float* V, int ldV, int n_blk,
-                  float* rows, int ld, hipStream_t s) {
+                  float* rows, int ld, hipStream_t s, const int32_t* n_dev,
+                  const int32_t* out_row) {
   if (n_blk <= 0) return SE_OK;
   if (b->n_parts < 1 || b->n_parts > 2) return fail(SE_EINVAL, "no transform part declared");
   TxRowsArgs a;
@@ -611,6 +615,8 @@ se_status rows_tx(const se_basis* b, const float* tx, const float* V, int ldV, i
   a.first1 = b->n_parts > 1 ? b->parts[1].first : 0;
   a.rows = rows;
   a.ld = ld;
+  a.n_dev = n_dev;
+  a.out_row = out_row;
   const int MT = (b->M + 15) / 16, NT = (b->N + 15) / 16;
   int waves = (MT >= 3 || MT * NT >= 6) ? 4 : 16;
   while (waves > 1 && (long long)waves * 256 > n_blk) waves /= 2;

@@ -132,22 +132,26 @@ def table_errors(t, C, D):
 
 
 def quant_table_errors(t, C, D):
-    """Per-atom error of the device's fixed-point class rows against the
-    oracle's own words of the same pattern (the reference of the fixed-point
-    route): row p of Gq holds the words of atom cls[p] against the atoms of
-    its class, in class order."""
+    """Per-atom error of the device's fixed-point rows against the oracle's
+    own words of the same pattern (the reference of the fixed-point route):
+    row p of the class words Gq holds the words of atom cls[p] against the
+    atoms of its class, in class order; without class words, row k of the
+    whole-row words Gq_rows holds atom k's words."""
     K = t.K
     Kc = K // 4
+    ref = oracle.quantise_table(oracle.unit_table(C, D)).astype(np.int64)
+    eps_D = np.abs(t.D.cpu().numpy().astype(np.float64) - D)
+    if t.Gq is None:   # whole-row words (the loop over whole rows)
+        Gq = t.Gq_rows.cpu().numpy()[:, :K].astype(np.int64)
+        return np.abs(Gq - ref).max(axis=1) * 2.0 ** -14, eps_D
     Gq = t.Gq.cpu().numpy().astype(np.int64)
     orig = t.cls.cpu().numpy()[:, 0].astype(np.int64)
-    ref = oracle.quantise_table(oracle.unit_table(C, D)).astype(np.int64)
     eps_G = np.zeros(K)
     for c in range(4):
         pos = np.arange(c * Kc, (c + 1) * Kc)
         a = orig[pos]
         diff = np.abs(Gq[pos] - ref[np.ix_(a, a)]).max(axis=1)
         eps_G[a] = diff * 2.0 ** -14
-    eps_D = np.abs(t.D.cpu().numpy().astype(np.float64) - D)
     return eps_G, eps_D
 
 

@@ -182,13 +182,57 @@ def test_tune_records_roundtrip_and_validation():
         B.tune_import("garbage")
     B.tune_clear()
     assert B.tune_export() == ""
+    # row-product records of rows on demand
+    B.tune_import("rows 2304 2304 10 64 4\n2048 1024 12 2 16 128\n")
+    text = B.tune_export()
+    assert "rows 2304 2304 10 64 4" in text and "2048 1024 12 2 16 128" in text
+    for bad in ("rows 2304 2304 10 96 1\n",     # unknown tile
+                "rows 2304 2304 10 64 3\n",     # unknown split
+                "rows 2304 2304 10 128 2\n",    # the wide tile does not split
+                "rows 2304 2304\n"):
+        with pytest.raises(B.SEError):
+            B.tune_import(bad)
+    B.tune_clear()
+    assert B.tune_export() == ""
+
+
+def test_rejects_bad_ondemand_plans_on_host():
+    """The prepared-dictionary and plan calls check their arguments before
+    any device work: NULL handles, complex or multi-frame dictionaries,
+    unknown flags."""
+    L = B.lib()
+    h = C.c_void_p()
+    bas = B.make_basis(24, 24, 1152, 0x1000)
+    assert L.se_ondemand_prepare(None, 0, C.byref(h), None) == B.SE_EINVAL
+    assert L.se_ondemand_prepare(C.byref(bas), 0, None, None) == B.SE_EINVAL
+    assert L.se_ondemand_prepare(C.byref(bas), 4, C.byref(h), None) == B.SE_EINVAL
+    assert b"unknown flags" in L.se_last_error()
+    cplx = B.make_basis(24, 24, 1152, 0x1000, phi_im_ptr=0x2000)
+    assert L.se_ondemand_prepare(C.byref(cplx), 0, C.byref(h), None) == B.SE_EINVAL
+    assert b"real dictionaries" in L.se_last_error()
+    vol = B.make_basis(16, 16, 2048, 0x1000, T=4)
+    assert L.se_ondemand_prepare(C.byref(vol), 0, C.byref(h), None) == B.SE_EINVAL
+    assert not h.value
+    assert L.se_ondemand_plan_ws_bytes(None, 10, 64, 0) == 0
+    blk = (B.se_block * 1)(B.se_block(0, 0, 0, 8, 8, 8, 8, 0))
+    prm = B.se_params(0.5, 10, 0)
+    p = C.c_void_p()
+    assert L.se_ondemand_plan_create(None, 1, 64, 64, blk, 1, prm, None, 0, None, 0, None,
+                                     C.byref(p)) == B.SE_EINVAL
+    fake = C.c_void_p(0x1000)
+    assert L.se_ondemand_run(None, fake, fake, None, None, None, 0, None) == B.SE_EINVAL
+    assert L.se_ondemand_plan_info(None, None, None, None) == -1
+    assert L.se_autotune_ondemand(None, fake, fake, 1, None, None) == B.SE_EINVAL
+    L.se_ondemand_release(None)
+    L.se_ondemand_plan_release(None)
 
 
 def test_struct_layouts_match_header(tmp_path):
     """Every ctypes structure of the binding has the size and field offsets of
     the C declaration (compiled here with the host compiler)."""
     structs = [B.se_part, B.se_basis, B.se_block, B.se_tables, B.se_params, B.se_serve_config,
-               B.se_loss, B.se_request, B.se_result, B.se_serve_stats, B.se_tune_result]
+               B.se_loss, B.se_request, B.se_result, B.se_serve_stats, B.se_tune_result,
+               B.se_tune_rows_result]
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "se.h"', "int main(void) {"]
     for S in structs:
         name = S.__name__
@@ -276,9 +320,11 @@ def test_rejects_bad_video_areas_on_host():
 
 
 def test_rejects_fixed_point_rows_on_host():
-    """SE_ROWS_Q14 is taken only by the one-launch calls on class tables with
-    fixed-point rows, SE_ROWS_BF16X3 only by rows on demand; unknown flags,
-    the other calls and misaligned rows are refused before any device work."""
+    """SE_ROWS_Q14 is taken by the one-launch calls on class tables with
+    fixed-point class rows and by the loop over whole rows on tables with
+    whole-row words, SE_ROWS_BF16X3 only by rows on demand; unknown flags,
+    the other cases and misaligned words are refused before any device
+    work."""
     L = B.lib()
     fake = C.c_void_p(0x1000)
     t = _tables_struct(K=2048, M=32, N=32)          # no parts, no class tables
@@ -313,6 +359,16 @@ def test_rejects_fixed_point_rows_on_host():
     assert L.se_weighted_gram(C.byref(bas), fake, 0, 0, C.byref(t), fake, 1 << 20,
                               None) == B.SE_EINVAL
     assert b"Gq" in L.se_last_error()
+    t.Gq = None
+    t.Gq_rows = 0x1002
+    assert L.se_weighted_gram(C.byref(bas), fake, 0, 0, C.byref(t), fake, 1 << 20,
+                              None) == B.SE_EINVAL
+    assert b"Gq_rows" in L.se_last_error()
+    # whole-row words: the loop over whole rows (these tables have no
+    # one-launch form) takes SE_ROWS_Q14 and reaches the workspace check
+    t.Gq_rows = 0x2000
+    for name in ("se_extrapolate_batch", "se_extrapolate_plain"):
+        assert call(name, q14) == B.SE_ENOMEM, name
 
 
 def test_rejects_overlapping_losses_on_host():

@@ -36,7 +36,8 @@ def upload_phi(phi):
 
 
 def shared_tables(images, blocks, phi32, M, N, rho_hat, precision=B.SE_FP32, flags=0,
-                  ref_block=0, parts=(), classes=True, fixed_point=False):
+                  ref_block=0, parts=(), classes=True, fixed_point=False,
+                  fixed_point_rows=False):
     """Weights of block ``ref_block`` computed on the device, then the tables
     (with buffers for parity-class tables unless ``classes`` is False)."""
     n_img, H, W = images.shape
@@ -44,7 +45,8 @@ def shared_tables(images, blocks, phi32, M, N, rho_hat, precision=B.SE_FP32, fla
     lost_d = torch.from_numpy(lost).to(dev())
     w = B.area_weights(M, N, rho_hat, lost_d, [blocks[ref_block]])
     t = B.weighted_gram(phi32, w[0].contiguous(), M, N, precision, flags, parts=parts,
-                        classes=classes, fixed_point=fixed_point)
+                        classes=classes, fixed_point=fixed_point,
+                        fixed_point_rows=fixed_point_rows)
     return t, w[0], lost
 
 

@@ -1,10 +1,11 @@
-"""Fixed-point class rows (Section III: the loop of Algorithm 3 has no
-division, so its tables suit fixed-point words; the bit depth is open).  The
-device's 16-bit words against the oracle's quantisation of its own FP64
+"""Fixed-point rows (Section III: the loop of Algorithm 3 has no division,
+so its tables suit fixed-point words; the bit depth is open).  Class rows:
+the device's 16-bit words against the oracle's quantisation of its own FP64
 table, the fixed-point route against the oracle run on those words, the
 exactness of the word arithmetic (the fixed-point route equals the FP32
 route on the dequantised rows bit for bit, eager and replayed from a graph),
-both loop shapes, areas of four frames and 64 x 64 areas."""
+both loop shapes, areas of four frames and 64 x 64 areas.  Whole rows (the
+loop over whole rows, tables without parts): the same three checks."""
 import numpy as np
 import pytest
 import torch
@@ -232,3 +233,82 @@ def test_fixed_point_edge_cases():
     with pytest.raises(RuntimeError, match="SE_ROWS_Q14"):
         B.extrapolate_batch(t2, torch.from_numpy(images).to(dev()), blocks, 0.5, 10,
                             rows_q14=True)
+
+
+# ---------------------------------------------------------------------------
+# whole-row words: the loop over whole rows (tables without the one-launch form)
+# ---------------------------------------------------------------------------
+def _dense_tables(d, M, n_img_blocks=None):
+    phi32 = synth.round_to_f32(d["phi"])
+    t, w, lost = shared_tables(d["images"], d["blocks"], upload_phi(phi32), M, M, 0.8,
+                               fixed_point_rows=True)
+    torch.cuda.synchronize()
+    assert t.n_classes == 0 and t.Gq_rows is not None and t.Gq_rows.dtype == torch.int16
+    return phi32, t, lost
+
+
+def _row_twin(t):
+    """The same tables with G replaced by the whole-row words times 2^-14
+    (FP32, exact): the FP32 loop on them must equal the fixed-point loop."""
+    return B.Tables(t.M, t.N, t.K, t.ldG, (t.Gq_rows.float() * 2.0 ** -14).contiguous(), t.D,
+                    t.Y, t.sqrtw, t.phi, t.info, t.precision, Yhi=t.Yhi, Ylo=t.Ylo,
+                    parts=t.parts, tx=t.tx, T=t.T)
+
+
+def test_whole_row_words_match_oracle():
+    d = synth.area32_inputs(2)
+    say("whole-row words: 32x32 areas, no parts, K=2048")
+    phi32, t, lost = _dense_tables(d, 32)
+    b = d["blocks"][0]
+    _, sup = oracle.area_signal(d["images"][b.img], lost[b.img], b.y0, b.x0, 32, 32)
+    C, D = oracle.table_generation(phi32, oracle.area_weights(32, 32, 0.8, sup))
+    G = oracle.unit_table(C, D)
+    ref = oracle.quantise_table(G).astype(np.int32)
+    Gq = t.Gq_rows.cpu().numpy().astype(np.int32)
+    K = 2048
+    diff = np.abs(Gq[:, :K] - ref)
+    x = G * 2.0 ** 14
+    near = np.abs(np.abs(x - np.floor(x)) - 0.5)[diff > 0]
+    print(f"whole-row words differing from the oracle's: {int((diff > 0).sum())} of {K * K} "
+          f"(by at most {int(diff.max())})")
+    assert diff.max() <= 1 and (near < 1e-2).all()
+    assert (Gq[np.arange(K), np.arange(K)] == 16384).all()
+    assert (Gq[:, K:] == 0).all()
+
+
+def test_whole_row_route_is_exact_word_arithmetic():
+    """The loop over whole rows with SE_ROWS_Q14 equals the FP32 loop on the
+    dequantised words bit for bit (batch call and plain per-block form)."""
+    d = synth.area32_inputs(4)
+    say("whole-row words: Q14 loop == FP32 loop on dequantised rows (batch, plain)")
+    _, t, _ = _dense_tables(d, 32)
+    q = _run(t, d["images"], d["blocks"], 100, True)
+    f = _run(_row_twin(t), d["images"], d["blocks"], 100, False)
+    for name, x, y in zip(("sel", "coef", "g_loss", "image"), q, f):
+        assert torch.equal(x, y), f"{name} differs"
+    img = torch.from_numpy(d["images"]).to(dev())
+    bl = d["blocks"][:8]
+    sel, coef, g = B.extrapolate_plain(t, img, bl, 0.5, 100, rows_q14=True)
+    img2 = torch.from_numpy(d["images"]).to(dev())
+    sel2, coef2, g2 = B.extrapolate_plain(_row_twin(t), img2, bl, 0.5, 100)
+    torch.cuda.synchronize()
+    assert torch.equal(sel, sel2) and torch.equal(coef, coef2) and torch.equal(g, g2)
+    assert torch.equal(img, img2)
+
+
+def test_whole_row_route_area64_against_oracle():
+    """64 x 64 areas without declared parts (K = 8192, the loop over whole
+    rows, four waves per block): the fixed-point loop against the oracle run
+    on its own words, on a seeded sample of 16 of 256 blocks."""
+    d = synth.area64_inputs(1)
+    say("whole-row words: 64x64 areas, no parts, K=8192, I=300, 256 blocks")
+    phi32, t, lost = _dense_tables(d, 64)
+    n = 256
+    sel, coef, g, img = [x.numpy() for x in _run(t, d["images"], d["blocks"], 300, True, n=n)]
+    sample = sorted(np.random.default_rng(64).choice(n, 16, replace=False))
+    st = oracle_check(d["images"], d["blocks"][:n], phi32, 64, 64, 0.8, 0.5, 300, sel, g, img,
+                      sample=sample, tol=TOL_Q14, q14=True, tables=t,
+                      lost=synth.lost_mask(2048, 2048, d["blocks"])[None])
+    print(f"whole-row words area 64 vs oracle on words: {describe(st)}")
+    assert st["worst"] <= TOL_Q14
+
