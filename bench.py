@@ -222,6 +222,9 @@ def main():
     ap.add_argument("--no-parts", action="store_true",
                     help="do not declare the dictionary's transform parts (projections by "
                          "GEMM against every atom)")
+    ap.add_argument("--clustered-route", default="all", choices=["all", "cached"],
+                    help="clustered: every route (default), or only the plans with every row "
+                         "cached, FP32 (a profile of that route alone)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="before timing, copy a buffer of this many MiB once (a kernel of "
                          "known traffic for scaling memory counters)")
@@ -394,6 +397,39 @@ def main():
                     "blocks"}
         del tq, dblk_q
 
+    # the route of an arbitrary (numerically defined) dictionary at the same
+    # workload: no declared parts, so the projections are the FP32 GEMM
+    # against every atom and the loop streams whole rows of G; and the same
+    # loop on whole rows as 16-bit words (SE_ROWS_Q14, opt-in)
+    arbitrary = None
+    if not args.no_parts:
+        ta = B.weighted_gram(phi_d, w[0].contiguous(), M, N, fixed_point_rows=True)
+        dblk_a = B.DeviceBlocks(ta, images_d, blocks)
+        ws_a = torch.empty(max(1, B.project_ws_bytes(ta, nblk)), dtype=torch.uint8, device=dev)
+
+        def dense_step(ev=None, st=None, q14=False):
+            if ev is not None:
+                ev[0].record(stream)
+            B.project(ta, images_d, dblk_a, R, ws_a, stream=st)
+            if ev is not None:
+                ev[1].record(stream)
+            B.iterate(ta, R, images_d, dblk_a, GAMMA, ITERS, stream=st, rows_q14=q14)
+            if ev is not None:
+                ev[2].record(stream)
+        a_ms, a_evs = timed(dense_step, args.steps)
+        aq_ms, aq_evs = timed(lambda ev=None, st=None: dense_step(ev, st, True), args.steps)
+        arbitrary = {
+            "ms_per_step": a_ms, "blocks_per_s": nblk / (a_ms * 1e-3),
+            "project_ms": float(np.mean([e[0].elapsed_time(e[1]) for e in a_evs])),
+            "loop_ms": float(np.mean([e[1].elapsed_time(e[2]) for e in a_evs])),
+            "rows_q14": {"ms_per_step": aq_ms, "blocks_per_s": nblk / (aq_ms * 1e-3),
+                         "loop_ms": float(np.mean([e[1].elapsed_time(e[2]) for e in aq_evs]))},
+            "what": "no declared transform parts (the route of any numerically defined "
+                    "dictionary): FP32 GEMM projections against all K atoms, then the loop "
+                    "on whole rows of G (eager, two launches); rows_q14: the loop reading "
+                    "G as 16-bit words (SE_ROWS_Q14, opt-in: the words change the result)"}
+        del ta, dblk_a, ws_a
+
     # the same step captured once into a HIP graph and replayed
     graph_info = None
     if not args.no_graph:
@@ -550,6 +586,7 @@ def main():
         "two_launch": split,
         "full_rows": full_rows,
         "fixed_point_rows": fixed_point,
+        "arbitrary_dictionary": arbitrary,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -846,8 +883,11 @@ def bench_clustered(args):
         for g in groups:
             cur.wait_stream(g["stream"])
 
-    call_ms = float(np.median(_timed(call_step, steps, 1)))
-    call_bf_ms = float(np.median(_timed(lambda: call_step(True), steps, 1)))
+    only_cached = args.clustered_route == "cached"
+    call_ms = call_bf_ms = None
+    if not only_cached:
+        call_ms = float(np.median(_timed(call_step, steps, 1)))
+        call_bf_ms = float(np.median(_timed(lambda: call_step(True), steps, 1)))
 
     def make_plans(rows_bf16, slots):
         plans = []
@@ -858,9 +898,14 @@ def bench_clustered(args):
                                              row_slots=slots, rows_bf16=rows_bf16)))
         return plans
 
+    # the group with the longest chain of dependent launches (the 48x48 areas:
+    # the largest row products) is issued first
+    order = sorted(range(len(groups)), key=lambda k: -groups[k]["area"])
+
     def plan_step(plans, outs=None):
         cur = torch.cuda.current_stream()
-        for k, (g, (_, pl)) in enumerate(zip(groups, plans)):
+        for k in order:
+            g, (_, pl) = groups[k], plans[k]
             st = g["stream"]
             st.wait_stream(cur)
             o = outs[k] if outs else (None, None, None)
@@ -871,9 +916,18 @@ def bench_clustered(args):
         for g in groups:
             cur.wait_stream(g["stream"])
 
-    def route(rows_bf16, slots, want_counts=False):
+    def route(rows_bf16, slots, want_counts=False, tune=False):
         plans = make_plans(rows_bf16, slots)
         res = {}
+        if tune:   # the row products' tile and split, per plan, on its own runs
+            res["tuned"] = {}
+            for g, (_, pl) in zip(groups, plans):
+                try:
+                    tile, split, ms = pl.autotune(g["w"], img, reps=1)
+                    res["tuned"][str(g["area"])] = {"tile": tile, "split": split}
+                except B.SEError:
+                    res["tuned"][str(g["area"])] = None   # no dense atoms to tune
+            torch.cuda.synchronize()
         if want_counts:   # selections of one eager run give the rows formed
             outs = [pl.outputs(dev, True, False, False) for _, pl in plans]
             plan_step(plans, outs)
@@ -894,9 +948,14 @@ def bench_clustered(args):
         torch.cuda.empty_cache()
         return res
 
-    cached = route(False, None, want_counts=True)
-    uncached = route(False, 0)
-    cached_bf = route(True, None)
+    cached = route(False, None, want_counts=True, tune=not args.no_autotune)
+    # batches the cached FP32 route ran (the one run that counts the rows, the
+    # warm-up and the timed runs, eager and replayed)
+    batches = 1 + (steps + 1) * (1 if args.no_graph else 2)
+    uncached = cached_bf = {}
+    if not only_cached:
+        uncached = route(False, 0)
+        cached_bf = route(True, None)
     # the dense row products (plus the diagonal and projection products of
     # every block) in FP32 matrix-core flops per batch
     flops = 0.0
@@ -917,7 +976,7 @@ def bench_clustered(args):
                     "selections of one run, x 2 x dense atoms x M*N) and the per-block diagonal "
                     "and projection products, per batch; k_gemm_nt_f32 time from the committed "
                     "kernel statistics of the same sources"}
-    if prof is not None and "gemm_f32_ms_per_batch" in prof:
+    if prof is not None and "gemm_f32_ms_per_batch" in prof and not only_cached:
         gms = float(prof["gemm_f32_ms_per_batch"])
         gemm.update({"kernel_ms_per_batch": gms, "tflops": flops / (gms * 1e-3) / 1e12,
                      "frac": flops / (gms * 1e-3) / 1e12 / 157.3})
@@ -934,14 +993,16 @@ def bench_clustered(args):
                                 "block, the three groups as one captured HIP graph"
                                 if "graph_ms" in cached else
                                 "prepared dictionaries + plans, every table row cached, eager"},
+            "cached_route_batches_run": batches,
+            "row_products_tuned": cached.get("tuned"),
             "blocks_per_area": {str(g["area"]): len(g["blocks"]) for g in groups},
             "rows_formed": rows_formed,
             "routes_ms": {"call_fp32": call_ms, "call_bf16x3_rows": call_bf_ms,
                           "plan_cached_eager": cached["eager_ms"],
                           "plan_cached_graph": cached.get("graph_ms"),
-                          "plan_uncached_eager": uncached["eager_ms"],
+                          "plan_uncached_eager": uncached.get("eager_ms"),
                           "plan_uncached_graph": uncached.get("graph_ms"),
-                          "plan_cached_bf16x3_rows_eager": cached_bf["eager_ms"],
+                          "plan_cached_bf16x3_rows_eager": cached_bf.get("eager_ms"),
                           "plan_cached_bf16x3_rows_graph": cached_bf.get("graph_ms")},
             "row_gemm": gemm}
 

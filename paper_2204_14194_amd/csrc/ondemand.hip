@@ -151,15 +151,16 @@ __global__ __launch_bounds__(kOdThreads) void k_od_step(OdArgs a) {
   // the row C_b[u_prev][:] (cached, or formed after the previous launch)
   const float* rows = a.rows + ((size_t)b * (a.slots + 1) + (upd ? a.cur[b] : 0)) * a.ld;
   // update with the previous row, then find this lane's first strict maximum
-  float bv = 0.0f;
+  // (and its D, so the winner's D_u needs no further load)
+  float bv = 0.0f, bd = 0.0f;
   int bi = 0x7fffffff;
   const int nj = a.ld / (4 * kOdThreads);
   for (int j = 0; j < nj; ++j) {
     const int k0 = 4 * (j * kOdThreads + t);
     if (k0 >= K) break;   // the padding (always 0) is neither updated nor a candidate
     float4 r = *reinterpret_cast<const float4*>(R + k0);
+    const float4 d = *reinterpret_cast<const float4*>(D + k0);
     if (upd) {
-      const float4 d = *reinterpret_cast<const float4*>(D + k0);
       float4 c = *reinterpret_cast<const float4*>(rows + k0);
       if (k0 + 4 > K) {   // row entries past K are never written
         c.y = k0 + 1 < K ? c.y : 0.0f;
@@ -172,23 +173,36 @@ __global__ __launch_bounds__(kOdThreads) void k_od_step(OdArgs a) {
       r.w = fmaf(-sc * d.w, c.w, r.w);
       *reinterpret_cast<float4*>(R + k0) = r;
     }
-    if (fabsf(r.x) > fabsf(bv)) { bv = r.x; bi = k0; }
-    if (fabsf(r.y) > fabsf(bv)) { bv = r.y; bi = k0 + 1; }
-    if (fabsf(r.z) > fabsf(bv)) { bv = r.z; bi = k0 + 2; }
-    if (fabsf(r.w) > fabsf(bv)) { bv = r.w; bi = k0 + 3; }
+    if (fabsf(r.x) > fabsf(bv)) { bv = r.x; bi = k0; bd = d.x; }
+    if (fabsf(r.y) > fabsf(bv)) { bv = r.y; bi = k0 + 1; bd = d.y; }
+    if (fabsf(r.z) > fabsf(bv)) { bv = r.z; bi = k0 + 2; bd = d.z; }
+    if (fabsf(r.w) > fabsf(bv)) { bv = r.w; bi = k0 + 3; bd = d.w; }
   }
   const uint64_t mine = make_key(bv, bi == 0x7fffffff ? 0 : bi);
   uint64_t key = wave_max_key((uint32_t)(mine >> 32), (uint32_t)mine);
+  // the D of the wave's winner (the lane whose key is the maximum; keys of
+  // different atoms differ, and with every score 0 the coefficient is 0
+  // whatever D is taken)
+  const int wl = (int)__builtin_ctzll(__builtin_amdgcn_ballot_w64(mine == key));
+  const float wd = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bd), wl));
   __shared__ uint64_t s_key[kOdThreads / 64];
-  if (lane == 0) s_key[wave] = key;
+  __shared__ float s_d[kOdThreads / 64];
+  if (lane == 0) {
+    s_key[wave] = key;
+    s_d[wave] = wd;
+  }
   __syncthreads();
   key = s_key[0];
+  float Du = s_d[0];
 #pragma unroll
-  for (int i = 1; i < kOdThreads / 64; ++i) key = s_key[i] > key ? s_key[i] : key;
+  for (int i = 1; i < kOdThreads / 64; ++i)
+    if (s_key[i] > key) {
+      key = s_key[i];
+      Du = s_d[i];
+    }
   int u;
   float rv;
   decode_key(key, K, u, rv);
-  const float Du = D[u];
   const float tc = a.gamma * rv;          // coefficient of the unit-norm atom
   const float c = tc * Du;                // eq. 19
   if (t == 0) {
@@ -197,25 +211,12 @@ __global__ __launch_bounds__(kOdThreads) void k_od_step(OdArgs a) {
     if (a.sel) a.sel[(size_t)ob * a.iters_max + a.nu] = u;
     if (a.coef) a.coef[(size_t)ob * a.iters_max + a.nu] = c;
   }
-  // model over the loss (eq. 9), compensated
-  const DevBlock d = a.blk[b];
-  const float* prow = a.phi + (size_t)u * P;
-  const int nloss = d.lh * d.lw;
-  for (int q = t; q < nloss; q += kOdThreads) {
-    const int my = q / d.lw, mx = q - my * d.lw;
-    const float pv = prow[(d.ly + my) * a.N + d.lx + mx];
-    float* gp = a.g + (size_t)b * a.ldg + q;
-    float* cp = a.gc + (size_t)b * a.ldg + q;
-    const float y = fmaf(c, pv, -*cp);
-    const float s = *gp + y;
-    *cp = (s - *gp) - y;
-    *gp = s;
-  }
   // the row C_b[u][:] for the next iteration: a cached row, or a request
-  // (w_b phi_u as a compact row of V) for the products after this launch
-  if (b >= a.nxt) return;
+  // (w_b phi_u as a compact row of V) for the products after this launch;
+  // decided by the last wave while the first ones update the model
+  const bool more = b < a.nxt;
   __shared__ int s_req;
-  if (t == 0) {
+  if (more && t == kOdThreads - 64) {
     int32_t* so = a.slot_of ? a.slot_of + (size_t)b * K + u : nullptr;
     const int have = so ? *so : 0;
     int row = a.slots;                     // the row recomputed on every use
@@ -233,6 +234,21 @@ __global__ __launch_bounds__(kOdThreads) void k_od_step(OdArgs a) {
     a.cur[b] = row;
     s_req = req;
   }
+  // model over the loss (eq. 9), compensated
+  const DevBlock d = a.blk[b];
+  const float* prow = a.phi + (size_t)u * P;
+  const int nloss = d.lh * d.lw;
+  for (int q = t; q < nloss; q += kOdThreads) {
+    const int my = q / d.lw, mx = q - my * d.lw;
+    const float pv = prow[(d.ly + my) * a.N + d.lx + mx];
+    float* gp = a.g + (size_t)b * a.ldg + q;
+    float* cp = a.gc + (size_t)b * a.ldg + q;
+    const float y = fmaf(c, pv, -*cp);
+    const float s = *gp + y;
+    *cp = (s - *gp) - y;
+    *gp = s;
+  }
+  if (!more) return;
   __syncthreads();
   const int req = s_req;
   if (req < 0) return;
