@@ -183,6 +183,7 @@ def issue_rates(images: int, profile: str, sources):
 
 
 LOOP_SOURCES = ("greedy.hip", "greedy_device.h", "argmax.h")
+CLUSTERED_SOURCES = ("gemm.hip", "ondemand.hip")
 FUSED_SOURCES = ("fused.hip", "greedy_device.h", "tx_device.h", "argmax.h")
 
 
@@ -969,8 +970,7 @@ def bench_clustered(args):
                                        "every_use": _row_requests(sel, g["iters"], False)}
         flops += 2.0 * kd * A * req + 2 * 2.0 * K * A * len(g["blocks"])
     best = cached.get("graph_ms", cached["eager_ms"])
-    prof = _profile_values(256, "ondemand_clustered_kernel_stats.txt",
-                           ["gemm.hip", "ondemand.hip", "transform.hip", "abi.cpp"])
+    prof = _profile_values(256, "ondemand_clustered_kernel_stats.txt", CLUSTERED_SOURCES)
     gemm = {"flops_per_batch": flops, "peak_tflops": 157.3,
             "what": "FP32 matrix-core flops of the dense row products (rows formed, from the "
                     "selections of one run, x 2 x dense atoms x M*N) and the per-block diagonal "

@@ -656,7 +656,13 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w,
  * later plans, and sets it in this plan.  A split other than none changes
  * the order of the FP32 sums (results stay within the FP32 rounding of the
  * products); SE_INVARIANT plans never split.  SE_EINVAL if the plan has
- * no dense atoms (every row a transform) or no blocks. */
+ * no dense atoms (every row a transform) or no blocks.
+ *
+ * se_ondemand_extrapolate: se_extrapolate_ondemand on a prepared dictionary
+ * (same arguments, results bit for bit; b replaced by d): no verification,
+ * no phi squared, no synchronisation; the descriptors are staged from host
+ * memory as by the other calls.  ws: se_ondemand_plan_ws_bytes(d, n_blk,
+ * max_loss, 0) bytes. */
 typedef struct se_od_dict se_od_dict;
 typedef struct se_od_plan se_od_plan;
 se_status se_ondemand_prepare(const se_basis* b, uint32_t flags, se_od_dict** out,
@@ -673,6 +679,11 @@ int32_t se_ondemand_plan_info(const se_od_plan* p, int32_t* iters_max, int32_t* 
 se_status se_ondemand_run(const se_od_plan* p, const float* w, uint8_t* images, int32_t* sel,
                           float* coef, float* g_loss, int32_t g_loss_ld, void* stream);
 void se_ondemand_plan_release(se_od_plan* p);
+se_status se_ondemand_extrapolate(const se_od_dict* d, const float* w, uint8_t* images,
+                                  int32_t n_img, int32_t H, int32_t W, const se_block* blocks,
+                                  int32_t n_blk, se_params prm, const int32_t* iters,
+                                  int32_t* sel, float* coef, float* g_loss, int32_t g_loss_ld,
+                                  void* ws, size_t ws_bytes, void* stream);
 typedef struct {
   int32_t row_tile, row_split;  /* 0 / -1: the automatic rules */
   float run_ms;                 /* best measured run time */

@@ -186,6 +186,9 @@ def lib():
     L.se_ondemand_plan_release.argtypes = [vp]
     L.se_autotune_ondemand.restype = i32
     L.se_autotune_ondemand.argtypes = [vp, vp, vp, i32, vp, vp]
+    L.se_ondemand_extrapolate.restype = i32
+    L.se_ondemand_extrapolate.argtypes = [vp, vp, vp, i32, i32, i32, vp, i32, se_params, vp, vp,
+                                          vp, vp, i32, vp, sz, vp]
     _lib = L
     return L
 
@@ -638,6 +641,35 @@ class OnDemandDict:
                                      C.byref(h), _stream(stream)))
         self.handle = h
 
+    def extrapolate(self, w: torch.Tensor, images: torch.Tensor, blocks: Sequence, gamma: float,
+                    iters, want_sel=True, want_coef=True, want_g=True, stream=None,
+                    rows_bf16: bool = False, invariant: bool = False):
+        """se_ondemand_extrapolate: extrapolate_ondemand on this prepared
+        dictionary (no synchronisation).  Returns (sel, coef, g_loss)."""
+        L = lib()
+        _dev_f32(w, "w")
+        n_img, H, W = images.shape
+        n = len(blocks)
+        dev = images.device
+        per = None
+        if isinstance(iters, int):
+            imax = iters
+        else:
+            per = (C.c_int32 * max(n, 1))(*[int(v) for v in iters])
+            imax = max([int(v) for v in iters] + [0])
+        sel = torch.empty((n, imax), dtype=torch.int32, device=dev) if want_sel else None
+        coef = torch.empty((n, imax), dtype=torch.float32, device=dev) if want_coef else None
+        gld = max([loss_size(b) for b in blocks] + [1])
+        g = torch.zeros((n, gld), dtype=torch.float32, device=dev) if want_g else None
+        ws = _workspace(L.se_ondemand_plan_ws_bytes(self.handle, n, gld, 0), dev)
+        prm = se_params(float(gamma), int(imax), (SE_ROWS_BF16X3 if rows_bf16 else 0) |
+                        (SE_INVARIANT if invariant else 0))
+        return _check_results(L.se_ondemand_extrapolate(self.handle, _ptr(w), _ptr(images), n_img,
+                                                        H, W, blocks_array(blocks), n, prm, per,
+                                                        _ptr(sel), _ptr(coef), _ptr(g), gld,
+                                                        _ptr(ws), ws.numel(), _stream(stream)),
+                              (sel, coef, g))
+
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             lib().se_ondemand_release(self.handle)
@@ -775,7 +807,7 @@ TUNE_EXPORTED = ("se_autotune_batch", "se_tune_export", "se_tune_import", "se_tu
                  "se_autotune_ondemand")
 PLAN_EXPORTED = ("se_ondemand_prepare", "se_ondemand_release", "se_ondemand_plan_ws_bytes",
                  "se_ondemand_plan_create", "se_ondemand_plan_info", "se_ondemand_run",
-                 "se_ondemand_plan_release")
+                 "se_ondemand_plan_release", "se_ondemand_extrapolate")
 EXPORTED = EXPORTED + SERVE_EXPORTED + TUNE_EXPORTED + PLAN_EXPORTED
 
 

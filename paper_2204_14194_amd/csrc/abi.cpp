@@ -1036,6 +1036,8 @@ static se_status plan_ondemand_batch(const se_basis* b, int n_img, int H, int W,
   return SE_OK;
 }
 
+// (pageable sources: each copy returns once its data has been staged, so the
+// vectors may go out of scope after the call)
 static se_status upload_ondemand_batch(const OdBatch& ob, const OdCarve& oc, hipStream_t s) {
   hipError_t e = hipMemcpyAsync(oc.dblk, ob.sorted.data(), ob.sorted.size() * sizeof(se_block),
                                 hipMemcpyHostToDevice, s);
@@ -1310,6 +1312,60 @@ se_status se_ondemand_plan_create(const se_od_dict* d, int32_t n_img, int32_t H,
 }
 
 void se_ondemand_plan_release(se_od_plan* p) { delete p; }
+
+se_status se_ondemand_extrapolate(const se_od_dict* d, const float* w, uint8_t* images,
+                                  int32_t n_img, int32_t H, int32_t W, const se_block* blocks,
+                                  int32_t n_blk, se_params prm, const int32_t* iters,
+                                  int32_t* sel, float* coef, float* g_loss, int32_t g_loss_ld,
+                                  void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  if (!d || !w || !images) return fail(SE_EINVAL, "NULL argument");
+  se_status st;
+  if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
+  if (prm.flags & SE_ROWS_Q14) return fail(SE_EINVAL, "rows on demand take no fixed-point rows");
+  if ((prm.flags & SE_ROWS_BF16X3) && !(d->flags & SE_ROWS_BF16X3))
+    return fail(SE_EINVAL, "SE_ROWS_BF16X3 needs a dictionary prepared with it");
+  const se_basis* b = &d->b;
+  OdBatch ob;
+  if ((st = plan_ondemand_batch(b, n_img, H, W, blocks, n_blk, prm, iters, ob))) return st;
+  if (n_blk == 0) return SE_OK;
+  const size_t need = se_ondemand_plan_ws_bytes(d, n_blk, ob.max_loss, 0);
+  if (!ws || ws_bytes < need) return fail(SE_ENOMEM, "workspace too small: need %zu bytes", need);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool bf16 = (prm.flags & SE_ROWS_BF16X3) != 0;
+  const bool invariant = (prm.flags & SE_INVARIANT) != 0;
+  Carver cv(ws);
+  OnDemandPlan pl{};
+  OdCarve oc;
+  carve_ondemand(cv, b, n_blk, ob.max_loss, 0, false, (d->flags & SE_ROWS_BF16X3) != 0, true, pl,
+                 oc);
+  fill_ondemand_plan(b, ob, oc, prm, pl);
+  pl.slots = 0;
+  pl.phi2 = d->phi2;
+  pl.phi2_ready = true;
+  pl.tx = d->tx;
+  pl.phi_hi = bf16 ? d->phi_hi : nullptr;
+  pl.phi_lo = bf16 ? d->phi_lo : nullptr;
+  pl.split_ready = true;
+  if (!bf16) pl.Vhi = pl.Vlo = nullptr;
+  if (invariant) pl.splitk_floats = 0;
+  for (int r = 0; r < 3; ++r) {
+    pl.row_tile[r] = 0;
+    pl.row_split[r] = invariant ? 1 : -1;
+  }
+  // pageable source: the call returns once the descriptors have been staged
+  if ((st = upload_ondemand_batch(ob, oc, s))) return st;
+  pl.w = w;
+  pl.images = images;
+  pl.H = H;
+  pl.W = W;
+  pl.sel = sel;
+  pl.coef = coef;
+  pl.g_loss = g_loss;
+  pl.g_loss_ld = g_loss ? g_loss_ld : 0;
+  if ((st = ondemand_run(pl, s))) return st;
+  return degenerate_status(ob.n_deg);
+}
 
 }  // extern "C"
 

@@ -101,6 +101,10 @@ struct se_server {
   std::map<sefase::PatternKey, sefase::CachedTables> cache;
   std::deque<sefase::Batch> inflight;
   size_t bytes_slots = 0, bytes_tables = 0, bytes_scratch = 0;
+  // dictionaries prepared for rows on demand, per basis set (on first use;
+  // counted with the tables, never evicted)
+  std::vector<se_od_dict*> dicts;
+  std::vector<bool> dict_tried;
   se_serve_stats stats{};    // published under mu
   se_serve_stats wstats{};   // worker-side counters
   std::thread worker;
@@ -130,6 +134,28 @@ static size_t tables_bytes(const se_basis& b) {
   return align_up((size_t)K * ld * 4, 256) + align_up((size_t)K * 4, 256) +
          align_up((size_t)K * P * 4, 256) + align_up((size_t)P * 4, 256) +
          align_up(tx_const_bytes(b.M, b.N, b.n_parts), 256) + cls + 256;
+}
+
+static void evict_for(Server* s, size_t need);
+
+// The basis set prepared for rows on demand (parts verified and phi squared
+// formed once: the one synchronisation of `st` for this basis), or nullptr
+// when the budget cannot hold it (the batch then takes the one-call form).
+static se_od_dict* ondemand_dict(Server* s, int bs, hipStream_t st) {
+  if (s->dicts[(size_t)bs]) return s->dicts[(size_t)bs];
+  if (s->dict_tried[(size_t)bs]) return nullptr;
+  s->dict_tried[(size_t)bs] = true;
+  const se_basis& b = s->sets[(size_t)bs];
+  const size_t bytes = align_up((size_t)b.K * b.M * b.N * 4, 256) +
+                       align_up(tx_const_bytes(b.M, b.N, b.n_parts), 256) + 512;
+  evict_for(s, bytes);
+  if (s->bytes_tables + s->bytes_slots + s->bytes_scratch + bytes > s->cfg.hbm_budget_bytes)
+    return nullptr;
+  se_od_dict* d = nullptr;
+  if (se_ondemand_prepare(&b, 0, &d, st) != SE_OK) return nullptr;
+  s->dicts[(size_t)bs] = d;
+  s->bytes_tables += bytes;
+  return d;
 }
 
 static void evict_for(Server* s, size_t need) {
@@ -429,9 +455,17 @@ static se_status launch_batch(Server* s, std::vector<Req*>& reqs, Batch& bt) {
                          w, aws, se_area_weights_ws_bytes(n), st);
     if (rc) return rc;
     const se_params prm{e.first.second, 0, SE_INVARIANT};
-    rc = se_extrapolate_ondemand(&b, w, s->slot_frames, nslot, H, W, blocks.data(), n, prm,
-                                 e.second.second.data(), nullptr, nullptr, nullptr, 0, ows,
-                                 ows_bytes, st);
+    int ml = 1;
+    for (auto& bl : blocks) ml = std::max(ml, bl.lh * bl.lw);
+    se_od_dict* dd = ondemand_dict(s, e.first.first, st);
+    if (dd && se_ondemand_plan_ws_bytes(dd, n, ml, 0) <= ows_bytes)   // no synchronisation
+      rc = se_ondemand_extrapolate(dd, w, s->slot_frames, nslot, H, W, blocks.data(), n, prm,
+                                   e.second.second.data(), nullptr, nullptr, nullptr, 0, ows,
+                                   ows_bytes, st);
+    else
+      rc = se_extrapolate_ondemand(&b, w, s->slot_frames, nslot, H, W, blocks.data(), n, prm,
+                                   e.second.second.data(), nullptr, nullptr, nullptr, 0, ows,
+                                   ows_bytes, st);
     if (rc && rc != SE_ENUMERIC) return rc;
   }
   for (Req* r : reqs) {
@@ -586,6 +620,8 @@ se_status se_serve_create(const se_serve_config* cfg, const se_basis* sets, int3
   std::unique_ptr<se_server> s(new se_server());
   s->cfg = *cfg;
   s->sets.assign(sets, sets + n_sets);
+  s->dicts.assign((size_t)n_sets, nullptr);
+  s->dict_tried.assign((size_t)n_sets, false);
   const size_t fb = (size_t)cfg->frame_H * cfg->frame_W;
   s->bytes_slots = 2 * fb * (size_t)cfg->max_slots;
   if (s->bytes_slots > cfg->hbm_budget_bytes) return fail(SE_ENOMEM, "slots exceed the budget");
@@ -663,6 +699,7 @@ se_status se_serve_destroy(se_server* s) {
   if (s->worker.joinable()) s->worker.join();
   for (hipStream_t st : s->streams) hipStreamSynchronize(st);
   for (auto& kv : s->cache) hipFree(kv.second.mem);
+  for (se_od_dict* d : s->dicts) se_ondemand_release(d);
   for (auto& sc : s->scratch)
     if (sc.p) hipFree(sc.p);
   for (hipStream_t st : s->streams) hipStreamDestroy(st);
