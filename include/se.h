@@ -273,14 +273,18 @@ typedef struct {
  *                 initial projections and the loop stay FP32.  Every other
  *                 call returns SE_EINVAL for it. */
 #define SE_ROWS_BF16X3 2u
-/*   SE_INVARIANT : every matrix product of the call (the initial projections
- *                 of eq. 12 and, on demand, the diagonals and table rows)
- *                 runs in one pass over its contraction, whatever the number
- *                 of blocks.  Without it a call with few blocks splits the
- *                 contraction over slices to fill the GPU, which changes the
- *                 order of the FP32 sums; with it each block's result is the
- *                 same whichever other blocks share the call (the server
- *                 sets it for the batches it forms from several requests).
+/*   SE_INVARIANT : every FP32 matrix product of the call (the initial
+ *                 projections of eq. 12 and, on demand, the diagonals and
+ *                 table rows) splits its contraction into a number of
+ *                 slices fixed by the number of samples per atom (one slice
+ *                 per 16 stages of 32 samples, at most 8), summed in slice
+ *                 order, whatever the number of blocks.  Without it the
+ *                 split follows the number of blocks (few blocks: more
+ *                 slices, to fill the GPU), which changes the order of the
+ *                 FP32 sums; with it each block's result is the same
+ *                 whichever other blocks share the call (the server sets it
+ *                 for the batches it forms from several requests).  The
+ *                 workspace sizes of every call include room for it.
  *                 Accepted by every call that takes se_params. */
 #define SE_INVARIANT 4u
 typedef struct {

@@ -225,20 +225,28 @@ static inline int round8(int v) { return (v + 7) & ~7; }
 
 // Partial products when the FP32 projection splits its contraction (few
 // blocks): sized for rows of the minimum table row length.
-static size_t project_splitk_floats(const se_tables* t, int n_blk) {
+// (partial products of the automatic split (mode 0), of the fixed split of
+// SE_INVARIANT (mode 1), or whichever is larger (mode 2: the public sizes,
+// which do not know the flags))
+static size_t project_splitk_floats(const se_tables* t, int n_blk, int mode = 2) {
   const int P = area_samples(t);
-  if (t->n_parts == 0) return gemm_splitk_floats(greedy_row_len(t->K), n_blk, P);
+  auto room = [&](int Mst) {
+    const size_t a = mode == 1 ? 0 : gemm_splitk_floats(Mst, n_blk, P);
+    const size_t b = mode == 0 ? 0 : gemm_invariant_floats(Mst, n_blk, P);
+    return std::max(a, b);
+  };
+  if (t->n_parts == 0) return room(greedy_row_len(t->K));
   if (t->n_parts > 2) return 0;
   int lo[3], hi[3];
   const int nr = dense_ranges(t->K, P, t->n_parts, t->parts, lo, hi);
   size_t f = 0;
-  for (int r = 0; r < nr; ++r) f = std::max(f, gemm_splitk_floats(hi[r] - lo[r], n_blk, P));
+  for (int r = 0; r < nr; ++r) f = std::max(f, room(hi[r] - lo[r]));
   return f;
 }
 
 // Workspace of the projection stage: X as float32 (and the partial
 // products), or as split bf16 pairs.
-static size_t project_ws(const se_tables* t, int n_blk) {
+static size_t project_ws(const se_tables* t, int n_blk, int mode = 2) {
   Carver cv(nullptr);
   const int P = area_samples(t);
   if (t->precision == SE_BF16X3) {
@@ -246,7 +254,7 @@ static size_t project_ws(const se_tables* t, int n_blk) {
     cv.take<uint16_t>((size_t)n_blk * round8(P));
   } else {
     cv.take<float>((size_t)n_blk * round4(P));
-    cv.take<float>(project_splitk_floats(t, n_blk));
+    cv.take<float>(project_splitk_floats(t, n_blk, mode));
   }
   return cv.off + 256;
 }
@@ -322,11 +330,12 @@ static se_status project_into(const se_tables* t, const uint8_t* images, int H, 
   }
   const int ldX = round4(P);
   float* X = cv.take<float>((size_t)n_blk * ldX);
-  // invariant: one pass over the contraction whatever the batch size (a
-  // split into slices depends on the number of blocks and changes the
-  // rounding)
-  const size_t split_floats = invariant ? 0 : project_splitk_floats(t, n_blk);
-  float* split = cv.take<float>(project_splitk_floats(t, n_blk));
+  // invariant: the contraction split into slices fixed by the number of
+  // samples, not by the number of blocks (the automatic split depends on the
+  // batch size, which would change the rounding)
+  const size_t split_floats = project_splitk_floats(t, n_blk, invariant ? 1 : 0);
+  float* split = cv.take<float>(split_floats);
+  const int split_rule = invariant ? kSplitShape : -1;
   launch_gather(images, H, W, dblk, n_blk, area_frames(t->T), t->M, t->N, t->sqrtw, X, ldX, s);
   if ((st = check_launch("gather"))) return st;
   if (t->phi_im) {
@@ -335,7 +344,8 @@ static se_status project_into(const se_tables* t, const uint8_t* images, int H, 
     const int K = t->K, half = ldR / 2;
     for (int part = 0; part < 2; ++part)
       if ((st = gemm_project_f32(t->Y + (size_t)part * K * P, P, K, X, ldX, n_blk, P,
-                                 R + part * half, ldR, 0, s, false, split, split_floats)))
+                                 R + part * half, ldR, 0, s, false, split, split_floats,
+                                 split_rule)))
         return st;
     launch_zero_range(R, n_blk, ldR, K, half, s);
     launch_zero_range(R, n_blk, ldR, half + K, ldR, s);
@@ -344,7 +354,7 @@ static se_status project_into(const se_tables* t, const uint8_t* images, int H, 
   const int tile = tune_lookup(t->K, P, n_blk).proj_tile;
   for (int r = 0; r < nr; ++r)
     if ((st = gemm_project_f32(t->Y + (size_t)lo[r] * P, P, hi[r] - lo[r], X, ldX, n_blk, P,
-                               R + lo[r], ldR, tile, s, pad, split, split_floats)))
+                               R + lo[r], ldR, tile, s, pad, split, split_floats, split_rule)))
       return st;
   return SE_OK;
 }
@@ -816,12 +826,13 @@ size_t se_extrapolate_batch_ws_bytes(const se_tables* t, int32_t n_blk) {
 // Workspace one batched call actually uses on its route: the descriptors,
 // and R with the projection workspace unless the projections stay in the
 // loop's workgroups.
-static size_t batch_route_ws(const se_tables* t, int n_blk) {
+// (the exact need of one call: the split room of its own flag)
+static size_t batch_route_ws(const se_tables* t, int n_blk, bool invariant) {
   Carver cv(nullptr);
   cv.take<se_block>((size_t)n_blk);
   if (!conceal_tx_supported(t)) {
     cv.take<float>((size_t)n_blk * r_row_len(t));
-    cv.take<char>(project_ws(t, n_blk));
+    cv.take<char>(project_ws(t, n_blk, invariant ? 1 : 0));
   }
   return cv.off;
 }
@@ -854,7 +865,7 @@ static se_status extrapolate(bool plain, const se_tables* t, uint8_t* images, in
   if (n_deg == n_blk && !sel && !coef && !g_loss) return degenerate_status(n_deg);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (use_static) {
-    const size_t need = batch_route_ws(t, n_blk);
+    const size_t need = batch_route_ws(t, n_blk, (prm.flags & SE_INVARIANT) != 0);
     if (need > SE_STATIC_SCRATCH_BYTES)
       return fail(SE_ENOMEM, "the batch needs %zu bytes of scratch; the static scratch holds %zu",
                   need, (size_t)SE_STATIC_SCRATCH_BYTES);
@@ -922,8 +933,10 @@ static size_t ondemand_splitk_floats(const se_basis* b, int n_blk, bool tuned = 
   const int nr = b->n_parts > 0 && b->n_parts <= 2
                      ? dense_ranges(b->K, P, b->n_parts, b->parts, lo, hi)
                      : 1;
+  f = std::max(f, gemm_invariant_floats(ld, n_blk, P));   // SE_INVARIANT's fixed split
   for (int r = 0; r < nr; ++r) {
     f = std::max(f, gemm_rows_splitk_floats(hi[r] - lo[r], n_blk, P, -1));
+    f = std::max(f, gemm_rows_splitk_floats(hi[r] - lo[r], n_blk, P, kSplitShape));
     if (tuned) f = std::max(f, gemm_rows_splitk_floats(hi[r] - lo[r], n_blk, P, 8));
   }
   return f;
@@ -1049,14 +1062,14 @@ static se_status upload_ondemand_batch(const OdBatch& ob, const OdCarve& oc, hip
 }
 
 // The row products' tile and split per dense range (tuner records, else the
-// automatic rules; one pass when invariant).
+// automatic rules; the fixed split when invariant).
 static void ondemand_row_shapes(const se_basis* b, int n_blk, bool invariant, OnDemandPlan& pl) {
   const int P = b->M * b->N;
   int lo[3] = {0, 0, 0}, hi[3] = {b->K, 0, 0};
   const int nr = b->n_parts > 0 ? dense_ranges(b->K, P, b->n_parts, b->parts, lo, hi) : 1;
   for (int r = 0; r < 3; ++r) {
     pl.row_tile[r] = 0;
-    pl.row_split[r] = invariant ? 1 : -1;
+    pl.row_split[r] = invariant ? kSplitShape : -1;
     if (r < nr) {
       const RowTune rt = tune_lookup_rows(hi[r] - lo[r], P, n_blk);
       pl.row_tile[r] = rt.tile;
@@ -1120,12 +1133,13 @@ static se_status extrapolate_ondemand(const se_basis* b, const float* w, uint8_t
   pl.slots = 0;
   pl.phi2_ready = false;
   pl.split_ready = false;
-  // invariant: every product in one pass over its contraction (the split
-  // depends on how many blocks iterate, which would change the rounding)
-  if (invariant) pl.splitk_floats = 0;
+  // invariant: every product split into slices fixed by the number of
+  // samples (the automatic split depends on how many blocks iterate, which
+  // would change the rounding)
+  pl.invariant = invariant;
   for (int r = 0; r < 3; ++r) {   // automatic shapes (the tuner's records are for plans)
     pl.row_tile[r] = 0;
-    pl.row_split[r] = invariant ? 1 : -1;
+    pl.row_split[r] = invariant ? kSplitShape : -1;
   }
   if (prm.flags & SE_ROWS_BF16X3) {
     pl.phi_hi = oc.phi_split;
@@ -1297,7 +1311,7 @@ se_status se_ondemand_plan_create(const se_od_dict* d, int32_t n_img, int32_t H,
     p->pl.split_ready = true;
     if (!bf16) p->pl.Vhi = p->pl.Vlo = nullptr;
     const bool invariant = (prm.flags & SE_INVARIANT) != 0;
-    if (invariant) p->pl.splitk_floats = 0;
+    p->pl.invariant = invariant;
     ondemand_row_shapes(&d->b, n_blk, invariant, p->pl);
     // the descriptors, copied once (the run reads them from the device)
     if ((st = upload_ondemand_batch(p->ob, oc, s)) ||
@@ -1348,10 +1362,10 @@ se_status se_ondemand_extrapolate(const se_od_dict* d, const float* w, uint8_t* 
   pl.phi_lo = bf16 ? d->phi_lo : nullptr;
   pl.split_ready = true;
   if (!bf16) pl.Vhi = pl.Vlo = nullptr;
-  if (invariant) pl.splitk_floats = 0;
+  pl.invariant = invariant;
   for (int r = 0; r < 3; ++r) {
     pl.row_tile[r] = 0;
-    pl.row_split[r] = invariant ? 1 : -1;
+    pl.row_split[r] = invariant ? kSplitShape : -1;
   }
   // pageable source: the call returns once the descriptors have been staged
   if ((st = upload_ondemand_batch(ob, oc, s))) return st;
@@ -1384,7 +1398,7 @@ void ondemand_plan_set_rows(se_od_plan* p, int tile, int split) {
   const bool invariant = (p->prm.flags & SE_INVARIANT) != 0;
   for (int r = 0; r < 3; ++r) {
     p->pl.row_tile[r] = tile;
-    p->pl.row_split[r] = invariant ? 1 : split;
+    p->pl.row_split[r] = invariant ? kSplitShape : split;
   }
 }
 }  // namespace sefase

@@ -319,6 +319,19 @@ static int splitk_slices(int Mst, int Nst, int P) {
 
 static inline int ldw_of(int Mst) { return (Mst + 3) & ~3; }
 
+// Slices of a contraction over P samples fixed by P alone (each at least 16
+// stages of kBK, at most 8): a product split this way sums every entry in an
+// order that does not depend on how many blocks share the product.
+static int shape_slices(int P) {
+  const int nk = (P + kBK - 1) / kBK;
+  return std::max(1, std::min(8, nk / 16));
+}
+
+size_t gemm_invariant_floats(int Mst, int Nst, int P) {
+  const int S = shape_slices(P);
+  return S > 1 ? (size_t)S * Nst * ldw_of(Mst) : 0;
+}
+
 size_t gemm_splitk_floats(int Mst, int Nst_max, int P) {
   // the largest S * Nst * ldw over every block count up to Nst_max
   size_t best = 0;
@@ -367,7 +380,9 @@ struct RowMap {
 // tile: 0 = automatic, 64 or 128.  split: -1 = automatic (slices when the
 // tiles alone leave the chip idle and the workspace holds the partials),
 // 0 or 1 = none, S = S slices (64-wide tiles only; falls back to none when
-// the workspace is too small).
+// the workspace is too small), kSplitShape = the slices of shape_slices(P)
+// whatever the number of blocks (an error when the workspace cannot hold
+// them: the caller relies on the fixed order).
 template <int MODE>
 static se_status dispatch_f32(const float* A, int lda, const float* B, int ldb, float* C, int ldc,
                               int Ma, int Nb, int Mst, int Nst, int P, int tile, hipStream_t s,
@@ -386,6 +401,17 @@ static se_status dispatch_f32(const float* A, int lda, const float* B, int ldb, 
       big = (long long)((Mst + 127) / 128) * ((Nst + 127) / 128);
     }
     tile = big >= 512 ? 128 : 64;
+  }
+  if (split == kSplitShape) {
+    split = shape_slices(P);
+    if (split > 1) {
+      const size_t need = (size_t)split * Nst * ldw_of(Mst);
+      if (MODE != kStoreTransposed || !vec || !ws || ws_floats < need ||
+          reinterpret_cast<uintptr_t>(ws) % 16 != 0)
+        return fail(SE_ENOMEM, "the fixed split of an invariant product needs %zu floats of "
+                               "workspace and aligned operands", need);
+      tile = 64;
+    }
   }
   if (tile == 128)
     return launch_f32<128, 128, MODE>(A, lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, vec, s, 1, 0,
@@ -420,14 +446,15 @@ se_status gemm_syrk_f32(const float* Y, int ldy, int K, int P, float* G, int ldg
 
 se_status gemm_project_f32(const float* Y, int ldy, int K, const float* X, int ldx, int n_blk,
                            int P, float* R, int ldr, int tile, hipStream_t s, bool pad, float* ws,
-                           size_t ws_floats) {
+                           size_t ws_floats, int split) {
   // S = Y X^T (atoms x blocks), stored transposed: R[b][k]; atoms K .. ldr-1 as 0
   return dispatch_f32<kStoreTransposed>(Y, ldy, X, ldx, R, ldr, K, n_blk, pad ? ldr : K, n_blk, P,
-                                        tile, s, ws, ws_floats);
+                                        tile, s, ws, ws_floats, split);
 }
 
 size_t gemm_rows_splitk_floats(int K, int n_max, int P, int split) {
   if (split == 0 || split == 1) return 0;
+  if (split == kSplitShape) return gemm_invariant_floats(K, n_max, P);
   if (split < 0) return gemm_splitk_floats(K, n_max, P);
   return (size_t)split * n_max * ldw_of(K);
 }

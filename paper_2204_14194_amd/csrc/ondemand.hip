@@ -329,11 +329,12 @@ se_status ondemand_run(const OnDemandPlan& pl, hipStream_t s) {
   hipLaunchKernelGGL(k_od_gather_w, dim3((P + 255) / 256, n), dim3(256), 0, s, pl.w, pl.orig, n,
                      P, pl.V, pl.ldV);
   if ((st = check_launch("od_gather_w"))) return st;
+  const int split_rule = pl.invariant ? kSplitShape : -1;
   if ((st = gemm_project_f32(pl.phi2, P, K, pl.V, pl.ldV, n, P, pl.D, pl.ld, 0, s, true,
-                             pl.splitk, pl.splitk_floats)))
+                             pl.splitk, pl.splitk_floats, split_rule)))
     return st;
   if ((st = gemm_project_f32(pl.phi, P, K, pl.X, pl.ldV, n, P, pl.R, pl.ld, 0, s, true, pl.splitk,
-                             pl.splitk_floats)))
+                             pl.splitk_floats, split_rule)))
     return st;
   hipLaunchKernelGGL(k_od_init, dim3((unsigned)(((size_t)n * pl.ld + 255) / 256)), dim3(256), 0,
                      s, pl.D, pl.R, n, pl.ld);

@@ -170,9 +170,17 @@ se_status gemm_syrk_f32(const float* Y, int ldy, int K, int P, float* G, int ldg
                         hipStream_t s);
 // R[b][k] = sum_p X[b][p] Y[k][p] for k < K, and 0 for K <= k < ldr when
 // pad (else those columns are left alone).  tile: 0 = automatic, 64 or 128.
+// split: -1 automatic (by the tile count; needs ws), 1 none, kSplitShape
+// the slices fixed by P alone (SE_INVARIANT: the same order for any batch;
+// SE_ENOMEM when ws cannot hold gemm_invariant_floats).
+constexpr int kSplitShape = -2;
 se_status gemm_project_f32(const float* Y, int ldy, int K, const float* X, int ldx,
                            int n_blk, int P, float* R, int ldr, int tile, hipStream_t s,
-                           bool pad = true, float* ws = nullptr, size_t ws_floats = 0);
+                           bool pad = true, float* ws = nullptr, size_t ws_floats = 0,
+                           int split = -1);
+// partial products of the fixed (kSplitShape) split of a product with Mst
+// stored atoms, Nst blocks and P samples (0 when it does not split)
+size_t gemm_invariant_floats(int Mst, int Nst, int P);
 // workspace (floats) that lets gemm_project_f32 split the contraction of a
 // product with Mst stored atoms, up to Nst_max blocks and P pixels; 0 when it
 // never splits.  Without it (or with less) the product runs unsplit.
@@ -305,6 +313,7 @@ struct OnDemandPlan {
   const float* tx;        // their A and B operands (when n_parts > 0)
   float* splitk;        // partial products of split contractions
   size_t splitk_floats;
+  bool invariant;       // the fixed split of SE_INVARIANT for every product
   // split-BF16 operands of the per-iteration dense row products (NULL: FP32)
   uint16_t* phi_hi;     // K x P
   uint16_t* phi_lo;

@@ -447,3 +447,35 @@ def test_autotuned_shapes_give_identical_results():
         np.testing.assert_array_equal(sel0, sel2)
         np.testing.assert_array_equal(g0, g2)
     B.tune_clear()
+
+
+@pytest.mark.parametrize("route", ["dense_tables", "ondemand"])
+def test_invariant_results_do_not_depend_on_the_batch(route):
+    """SE_INVARIANT: every FP32 product splits its contraction into slices
+    fixed by the number of samples, so a block's result is bit-identical
+    whether it is concealed among 8 blocks or among 256 (without the flag the
+    split follows the batch size).  Dense tables (the projection GEMM against
+    every atom) and rows on demand (diagonals, projections and table rows)."""
+    d = synth.area32_inputs(16)
+    blocks = d["blocks"]
+    say(f"SE_INVARIANT, batch of 8 vs batch of {len(blocks)}: {route}")
+    phi = synth.round_to_f32(d["phi"])
+    phi_d = upload_phi(phi)
+    lost = np.stack([synth.lost_mask(128, 128, blocks, i) for i in range(16)])
+    lost_d = torch.from_numpy(lost).to(dev())
+    sub = list(range(0, len(blocks), 32))            # 8 blocks spread over the images
+
+    def run(bl):
+        img = torch.from_numpy(d["images"]).to(dev())
+        if route == "dense_tables":
+            t, _, _ = shared_tables(d["images"], blocks, phi_d, 32, 32, 0.8)
+            out = B.extrapolate_batch(t, img, bl, 0.5, 100, invariant=True)
+        else:
+            w = B.area_weights(32, 32, 0.8, lost_d, bl)
+            out = B.extrapolate_ondemand(phi_d, 32, 32, w, img, bl, 0.5, 100, invariant=True)
+        torch.cuda.synchronize()
+        return [x.cpu().numpy() for x in out]
+    full = run(blocks)
+    part = run([blocks[i] for i in sub])
+    for name, x, y in zip(("sel", "coef", "g_loss"), full, part):
+        assert np.array_equal(x[sub], y), f"{name} depends on the batch"
