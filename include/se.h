@@ -663,10 +663,10 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w,
  * no dense atoms (every row a transform) or no blocks.
  *
  * se_ondemand_extrapolate: se_extrapolate_ondemand on a prepared dictionary
- * (same arguments, results bit for bit; b replaced by d): no verification,
- * no phi squared, no synchronisation; the descriptors are staged from host
- * memory as by the other calls.  ws: se_ondemand_plan_ws_bytes(d, n_blk,
- * max_loss, 0) bytes. */
+ * (same arguments and results, bit for bit; b replaced by d, and row_slots
+ * as for a plan): no verification, no phi squared, no synchronisation; the
+ * descriptors are staged from host memory as by the other calls.  ws:
+ * se_ondemand_plan_ws_bytes(d, n_blk, max_loss, row_slots) bytes. */
 typedef struct se_od_dict se_od_dict;
 typedef struct se_od_plan se_od_plan;
 se_status se_ondemand_prepare(const se_basis* b, uint32_t flags, se_od_dict** out,
@@ -687,7 +687,7 @@ se_status se_ondemand_extrapolate(const se_od_dict* d, const float* w, uint8_t* 
                                   int32_t n_img, int32_t H, int32_t W, const se_block* blocks,
                                   int32_t n_blk, se_params prm, const int32_t* iters,
                                   int32_t* sel, float* coef, float* g_loss, int32_t g_loss_ld,
-                                  void* ws, size_t ws_bytes, void* stream);
+                                  int32_t row_slots, void* ws, size_t ws_bytes, void* stream);
 typedef struct {
   int32_t row_tile, row_split;  /* 0 / -1: the automatic rules */
   float run_ms;                 /* best measured run time */

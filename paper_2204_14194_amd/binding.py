@@ -188,7 +188,7 @@ def lib():
     L.se_autotune_ondemand.argtypes = [vp, vp, vp, i32, vp, vp]
     L.se_ondemand_extrapolate.restype = i32
     L.se_ondemand_extrapolate.argtypes = [vp, vp, vp, i32, i32, i32, vp, i32, se_params, vp, vp,
-                                          vp, vp, i32, vp, sz, vp]
+                                          vp, vp, i32, i32, vp, sz, vp]
     _lib = L
     return L
 
@@ -643,9 +643,10 @@ class OnDemandDict:
 
     def extrapolate(self, w: torch.Tensor, images: torch.Tensor, blocks: Sequence, gamma: float,
                     iters, want_sel=True, want_coef=True, want_g=True, stream=None,
-                    rows_bf16: bool = False, invariant: bool = False):
+                    rows_bf16: bool = False, invariant: bool = False, row_slots: int = 0):
         """se_ondemand_extrapolate: extrapolate_ondemand on this prepared
-        dictionary (no synchronisation).  Returns (sel, coef, g_loss)."""
+        dictionary (no synchronisation), caching ``row_slots`` table rows per
+        block.  Returns (sel, coef, g_loss)."""
         L = lib()
         _dev_f32(w, "w")
         n_img, H, W = images.shape
@@ -661,13 +662,14 @@ class OnDemandDict:
         coef = torch.empty((n, imax), dtype=torch.float32, device=dev) if want_coef else None
         gld = max([loss_size(b) for b in blocks] + [1])
         g = torch.zeros((n, gld), dtype=torch.float32, device=dev) if want_g else None
-        ws = _workspace(L.se_ondemand_plan_ws_bytes(self.handle, n, gld, 0), dev)
+        ws = _workspace(L.se_ondemand_plan_ws_bytes(self.handle, n, gld, int(row_slots)), dev)
         prm = se_params(float(gamma), int(imax), (SE_ROWS_BF16X3 if rows_bf16 else 0) |
                         (SE_INVARIANT if invariant else 0))
         return _check_results(L.se_ondemand_extrapolate(self.handle, _ptr(w), _ptr(images), n_img,
                                                         H, W, blocks_array(blocks), n, prm, per,
                                                         _ptr(sel), _ptr(coef), _ptr(g), gld,
-                                                        _ptr(ws), ws.numel(), _stream(stream)),
+                                                        int(row_slots), _ptr(ws), ws.numel(),
+                                                        _stream(stream)),
                               (sel, coef, g))
 
     def close(self):

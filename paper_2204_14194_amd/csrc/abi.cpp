@@ -1331,9 +1331,10 @@ se_status se_ondemand_extrapolate(const se_od_dict* d, const float* w, uint8_t* 
                                   int32_t n_img, int32_t H, int32_t W, const se_block* blocks,
                                   int32_t n_blk, se_params prm, const int32_t* iters,
                                   int32_t* sel, float* coef, float* g_loss, int32_t g_loss_ld,
-                                  void* ws, size_t ws_bytes, void* stream) {
+                                  int32_t row_slots, void* ws, size_t ws_bytes, void* stream) {
   g_err[0] = 0;
   if (!d || !w || !images) return fail(SE_EINVAL, "NULL argument");
+  if (row_slots < 0) return fail(SE_EINVAL, "row_slots < 0");
   se_status st;
   if ((st = check_params(prm, g_loss, g_loss_ld))) return st;
   if (prm.flags & SE_ROWS_Q14) return fail(SE_EINVAL, "rows on demand take no fixed-point rows");
@@ -1343,7 +1344,8 @@ se_status se_ondemand_extrapolate(const se_od_dict* d, const float* w, uint8_t* 
   OdBatch ob;
   if ((st = plan_ondemand_batch(b, n_img, H, W, blocks, n_blk, prm, iters, ob))) return st;
   if (n_blk == 0) return SE_OK;
-  const size_t need = se_ondemand_plan_ws_bytes(d, n_blk, ob.max_loss, 0);
+  const int slots = std::min(row_slots, std::min(ob.iters_max, b->K));
+  const size_t need = se_ondemand_plan_ws_bytes(d, n_blk, ob.max_loss, slots);
   if (!ws || ws_bytes < need) return fail(SE_ENOMEM, "workspace too small: need %zu bytes", need);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool bf16 = (prm.flags & SE_ROWS_BF16X3) != 0;
@@ -1351,10 +1353,10 @@ se_status se_ondemand_extrapolate(const se_od_dict* d, const float* w, uint8_t* 
   Carver cv(ws);
   OnDemandPlan pl{};
   OdCarve oc;
-  carve_ondemand(cv, b, n_blk, ob.max_loss, 0, false, (d->flags & SE_ROWS_BF16X3) != 0, true, pl,
-                 oc);
+  carve_ondemand(cv, b, n_blk, ob.max_loss, slots, false, (d->flags & SE_ROWS_BF16X3) != 0, true,
+                 pl, oc);
   fill_ondemand_plan(b, ob, oc, prm, pl);
-  pl.slots = 0;
+  pl.slots = slots;
   pl.phi2 = d->phi2;
   pl.phi2_ready = true;
   pl.tx = d->tx;

@@ -140,19 +140,24 @@ static void evict_for(Server* s, size_t need);
 
 // The basis set prepared for rows on demand (parts verified and phi squared
 // formed once: the one synchronisation of `st` for this basis), or nullptr
-// when the budget cannot hold it (the batch then takes the one-call form).
-static se_od_dict* ondemand_dict(Server* s, int bs, hipStream_t st) {
+// when the budget cannot hold it beside `reserve` bytes of scratch for the
+// stream's batch (the batch then takes the one-call form).  Prepared
+// dictionaries stay until the server ends and count with the tables.
+static se_od_dict* ondemand_dict(Server* s, int bs, int si, hipStream_t st, size_t reserve) {
   if (s->dicts[(size_t)bs]) return s->dicts[(size_t)bs];
   if (s->dict_tried[(size_t)bs]) return nullptr;
-  s->dict_tried[(size_t)bs] = true;
   const se_basis& b = s->sets[(size_t)bs];
   const size_t bytes = align_up((size_t)b.K * b.M * b.N * 4, 256) +
                        align_up(tx_const_bytes(b.M, b.N, b.n_parts), 256) + 512;
-  evict_for(s, bytes);
-  if (s->bytes_tables + s->bytes_slots + s->bytes_scratch + bytes > s->cfg.hbm_budget_bytes)
-    return nullptr;
+  const size_t mine = s->scratch[(size_t)si].bytes;
+  const size_t scratch = s->bytes_scratch - mine + std::max(mine, reserve);
+  if (s->bytes_tables + s->bytes_slots + scratch + bytes > s->cfg.hbm_budget_bytes)
+    return nullptr;   // not now (the budget may hold it later)
   se_od_dict* d = nullptr;
-  if (se_ondemand_prepare(&b, 0, &d, st) != SE_OK) return nullptr;
+  if (se_ondemand_prepare(&b, 0, &d, st) != SE_OK) {
+    s->dict_tried[(size_t)bs] = true;   // not preparable: the one-call form from now on
+    return nullptr;
+  }
   s->dicts[(size_t)bs] = d;
   s->bytes_tables += bytes;
   return d;
@@ -364,8 +369,10 @@ static se_status launch_batch(Server* s, std::vector<Req*>& reqs, Batch& bt) {
   // any isolated group may fall back to the on-demand path (budget), so size
   // the on-demand workspace for every block of a dictionary
   std::map<int, std::pair<int, int>> per_basis;   // basis -> (blocks, max loss)
+  std::map<int, int> iters_of;                      // basis -> largest iteration count
   for (auto& e : g.iso) {
     const int bs = std::get<0>(e.first).basis;
+    iters_of[bs] = std::max(iters_of[bs], std::get<2>(e.first));
     const se_basis& b = s->sets[(size_t)bs];
     se_tables t{};
     t.M = b.M;
@@ -386,16 +393,29 @@ static se_status launch_batch(Server* s, std::vector<Req*>& reqs, Batch& bt) {
     auto& pb = per_basis[e.first.first];
     pb.first += (int)e.second.first.size();
     for (auto& bl : e.second.first) pb.second = std::max(pb.second, bl.lh * bl.lw);
+    for (int v : e.second.second) iters_of[e.first.first] = std::max(iters_of[e.first.first], v);
   }
+  // with the prepared dictionary, room for every table row a block forms
+  // (each formed once: rows on demand with a row cache)
   for (auto& kv : per_basis) {
     const se_basis& b = s->sets[(size_t)kv.first];
     const int n = kv.second.first, ml = std::max(1, kv.second.second);
-    call_max = std::max(call_max, se_extrapolate_ondemand_ws_bytes(&b, n, ml) +
-                                      align_up((size_t)n * b.M * b.N * 4, 256) +
-                                      se_area_weights_ws_bytes(n) + 512);
+    const size_t extra = align_up((size_t)n * b.M * b.N * 4, 256) + se_area_weights_ws_bytes(n) + 512;
+    call_max = std::max(call_max, se_extrapolate_ondemand_ws_bytes(&b, n, ml) + extra);
   }
+  size_t call_cache = call_max;
+  for (auto& kv : per_basis) {
+    const se_basis& b = s->sets[(size_t)kv.first];
+    const int n = kv.second.first, ml = std::max(1, kv.second.second);
+    const size_t extra = align_up((size_t)n * b.M * b.N * 4, 256) + se_area_weights_ws_bytes(n) + 512;
+    if (se_od_dict* dd = ondemand_dict(s, kv.first, si, st, need + call_max))
+      call_cache = std::max(call_cache,
+                            se_ondemand_plan_ws_bytes(dd, n, ml, iters_of[kv.first]) + extra);
+  }
+  // the row cache when the budget holds it, else every row formed on use
+  se_status rc = ensure_scratch(s, si, need + call_cache);
+  if (rc != SE_OK && call_cache > call_max) rc = ensure_scratch(s, si, need + call_max);
   need += call_max;
-  se_status rc = ensure_scratch(s, si, need);
   if (rc) return rc;
   char* base = static_cast<char*>(s->scratch[(size_t)si].p);
   int4* rects = reinterpret_cast<int4*>(base);
@@ -457,11 +477,15 @@ static se_status launch_batch(Server* s, std::vector<Req*>& reqs, Batch& bt) {
     const se_params prm{e.first.second, 0, SE_INVARIANT};
     int ml = 1;
     for (auto& bl : blocks) ml = std::max(ml, bl.lh * bl.lw);
-    se_od_dict* dd = ondemand_dict(s, e.first.first, st);
-    if (dd && se_ondemand_plan_ws_bytes(dd, n, ml, 0) <= ows_bytes)   // no synchronisation
+    int itmax = 0;
+    for (int v : e.second.second) itmax = std::max(itmax, v);
+    se_od_dict* dd = s->dicts[(size_t)e.first.first];   // prepared while sizing, if at all
+    // every table row cached if the scratch holds it (see the sizing above)
+    const int slots = dd && se_ondemand_plan_ws_bytes(dd, n, ml, itmax) <= ows_bytes ? itmax : 0;
+    if (dd && se_ondemand_plan_ws_bytes(dd, n, ml, slots) <= ows_bytes)   // no synchronisation
       rc = se_ondemand_extrapolate(dd, w, s->slot_frames, nslot, H, W, blocks.data(), n, prm,
-                                   e.second.second.data(), nullptr, nullptr, nullptr, 0, ows,
-                                   ows_bytes, st);
+                                   e.second.second.data(), nullptr, nullptr, nullptr, 0, slots,
+                                   ows, ows_bytes, st);
     else
       rc = se_extrapolate_ondemand(&b, w, s->slot_frames, nslot, H, W, blocks.data(), n, prm,
                                    e.second.second.data(), nullptr, nullptr, nullptr, 0, ows,

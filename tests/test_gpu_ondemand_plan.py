@@ -94,12 +94,14 @@ def test_plan_equals_call_for_any_row_cache(area, with_parts):
     torch.cuda.synchronize()
     ref = tuple(x.cpu().numpy() for x in ref) + (img.cpu().numpy(),)
     d = B.OnDemandDict(phi_d, area, area, parts=parts)
-    # the one-call form on the prepared dictionary
-    img = img0.clone()
-    got = B.OnDemandDict.extrapolate(d, w, img, c["blocks"], 0.5, c["iters"])
-    torch.cuda.synchronize()
-    assert_same(tuple(x.cpu().numpy() for x in got) + (img.cpu().numpy(),), ref,
-                "se_ondemand_extrapolate", c["iters"])
+    # the one-call form on the prepared dictionary, without and with cached rows
+    for slots in (0, 200):
+        img = img0.clone()
+        got = B.OnDemandDict.extrapolate(d, w, img, c["blocks"], 0.5, c["iters"],
+                                         row_slots=slots)
+        torch.cuda.synchronize()
+        assert_same(tuple(x.cpu().numpy() for x in got) + (img.cpu().numpy(),), ref,
+                    f"se_ondemand_extrapolate, row_slots={slots}", c["iters"])
     for slots in (0, 3, None):
         plan = B.OnDemandPlan(d, img0, c["blocks"], 0.5, c["iters"], row_slots=slots)
         got = run_plan(plan, w, img0)
