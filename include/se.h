@@ -652,8 +652,9 @@ se_status se_extrapolate_ondemand(const se_basis* b, const float* w,
  * race; serialise them.  Returns SE_ENUMERIC, after completing the work,
  * if some blocks have no available sample, as se_extrapolate_ondemand.
  *
- * se_autotune_ondemand times the row products' tile (64 or 128) and split
- * of the contraction (1, 2, 4 or 8 slices, or the automatic rule) on runs
+ * se_autotune_ondemand times the row products' tile (64 x 64, 128 x 128, or
+ * 128 atoms x 64 blocks, code 12864) and split of the contraction (1, 2, 4
+ * or 8 slices, or the automatic rule) on runs
  * of the plan (`reps` each after a warm-up, synchronising `stream`;
  * images are rewritten with the same values, sel/coef/g_loss not written),
  * records the fastest per (dense atoms, M*N, block-count bucket) for

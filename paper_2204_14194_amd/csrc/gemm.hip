@@ -377,7 +377,39 @@ struct RowMap {
   const int32_t* cmap = nullptr;
 };
 
-// tile: 0 = automatic, 64 or 128.  split: -1 = automatic (slices when the
+// Tiles of BM x BN with the contraction split over slices (partial products
+// in ws, summed in slice order) when `split` asks for it and ws holds them,
+// else unsplit.
+template <int BM, int BN, int MODE>
+static se_status launch_tiles(const float* A, int lda, const float* B, int ldb, float* C, int ldc,
+                              int Ma, int Nb, int Mst, int Nst, int P, bool vec, hipStream_t s,
+                              float* ws, size_t ws_floats, int split, const RowMap& map) {
+  if (MODE == kStoreTransposed && ws && vec && Mst > 0 && Nst > 0 && split != 0 && split != 1) {
+    // few tiles: split the contraction over slices that write partial
+    // products to the workspace, then sum them in slice order
+    const int nk = (P + kBK - 1) / kBK;
+    const int S = split < 0 ? splitk_slices(Mst, Nst, P) : std::min(split, nk);
+    const int ldw = ldw_of(Mst);
+    const size_t wstride = (size_t)Nst * ldw;
+    if (S > 1 && (size_t)S * wstride <= ws_floats &&
+        reinterpret_cast<uintptr_t>(ws) % 16 == 0) {
+      const int kchunk = ((nk + S - 1) / S) * kBK;
+      const int Sr = (nk + kchunk / kBK - 1) / (kchunk / kBK);   // slices that hold stages
+      se_status st = launch_f32<BM, BN, MODE>(A, lda, B, ldb, ws, ldw, Ma, Nb, Mst, Nst, P, true,
+                                              s, Sr, kchunk, wstride, map.nb_dev, nullptr);
+      if (st) return st;
+      const dim3 grid((unsigned)((Mst + 1023) / 1024), (unsigned)Nst);
+      hipLaunchKernelGGL(k_splitk_sum<true>, grid, dim3(256), 0, s, ws, ldw, wstride, Sr, C, ldc,
+                         Nst, Mst, map.nb_dev, map.cmap);
+      return check_launch("splitk_sum");
+    }
+  }
+  return launch_f32<BM, BN, MODE>(A, lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, vec, s, 1, 0, 0,
+                                  map.nb_dev, map.cmap);
+}
+
+// tile: 0 = automatic, 64, 128, or kTile128x64 (128 atoms x 64 blocks, for
+// products with few blocks).  split: -1 = automatic (slices when the
 // tiles alone leave the chip idle and the workspace holds the partials),
 // 0 or 1 = none, S = S slices (64-wide tiles only; falls back to none when
 // the workspace is too small), kSplitShape = the slices of shape_slices(P)
@@ -416,28 +448,11 @@ static se_status dispatch_f32(const float* A, int lda, const float* B, int ldb, 
   if (tile == 128)
     return launch_f32<128, 128, MODE>(A, lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, vec, s, 1, 0,
                                       0, map.nb_dev, map.cmap);
-  if (MODE == kStoreTransposed && ws && vec && Mst > 0 && Nst > 0 && split != 0 && split != 1) {
-    // few tiles: split the contraction over slices that write partial
-    // products to the workspace, then sum them in slice order
-    const int nk = (P + kBK - 1) / kBK;
-    const int S = split < 0 ? splitk_slices(Mst, Nst, P) : std::min(split, nk);
-    const int ldw = ldw_of(Mst);
-    const size_t wstride = (size_t)Nst * ldw;
-    if (S > 1 && (size_t)S * wstride <= ws_floats &&
-        reinterpret_cast<uintptr_t>(ws) % 16 == 0) {
-      const int kchunk = ((nk + S - 1) / S) * kBK;
-      const int Sr = (nk + kchunk / kBK - 1) / (kchunk / kBK);   // slices that hold stages
-      se_status st = launch_f32<64, 64, MODE>(A, lda, B, ldb, ws, ldw, Ma, Nb, Mst, Nst, P, true,
-                                              s, Sr, kchunk, wstride, map.nb_dev, nullptr);
-      if (st) return st;
-      const dim3 grid((unsigned)((Mst + 1023) / 1024), (unsigned)Nst);
-      hipLaunchKernelGGL(k_splitk_sum<true>, grid, dim3(256), 0, s, ws, ldw, wstride, Sr, C, ldc,
-                         Nst, Mst, map.nb_dev, map.cmap);
-      return check_launch("splitk_sum");
-    }
-  }
-  return launch_f32<64, 64, MODE>(A, lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, vec, s, 1, 0, 0,
-                                  map.nb_dev, map.cmap);
+  if (MODE == kStoreTransposed && tile == kTile128x64)
+    return launch_tiles<128, 64, MODE>(A, lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, vec, s, ws,
+                                       ws_floats, split, map);
+  return launch_tiles<64, 64, MODE>(A, lda, B, ldb, C, ldc, Ma, Nb, Mst, Nst, P, vec, s, ws,
+                                    ws_floats, split, map);
 }
 
 se_status gemm_syrk_f32(const float* Y, int ldy, int K, int P, float* G, int ldg, hipStream_t s) {

@@ -174,6 +174,7 @@ se_status gemm_syrk_f32(const float* Y, int ldy, int K, int P, float* G, int ldg
 // the slices fixed by P alone (SE_INVARIANT: the same order for any batch;
 // SE_ENOMEM when ws cannot hold gemm_invariant_floats).
 constexpr int kSplitShape = -2;
+constexpr int kTile128x64 = 12864;   // tile code: 128 atoms x 64 blocks
 se_status gemm_project_f32(const float* Y, int ldy, int K, const float* X, int ldx,
                            int n_blk, int P, float* R, int ldr, int tile, hipStream_t s,
                            bool pad = true, float* ws = nullptr, size_t ws_floats = 0,
@@ -376,8 +377,8 @@ struct TuneChoice {
   int loop_waves = 0, loop_vpl = 0, proj_tile = 0;
 };
 TuneChoice tune_lookup(int K, int P, int n_blk);
-// rows on demand: the row products' tile (0 automatic, 64, 128) and split
-// (-1 automatic, 1 none, 2/4/8 slices) for Kd dense atoms of P pixels
+// rows on demand: the row products' tile (0 automatic, 64, 128, kTile128x64)
+// and split (-1 automatic, 1 none, 2/4/8 slices) for Kd dense atoms of P pixels
 struct RowTune {
   int tile = 0, split = -1;
 };

@@ -48,7 +48,7 @@ RowTune tune_lookup_rows(int Kd, int P, int n_blk) {
 }
 
 static bool row_tune_valid(int tile, int split) {
-  return (tile == 0 || tile == 64 || tile == 128) &&
+  return (tile == 0 || tile == 64 || tile == 128 || tile == kTile128x64) &&
          (split == -1 || split == 1 || split == 2 || split == 4 || split == 8) &&
          !(tile == 128 && split > 1);
 }
@@ -141,7 +141,9 @@ se_status se_autotune_ondemand(se_od_plan* p, const float* w, uint8_t* images, i
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(SE_EHIP, "event creation failed");
-  static const RowTune cand[] = {{64, 1}, {64, 2}, {64, 4}, {64, 8}, {128, 1}, {0, -1}};
+  static const RowTune cand[] = {{64, 1},          {64, 2},          {64, 4},
+                                 {64, 8},          {128, 1},         {kTile128x64, 1},
+                                 {kTile128x64, 2}, {kTile128x64, 4}, {0, -1}};
   se_status st = SE_OK;
   RowTune best;
   float best_ms = 1e30f;

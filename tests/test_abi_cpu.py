@@ -183,9 +183,10 @@ def test_tune_records_roundtrip_and_validation():
     B.tune_clear()
     assert B.tune_export() == ""
     # row-product records of rows on demand
-    B.tune_import("rows 2304 2304 10 64 4\n2048 1024 12 2 16 128\n")
+    B.tune_import("rows 2304 2304 10 64 4\n2048 1024 12 2 16 128\nrows 576 576 9 12864 2\n")
     text = B.tune_export()
     assert "rows 2304 2304 10 64 4" in text and "2048 1024 12 2 16 128" in text
+    assert "rows 576 576 9 12864 2" in text           # 128 atoms x 64 blocks, 2 slices
     for bad in ("rows 2304 2304 10 96 1\n",     # unknown tile
                 "rows 2304 2304 10 64 3\n",     # unknown split
                 "rows 2304 2304 10 128 2\n",    # the wide tile does not split
