@@ -105,6 +105,16 @@ typedef enum { SE_FP32 = 0, SE_BF16X3 = 1 } se_precision;
  * and M must be a power of two. */
 #define SE_PART_DCT2 1
 #define SE_PART_WHT2 2
+/* SE_PART_DFT2: complex 2-D DFT atoms (Section VI's complex case), atom
+ * k1*N + k2 = exp(j 2 pi (k1 m / M + k2 n / N)) / sqrt(M N) at pixel (m, n),
+ * real parts in phi and imaginary parts in phi_im.  Declared only on a
+ * complex dictionary, as its one part, on two-dimensional areas (any M, N
+ * <= 64).  The weighted scalar products with these atoms are the 2-D DFT
+ * of the weighted block, computed as two small complex matrix products per
+ * block (the initial projections of eq. 12); the tables (Algorithm 2) are
+ * still the product of all atoms.  Verified like the real kinds, against
+ * the exact phases (k1 m N + k2 n M) mod M N. */
+#define SE_PART_DFT2 3
 typedef struct {
   int32_t kind, first;
 } se_part;
@@ -115,7 +125,8 @@ typedef struct {
  * phi_im: NULL for a real dictionary; for a complex one (the paper's general
  * case, e.g. 2-D DFT atoms) the imaginary parts, device K x (M*N) float32,
  * with phi holding the real parts.  Complex dictionaries take FP32 tables,
- * declare no transform parts, and are concealed by the batched calls
+ * declare at most one transform part (of kind SE_PART_DFT2; no other kind),
+ * and are concealed by the batched calls
  * (se_extrapolate_batch, se_project/se_iterate, se_extrapolate_device);
  * the other calls refuse them (SE_EINVAL).
  * T: frames per area (0 or 1: a two-dimensional area).  With T > 1 the
@@ -310,7 +321,9 @@ int32_t se_table_ld(int32_t K);
 /* Size of the transform operand buffer se_tables.tx for an M x N area with
  * n_parts declared transform parts; 0 if n_parts is 0 or out of range, or
  * M or N outside 1..64.  For areas of T frames pass T*M as M (the frames
- * are transformed stacked). */
+ * are transformed stacked).  Any n_parts of 1 or 2 gets room for the
+ * operands of two transforms (a SE_PART_DFT2 part takes the cosine and the
+ * sine matrices). */
 size_t se_tables_tx_bytes(int32_t M, int32_t N, int32_t n_parts);
 
 /* ------------------------------------------------------------------------ */

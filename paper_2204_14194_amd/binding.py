@@ -23,7 +23,7 @@ SE_DIAG_AUTO, SE_DIAG_FP64, SE_DIAG_FP32 = 0, 1, 2
 SE_ROWS_Q14 = 1   # se_params.flags: the loop reads the fixed-point class rows
 SE_ROWS_BF16X3 = 2   # se_params.flags: rows on demand from split-BF16 products
 SE_INVARIANT = 4     # se_params.flags: products in one pass, independent of the batch
-SE_PART_DCT2, SE_PART_WHT2 = 1, 2
+SE_PART_DCT2, SE_PART_WHT2, SE_PART_DFT2 = 1, 2, 3
 
 # every symbol include/se.h declares
 EXPORTED = (
@@ -57,11 +57,11 @@ class se_basis(C.Structure):
                 ("T", C.c_int32)]
 
 
-_PART_NAMES = {"dct": SE_PART_DCT2, "wht": SE_PART_WHT2}
+_PART_NAMES = {"dct": SE_PART_DCT2, "wht": SE_PART_WHT2, "dft": SE_PART_DFT2}
 
 
 def _parts_arg(parts) -> tuple:
-    """(kind, first) pairs; kind an SE_PART_* value or 'dct' / 'wht'."""
+    """(kind, first) pairs; kind an SE_PART_* value or 'dct' / 'wht' / 'dft'."""
     parts = tuple((_PART_NAMES[k] if isinstance(k, str) else int(k), int(f)) for k, f in parts)
     if len(parts) > 2:
         raise ValueError("at most two transform parts")

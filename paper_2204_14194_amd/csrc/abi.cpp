@@ -143,10 +143,22 @@ static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 // Declared transform parts: known kinds, inside [0, K), disjoint, areas up to
 // 64 x 64 (powers of two for Walsh-Hadamard); an area of T frames is
-// transformed with its frames stacked, so T M <= 64.
-static se_status check_parts(int T, int M, int N, int K, int n_parts, const se_part* parts) {
+// transformed with its frames stacked, so T M <= 64.  A complex dictionary
+// declares at most one part, a DFT part on a two-dimensional area; a real
+// one declares none.
+static se_status check_parts(int T, int M, int N, int K, int n_parts, const se_part* parts,
+                             bool complex_dict) {
   if (n_parts < 0 || n_parts > 2) return fail(SE_EINVAL, "n_parts=%d must be 0, 1 or 2", n_parts);
   if (n_parts == 0) return SE_OK;
+  for (int q = 0; q < n_parts; ++q)
+    if ((parts[q].kind == SE_PART_DFT2) != complex_dict)
+      return fail(SE_EINVAL, complex_dict ? "part %d: complex dictionaries take DFT parts only"
+                                          : "part %d: a DFT part needs a complex dictionary",
+                  q);
+  if (complex_dict) {
+    if (n_parts != 1) return fail(SE_EINVAL, "a complex dictionary declares at most one part");
+    if (T != 1) return fail(SE_EINVAL, "DFT parts take two-dimensional areas");
+  }
   if ((long long)T * M > 64 || N > 64)
     return fail(SE_EINVAL, "transform parts need T M, N <= 64 (got %dx%dx%d)", T, M, N);
   if (T > 1 && !is_pow2(M))
@@ -154,7 +166,7 @@ static se_status check_parts(int T, int M, int N, int K, int n_parts, const se_p
   const int P = T * M * N;
   for (int q = 0; q < n_parts; ++q) {
     const se_part& p = parts[q];
-    if (p.kind != SE_PART_DCT2 && p.kind != SE_PART_WHT2)
+    if (p.kind != SE_PART_DCT2 && p.kind != SE_PART_WHT2 && p.kind != SE_PART_DFT2)
       return fail(SE_EINVAL, "part %d: unknown kind %d", q, p.kind);
     if (p.kind == SE_PART_WHT2 && (!is_pow2(T) || !is_pow2(M) || !is_pow2(N)))
       return fail(SE_EINVAL, "part %d: Walsh-Hadamard needs power-of-two T, M, N", q);
@@ -168,7 +180,8 @@ static se_status check_parts(int T, int M, int N, int K, int n_parts, const se_p
 }
 
 se_status check_basis_parts(const se_basis* b) {
-  return check_parts(area_frames(b->T), b->M, b->N, b->K, b->n_parts, b->parts);
+  return check_parts(area_frames(b->T), b->M, b->N, b->K, b->n_parts, b->parts,
+                     b->phi_im != nullptr);
 }
 
 static se_status check_tables(const se_tables* t) {
@@ -186,13 +199,13 @@ static se_status check_tables(const se_tables* t) {
     return fail(SE_EINVAL, "unknown table precision %d", t->precision);
   if (t->precision == SE_BF16X3 && (!t->Yhi || !t->Ylo))
     return fail(SE_EINVAL, "BF16X3 tables need Yhi and Ylo");
-  se_status st = check_parts(area_frames(t->T), t->M, t->N, t->K, t->n_parts, t->parts);
+  se_status st = check_parts(area_frames(t->T), t->M, t->N, t->K, t->n_parts, t->parts,
+                             t->phi_im != nullptr);
   if (st) return st;
   if (t->n_parts > 0 && (!t->tx || reinterpret_cast<uintptr_t>(t->tx) % 16))
     return fail(SE_EINVAL, "tables with transform parts need a 16-byte aligned tx buffer");
   if (t->phi_im) {
     if (t->precision != SE_FP32) return fail(SE_EINVAL, "complex dictionaries take FP32 tables");
-    if (t->n_parts != 0) return fail(SE_EINVAL, "complex dictionaries declare no transform parts");
     if (!t->G_im || reinterpret_cast<uintptr_t>(t->G_im) % 16)
       return fail(SE_EINVAL, "complex tables need a 16-byte aligned G_im");
     if (!complex_loop_for(t->K)) return fail(SE_EINVAL, "no complex loop shape for K=%d", t->K);
@@ -284,8 +297,10 @@ static se_status verify_parts(const se_basis* b, int32_t* flag, hipStream_t s,
   if (hipMemsetAsync(flag, 0, sizeof(int32_t), s) != hipSuccess)
     return fail(SE_EHIP, "flag clear failed");
   for (int q = 0; q < b->n_parts; ++q)
-    if ((st = check_part(b->phi, area_frames(b->T), b->M, b->N, b->parts[q].kind,
-                         b->parts[q].first, flag, s)))
+    if ((st = b->parts[q].kind == SE_PART_DFT2
+                  ? check_dft_part(b->phi, b->phi_im, b->M, b->N, b->parts[q].first, flag, s)
+                  : check_part(b->phi, area_frames(b->T), b->M, b->N, b->parts[q].kind,
+                               b->parts[q].first, flag, s)))
       return st;
   int32_t got[2] = {0, 0};
   if (hipMemcpyAsync(got, flag, (extra ? 2 : 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
@@ -307,9 +322,18 @@ static se_status project_into(const se_tables* t, const uint8_t* images, int H, 
   int lo[3] = {0, 0, 0}, hi[3] = {t->K, 0, 0};
   int nr = 1;
   if (t->n_parts > 0) {
-    if ((st = project_tx(t, images, H, W, dblk, n_blk, R, ldR, s))) return st;
+    // a complex DFT part writes its own columns only (R's two halves); the
+    // padding is written below
+    st = t->phi_im ? project_dft(t, images, H, W, dblk, n_blk, R, ldR, ldR / 2, s)
+                   : project_tx(t, images, H, W, dblk, n_blk, R, ldR, s);
+    if (st) return st;
     nr = dense_ranges(t->K, P, t->n_parts, t->parts, lo, hi);
-    if (nr == 0) return SE_OK;
+    if (nr == 0 && !t->phi_im) return SE_OK;
+  }
+  if (t->phi_im && nr == 0) {
+    launch_zero_range(R, n_blk, ldR, t->K, ldR / 2, s);
+    launch_zero_range(R, n_blk, ldR, ldR / 2 + t->K, ldR, s);
+    return check_launch("zero_range");
   }
   const bool pad = t->n_parts == 0;   // else the transform kernel wrote the padding
   Carver cv(ws);
@@ -340,13 +364,15 @@ static se_status project_into(const se_tables* t, const uint8_t* images, int H, 
   if ((st = check_launch("gather"))) return st;
   if (t->phi_im) {
     // complex dictionary: real and imaginary parts of eq. 12 from the two
-    // halves of Y, into the two halves of each row of R
+    // halves of Y, into the two halves of each row of R (the atoms outside
+    // a DFT part)
     const int K = t->K, half = ldR / 2;
     for (int part = 0; part < 2; ++part)
-      if ((st = gemm_project_f32(t->Y + (size_t)part * K * P, P, K, X, ldX, n_blk, P,
-                                 R + part * half, ldR, 0, s, false, split, split_floats,
-                                 split_rule)))
-        return st;
+      for (int r = 0; r < nr; ++r)
+        if ((st = gemm_project_f32(t->Y + ((size_t)part * K + lo[r]) * P, P, hi[r] - lo[r], X,
+                                   ldX, n_blk, P, R + part * half + lo[r], ldR, 0, s, false, split,
+                                   split_floats, split_rule)))
+          return st;
     launch_zero_range(R, n_blk, ldR, K, half, s);
     launch_zero_range(R, n_blk, ldR, half + K, ldR, s);
     return check_launch("zero_range");
@@ -472,7 +498,9 @@ const char* se_last_error(void) { return g_err; }
 int32_t se_version(void) { return 100; }
 int32_t se_table_ld(int32_t K) { return K >= 1 && greedy_waves_for(K) ? greedy_row_len(K) : 0; }
 size_t se_tables_tx_bytes(int32_t M, int32_t N, int32_t n_parts) {
-  return tx_const_bytes(M, N, n_parts);
+  // room for two transforms: a DFT part is stored as its real and its
+  // imaginary transform
+  return n_parts == 1 || n_parts == 2 ? tx_const_bytes(M, N, 2) : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -583,6 +611,9 @@ se_status se_weighted_gram(const se_basis* b, const float* w, se_precision prec,
     launch_scale_y(b->phi, t->D, t->sqrtw, K, P, t->Y, s);
     launch_scale_y(b->phi_im, t->D, t->sqrtw, K, P, t->Y + (size_t)K * P, s, true);
     if ((st = check_launch("scale_y"))) return st;
+    // a DFT part's projections are transforms (its operands from D and w);
+    // the table itself stays the product of all atoms
+    if (t->n_parts > 0 && (st = build_tx(t, s))) return st;
     launch_zero_cols(t->G, K, K, t->ldG, s);
     launch_zero_cols(t->G_im, K, K, t->ldG, s);
     if ((st = check_launch("zero_cols"))) return st;

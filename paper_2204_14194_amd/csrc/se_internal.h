@@ -218,10 +218,26 @@ void launch_gather_split(const uint8_t* images, int H, int W, const DevBlock* bl
                          uint16_t* Xlo, int ldX, hipStream_t s);
 
 // transform.hip -- declared transform parts of a dictionary (Section VI)
+// 1-D matrices of a complex DFT part in the operand buffer (internal kinds,
+// beside the SE_PART_* kinds): Ar = cos(2 pi k m / n) / sqrt(n) and
+// Ai = -sin(2 pi k m / n) / sqrt(n), the conjugate DFT matrix Ar + j Ai
+constexpr int kKindDftRe = 16, kKindDftIm = 17;
+// transforms whose operands the buffer holds: a DFT part takes two
+inline int tx_layout_parts(int n_parts, const se_part* parts) {
+  return n_parts == 1 && parts[0].kind == SE_PART_DFT2 ? 2 : n_parts;
+}
 // sets *dflag (device) to 1 if an atom of the part differs from its definition
 // (T frames of Ms rows stacked: the vertical transform is A_T (x) A_Ms)
 se_status check_part(const float* phi, int T, int Ms, int N, int kind, int first, int* dflag,
                      hipStream_t s);
+// the same for a complex DFT part (real parts phi, imaginary parts phi_im)
+se_status check_dft_part(const float* phi, const float* phi_im, int M, int N, int first,
+                         int* dflag, hipStream_t s);
+// complex tables with a DFT part: R[b][first + k] (real parts) and
+// R[b][im + first + k] (imaginary parts) of eq. 12 for the part's atoms; no
+// other column is written
+se_status project_dft(const se_tables* t, const uint8_t* images, int H, int W,
+                      const DevBlock* blk, int n_blk, float* R, int ldR, int im, hipStream_t s);
 // R[b][first + k] of every part of t, and 0 in columns K .. ldR-1
 se_status project_tx(const se_tables* t, const uint8_t* images, int H, int W,
                      const DevBlock* blk, int n_blk, float* R, int ldR, hipStream_t s);

@@ -35,6 +35,9 @@ __device__ void build_cos_table(int n, double* ct) {
 __device__ inline double basis_1d_d(int kind, int n, int k, int m, const double* ct, double inv,
                                     double a2) {
   if (kind == SE_PART_WHT2) return (__popc(k & m) & 1) ? -inv : inv;
+  // the conjugate DFT matrix: phase index (k m) mod n, sin(x) = cos(x + 3 pi / 2)
+  if (kind == kKindDftRe) return inv * ct[4 * ((k * m) % n)];
+  if (kind == kKindDftIm) return -inv * ct[(4 * ((k * m) % n) + 3 * n) % (4 * n)];
   if (k == 0) return inv;
   if (2 * k == n) return ((m & 3) == 0 || (m & 3) == 3) ? inv : -inv;
   return a2 * ct[((2 * m + 1) * k) % (4 * n)];
@@ -93,6 +96,31 @@ __global__ __launch_bounds__(kTxThreads) void k_check_part(const float* __restri
     for (int p = threadIdx.x; p < P; p += blockDim.x) {
       const int m = p / N, n = p - m * N;
       if (fabsf(row[p] - A[k1 * M + m] * Bm[k2 * N + n]) > tol) bad = 1;
+    }
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+// A complex DFT part: every atom k1 N + k2 of the part against its exact
+// value exp(j 2 pi q / M N) / sqrt(M N), q = (k1 m N + k2 n M) mod M N, in
+// both the real (phi) and the imaginary parts (phi_im).
+__global__ __launch_bounds__(kTxThreads) void k_check_dft(const float* __restrict__ phi,
+                                                         const float* __restrict__ phi_im, int M,
+                                                         int N, int first, float tol,
+                                                         int* __restrict__ flag) {
+  const int P = M * N;
+  const double sc = 1.0 / sqrt((double)P);
+  int bad = 0;
+  for (int k = blockIdx.x; k < P; k += gridDim.x) {
+    const int k1 = k / N, k2 = k - k1 * N;
+    const size_t row = (size_t)(first + k) * P;
+    for (int p = threadIdx.x; p < P; p += blockDim.x) {
+      const int m = p / N, n = p - m * N;
+      const int q = (k1 * m * N + k2 * n * M) % P;
+      double sn, cs;
+      sincospi(2.0 * (double)q / (double)P, &sn, &cs);
+      if (fabs((double)phi[row + p] - cs * sc) > tol || fabs((double)phi_im[row + p] - sn * sc) > tol)
+        bad = 1;
     }
   }
   if (bad) atomicOr(flag, 1);
@@ -209,6 +237,122 @@ __global__ __launch_bounds__((tx_max_threads<MT, NT>())) void k_project_tx(TxArg
       }
     }
     if (STAGE) wave_sync();   // the copies read before the next block's X writes
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initial projections of a complex DFT part (eq. 12 with conjugated atoms,
+// Section VI): the weighted scalar products of the block's samples s with
+// the atoms phi_(k1 N + k2) = exp(j 2 pi (k1 m / M + k2 n / N)) / sqrt(M N)
+// are Z = Ac X Bc^T, X = w s, with the conjugate 1-D DFT matrices
+// Ac = Ar + j Ai (M x M) and Bc = Br + j Bi (N x N).  X is real, so
+//   Yr = X Br^T, Yi = X Bi^T,  Re Z = Ar Yr - Ai Yi,  Im Z = Ai Yr + Ar Yi
+// -- six real products of the transform sizes, on the same fragments and
+// matrix-core steps as the real transforms (the operand buffer holds Ar, Br
+// as its first transform and Ai, Bi as its second; Df holds D_k once per
+// transform).  Output: R[b][first + k] = D_k Re Z_k, R[b][im + first + k] =
+// D_k Im Z_k.  One column tile of Z at a time.
+template <int MT, int NT>
+__device__ inline void dft_cols(int c, const float* Ar, const float* Ai, const float* Br,
+                                const float* Bi, const float* Df, const floatx4 (&x)[MT][NT],
+                                int M, int N, float* Rre, float* Rim) {
+  const int l = threadIdx.x & 63;
+  floatx4 yr[MT], yi[MT];
+#pragma unroll
+  for (int i = 0; i < MT; ++i) {
+    yr[i] = floatx4{0.f, 0.f, 0.f, 0.f};
+    yi[i] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+#pragma unroll
+  for (int sq = 0; sq < NT; ++sq) {
+    const floatx4 br = *reinterpret_cast<const floatx4*>(Br + ((c * NT + sq) * 64 + l) * 4);
+    const floatx4 bi = *reinterpret_cast<const floatx4*>(Bi + ((c * NT + sq) * 64 + l) * 4);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < MT; ++i) {
+        yr[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[i][sq][t], br[t], yr[i], 0, 0, 0);
+        yi[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[i][sq][t], bi[t], yi[i], 0, 0, 0);
+      }
+  }
+  floatx4 zr[MT], zi[MT];
+#pragma unroll
+  for (int r = 0; r < MT; ++r) {
+    zr[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+    zi[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+#pragma unroll
+  for (int i = 0; i < MT; ++i) {
+    const floatx4 yn = -yi[i];
+#pragma unroll
+    for (int r = 0; r < MT; ++r) {
+      const floatx4 ar = *reinterpret_cast<const floatx4*>(Ar + ((r * MT + i) * 64 + l) * 4);
+      const floatx4 ai = *reinterpret_cast<const floatx4*>(Ai + ((r * MT + i) * 64 + l) * 4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        zr[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[e], yr[i][e], zr[r], 0, 0, 0);
+        zi[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[e], yr[i][e], zi[r], 0, 0, 0);
+        zr[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[e], yn[e], zr[r], 0, 0, 0);
+        zi[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[e], yi[i][e], zi[r], 0, 0, 0);
+      }
+    }
+  }
+  const int k2 = 16 * c + (l & 15);
+#pragma unroll
+  for (int r = 0; r < MT; ++r) {
+    const floatx4 dv = *reinterpret_cast<const floatx4*>(Df + ((c * MT + r) * 64 + l) * 4);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k1 = 16 * r + 4 * (l >> 4) + e;
+      if (k1 < M && k2 < N) {
+        Rre[k1 * N + k2] = dv[e] * zr[r][e];
+        Rim[k1 * N + k2] = dv[e] * zi[r][e];
+      }
+    }
+  }
+}
+
+// One wave per block, the workgroup's waves looping over blocks; each
+// workgroup copies the operand buffer to LDS once (the loaders and the X
+// operands of the real transforms).  Half the real transforms' workgroup
+// bound: the two accumulator sets need more registers per lane.
+template <int MT, int NT>
+constexpr int dft_max_threads() {
+  return tx_max_threads<MT, NT>() / 2;
+}
+
+template <int MT, int NT>
+__global__ __launch_bounds__((dft_max_threads<MT, NT>())) void k_project_dft(TxArgs a, TxLayout L,
+                                                                             int im) {
+  extern __shared__ floatx4 smv[];
+  float* sm = reinterpret_cast<float*>(smv);
+  const int M = L.M, N = L.N;
+  const int wave = threadIdx.x >> 6, W = blockDim.x >> 6;
+  float* Xf = sm + L.oXf + wave * L.wsz;
+  int b = blockIdx.x * W + wave;
+  DevBlock d = a.blk[b < a.n_blk ? b : 0];
+  TxPixels<MT, NT> P;
+  tx_load<MT, NT>(a, d, M, N, P);
+  {
+    const floatx4* src = reinterpret_cast<const floatx4*>(a.tx);
+    for (int x = threadIdx.x; x < L.nconst / 4; x += blockDim.x) smv[x] = src[x];
+  }
+  __syncthreads();
+  const float* Ar = sm + L.oAf;
+  const float* Ai = Ar + MT * MT * 256;
+  const float* Br = sm + L.oBtf;
+  const float* Bi = Br + NT * NT * 256;
+  const float* Df = sm + L.oDf;
+  for (bool first = true; b < a.n_blk; b += gridDim.x * W, first = false) {
+    if (!first) {
+      d = a.blk[b];
+      tx_load<MT, NT>(a, d, M, N, P);
+    }
+    floatx4 xv[MT][NT];
+    tx_x_operands<MT, NT>(a, d, M, N, P, sm + L.oWf, Xf, xv);
+    float* Rre = a.R + (size_t)b * a.ldR + a.first0;
+#pragma unroll 1
+    for (int c = 0; c < NT; ++c) dft_cols<MT, NT>(c, Ar, Ai, Br, Bi, Df, xv, M, N, Rre, Rre + im);
   }
 }
 
@@ -406,6 +550,15 @@ se_status check_part(const float* phi, int T, int Ms, int N, int kind, int first
   return check_launch("check_part");
 }
 
+se_status check_dft_part(const float* phi, const float* phi_im, int M, int N, int first,
+                         int* dflag, hipStream_t s) {
+  const int P = M * N;
+  const int grid = P < 2048 ? P : 2048;
+  hipLaunchKernelGGL(k_check_dft, dim3(grid), dim3(kTxThreads), 0, s, phi, phi_im, M, N, first,
+                     2e-6f, dflag);
+  return check_launch("check_dft_part");
+}
+
 size_t tx_const_bytes(int M, int N, int n_parts) {
   if (M < 1 || N < 1 || M > 64 || N > 64 || n_parts < 1 || n_parts > 2) return 0;
   return (size_t)TxLayout(M, N, n_parts, 0).nconst * 4;
@@ -417,15 +570,22 @@ se_status build_tx(const se_tables* t, hipStream_t s) {
   a.Ms = t->M;
   a.M = tx_rows(t);
   a.N = t->N;
-  a.parts = t->n_parts;
+  a.parts = tx_layout_parts(t->n_parts, t->parts);
   a.kind0 = t->parts[0].kind;
   a.first0 = t->parts[0].first;
   a.kind1 = t->n_parts > 1 ? t->parts[1].kind : 0;
   a.first1 = t->n_parts > 1 ? t->parts[1].first : 0;
+  if (a.kind0 == SE_PART_DFT2) {
+    // the real and the imaginary 1-D matrices as the two transforms, both
+    // scaled by the part's D
+    a.kind0 = kKindDftRe;
+    a.kind1 = kKindDftIm;
+    a.first1 = a.first0;
+  }
   a.D = t->D;
   a.sqrtw = t->sqrtw;
   a.tx = t->tx;
-  const TxLayout L(a.M, t->N, t->n_parts, 0);
+  const TxLayout L(a.M, t->N, a.parts, 0);
   const int grid = (L.nconst + kTxThreads - 1) / kTxThreads;
   hipLaunchKernelGGL(k_build_tx, dim3(grid), dim3(kTxThreads),
                      (size_t)4 * (a.Ms + a.N + a.T) * 8, s, a, L);
@@ -672,6 +832,62 @@ se_status project_tx(const se_tables* t, const uint8_t* images, int H, int W, co
 #define SE_TX_CASE(mt, nt) \
   case mt * 10 + nt:       \
     return launch_tx_np<mt, nt>(a, L, grid, lds, s, vol);
+    SE_TX_CASE(1, 1) SE_TX_CASE(1, 2) SE_TX_CASE(1, 3) SE_TX_CASE(1, 4)
+    SE_TX_CASE(2, 1) SE_TX_CASE(2, 2) SE_TX_CASE(2, 3) SE_TX_CASE(2, 4)
+    SE_TX_CASE(3, 1) SE_TX_CASE(3, 2) SE_TX_CASE(3, 3) SE_TX_CASE(3, 4)
+    SE_TX_CASE(4, 1) SE_TX_CASE(4, 2) SE_TX_CASE(4, 3) SE_TX_CASE(4, 4)
+#undef SE_TX_CASE
+    default: return fail(SE_EINVAL, "transform parts need M, N <= 64");
+  }
+}
+
+template <int MT, int NT>
+static se_status launch_dft(const TxArgs& a, const TxLayout& L, int grid, size_t lds, int im,
+                            hipStream_t s) {
+  static std::atomic<uint64_t> raised{0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev > 63)
+    return fail(SE_EHIP, "project_dft: no current device");
+  if (lds > 64 * 1024 && !(raised.load() & (1ull << dev))) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_project_dft<MT, NT>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+      return fail(SE_EHIP, "project_dft: %zu bytes of LDS refused", lds);
+    raised.fetch_or(1ull << dev);
+  }
+  hipLaunchKernelGGL((k_project_dft<MT, NT>), dim3(grid), dim3(64 * L.waves), lds, s, a, L, im);
+  return check_launch("project_dft");
+}
+
+se_status project_dft(const se_tables* t, const uint8_t* images, int H, int W,
+                      const DevBlock* blk, int n_blk, float* R, int ldR, int im, hipStream_t s) {
+  if (t->n_parts != 1 || t->parts[0].kind != SE_PART_DFT2 || area_frames(t->T) != 1)
+    return fail(SE_EINVAL, "no DFT part declared");
+  if (n_blk <= 0) return SE_OK;
+  TxArgs a;
+  a.images = images;
+  a.H = H;
+  a.W = W;
+  a.blk = blk;
+  a.n_blk = n_blk;
+  a.K = t->K;
+  a.tx = t->tx;
+  a.first0 = t->parts[0].first;
+  a.first1 = a.first0;
+  a.R = R;
+  a.ldR = ldR;
+  a.fs = 0;
+  int waves = tx_waves(t->M, t->N, 2, n_blk);
+  if (waves == 0) return fail(SE_EINVAL, "transform of a %dx%d area exceeds LDS", t->M, t->N);
+  const int MT = (t->M + 15) / 16, NT = (t->N + 15) / 16;
+  waves = std::min(waves, (MT >= 3 || MT * NT >= 6) ? 2 : 8);   // dft_max_threads / 64
+  const TxLayout L(t->M, t->N, 2, waves);
+  const size_t lds = L.bytes();
+  const int per_cu = (int)std::min<size_t>(4, (160 * 1024) / lds);
+  const int grid = std::max(1, std::min((n_blk + waves - 1) / waves, 256 * per_cu));
+  switch (L.MT * 10 + L.NT) {
+#define SE_TX_CASE(mt, nt) \
+  case mt * 10 + nt:       \
+    return launch_dft<mt, nt>(a, L, grid, lds, im, s);
     SE_TX_CASE(1, 1) SE_TX_CASE(1, 2) SE_TX_CASE(1, 3) SE_TX_CASE(1, 4)
     SE_TX_CASE(2, 1) SE_TX_CASE(2, 2) SE_TX_CASE(2, 3) SE_TX_CASE(2, 4)
     SE_TX_CASE(3, 1) SE_TX_CASE(3, 2) SE_TX_CASE(3, 3) SE_TX_CASE(3, 4)

@@ -191,14 +191,13 @@ def dictionary(M: int, N: int, parts: Sequence[str], seed: int = 101,
 
 def dictionary_parts(M: int, N: int, parts: Sequence[str], n_gauss: int = 0):
     """Where the transform sub-dictionaries of dictionary(M, N, parts, ...)
-    start: a list of (name, first atom) for each 'dct' and 'wht' part."""
+    start: a list of (name, first atom) for each 'dct', 'wht' and 'dft' part
+    (binarized DFT and Gaussian atoms have no transform)."""
     out, first = [], 0
     for p in parts:
-        if p in ("dct", "wht"):
+        if p in ("dct", "wht", "dft"):
             out.append((p, first))
-            first += M * N
-        else:
-            first += n_gauss
+        first += n_gauss if p == "gauss" else M * N
     return out
 
 
@@ -301,6 +300,7 @@ def dft32_inputs(n_img: int = 1, seed0: int = 0):
     blocks = grid_layout(128, 128, 32, 8, n_img)
     phi = dictionary(32, 32, ("dft", "bdft"))
     return dict(images=imgs, blocks=blocks, phi=phi, M=32, N=32,
+                tx_parts=dictionary_parts(32, 32, ("dft", "bdft")),
                 rho_hat=0.8, gamma=0.5, iters=100)
 
 

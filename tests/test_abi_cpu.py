@@ -95,7 +95,8 @@ def test_rejects_bad_transform_parts_on_host():
     fake = C.c_void_p(0x1000)
     t = _tables_struct(K=2048, M=32, N=32)
     cases = [
-        ((3, 0),), ((B.SE_PART_DCT2, -1),), ((B.SE_PART_DCT2, 1025),),
+        ((9, 0),), ((B.SE_PART_DCT2, -1),), ((B.SE_PART_DCT2, 1025),),
+        ((B.SE_PART_DFT2, 0),),            # a DFT part needs a complex dictionary
         ((B.SE_PART_DCT2, 0), (B.SE_PART_WHT2, 1000)),
         ((B.SE_PART_DCT2, 0), (B.SE_PART_WHT2, 1024), (B.SE_PART_DCT2, 0)),
     ]
@@ -103,6 +104,13 @@ def test_rejects_bad_transform_parts_on_host():
         bas = B.se_basis(32, 32, 2048, 0x1000, len(parts), B._part_array(parts[:2]))
         r = L.se_weighted_gram(C.byref(bas), fake, 0, 0, C.byref(t), fake, 1 << 20, None)
         assert r == B.SE_EINVAL, parts
+    # a complex dictionary declares one DFT part and nothing else
+    for parts, what in ((((B.SE_PART_DCT2, 0),), b"DFT parts only"),
+                        (((B.SE_PART_DFT2, 0), (B.SE_PART_DFT2, 1024)), b"at most one part"),
+                        (((B.SE_PART_DFT2, 1025),), b"outside")):
+        bas = B.make_basis(32, 32, 2048, 0x1000, parts, phi_im_ptr=0x2000)
+        r = L.se_weighted_gram(C.byref(bas), fake, 0, 0, C.byref(t), fake, 1 << 20, None)
+        assert r == B.SE_EINVAL and what in L.se_last_error(), parts
     # Walsh-Hadamard needs power-of-two sides; transforms need sides <= 64
     t48 = _tables_struct(K=4096, M=48, N=48)
     bas = B.make_basis(48, 48, 4096, 0x1000, [(B.SE_PART_WHT2, 0)])
@@ -129,9 +137,11 @@ def test_rejects_bad_transform_parts_on_host():
     r = L.se_extrapolate_batch(C.byref(tb), fake, 1, 64, 64, blk, 1, B.se_params(0.5, 10, 0),
                                None, None, None, 0, fake, 1 << 30, None)
     assert r == B.SE_EINVAL and b"tx" in L.se_last_error()
-    # its size: fragments of A, B (per part), D (per part) and w, 1 KiB per 16 x 16 tile
+    # its size: fragments of A, B (per transform), D (per transform) and w, 1 KiB per
+    # 16 x 16 tile, room for two transforms (a DFT part is a real and an imaginary one)
     assert L.se_tables_tx_bytes(32, 32, 2) == (2 * 4 + 2 * 4 + 2 * 4 + 4) * 1024
-    assert L.se_tables_tx_bytes(7, 5, 1) == 4 * 1024
+    assert L.se_tables_tx_bytes(32, 32, 1) == L.se_tables_tx_bytes(32, 32, 2)
+    assert L.se_tables_tx_bytes(7, 5, 1) == 7 * 1024
     assert L.se_tables_tx_bytes(32, 32, 0) == 0 and L.se_tables_tx_bytes(65, 8, 1) == 0
 
 

@@ -16,12 +16,12 @@ from test_gpu_parity import TOL_FP32, dev, say, upload_phi
 pytestmark = pytest.mark.gpu
 
 
-def _tables(phi, images, blocks, M, N, ref_block=0):
+def _tables(phi, images, blocks, M, N, ref_block=0, parts=()):
     n_img, H, W = images.shape
     lost = np.stack([synth.lost_mask(H, W, blocks, i) for i in range(n_img)])
     w = B.area_weights(M, N, 0.8, torch.from_numpy(lost).to(dev()), [blocks[ref_block]])
     t = B.weighted_gram(upload_phi(phi.real), w[0].contiguous(), M, N,
-                        phi_im=upload_phi(phi.imag))
+                        phi_im=upload_phi(phi.imag), parts=parts)
     return t, w[0], lost
 
 
@@ -79,6 +79,70 @@ def test_complex_project_matches_oracle():
         assert err <= 1e-5 * scale, f"block {i}: {err} vs scale {scale}"
 
 
+@pytest.mark.parametrize("M,N,subs", [(16, 16, ("dft", "bdft")), (20, 12, ("bdft", "dft")),
+                                      (16, 16, ("dft",))])
+def test_dft_part_projections_match_oracle(M, N, subs):
+    """A declared DFT part (Section VI's complex case): the projections of
+    its atoms are 2-D DFTs of the weighted blocks (six real products on the
+    matrix cores), the other atoms' the GEMM; against the oracle's conjugated
+    scalar products (eq. 12), with blocks across the image border, an area
+    whose sides are not multiples of 16, a part that does not start at atom
+    0, and a dictionary that is only the part."""
+    say(f"complex projections with a DFT part: {M}x{N}, {subs}")
+    phi = synth.round_to_f32(synth.dictionary(M, N, subs))
+    parts = synth.dictionary_parts(M, N, subs)
+    assert [p for p, _ in parts] == ["dft"]
+    H, W = 3 * M + 4, 3 * N + 8
+    images = np.stack([synth.synth_image(H, W, seed=80 + s) for s in range(2)])
+    blocks = [synth.Block(i, y, x, 5, 5, 6, 6)
+              for i in range(2) for (y, x) in ((-3, -2), (M, N), (2 * M, 2 * N + 6))]
+    t, w_d, lost = _tables(phi, images, blocks, M, N, ref_block=1, parts=parts)
+    t0, _, _ = _tables(phi, images, blocks, M, N, ref_block=1)
+    K = phi.shape[0]
+    img = torch.from_numpy(images).to(dev())
+    db = B.DeviceBlocks(t, img, blocks)
+    Rs = []
+    for tt in (t, t0):
+        R = torch.full((len(blocks), tt.ldR), float("nan"), dtype=torch.float32, device=dev())
+        ws = torch.empty(max(1, B.project_ws_bytes(tt, len(blocks))), dtype=torch.uint8,
+                         device=dev())
+        B.project(tt, img, db, R, ws)
+        torch.cuda.synchronize()
+        Rs.append(R.cpu().numpy().astype(np.float64))
+    Rh, R0 = Rs
+    L = t.ldG
+    assert np.all(Rh[:, K:L] == 0) and np.all(Rh[:, L + K:] == 0)
+    # the tables themselves do not depend on the declaration
+    np.testing.assert_array_equal(t.G.cpu().numpy(), t0.G.cpu().numpy())
+    np.testing.assert_array_equal(t.G_im.cpu().numpy(), t0.G_im.cpu().numpy())
+    w = w_d.cpu().numpy().astype(np.float64)
+    _, D_ref = oracle.table_generation(phi, w)
+    first = parts[0][1]
+    part = slice(first, first + M * N)
+    for i, b in enumerate(blocks):
+        s, _ = oracle.area_signal(images[b.img], lost[b.img], b.y0, b.x0, M, N)
+        ref = D_ref * (np.conj(phi) @ (w * s))
+        scale = np.abs(ref).max()
+        err = max(np.abs(Rh[i, :K] - ref.real).max(), np.abs(Rh[i, L:L + K] - ref.imag).max())
+        assert err <= 1e-5 * scale, f"block {i}: {err} vs scale {scale}"
+        # outside the part both routes run the same GEMM
+        out = np.ones(K, bool)
+        out[part] = False
+        np.testing.assert_array_equal(Rh[i, :K][out], R0[i, :K][out])
+        np.testing.assert_array_equal(Rh[i, L:L + K][out], R0[i, L:L + K][out])
+
+
+def test_dft_part_refused_when_it_does_not_match():
+    """A DFT part is verified against the atoms given: declared over the
+    binarized atoms it fails with SE_EINVAL."""
+    M = N = 16
+    say("complex tables: a DFT part over binarized DFT atoms is refused")
+    phi = synth.round_to_f32(synth.dictionary(M, N, ("dft", "bdft")))
+    with pytest.raises(RuntimeError, match="does not match"):
+        B.weighted_gram(upload_phi(phi.real), torch.ones(M * N, device=dev()), M, N,
+                        phi_im=upload_phi(phi.imag), parts=[("dft", M * N)])
+
+
 def _batch(t, images, blocks, iters):
     img = torch.from_numpy(images).to(dev())
     sel, coef, g = B.extrapolate_batch(t, img, blocks, 0.5, iters)
@@ -86,8 +150,10 @@ def _batch(t, images, blocks, iters):
     return sel.cpu().numpy(), coef.cpu().numpy(), g.cpu().numpy(), img.cpu().numpy()
 
 
-@pytest.mark.parametrize("parts,n_img", [(("dft",), 2), (("dft", "bdft"), 2)])
-def test_complex_batch_parity(parts, n_img):
+@pytest.mark.parametrize("parts,n_img,declare", [(("dft",), 2, False),
+                                                 (("dft", "bdft"), 2, False),
+                                                 (("dft", "bdft"), 2, True)])
+def test_complex_batch_parity(parts, n_img, declare):
     """Algorithm 3 with complex atoms: selections equal to the oracle's
     (modulo parallel atoms and near-ties) and the real part of the model
     within the FP32 bar.  For a real signal the DFT coefficients of
@@ -96,9 +162,11 @@ def test_complex_batch_parity(parts, n_img):
     such picks as ties (the oracle re-run along the device's choices, within
     the near-tie window, must give the same model)."""
     d = synth.dft32_inputs(n_img)
-    say(f"complex batch: 32x32 areas, {parts}, {len(d['blocks'])} blocks, I=100")
+    say(f"complex batch: 32x32 areas, {parts}, DFT part declared: {declare}, "
+        f"{len(d['blocks'])} blocks, I=100")
     phi = synth.round_to_f32(synth.dictionary(32, 32, parts))
-    t, _, _ = _tables(phi, d["images"], d["blocks"], 32, 32)
+    t, _, _ = _tables(phi, d["images"], d["blocks"], 32, 32,
+                      parts=synth.dictionary_parts(32, 32, parts) if declare else ())
     sel, coef, g, out = _batch(t, d["images"], d["blocks"], 100)
     assert coef.shape[1] == 200
     st = oracle_check(d["images"], d["blocks"], phi, 32, 32, 0.8, 0.5, 100, sel, g, out,
