@@ -69,35 +69,78 @@ __device__ __forceinline__ float class_lane_max(const float (&R)[NJ][4]) {
   return m;
 }
 
+// The largest (mk) and the second largest (sk) of four wave-uniform words,
+// on the scalar unit (written out: the compiler would merge the chain of
+// maxima into vector max3 forms and take the comparisons as lane masks).
+__device__ __forceinline__ void top2_u32(const uint32_t (&k)[4], uint32_t& mk, uint32_t& sk) {
+  uint32_t a, b, c;
+  asm("s_max_u32 %[a], %[k0], %[k1]\n\t"
+      "s_min_u32 %[b], %[k0], %[k1]\n\t"
+      "s_max_u32 %[c], %[k2], %[k3]\n\t"
+      "s_min_u32 %[sk], %[k2], %[k3]\n\t"
+      "s_max_u32 %[mk], %[a], %[c]\n\t"
+      "s_min_u32 %[a], %[a], %[c]\n\t"
+      "s_max_u32 %[b], %[b], %[sk]\n\t"
+      "s_max_u32 %[sk], %[a], %[b]"
+      : [mk] "=&s"(mk), [sk] "=&s"(sk), [a] "=&s"(a), [b] "=&s"(b), [c] "=&s"(c)
+      : [k0] "s"(k[0]), [k1] "s"(k[1]), [k2] "s"(k[2]), [k3] "s"(k[3])
+      : "scc");
+}
+
+// Of four wave-uniform (key, x, y) triples, x and y of the first whose key
+// equals mk (the last if none does), on the scalar unit.
+__device__ __forceinline__ void pick4_u32(const uint32_t (&k)[4], uint32_t mk, const int (&x)[4],
+                                          const uint32_t (&y)[4], int& xo, uint32_t& yo) {
+  asm("s_cmp_eq_u32 %[k2], %[mk]\n\t"
+      "s_cselect_b32 %[xo], %[x2], %[x3]\n\t"
+      "s_cselect_b32 %[yo], %[y2], %[y3]\n\t"
+      "s_cmp_eq_u32 %[k1], %[mk]\n\t"
+      "s_cselect_b32 %[xo], %[x1], %[xo]\n\t"
+      "s_cselect_b32 %[yo], %[y1], %[yo]\n\t"
+      "s_cmp_eq_u32 %[k0], %[mk]\n\t"
+      "s_cselect_b32 %[xo], %[x0], %[xo]\n\t"
+      "s_cselect_b32 %[yo], %[y0], %[yo]"
+      : [xo] "=&s"(xo), [yo] "=&s"(yo)
+      : [mk] "s"(mk), [k0] "s"(k[0]), [k1] "s"(k[1]), [k2] "s"(k[2]), [x0] "s"(x[0]),
+        [x1] "s"(x[1]), [x2] "s"(x[2]), [x3] "s"(x[3]), [y0] "s"(y[0]), [y1] "s"(y[1]),
+        [y2] "s"(y[2]), [y3] "s"(y[3])
+      : "scc");
+}
+
 // Class form, one wave per block: the winner of class C, found when the
-// class changes (once at the start, then after each update of the class):
-// the class's largest |R~| over the wave (wm, float bits), whether one lane
-// alone holds it (one), and, if so, its position in the class order and its
-// signed value.  The holding lane's lowest position at the maximum is that
-// lane's lowest atom of the class (positions follow the atom order inside a
-// class).
+// class changes (once at the start, then after each update of the class),
+// as wave-uniform words: key = (largest |R~| of the class over the wave, as
+// float bits) << 1, plus 1 when several lanes hold it (the sign bit of |R~|
+// is 0, so the shift loses nothing and keys order as the maxima, a held-by-
+// several key above a held-by-one key of the same maximum); and the single
+// holder's position in the class order and signed value (float bits).  The
+// holding lane's lowest position at the maximum is that lane's lowest atom of
+// the class (positions follow the atom order inside a class).
 template <int NJ, int NJC, int C, int T>
-__device__ __forceinline__ void class_winner(const float (&R)[NJ][4], int t, float& lm,
-                                             uint32_t& wm, bool& one, int& pos, float& val) {
+__device__ __forceinline__ void class_winner(const float (&R)[NJ][4], int t, uint32_t& key,
+                                             int& pos, uint32_t& val) {
   const float m = class_lane_max<NJ, NJC, C>(R);
-  int p = 4 * NJC - 1;
+  // value i of the class (sweep C NJC + i / 4, entry i % 4) has the position
+  // 4 ((C NJC + i / 4) T + t) + i % 4; p holds it without the lane's 4 t
+  int p = 4 * (C * NJC + NJC - 1) * T + 3;
   float v = R[C * NJC + NJC - 1][3];
 #pragma unroll
   for (int i = 4 * NJC - 2; i >= 0; --i) {
     const float x = R[C * NJC + (i >> 2)][i & 3];
     const bool hit = fabsf(x) == m;
-    p = hit ? i : p;
+    p = hit ? 4 * (C * NJC + (i >> 2)) * T + (i & 3) : p;
     v = hit ? x : v;
   }
-  lm = m;
-  wm = __float_as_uint(wave_max_f32(m));
+  const uint32_t wm = __float_as_uint(wave_max_f32(m));
   const uint64_t holders = __builtin_amdgcn_ballot_w64(__float_as_uint(m) == wm);
-  one = __builtin_popcountll(holders) == 1;
+  // (1 to 64 holders: (count + 62) >> 6 is 0 for one, 1 for more -- an
+  // integer form without a boolean, so the words stay in scalar registers)
+  key = (wm << 1) | (((uint32_t)__builtin_popcountll(holders) + 62u) >> 6);
   const int L = (int)__builtin_ctzll(holders);
-  const int pl = __builtin_amdgcn_readlane(p, L);
-  pos = 4 * ((C * NJC + (pl >> 2)) * T + L) + (pl & 3);
-  val = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), L));
+  pos = __builtin_amdgcn_readlane(p, L) + 4 * L;
+  val = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(v), L);
 }
+
 
 // Class form: the classes (bit c) of the sweeps set in a mask of sweeps
 // (class c holds the sweeps c NJC .. c NJC + NJC - 1).
@@ -211,21 +254,23 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
   int par = 0;
   const float gamma = a.gamma;
 
-  // each class's winner kept across iterations (class form, one wave): the
-  // lane maxima, and, uniform, the wave maximum (float bits), whether one
-  // lane alone holds it, its position and signed value
+  // each class's winner kept across iterations (class form, one wave; the
+  // wave-uniform words of class_winner)
   constexpr bool INC = CLS && WAVES == 1;
-  float lmc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  uint32_t wmc[4] = {0u, 0u, 0u, 0u};
-  bool c_one[4] = {false, false, false, false};
+  uint32_t ck[4] = {0u, 0u, 0u, 0u};
   int c_pos[4] = {0, 0, 0, 0};
-  float c_val[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  uint32_t c_val[4] = {0u, 0u, 0u, 0u};
   if constexpr (INC) {
-    class_winner<NJ, NJC, 0, T>(R, t, lmc[0], wmc[0], c_one[0], c_pos[0], c_val[0]);
-    class_winner<NJ, NJC, 1, T>(R, t, lmc[1], wmc[1], c_one[1], c_pos[1], c_val[1]);
-    class_winner<NJ, NJC, 2, T>(R, t, lmc[2], wmc[2], c_one[2], c_pos[2], c_val[2]);
-    class_winner<NJ, NJC, 3, T>(R, t, lmc[3], wmc[3], c_one[3], c_pos[3], c_val[3]);
+    class_winner<NJ, NJC, 0, T>(R, t, ck[0], c_pos[0], c_val[0]);
+    class_winner<NJ, NJC, 1, T>(R, t, ck[1], c_pos[1], c_val[1]);
+    class_winner<NJ, NJC, 2, T>(R, t, ck[2], c_pos[2], c_val[2]);
+    class_winner<NJ, NJC, 3, T>(R, t, ck[3], c_pos[3], c_val[3]);
   }
+  // the selections and coefficients of 64 iterations, gathered in the lanes
+  // of wave 0 (lane i: iteration i mod 64) and written together
+  int sel_buf = 0;
+  float coef_buf = 0.0f;
+  int flush_at = min(63, a.iters - 1);
 
   for (int it = 0; it < a.iters; ++it) {
     int u = 0;
@@ -235,19 +280,22 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     bool class_key = false;                    // key from class_tie_key
     if constexpr (INC) {
       // ---- the largest class maximum: its class's winner, unless it ties
-      // (between classes, or between lanes of the class)
-      const uint32_t Mb = max(max(wmc[0], wmc[1]), max(wmc[2], wmc[3]));
-      if (Mb != 0u) {
-        const uint32_t at = (wmc[0] == Mb ? 1u : 0u) | (wmc[1] == Mb ? 2u : 0u) |
-                            (wmc[2] == Mb ? 4u : 0u) | (wmc[3] == Mb ? 8u : 0u);
-        const int cw = (int)__builtin_ctz(at);
-        const bool one = cw == 0 ? c_one[0] : cw == 1 ? c_one[1] : cw == 2 ? c_one[2] : c_one[3];
-        if ((at & (at - 1u)) == 0u && one) {
-          u = cw == 0 ? c_pos[0] : cw == 1 ? c_pos[1] : cw == 2 ? c_pos[2] : c_pos[3];
-          rv = cw == 0 ? c_val[0] : cw == 1 ? c_val[1] : cw == 2 ? c_val[2] : c_val[3];
+      // (between classes, or between lanes of the class).  With the largest
+      // key mk and the second largest sk of the four, the winner is direct
+      // exactly when mk is even (one holder) and sk < mk (no other class at
+      // the same maximum), i.e. (sk | 1) < thr with thr = mk for an even mk
+      // and 0 for an odd one (integer forms: no boolean lane masks).
+      uint32_t mk, sk;
+      top2_u32(ck, mk, sk);
+      if (mk > 1u) {                           // a nonzero maximum
+        const uint32_t thr = mk & ((mk & 1u) - 1u);
+        if ((sk | 1u) < thr) {
+          uint32_t vb;
+          pick4_u32(ck, mk, c_pos, c_val, u, vb);
+          rv = __uint_as_float(vb);
         } else {
           // exact ties across lanes or between classes: the lowest atom index
-          key = class_tie_key<NJ, T>(R, Mb, a.cl, t);
+          key = class_tie_key<NJ, T>(R, mk >> 1, a.cl, t);
           direct = false;
           class_key = true;
         }
@@ -425,9 +473,16 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     if constexpr (!CLS) Du = ((const __attribute__((address_space(4))) float*)a.D)[u];
     const float c = tc * Du;                  // eq. 19
     if (a.sel || a.coef) {                    // uniform test first: no lane mask work
-      if (t == 0) {
-        if (a.sel) a.sel[(size_t)b * a.iters + it] = ou;
-        if (a.coef) a.coef[(size_t)b * a.iters + it] = c;
+      const int slot = it & 63;
+      sel_buf = lane == slot ? ou : sel_buf;
+      coef_buf = lane == slot ? c : coef_buf;
+      if (it == flush_at) {                   // uniform: every 64 iterations, and the last
+        const size_t at = (size_t)b * a.iters + (it - slot) + lane;
+        if (wave == 0 && lane <= slot) {
+          if (a.sel) a.sel[at] = sel_buf;
+          if (a.coef) a.coef[at] = coef_buf;
+        }
+        flush_at = min(flush_at + 64, a.iters - 1);
       }
     }
     // eq. 9, compensated (the class form applies it after eq. 20: its
@@ -465,7 +520,7 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     }
     const float tr = Q16 ? tc * (1.0f / 16384.0f) : tc;   // eq. 20 factor per row entry
     if (CLS) {
-      const int cu = u / (T * NJC * 4);         // the selected atom's class (uniform)
+      const int cu = (int)((uint32_t)u / (T * NJC * 4));   // the selected atom's class (uniform)
 #pragma unroll
       for (int cc = 0; cc < 4; ++cc)
         if (cc == cu) {
@@ -478,10 +533,10 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
           }
           if constexpr (INC) {                  // the class's new winner
             switch (cc) {
-              case 0: class_winner<NJ, NJC, 0, T>(R, t, lmc[0], wmc[0], c_one[0], c_pos[0], c_val[0]); break;
-              case 1: class_winner<NJ, NJC, 1, T>(R, t, lmc[1], wmc[1], c_one[1], c_pos[1], c_val[1]); break;
-              case 2: class_winner<NJ, NJC, 2, T>(R, t, lmc[2], wmc[2], c_one[2], c_pos[2], c_val[2]); break;
-              default: class_winner<NJ, NJC, 3, T>(R, t, lmc[3], wmc[3], c_one[3], c_pos[3], c_val[3]); break;
+              case 0: class_winner<NJ, NJC, 0, T>(R, t, ck[0], c_pos[0], c_val[0]); break;
+              case 1: class_winner<NJ, NJC, 1, T>(R, t, ck[1], c_pos[1], c_val[1]); break;
+              case 2: class_winner<NJ, NJC, 2, T>(R, t, ck[2], c_pos[2], c_val[2]); break;
+              default: class_winner<NJ, NJC, 3, T>(R, t, ck[3], c_pos[3], c_val[3]); break;
             }
           }
         }
