@@ -520,7 +520,7 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     }
     const float tr = Q16 ? tc * (1.0f / 16384.0f) : tc;   // eq. 20 factor per row entry
     if (CLS) {
-      const int cu = (int)((uint32_t)u / (T * NJC * 4));   // the selected atom's class (uniform)
+      const int cu = u / (T * NJC * 4);         // the selected atom's class (uniform)
 #pragma unroll
       for (int cc = 0; cc < 4; ++cc)
         if (cc == cu) {
