@@ -59,6 +59,11 @@ namespace sefase {
 
 constexpr int kQPL = 4;   // loss pixels per lane (the loss may hold <= 4 T pixels)
 
+// Fourth word of a raw buffer resource on gfx9-family devices (32-bit data
+// format; offsets are bounds-checked against the record count in bytes).
+constexpr int kBufferWord3 = 0x00020000;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 // Largest |R~| of a lane's values in class C (sweeps C NJC .. C NJC + NJC - 1).
 template <int NJ, int NJC, int C>
 __device__ __forceinline__ float class_lane_max(const float (&R)[NJ][4]) {
@@ -69,11 +74,14 @@ __device__ __forceinline__ float class_lane_max(const float (&R)[NJ][4]) {
   return m;
 }
 
-// The largest (mk) and the second largest (sk) of four wave-uniform words,
-// on the scalar unit (written out: the compiler would merge the chain of
-// maxima into vector max3 forms and take the comparisons as lane masks).
-__device__ __forceinline__ void top2_u32(const uint32_t (&k)[4], uint32_t& mk, uint32_t& sk) {
-  uint32_t a, b, c;
+// Of four wave-uniform keys (class_winner below): the largest, mk, and
+// whether it is direct -- mk even (one holder) and the second largest sk
+// below it (no other class at the same maximum), i.e. (sk | 1) < thr with
+// thr = mk for an even mk and 0 for an odd one; dir = 1 or 0.  On the
+// scalar unit (written out: the compiler would merge the chain of maxima
+// into vector max3 forms and take the comparisons as lane masks).
+__device__ __forceinline__ void top2_u32(const uint32_t (&k)[4], uint32_t& mk, uint32_t& dir) {
+  uint32_t a, b, c, sk;
   asm("s_max_u32 %[a], %[k0], %[k1]\n\t"
       "s_min_u32 %[b], %[k0], %[k1]\n\t"
       "s_max_u32 %[c], %[k2], %[k3]\n\t"
@@ -81,8 +89,15 @@ __device__ __forceinline__ void top2_u32(const uint32_t (&k)[4], uint32_t& mk, u
       "s_max_u32 %[mk], %[a], %[c]\n\t"
       "s_min_u32 %[a], %[a], %[c]\n\t"
       "s_max_u32 %[b], %[b], %[sk]\n\t"
-      "s_max_u32 %[sk], %[a], %[b]"
-      : [mk] "=&s"(mk), [sk] "=&s"(sk), [a] "=&s"(a), [b] "=&s"(b), [c] "=&s"(c)
+      "s_max_u32 %[sk], %[a], %[b]\n\t"
+      "s_or_b32 %[sk], %[sk], 1\n\t"
+      "s_and_b32 %[c], %[mk], 1\n\t"
+      "s_add_u32 %[c], %[c], -1\n\t"
+      "s_and_b32 %[c], %[c], %[mk]\n\t"
+      "s_cmp_lt_u32 %[sk], %[c]\n\t"
+      "s_cselect_b32 %[dir], 1, 0"
+      : [mk] "=&s"(mk), [dir] "=&s"(dir), [sk] "=&s"(sk), [a] "=&s"(a), [b] "=&s"(b),
+        [c] "=&s"(c)
       : [k0] "s"(k[0]), [k1] "s"(k[1]), [k2] "s"(k[2]), [k3] "s"(k[3])
       : "scc");
 }
@@ -270,6 +285,13 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
   // of wave 0 (lane i: iteration i mod 64) and written together
   int sel_buf = 0;
   float coef_buf = 0.0f;
+  // class form: buffer resources of the class rows and of the atoms (the
+  // class tables exist for areas of at most 64 x 64 samples and K <= 32768,
+  // so every byte offset fits 32 bits; unused by the other forms)
+  const __amdgpu_buffer_rsrc_t gc_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(a.Gc), (short)0, K * (T * NJ * 4), kBufferWord3);
+  const __amdgpu_buffer_rsrc_t phi_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(a.phi), (short)0, K * (P * 4), kBufferWord3);
   int flush_at = min(63, a.iters - 1);
 
   for (int it = 0; it < a.iters; ++it) {
@@ -280,25 +302,18 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     bool class_key = false;                    // key from class_tie_key
     if constexpr (INC) {
       // ---- the largest class maximum: its class's winner, unless it ties
-      // (between classes, or between lanes of the class).  With the largest
-      // key mk and the second largest sk of the four, the winner is direct
-      // exactly when mk is even (one holder) and sk < mk (no other class at
-      // the same maximum), i.e. (sk | 1) < thr with thr = mk for an even mk
-      // and 0 for an odd one (integer forms: no boolean lane masks).
-      uint32_t mk, sk;
-      top2_u32(ck, mk, sk);
-      if (mk > 1u) {                           // a nonzero maximum
-        const uint32_t thr = mk & ((mk & 1u) - 1u);
-        if ((sk | 1u) < thr) {
-          uint32_t vb;
-          pick4_u32(ck, mk, c_pos, c_val, u, vb);
-          rv = __uint_as_float(vb);
-        } else {
-          // exact ties across lanes or between classes: the lowest atom index
-          key = class_tie_key<NJ, T>(R, mk >> 1, a.cl, t);
-          direct = false;
-          class_key = true;
-        }
+      // (between classes, or between lanes of the class)
+      uint32_t mk, dir;
+      top2_u32(ck, mk, dir);
+      if (dir != 0u) {
+        uint32_t vb;
+        pick4_u32(ck, mk, c_pos, c_val, u, vb);
+        rv = __uint_as_float(vb);
+      } else if (mk > 1u) {                    // a nonzero maximum (else atom 0, value 0)
+        // exact ties across lanes or between classes: the lowest atom index
+        key = class_tie_key<NJ, T>(R, mk >> 1, a.cl, t);
+        direct = false;
+        class_key = true;
       }
     } else {
     // ---- this wave's largest |R~| and its lowest index ---------------------
@@ -440,8 +455,15 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
 #pragma unroll
       for (int j = 0; j < NR; ++j) qrow[j] = *reinterpret_cast<const uint2*>(g16 + 4 * (j * T + t));
     } else if constexpr (CLS) {
+      // buffer loads: the row's byte offset is a scalar offset on a fixed
+      // resource, the lane's part a loop-invariant vector offset
+      const int so = u * (T * NJ * 4);
 #pragma unroll
-      for (int j = 0; j < NR; ++j) row[j] = *reinterpret_cast<const float4*>(grow + 4 * (j * T + t));
+      for (int j = 0; j < NR; ++j) {
+        const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(gc_rsrc, 16 * (j * T + t), so, 0);
+        row[j] = make_float4(__uint_as_float(q.x), __uint_as_float(q.y), __uint_as_float(q.z),
+                             __uint_as_float(q.w));
+      }
     }
     // the selected atom's original index and D (the class form: from the
     // class table; a scalar load that does not wait behind vector loads)
@@ -458,11 +480,22 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     // only for losses larger than the workgroup, one uniform branch)
     const float* prow = a.phi + (size_t)ou * P;
     float pv[kQPL];
-    pv[0] = prow[poff[0]];
-    if (nq > 1) {
+    if constexpr (CLS) {                       // (buffer loads, as the rows)
+      const int so = ou * (P * 4);
+      pv[0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(phi_rsrc, 4 * poff[0], so, 0));
+      if (nq > 1) {
 #pragma unroll
-      for (int q = 1; q < kQPL; ++q)
-        if (q < nq) pv[q] = prow[poff[q]];
+        for (int q = 1; q < kQPL; ++q)
+          if (q < nq)
+            pv[q] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(phi_rsrc, 4 * poff[q], so, 0));
+      }
+    } else {
+      pv[0] = prow[poff[0]];
+      if (nq > 1) {
+#pragma unroll
+        for (int q = 1; q < kQPL; ++q)
+          if (q < nq) pv[q] = prow[poff[q]];
+      }
     }
     if constexpr (!CLS && !Q16) {
 #pragma unroll
