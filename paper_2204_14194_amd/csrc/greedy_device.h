@@ -74,13 +74,16 @@ __device__ __forceinline__ float class_lane_max(const float (&R)[NJ][4]) {
   return m;
 }
 
-// Of four wave-uniform keys (class_winner below): the largest, mk, and
-// whether it is direct -- mk even (one holder) and the second largest sk
-// below it (no other class at the same maximum), i.e. (sk | 1) < thr with
-// thr = mk for an even mk and 0 for an odd one; dir = 1 or 0.  On the
-// scalar unit (written out: the compiler would merge the chain of maxima
-// into vector max3 forms and take the comparisons as lane masks).
-__device__ __forceinline__ void top2_u32(const uint32_t (&k)[4], uint32_t& mk, uint32_t& dir) {
+// Of four wave-uniform keys (class_winner below): the largest, mk; whether
+// it is direct -- mk even (one holder) and the second largest sk below it
+// (no other class at the same maximum), i.e. (sk | 1) < thr with thr = mk
+// for an even mk and 0 for an odd one; dir = 1 or 0 -- and x, y of the first
+// class whose key equals mk (the position and value bits of its winner).
+// On the scalar unit (written out: the compiler would merge the chain of
+// maxima into vector max3 forms and take the comparisons as lane masks).
+__device__ __forceinline__ void select_class(const uint32_t (&k)[4], const int (&x)[4],
+                                             const uint32_t (&y)[4], uint32_t& mk,
+                                             uint32_t& dir, int& xo, uint32_t& yo) {
   uint32_t a, b, c, sk;
   asm("s_max_u32 %[a], %[k0], %[k1]\n\t"
       "s_min_u32 %[b], %[k0], %[k1]\n\t"
@@ -95,18 +98,8 @@ __device__ __forceinline__ void top2_u32(const uint32_t (&k)[4], uint32_t& mk, u
       "s_add_u32 %[c], %[c], -1\n\t"
       "s_and_b32 %[c], %[c], %[mk]\n\t"
       "s_cmp_lt_u32 %[sk], %[c]\n\t"
-      "s_cselect_b32 %[dir], 1, 0"
-      : [mk] "=&s"(mk), [dir] "=&s"(dir), [sk] "=&s"(sk), [a] "=&s"(a), [b] "=&s"(b),
-        [c] "=&s"(c)
-      : [k0] "s"(k[0]), [k1] "s"(k[1]), [k2] "s"(k[2]), [k3] "s"(k[3])
-      : "scc");
-}
-
-// Of four wave-uniform (key, x, y) triples, x and y of the first whose key
-// equals mk (the last if none does), on the scalar unit.
-__device__ __forceinline__ void pick4_u32(const uint32_t (&k)[4], uint32_t mk, const int (&x)[4],
-                                          const uint32_t (&y)[4], int& xo, uint32_t& yo) {
-  asm("s_cmp_eq_u32 %[k2], %[mk]\n\t"
+      "s_cselect_b32 %[dir], 1, 0\n\t"
+      "s_cmp_eq_u32 %[k2], %[mk]\n\t"
       "s_cselect_b32 %[xo], %[x2], %[x3]\n\t"
       "s_cselect_b32 %[yo], %[y2], %[y3]\n\t"
       "s_cmp_eq_u32 %[k1], %[mk]\n\t"
@@ -115,8 +108,9 @@ __device__ __forceinline__ void pick4_u32(const uint32_t (&k)[4], uint32_t mk, c
       "s_cmp_eq_u32 %[k0], %[mk]\n\t"
       "s_cselect_b32 %[xo], %[x0], %[xo]\n\t"
       "s_cselect_b32 %[yo], %[y0], %[yo]"
-      : [xo] "=&s"(xo), [yo] "=&s"(yo)
-      : [mk] "s"(mk), [k0] "s"(k[0]), [k1] "s"(k[1]), [k2] "s"(k[2]), [x0] "s"(x[0]),
+      : [mk] "=&s"(mk), [dir] "=&s"(dir), [xo] "=&s"(xo), [yo] "=&s"(yo), [sk] "=&s"(sk),
+        [a] "=&s"(a), [b] "=&s"(b), [c] "=&s"(c)
+      : [k0] "s"(k[0]), [k1] "s"(k[1]), [k2] "s"(k[2]), [k3] "s"(k[3]), [x0] "s"(x[0]),
         [x1] "s"(x[1]), [x2] "s"(x[2]), [x3] "s"(x[3]), [y0] "s"(y[0]), [y1] "s"(y[1]),
         [y2] "s"(y[2]), [y3] "s"(y[3])
       : "scc");
@@ -303,17 +297,18 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     if constexpr (INC) {
       // ---- the largest class maximum: its class's winner, unless it ties
       // (between classes, or between lanes of the class)
-      uint32_t mk, dir;
-      top2_u32(ck, mk, dir);
-      if (dir != 0u) {
-        uint32_t vb;
-        pick4_u32(ck, mk, c_pos, c_val, u, vb);
-        rv = __uint_as_float(vb);
-      } else if (mk > 1u) {                    // a nonzero maximum (else atom 0, value 0)
-        // exact ties across lanes or between classes: the lowest atom index
-        key = class_tie_key<NJ, T>(R, mk >> 1, a.cl, t);
-        direct = false;
-        class_key = true;
+      uint32_t mk, dir, vb;
+      select_class(ck, c_pos, c_val, mk, dir, u, vb);   // (u, vb taken when direct)
+      rv = __uint_as_float(vb);
+      if (dir == 0u) {
+        u = 0;                                  // every score zero: atom 0, value 0
+        rv = 0.0f;
+        if (mk > 1u) {
+          // exact ties across lanes or between classes: the lowest atom index
+          key = class_tie_key<NJ, T>(R, mk >> 1, a.cl, t);
+          direct = false;
+          class_key = true;
+        }
       }
     } else {
     // ---- this wave's largest |R~| and its lowest index ---------------------

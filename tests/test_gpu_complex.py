@@ -175,14 +175,17 @@ def test_complex_batch_parity(parts, n_img, declare):
     assert st["worst"] <= TOL_FP32
 
 
-def test_complex_routes_agree_and_refusals():
+@pytest.mark.parametrize("declare", [False, True])
+def test_complex_routes_agree_and_refusals(declare):
     """The batched call, the two stages and the device-descriptor call give
-    the same bits; the per-block form, rows on demand and split-BF16 tables
-    refuse complex dictionaries."""
+    the same bits (with and without the DFT half declared as a transform
+    part); the per-block form, rows on demand and split-BF16 tables refuse
+    complex dictionaries."""
     d = synth.dft32_inputs(1)
-    say("complex tables: routes agree; unsupported calls refuse")
+    say(f"complex tables: routes agree (DFT part declared: {declare}); unsupported calls refuse")
     phi = synth.round_to_f32(d["phi"])
-    t, w_d, _ = _tables(phi, d["images"], d["blocks"], 32, 32)
+    t, w_d, _ = _tables(phi, d["images"], d["blocks"], 32, 32,
+                        parts=d["tx_parts"] if declare else ())
     sel0, coef0, g0, out0 = _batch(t, d["images"], d["blocks"], 60)
     n = len(d["blocks"])
     img = torch.from_numpy(d["images"]).to(dev())
