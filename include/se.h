@@ -323,7 +323,8 @@ int32_t se_table_ld(int32_t K);
  * M or N outside 1..64.  For areas of T frames pass T*M as M (the frames
  * are transformed stacked).  Any n_parts of 1 or 2 gets room for the
  * operands of two transforms (a SE_PART_DFT2 part takes the cosine and the
- * sine matrices). */
+ * sine matrices) and for a second copy of them with the rows in parity-class
+ * order (read by the one-launch loop on parity-class rows). */
 size_t se_tables_tx_bytes(int32_t M, int32_t N, int32_t n_parts);
 
 /* ------------------------------------------------------------------------ */

@@ -53,34 +53,43 @@ void k_conceal_tx(GreedyArgs a, TxArgs x, TxLayout L) {
   if (computes) {
 #pragma unroll 1
     for (int q = wave; q < NP; q += WAVES) {
-      float* Rq = Rs + (q ? x.first1 : x.first0);
-      // a square area transforms rows and columns with the same matrix, whose
-      // two fragment orders then coincide: one copy is read
-      const float* Af = x.tx + L.oAf + q * MT * MT * 256;
-      const float* Btf = M == N ? Af : x.tx + L.oBtf + q * NT * NT * 256;
-      tx_part<MT, NT, true>(Af, Btf, x.tx + L.oDf + q * MT * NT * 256, xv, M, N,
-                            [&](int k1, int k2, float v) { Rq[k1 * N + k2] = v; });
+      // a square area of one frame transforms rows and columns with the same
+      // matrix, whose two fragment orders then coincide: one copy is read
+      if constexpr (CLS) {
+        // the class-order operands: the transform's 2 x 2 parity quadrants
+        // are the parity classes' atoms of this part in class order, so the
+        // output goes straight to its class position (class c = 2 pv + ph
+        // in blocks of K / 4; in a class the part with the lower first atom
+        // first; in a part row-major over (frame, row / 2, column / 2))
+        const float* Af = x.tx + L.oAc + q * MT * MT * 256;
+        const float* Btf = M == N && !VOL ? Af : x.tx + L.oBc + q * NT * NT * 256;
+        const int HV = M / 2, HN = N / 2, Kc = a.K / 4;
+        const int qoff = (q ? x.first1 > x.first0 : x.first0 > x.first1) ? HV * HN : 0;
+        tx_part<MT, NT, true>(Af, Btf, x.tx + L.oDc + q * MT * NT * 256, xv, M, N,
+                              [&](int k1, int k2, float v) {
+                                const int pv = k1 >= HV, ph = k2 >= HN;
+                                Rs[(2 * pv + ph) * Kc + qoff + (k1 - pv * HV) * HN + k2 -
+                                   ph * HN] = v;
+                              });
+      } else {
+        float* Rq = Rs + (q ? x.first1 : x.first0);
+        const float* Af = x.tx + L.oAf + q * MT * MT * 256;
+        const float* Btf = M == N ? Af : x.tx + L.oBtf + q * NT * NT * 256;
+        tx_part<MT, NT, true>(Af, Btf, x.tx + L.oDf + q * MT * NT * 256, xv, M, N,
+                              [&](int k1, int k2, float v) { Rq[k1 * N + k2] = v; });
+      }
     }
   }
   for (int k = a.K + t; k < T * VPL; k += T) Rs[k] = 0.0f;   // padding atoms
   __syncthreads();
 
   // ---- Algorithm 3 from R~^(0) ------------------------------------------------
+  // (in the loop's order: atom order, or the class order the class form wrote)
   float R[NJ][4];
-  if (CLS) {
-    // the class order: position 4 (j T + t) + e holds the atom cls[.].x
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int4 q0 = *reinterpret_cast<const int4*>(a.cls + 4 * (j * T + t));
-      const int4 q1 = *reinterpret_cast<const int4*>(a.cls + 4 * (j * T + t) + 2);
-      R[j][0] = Rs[q0.x]; R[j][1] = Rs[q0.z]; R[j][2] = Rs[q1.x]; R[j][3] = Rs[q1.z];
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const floatx4 v = *reinterpret_cast<const floatx4*>(Rs + 4 * (j * T + t));
-      R[j][0] = v[0]; R[j][1] = v[1]; R[j][2] = v[2]; R[j][3] = v[3];
-    }
+  for (int j = 0; j < NJ; ++j) {
+    const floatx4 v = *reinterpret_cast<const floatx4*>(Rs + 4 * (j * T + t));
+    R[j][0] = v[0]; R[j][1] = v[1]; R[j][2] = v[2]; R[j][3] = v[3];
   }
   greedy_block<WAVES, VPL, CLS, Q16>(a, b, R);
 }

@@ -151,7 +151,23 @@ __global__ __launch_bounds__(kTxThreads) void k_build_tx(TxBuildArgs a, TxLayout
   const double iN = 1.0 / sqrt((double)N), aN = sqrt(2.0 / (double)N);
   const VertBasis vb{a.T, a.Ms, ctT, ctS};
   const int nA = MT * MT * 256, nB = NT * NT * 256, nD = MT * NT * 256;
-  for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < L.nconst; x += gridDim.x * blockDim.x) {
+  // class-order operands: two DCT-II / Walsh-Hadamard parts on areas of even
+  // sides (the parity classes); otherwise that region stays 0
+  const bool kinds_ok = (a.kind0 == SE_PART_DCT2 || a.kind0 == SE_PART_WHT2) &&
+                        (a.kind1 == SE_PART_DCT2 || a.kind1 == SE_PART_WHT2);
+  const bool cls = a.parts == 2 && kinds_ok && (a.Ms & 1) == 0 && (N & 1) == 0;
+  const int HV = M / 2, HS = a.Ms / 2, HN = N / 2;
+  // original stacked row of class-order row k (parity, frame, row / 2), and
+  // original column of class-order column k (parity, column / 2)
+  auto vrow = [&](int kind, int k) {
+    const int pv = k / HV, rem = k - pv * HV, kt = rem / HS;
+    return kt * a.Ms + parity_row(kind, rem - kt * HS, pv);
+  };
+  auto hcol = [&](int kind, int k) {
+    const int ph = k / HN;
+    return parity_row(kind, k - ph * HN, ph);
+  };
+  for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < L.ntotal; x += gridDim.x * blockDim.x) {
     float v = 0.0f;
     if (x < L.oBtf) {                       // Af
       const int q = x / nA, y = x - q * nA;
@@ -167,6 +183,32 @@ __global__ __launch_bounds__(kTxThreads) void k_build_tx(TxBuildArgs a, TxLayout
       if (k2 < N && n < N) v = basis_1d(q ? a.kind1 : a.kind0, N, k2, n, ctN, iN, aN);
     } else if (!a.D) {                      // operands of unscaled transforms only
       break;
+    } else if (x >= L.nconst) {             // class-order Ac, Bc, Dc
+      if (cls) {
+        if (x < L.oBc) {
+          const int z = x - L.oAc, q = z / nA, y = z - q * nA;
+          const int e = y & 3, l = (y >> 2) & 63, ri = y >> 8;
+          const int r = ri / MT, i = ri - r * MT;
+          const int row = 16 * r + (l & 15), col = 16 * i + 4 * (l >> 4) + e;
+          const int kind = q ? a.kind1 : a.kind0;
+          if (row < M && col < M) v = vb(kind, vrow(kind, row), col);
+        } else if (x < L.oDc) {
+          const int z = x - L.oBc, q = z / nB, y = z - q * nB;
+          const int t = y & 3, l = (y >> 2) & 63, cs = y >> 8;
+          const int c = cs / NT, sq = cs - c * NT;
+          const int k2 = 16 * c + (l & 15), n = 16 * sq + 4 * (l >> 4) + t;
+          const int kind = q ? a.kind1 : a.kind0;
+          if (k2 < N && n < N) v = basis_1d(kind, N, hcol(kind, k2), n, ctN, iN, aN);
+        } else {
+          const int z = x - L.oDc, q = z / nD, y = z - q * nD;
+          const int e = y & 3, l = (y >> 2) & 63, cr = y >> 8;
+          const int c = cr / MT, r = cr - c * MT;
+          const int k1 = 16 * r + 4 * (l >> 4) + e, k2 = 16 * c + (l & 15);
+          const int kind = q ? a.kind1 : a.kind0;
+          if (k1 < M && k2 < N)
+            v = a.D[(q ? a.first1 : a.first0) + vrow(kind, k1) * N + hcol(kind, k2)];
+        }
+      }
     } else if (x < L.oWf) {                 // Df
       const int z = x - L.oDf, q = z / nD, y = z - q * nD;
       const int e = y & 3, l = (y >> 2) & 63, cr = y >> 8;
@@ -561,7 +603,7 @@ se_status check_dft_part(const float* phi, const float* phi_im, int M, int N, in
 
 size_t tx_const_bytes(int M, int N, int n_parts) {
   if (M < 1 || N < 1 || M > 64 || N > 64 || n_parts < 1 || n_parts > 2) return 0;
-  return (size_t)TxLayout(M, N, n_parts, 0).nconst * 4;
+  return (size_t)TxLayout(M, N, n_parts, 0).ntotal * 4;
 }
 
 se_status build_tx(const se_tables* t, hipStream_t s) {
@@ -586,7 +628,7 @@ se_status build_tx(const se_tables* t, hipStream_t s) {
   a.sqrtw = t->sqrtw;
   a.tx = t->tx;
   const TxLayout L(a.M, t->N, a.parts, 0);
-  const int grid = (L.nconst + kTxThreads - 1) / kTxThreads;
+  const int grid = (L.ntotal + kTxThreads - 1) / kTxThreads;
   hipLaunchKernelGGL(k_build_tx, dim3(grid), dim3(kTxThreads),
                      (size_t)4 * (a.Ms + a.N + a.T) * 8, s, a, L);
   return check_launch("build_tx");

@@ -36,8 +36,14 @@ struct TxLayout {
   int M, N, MT, NT, parts, waves;
   // offsets in floats; [0, nconst) is the copy of se_tables.tx.  Each wave
   // owns wsz floats at oXf: its X fragments, and with staging (zs > 0) one
-  // part's M x N output at row stride zs.
+  // part's M x N output at row stride zs.  With two parts, se_tables.tx
+  // continues after nconst with the class-order operands (oAc, oBc, oDc, up
+  // to ntotal): A, B and D of both parts with their rows sorted by (parity,
+  // frame, row / 2), so that each 2 x 2 parity quadrant of a transform is
+  // one parity class's atoms of the part in class order (read from device
+  // memory by the one-launch class kernel only, never copied to LDS).
   int oAf, oBtf, oDf, oWf, nconst, oXf, zs, wsz, nfloat;
+  int oAc, oBc, oDc, ntotal;
   __host__ __device__ TxLayout(int M_, int N_, int parts_, int waves_, bool stage = false)
       : M(M_), N(N_), parts(parts_), waves(waves_) {
     MT = (M + 15) / 16;
@@ -47,6 +53,10 @@ struct TxLayout {
     oDf = oBtf + parts * NT * NT * 256;
     oWf = oDf + parts * MT * NT * 256;
     nconst = oWf + MT * NT * 256;
+    oAc = nconst;
+    oBc = oAc + (parts == 2 ? 2 * MT * MT * 256 : 0);
+    oDc = oBc + (parts == 2 ? 2 * NT * NT * 256 : 0);
+    ntotal = oDc + (parts == 2 ? 2 * MT * NT * 256 : 0);
     oXf = nconst;
     zs = stage ? N + 4 : 0;
     wsz = MT * NT * 256 > M * zs ? MT * NT * 256 : M * zs;

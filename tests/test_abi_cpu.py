@@ -138,10 +138,11 @@ def test_rejects_bad_transform_parts_on_host():
                                None, None, None, 0, fake, 1 << 30, None)
     assert r == B.SE_EINVAL and b"tx" in L.se_last_error()
     # its size: fragments of A, B (per transform), D (per transform) and w, 1 KiB per
-    # 16 x 16 tile, room for two transforms (a DFT part is a real and an imaginary one)
-    assert L.se_tables_tx_bytes(32, 32, 2) == (2 * 4 + 2 * 4 + 2 * 4 + 4) * 1024
+    # 16 x 16 tile, room for two transforms (a DFT part is a real and an imaginary one),
+    # then A, B and D of both transforms once more in class order
+    assert L.se_tables_tx_bytes(32, 32, 2) == (2 * 4 + 2 * 4 + 2 * 4 + 4 + 2 * (4 + 4 + 4)) * 1024
     assert L.se_tables_tx_bytes(32, 32, 1) == L.se_tables_tx_bytes(32, 32, 2)
-    assert L.se_tables_tx_bytes(7, 5, 1) == 7 * 1024
+    assert L.se_tables_tx_bytes(7, 5, 1) == (7 + 6) * 1024
     assert L.se_tables_tx_bytes(32, 32, 0) == 0 and L.se_tables_tx_bytes(65, 8, 1) == 0
 
 
