@@ -334,6 +334,11 @@ size_t se_tables_tx_bytes(int32_t M, int32_t N, int32_t n_parts);
 /* w_b[m*N+n] = rho_hat ^ sqrt((m-(M-1)/2)^2 + (n-(N-1)/2)^2) for every
  * pixel of block b's area that lies inside the image and is not lost, and
  * 0 elsewhere (eq. 4: the loss and every unavailable pixel are masked).
+ * Frames whose rows are stored with a pitch larger than their width are
+ * passed with W = the pitch and their padding columns marked lost in this
+ * mask: the padding then has weight 0, as samples outside the frame do, so
+ * every result equals the unpadded frame's and the padding is never
+ * written (the server computes its own weights and takes unpadded frames).
  *   lost    : device uint8, n_img images of H x W (row pitch W, image
  *             stride H*W); nonzero = lost pixel
  *   blocks  : host, n_blk descriptors (only img, y0, x0 are read)

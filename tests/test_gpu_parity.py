@@ -351,6 +351,43 @@ def run_ondemand(phi32, M, N, images, blocks, gamma, iters):
     return sel.cpu().numpy(), coef.cpu().numpy(), g.cpu().numpy(), img_d.cpu().numpy()
 
 
+@pytest.mark.parametrize("with_parts", [False, True])
+def test_pitched_frames_via_lost_padding(with_parts):
+    """Frames whose rows are stored with a pitch larger than their width:
+    passed with W = pitch and the padding columns marked lost in the mask the
+    weights are computed from, they carry weight 0 like samples outside the
+    image, so every output equals the unpadded frame's bit for bit and the
+    padding is never written (areas across the right border included)."""
+    say(f"pitched frames: 100-wide rows in a 128-wide pitch, parts {with_parts}")
+    M = N = 32
+    H, W, P = 96, 100, 128
+    phi = synth.round_to_f32(synth.dictionary(M, N, ("dct", "wht")))
+    parts = synth.dictionary_parts(M, N, ("dct", "wht")) if with_parts else ()
+    blocks = [synth.Block(0, y, x, 12, 12, 8, 8) for y in (-10, 30, 70) for x in (-8, 40, 80)]
+    base = synth.synth_image(H, W, seed=91)
+    rng = np.random.default_rng(5)
+    padded = np.concatenate([base, rng.integers(0, 256, (H, P - W), dtype=np.uint8)], axis=1)
+    lost = synth.lost_mask(H, W, blocks)
+    lost_p = np.concatenate([lost, np.ones((H, P - W), dtype=np.uint8)], axis=1)
+    out = []
+    for img, lm in ((base, lost), (padded, lost_p)):
+        w = B.area_weights(M, N, 0.8, torch.from_numpy(lm[None]).to(dev()), blocks)
+        img_d = torch.from_numpy(img[None].copy()).to(dev())
+        sel, coef, g = B.extrapolate_ondemand(upload_phi(phi), M, N, w, img_d, blocks, 0.5, 60,
+                                              parts=parts)
+        torch.cuda.synchronize()
+        out.append((w.cpu().numpy(), sel.cpu().numpy(), coef.cpu().numpy(), g.cpu().numpy(),
+                    img_d.cpu().numpy()[0]))
+    (w0, s0, c0, g0, i0), (w1, s1, c1, g1, i1) = out
+    np.testing.assert_array_equal(w0, w1)
+    np.testing.assert_array_equal(s0, s1)
+    np.testing.assert_array_equal(c0, c1)
+    np.testing.assert_array_equal(g0, g1)
+    np.testing.assert_array_equal(i0, i1[:, :W])
+    np.testing.assert_array_equal(i1[:, W:], padded[:, W:])
+    assert not np.array_equal(i0, base)        # the losses were concealed
+
+
 def test_ondemand_equals_shared_tables_on_isolated_blocks():
     """Identical weights for every block: forming rows on demand must give
     the same result as the shared table (and the oracle)."""
