@@ -147,6 +147,115 @@ __device__ void tx_part(const float* Af, const float* Btf, const float* Df,
   if (NT & 1) tx_cols<MT, NT, 1, SCALE>(NT - 1, Af, Btf, Df, x, M, N, out);
 }
 
+// ---------------------------------------------------------------------------
+// Class-order transforms with the vertical fold.  With the operand rows in
+// class order (TxLayout's oAc, oBc, oDc), rows [0, M/2) of the vertical
+// matrix A' are even about the area's centre (A'[k][M-1-m] = A'[k][m]) and
+// rows [M/2, M) odd (= -A'[k][m]), for the DCT-II and the Walsh-Hadamard
+// rows alike.  So A' X = [A'_e (X_top + X_bot~); A'_o (X_top - X_bot~)] over
+// the first M/2 columns of A', X_bot~ the bottom rows of X upside down: half
+// the contraction of the vertical stage.  For M = 16 MT (MT even) the mirror
+// of row 16 i + r is row 16 (MT-1-i) + 15 - r: the same lane of the mirrored
+// lane within its row of 16 lanes (a DPP row mirror) in register MT-1-i.
+//   xf[0] = X_top + X_bot~, xf[1] = X_top - X_bot~ (MT/2 row tiles each)
+template <int MT, int NT>
+__device__ inline void tx_fold_rows(const floatx4 (&x)[MT][NT], floatx4 (&xf)[2][MT / 2][NT]) {
+#pragma unroll
+  for (int i = 0; i < MT / 2; ++i)
+#pragma unroll
+    for (int sq = 0; sq < NT; ++sq)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float m = __int_as_float(__builtin_amdgcn_update_dpp(
+            0, __float_as_int(x[MT - 1 - i][sq][t]), 0x140 /* row_mirror */, 0xF, 0xF, false));
+        xf[0][i][sq][t] = x[i][sq][t] + m;
+        xf[1][i][sq][t] = x[i][sq][t] - m;
+      }
+}
+
+// Column tiles c0 .. c0 + CP - 1 of the class-order rows of parity pv (rows
+// pv M/2 .. pv M/2 + M/2 - 1) from the folded operand xf = xf[pv]: the
+// scheme of tx_cols with MT/2 row tiles in both stages; out(k1, k2, D_k z)
+// with k1 the class-order row.
+template <int MT, int NT, int CP, typename Out>
+__device__ inline void tx_cols_fold(int c0, int pv, const float* Af, const float* Btf,
+                                    const float* Df, const floatx4 (&x)[MT / 2][NT], int M,
+                                    int N, Out& out) {
+  constexpr int MH = MT / 2;
+  const int l = threadIdx.x & 63;
+  floatx4 y[CP][MH];
+#pragma unroll
+  for (int cc = 0; cc < CP; ++cc)
+#pragma unroll
+    for (int i = 0; i < MH; ++i) y[cc][i] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int sq = 0; sq < NT; ++sq) {
+    floatx4 bv[CP];
+#pragma unroll
+    for (int cc = 0; cc < CP; ++cc)
+      bv[cc] = *reinterpret_cast<const floatx4*>(Btf + (((c0 + cc) * NT + sq) * 64 + l) * 4);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int cc = 0; cc < CP; ++cc)
+#pragma unroll
+        for (int i = 0; i < MH; ++i)
+          y[cc][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[i][sq][t], bv[cc][t], y[cc][i], 0, 0, 0);
+  }
+  floatx4 z[CP][MH];
+#pragma unroll
+  for (int cc = 0; cc < CP; ++cc)
+#pragma unroll
+    for (int r = 0; r < MH; ++r) z[cc][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < MH; ++i) {
+    floatx4 av[MH];
+#pragma unroll
+    for (int r = 0; r < MH; ++r)
+      av[r] = *reinterpret_cast<const floatx4*>(Af + (((pv * MH + r) * MT + i) * 64 + l) * 4);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int cc = 0; cc < CP; ++cc)
+#pragma unroll
+        for (int r = 0; r < MH; ++r)
+          z[cc][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r][e], y[cc][i][e], z[cc][r], 0, 0, 0);
+  }
+#pragma unroll
+  for (int cc = 0; cc < CP; ++cc) {
+    const int c = c0 + cc, k2 = 16 * c + (l & 15);
+#pragma unroll
+    for (int r = 0; r < MH; ++r) {
+      const int rr = pv * MH + r;
+      const floatx4 dv = *reinterpret_cast<const floatx4*>(Df + ((c * MT + rr) * 64 + l) * 4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k1 = 16 * rr + 4 * (l >> 4) + e;
+        if (k1 < M && k2 < N) out(k1, k2, dv[e] * z[cc][r][e]);
+      }
+    }
+  }
+}
+
+// One part in class order from the folded operands: both parities, two
+// column tiles per pass.
+template <int MT, int NT, typename Out>
+__device__ void tx_part_fold(const float* Af, const float* Btf, const float* Df,
+                             const floatx4 (&xf)[2][MT / 2][NT], int M, int N, Out out) {
+  // both parities unrolled: a register array indexed at run time would go
+  // to scratch
+#pragma unroll
+  for (int pv = 0; pv < 2; ++pv) {
+#pragma unroll 1
+    for (int c0 = 0; c0 + 1 < NT; c0 += 2) {
+      int opaque = 0;
+      asm volatile("" : "+s"(opaque));
+      tx_cols_fold<MT, NT, 2>(c0, pv, Af + opaque, Btf, Df, xf[pv], M, N, out);
+    }
+    if (NT & 1) tx_cols_fold<MT, NT, 1>(NT - 1, pv, Af, Btf, Df, xf[pv], M, N, out);
+  }
+}
+
 // Orders this wave's LDS writes before its later reads (and reads before
 // later writes).
 __device__ inline void wave_sync() {
