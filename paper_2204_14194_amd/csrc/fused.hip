@@ -119,6 +119,9 @@ void k_conceal_tx(GreedyArgs a, TxArgs x, TxLayout L) {
 template <int WAVES, int VPL, int MT, int NT, int NP, bool CLS, bool VOL = false, bool Q16 = false>
 static se_status launch_conceal(const GreedyArgs& a, const TxArgs& x, const TxLayout& L, int grid,
                                 hipStream_t s) {
+  // the class form's folded projection writes whole tiles unchecked
+  if (CLS && !VOL && MT % 2 == 0 && (L.M != 16 * MT || L.N != 16 * NT))
+    return fail(SE_EINVAL, "folded projection needs whole tiles (%dx%d)", L.M, L.N);
   const size_t lds = (size_t)conceal_lds_floats<WAVES, VPL, MT, NT, NP>() * 4;
   hipLaunchKernelGGL((k_conceal_tx<WAVES, VPL, MT, NT, NP, CLS, VOL, Q16>), dim3(grid),
                      dim3(64 * WAVES), lds, s, a, x, L);

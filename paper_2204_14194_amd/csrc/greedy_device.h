@@ -128,18 +128,40 @@ __device__ __forceinline__ void select_class(const uint32_t (&k)[4], const int (
 template <int NJ, int NJC, int C, int T>
 __device__ __forceinline__ void class_winner(const float (&R)[NJ][4], int t, uint32_t& key,
                                              int& pos, uint32_t& val) {
-  const float m = class_lane_max<NJ, NJC, C>(R);
-  // value i of the class (sweep C NJC + i / 4, entry i % 4) has the position
-  // 4 ((C NJC + i / 4) T + t) + i % 4; p holds it without the lane's 4 t
-  int p = 4 * (C * NJC + NJC - 1) * T + 3;
-  float v = R[C * NJC + NJC - 1][3];
+  // the lane's maximum through its sweep maxima
+  float ms[NJC];
 #pragma unroll
-  for (int i = 4 * NJC - 2; i >= 0; --i) {
-    const float x = R[C * NJC + (i >> 2)][i & 3];
-    const bool hit = fabsf(x) == m;
-    p = hit ? 4 * (C * NJC + (i >> 2)) * T + (i & 3) : p;
-    v = hit ? x : v;
+  for (int s = 0; s < NJC; ++s) {
+    const float* r = R[C * NJC + s];
+    ms[s] = fmaxf(fmaxf(fabsf(r[0]), fabsf(r[1])), fmaxf(fabsf(r[2]), fabsf(r[3])));
   }
+  float m = ms[0];
+#pragma unroll
+  for (int s = 1; s < NJC; ++s) m = fmaxf(m, ms[s]);
+  // value e of sweep C NJC + s has the position 4 ((C NJC + s) T + t) + e, and
+  // the sweeps' positions increase with s: the lowest sweep at the maximum
+  // (its four values q and base b, without the lane's 4 t) ...
+  float q[4];
+  int b = 4 * (C * NJC + NJC - 1) * T;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) q[e] = R[C * NJC + NJC - 1][e];
+#pragma unroll
+  for (int s = NJC - 2; s >= 0; --s) {
+    const bool hit = ms[s] == m;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) q[e] = hit ? R[C * NJC + s][e] : q[e];
+    b = hit ? 4 * (C * NJC + s) * T : b;
+  }
+  // ... then its lowest entry at the maximum
+  int p = 3;
+  float v = q[3];
+#pragma unroll
+  for (int e = 2; e >= 0; --e) {
+    const bool hit = fabsf(q[e]) == m;
+    p = hit ? e : p;
+    v = hit ? q[e] : v;
+  }
+  p += b;
   const uint32_t wm = __float_as_uint(wave_max_f32(m));
   const uint64_t holders = __builtin_amdgcn_ballot_w64(__float_as_uint(m) == wm);
   // (1 to 64 holders: (count + 62) >> 6 is 0 for one, 1 for more -- an

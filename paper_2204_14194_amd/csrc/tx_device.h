@@ -176,7 +176,8 @@ __device__ inline void tx_fold_rows(const floatx4 (&x)[MT][NT], floatx4 (&xf)[2]
 // Column tiles c0 .. c0 + CP - 1 of the class-order rows of parity pv (rows
 // pv M/2 .. pv M/2 + M/2 - 1) from the folded operand xf = xf[pv]: the
 // scheme of tx_cols with MT/2 row tiles in both stages; out(k1, k2, D_k z)
-// with k1 the class-order row.
+// with k1 the class-order row.  Whole tiles only (M = 16 MT, N = 16 NT): every
+// output is in range.
 template <int MT, int NT, int CP, typename Out>
 __device__ inline void tx_cols_fold(int c0, int pv, const float* Af, const float* Btf,
                                     const float* Df, const floatx4 (&x)[MT / 2][NT], int M,
@@ -229,10 +230,7 @@ __device__ inline void tx_cols_fold(int c0, int pv, const float* Af, const float
       const int rr = pv * MH + r;
       const floatx4 dv = *reinterpret_cast<const floatx4*>(Df + ((c * MT + rr) * 64 + l) * 4);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int k1 = 16 * rr + 4 * (l >> 4) + e;
-        if (k1 < M && k2 < N) out(k1, k2, dv[e] * z[cc][r][e]);
-      }
+      for (int e = 0; e < 4; ++e) out(16 * rr + 4 * (l >> 4) + e, k2, dv[e] * z[cc][r][e]);
     }
   }
 }
