@@ -51,25 +51,35 @@ void k_conceal_tx(GreedyArgs a, TxArgs x, TxLayout L) {
   }
   __syncthreads();   // every X operand is in registers: the LDS becomes the row
   // class form on one frame (the launcher's areas have M = 16 MT rows, MT
-  // even): the vertical stage on the folded rows (half the contraction;
-  // tx_fold_rows)
+  // even, and N = 16 NT columns): the vertical stage on the folded rows
+  // (tx_fold_rows), and for NT even the horizontal stage on the folded
+  // columns too (tx_fold_cols): a quarter of the contraction
   constexpr bool FOLD = CLS && !VOL && MT % 2 == 0;
   if constexpr (FOLD) {
     if (computes) {
       floatx4 xf[2][MT / 2][NT];
       tx_fold_rows<MT, NT>(xv, xf);
+      constexpr bool HFOLD = NT % 2 == 0;
+      floatx4 xh[2][2][MT / 2][HFOLD ? NT / 2 : 1];
+      if constexpr (HFOLD) {
+        tx_fold_cols<MT / 2, NT>(xf[0], xh[0]);
+        tx_fold_cols<MT / 2, NT>(xf[1], xh[1]);
+      }
       const int HV = M / 2, HN = N / 2, Kc = a.K / 4;
 #pragma unroll 1
       for (int q = wave; q < NP; q += WAVES) {
         const float* Af = x.tx + L.oAc + q * MT * MT * 256;
         const float* Btf = M == N ? Af : x.tx + L.oBc + q * NT * NT * 256;
+        const float* Df = x.tx + L.oDc + q * MT * NT * 256;
         const int qoff = (q ? x.first1 > x.first0 : x.first0 > x.first1) ? HV * HN : 0;
-        tx_part_fold<MT, NT>(Af, Btf, x.tx + L.oDc + q * MT * NT * 256, xf, M, N,
-                             [&](int k1, int k2, float v) {
-                               const int pv = k1 >= HV, ph = k2 >= HN;
-                               Rs[(2 * pv + ph) * Kc + qoff + (k1 - pv * HV) * HN + k2 -
-                                  ph * HN] = v;
-                             });
+        auto out = [&](int k1, int k2, float v) {
+          const int pv = k1 >= HV, ph = k2 >= HN;
+          Rs[(2 * pv + ph) * Kc + qoff + (k1 - pv * HV) * HN + k2 - ph * HN] = v;
+        };
+        if constexpr (HFOLD)
+          tx_part_hfold<MT, NT>(Af, Btf, Df, xh, out);
+        else
+          tx_part_fold<MT, NT>(Af, Btf, Df, xf, out);
       }
     }
   } else if (computes) {

@@ -173,36 +173,15 @@ __device__ inline void tx_fold_rows(const floatx4 (&x)[MT][NT], floatx4 (&xf)[2]
       }
 }
 
-// Column tiles c0 .. c0 + CP - 1 of the class-order rows of parity pv (rows
-// pv M/2 .. pv M/2 + M/2 - 1) from the folded operand xf = xf[pv]: the
-// scheme of tx_cols with MT/2 row tiles in both stages; out(k1, k2, D_k z)
-// with k1 the class-order row.  Whole tiles only (M = 16 MT, N = 16 NT): every
-// output is in range.
+// Stage 2 of the folded forms and the output: z = A'_pv y over the first M/2
+// columns of the class-order rows of parity pv (rows pv M/2 .. pv M/2 +
+// M/2 - 1), out(k1, k2, D_k z) with k1 the class-order row.  Whole tiles
+// only (M = 16 MT, N = 16 NT): every output is in range.
 template <int MT, int NT, int CP, typename Out>
-__device__ inline void tx_cols_fold(int c0, int pv, const float* Af, const float* Btf,
-                                    const float* Df, const floatx4 (&x)[MT / 2][NT], int M,
-                                    int N, Out& out) {
+__device__ inline void tx_fold_rows_out(int c0, int pv, const float* Af, const float* Df,
+                                        const floatx4 (&y)[CP][MT / 2], Out& out) {
   constexpr int MH = MT / 2;
   const int l = threadIdx.x & 63;
-  floatx4 y[CP][MH];
-#pragma unroll
-  for (int cc = 0; cc < CP; ++cc)
-#pragma unroll
-    for (int i = 0; i < MH; ++i) y[cc][i] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int sq = 0; sq < NT; ++sq) {
-    floatx4 bv[CP];
-#pragma unroll
-    for (int cc = 0; cc < CP; ++cc)
-      bv[cc] = *reinterpret_cast<const floatx4*>(Btf + (((c0 + cc) * NT + sq) * 64 + l) * 4);
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int cc = 0; cc < CP; ++cc)
-#pragma unroll
-        for (int i = 0; i < MH; ++i)
-          y[cc][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[i][sq][t], bv[cc][t], y[cc][i], 0, 0, 0);
-  }
   floatx4 z[CP][MH];
 #pragma unroll
   for (int cc = 0; cc < CP; ++cc)
@@ -235,11 +214,120 @@ __device__ inline void tx_cols_fold(int c0, int pv, const float* Af, const float
   }
 }
 
+// Column tiles c0 .. c0 + CP - 1 of the class-order rows of parity pv from
+// the row-folded operand x = xf[pv]: the scheme of tx_cols with MT/2 row
+// tiles in both stages.
+template <int MT, int NT, int CP, typename Out>
+__device__ inline void tx_cols_fold(int c0, int pv, const float* Af, const float* Btf,
+                                    const float* Df, const floatx4 (&x)[MT / 2][NT], Out& out) {
+  constexpr int MH = MT / 2;
+  const int l = threadIdx.x & 63;
+  floatx4 y[CP][MH];
+#pragma unroll
+  for (int cc = 0; cc < CP; ++cc)
+#pragma unroll
+    for (int i = 0; i < MH; ++i) y[cc][i] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int sq = 0; sq < NT; ++sq) {
+    floatx4 bv[CP];
+#pragma unroll
+    for (int cc = 0; cc < CP; ++cc)
+      bv[cc] = *reinterpret_cast<const floatx4*>(Btf + (((c0 + cc) * NT + sq) * 64 + l) * 4);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int cc = 0; cc < CP; ++cc)
+#pragma unroll
+        for (int i = 0; i < MH; ++i)
+          y[cc][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[i][sq][t], bv[cc][t], y[cc][i], 0, 0, 0);
+  }
+  tx_fold_rows_out<MT, NT, CP>(c0, pv, Af, Df, y, out);
+}
+
+// The horizontal fold on top: the class-order columns of B' split the same
+// way (columns [0, N/2) even about the area's centre, [N/2, N) odd), so
+// column tile c of the horizontal stage needs only the first N/2 columns of
+// X_f +- X_f~, X_f~ the columns of X_f right to left.  Column n = 16 sq +
+// 4 g + t (g = lane / 16) mirrors to 16 (NT-1-sq) + 4 (3-g) + 3-t: register
+// [NT-1-sq][3-t] of lane ^ 48 (a crossbar permute, once per block).
+//   xh[0] = X_f + X_f~, xh[1] = X_f - X_f~ (NT/2 column tiles each)
+template <int MH, int NT>
+__device__ inline void tx_fold_cols(const floatx4 (&x)[MH][NT], floatx4 (&xh)[2][MH][NT / 2]) {
+  const int src = ((threadIdx.x & 63) ^ 48) * 4;
+#pragma unroll
+  for (int i = 0; i < MH; ++i)
+#pragma unroll
+    for (int sq = 0; sq < NT / 2; ++sq)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float m = __int_as_float(
+            __builtin_amdgcn_ds_bpermute(src, __float_as_int(x[i][NT - 1 - sq][3 - t])));
+        xh[0][i][sq][t] = x[i][sq][t] + m;
+        xh[1][i][sq][t] = x[i][sq][t] - m;
+      }
+}
+
+// Column tiles c0 and c0 + 1 of the class-order rows of parity pv from the
+// fully folded operands of their column parities (xa for c0, xb for c0 + 1).
+template <int MT, int NT, typename Out>
+__device__ inline void tx_cols_hfold(int c0, int pv, const float* Af, const float* Btf,
+                                     const float* Df, const floatx4 (&xa)[MT / 2][NT / 2],
+                                     const floatx4 (&xb)[MT / 2][NT / 2], Out& out) {
+  constexpr int MH = MT / 2;
+  const int l = threadIdx.x & 63;
+  floatx4 y[2][MH];
+#pragma unroll
+  for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+    for (int i = 0; i < MH; ++i) y[cc][i] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int sq = 0; sq < NT / 2; ++sq) {
+    floatx4 bv[2];
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc)
+      bv[cc] = *reinterpret_cast<const floatx4*>(Btf + (((c0 + cc) * NT + sq) * 64 + l) * 4);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < MH; ++i) {
+        y[0][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[i][sq][t], bv[0][t], y[0][i], 0, 0, 0);
+        y[1][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(xb[i][sq][t], bv[1][t], y[1][i], 0, 0, 0);
+      }
+  }
+  tx_fold_rows_out<MT, NT, 2>(c0, pv, Af, Df, y, out);
+}
+
+// One part in class order from the fully folded operands (NT even): one pass
+// per pair of column tiles of one column parity, or one pass over the two
+// column tiles when each parity has one.
+template <int MT, int NT, typename Out>
+__device__ void tx_part_hfold(const float* Af, const float* Btf, const float* Df,
+                              const floatx4 (&xh)[2][2][MT / 2][NT / 2], Out out) {
+  constexpr int NH = NT / 2;
+  static_assert(NH == 1 || NH % 2 == 0, "pairs of column tiles");
+#pragma unroll
+  for (int pv = 0; pv < 2; ++pv) {
+    if constexpr (NH == 1) {
+      tx_cols_hfold<MT, NT>(0, pv, Af, Btf, Df, xh[pv][0], xh[pv][1], out);
+    } else {
+#pragma unroll
+      for (int ph = 0; ph < 2; ++ph) {
+#pragma unroll 1
+        for (int c0 = ph * NH; c0 < ph * NH + NH; c0 += 2) {
+          int opaque = 0;
+          asm volatile("" : "+s"(opaque));
+          tx_cols_hfold<MT, NT>(c0, pv, Af + opaque, Btf, Df, xh[pv][ph], xh[pv][ph], out);
+        }
+      }
+    }
+  }
+}
+
 // One part in class order from the folded operands: both parities, two
 // column tiles per pass.
 template <int MT, int NT, typename Out>
 __device__ void tx_part_fold(const float* Af, const float* Btf, const float* Df,
-                             const floatx4 (&xf)[2][MT / 2][NT], int M, int N, Out out) {
+                             const floatx4 (&xf)[2][MT / 2][NT], Out out) {
   // both parities unrolled: a register array indexed at run time would go
   // to scratch
 #pragma unroll
@@ -248,9 +336,9 @@ __device__ void tx_part_fold(const float* Af, const float* Btf, const float* Df,
     for (int c0 = 0; c0 + 1 < NT; c0 += 2) {
       int opaque = 0;
       asm volatile("" : "+s"(opaque));
-      tx_cols_fold<MT, NT, 2>(c0, pv, Af + opaque, Btf, Df, xf[pv], M, N, out);
+      tx_cols_fold<MT, NT, 2>(c0, pv, Af + opaque, Btf, Df, xf[pv], out);
     }
-    if (NT & 1) tx_cols_fold<MT, NT, 1>(NT - 1, pv, Af, Btf, Df, xf[pv], M, N, out);
+    if (NT & 1) tx_cols_fold<MT, NT, 1>(NT - 1, pv, Af, Btf, Df, xf[pv], out);
   }
 }
 
