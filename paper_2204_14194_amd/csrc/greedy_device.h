@@ -306,6 +306,8 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
   // so every byte offset fits 32 bits; unused by the other forms)
   const __amdgpu_buffer_rsrc_t gc_rsrc = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float*>(a.Gc), (short)0, K * (T * NJ * 4), kBufferWord3);
+  const __amdgpu_buffer_rsrc_t gq_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<int16_t*>(a.Gq), (short)0, K * (T * NJ * 2), kBufferWord3);
   const __amdgpu_buffer_rsrc_t phi_rsrc = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float*>(a.phi), (short)0, K * (P * 4), kBufferWord3);
   int flush_at = min(63, a.iters - 1);
@@ -467,8 +469,16 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     const float* grow = CLS ? a.Gc + (size_t)u * (T * NJ) : a.G + (size_t)u * a.ldG;
     float4 row[NR];
     uint2 qrow[Q16 ? NR : 1];
-    if constexpr (Q16) {
-      const int16_t* g16 = CLS ? a.Gq + (size_t)u * (T * NJ) : a.Gqr + (size_t)u * a.ldG;
+    if constexpr (Q16 && CLS) {
+      // (buffer loads, as the FP32 class rows)
+      const int so = u * (T * NJ * 2);
+#pragma unroll
+      for (int j = 0; j < NR; ++j) {
+        const auto q = __builtin_amdgcn_raw_buffer_load_b64(gq_rsrc, 8 * (j * T + t), so, 0);
+        qrow[j] = make_uint2(q[0], q[1]);
+      }
+    } else if constexpr (Q16) {
+      const int16_t* g16 = a.Gqr + (size_t)u * a.ldG;
 #pragma unroll
       for (int j = 0; j < NR; ++j) qrow[j] = *reinterpret_cast<const uint2*>(g16 + 4 * (j * T + t));
     } else if constexpr (CLS) {
