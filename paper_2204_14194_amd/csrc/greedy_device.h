@@ -283,7 +283,10 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
   __shared__ uint64_t s_key[2][WAVES];
   __shared__ uint64_t s_tie[WAVES];
   int par = 0;
-  const float gamma = a.gamma;
+  // gamma in a vector register (loop-invariant): gamma times a scalar value
+  // is then one vector multiply (a vector instruction reads one scalar)
+  float gamma;
+  asm("v_mov_b32 %0, %1" : "=v"(gamma) : "s"(a.gamma));
 
   // each class's winner kept across iterations (class form, one wave; the
   // wave-uniform words of class_winner)
@@ -484,10 +487,11 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     } else if constexpr (CLS) {
       // buffer loads: the row's byte offset is a scalar offset on a fixed
       // resource, the lane's part a loop-invariant vector offset
+      // (sweep j's 16 T-byte step in the scalar offset: one vector offset for all)
       const int so = u * (T * NJ * 4);
 #pragma unroll
       for (int j = 0; j < NR; ++j) {
-        const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(gc_rsrc, 16 * (j * T + t), so, 0);
+        const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(gc_rsrc, 16 * t, so + 16 * j * T, 0);
         row[j] = make_float4(__uint_as_float(q.x), __uint_as_float(q.y), __uint_as_float(q.z),
                              __uint_as_float(q.w));
       }
@@ -497,7 +501,10 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
     int ou = u;
     float Du = 0.0f;
     if constexpr (CLS) {
-      const uint64_t cu = ((const __attribute__((address_space(4))) uint64_t*)a.cls)[u];
+      // (an unsigned 32-bit byte offset: the load takes it as its offset
+      // register, no 64-bit address is formed)
+      const uint64_t cu = *(const __attribute__((address_space(4))) uint64_t*)(
+          (const __attribute__((address_space(4))) char*)a.cls + ((uint32_t)u << 3));
       ou = (int)(uint32_t)cu;
       Du = __uint_as_float((uint32_t)(cu >> 32));
     }
