@@ -164,9 +164,16 @@ __device__ __forceinline__ void class_winner(const float (&R)[NJ][4], int t, uin
   p += b;
   const uint32_t wm = __float_as_uint(wave_max_f32(m));
   const uint64_t holders = __builtin_amdgcn_ballot_w64(__float_as_uint(m) == wm);
-  // (1 to 64 holders: (count + 62) >> 6 is 0 for one, 1 for more -- an
-  // integer form without a boolean, so the words stay in scalar registers)
-  key = (wm << 1) | (((uint32_t)__builtin_popcountll(holders) + 62u) >> 6);
+  // key = 2 wm + (more than one holder), as wm + wm + carry with the carry
+  // from the holder count (scalar instructions: the compiler would take the
+  // comparison as a lane mask)
+  uint32_t cnt;
+  asm("s_bcnt1_i32_b64 %[c], %[h]\n\t"
+      "s_cmp_gt_u32 %[c], 1\n\t"
+      "s_addc_u32 %[k], %[w], %[w]"
+      : [k] "=s"(key), [c] "=&s"(cnt)
+      : [h] "s"(holders), [w] "s"(wm)
+      : "scc");
   const int L = (int)__builtin_ctzll(holders);
   pos = __builtin_amdgcn_readlane(p, L) + 4 * L;
   val = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(v), L);
