@@ -116,17 +116,18 @@ __device__ __forceinline__ void select_class(const uint32_t (&k)[4], const int (
       : "scc");
 }
 
-// Class form, one wave per block: the winner of class C, found when the
+// Class form: the winner of class C among a wave's values, found when the
 // class changes (once at the start, then after each update of the class),
 // as wave-uniform words: key = (largest |R~| of the class over the wave, as
 // float bits) << 1, plus 1 when several lanes hold it (the sign bit of |R~|
 // is 0, so the shift loses nothing and keys order as the maxima, a held-by-
 // several key above a held-by-one key of the same maximum); and the single
-// holder's position in the class order and signed value (float bits).  The
+// holder's position in the class order (wpos: the wave's offset, 4 x 64 x
+// its index) and signed value (float bits).  The
 // holding lane's lowest position at the maximum is that lane's lowest atom of
 // the class (positions follow the atom order inside a class).
 template <int NJ, int NJC, int C, int T>
-__device__ __forceinline__ void class_winner(const float (&R)[NJ][4], int t, uint32_t& key,
+__device__ __forceinline__ void class_winner(const float (&R)[NJ][4], int wpos, uint32_t& key,
                                              int& pos, uint32_t& val) {
   // the lane's maximum through its sweep maxima
   float ms[NJC];
@@ -175,7 +176,7 @@ __device__ __forceinline__ void class_winner(const float (&R)[NJ][4], int t, uin
       : [h] "s"(holders), [w] "s"(wm)
       : "scc");
   const int L = (int)__builtin_ctzll(holders);
-  pos = __builtin_amdgcn_readlane(p, L) + 4 * L;
+  pos = __builtin_amdgcn_readlane(p, L) + 4 * L + wpos;
   val = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(v), L);
 }
 
@@ -295,17 +296,18 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
   float gamma;
   asm("v_mov_b32 %0, %1" : "=v"(gamma) : "s"(a.gamma));
 
-  // each class's winner kept across iterations (class form, one wave; the
+  // each class's winner kept across iterations (class form; per wave, the
   // wave-uniform words of class_winner)
-  constexpr bool INC = CLS && WAVES == 1;
+  constexpr bool INC = CLS;
+  const int wpos = WAVES == 1 ? 0 : __builtin_amdgcn_readfirstlane(256 * wave);
   uint32_t ck[4] = {0u, 0u, 0u, 0u};
   int c_pos[4] = {0, 0, 0, 0};
   uint32_t c_val[4] = {0u, 0u, 0u, 0u};
   if constexpr (INC) {
-    class_winner<NJ, NJC, 0, T>(R, t, ck[0], c_pos[0], c_val[0]);
-    class_winner<NJ, NJC, 1, T>(R, t, ck[1], c_pos[1], c_val[1]);
-    class_winner<NJ, NJC, 2, T>(R, t, ck[2], c_pos[2], c_val[2]);
-    class_winner<NJ, NJC, 3, T>(R, t, ck[3], c_pos[3], c_val[3]);
+    class_winner<NJ, NJC, 0, T>(R, wpos, ck[0], c_pos[0], c_val[0]);
+    class_winner<NJ, NJC, 1, T>(R, wpos, ck[1], c_pos[1], c_val[1]);
+    class_winner<NJ, NJC, 2, T>(R, wpos, ck[2], c_pos[2], c_val[2]);
+    class_winner<NJ, NJC, 3, T>(R, wpos, ck[3], c_pos[3], c_val[3]);
   }
   // the selections and coefficients of 64 iterations, gathered in the lanes
   // of wave 0 (lane i: iteration i mod 64) and written together
@@ -334,15 +336,23 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
       uint32_t mk, dir, vb;
       select_class(ck, c_pos, c_val, mk, dir, u, vb);   // (u, vb taken when direct)
       rv = __uint_as_float(vb);
-      if (dir == 0u) {
-        u = 0;                                  // every score zero: atom 0, value 0
-        rv = 0.0f;
-        if (mk > 1u) {
-          // exact ties across lanes or between classes: the lowest atom index
-          key = class_tie_key<NJ, T>(R, mk >> 1, a.cl, t);
-          direct = false;
-          class_key = true;
+      if constexpr (WAVES == 1) {
+        if (dir == 0u) {
+          u = 0;                                // every score zero: atom 0, value 0
+          rv = 0.0f;
+          if (mk > 1u) {
+            // exact ties across lanes or between classes: the lowest atom index
+            key = class_tie_key<NJ, T>(R, mk >> 1, a.cl, t);
+            direct = false;
+            class_key = true;
+          }
         }
+      } else {
+        // this wave's candidate as a key for the waves' reduction below,
+        // marked for the atom-index rule when it is not direct (several
+        // lanes or classes of the wave at its maximum); 0 when every value
+        // of the wave is 0
+        key = mk > 1u ? (make_key(rv, u) | (uint64_t)(dir == 0u)) : 0ull;
       }
     } else {
     // ---- this wave's largest |R~| and its lowest index ---------------------
@@ -607,10 +617,10 @@ __device__ __forceinline__ void greedy_block(const GreedyArgs& a, int b, float (
           }
           if constexpr (INC) {                  // the class's new winner
             switch (cc) {
-              case 0: class_winner<NJ, NJC, 0, T>(R, t, ck[0], c_pos[0], c_val[0]); break;
-              case 1: class_winner<NJ, NJC, 1, T>(R, t, ck[1], c_pos[1], c_val[1]); break;
-              case 2: class_winner<NJ, NJC, 2, T>(R, t, ck[2], c_pos[2], c_val[2]); break;
-              default: class_winner<NJ, NJC, 3, T>(R, t, ck[3], c_pos[3], c_val[3]); break;
+              case 0: class_winner<NJ, NJC, 0, T>(R, wpos, ck[0], c_pos[0], c_val[0]); break;
+              case 1: class_winner<NJ, NJC, 1, T>(R, wpos, ck[1], c_pos[1], c_val[1]); break;
+              case 2: class_winner<NJ, NJC, 2, T>(R, wpos, ck[2], c_pos[2], c_val[2]); break;
+              default: class_winner<NJ, NJC, 3, T>(R, wpos, ck[3], c_pos[3], c_val[3]); break;
             }
           }
         }
