@@ -34,10 +34,11 @@
 // and eq. 20 updates only the selected atom's class -- every other entry of
 // its row of D C D is 0.  The selected position maps to its original atom
 // (for the model, the reported selection and D) through the class table.
-// With one wave per block the largest |R~| of each class is kept, per lane
-// and over the wave, across iterations: only the updated class is rescanned,
-// the class maxima are compared in scalar registers, and the winner is found
-// in the winning class.  Inside a class positions follow the atom order, so
+// Each wave keeps the largest |R~| of each class over its values across
+// iterations: only the updated class is rescanned, the class maxima are
+// compared in scalar registers, and the winner is found in the winning class
+// (with several waves per block, each wave's pick enters the waves'
+// reduction as a key).  Inside a class positions follow the atom order, so
 // the lowest position holding the maximum is its lowest atom; across classes
 // they do not, so an exact tie between classes (or any tie the position
 // order cannot settle: several lanes, several groups of one lane, several
