@@ -429,7 +429,37 @@ def main():
                     "dictionary): FP32 GEMM projections against all K atoms, then the loop "
                     "on whole rows of G (eager, two launches); rows_q14: the loop reading "
                     "G as 16-bit words (SE_ROWS_Q14, opt-in: the words change the result)"}
-        del ta, dblk_a, ws_a
+        # the same route with the tables and projections as three BF16
+        # products each (SE_BF16X3), and how many blocks keep every selection
+        # of the FP32 route
+        tb = B.weighted_gram(phi_d, w[0].contiguous(), M, N, precision=B.SE_BF16X3)
+        dblk_b = B.DeviceBlocks(tb, images_d, blocks)
+        ws_b = torch.empty(max(1, B.project_ws_bytes(tb, nblk)), dtype=torch.uint8, device=dev)
+
+        def bf16x3_step(ev=None, st=None):
+            if ev is not None:
+                ev[0].record(stream)
+            B.project(tb, images_d, dblk_b, R, ws_b, stream=st)
+            if ev is not None:
+                ev[1].record(stream)
+            B.iterate(tb, R, images_d, dblk_b, GAMMA, ITERS, stream=st)
+            if ev is not None:
+                ev[2].record(stream)
+        b_ms, b_evs = timed(bf16x3_step, args.steps)
+        sels = []
+        for tt in (ta, tb):
+            img = torch.from_numpy(d["images"]).to(dev)
+            sel_, _, _ = B.extrapolate_batch(tt, img, blocks, GAMMA, ITERS, want_coef=False)
+            torch.cuda.synchronize()
+            sels.append(sel_.cpu().numpy())
+        arbitrary["bf16x3"] = {
+            "dtype": "bf16x3", "ms_per_step": b_ms, "blocks_per_s": nblk / (b_ms * 1e-3),
+            "project_ms": float(np.mean([e[0].elapsed_time(e[1]) for e in b_evs])),
+            "loop_ms": float(np.mean([e[1].elapsed_time(e[2]) for e in b_evs])),
+            "same_selections_as_fp32_frac": float(np.all(sels[0] == sels[1], axis=1).mean()),
+            "what": "tables and projections as three BF16 products (hi x hi + hi x lo + lo x "
+                    "hi, SE_BF16X3), the loop in FP32 as above (eager, two launches)"}
+        del ta, dblk_a, ws_a, tb, dblk_b, ws_b
 
     # the same step captured once into a HIP graph and replayed
     graph_info = None
